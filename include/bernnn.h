@@ -1,0 +1,197 @@
+/*
+ * bernnn.h -- C ABI of the MI355X (gfx950) BERN-NN bound-propagation library.
+ *
+ * The library computes, for a fully connected ReLU network and an input box
+ * I_n(d_lo, d_hi), polynomial upper/lower approximations of every neuron
+ * (Problem 1 of the paper, Section 2.2) and the absolute bounds they give
+ * (Section 5.3, last paragraph): the pre-activation interval [lo, hi] of each
+ * hidden neuron (Step 1 of Section 5.1) and the output interval of each network
+ * output (Def. 2 applied to the output polynomials).
+ *
+ * Polynomials live on the GPU as dense power-basis coefficient tensors in the
+ * box-normalised coordinate t in [0,1]^n (x = d_lo + (d_hi - d_lo) t); a
+ * polynomial of per-variable degree D has (D+1)^n coefficients, last variable
+ * fastest (the layout of Section 4.1, Example 1, in the power basis).
+ *
+ * Conventions for every entry point below:
+ *   - Pointers named "device" are GPU (HBM) pointers on the current HIP device;
+ *     "host" pointers are ordinary CPU memory.
+ *   - Calls taking a `stream` (a hipStream_t passed as void*, NULL = the
+ *     default stream) are asynchronous with respect to the host: they only
+ *     enqueue work. Their results are valid once the stream has completed.
+ *     They never allocate device memory: scratch comes from the caller's
+ *     workspace.
+ *   - The caller owns every array it passes. The library owns the handles it
+ *     returns and the device copies of the weights made at creation; it keeps
+ *     no caller pointer after the call returns (the enqueued work still reads
+ *     and writes them until the stream completes).
+ *   - No exception crosses this interface. On error nothing is enqueued (or,
+ *     for errors detected on the device, the outputs are unspecified), the
+ *     status says why and bern_last_error() returns a message for the calling
+ *     thread.
+ *   - All matrices are row-major.
+ */
+#ifndef BERNNN_H
+#define BERNNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BERN_OK = 0,
+  BERN_E_ARG = -1,       /* null pointer, count < 1, unknown enum value            */
+  BERN_E_SHAPE = -2,     /* widths / degree combination the library cannot hold    */
+  BERN_E_BOX = -3,       /* d_lo > d_hi or a non-finite box coordinate (host check) */
+  BERN_E_DEGREE = -4,    /* L outside 1..8, or a degree code outside its range     */
+  BERN_E_TOO_LARGE = -5, /* (D+1)^n overflows, or one box does not fit the workspace */
+  BERN_E_OOM = -6,       /* a library-side allocation (handles, weights) failed    */
+  BERN_E_WORKSPACE = -7, /* workspace pointer/size unusable (null, misaligned)     */
+  BERN_E_DEVICE = -8,    /* a HIP runtime call failed                              */
+  BERN_E_NUMERIC = -9    /* non-finite weights or a non-finite intermediate bound  */
+} bern_status;
+
+typedef enum {
+  BERN_FP64 = 0,        /* every tensor and every operation in FP64                 */
+  BERN_FP32_PADDED = 1  /* FP32 tensors, FP64 basis change and scalars; every bound
+                           is pushed outward by a rigorous rounding-error radius   */
+} bern_precision;
+
+typedef enum {
+  BERN_PLAN_PLAIN = 0,   /* the paper's rule: ReLU order L for every unstable neuron,
+                            all neurons of hidden layer i stored at degree L*D_i
+                            (Section 5.4, elevation to the highest expected degree) */
+  BERN_PLAN_GIVEN = 1,   /* caller's int8 code per (box, hidden neuron): 1..8 = ReLU
+                            Bernstein order for that neuron if unstable, 0 = linear
+                            fallback; stable neurons keep degree D (active) or 0
+                            (inactive); each layer is stored at the largest degree  */
+  BERN_PLAN_LEARNED = 2  /* like GIVEN, with the codes chosen on the device by a
+                            degree predictor (bern_pred) from each neuron's interval
+                            and coefficient statistics                             */
+} bern_plan;
+
+typedef enum {
+  BERN_SCHED_PER_BOX = 0, /* one launch sequence per box (the plain form)            */
+  BERN_SCHED_BATCHED = 1  /* all boxes of a wave in one captured HIP graph launch    */
+} bern_sched;
+
+typedef struct bern_net bern_net;   /* opaque: network on the device               */
+typedef struct bern_pred bern_pred; /* opaque: degree predictor (MLP) on the device */
+
+typedef struct {
+  int32_t L;          /* ReLU approximation order of the plain rule, 1..8          */
+  int32_t precision;  /* bern_precision                                            */
+  int32_t plan;       /* bern_plan                                                 */
+  int32_t sched;      /* bern_sched                                                */
+  const bern_pred *pred; /* predictor for BERN_PLAN_LEARNED, else ignored           */
+  int32_t max_wave;   /* upper limit on boxes per wave (0 = as many as fit)         */
+  int32_t reserved[7];
+} bern_opts;
+
+typedef struct {
+  int32_t n_waves;      /* waves the boxes were split into                          */
+  int32_t boxes_per_wave;
+  int32_t out_degree;   /* largest per-variable degree of an output polynomial      */
+  int32_t reserved0;
+  uint64_t workspace_used; /* bytes of the workspace actually used                  */
+  uint64_t reserved[6];
+} bern_stats;
+
+/* Fill *opts with defaults: L = 2, FP64, plain plan, per-box schedule. */
+void bern_opts_default(bern_opts *opts);
+
+/* Create a network handle (Section 2.1 notation).
+ *   H        number of affine layers (H-1 hidden ReLU layers), 1..64
+ *   widths   host, H+1 entries: n = h_0 (input dimension, 1..16), h_1, ..., h_H
+ *   W        host, all W^(i) (h_i x h_{i-1}, row-major) concatenated, i = 1..H
+ *   b        host, all b^(i) (h_i) concatenated
+ *   out      receives the handle; free it with bern_net_destroy.
+ * The weights are copied to the current HIP device (FP64 and an FP32 copy).
+ * Errors: BERN_E_ARG (nulls, bad sizes), BERN_E_NUMERIC (non-finite weights),
+ * BERN_E_OOM / BERN_E_DEVICE. */
+bern_status bern_net_create(int32_t H, const int32_t *widths, const double *W, const double *b,
+                            bern_net **out);
+void bern_net_destroy(bern_net *net);
+
+/* Number of network inputs / hidden neurons / outputs of a handle. */
+int32_t bern_net_inputs(const bern_net *net);
+int32_t bern_net_hidden(const bern_net *net);
+int32_t bern_net_outputs(const bern_net *net);
+
+/* Workspace bytes bern_bounds needs to process `n_boxes` boxes in a single
+ * wave with these options (the schedule BERN_SCHED_PER_BOX always needs the
+ * one-box size). A smaller workspace is accepted by bern_bounds, which then
+ * splits the boxes into waves; *one_box receives the smallest usable size.
+ * For BERN_PLAN_GIVEN / BERN_PLAN_LEARNED the size covers the largest degree
+ * the plan can reach (every unstable neuron at its largest code).
+ * Errors: BERN_E_ARG, BERN_E_DEGREE, BERN_E_TOO_LARGE (tensor size overflow). */
+bern_status bern_workspace_size(const bern_net *net, const bern_opts *opts, int64_t n_boxes,
+                                size_t *bytes, size_t *one_box);
+
+/* Bounds of `n_boxes` boxes (Problem 1), asynchronous on `stream`.
+ *   box_lo, box_hi   device, [n_boxes][n] FP64; d_lo <= d_hi required (the
+ *                    library checks it on the device; a violation gives NaN
+ *                    bounds for that box, never an invalid memory access)
+ *   plan             device, [n_boxes][sum of hidden widths] int8 codes for
+ *                    BERN_PLAN_GIVEN (1..8 or 0), else NULL
+ *   neuron_lo/hi     device, [n_boxes][sum of hidden widths] FP64: the
+ *                    pre-activation interval of every hidden neuron, layer by
+ *                    layer (Step 1); may be NULL
+ *   out_lo/out_hi    device, [n_boxes][h_H] FP64 output bounds
+ *   used_plan        device, [n_boxes][sum of hidden widths] int8 or NULL:
+ *                    the rule applied per neuron (0 inactive, -1 active,
+ *                    -2 linear fallback, k >= 1 ReLU order k)
+ *   workspace        device scratch of ws_bytes bytes, 256-byte aligned
+ *   stats            host, optional
+ * Errors: BERN_E_ARG, BERN_E_DEGREE, BERN_E_WORKSPACE (too small for one
+ * box), BERN_E_DEVICE. */
+bern_status bern_bounds(const bern_net *net, const bern_opts *opts, int64_t n_boxes,
+                        const double *box_lo, const double *box_hi, const int8_t *plan,
+                        double *neuron_lo, double *neuron_hi, double *out_lo, double *out_hi,
+                        int8_t *used_plan, void *workspace, size_t ws_bytes, void *stream,
+                        bern_stats *stats);
+
+/* Step-level entry points. Each runs one kernel of the hot path on
+ * caller-provided device buffers, asynchronously on `stream`; the tests use
+ * them to check every kernel on its own against the oracle.
+ *
+ * bern_basis_minmax -- power-to-Bernstein basis change at degree D
+ * (Def. 1 coefficients, textbook per-variable identity t^j =
+ * sum_{k>=j} C(k,j)/C(D,j) Ber_{k,D}) and the range enclosure of Def. 2:
+ *   coef     device, [count][(D+1)^n] power coefficients (FP64 if fp64 != 0,
+ *            else FP32)
+ *   bern     device, [count][(D+1)^n] FP64 Bernstein coefficients out, or NULL
+ *   mn, mx   device, [count] FP64: smallest / largest Bernstein coefficient
+ *   l1       device, [count] FP64: sum of |power coefficients|, or NULL
+ *   scratch  device, >= bern_basis_minmax_scratch(n, D, count) bytes */
+size_t bern_basis_minmax_scratch(int32_t n, int32_t D, int64_t count);
+bern_status bern_basis_minmax(int32_t n, int32_t D, int64_t count, const void *coef, int32_t fp64,
+                              double *bern, double *mn, double *mx, double *l1, void *scratch,
+                              size_t scratch_bytes, void *stream);
+
+/* bern_poly_mul -- the product "Prod" of Section 4.2 on power-basis tensors:
+ * out_K = sum_{I+J=K} A_I B_J for `count` independent pairs,
+ *   A  device [count][(da+1)^n], B device [count][(db+1)^n],
+ *   out device [count][(da+db+1)^n]; all FP64 (fp64 != 0) or all FP32.
+ * A and B may be the same pointer (a square). */
+bern_status bern_poly_mul(int32_t n, int32_t da, int32_t db, int64_t count, const void *A,
+                          const void *B, void *out, int32_t fp64, void *stream);
+
+/* bern_relu_poly -- Step 2 for `count` neurons: from [lo, hi] and order L,
+ * the power coefficients c[0..L] in u = (y-lo)/(hi-lo) of the Bernstein
+ * over-approximant of ReLU (Def. 1, Prop. 1) and its value e at y = 0
+ * (Prop. 2). Device arrays: lo, hi [count]; c [count][L+1]; e [count]. */
+bern_status bern_relu_poly(int64_t count, int32_t L, const double *lo, const double *hi, double *c,
+                           double *e, void *stream);
+
+/* Status name and the calling thread's last error message. */
+const char *bern_status_str(int32_t status);
+const char *bern_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BERNNN_H */

@@ -1,0 +1,238 @@
+"""Thin Python binding of ``libbernnn.so`` (the C ABI declared in
+``include/bernnn.h``).
+
+Argument marshalling only: PyTorch provides device memory and the stream, every
+step of the computation runs in the library's HIP kernels. There is no CPU
+fallback: if the library is missing the import of this module's functions
+raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbernnn.so")
+
+BERN_OK = 0
+FP64, FP32_PADDED = 0, 1
+PLAN_PLAIN, PLAN_GIVEN, PLAN_LEARNED = 0, 1, 2
+SCHED_PER_BOX, SCHED_BATCHED = 0, 1
+
+_PREC = {"fp64": FP64, "fp32": FP32_PADDED, "fp32_padded": FP32_PADDED}
+_PLAN = {"plain": PLAN_PLAIN, "given": PLAN_GIVEN, "learned": PLAN_LEARNED}
+_SCHED = {"per_box": SCHED_PER_BOX, "batched": SCHED_BATCHED}
+
+_vp = ctypes.c_void_p
+
+
+class bern_opts(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("precision", ctypes.c_int32), ("plan", ctypes.c_int32),
+                ("sched", ctypes.c_int32), ("pred", ctypes.c_void_p), ("max_wave", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 7)]
+
+
+class bern_stats(ctypes.Structure):
+    _fields_ = [("n_waves", ctypes.c_int32), ("boxes_per_wave", ctypes.c_int32), ("out_degree", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("workspace_used", ctypes.c_uint64),
+                ("reserved", ctypes.c_uint64 * 6)]
+
+
+class BernError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{status_str(status)}: {msg}")
+        self.status = status
+
+
+_LIB = None
+
+
+def lib():
+    """Load the in-tree HIP library (raises if it was not built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2211_14438_amd/build.py "
+                          "(or __graft_entry__.build()); there is no CPU fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    i32, i64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    L.bern_status_str.restype = ctypes.c_char_p
+    L.bern_status_str.argtypes = [i32]
+    L.bern_last_error.restype = ctypes.c_char_p
+    L.bern_last_error.argtypes = []
+    L.bern_opts_default.restype = None
+    L.bern_opts_default.argtypes = [ctypes.POINTER(bern_opts)]
+    L.bern_net_create.restype = i32
+    L.bern_net_create.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_vp)]
+    L.bern_net_destroy.restype = None
+    L.bern_net_destroy.argtypes = [_vp]
+    for f in ("bern_net_inputs", "bern_net_hidden", "bern_net_outputs"):
+        getattr(L, f).restype = i32
+        getattr(L, f).argtypes = [_vp]
+    L.bern_workspace_size.restype = i32
+    L.bern_workspace_size.argtypes = [_vp, ctypes.POINTER(bern_opts), i64, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+    L.bern_bounds.restype = i32
+    L.bern_bounds.argtypes = [_vp, ctypes.POINTER(bern_opts), i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, sz,
+                              _vp, ctypes.POINTER(bern_stats)]
+    L.bern_basis_minmax_scratch.restype = sz
+    L.bern_basis_minmax_scratch.argtypes = [i32, i32, i64]
+    L.bern_basis_minmax.restype = i32
+    L.bern_basis_minmax.argtypes = [i32, i32, i64, _vp, i32, _vp, _vp, _vp, _vp, _vp, sz, _vp]
+    L.bern_poly_mul.restype = i32
+    L.bern_poly_mul.argtypes = [i32, i32, i32, i64, _vp, _vp, _vp, i32, _vp]
+    L.bern_relu_poly.restype = i32
+    L.bern_relu_poly.argtypes = [i64, i32, _vp, _vp, _vp, _vp, _vp]
+    _LIB = L
+    return L
+
+
+EXPORTED = ("bern_opts_default", "bern_net_create", "bern_net_destroy", "bern_net_inputs", "bern_net_hidden",
+            "bern_net_outputs", "bern_workspace_size", "bern_bounds", "bern_basis_minmax_scratch",
+            "bern_basis_minmax", "bern_poly_mul", "bern_relu_poly", "bern_status_str", "bern_last_error")
+
+
+def status_str(s):
+    return lib().bern_status_str(int(s)).decode()
+
+
+def _check(st):
+    if st != BERN_OK:
+        raise BernError(st, lib().bern_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def make_opts(L=2, precision="fp64", plan="plain", sched="per_box", max_wave=0, pred=None):
+    o = bern_opts()
+    lib().bern_opts_default(ctypes.byref(o))
+    o.L = int(L)
+    o.precision = _PREC[precision] if isinstance(precision, str) else int(precision)
+    o.plan = _PLAN[plan] if isinstance(plan, str) else int(plan)
+    o.sched = _SCHED[sched] if isinstance(sched, str) else int(sched)
+    o.max_wave = int(max_wave)
+    o.pred = None if pred is None else pred
+    return o
+
+
+class Net:
+    """A network on the current HIP device (weights copied at creation)."""
+
+    def __init__(self, Ws, bs):
+        self.widths = [int(Ws[0].shape[1])] + [int(w.shape[0]) for w in Ws]
+        self.H = len(Ws)
+        W = np.ascontiguousarray(np.concatenate([np.asarray(w, np.float64).ravel() for w in Ws]))
+        b = np.ascontiguousarray(np.concatenate([np.asarray(x, np.float64).ravel() for x in bs]))
+        widths = (ctypes.c_int32 * (self.H + 1))(*self.widths)
+        h = _vp()
+        _check(lib().bern_net_create(self.H, widths, W.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(h)))
+        self.handle = h
+        self.n = self.widths[0]
+        self.n_hidden = int(sum(self.widths[1:-1]))
+        self.n_out = self.widths[-1]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().bern_net_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_size(self, n_boxes, **opt):
+        o = make_opts(**opt)
+        total, one = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().bern_workspace_size(self.handle, ctypes.byref(o), int(n_boxes), ctypes.byref(total),
+                                         ctypes.byref(one)))
+        return total.value, one.value
+
+
+def bounds(net, box_lo, box_hi, L=2, precision="fp64", plan="plain", sched="per_box", degree_plan=None,
+           max_wave=0, workspace=None, stream=None, outputs=None, pred=None):
+    """Bounds of every box. ``box_lo``/``box_hi``: float64 CUDA tensors
+    [n_boxes, n]. Returns a dict of CUDA tensors (neuron_lo/hi, out_lo/hi,
+    used_plan) plus the run statistics. Asynchronous on ``stream``."""
+    import torch
+    dev = box_lo.device
+    assert box_lo.dtype == torch.float64 and box_hi.dtype == torch.float64
+    box_lo = box_lo.contiguous()
+    box_hi = box_hi.contiguous()
+    nb = box_lo.shape[0]
+    o = make_opts(L=L, precision=precision, plan=plan, sched=sched, max_wave=max_wave, pred=pred)
+    if outputs is None:
+        nh = max(net.n_hidden, 1)
+        outputs = dict(
+            neuron_lo=torch.empty((nb, nh), dtype=torch.float64, device=dev),
+            neuron_hi=torch.empty((nb, nh), dtype=torch.float64, device=dev),
+            out_lo=torch.empty((nb, net.n_out), dtype=torch.float64, device=dev),
+            out_hi=torch.empty((nb, net.n_out), dtype=torch.float64, device=dev),
+            used_plan=torch.empty((nb, nh), dtype=torch.int8, device=dev),
+        )
+    if workspace is None:
+        total, one = net.workspace_size(nb, L=L, precision=precision, plan=plan, sched=sched, max_wave=max_wave)
+        workspace = torch.empty(total + 256, dtype=torch.uint8, device=dev)
+    ws_ptr = workspace.data_ptr()
+    pad = (-ws_ptr) % 256
+    ws_bytes = workspace.numel() - pad
+    st = bern_stats()
+    if degree_plan is not None:
+        degree_plan = degree_plan.contiguous()
+    _check(lib().bern_bounds(net.handle, ctypes.byref(o), nb, _ptr(box_lo), _ptr(box_hi), _ptr(degree_plan),
+                             _ptr(outputs["neuron_lo"]), _ptr(outputs["neuron_hi"]), _ptr(outputs["out_lo"]),
+                             _ptr(outputs["out_hi"]), _ptr(outputs.get("used_plan")), ctypes.c_void_p(ws_ptr + pad),
+                             ws_bytes, _stream(stream), ctypes.byref(st)))
+    res = dict(outputs)
+    res["stats"] = dict(n_waves=st.n_waves, boxes_per_wave=st.boxes_per_wave, out_degree=st.out_degree,
+                        workspace_used=st.workspace_used)
+    res["workspace"] = workspace
+    return res
+
+
+def basis_minmax(coef, n, D, want_bern=False, stream=None):
+    """Step-level basis change + enclosure for a [count, (D+1)^n] tensor."""
+    import torch
+    coef = coef.contiguous()
+    count = coef.shape[0]
+    dev = coef.device
+    mn = torch.empty(count, dtype=torch.float64, device=dev)
+    mx = torch.empty(count, dtype=torch.float64, device=dev)
+    l1 = torch.empty(count, dtype=torch.float64, device=dev)
+    bern = torch.empty(coef.shape, dtype=torch.float64, device=dev) if want_bern else None
+    _check(lib().bern_basis_minmax(n, D, count, _ptr(coef), 1 if coef.dtype == torch.float64 else 0, _ptr(bern),
+                                   _ptr(mn), _ptr(mx), _ptr(l1), None, 0, _stream(stream)))
+    return dict(min=mn, max=mx, l1=l1, bern=bern)
+
+
+def poly_mul(A, B, n, da, db, stream=None):
+    import torch
+    A = A.contiguous()
+    B = A if B is None else B.contiguous()
+    count = A.shape[0]
+    out = torch.empty((count, (da + db + 1) ** n), dtype=A.dtype, device=A.device)
+    _check(lib().bern_poly_mul(n, da, db, count, _ptr(A), _ptr(B), _ptr(out), 1 if A.dtype == torch.float64 else 0,
+                               _stream(stream)))
+    return out
+
+
+def relu_poly(lo, hi, L, stream=None):
+    import torch
+    count = lo.shape[0]
+    c = torch.empty((count, L + 1), dtype=torch.float64, device=lo.device)
+    e = torch.empty(count, dtype=torch.float64, device=lo.device)
+    _check(lib().bern_relu_poly(count, L, _ptr(lo.contiguous()), _ptr(hi.contiguous()), _ptr(c), _ptr(e),
+                                _stream(stream)))
+    return c, e

@@ -1,0 +1,113 @@
+// Affine steps of the hot path on gfx950.
+//
+//  * layer-1 pre-activation in closed form (Section 5.3 input initialisation
+//    followed by eqs. upper/lower_bounds_layer): with x_a = d_lo_a + w_a t_a the
+//    pre-activation W x + b is affine in t, so its power tensor at degree
+//    (1,...,1) has the constant b + W d_lo at index 0 and W_ja w_a at the index
+//    with a single 1 on axis a; upper = lower.
+//  * interval affine map of a hidden/output layer (eqs. upper_bounds_layer,
+//    lower_bounds_layer): U^ = W+ U + W- L + b, L^ = W+ L + W- U + b, computed
+//    in midpoint-radius form U^, L^ = W M +- |W| R + b with M = (U+L)/2 and
+//    R = (U-L)/2 (equal in exact arithmetic, half the multiply-adds). In the
+//    power basis the bias only touches the constant coefficient.
+//
+// Layout: tensors [box][neuron][bound 0=upper,1=lower][coefficient].
+#include "common.hpp"
+
+namespace bern {
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) layer1_kernel(Layer1Args a) {
+  const int64_t C = (int64_t)1 << a.n;
+  const int64_t total = a.nboxes * a.h * C;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = i % C;
+    const int64_t bj = i / C;  // box * h + j
+    const int j = (int)(bj % a.h);
+    const int64_t box = bj / a.h;
+    const double *lo = a.box_lo + box * a.n;
+    const double *hi = a.box_hi + box * a.n;
+    const double *w = a.W + (int64_t)j * a.n;
+    double v = 0.0;
+    if (c == 0) {
+      v = a.b[j];
+      for (int k = 0; k < a.n; ++k) v = fma(w[k], lo[k], v);
+    } else if ((c & (c - 1)) == 0) {
+      // single set bit: axis a with position 2^(n-1-a)
+      const int axis = a.n - 1 - (__ffsll((unsigned long long)c) - 1);
+      v = w[axis] * (hi[axis] - lo[axis]);
+    }
+    T *out = reinterpret_cast<T *>(a.pre) + bj * 2 * C;
+    out[c] = (T)v;
+    out[C + c] = (T)v;
+  }
+}
+
+hipError_t launch_layer1(const Layer1Args &a, hipStream_t s) {
+  const int64_t total = a.nboxes * a.h * ((int64_t)1 << a.n);
+  const int64_t blocks = (total + kBlock - 1) / kBlock;
+  const unsigned grid = (unsigned)std::min<int64_t>(blocks, 65536);
+  if (a.fp64)
+    hipLaunchKernelGGL(layer1_kernel<double>, dim3(grid), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(layer1_kernel<float>, dim3(grid), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+// One thread per coefficient c; MB output neurons per block row. Block x
+// index runs over output-neuron chunks first so that the blocks reading the
+// same coefficient range of the previous layer run together and share L2.
+template <typename T, int MB>
+__global__ void __launch_bounds__(kBlock) gemm_kernel(GemmArgs a) {
+  const int m0 = blockIdx.x * MB;
+  const int64_t c = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+  const int64_t box = blockIdx.z;
+  if (c >= a.C) return;
+  const T *X = reinterpret_cast<const T *>(a.post) + box * a.hin * 2 * a.C;
+  const T *W = reinterpret_cast<const T *>(a.W);
+  T accM[MB], accR[MB];
+#pragma unroll
+  for (int mm = 0; mm < MB; ++mm) accM[mm] = accR[mm] = (T)0;
+  const int mcount = min(MB, a.h - m0);
+  for (int k = 0; k < a.hin; ++k) {
+    const T u = X[(int64_t)k * 2 * a.C + c];
+    const T l = X[(int64_t)k * 2 * a.C + a.C + c];
+    const T M = (u + l) * (T)0.5;
+    const T R = (u - l) * (T)0.5;
+#pragma unroll
+    for (int mm = 0; mm < MB; ++mm) {
+      if (mm < mcount) {
+        const T w = W[(int64_t)(m0 + mm) * a.hin + k];
+        accM[mm] = fma(w, M, accM[mm]);
+        accR[mm] = fma(fabs(w), R, accR[mm]);
+      }
+    }
+  }
+  T *Y = reinterpret_cast<T *>(a.pre) + box * a.h * 2 * a.C;
+#pragma unroll
+  for (int mm = 0; mm < MB; ++mm) {
+    if (mm < mcount) {
+      const int m = m0 + mm;
+      const T bias = (c == 0) ? (T)a.b[m] : (T)0;
+      Y[(int64_t)m * 2 * a.C + c] = accM[mm] + accR[mm] + bias;
+      Y[(int64_t)m * 2 * a.C + a.C + c] = accM[mm] - accR[mm] + bias;
+    }
+  }
+}
+
+hipError_t launch_gemm(const GemmArgs &a, hipStream_t s) {
+  const unsigned cblocks = (unsigned)((a.C + kBlock - 1) / kBlock);
+  if (a.fp64) {
+    constexpr int MB = 16;
+    dim3 grid((a.h + MB - 1) / MB, cblocks, (unsigned)a.nboxes);
+    hipLaunchKernelGGL((gemm_kernel<double, MB>), grid, dim3(kBlock), 0, s, a);
+  } else {
+    constexpr int MB = 32;
+    dim3 grid((a.h + MB - 1) / MB, cblocks, (unsigned)a.nboxes);
+    hipLaunchKernelGGL((gemm_kernel<float, MB>), grid, dim3(kBlock), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace bern

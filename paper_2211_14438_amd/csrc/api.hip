@@ -1,0 +1,476 @@
+// C ABI of the bound-propagation library: validation, planning of degrees and
+// workspace, waves of boxes, and the per-layer launch sequence (the driver of
+// Section 5.3: input initialisation, then for each layer the affine map of
+// Section 5.2, the bounds of Step 1, the approximant of Step 2 and the
+// composition of Step 3, and finally the output bounds).
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "common.hpp"
+
+namespace bern {
+
+static thread_local char g_err[1024] = "";
+
+void set_error(const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+size_t device_lds_limit() {
+  static std::mutex mu;
+  static int cached[64];
+  static bool init[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 64 * 1024;
+  std::lock_guard<std::mutex> g(mu);
+  if (!init[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+      v = 64 * 1024;
+    cached[dev] = v;
+    init[dev] = true;
+  }
+  return (size_t)cached[dev];
+}
+
+// Host-side plan of one network under one set of options: degree of every
+// layer's pre-activation and post tensors and the per-box workspace layout.
+struct Plan {
+  int H, n, L, Lmax;
+  bool fp64;
+  std::vector<int> Dpre, Dpost;     // per layer i = 1..H (index i-1); Dpost for hidden layers
+  std::vector<int64_t> Cpre, Cpost;
+  size_t elem;
+  // per-box bytes of each region
+  size_t recs, arenaA, arenaB, conv, horner, flags;
+  size_t per_box() const { return recs + arenaA + arenaB + conv + horner + flags; }
+};
+
+}  // namespace bern
+
+struct bern_net {
+  int H = 0, n = 0, nh = 0, o = 0, hmax = 0;
+  std::vector<int> widths;
+  std::vector<int64_t> woff, boff, noff;  // per layer offsets into W, b and hidden neurons
+  double *W64 = nullptr, *b64 = nullptr;
+  float *W32 = nullptr;
+  int device = 0;
+};
+
+struct bern_pred {
+  int dummy;
+};
+
+using namespace bern;
+
+static bern_status plan_net(const bern_net *net, const bern_opts *o, Plan &p) {
+  p.H = net->H;
+  p.n = net->n;
+  p.fp64 = o->precision == BERN_FP64;
+  p.elem = p.fp64 ? 8 : 4;
+  p.L = o->L;
+  if (o->plan == BERN_PLAN_PLAIN) {
+    if (o->L < 1 || o->L > kMaxOrder) {
+      set_error("L = %d outside 1..%d", o->L, kMaxOrder);
+      return BERN_E_DEGREE;
+    }
+    p.Lmax = o->L;
+  } else {
+    set_error("plan %d not available in this build", o->plan);
+    return BERN_E_ARG;
+  }
+  p.Dpre.assign(p.H, 0);
+  p.Dpost.assign(p.H, 0);
+  p.Cpre.assign(p.H, 0);
+  p.Cpost.assign(p.H, 0);
+  int D = 1;
+  const int64_t cap = (int64_t)1 << 36;
+  p.recs = p.arenaA = p.arenaB = p.conv = p.horner = 0;
+  for (int i = 0; i < p.H; ++i) {
+    const int h = net->widths[i + 1];
+    p.Dpre[i] = D;
+    p.Cpre[i] = tsize(p.n, D, cap);
+    if (p.Cpre[i] < 0) {
+      set_error("layer %d: (%d+1)^%d coefficients overflow", i + 1, D, p.n);
+      return BERN_E_TOO_LARGE;
+    }
+    p.arenaA = std::max(p.arenaA, align256((size_t)h * 2 * p.Cpre[i] * p.elem));
+    const size_t cs = convert_scratch_bytes(p.n, D, h, 1);
+    p.conv = std::max(p.conv, cs);
+    if (i < p.H - 1) {
+      const int Dn = p.Lmax * D;
+      p.Dpost[i] = Dn;
+      p.Cpost[i] = tsize(p.n, Dn, cap);
+      if (p.Cpost[i] < 0) {
+        set_error("layer %d post: (%d+1)^%d coefficients overflow", i + 1, Dn, p.n);
+        return BERN_E_TOO_LARGE;
+      }
+      p.arenaB = std::max(p.arenaB, align256((size_t)h * 2 * p.Cpost[i] * p.elem));
+      p.recs = std::max(p.recs, align256((size_t)h * sizeof(NeuronRec)));
+      if (p.Lmax >= 2) p.horner = std::max(p.horner, compose_scratch_bytes(p.n, D, p.Lmax, h, 1, p.fp64));
+      D = Dn;
+    }
+  }
+  p.flags = 256;
+  return BERN_OK;
+}
+
+extern "C" {
+
+void bern_opts_default(bern_opts *opts) {
+  if (!opts) return;
+  memset(opts, 0, sizeof(*opts));
+  opts->L = 2;
+  opts->precision = BERN_FP64;
+  opts->plan = BERN_PLAN_PLAIN;
+  opts->sched = BERN_SCHED_PER_BOX;
+}
+
+const char *bern_status_str(int32_t s) {
+  switch (s) {
+    case BERN_OK: return "BERN_OK";
+    case BERN_E_ARG: return "BERN_E_ARG";
+    case BERN_E_SHAPE: return "BERN_E_SHAPE";
+    case BERN_E_BOX: return "BERN_E_BOX";
+    case BERN_E_DEGREE: return "BERN_E_DEGREE";
+    case BERN_E_TOO_LARGE: return "BERN_E_TOO_LARGE";
+    case BERN_E_OOM: return "BERN_E_OOM";
+    case BERN_E_WORKSPACE: return "BERN_E_WORKSPACE";
+    case BERN_E_DEVICE: return "BERN_E_DEVICE";
+    case BERN_E_NUMERIC: return "BERN_E_NUMERIC";
+    default: return "BERN_UNKNOWN";
+  }
+}
+
+const char *bern_last_error(void) { return g_err; }
+
+bern_status bern_net_create(int32_t H, const int32_t *widths, const double *W, const double *b, bern_net **out) {
+  if (!out) { set_error("out is null"); return BERN_E_ARG; }
+  *out = nullptr;
+  if (H < 1 || H > 64 || !widths || !W || !b) {
+    set_error("bad network description (H = %d)", H);
+    return BERN_E_ARG;
+  }
+  if (widths[0] < 1 || widths[0] > kMaxInputs) {
+    set_error("input dimension %d outside 1..%d", widths[0], kMaxInputs);
+    return BERN_E_ARG;
+  }
+  int64_t nw = 0, nb = 0;
+  for (int i = 1; i <= H; ++i) {
+    if (widths[i] < 1 || widths[i] > 65535) {
+      set_error("width h_%d = %d outside 1..65535", i, widths[i]);
+      return BERN_E_ARG;
+    }
+    nw += (int64_t)widths[i] * widths[i - 1];
+    nb += widths[i];
+  }
+  for (int64_t i = 0; i < nw; ++i)
+    if (!std::isfinite(W[i])) { set_error("non-finite weight at %lld", (long long)i); return BERN_E_NUMERIC; }
+  for (int64_t i = 0; i < nb; ++i)
+    if (!std::isfinite(b[i])) { set_error("non-finite bias at %lld", (long long)i); return BERN_E_NUMERIC; }
+  bern_net *net = new (std::nothrow) bern_net();
+  if (!net) { set_error("out of host memory"); return BERN_E_OOM; }
+  net->H = H;
+  net->n = widths[0];
+  net->widths.assign(widths, widths + H + 1);
+  net->o = widths[H];
+  int64_t wo = 0, bo = 0, no = 0;
+  for (int i = 1; i <= H; ++i) {
+    net->woff.push_back(wo);
+    net->boff.push_back(bo);
+    net->noff.push_back(no);
+    wo += (int64_t)widths[i] * widths[i - 1];
+    bo += widths[i];
+    if (i < H) no += widths[i];
+    net->hmax = std::max(net->hmax, widths[i]);
+  }
+  net->nh = (int)no;
+  std::vector<float> w32(nw);
+  for (int64_t i = 0; i < nw; ++i) w32[i] = (float)W[i];
+  (void)hipGetDevice(&net->device);
+  auto fail = [&](hipError_t e) {
+    set_error("device allocation/copy failed: %s", hipGetErrorString(e));
+    (void)hipFree(net->W64); (void)hipFree(net->b64); (void)hipFree(net->W32);
+    delete net;
+    return BERN_E_DEVICE;
+  };
+  hipError_t e;
+  if ((e = hipMalloc(&net->W64, nw * 8)) != hipSuccess) return fail(e);
+  if ((e = hipMalloc(&net->W32, nw * 4)) != hipSuccess) return fail(e);
+  if ((e = hipMalloc(&net->b64, nb * 8)) != hipSuccess) return fail(e);
+  if ((e = hipMemcpy(net->W64, W, nw * 8, hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
+  if ((e = hipMemcpy(net->W32, w32.data(), nw * 4, hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
+  if ((e = hipMemcpy(net->b64, b, nb * 8, hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
+  *out = net;
+  return BERN_OK;
+}
+
+void bern_net_destroy(bern_net *net) {
+  if (!net) return;
+  (void)hipFree(net->W64);
+  (void)hipFree(net->W32);
+  (void)hipFree(net->b64);
+  delete net;
+}
+
+int32_t bern_net_inputs(const bern_net *net) { return net ? net->n : 0; }
+int32_t bern_net_hidden(const bern_net *net) { return net ? net->nh : 0; }
+int32_t bern_net_outputs(const bern_net *net) { return net ? net->o : 0; }
+
+static bern_status check_opts(const bern_net *net, const bern_opts *o) {
+  if (!net || !o) { set_error("null net or options"); return BERN_E_ARG; }
+  if (o->precision != BERN_FP64 && o->precision != BERN_FP32_PADDED) {
+    set_error("unknown precision %d", o->precision);
+    return BERN_E_ARG;
+  }
+  if (o->sched != BERN_SCHED_PER_BOX && o->sched != BERN_SCHED_BATCHED) {
+    set_error("unknown schedule %d", o->sched);
+    return BERN_E_ARG;
+  }
+  if (o->plan < BERN_PLAN_PLAIN || o->plan > BERN_PLAN_LEARNED) {
+    set_error("unknown plan %d", o->plan);
+    return BERN_E_ARG;
+  }
+  return BERN_OK;
+}
+
+bern_status bern_workspace_size(const bern_net *net, const bern_opts *opts, int64_t n_boxes, size_t *bytes,
+                                size_t *one_box) {
+  bern_status st = check_opts(net, opts);
+  if (st != BERN_OK) return st;
+  if (!bytes || n_boxes < 1) { set_error("bad arguments"); return BERN_E_ARG; }
+  Plan p;
+  if ((st = plan_net(net, opts, p)) != BERN_OK) return st;
+  const int64_t wave = opts->sched == BERN_SCHED_PER_BOX ? 1 : n_boxes;
+  *bytes = p.per_box() * (size_t)wave;
+  if (one_box) *one_box = p.per_box();
+  return BERN_OK;
+}
+
+}  // extern "C"
+
+// Device-side validity of the boxes of a wave: flag[b] = 1 for a box with
+// d_lo > d_hi or a non-finite coordinate; such boxes get NaN bounds.
+__global__ void box_check_kernel(int n, int64_t nb, const double *lo, const double *hi, int *flag) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  int bad = 0;
+  for (int a = 0; a < n; ++a) {
+    const double l = lo[b * n + a], h = hi[b * n + a];
+    if (!(l <= h) || !std::isfinite(l) || !std::isfinite(h)) bad = 1;
+  }
+  flag[b] = bad;
+}
+
+__global__ void poison_kernel(int64_t nb, const int *flag, int nh, int o, double *nlo, double *nhi, double *olo,
+                              double *ohi) {
+  const int64_t b = blockIdx.x;
+  if (b >= nb || !flag[b]) return;
+  const double nan = __builtin_nan("");
+  for (int j = threadIdx.x; j < nh; j += blockDim.x) {
+    if (nlo) nlo[b * nh + j] = nan;
+    if (nhi) nhi[b * nh + j] = nan;
+  }
+  for (int j = threadIdx.x; j < o; j += blockDim.x) {
+    olo[b * o + j] = nan;
+    ohi[b * o + j] = nan;
+  }
+}
+
+// Enqueue the whole launch sequence of one wave of `B` boxes.
+static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts *o, int64_t B, const double *box_lo,
+                            const double *box_hi, const int8_t *plan, double *nlo, double *nhi, double *olo,
+                            double *ohi, int8_t *used, char *ws, hipStream_t s) {
+  char *cur = ws;
+  NeuronRec *recs = reinterpret_cast<NeuronRec *>(cur); cur += p.recs * B;
+  void *A = cur; cur += p.arenaA * B;
+  void *Bp = cur; cur += p.arenaB * B;
+  double *conv = reinterpret_cast<double *>(cur); cur += p.conv * B;
+  void *horner = cur; cur += p.horner * B;
+  int *flags = reinterpret_cast<int *>(cur);
+  const int n = net->n;
+
+  hipLaunchKernelGGL(box_check_kernel, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, n, B, box_lo, box_hi,
+                     flags);
+  BERN_HIP_TRY(hipGetLastError());
+
+  for (int i = 0; i < p.H; ++i) {
+    const int hin = net->widths[i], h = net->widths[i + 1];
+    const bool last = (i == p.H - 1);
+    // affine map -> pre-activation tensors in arena A
+    if (i == 0) {
+      Layer1Args a{n, h, B, box_lo, box_hi, net->W64 + net->woff[0], net->b64 + net->boff[0], A, p.fp64 ? 1 : 0};
+      BERN_HIP_TRY(launch_layer1(a, s));
+    } else {
+      GemmArgs a{};
+      a.hin = hin;
+      a.h = h;
+      a.C = p.Cpre[i];
+      a.nboxes = B;
+      a.post = Bp;
+      a.pre = A;
+      a.W = p.fp64 ? (const void *)(net->W64 + net->woff[i]) : (const void *)(net->W32 + net->woff[i]);
+      a.b = net->b64 + net->boff[i];
+      a.fp64 = p.fp64 ? 1 : 0;
+      BERN_HIP_TRY(launch_gemm(a, s));
+    }
+    // bounds read-off (+ rules and approximants for hidden layers)
+    ConvertArgs c{};
+    c.n = n;
+    c.D = p.Dpre[i];
+    c.h = h;
+    c.L = p.L;
+    c.C = p.Cpre[i];
+    c.nboxes = B;
+    c.pre = A;
+    c.fp64 = p.fp64 ? 1 : 0;
+    c.recs = recs;
+    c.scratch = conv;
+    c.scratch_bytes = p.conv * B;
+    c.plan = plan;
+    c.plan_ld = net->nh;
+    c.plan_col0 = last ? 0 : net->noff[i];
+    if (last) {
+      c.mode = 1;
+      c.out_lo = olo;
+      c.out_hi = ohi;
+      c.ld_out = net->o;
+      c.col0 = 0;
+      c.used = nullptr;
+    } else {
+      c.mode = 0;
+      c.out_lo = nlo;
+      c.out_hi = nhi;
+      c.ld_out = net->nh;
+      c.col0 = net->noff[i];
+      c.used = used;
+    }
+    BERN_HIP_TRY(launch_convert(c, s));
+    if (last) break;
+    // composition -> post tensors in arena B
+    ComposeArgs m{};
+    m.n = n;
+    m.Din = p.Dpre[i];
+    m.Dout = p.Dpost[i];
+    m.h = h;
+    m.nbounds = 2;
+    m.Lmax = p.Lmax;
+    m.Cin = p.Cpre[i];
+    m.Cout = p.Cpost[i];
+    m.Cq = ipow(p.Dpre[i] * std::max(1, p.Lmax - 1) + 1, n);
+    m.nboxes = B;
+    m.pre = A;
+    m.post = Bp;
+    m.recs = recs;
+    m.fp64 = p.fp64 ? 1 : 0;
+    m.scratch = horner;
+    m.scratch_bytes = p.horner * B;
+    BERN_HIP_TRY(launch_compose(m, s));
+  }
+  hipLaunchKernelGGL(poison_kernel, dim3((unsigned)B), dim3(64), 0, s, B, (const int *)flags, net->nh, net->o, nlo,
+                     nhi, olo, ohi);
+  BERN_HIP_TRY(hipGetLastError());
+  return BERN_OK;
+}
+
+extern "C" bern_status bern_bounds(const bern_net *net, const bern_opts *opts, int64_t n_boxes, const double *box_lo,
+                                   const double *box_hi, const int8_t *plan, double *neuron_lo, double *neuron_hi,
+                                   double *out_lo, double *out_hi, int8_t *used_plan, void *workspace,
+                                   size_t ws_bytes, void *stream, bern_stats *stats) {
+  bern_status st = check_opts(net, opts);
+  if (st != BERN_OK) return st;
+  if (n_boxes < 1 || !box_lo || !box_hi || !out_lo || !out_hi) {
+    set_error("bad arguments (n_boxes = %lld)", (long long)n_boxes);
+    return BERN_E_ARG;
+  }
+  if (!workspace || ((uintptr_t)workspace & 255)) {
+    set_error("workspace must be a non-null 256-byte aligned device pointer");
+    return BERN_E_WORKSPACE;
+  }
+  if (opts->plan == BERN_PLAN_GIVEN && !plan) {
+    set_error("BERN_PLAN_GIVEN needs a plan array");
+    return BERN_E_ARG;
+  }
+  Plan p;
+  if ((st = plan_net(net, opts, p)) != BERN_OK) return st;
+  const size_t per_box = p.per_box();
+  if (ws_bytes < per_box) {
+    set_error("workspace of %zu bytes is smaller than one box needs (%zu)", ws_bytes, per_box);
+    return BERN_E_WORKSPACE;
+  }
+  int64_t wave = (int64_t)(ws_bytes / per_box);
+  if (opts->sched == BERN_SCHED_PER_BOX) wave = 1;
+  if (opts->max_wave > 0) wave = std::min<int64_t>(wave, opts->max_wave);
+  wave = std::min<int64_t>(wave, std::min<int64_t>(n_boxes, 65535));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int nwaves = 0;
+  for (int64_t b0 = 0; b0 < n_boxes; b0 += wave) {
+    const int64_t B = std::min<int64_t>(wave, n_boxes - b0);
+    st = run_wave(net, p, opts, B, box_lo + b0 * net->n, box_hi + b0 * net->n,
+                  plan ? plan + b0 * net->nh : nullptr, neuron_lo ? neuron_lo + b0 * net->nh : nullptr,
+                  neuron_hi ? neuron_hi + b0 * net->nh : nullptr, out_lo + b0 * net->o, out_hi + b0 * net->o,
+                  used_plan ? used_plan + b0 * net->nh : nullptr, reinterpret_cast<char *>(workspace), s);
+    if (st != BERN_OK) return st;
+    ++nwaves;
+  }
+  if (stats) {
+    memset(stats, 0, sizeof(*stats));
+    stats->n_waves = nwaves;
+    stats->boxes_per_wave = (int32_t)wave;
+    stats->out_degree = p.Dpre[p.H - 1];
+    stats->workspace_used = per_box * (size_t)wave;
+  }
+  return BERN_OK;
+}
+
+// ---------------------------------------------------- step-level entry points
+extern "C" size_t bern_basis_minmax_scratch(int32_t n, int32_t D, int64_t count) {
+  return basis_minmax_scratch(n, D, count);
+}
+
+extern "C" bern_status bern_basis_minmax(int32_t n, int32_t D, int64_t count, const void *coef, int32_t fp64,
+                                         double *bern_out, double *mn, double *mx, double *l1, void *scratch,
+                                         size_t scratch_bytes, void *stream) {
+  if (n < 1 || n > kMaxInputs || D < 0 || D > 64 || count < 1 || count > 65535 || !coef || !mn || !mx) {
+    set_error("bad arguments");
+    return BERN_E_ARG;
+  }
+  (void)scratch_bytes;
+  hipError_t e = launch_basis_minmax(n, D, count, coef, fp64, bern_out, mn, mx, l1, (double *)scratch,
+                                     reinterpret_cast<hipStream_t>(stream));
+  if (e == hipErrorInvalidValue) {
+    set_error("tensor of (%d+1)^%d coefficients exceeds the one-block limit", D, n);
+    return BERN_E_TOO_LARGE;
+  }
+  BERN_HIP_TRY(e);
+  return BERN_OK;
+}
+
+extern "C" bern_status bern_poly_mul(int32_t n, int32_t da, int32_t db, int64_t count, const void *A,
+                                     const void *B, void *out, int32_t fp64, void *stream) {
+  if (n < 1 || n > kMaxInputs || da < 0 || db < 0 || da > 64 || db > 64 || count < 1 || count > 65535 || !A || !B ||
+      !out) {
+    set_error("bad arguments");
+    return BERN_E_ARG;
+  }
+  BERN_HIP_TRY(launch_poly_mul(n, da, db, count, A, B, out, fp64, reinterpret_cast<hipStream_t>(stream)));
+  return BERN_OK;
+}
+
+extern "C" bern_status bern_relu_poly(int64_t count, int32_t L, const double *lo, const double *hi, double *c,
+                                      double *e, void *stream) {
+  if (count < 1 || L < 1 || L > kMaxOrder || !lo || !hi || !c || !e) {
+    set_error("bad arguments");
+    return BERN_E_ARG;
+  }
+  BERN_HIP_TRY(launch_relu_poly(count, L, lo, hi, c, e, reinterpret_cast<hipStream_t>(stream)));
+  return BERN_OK;
+}

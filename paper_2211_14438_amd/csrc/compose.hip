@@ -1,0 +1,489 @@
+// Composition of the ReLU approximant with a neuron's input polynomials
+// (Step 3 of Section 5.1, eqs. post_bounds_1/2) on gfx950.
+//
+// For an unstable neuron with pre-activation interval [lo, hi] and ReLU order
+// L, with nu(P) = (P - lo)/(hi - lo) and the power series c_0..c_L of Step 2:
+//     U = sum_j c_j nu(U^)^j,        L = sum_j c_j nu(L^)^j - e.
+// Powers of a polynomial are products "Prod" (Section 4.2): dense n-d
+// convolutions of power-coefficient tensors. In the power basis, lifting a
+// tensor to a higher degree (Prop. 4 elevation) is a zero pad, and adding a
+// constant only touches the constant coefficient.
+//
+//  * order 2 (the common case): U = c_2 nu^2 + c_1 nu + c_0. The square nu^2
+//    is a symmetric convolution, computed over half of the index pairs. The
+//    tensor is split into outer axes and NI trailing "row" axes; nu sits in
+//    LDS row by row, each thread owns one output row and accumulates the
+//    row-by-row convolutions of its (I, K-I) outer pairs in registers.
+//  * order >= 3 (and degrees without a specialised kernel): Horner steps
+//    Q <- nu * Q + c_j, one launch per step, generic runtime degrees.
+//  * order 1, active (identity), inactive (zero) and the linear fallback are
+//    element-wise writes.
+// Every result is written at the layer's post degree Dout (zero padded).
+#include "common.hpp"
+
+namespace bern {
+
+__host__ __device__ constexpr int cpow(int b, int e) { return e == 0 ? 1 : b * cpow(b, e - 1); }
+
+// item index of (box, neuron j, bound s)
+__device__ inline int64_t item_of(const ComposeArgs &a, int64_t box, int j, int s) {
+  return (box * a.h + j) * a.nbounds + s;
+}
+
+__device__ inline void rec_of(const ComposeArgs &a, int64_t box, int j, int &kind, double &lo, double &w,
+                              const double *&c, double &e) {
+  if (a.recs) {
+    const NeuronRec &r = a.recs[box * a.h + j];
+    kind = r.kind;
+    lo = r.lo;
+    w = r.hi - r.lo;
+    c = r.c;
+    e = r.e;
+  } else {  // plain product mode (step-level entry point): nu = P, out = P^2
+    kind = 2;
+    lo = 0.0;
+    w = 1.0;
+    c = nullptr;
+    e = 0.0;
+  }
+}
+
+// ------------------------------------------------------------ row conv
+template <typename T, int D, int NI>
+__device__ __forceinline__ void row_conv(const T *ra, const T *rb, T *acc) {
+  constexpr int D1 = D + 1, E1 = 2 * D + 1;
+  if constexpr (NI == 1) {
+#pragma unroll
+    for (int i = 0; i < D1; ++i)
+#pragma unroll
+      for (int j = 0; j < D1; ++j) acc[i + j] = fma(ra[i], rb[j], acc[i + j]);
+  } else {
+#pragma unroll
+    for (int i0 = 0; i0 < D1; ++i0)
+#pragma unroll
+      for (int i1 = 0; i1 < D1; ++i1)
+#pragma unroll
+        for (int j0 = 0; j0 < D1; ++j0)
+#pragma unroll
+          for (int j1 = 0; j1 < D1; ++j1)
+            acc[(i0 + j0) * E1 + i1 + j1] = fma(ra[i0 * D1 + i1], rb[j0 * D1 + j1], acc[(i0 + j0) * E1 + i1 + j1]);
+  }
+}
+
+// Square path: nu in LDS as rows of R = (D+1)^NI coefficients (pitch RP);
+// thread = one output row of the layer's post tensor.
+template <typename T, int D, int NI>
+__global__ void __launch_bounds__(kBlock) compose_sq_kernel(ComposeArgs a) {
+  constexpr int D1 = D + 1, E1 = 2 * D + 1;
+  constexpr int R = cpow(D1, NI), RO = cpow(E1, NI);
+  constexpr int RP = (R + 3) & ~3;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *rows = reinterpret_cast<T *>(smem_raw);
+
+  const int j = blockIdx.y / a.nbounds, s = blockIdx.y % a.nbounds;
+  const int64_t box = blockIdx.z;
+  int kind;
+  double lo, w, e;
+  const double *cc;
+  rec_of(a, box, j, kind, lo, w, cc, e);
+  if (kind != 2) return;
+
+  const int no = a.n - NI;
+  const int64_t it = item_of(a, box, j, s);
+  const T *p = reinterpret_cast<const T *>(a.pre) + it * a.Cin;
+  for (int64_t i = threadIdx.x; i < a.Cin; i += blockDim.x) {
+    double v = (double)p[i];
+    if (i == 0) v -= lo;
+    rows[(i / R) * RP + (i % R)] = (T)(v / w);
+  }
+  __syncthreads();
+
+  const int Do1 = a.Dout + 1;
+  int64_t Mo = 1;
+  for (int q = 0; q < no; ++q) Mo *= Do1;
+  const int64_t ko = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ko >= Mo) return;
+  const int Rout = (NI == 1) ? Do1 : Do1 * Do1;
+  T *out = reinterpret_cast<T *>(a.post) + it * a.Cout + ko * Rout;
+
+  // outer digits of ko (base Dout+1): per-axis pair ranges packed 4 bits/axis
+  uint64_t lop = 0, hip = 0;
+  int64_t rK = 0, cnt = 1;
+  bool zero = false, lin_ok = true, origin = true;
+  {
+    int64_t rem = ko, pw = 1;
+    for (int q = no - 1; q >= 0; --q) {
+      const int k = (int)(rem % Do1);
+      rem /= Do1;
+      if (k > 2 * D) zero = true;
+      const int l = max(0, k - D), hh = min(k, D);
+      const int sh = 4 * (no - 1 - q);
+      lop |= (uint64_t)(l & 15) << sh;
+      hip |= (uint64_t)(hh & 15) << sh;
+      cnt *= (hh - l + 1);
+      rK += (int64_t)k * pw;
+      pw *= D1;
+      if (k > D) lin_ok = false;
+      if (k != 0) origin = false;
+    }
+  }
+  if (zero) {
+    for (int q = 0; q < Rout; ++q) out[q] = (T)0;
+    return;
+  }
+
+  T acc[RO];
+#pragma unroll
+  for (int q = 0; q < RO; ++q) acc[q] = (T)0;
+  int64_t rI = 0;
+  {
+    int64_t pw = 1;
+    for (int q = no - 1; q >= 0; --q) {
+      rI += (int64_t)((lop >> (4 * (no - 1 - q))) & 15) * pw;
+      pw *= D1;
+    }
+  }
+  uint64_t iv = lop;
+  const int64_t half = cnt >> 1;
+  for (int64_t t = 0; t < half; ++t) {
+    T ra[R], rb[R];
+    const T *pa = rows + rI * RP;
+    const T *pb = rows + (rK - rI) * RP;
+#pragma unroll
+    for (int q = 0; q < R; ++q) { ra[q] = pa[q]; rb[q] = pb[q]; }
+    row_conv<T, D, NI>(ra, rb, acc);
+    int64_t pw = 1;
+    for (int q = no - 1; q >= 0; --q) {
+      const int sh = 4 * (no - 1 - q);
+      const int d = (int)((iv >> sh) & 15), hh = (int)((hip >> sh) & 15);
+      if (d < hh) {
+        iv += (uint64_t)1 << sh;
+        rI += pw;
+        break;
+      }
+      const int l = (int)((lop >> sh) & 15);
+      iv = (iv & ~((uint64_t)15 << sh)) | ((uint64_t)l << sh);
+      rI -= (int64_t)(d - l) * pw;
+      pw *= D1;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < RO; ++q) acc[q] = acc[q] + acc[q];
+  if (cnt & 1) {  // middle pair I = K - I
+    T ra[R];
+    const T *pa = rows + rI * RP;
+#pragma unroll
+    for (int q = 0; q < R; ++q) ra[q] = pa[q];
+    row_conv<T, D, NI>(ra, ra, acc);
+  }
+
+  // epilogue: c2 nu^2 + c1 nu + (c0 - e for the lower bound)
+  const T c2 = cc ? (T)cc[2] : (T)1;
+  const T c1 = cc ? (T)cc[1] : (T)0;
+  const T cst = cc ? (T)(cc[0] - (s == 1 ? e : 0.0)) : (T)0;
+  T lin[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) lin[q] = (T)0;
+  if (lin_ok) {
+    const T *pl = rows + rK * RP;
+#pragma unroll
+    for (int q = 0; q < R; ++q) lin[q] = pl[q];
+  }
+  if (a.Dout != 2 * D)
+    for (int q = 0; q < Rout; ++q) out[q] = (T)0;
+  if constexpr (NI == 1) {
+#pragma unroll
+    for (int q0 = 0; q0 < E1; ++q0) {
+      T v = c2 * acc[q0];
+      if (q0 <= D) v = fma(c1, lin[q0], v);
+      if (origin && q0 == 0) v += cst;
+      out[q0] = v;
+    }
+  } else {
+#pragma unroll
+    for (int q0 = 0; q0 < E1; ++q0)
+#pragma unroll
+      for (int q1 = 0; q1 < E1; ++q1) {
+        T v = c2 * acc[q0 * E1 + q1];
+        if (q0 <= D && q1 <= D) v = fma(c1, lin[q0 * D1 + q1], v);
+        if (origin && q0 == 0 && q1 == 0) v += cst;
+        out[q0 * Do1 + q1] = v;
+      }
+  }
+}
+
+// ------------------------------------------------- element-wise rules
+// inactive -> 0, active -> copy, order 1 -> c1 nu + c0 (- e), fallback -> affine.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) compose_simple_kernel(ComposeArgs a) {
+  const int j = blockIdx.y / a.nbounds, s = blockIdx.y % a.nbounds;
+  const int64_t box = blockIdx.z;
+  const NeuronRec &r = a.recs[box * a.h + j];
+  const int kind = r.kind;
+  if (kind >= 2) return;
+  const int64_t it = item_of(a, box, j, s);
+  const T *p = reinterpret_cast<const T *>(a.pre) + it * a.Cin;
+  T *out = reinterpret_cast<T *>(a.post) + it * a.Cout;
+  const int Do1 = a.Dout + 1, Di1 = a.Din + 1;
+  for (int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; K < a.Cout; K += (int64_t)gridDim.x * blockDim.x) {
+    // digits of K in base Dout+1 -> index in the input tensor (base Din+1)
+    int64_t rem = K, idx = 0, pw = 1;
+    bool inside = true;
+    int ones = 0, one_axis = -1;
+    for (int q = a.n - 1; q >= 0; --q) {
+      const int k = (int)(rem % Do1);
+      rem /= Do1;
+      if (k > a.Din) inside = false;
+      idx += (int64_t)k * pw;
+      pw *= Di1;
+      if (k == 1) { ++ones; one_axis = q; }
+      else if (k != 0) ones = 100;
+    }
+    double v = 0.0;
+    if (kind == kActive) {
+      v = inside ? (double)p[idx] : 0.0;
+    } else if (kind == 1) {
+      if (inside) {
+        double x = (double)p[idx];
+        if (K == 0) x -= r.lo;
+        v = r.c[1] * (x / (r.hi - r.lo));
+      }
+      if (K == 0) v += r.c[0] - (s == 1 ? r.e : 0.0);
+    } else if (kind == kFallback) {
+      const double *fb = (s == 0) ? r.fbU : r.fbL;
+      if (K == 0) v = fb[0];
+      else if (ones == 1) v = fb[1 + one_axis];
+    }
+    out[K] = (T)v;
+  }
+}
+
+// ------------------------------------------------ generic Horner step
+// Step m (1 <= m <= L-1) of Q^(m) = nu * Q^(m-1) + c_{L-1-m}, where
+// Q^(0) = c_L nu + c_{L-1}; Q^(m) has degree (m+1) Din. The last step adds
+// -e (lower bound) and writes the post tensor at degree Dout.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) compose_horner_kernel(ComposeArgs a, int m, int sq_D) {
+  const int j = blockIdx.y / a.nbounds, s = blockIdx.y % a.nbounds;
+  const int64_t box = blockIdx.z;
+  const NeuronRec &r = a.recs[box * a.h + j];
+  const int L = r.kind;
+  if (L < 2 || (L == 2 && sq_D == a.Din) || m > L - 1) return;
+  const bool last = (m == L - 1);
+  const int64_t it = item_of(a, box, j, s);
+  const T *p = reinterpret_cast<const T *>(a.pre) + it * a.Cin;
+  const int Din = a.Din, Di1 = Din + 1;
+  const int dq = m * Din;          // degree of Q^(m-1)
+  const int dout_m = (m + 1) * Din; // degree of Q^(m)
+  const int Dt = last ? a.Dout : dout_m;  // degree of the written tensor
+  const int64_t Ct = last ? a.Cout : ipow(dout_m + 1, a.n);
+  T *dst = last ? reinterpret_cast<T *>(a.post) + it * a.Cout
+                : reinterpret_cast<T *>(a.scratch) + (it * 2 + (m & 1)) * a.Cq;
+  const T *qsrc = reinterpret_cast<const T *>(a.scratch) + (it * 2 + ((m - 1) & 1)) * a.Cq;
+  const double lo = r.lo, w = r.hi - r.lo;
+  const double cL = r.c[L], cL1 = r.c[L - 1], cadd = r.c[L - 1 - m];
+  const int Dq1 = dq + 1;
+  for (int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; K < Ct; K += (int64_t)gridDim.x * blockDim.x) {
+    int k[kMaxInputs];
+    int64_t rem = K;
+    bool inside = true;
+    for (int q = a.n - 1; q >= 0; --q) {
+      k[q] = (int)(rem % (Dt + 1));
+      rem /= (Dt + 1);
+      if (k[q] > dout_m) inside = false;
+    }
+    double v = 0.0;
+    if (inside) {
+      int lo_[kMaxInputs], hi_[kMaxInputs], i[kMaxInputs];
+      bool any = true;
+      for (int q = 0; q < a.n; ++q) {
+        lo_[q] = max(0, k[q] - dq);
+        hi_[q] = min(k[q], Din);
+        i[q] = lo_[q];
+        if (lo_[q] > hi_[q]) any = false;
+      }
+      while (any) {
+        int64_t iI = 0, iJ = 0;
+        for (int q = 0; q < a.n; ++q) {
+          iI = iI * Di1 + i[q];
+          iJ = iJ * Dq1 + (k[q] - i[q]);
+        }
+        double nu = (double)p[iI];
+        if (iI == 0) nu -= lo;
+        nu /= w;
+        double qv;
+        if (m == 1) {
+          double x = (double)p[iJ];
+          if (iJ == 0) x -= lo;
+          qv = cL * (x / w) + (iJ == 0 ? cL1 : 0.0);
+        } else {
+          qv = (double)qsrc[iJ];
+        }
+        v = fma(nu, qv, v);
+        int q = a.n - 1;
+        for (; q >= 0; --q) {
+          if (i[q] < hi_[q]) { ++i[q]; break; }
+          i[q] = lo_[q];
+        }
+        if (q < 0) any = false;
+      }
+      if (K == 0) v += cadd - ((last && s == 1) ? r.e : 0.0);
+    }
+    dst[K] = (T)v;
+  }
+}
+
+// ------------------------------------------------ plain product kernel
+template <typename T>
+__global__ void __launch_bounds__(kBlock) polymul_kernel(int n, int da, int db, int64_t count, const T *A, const T *B,
+                                                         T *out) {
+  const int dc = da + db;
+  const int64_t Ca = ipow(da + 1, n), Cb = ipow(db + 1, n), Cc = ipow(dc + 1, n);
+  const int64_t it = blockIdx.y;
+  for (int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; K < Cc; K += (int64_t)gridDim.x * blockDim.x) {
+    int k[kMaxInputs], lo_[kMaxInputs], hi_[kMaxInputs], i[kMaxInputs];
+    int64_t rem = K;
+    for (int q = n - 1; q >= 0; --q) {
+      k[q] = (int)(rem % (dc + 1));
+      rem /= (dc + 1);
+    }
+    for (int q = 0; q < n; ++q) {
+      lo_[q] = max(0, k[q] - db);
+      hi_[q] = min(k[q], da);
+      i[q] = lo_[q];
+    }
+    double v = 0.0;
+    bool more = true;
+    while (more) {
+      int64_t iI = 0, iJ = 0;
+      for (int q = 0; q < n; ++q) {
+        iI = iI * (da + 1) + i[q];
+        iJ = iJ * (db + 1) + (k[q] - i[q]);
+      }
+      v = fma((double)A[it * Ca + iI], (double)B[it * Cb + iJ], v);
+      int q = n - 1;
+      for (; q >= 0; --q) {
+        if (i[q] < hi_[q]) { ++i[q]; break; }
+        i[q] = lo_[q];
+      }
+      if (q < 0) more = false;
+    }
+    out[it * Cc + K] = (T)v;
+  }
+}
+
+// ------------------------------------------------------------ dispatch
+template <typename T, int D, int NI>
+static hipError_t launch_sq(const ComposeArgs &a, hipStream_t s) {
+  constexpr int R = cpow(D + 1, NI), RP = (R + 3) & ~3;
+  const int no = a.n - NI;
+  const int64_t Mo = ipow(a.Dout + 1, no);
+  const size_t lds = (size_t)(a.Cin / R) * RP * sizeof(T);
+  if (lds > device_lds_limit()) return hipErrorNotSupported;
+  RET_IF(hipFuncSetAttribute((const void *)compose_sq_kernel<T, D, NI>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)lds));
+  dim3 grid((unsigned)((Mo + kBlock - 1) / kBlock), (unsigned)(a.h * a.nbounds), (unsigned)a.nboxes);
+  hipLaunchKernelGGL((compose_sq_kernel<T, D, NI>), grid, dim3(kBlock), lds, s, a);
+  return hipGetLastError();
+}
+
+// Returns the degree the square kernel handles for this launch (or -1).
+template <typename T>
+static int sq_dispatch(const ComposeArgs &a, hipStream_t s, hipError_t &err) {
+  const int D = a.Din;
+  const bool ni2 = a.n >= 2;
+  if (a.Dout < 2 * D) return -1;
+  err = hipSuccess;
+  switch (D) {
+    case 1: err = ni2 ? launch_sq<T, 1, 2>(a, s) : launch_sq<T, 1, 1>(a, s); break;
+    case 2: err = ni2 ? launch_sq<T, 2, 2>(a, s) : launch_sq<T, 2, 1>(a, s); break;
+    case 3: err = ni2 ? launch_sq<T, 3, 2>(a, s) : launch_sq<T, 3, 1>(a, s); break;
+    case 4: err = ni2 ? launch_sq<T, 4, 2>(a, s) : launch_sq<T, 4, 1>(a, s); break;
+    case 5: err = launch_sq<T, 5, 1>(a, s); break;
+    case 6: err = launch_sq<T, 6, 1>(a, s); break;
+    case 7: err = launch_sq<T, 7, 1>(a, s); break;
+    case 8: err = launch_sq<T, 8, 1>(a, s); break;
+    default: return -1;
+  }
+  if (err == hipErrorNotSupported) {  // nu does not fit LDS: Horner path instead
+    (void)hipGetLastError();
+    err = hipSuccess;
+    return -1;
+  }
+  return err == hipSuccess ? D : -1;
+}
+
+template <typename T>
+static hipError_t compose_all(const ComposeArgs &a, hipStream_t s) {
+  // element-wise rules
+  {
+    const int64_t blocks = std::min<int64_t>((a.Cout + kBlock - 1) / kBlock, 4096);
+    dim3 grid((unsigned)blocks, (unsigned)(a.h * a.nbounds), (unsigned)a.nboxes);
+    hipLaunchKernelGGL(compose_simple_kernel<T>, grid, dim3(kBlock), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  // order-2 square
+  hipError_t err = hipSuccess;
+  const int sqD = sq_dispatch<T>(a, s, err);
+  if (err != hipSuccess) return err;
+  // Horner steps for higher orders (and order 2 without a square kernel)
+  const int Lmax = a.Lmax;
+  if (Lmax >= 3 || (Lmax == 2 && sqD != a.Din)) {
+    for (int m = 1; m <= Lmax - 1; ++m) {
+      const int64_t Ct = std::max<int64_t>(a.Cout, ipow(a.Din * (m + 1) + 1, a.n));
+      const int64_t blocks = std::min<int64_t>((Ct + kBlock - 1) / kBlock, 4096);
+      dim3 grid((unsigned)blocks, (unsigned)(a.h * a.nbounds), (unsigned)a.nboxes);
+      hipLaunchKernelGGL(compose_horner_kernel<T>, grid, dim3(kBlock), 0, s, a, m, sqD);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_compose(const ComposeArgs &a, hipStream_t s) {
+  return a.fp64 ? compose_all<double>(a, s) : compose_all<float>(a, s);
+}
+
+size_t compose_scratch_bytes(int n, int Din, int Lmax, int h, int64_t nboxes, int fp64) {
+  if (Lmax < 2) return 0;
+  const int64_t Cq = ipow(Din * (Lmax - 1) + 1, n);
+  return align256((size_t)nboxes * h * 2 * 2 * Cq * (fp64 ? 8 : 4));
+}
+
+hipError_t launch_poly_mul(int n, int da, int db, int64_t count, const void *A, const void *B, void *out, int fp64,
+                           hipStream_t s) {
+  const int64_t Cc = ipow(da + db + 1, n);
+  if (A == B && da == db) {
+    ComposeArgs a{};
+    a.n = n;
+    a.Din = da;
+    a.Dout = 2 * da;
+    a.h = 1;
+    a.nbounds = 1;
+    a.Lmax = 2;
+    a.Cin = ipow(da + 1, n);
+    a.Cout = Cc;
+    a.nboxes = count;
+    a.pre = A;
+    a.post = out;
+    a.recs = nullptr;
+    a.fp64 = fp64;
+    hipError_t err = hipSuccess;
+    const int d = fp64 ? sq_dispatch<double>(a, s, err) : sq_dispatch<float>(a, s, err);
+    if (err != hipSuccess) return err;
+    if (d == da) return hipSuccess;
+  }
+  const int64_t blocks = std::min<int64_t>((Cc + kBlock - 1) / kBlock, 4096);
+  dim3 grid((unsigned)blocks, (unsigned)count);
+  if (fp64)
+    hipLaunchKernelGGL(polymul_kernel<double>, grid, dim3(kBlock), 0, s, n, da, db, count, (const double *)A,
+                       (const double *)B, (double *)out);
+  else
+    hipLaunchKernelGGL(polymul_kernel<float>, grid, dim3(kBlock), 0, s, n, da, db, count, (const float *)A,
+                       (const float *)B, (float *)out);
+  return hipGetLastError();
+}
+
+}  // namespace bern

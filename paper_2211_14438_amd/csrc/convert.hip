@@ -1,0 +1,480 @@
+// Bounds read-off (Step 1 of Section 5.1, Def. 2) and the ReLU approximant
+// (Step 2) on gfx950.
+//
+// A pre-activation polynomial of per-variable degree D arrives as power
+// coefficients a_J in the box coordinate t. Its Bernstein coefficients at
+// degree D follow from the identity t^j = sum_{k>=j} C(k,j)/C(D,j) B_{k,D}(t)
+// applied along every variable: a triangular (D+1)x(D+1) contraction per
+// axis, b_k = sum_{j<=k} C(k,j)/C(D,j) a_j. The range enclosure (Def. 2) then
+// gives lo = min b(lower) and hi = max b(upper). The contraction always runs
+// in FP64, whatever the tensor precision.
+//
+// Tensors that fit the LDS budget are converted by one block each, all axes
+// in LDS. Larger tensors take two passes: the trailing axes that fit LDS are
+// converted per slice into an FP64 staging buffer, then the leading axes are
+// converted per column chunk and reduced to per-chunk extrema, which a last
+// small kernel folds.
+//
+// The same kernels pick each hidden neuron's rule (stable neurons, Section 5.1
+// readings; plan codes) and build the ReLU over-approximant of Step 2: Bernstein
+// coefficients b_k = sigma(lo + (hi-lo) k/L) (eq. bernpolcoeff2) turned into
+// the power series in u = (y-lo)/(hi-lo) by forward differences,
+// c_j = C(L,j) Delta^j b_0, and its value e at y = 0 (Prop. 2).
+#include "common.hpp"
+
+namespace bern {
+
+constexpr int kSmallLds = 16384;  // FP64 elements of a tensor converted in one block (128 KiB)
+constexpr int kTileLds = 8192;    // FP64 elements per staged tile of the two-pass path
+
+__device__ inline double binom_d(int n, int k) {
+  if (k < 0 || k > n) return 0.0;
+  if (k > n - k) k = n - k;
+  double r = 1.0;
+  for (int i = 1; i <= k; ++i) r = r * (double)(n - k + i) / (double)i;
+  return rint(r);
+}
+
+// Block-wide reductions over wave64 shuffles + LDS.
+template <typename Op>
+__device__ double block_reduce(double v, Op op, double *red) {
+  for (int off = 32; off > 0; off >>= 1) v = op(v, __shfl_xor(v, off, 64));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = op(r, red[w]);
+    red[0] = r;
+  }
+  __syncthreads();
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+struct OpMin { __device__ double operator()(double a, double b) const { return fmin(a, b); } };
+struct OpMax { __device__ double operator()(double a, double b) const { return fmax(a, b); } };
+struct OpAdd { __device__ double operator()(double a, double b) const { return a + b; } };
+
+// ReLU over-approximant on [lo, hi] (lo < 0 < hi) of order L: power
+// coefficients c[0..L] in u and e = value at y = 0.
+__device__ void relu_poly_dev(double lo, double hi, int L, double *c, double *e) {
+  double d[kMaxOrder + 1];
+#pragma unroll
+  for (int k = 0; k <= kMaxOrder; ++k) {
+    const double y = lo + (hi - lo) * (double)k / (double)L;
+    d[k] = (k <= L) ? fmax(y, 0.0) : 0.0;
+  }
+#pragma unroll
+  for (int j = 1; j <= kMaxOrder; ++j) {
+#pragma unroll
+    for (int k = kMaxOrder; k >= j; --k)
+      if (j <= L && k <= L) d[k] -= d[k - 1];
+  }
+#pragma unroll
+  for (int j = 0; j <= kMaxOrder; ++j) c[j] = (j <= L) ? binom_d(L, j) * d[j] : 0.0;
+  const double u0 = -lo / (hi - lo);
+  double v = 0.0;
+#pragma unroll
+  for (int j = kMaxOrder; j >= 0; --j)
+    if (j <= L) v = fma(v, u0, c[j]);
+  *e = v;
+}
+
+// In-place per-axis basis change of a tensor held in LDS (`t`, C doubles),
+// axes [ax0, n). Table tab[k*(D+1)+j] = C(k,j)/C(D,j).
+__device__ void lds_basis_change(double *t, int64_t C, int n, int D, int ax0, int ax1, const double *tab) {
+  const int D1 = D + 1;
+  int64_t stride = 1;
+  for (int ax = n - 1; ax >= ax0; --ax) {
+    if (ax < ax1) {
+      const int64_t fibres = C / D1;
+      for (int64_t f = threadIdx.x; f < fibres; f += blockDim.x) {
+        const int64_t base = (f / stride) * stride * D1 + (f % stride);
+        // descending k keeps the inputs a_j (j < k) intact until they are used
+        for (int k = D; k >= 0; --k) {
+          double s = 0.0;
+          for (int j = 0; j <= k; ++j) s = fma(tab[k * D1 + j], t[base + (int64_t)j * stride], s);
+          t[base + (int64_t)k * stride] = s;
+        }
+      }
+      __syncthreads();
+    }
+    stride *= D1;
+  }
+}
+
+__device__ void fill_table(double *tab, int D) {
+  const int D1 = D + 1;
+  for (int i = threadIdx.x; i < D1 * D1; i += blockDim.x) {
+    const int k = i / D1, j = i % D1;
+    tab[i] = (j <= k) ? binom_d(k, j) / binom_d(D, j) : 0.0;
+  }
+  __syncthreads();
+}
+
+// Least-squares affine fit of the Bernstein control net {(K/D, b_K)} and the
+// extreme remainder (linear fallback rule). Outputs beta[0] = mean,
+// beta[1+a] = slope along axis a for l(t) = beta0 + sum beta_a (t_a - 1/2),
+// and *ext = max (upper, sign > 0) or min (lower) of b_K - l(K/D).
+__device__ void lds_affine_fit(const double *t, int64_t C, int n, int D, int sign, double *beta, double *ext,
+                               double *red) {
+  const int D1 = D + 1;
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < C; i += blockDim.x) m += t[i];
+  beta[0] = block_reduce(m, OpAdd(), red) / (double)C;
+  // sum over one axis of (k/D - 1/2)^2, times the other axes' sizes
+  double s1 = 0.0;
+  for (int k = 0; k <= D; ++k) { const double s = (double)k / D - 0.5; s1 += s * s; }
+  const double ss = s1 * (double)(C / D1);
+  int64_t stride = C / D1;  // stride of axis 0
+  for (int a = 0; a < n; ++a) {
+    double p = 0.0;
+    for (int64_t i = threadIdx.x; i < C; i += blockDim.x) {
+      const int k = (int)((i / stride) % D1);
+      p += t[i] * ((double)k / D - 0.5);
+    }
+    beta[1 + a] = block_reduce(p, OpAdd(), red) / ss;
+    stride /= D1;
+  }
+  double e = sign > 0 ? -INFINITY : INFINITY;
+  for (int64_t i = threadIdx.x; i < C; i += blockDim.x) {
+    double l = beta[0];
+    int64_t rem = i;
+    for (int a = n - 1; a >= 0; --a) {
+      const int k = (int)(rem % D1);
+      rem /= D1;
+      l += beta[1 + a] * ((double)k / D - 0.5);
+    }
+    const double r = t[i] - l;
+    e = sign > 0 ? fmax(e, r) : fmin(e, r);
+  }
+  *ext = sign > 0 ? block_reduce(e, OpMax(), red) : block_reduce(e, OpMin(), red);
+}
+
+// Choose the rule of one hidden neuron and fill its record (thread 0 only).
+__device__ void finish_neuron(const ConvertArgs &a, int64_t box, int j, double lo, double hi, const double *fitU,
+                              double extU, const double *fitL, double extL) {
+  NeuronRec &r = a.recs[box * a.h + j];
+  r.lo = lo;
+  r.hi = hi;
+  r.padU = r.padL = 0.0;
+  int code = a.L;
+  if (a.plan) code = a.plan[box * a.plan_ld + a.plan_col0 + j];
+  int kind, deg;
+  if (!(hi > 0.0)) { kind = kInactive; deg = 0; }     // hi <= 0 (also NaN) -> zero polynomial
+  else if (lo >= 0.0) { kind = kActive; deg = a.D; }
+  else if (code >= 1) { kind = code; deg = code * a.D; }
+  else { kind = kFallback; deg = 1; }
+  if (!a.plan) deg = a.L * a.D;  // plain rule: uniform degree per layer
+  r.kind = kind;
+  r.deg = deg;
+#pragma unroll
+  for (int k = 0; k <= kMaxOrder; ++k) r.c[k] = 0.0;
+  r.e = 0.0;
+  if (kind >= 1) relu_poly_dev(lo, hi, kind, r.c, &r.e);
+  if (kind == kFallback) {
+    // degree-1 approximant: upper lambda (U^ - lo), lower lambda L^; both
+    // replaced by their least-squares affine fit plus the extreme remainder.
+    const double lam = hi / (hi - lo);
+    double sU = 0.0, sL = 0.0;
+    for (int ax = 0; ax < a.n; ++ax) { sU += fitU[1 + ax]; sL += fitL[1 + ax]; }
+    r.fbU[0] = lam * (fitU[0] - lo - 0.5 * sU + extU);
+    r.fbL[0] = lam * (fitL[0] - 0.5 * sL + extL);
+    for (int ax = 0; ax < a.n; ++ax) {
+      r.fbU[1 + ax] = lam * fitU[1 + ax];
+      r.fbL[1 + ax] = lam * fitL[1 + ax];
+    }
+  }
+  if (a.used) a.used[box * a.ld_out + a.col0 + j] = (int8_t)kind;
+}
+
+// One block per (box, neuron): both bounds of the neuron, all axes in LDS.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) convert_small_kernel(ConvertArgs a) {
+  extern __shared__ double lds[];
+  const int D1 = a.D + 1;
+  double *t = lds;
+  double *tab = lds + a.C;
+  double *red = tab + D1 * D1;
+  __shared__ double fit[2][kMaxInputs + 1];
+  __shared__ double ext[2];
+  const int64_t item = blockIdx.x;  // box * h + j
+  const int64_t box = item / a.h;
+  const int j = (int)(item % a.h);
+  fill_table(tab, a.D);
+  const bool want_fit = a.mode == 0 && a.plan && a.D > 0 && a.plan[box * a.plan_ld + a.plan_col0 + j] == 0;
+  if (threadIdx.x < 2 * (kMaxInputs + 1)) fit[threadIdx.x / (kMaxInputs + 1)][threadIdx.x % (kMaxInputs + 1)] = 0.0;
+  if (threadIdx.x < 2) ext[threadIdx.x] = 0.0;
+  double ext_lo = 0.0, ext_hi = 0.0;
+  for (int s = 1; s >= 0; --s) {  // lower first, then upper
+    const T *p = reinterpret_cast<const T *>(a.pre) + (item * 2 + s) * a.C;
+    for (int64_t i = threadIdx.x; i < a.C; i += blockDim.x) t[i] = (double)p[i];
+    __syncthreads();
+    lds_basis_change(t, a.C, a.n, a.D, 0, a.n, tab);
+    double v = s ? INFINITY : -INFINITY;
+    for (int64_t i = threadIdx.x; i < a.C; i += blockDim.x) v = s ? fmin(v, t[i]) : fmax(v, t[i]);
+    v = s ? block_reduce(v, OpMin(), red) : block_reduce(v, OpMax(), red);
+    if (s) ext_lo = v; else ext_hi = v;
+    if (want_fit) {
+      double beta[kMaxInputs + 1];
+      double e;
+      lds_affine_fit(t, a.C, a.n, a.D, s ? -1 : 1, beta, &e, red);
+      if (threadIdx.x == 0) {
+        for (int ax = 0; ax <= a.n; ++ax) fit[s][ax] = beta[ax];
+        ext[s] = e;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (a.mode == 1) {
+      a.out_lo[box * a.ld_out + a.col0 + j] = ext_lo;
+      a.out_hi[box * a.ld_out + a.col0 + j] = ext_hi;
+    } else {
+      if (a.out_lo) a.out_lo[box * a.ld_out + a.col0 + j] = ext_lo;
+      if (a.out_hi) a.out_hi[box * a.ld_out + a.col0 + j] = ext_hi;
+      finish_neuron(a, box, j, ext_lo, ext_hi, fit[0], want_fit ? ext[0] : 0.0, fit[1], want_fit ? ext[1] : 0.0);
+    }
+  }
+}
+
+// ---------------------------------------------------------- two-pass path
+struct Split {
+  int m;         // trailing axes converted in pass A
+  int64_t Ci;    // (D+1)^m
+  int64_t Co;    // (D+1)^(n-m)
+  int64_t Q;     // inner columns per pass-B tile
+  int64_t nchunk;
+};
+
+// FP64 elements of one staged tile: the smaller of kTileLds and what the
+// device lets one block hold next to the basis-change table.
+static int64_t tile_elems(int D) {
+  const int64_t fit = (int64_t)(device_lds_limit() / sizeof(double)) - (int64_t)(D + 1) * (D + 1) - 64;
+  return std::min<int64_t>(kTileLds, fit);
+}
+
+static Split make_split(int n, int D) {
+  Split s{};
+  const int64_t tile = tile_elems(D);
+  s.m = 0;
+  s.Ci = 1;
+  while (s.m < n && s.Ci * (D + 1) <= tile) { s.Ci *= (D + 1); ++s.m; }
+  s.Co = ipow(D + 1, n - s.m);
+  s.Q = tile / (s.Co > 0 ? s.Co : 1);
+  int64_t q = 1;
+  while (q * 2 <= s.Q) q *= 2;
+  s.Q = q < 1 ? 1 : q;
+  if (s.Q > s.Ci) s.Q = s.Ci;
+  s.nchunk = (s.Ci + s.Q - 1) / s.Q;
+  return s;
+}
+
+// Pass A: one block per (tensor, outer slice): convert the m trailing axes.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) convert_passA_kernel(ConvertArgs a, Split sp) {
+  extern __shared__ double lds[];
+  const int D1 = a.D + 1;
+  double *t = lds;
+  double *tab = lds + sp.Ci;
+  const int64_t tensor = blockIdx.y;  // (box*h + j)*2 + s
+  const int64_t o = blockIdx.x;
+  fill_table(tab, a.D);
+  const T *p = reinterpret_cast<const T *>(a.pre) + tensor * a.C + o * sp.Ci;
+  for (int64_t i = threadIdx.x; i < sp.Ci; i += blockDim.x) t[i] = (double)p[i];
+  __syncthreads();
+  lds_basis_change(t, sp.Ci, sp.m, a.D, 0, sp.m, tab);
+  double *q = a.scratch + tensor * a.C + o * sp.Ci;
+  for (int64_t i = threadIdx.x; i < sp.Ci; i += blockDim.x) q[i] = t[i];
+  (void)D1;
+}
+
+// Pass B: one block per (tensor, column chunk): convert the n-m leading axes
+// of a [Co][Q] tile and reduce it to one extremum (min for lower bounds,
+// max for upper bounds) written to the partials area.
+__global__ void __launch_bounds__(kBlock) convert_passB_kernel(ConvertArgs a, Split sp, double *partial) {
+  extern __shared__ double lds[];
+  const int D1 = a.D + 1;
+  double *t = lds;                      // [Co][Q]
+  double *tab = lds + sp.Co * sp.Q;
+  double *red = tab + D1 * D1;
+  const int64_t tensor = blockIdx.y;
+  const int s = (int)(tensor & 1);
+  const int64_t q0 = (int64_t)blockIdx.x * sp.Q;
+  const int64_t qn = min(sp.Q, sp.Ci - q0);
+  fill_table(tab, a.D);
+  const double *src = a.scratch + tensor * a.C;
+  for (int64_t i = threadIdx.x; i < sp.Co * sp.Q; i += blockDim.x) {
+    const int64_t o = i / sp.Q, q = i % sp.Q;
+    t[i] = (q < qn) ? src[o * sp.Ci + q0 + q] : 0.0;
+  }
+  __syncthreads();
+  // leading axes of the [Co] part; the Q columns are the fastest index.
+  const int nl = a.n - sp.m;
+  int64_t stride = sp.Q;
+  for (int ax = nl - 1; ax >= 0; --ax) {
+    const int64_t fibres = sp.Co * sp.Q / D1;
+    for (int64_t f = threadIdx.x; f < fibres; f += blockDim.x) {
+      const int64_t base = (f / stride) * stride * D1 + (f % stride);
+      for (int k = a.D; k >= 0; --k) {
+        double acc = 0.0;
+        for (int jj = 0; jj <= k; ++jj) acc = fma(tab[k * D1 + jj], t[base + (int64_t)jj * stride], acc);
+        t[base + (int64_t)k * stride] = acc;
+      }
+    }
+    __syncthreads();
+    stride *= D1;
+  }
+  double v = s ? INFINITY : -INFINITY;
+  for (int64_t i = threadIdx.x; i < sp.Co * sp.Q; i += blockDim.x) {
+    if (i % sp.Q < qn) v = s ? fmin(v, t[i]) : fmax(v, t[i]);
+  }
+  v = s ? block_reduce(v, OpMin(), red) : block_reduce(v, OpMax(), red);
+  if (threadIdx.x == 0) partial[tensor * sp.nchunk + blockIdx.x] = v;
+}
+
+// Fold the per-chunk extrema of both bounds of one neuron.
+__global__ void __launch_bounds__(64) convert_final_kernel(ConvertArgs a, Split sp, const double *partial) {
+  const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= a.nboxes * a.h) return;
+  const int64_t box = item / a.h;
+  const int j = (int)(item % a.h);
+  double lo = INFINITY, hi = -INFINITY;
+  for (int64_t c = 0; c < sp.nchunk; ++c) {
+    lo = fmin(lo, partial[(item * 2 + 1) * sp.nchunk + c]);
+    hi = fmax(hi, partial[(item * 2 + 0) * sp.nchunk + c]);
+  }
+  if (a.mode == 1) {
+    a.out_lo[box * a.ld_out + a.col0 + j] = lo;
+    a.out_hi[box * a.ld_out + a.col0 + j] = hi;
+  } else {
+    if (a.out_lo) a.out_lo[box * a.ld_out + a.col0 + j] = lo;
+    if (a.out_hi) a.out_hi[box * a.ld_out + a.col0 + j] = hi;
+    const double zero[kMaxInputs + 1] = {0};
+    finish_neuron(a, box, j, lo, hi, zero, 0.0, zero, 0.0);
+  }
+}
+
+static bool use_small(int64_t C) {
+  const int64_t fit = (int64_t)(device_lds_limit() / sizeof(double)) - 17 * 17 - 64;
+  return C <= kSmallLds && C <= fit;
+}
+
+size_t convert_scratch_bytes(int n, int D, int h, int64_t nboxes) {
+  const int64_t C = ipow(D + 1, n);
+  if (use_small(C)) return 0;
+  const Split sp = make_split(n, D);
+  return align256((size_t)nboxes * h * 2 * C * sizeof(double)) +
+         align256((size_t)nboxes * h * 2 * sp.nchunk * sizeof(double));
+}
+
+hipError_t launch_convert(const ConvertArgs &a, hipStream_t s) {
+  const int D1 = a.D + 1;
+  if (use_small(a.C)) {
+    const size_t lds = (a.C + D1 * D1 + 16) * sizeof(double);
+    auto k = a.fp64 ? convert_small_kernel<double> : convert_small_kernel<float>;
+    RET_IF(hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k, dim3((unsigned)(a.nboxes * a.h)), dim3(kBlock), lds, s, a);
+    return hipGetLastError();
+  }
+  const Split sp = make_split(a.n, a.D);
+  if (sp.Co > tile_elems(a.D)) return hipErrorInvalidValue;
+  double *partial = reinterpret_cast<double *>(reinterpret_cast<char *>(a.scratch) +
+                                               align256((size_t)a.nboxes * a.h * 2 * a.C * sizeof(double)));
+  const int64_t tensors = a.nboxes * a.h * 2;
+  {
+    const size_t lds = (sp.Ci + D1 * D1) * sizeof(double);
+    auto k = a.fp64 ? convert_passA_kernel<double> : convert_passA_kernel<float>;
+    RET_IF(hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k, dim3((unsigned)sp.Co, (unsigned)tensors), dim3(kBlock), lds, s, a, sp);
+  }
+  {
+    const size_t lds = (sp.Co * sp.Q + D1 * D1 + 16) * sizeof(double);
+    RET_IF(hipFuncSetAttribute((const void *)convert_passB_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(convert_passB_kernel, dim3((unsigned)sp.nchunk, (unsigned)tensors), dim3(kBlock), lds, s, a,
+                       sp, partial);
+  }
+  hipLaunchKernelGGL(convert_final_kernel, dim3((unsigned)((a.nboxes * a.h + 63) / 64)), dim3(64), 0, s, a, sp,
+                     (const double *)partial);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------- step-level primitives
+
+// Basis change of `count` independent tensors: Bernstein coefficients (if
+// requested), min, max and sum of |power coefficients|; one block per tensor.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) basis_minmax_kernel(int n, int D, int64_t C, const T *coef, double *bern,
+                                                              double *mn, double *mx, double *l1) {
+  extern __shared__ double lds[];
+  const int D1 = D + 1;
+  double *t = lds;
+  double *tab = lds + C;
+  double *red = tab + D1 * D1;
+  const int64_t item = blockIdx.x;
+  fill_table(tab, D);
+  double s1 = 0.0;
+  for (int64_t i = threadIdx.x; i < C; i += blockDim.x) {
+    t[i] = (double)coef[item * C + i];
+    s1 += fabs(t[i]);
+  }
+  __syncthreads();
+  lds_basis_change(t, C, n, D, 0, n, tab);
+  double vmin = INFINITY, vmax = -INFINITY;
+  for (int64_t i = threadIdx.x; i < C; i += blockDim.x) {
+    vmin = fmin(vmin, t[i]);
+    vmax = fmax(vmax, t[i]);
+    if (bern) bern[item * C + i] = t[i];
+  }
+  vmin = block_reduce(vmin, OpMin(), red);
+  vmax = block_reduce(vmax, OpMax(), red);
+  s1 = block_reduce(s1, OpAdd(), red);
+  if (threadIdx.x == 0) {
+    mn[item] = vmin;
+    mx[item] = vmax;
+    if (l1) l1[item] = s1;
+  }
+}
+
+size_t basis_minmax_scratch(int, int, int64_t) { return 0; }
+
+hipError_t launch_basis_minmax(int n, int D, int64_t count, const void *coef, int fp64, double *bern, double *mn,
+                               double *mx, double *l1, double *, hipStream_t s) {
+  const int64_t C = ipow(D + 1, n);
+  if (!use_small(C)) return hipErrorInvalidValue;
+  const int D1 = D + 1;
+  const size_t lds = (C + D1 * D1 + 16) * sizeof(double);
+  if (fp64) {
+    RET_IF(hipFuncSetAttribute((const void *)basis_minmax_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)lds));
+    hipLaunchKernelGGL(basis_minmax_kernel<double>, dim3((unsigned)count), dim3(kBlock), lds, s, n, D, C,
+                       (const double *)coef, bern, mn, mx, l1);
+  } else {
+    RET_IF(hipFuncSetAttribute((const void *)basis_minmax_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)lds));
+    hipLaunchKernelGGL(basis_minmax_kernel<float>, dim3((unsigned)count), dim3(kBlock), lds, s, n, D, C,
+                       (const float *)coef, bern, mn, mx, l1);
+  }
+  return hipGetLastError();
+}
+
+__global__ void relu_poly_kernel(int64_t count, int L, const double *lo, const double *hi, double *c, double *e) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  double cc[kMaxOrder + 1], ee;
+  relu_poly_dev(lo[i], hi[i], L, cc, &ee);
+  for (int k = 0; k <= L; ++k) c[i * (L + 1) + k] = cc[k];
+  e[i] = ee;
+}
+
+hipError_t launch_relu_poly(int64_t count, int L, const double *lo, const double *hi, double *c, double *e,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(relu_poly_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, count, L, lo, hi, c,
+                     e);
+  return hipGetLastError();
+}
+
+}  // namespace bern
