@@ -187,6 +187,20 @@ bern_status bern_poly_mul(int32_t n, int32_t da, int32_t db, int64_t count, cons
 bern_status bern_relu_poly(int64_t count, int32_t L, const double *lo, const double *hi, double *c,
                            double *e, void *stream);
 
+/* Kernel timing for measurement. While enabled, every kernel the library
+ * launches is bracketed by two HIP events recorded on the stream it runs on
+ * (process-wide setting; not for use while a stream is being captured).
+ * bern_prof_read waits for the recorded events and returns, for one kernel
+ * class (0 .. bern_prof_classes()-1, named by bern_prof_name), the number of
+ * launches, their summed duration in milliseconds and their summed
+ * algorithmic HBM bytes where the launch shape alone fixes them (else 0).
+ * bern_prof_reset forgets every record. */
+bern_status bern_prof_enable(int32_t on);
+bern_status bern_prof_reset(void);
+int32_t bern_prof_classes(void);
+const char *bern_prof_name(int32_t cls);
+bern_status bern_prof_read(int32_t cls, int64_t *launches, double *ms, double *bytes);
+
 /* Status name and the calling thread's last error message. */
 const char *bern_status_str(int32_t status);
 const char *bern_last_error(void);

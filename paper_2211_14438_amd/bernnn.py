@@ -84,13 +84,25 @@ def lib():
     L.bern_poly_mul.argtypes = [i32, i32, i32, i64, _vp, _vp, _vp, i32, _vp]
     L.bern_relu_poly.restype = i32
     L.bern_relu_poly.argtypes = [i64, i32, _vp, _vp, _vp, _vp, _vp]
+    L.bern_prof_enable.restype = i32
+    L.bern_prof_enable.argtypes = [i32]
+    L.bern_prof_reset.restype = i32
+    L.bern_prof_reset.argtypes = []
+    L.bern_prof_classes.restype = i32
+    L.bern_prof_classes.argtypes = []
+    L.bern_prof_name.restype = ctypes.c_char_p
+    L.bern_prof_name.argtypes = [i32]
+    L.bern_prof_read.restype = i32
+    L.bern_prof_read.argtypes = [i32, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_double)]
     _LIB = L
     return L
 
 
 EXPORTED = ("bern_opts_default", "bern_net_create", "bern_net_destroy", "bern_net_inputs", "bern_net_hidden",
             "bern_net_outputs", "bern_workspace_size", "bern_bounds", "bern_basis_minmax_scratch",
-            "bern_basis_minmax", "bern_poly_mul", "bern_relu_poly", "bern_status_str", "bern_last_error")
+            "bern_basis_minmax", "bern_poly_mul", "bern_relu_poly", "bern_status_str", "bern_last_error",
+            "bern_prof_enable", "bern_prof_reset", "bern_prof_classes", "bern_prof_name", "bern_prof_read")
 
 
 def status_str(s):
@@ -200,6 +212,27 @@ def bounds(net, box_lo, box_hi, L=2, precision="fp64", plan="plain", sched="per_
                         workspace_used=st.workspace_used)
     res["workspace"] = workspace
     return res
+
+
+def prof_enable(on=True):
+    _check(lib().bern_prof_enable(1 if on else 0))
+
+
+def prof_reset():
+    _check(lib().bern_prof_reset())
+
+
+def prof_read():
+    """{kernel class: (launches, total ms, algorithmic bytes)} of the
+    launches recorded since the last reset (waits for them)."""
+    L = lib()
+    out = {}
+    for c in range(L.bern_prof_classes()):
+        n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        _check(L.bern_prof_read(c, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+        if n.value:
+            out[L.bern_prof_name(c).decode()] = (n.value, ms.value, by.value)
+    return out
 
 
 def basis_minmax(coef, n, D, want_bern=False, stream=None):

@@ -48,6 +48,7 @@ hipError_t launch_layer1(const Layer1Args &a, hipStream_t s) {
   const int64_t total = a.nboxes * a.h * ((int64_t)1 << a.n);
   const int64_t blocks = (total + kBlock - 1) / kBlock;
   const unsigned grid = (unsigned)std::min<int64_t>(blocks, 65536);
+  ProfScope ps(kProfLayer1, s, (double)total * 2 * (a.fp64 ? 8 : 4));
   if (a.fp64)
     hipLaunchKernelGGL(layer1_kernel<double>, dim3(grid), dim3(kBlock), 0, s, a);
   else
@@ -58,55 +59,88 @@ hipError_t launch_layer1(const Layer1Args &a, hipStream_t s) {
 // One thread per coefficient c; MB output neurons per block row. Block x
 // index runs over output-neuron chunks first so that the blocks reading the
 // same coefficient range of the previous layer run together and share L2.
+// Arithmetic is FP64 whatever the storage type; in FP32 mode each block also
+// reports, per output neuron and bound, the sum of |fl32(y) - y| over its
+// coefficients (the exact rounding of the stored tensor), reduced in a fixed
+// order.
 template <typename T, int MB>
 __global__ void __launch_bounds__(kBlock) gemm_kernel(GemmArgs a) {
+  __shared__ double red[kBlock / 64][MB][2];
   const int m0 = blockIdx.x * MB;
   const int64_t c = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
   const int64_t box = blockIdx.z;
-  if (c >= a.C) return;
+  const bool valid = c < a.C;
   const T *X = reinterpret_cast<const T *>(a.post) + box * a.hin * 2 * a.C;
-  const T *W = reinterpret_cast<const T *>(a.W);
-  T accM[MB], accR[MB];
+  double accM[MB], accR[MB];
 #pragma unroll
-  for (int mm = 0; mm < MB; ++mm) accM[mm] = accR[mm] = (T)0;
+  for (int mm = 0; mm < MB; ++mm) accM[mm] = accR[mm] = 0.0;
   const int mcount = min(MB, a.h - m0);
-  for (int k = 0; k < a.hin; ++k) {
-    const T u = X[(int64_t)k * 2 * a.C + c];
-    const T l = X[(int64_t)k * 2 * a.C + a.C + c];
-    const T M = (u + l) * (T)0.5;
-    const T R = (u - l) * (T)0.5;
+  if (valid) {
+    for (int k = 0; k < a.hin; ++k) {
+      const double u = (double)X[(int64_t)k * 2 * a.C + c];
+      const double l = (double)X[(int64_t)k * 2 * a.C + a.C + c];
+      const double M = (u + l) * 0.5;
+      const double R = (u - l) * 0.5;
 #pragma unroll
-    for (int mm = 0; mm < MB; ++mm) {
-      if (mm < mcount) {
-        const T w = W[(int64_t)(m0 + mm) * a.hin + k];
-        accM[mm] = fma(w, M, accM[mm]);
-        accR[mm] = fma(fabs(w), R, accR[mm]);
+      for (int mm = 0; mm < MB; ++mm) {
+        if (mm < mcount) {
+          const double w = a.W[(int64_t)(m0 + mm) * a.hin + k];
+          accM[mm] = fma(w, M, accM[mm]);
+          accR[mm] = fma(fabs(w), R, accR[mm]);
+        }
       }
     }
   }
   T *Y = reinterpret_cast<T *>(a.pre) + box * a.h * 2 * a.C;
+  const bool track = a.rpart != nullptr;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int mm = 0; mm < MB; ++mm) {
-    if (mm < mcount) {
+    double ru = 0.0, rl = 0.0;
+    if (mm < mcount && valid) {
       const int m = m0 + mm;
-      const T bias = (c == 0) ? (T)a.b[m] : (T)0;
-      Y[(int64_t)m * 2 * a.C + c] = accM[mm] + accR[mm] + bias;
-      Y[(int64_t)m * 2 * a.C + a.C + c] = accM[mm] - accR[mm] + bias;
+      const double bias = (c == 0) ? a.b[m] : 0.0;
+      const double yu = accM[mm] + accR[mm] + bias;
+      const double yl = accM[mm] - accR[mm] + bias;
+      const T su = (T)yu, sl = (T)yl;
+      Y[(int64_t)m * 2 * a.C + c] = su;
+      Y[(int64_t)m * 2 * a.C + a.C + c] = sl;
+      ru = fabs((double)su - yu);
+      rl = fabs((double)sl - yl);
     }
+    if (track && mm < mcount) {
+      for (int off = 32; off > 0; off >>= 1) {
+        ru += __shfl_xor(ru, off, 64);
+        rl += __shfl_xor(rl, off, 64);
+      }
+      if (lane == 0) {
+        red[wid][mm][0] = ru;
+        red[wid][mm][1] = rl;
+      }
+    }
+  }
+  if (!track) return;
+  __syncthreads();
+  if (threadIdx.x < 2 * mcount) {
+    const int mm = threadIdx.x >> 1, s = threadIdx.x & 1;
+    double v = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v += red[w][mm][s];
+    a.rpart[((box * a.h + m0 + mm) * 2 + s) * a.cblocks + blockIdx.y] = v;
   }
 }
 
-hipError_t launch_gemm(const GemmArgs &a, hipStream_t s) {
-  const unsigned cblocks = (unsigned)((a.C + kBlock - 1) / kBlock);
-  if (a.fp64) {
-    constexpr int MB = 16;
-    dim3 grid((a.h + MB - 1) / MB, cblocks, (unsigned)a.nboxes);
+int64_t gemm_cblocks(int64_t C) { return (C + kBlock - 1) / kBlock; }
+
+hipError_t launch_gemm(const GemmArgs &a0, hipStream_t s) {
+  GemmArgs a = a0;
+  a.cblocks = gemm_cblocks(a.C);
+  constexpr int MB = 32;
+  dim3 grid((a.h + MB - 1) / MB, (unsigned)a.cblocks, (unsigned)a.nboxes);
+  ProfScope ps(kProfGemm, s, (double)a.nboxes * (2.0 * a.hin + 2.0 * a.h) * a.C * (a.fp64 ? 8 : 4));
+  if (a.fp64)
     hipLaunchKernelGGL((gemm_kernel<double, MB>), grid, dim3(kBlock), 0, s, a);
-  } else {
-    constexpr int MB = 32;
-    dim3 grid((a.h + MB - 1) / MB, cblocks, (unsigned)a.nboxes);
+  else
     hipLaunchKernelGGL((gemm_kernel<float, MB>), grid, dim3(kBlock), 0, s, a);
-  }
   return hipGetLastError();
 }
 

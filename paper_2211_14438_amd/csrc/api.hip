@@ -24,6 +24,67 @@ void set_error(const char *fmt, ...) {
   va_end(ap);
 }
 
+// ---------------------------------------------------------------- profiler
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+struct ProfRec {
+  int cls;
+  hipEvent_t a, b;
+  double bytes;
+};
+static std::vector<ProfRec> g_prof;
+static std::vector<hipEvent_t> g_pool;  // idle events, created ahead of the timed work
+
+static hipEvent_t pool_get() {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+static void pool_fill(size_t n) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  while (g_pool.size() < n) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) break;
+    g_pool.push_back(e);
+  }
+}
+
+ProfScope::ProfScope(int c, hipStream_t st, double by) : cls(c), s(st), bytes(by), ev0(nullptr) {
+  if (!g_prof_on) return;
+  hipEvent_t e = pool_get();
+  if (!e) return;
+  if (hipEventRecord(e, s) != hipSuccess) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_pool.push_back(e);
+    return;
+  }
+  ev0 = e;
+}
+
+ProfScope::~ProfScope() {
+  if (!ev0) return;
+  hipEvent_t e = pool_get();
+  if (!e || hipEventRecord(e, s) != hipSuccess) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_pool.push_back((hipEvent_t)ev0);
+    if (e) g_pool.push_back(e);
+    return;
+  }
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  g_prof.push_back({cls, (hipEvent_t)ev0, e, bytes});
+}
+
+static const char *kProfNames[kProfCount] = {"layer1",         "gemm",           "convert_small",  "convert_passA",
+                                             "convert_passB",  "convert_final",  "compose_simple", "compose_square",
+                                             "compose_horner", "poly_mul",       "misc"};
+
 size_t device_lds_limit() {
   static std::mutex mu;
   static int cached[64];
@@ -49,9 +110,10 @@ struct Plan {
   std::vector<int> Dpre, Dpost;     // per layer i = 1..H (index i-1); Dpost for hidden layers
   std::vector<int64_t> Cpre, Cpost;
   size_t elem;
+  std::vector<int64_t> nbx;         // compose blocks per item, hidden layers
   // per-box bytes of each region
-  size_t recs, arenaA, arenaB, conv, horner, flags;
-  size_t per_box() const { return recs + arenaA + arenaB + conv + horner + flags; }
+  size_t recs, arenaA, arenaB, conv, horner, flags, gpart, cpart;
+  size_t per_box() const { return 2 * recs + arenaA + arenaB + conv + horner + flags + gpart + cpart; }
 };
 
 }  // namespace bern
@@ -91,9 +153,10 @@ static bern_status plan_net(const bern_net *net, const bern_opts *o, Plan &p) {
   p.Dpost.assign(p.H, 0);
   p.Cpre.assign(p.H, 0);
   p.Cpost.assign(p.H, 0);
+  p.nbx.assign(p.H, 0);
   int D = 1;
   const int64_t cap = (int64_t)1 << 36;
-  p.recs = p.arenaA = p.arenaB = p.conv = p.horner = 0;
+  p.recs = p.arenaA = p.arenaB = p.conv = p.horner = p.gpart = p.cpart = 0;
   for (int i = 0; i < p.H; ++i) {
     const int h = net->widths[i + 1];
     p.Dpre[i] = D;
@@ -105,6 +168,7 @@ static bern_status plan_net(const bern_net *net, const bern_opts *o, Plan &p) {
     p.arenaA = std::max(p.arenaA, align256((size_t)h * 2 * p.Cpre[i] * p.elem));
     const size_t cs = convert_scratch_bytes(p.n, D, h, 1);
     p.conv = std::max(p.conv, cs);
+    if (!p.fp64 && i > 0) p.gpart = std::max(p.gpart, align256((size_t)h * 2 * gemm_cblocks(p.Cpre[i]) * 8));
     if (i < p.H - 1) {
       const int Dn = p.Lmax * D;
       p.Dpost[i] = Dn;
@@ -115,6 +179,8 @@ static bern_status plan_net(const bern_net *net, const bern_opts *o, Plan &p) {
       }
       p.arenaB = std::max(p.arenaB, align256((size_t)h * 2 * p.Cpost[i] * p.elem));
       p.recs = std::max(p.recs, align256((size_t)h * sizeof(NeuronRec)));
+      p.nbx[i] = compose_nbx(p.n, D, Dn, p.Cpost[i], p.fp64);
+      if (!p.fp64) p.cpart = std::max(p.cpart, align256((size_t)h * 2 * p.nbx[i] * 2 * 8));
       if (p.Lmax >= 2) p.horner = std::max(p.horner, compose_scratch_bytes(p.n, D, p.Lmax, h, 1, p.fp64));
       D = Dn;
     }
@@ -290,7 +356,11 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
                             const double *box_hi, const int8_t *plan, double *nlo, double *nhi, double *olo,
                             double *ohi, int8_t *used, char *ws, hipStream_t s) {
   char *cur = ws;
-  NeuronRec *recs = reinterpret_cast<NeuronRec *>(cur); cur += p.recs * B;
+  NeuronRec *recbuf[2];
+  recbuf[0] = reinterpret_cast<NeuronRec *>(cur); cur += p.recs * B;
+  recbuf[1] = reinterpret_cast<NeuronRec *>(cur); cur += p.recs * B;
+  double *gpart = reinterpret_cast<double *>(cur); cur += p.gpart * B;
+  double *cpart = reinterpret_cast<double *>(cur); cur += p.cpart * B;
   void *A = cur; cur += p.arenaA * B;
   void *Bp = cur; cur += p.arenaB * B;
   double *conv = reinterpret_cast<double *>(cur); cur += p.conv * B;
@@ -298,13 +368,18 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
   int *flags = reinterpret_cast<int *>(cur);
   const int n = net->n;
 
-  hipLaunchKernelGGL(box_check_kernel, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, n, B, box_lo, box_hi,
-                     flags);
+  {
+    ProfScope ps(kProfMisc, s, 0.0);
+    hipLaunchKernelGGL(box_check_kernel, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, n, B, box_lo, box_hi,
+                       flags);
+  }
   BERN_HIP_TRY(hipGetLastError());
 
   for (int i = 0; i < p.H; ++i) {
     const int hin = net->widths[i], h = net->widths[i + 1];
     const bool last = (i == p.H - 1);
+    NeuronRec *recs = recbuf[i & 1];
+    const NeuronRec *prev = recbuf[(i + 1) & 1];
     // affine map -> pre-activation tensors in arena A
     if (i == 0) {
       Layer1Args a{n, h, B, box_lo, box_hi, net->W64 + net->woff[0], net->b64 + net->boff[0], A, p.fp64 ? 1 : 0};
@@ -317,9 +392,10 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       a.nboxes = B;
       a.post = Bp;
       a.pre = A;
-      a.W = p.fp64 ? (const void *)(net->W64 + net->woff[i]) : (const void *)(net->W32 + net->woff[i]);
+      a.W = net->W64 + net->woff[i];
       a.b = net->b64 + net->boff[i];
       a.fp64 = p.fp64 ? 1 : 0;
+      a.rpart = p.fp64 ? nullptr : gpart;
       BERN_HIP_TRY(launch_gemm(a, s));
     }
     // bounds read-off (+ rules and approximants for hidden layers)
@@ -336,6 +412,15 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
     c.scratch = conv;
     c.scratch_bytes = p.conv * B;
     c.plan = plan;
+    c.layer = i;
+    c.hin = hin;
+    c.prev = prev;
+    c.W = net->W64 + net->woff[i];
+    c.b = net->b64 + net->boff[i];
+    c.box_lo = box_lo;
+    c.box_hi = box_hi;
+    c.rpart = gpart;
+    c.cblocks = gemm_cblocks(p.Cpre[i]);
     c.plan_ld = net->nh;
     c.plan_col0 = last ? 0 : net->noff[i];
     if (last) {
@@ -373,10 +458,15 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
     m.fp64 = p.fp64 ? 1 : 0;
     m.scratch = horner;
     m.scratch_bytes = p.horner * B;
+    m.nbx = p.nbx[i];
+    m.part = p.fp64 ? nullptr : cpart;
     BERN_HIP_TRY(launch_compose(m, s));
   }
-  hipLaunchKernelGGL(poison_kernel, dim3((unsigned)B), dim3(64), 0, s, B, (const int *)flags, net->nh, net->o, nlo,
-                     nhi, olo, ohi);
+  {
+    ProfScope ps(kProfMisc, s, 0.0);
+    hipLaunchKernelGGL(poison_kernel, dim3((unsigned)B), dim3(64), 0, s, B, (const int *)flags, net->nh, net->o,
+                       nlo, nhi, olo, ohi);
+  }
   BERN_HIP_TRY(hipGetLastError());
   return BERN_OK;
 }
@@ -428,6 +518,53 @@ extern "C" bern_status bern_bounds(const bern_net *net, const bern_opts *opts, i
     stats->out_degree = p.Dpre[p.H - 1];
     stats->workspace_used = per_box * (size_t)wave;
   }
+  return BERN_OK;
+}
+
+// ---------------------------------------------------------------- profiler
+extern "C" bern_status bern_prof_enable(int32_t on) {
+  if (on) pool_fill(8192);
+  g_prof_on = on != 0;
+  return BERN_OK;
+}
+
+extern "C" bern_status bern_prof_reset(void) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  for (auto &r : g_prof) {
+    (void)hipEventSynchronize(r.b);
+    g_pool.push_back(r.a);
+    g_pool.push_back(r.b);
+  }
+  g_prof.clear();
+  return BERN_OK;
+}
+
+extern "C" int32_t bern_prof_classes(void) { return kProfCount; }
+
+extern "C" const char *bern_prof_name(int32_t cls) {
+  return (cls >= 0 && cls < kProfCount) ? kProfNames[cls] : "";
+}
+
+extern "C" bern_status bern_prof_read(int32_t cls, int64_t *launches, double *ms, double *bytes) {
+  if (cls < 0 || cls >= kProfCount || !launches || !ms || !bytes) {
+    set_error("bad arguments");
+    return BERN_E_ARG;
+  }
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  int64_t n = 0;
+  double t = 0.0, by = 0.0;
+  for (auto &r : g_prof) {
+    if (r.cls != cls) continue;
+    BERN_HIP_TRY(hipEventSynchronize(r.b));
+    float e = 0.f;
+    BERN_HIP_TRY(hipEventElapsedTime(&e, r.a, r.b));
+    ++n;
+    t += e;
+    by += r.bytes;
+  }
+  *launches = n;
+  *ms = t;
+  *bytes = by;
   return BERN_OK;
 }
 

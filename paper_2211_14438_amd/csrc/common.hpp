@@ -53,20 +53,65 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // What the library knows about one hidden neuron of one box after its
 // pre-activation bounds were read (Step 1) and its rule chosen (Step 2).
+// FP32 mode: every stored polynomial p~ carries a radius eps such that the
+// exact neuron value stays within [L~(t) - epsL, U~(t) + epsU] on the box.
 struct NeuronRec {
-  double lo, hi;          // pre-activation interval [lo, hi]
-  double c[kMaxOrder + 1];// over-approximant, power series in u = (y-lo)/(hi-lo)
-  double e;               // its value at y = 0 (Prop. 2 shift)
-  double padU, padL;      // FP32 mode: rounding radius of the post polynomials
-  int32_t kind;           // 0 inactive, -1 active, -2 linear fallback, k >= 1 order k
-  int32_t deg;            // per-variable degree of the post polynomials
+  double lo, hi;           // pre-activation interval [lo, hi] (padded in FP32 mode)
+  double c[kMaxOrder + 1]; // over-approximant, power series in u = (y-lo)/(hi-lo)
+  double e;                // its value at y = 0 (Prop. 2 shift), rounded up in FP32 mode
+  double dB;               // FP32 mode: bound on the rounding of c (sup over u in [0,1])
+  double epsU, epsL;       // radii of the stored pre-activation polynomials
+  double l1U, l1L;         // sum of |coefficients| of the stored pre-activation polynomials
+  double padU, padL;       // radii of the stored post polynomials
+  double pl1U, pl1L;       // sum of |coefficients| of the stored post polynomials
+  int32_t kind;            // 0 inactive, -1 active, -2 linear fallback, k >= 1 order k
+  int32_t deg;             // per-variable degree of the post polynomials
   // Linear fallback: affine post polynomials a0 + sum_a a_{1+a} t_a (power basis).
   double fbU[kMaxInputs + 1];
   double fbL[kMaxInputs + 1];
+  double fbpadU, fbpadL;   // radii of the fallback's own FP64 arithmetic
 };
+
+// Rounding-error helpers (FP32 mode). gamma(m) = m u / (1 - m u) for FP64.
+__host__ __device__ inline double gamma64(double m) {
+  const double u = 1.1102230246251565e-16;  // 2^-53
+  return m * u / (1.0 - m * u);
+}
+// Push an FP64 value outward by more than its own rounding.
+__host__ __device__ inline double round_down(double x) { return x - fabs(x) * 8.9e-16 - 1e-300; }
+__host__ __device__ inline double round_up(double x) { return x + fabs(x) * 8.9e-16 + 1e-300; }
+constexpr double kPadSafety = 1.0 + 1.0 / (1 << 20);  // covers the FP64 sums that build the radii
 
 // Per-neuron kind codes.
 enum : int32_t { kInactive = 0, kActive = -1, kFallback = -2 };
+
+// --------------------------------------------------------------- profiling
+// When enabled (bern_prof_enable), every kernel launch is bracketed by two
+// HIP events recorded on its own stream; bern_prof_read sums the elapsed times
+// per kernel class. `bytes` is the launch's algorithmic HBM traffic when the
+// shape alone fixes it (0 otherwise).
+enum ProfClass : int {
+  kProfLayer1 = 0,
+  kProfGemm,
+  kProfConvertSmall,
+  kProfConvertPassA,
+  kProfConvertPassB,
+  kProfConvertFinal,
+  kProfComposeSimple,
+  kProfComposeSquare,
+  kProfComposeHorner,
+  kProfPolyMul,
+  kProfMisc,
+  kProfCount
+};
+struct ProfScope {
+  ProfScope(int cls, hipStream_t s, double bytes);
+  ~ProfScope();
+  int cls;
+  hipStream_t s;
+  double bytes;
+  void *ev0;
+};
 
 // ----------------------------------------------------------- kernel launchers
 // Defined in the .hip files; every launcher enqueues on `stream` and returns a
@@ -87,10 +132,13 @@ struct GemmArgs {
   int64_t C, nboxes;
   const void *post;               // [B][hin][2][C]
   void *pre;                      // [B][h][2][C]
-  const void *W;                  // [h][hin] in the tensor precision
+  const double *W;                // [h][hin]
   const double *b;                // [h]
   int fp64;
+  double *rpart;                  // FP32 mode: [B][h][2][cblocks] sums of |fl32(y) - y|
+  int64_t cblocks;                // coefficient blocks of the launch (set by the launcher)
 };
+int64_t gemm_cblocks(int64_t C);
 hipError_t launch_gemm(const GemmArgs &a, hipStream_t s);
 
 struct ConvertArgs {
@@ -99,6 +147,14 @@ struct ConvertArgs {
   const void *pre;                // [B][h][2][C] power coefficients
   int fp64;
   NeuronRec *recs;                // [B][h] (hidden layers)
+  // FP32 mode: inputs of the pre-activation radii
+  int layer;                      // 0 = first layer (closed form), else GEMM output
+  int hin;
+  const NeuronRec *prev;          // [B][hin] records of the previous layer (layer > 0)
+  const double *W, *b;            // this layer's W [h][hin] and b [h] (FP64)
+  const double *box_lo, *box_hi;  // [B][n] (layer 0)
+  const double *rpart;            // GEMM rounding partials [B][h][2][cblocks] (layer > 0)
+  int64_t cblocks;
   double *out_lo, *out_hi;        // [B][ld_out] bounds written at column col0 + j
   int64_t ld_out, col0;
   int8_t *used;                   // [B][ld_out] or null (hidden layers)
@@ -113,6 +169,8 @@ size_t convert_scratch_bytes(int n, int D, int h, int64_t nboxes);
 
 struct ComposeArgs {
   int n, Din, Dout, h;
+  double *part;                   // FP32 mode: [B*h*nbounds][nbx][2] (rounding sum, l1 sum) per block
+  int64_t nbx;                    // blocks per item of every compose launch of the layer
   int nbounds;                    // 2 (upper, lower) for the network, 1 for plain products
   int Lmax;                       // largest ReLU order any neuron of the launch may use
   int64_t Cin, Cout, nboxes;
@@ -125,6 +183,8 @@ struct ComposeArgs {
   size_t scratch_bytes;
 };
 hipError_t launch_compose(const ComposeArgs &a, hipStream_t s);
+// Blocks per item the compose launches of a layer use (partials stride).
+int64_t compose_nbx(int n, int Din, int Dout, int64_t Cout, int fp64);
 size_t compose_scratch_bytes(int n, int Din, int Lmax, int h, int64_t nboxes, int fp64);
 
 // Largest dynamic LDS allocation one block may use on the current device.

@@ -19,6 +19,13 @@
 //  * order 1, active (identity), inactive (zero) and the linear fallback are
 //    element-wise writes.
 // Every result is written at the layer's post degree Dout (zero padded).
+//
+// Arithmetic is FP64 for both storage types: with packed FP32 math off, FP32
+// and FP64 FMAs issue at the same rate on gfx950, and FP64 keeps the rounding
+// radius of FP32 mode down to the final FP32 stores. In FP32 mode the input
+// radius is folded into nu (U^ + epsU, L^ - epsL keep nu in [0,1] exactly),
+// and every block reports the exact sum of |fl32(q) - q| over the
+// coefficients it stored, plus their l1 norm, for the radius of the result.
 #include "common.hpp"
 
 namespace bern {
@@ -30,27 +37,55 @@ __device__ inline int64_t item_of(const ComposeArgs &a, int64_t box, int j, int 
   return (box * a.h + j) * a.nbounds + s;
 }
 
-__device__ inline void rec_of(const ComposeArgs &a, int64_t box, int j, int &kind, double &lo, double &w,
-                              const double *&c, double &e) {
-  if (a.recs) {
-    const NeuronRec &r = a.recs[box * a.h + j];
-    kind = r.kind;
-    lo = r.lo;
-    w = r.hi - r.lo;
-    c = r.c;
-    e = r.e;
-  } else {  // plain product mode (step-level entry point): nu = P, out = P^2
-    kind = 2;
-    lo = 0.0;
-    w = 1.0;
-    c = nullptr;
-    e = 0.0;
+// Block-wide sums of (rounding, l1) in a fixed order; thread 0 writes them.
+__device__ void block_partials(const ComposeArgs &a, int64_t it, double r, double l1) {
+  __shared__ double red[kBlock / 64][2];
+  for (int off = 32; off > 0; off >>= 1) {
+    r += __shfl_xor(r, off, 64);
+    l1 += __shfl_xor(l1, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[wid][0] = r;
+    red[wid][1] = l1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sr = 0.0, sl = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      sr += red[w][0];
+      sl += red[w][1];
+    }
+    a.part[(it * a.nbx + blockIdx.x) * 2 + 0] = sr;
+    a.part[(it * a.nbx + blockIdx.x) * 2 + 1] = sl;
   }
 }
 
+// Store one coefficient; track its rounding and magnitude.
+template <typename T>
+__device__ __forceinline__ void store(T *dst, double q, double &r, double &l1) {
+  const T v = (T)q;
+  *dst = v;
+  r += fabs((double)v - q);
+  l1 += fabs((double)v);
+}
+
+struct NuSource {
+  double lo, w, shift;  // nu = (p + shift*[K=0] - lo) / w
+};
+
+__device__ inline NuSource nu_of(const ComposeArgs &a, const NeuronRec *r, int s) {
+  if (!r) return {0.0, 1.0, 0.0};  // plain product mode: nu = p
+  NuSource v;
+  v.lo = r->lo;
+  v.w = r->hi - r->lo;
+  v.shift = a.fp64 ? 0.0 : (s == 0 ? r->epsU : -r->epsL);
+  return v;
+}
+
 // ------------------------------------------------------------ row conv
-template <typename T, int D, int NI>
-__device__ __forceinline__ void row_conv(const T *ra, const T *rb, T *acc) {
+template <int D, int NI>
+__device__ __forceinline__ void row_conv(const double *ra, const double *rb, double *acc) {
   constexpr int D1 = D + 1, E1 = 2 * D + 1;
   if constexpr (NI == 1) {
 #pragma unroll
@@ -70,31 +105,35 @@ __device__ __forceinline__ void row_conv(const T *ra, const T *rb, T *acc) {
   }
 }
 
-// Square path: nu in LDS as rows of R = (D+1)^NI coefficients (pitch RP);
+template <int D, int NI>
+struct SqGeom {
+  static constexpr int D1 = D + 1, E1 = 2 * D + 1;
+  static constexpr int R = cpow(D1, NI), RO = cpow(E1, NI);
+  static constexpr int RP = (R + 1) & ~1;  // row pitch in doubles (16-byte aligned rows)
+};
+
+// Square path: nu in LDS (FP64) as rows of R = (D+1)^NI coefficients;
 // thread = one output row of the layer's post tensor.
 template <typename T, int D, int NI>
 __global__ void __launch_bounds__(kBlock) compose_sq_kernel(ComposeArgs a) {
-  constexpr int D1 = D + 1, E1 = 2 * D + 1;
-  constexpr int R = cpow(D1, NI), RO = cpow(E1, NI);
-  constexpr int RP = (R + 3) & ~3;
+  using G = SqGeom<D, NI>;
+  constexpr int D1 = G::D1, E1 = G::E1, R = G::R, RO = G::RO, RP = G::RP;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *rows = reinterpret_cast<T *>(smem_raw);
+  double *rows = reinterpret_cast<double *>(smem_raw);
 
   const int j = blockIdx.y / a.nbounds, s = blockIdx.y % a.nbounds;
   const int64_t box = blockIdx.z;
-  int kind;
-  double lo, w, e;
-  const double *cc;
-  rec_of(a, box, j, kind, lo, w, cc, e);
-  if (kind != 2) return;
+  const NeuronRec *rec = a.recs ? &a.recs[box * a.h + j] : nullptr;
+  if (rec && rec->kind != 2) return;
+  const NuSource ns = nu_of(a, rec, s);
 
   const int no = a.n - NI;
   const int64_t it = item_of(a, box, j, s);
   const T *p = reinterpret_cast<const T *>(a.pre) + it * a.Cin;
   for (int64_t i = threadIdx.x; i < a.Cin; i += blockDim.x) {
     double v = (double)p[i];
-    if (i == 0) v -= lo;
-    rows[(i / R) * RP + (i % R)] = (T)(v / w);
+    if (i == 0) v += ns.shift - ns.lo;
+    rows[(i / R) * RP + (i % R)] = v / ns.w;
   }
   __syncthreads();
 
@@ -102,15 +141,16 @@ __global__ void __launch_bounds__(kBlock) compose_sq_kernel(ComposeArgs a) {
   int64_t Mo = 1;
   for (int q = 0; q < no; ++q) Mo *= Do1;
   const int64_t ko = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (ko >= Mo) return;
+  const bool valid = ko < Mo;
   const int Rout = (NI == 1) ? Do1 : Do1 * Do1;
-  T *out = reinterpret_cast<T *>(a.post) + it * a.Cout + ko * Rout;
+  T *out = reinterpret_cast<T *>(a.post) + it * a.Cout + (valid ? ko : 0) * Rout;
+  double rsum = 0.0, l1sum = 0.0;
 
   // outer digits of ko (base Dout+1): per-axis pair ranges packed 4 bits/axis
   uint64_t lop = 0, hip = 0;
   int64_t rK = 0, cnt = 1;
-  bool zero = false, lin_ok = true, origin = true;
-  {
+  bool zero = !valid, lin_ok = true, origin = true;
+  if (valid) {
     int64_t rem = ko, pw = 1;
     for (int q = no - 1; q >= 0; --q) {
       const int k = (int)(rem % Do1);
@@ -128,88 +168,92 @@ __global__ void __launch_bounds__(kBlock) compose_sq_kernel(ComposeArgs a) {
     }
   }
   if (zero) {
-    for (int q = 0; q < Rout; ++q) out[q] = (T)0;
-    return;
-  }
-
-  T acc[RO];
-#pragma unroll
-  for (int q = 0; q < RO; ++q) acc[q] = (T)0;
-  int64_t rI = 0;
-  {
-    int64_t pw = 1;
-    for (int q = no - 1; q >= 0; --q) {
-      rI += (int64_t)((lop >> (4 * (no - 1 - q))) & 15) * pw;
-      pw *= D1;
-    }
-  }
-  uint64_t iv = lop;
-  const int64_t half = cnt >> 1;
-  for (int64_t t = 0; t < half; ++t) {
-    T ra[R], rb[R];
-    const T *pa = rows + rI * RP;
-    const T *pb = rows + (rK - rI) * RP;
-#pragma unroll
-    for (int q = 0; q < R; ++q) { ra[q] = pa[q]; rb[q] = pb[q]; }
-    row_conv<T, D, NI>(ra, rb, acc);
-    int64_t pw = 1;
-    for (int q = no - 1; q >= 0; --q) {
-      const int sh = 4 * (no - 1 - q);
-      const int d = (int)((iv >> sh) & 15), hh = (int)((hip >> sh) & 15);
-      if (d < hh) {
-        iv += (uint64_t)1 << sh;
-        rI += pw;
-        break;
-      }
-      const int l = (int)((lop >> sh) & 15);
-      iv = (iv & ~((uint64_t)15 << sh)) | ((uint64_t)l << sh);
-      rI -= (int64_t)(d - l) * pw;
-      pw *= D1;
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < RO; ++q) acc[q] = acc[q] + acc[q];
-  if (cnt & 1) {  // middle pair I = K - I
-    T ra[R];
-    const T *pa = rows + rI * RP;
-#pragma unroll
-    for (int q = 0; q < R; ++q) ra[q] = pa[q];
-    row_conv<T, D, NI>(ra, ra, acc);
-  }
-
-  // epilogue: c2 nu^2 + c1 nu + (c0 - e for the lower bound)
-  const T c2 = cc ? (T)cc[2] : (T)1;
-  const T c1 = cc ? (T)cc[1] : (T)0;
-  const T cst = cc ? (T)(cc[0] - (s == 1 ? e : 0.0)) : (T)0;
-  T lin[R];
-#pragma unroll
-  for (int q = 0; q < R; ++q) lin[q] = (T)0;
-  if (lin_ok) {
-    const T *pl = rows + rK * RP;
-#pragma unroll
-    for (int q = 0; q < R; ++q) lin[q] = pl[q];
-  }
-  if (a.Dout != 2 * D)
-    for (int q = 0; q < Rout; ++q) out[q] = (T)0;
-  if constexpr (NI == 1) {
-#pragma unroll
-    for (int q0 = 0; q0 < E1; ++q0) {
-      T v = c2 * acc[q0];
-      if (q0 <= D) v = fma(c1, lin[q0], v);
-      if (origin && q0 == 0) v += cst;
-      out[q0] = v;
-    }
+    if (valid)
+      for (int q = 0; q < Rout; ++q) out[q] = (T)0;
   } else {
+    double acc[RO];
 #pragma unroll
-    for (int q0 = 0; q0 < E1; ++q0)
-#pragma unroll
-      for (int q1 = 0; q1 < E1; ++q1) {
-        T v = c2 * acc[q0 * E1 + q1];
-        if (q0 <= D && q1 <= D) v = fma(c1, lin[q0 * D1 + q1], v);
-        if (origin && q0 == 0 && q1 == 0) v += cst;
-        out[q0 * Do1 + q1] = v;
+    for (int q = 0; q < RO; ++q) acc[q] = 0.0;
+    int64_t rI = 0;
+    {
+      int64_t pw = 1;
+      for (int q = no - 1; q >= 0; --q) {
+        rI += (int64_t)((lop >> (4 * (no - 1 - q))) & 15) * pw;
+        pw *= D1;
       }
+    }
+    uint64_t iv = lop;
+    const int64_t half = cnt >> 1;
+    for (int64_t t = 0; t < half; ++t) {
+      double ra[R], rb[R];
+      const double *pa = rows + rI * RP;
+      const double *pb = rows + (rK - rI) * RP;
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        ra[q] = pa[q];
+        rb[q] = pb[q];
+      }
+      row_conv<D, NI>(ra, rb, acc);
+      int64_t pw = 1;
+      for (int q = no - 1; q >= 0; --q) {
+        const int sh = 4 * (no - 1 - q);
+        const int d = (int)((iv >> sh) & 15), hh = (int)((hip >> sh) & 15);
+        if (d < hh) {
+          iv += (uint64_t)1 << sh;
+          rI += pw;
+          break;
+        }
+        const int l = (int)((lop >> sh) & 15);
+        iv = (iv & ~((uint64_t)15 << sh)) | ((uint64_t)l << sh);
+        rI -= (int64_t)(d - l) * pw;
+        pw *= D1;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < RO; ++q) acc[q] = acc[q] + acc[q];
+    if (cnt & 1) {  // middle pair I = K - I
+      double ra[R];
+      const double *pa = rows + rI * RP;
+#pragma unroll
+      for (int q = 0; q < R; ++q) ra[q] = pa[q];
+      row_conv<D, NI>(ra, ra, acc);
+    }
+
+    // epilogue: c2 nu^2 + c1 nu + (c0 - e for the lower bound)
+    const double c2 = rec ? rec->c[2] : 1.0;
+    const double c1 = rec ? rec->c[1] : 0.0;
+    const double cst = rec ? rec->c[0] - (s == 1 ? rec->e : 0.0) : 0.0;
+    double lin[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) lin[q] = 0.0;
+    if (lin_ok) {
+      const double *pl = rows + rK * RP;
+#pragma unroll
+      for (int q = 0; q < R; ++q) lin[q] = pl[q];
+    }
+    if (a.Dout != 2 * D)
+      for (int q = 0; q < Rout; ++q) out[q] = (T)0;
+    if constexpr (NI == 1) {
+#pragma unroll
+      for (int q0 = 0; q0 < E1; ++q0) {
+        double v = c2 * acc[q0];
+        if (q0 <= D) v = fma(c1, lin[q0], v);
+        if (origin && q0 == 0) v += cst;
+        store(out + q0, v, rsum, l1sum);
+      }
+    } else {
+#pragma unroll
+      for (int q0 = 0; q0 < E1; ++q0)
+#pragma unroll
+        for (int q1 = 0; q1 < E1; ++q1) {
+          double v = c2 * acc[q0 * E1 + q1];
+          if (q0 <= D && q1 <= D) v = fma(c1, lin[q0 * D1 + q1], v);
+          if (origin && q0 == 0 && q1 == 0) v += cst;
+          store(out + q0 * Do1 + q1, v, rsum, l1sum);
+        }
+    }
   }
+  if (a.part) block_partials(a, it, rsum, l1sum);
 }
 
 // ------------------------------------------------- element-wise rules
@@ -221,10 +265,12 @@ __global__ void __launch_bounds__(kBlock) compose_simple_kernel(ComposeArgs a) {
   const NeuronRec &r = a.recs[box * a.h + j];
   const int kind = r.kind;
   if (kind >= 2) return;
+  const NuSource ns = nu_of(a, &r, s);
   const int64_t it = item_of(a, box, j, s);
   const T *p = reinterpret_cast<const T *>(a.pre) + it * a.Cin;
   T *out = reinterpret_cast<T *>(a.post) + it * a.Cout;
   const int Do1 = a.Dout + 1, Di1 = a.Din + 1;
+  double rsum = 0.0, l1sum = 0.0;
   for (int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; K < a.Cout; K += (int64_t)gridDim.x * blockDim.x) {
     // digits of K in base Dout+1 -> index in the input tensor (base Din+1)
     int64_t rem = K, idx = 0, pw = 1;
@@ -236,8 +282,12 @@ __global__ void __launch_bounds__(kBlock) compose_simple_kernel(ComposeArgs a) {
       if (k > a.Din) inside = false;
       idx += (int64_t)k * pw;
       pw *= Di1;
-      if (k == 1) { ++ones; one_axis = q; }
-      else if (k != 0) ones = 100;
+      if (k == 1) {
+        ++ones;
+        one_axis = q;
+      } else if (k != 0) {
+        ones = 100;
+      }
     }
     double v = 0.0;
     if (kind == kActive) {
@@ -245,8 +295,8 @@ __global__ void __launch_bounds__(kBlock) compose_simple_kernel(ComposeArgs a) {
     } else if (kind == 1) {
       if (inside) {
         double x = (double)p[idx];
-        if (K == 0) x -= r.lo;
-        v = r.c[1] * (x / (r.hi - r.lo));
+        if (K == 0) x += ns.shift - ns.lo;
+        v = r.c[1] * (x / ns.w);
       }
       if (K == 0) v += r.c[0] - (s == 1 ? r.e : 0.0);
     } else if (kind == kFallback) {
@@ -254,14 +304,16 @@ __global__ void __launch_bounds__(kBlock) compose_simple_kernel(ComposeArgs a) {
       if (K == 0) v = fb[0];
       else if (ones == 1) v = fb[1 + one_axis];
     }
-    out[K] = (T)v;
+    store(out + K, v, rsum, l1sum);
   }
+  if (a.part) block_partials(a, it, rsum, l1sum);
 }
 
 // ------------------------------------------------ generic Horner step
 // Step m (1 <= m <= L-1) of Q^(m) = nu * Q^(m-1) + c_{L-1-m}, where
-// Q^(0) = c_L nu + c_{L-1}; Q^(m) has degree (m+1) Din. The last step adds
-// -e (lower bound) and writes the post tensor at degree Dout.
+// Q^(0) = c_L nu + c_{L-1}; Q^(m) has degree (m+1) Din. Intermediates stay in
+// FP64 scratch; the last step adds -e (lower bound) and writes the post
+// tensor at degree Dout.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) compose_horner_kernel(ComposeArgs a, int m, int sq_D) {
   const int j = blockIdx.y / a.nbounds, s = blockIdx.y % a.nbounds;
@@ -269,20 +321,22 @@ __global__ void __launch_bounds__(kBlock) compose_horner_kernel(ComposeArgs a, i
   const NeuronRec &r = a.recs[box * a.h + j];
   const int L = r.kind;
   if (L < 2 || (L == 2 && sq_D == a.Din) || m > L - 1) return;
+  const NuSource ns = nu_of(a, &r, s);
   const bool last = (m == L - 1);
   const int64_t it = item_of(a, box, j, s);
   const T *p = reinterpret_cast<const T *>(a.pre) + it * a.Cin;
   const int Din = a.Din, Di1 = Din + 1;
-  const int dq = m * Din;          // degree of Q^(m-1)
-  const int dout_m = (m + 1) * Din; // degree of Q^(m)
-  const int Dt = last ? a.Dout : dout_m;  // degree of the written tensor
+  const int dq = m * Din;            // degree of Q^(m-1)
+  const int dout_m = (m + 1) * Din;  // degree of Q^(m)
+  const int Dt = last ? a.Dout : dout_m;
   const int64_t Ct = last ? a.Cout : ipow(dout_m + 1, a.n);
-  T *dst = last ? reinterpret_cast<T *>(a.post) + it * a.Cout
-                : reinterpret_cast<T *>(a.scratch) + (it * 2 + (m & 1)) * a.Cq;
-  const T *qsrc = reinterpret_cast<const T *>(a.scratch) + (it * 2 + ((m - 1) & 1)) * a.Cq;
-  const double lo = r.lo, w = r.hi - r.lo;
+  double *scr = reinterpret_cast<double *>(a.scratch);
+  double *dsts = scr + (it * 2 + (m & 1)) * a.Cq;
+  T *dstp = reinterpret_cast<T *>(a.post) + it * a.Cout;
+  const double *qsrc = scr + (it * 2 + ((m - 1) & 1)) * a.Cq;
   const double cL = r.c[L], cL1 = r.c[L - 1], cadd = r.c[L - 1 - m];
   const int Dq1 = dq + 1;
+  double rsum = 0.0, l1sum = 0.0;
   for (int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; K < Ct; K += (int64_t)gridDim.x * blockDim.x) {
     int k[kMaxInputs];
     int64_t rem = K;
@@ -309,27 +363,89 @@ __global__ void __launch_bounds__(kBlock) compose_horner_kernel(ComposeArgs a, i
           iJ = iJ * Dq1 + (k[q] - i[q]);
         }
         double nu = (double)p[iI];
-        if (iI == 0) nu -= lo;
-        nu /= w;
+        if (iI == 0) nu += ns.shift - ns.lo;
+        nu /= ns.w;
         double qv;
         if (m == 1) {
           double x = (double)p[iJ];
-          if (iJ == 0) x -= lo;
-          qv = cL * (x / w) + (iJ == 0 ? cL1 : 0.0);
+          if (iJ == 0) x += ns.shift - ns.lo;
+          qv = cL * (x / ns.w) + (iJ == 0 ? cL1 : 0.0);
         } else {
-          qv = (double)qsrc[iJ];
+          qv = qsrc[iJ];
         }
         v = fma(nu, qv, v);
         int q = a.n - 1;
         for (; q >= 0; --q) {
-          if (i[q] < hi_[q]) { ++i[q]; break; }
+          if (i[q] < hi_[q]) {
+            ++i[q];
+            break;
+          }
           i[q] = lo_[q];
         }
         if (q < 0) any = false;
       }
       if (K == 0) v += cadd - ((last && s == 1) ? r.e : 0.0);
     }
-    dst[K] = (T)v;
+    if (last)
+      store(dstp + K, v, rsum, l1sum);
+    else
+      dsts[K] = v;
+  }
+  if (last && a.part) block_partials(a, it, rsum, l1sum);
+}
+
+// ---------------------------------------------- post radii (FP32 mode)
+// One thread per (box, neuron): fold the blocks' partial sums and add the
+// analytic part of the radius of each post polynomial:
+//  * the perturbation of nu by FP64 rounding: |nu~ - nu| <= dnu in sup norm,
+//    and since nu and nu~ stay in [0, 1 + dnu] on the box,
+//    |Q(nu~) - Q(nu)| <= sum_j |c_j| j dnu (1 + dnu)^(j-1);
+//  * the rounding of the approximant's coefficients (dB);
+//  * FP64 accumulation of the products: gamma(L (C + 4)) sum_j |c_j| N^j with
+//    N >= ||nu~||_1 + 1.
+__global__ void post_radii_kernel(ComposeArgs a, NeuronRec *recs) {
+  const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= a.nboxes * a.h) return;
+  NeuronRec &r = recs[item];
+  const int kind = r.kind;
+  for (int s = 0; s < 2; ++s) {
+    const int64_t it = item * 2 + s;
+    double rs = 0.0, l1 = 0.0;
+    for (int64_t b = 0; b < a.nbx; ++b) {
+      rs += a.part[(it * a.nbx + b) * 2 + 0];
+      l1 += a.part[(it * a.nbx + b) * 2 + 1];
+    }
+    const double eps_pre = s == 0 ? r.epsU : r.epsL;
+    const double l1_pre = s == 0 ? r.l1U : r.l1L;
+    double pad = 0.0;
+    if (kind == kInactive) {
+      l1 = 0.0;
+    } else if (kind == kActive) {
+      pad = eps_pre;
+      l1 = l1_pre;
+    } else if (kind == kFallback) {
+      pad = rs + (s == 0 ? r.fbpadU : r.fbpadL);
+    } else {
+      const double w = r.hi - r.lo;
+      const double src = l1_pre + eps_pre + fabs(r.lo);
+      const double dnu = gamma64(6) * src / w;
+      const double N = src / w * (1.0 + gamma64(6)) + 1.0;
+      double t1 = 0.0, t3 = 0.0, pw = 1.0;
+      for (int jj = 1; jj <= kind; ++jj) t1 += fabs(r.c[jj]) * jj * dnu * pow(1.0 + dnu, jj - 1);
+      for (int jj = 0; jj <= kind; ++jj) {
+        t3 += fabs(r.c[jj]) * pw;
+        pw *= N;
+      }
+      pad = rs + t1 + r.dB + gamma64((double)kind * ((double)a.Cin + 4.0)) * t3;
+    }
+    pad *= kPadSafety;
+    if (s == 0) {
+      r.padU = pad;
+      r.pl1U = l1;
+    } else {
+      r.padL = pad;
+      r.pl1L = l1;
+    }
   }
 }
 
@@ -363,7 +479,10 @@ __global__ void __launch_bounds__(kBlock) polymul_kernel(int n, int da, int db, 
       v = fma((double)A[it * Ca + iI], (double)B[it * Cb + iJ], v);
       int q = n - 1;
       for (; q >= 0; --q) {
-        if (i[q] < hi_[q]) { ++i[q]; break; }
+        if (i[q] < hi_[q]) {
+          ++i[q];
+          break;
+        }
         i[q] = lo_[q];
       }
       if (q < 0) more = false;
@@ -373,27 +492,49 @@ __global__ void __launch_bounds__(kBlock) polymul_kernel(int n, int da, int db, 
 }
 
 // ------------------------------------------------------------ dispatch
+static int sq_ni(int n, int D) { return (D <= 4 && n >= 2) ? 2 : 1; }
+
+// LDS bytes of the square kernel for (n, D), or 0 if there is none.
+static size_t sq_lds(int n, int D) {
+  if (D < 1 || D > 8) return 0;
+  const int NI = sq_ni(n, D);
+  const int64_t R = ipow(D + 1, NI), RP = (R + 1) & ~1;
+  return (size_t)(ipow(D + 1, n) / R) * RP * sizeof(double);
+}
+
+static bool sq_handles(int n, int Din, int Dout) {
+  const size_t l = sq_lds(n, Din);
+  return l > 0 && l <= device_lds_limit() && Dout >= 2 * Din;
+}
+
+int64_t compose_nbx(int n, int Din, int Dout, int64_t Cout, int) {
+  if (sq_handles(n, Din, Dout)) {
+    const int64_t Mo = ipow(Dout + 1, n - sq_ni(n, Din));
+    return (Mo + kBlock - 1) / kBlock;
+  }
+  return std::min<int64_t>((Cout + kBlock - 1) / kBlock, 4096);
+}
+
 template <typename T, int D, int NI>
 static hipError_t launch_sq(const ComposeArgs &a, hipStream_t s) {
-  constexpr int R = cpow(D + 1, NI), RP = (R + 3) & ~3;
-  const int no = a.n - NI;
-  const int64_t Mo = ipow(a.Dout + 1, no);
-  const size_t lds = (size_t)(a.Cin / R) * RP * sizeof(T);
-  if (lds > device_lds_limit()) return hipErrorNotSupported;
+  const size_t lds = sq_lds(a.n, D);
   RET_IF(hipFuncSetAttribute((const void *)compose_sq_kernel<T, D, NI>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)lds));
+                             (int)lds));
+  const int64_t Mo = ipow(a.Dout + 1, a.n - NI);
   dim3 grid((unsigned)((Mo + kBlock - 1) / kBlock), (unsigned)(a.h * a.nbounds), (unsigned)a.nboxes);
+  ProfScope ps(a.recs ? kProfComposeSquare : kProfPolyMul, s, 0.0);
   hipLaunchKernelGGL((compose_sq_kernel<T, D, NI>), grid, dim3(kBlock), lds, s, a);
   return hipGetLastError();
 }
 
-// Returns the degree the square kernel handles for this launch (or -1).
+// Launch the square kernel if one handles this degree; returns that degree
+// (or -1 when the Horner path must take the order-2 neurons).
 template <typename T>
 static int sq_dispatch(const ComposeArgs &a, hipStream_t s, hipError_t &err) {
   const int D = a.Din;
-  const bool ni2 = a.n >= 2;
-  if (a.Dout < 2 * D) return -1;
   err = hipSuccess;
+  if (!sq_handles(a.n, D, a.Dout)) return -1;
+  const bool ni2 = sq_ni(a.n, D) == 2;
   switch (D) {
     case 1: err = ni2 ? launch_sq<T, 1, 2>(a, s) : launch_sq<T, 1, 1>(a, s); break;
     case 2: err = ni2 ? launch_sq<T, 2, 2>(a, s) : launch_sq<T, 2, 1>(a, s); break;
@@ -405,39 +546,35 @@ static int sq_dispatch(const ComposeArgs &a, hipStream_t s, hipError_t &err) {
     case 8: err = launch_sq<T, 8, 1>(a, s); break;
     default: return -1;
   }
-  if (err == hipErrorNotSupported) {  // nu does not fit LDS: Horner path instead
-    (void)hipGetLastError();
-    err = hipSuccess;
-    return -1;
-  }
   return err == hipSuccess ? D : -1;
 }
 
 template <typename T>
 static hipError_t compose_all(const ComposeArgs &a, hipStream_t s) {
-  // element-wise rules
+  const unsigned gx = (unsigned)a.nbx;
   {
-    const int64_t blocks = std::min<int64_t>((a.Cout + kBlock - 1) / kBlock, 4096);
-    dim3 grid((unsigned)blocks, (unsigned)(a.h * a.nbounds), (unsigned)a.nboxes);
+    dim3 grid(gx, (unsigned)(a.h * a.nbounds), (unsigned)a.nboxes);
+    ProfScope ps(kProfComposeSimple, s, 0.0);
     hipLaunchKernelGGL(compose_simple_kernel<T>, grid, dim3(kBlock), 0, s, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    RET_IF(hipGetLastError());
   }
-  // order-2 square
   hipError_t err = hipSuccess;
   const int sqD = sq_dispatch<T>(a, s, err);
-  if (err != hipSuccess) return err;
-  // Horner steps for higher orders (and order 2 without a square kernel)
+  RET_IF(err);
   const int Lmax = a.Lmax;
   if (Lmax >= 3 || (Lmax == 2 && sqD != a.Din)) {
     for (int m = 1; m <= Lmax - 1; ++m) {
-      const int64_t Ct = std::max<int64_t>(a.Cout, ipow(a.Din * (m + 1) + 1, a.n));
-      const int64_t blocks = std::min<int64_t>((Ct + kBlock - 1) / kBlock, 4096);
-      dim3 grid((unsigned)blocks, (unsigned)(a.h * a.nbounds), (unsigned)a.nboxes);
+      dim3 grid(gx, (unsigned)(a.h * a.nbounds), (unsigned)a.nboxes);
+      ProfScope ps(kProfComposeHorner, s, 0.0);
       hipLaunchKernelGGL(compose_horner_kernel<T>, grid, dim3(kBlock), 0, s, a, m, sqD);
-      hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
+      RET_IF(hipGetLastError());
     }
+  }
+  if (a.part) {
+    ProfScope ps(kProfMisc, s, 0.0);
+    hipLaunchKernelGGL(post_radii_kernel, dim3((unsigned)((a.nboxes * a.h + 63) / 64)), dim3(64), 0, s, a,
+                       const_cast<NeuronRec *>(a.recs));
+    RET_IF(hipGetLastError());
   }
   return hipSuccess;
 }
@@ -446,16 +583,16 @@ hipError_t launch_compose(const ComposeArgs &a, hipStream_t s) {
   return a.fp64 ? compose_all<double>(a, s) : compose_all<float>(a, s);
 }
 
-size_t compose_scratch_bytes(int n, int Din, int Lmax, int h, int64_t nboxes, int fp64) {
+size_t compose_scratch_bytes(int n, int Din, int Lmax, int h, int64_t nboxes, int) {
   if (Lmax < 2) return 0;
   const int64_t Cq = ipow(Din * (Lmax - 1) + 1, n);
-  return align256((size_t)nboxes * h * 2 * 2 * Cq * (fp64 ? 8 : 4));
+  return align256((size_t)nboxes * h * 2 * 2 * Cq * sizeof(double));
 }
 
 hipError_t launch_poly_mul(int n, int da, int db, int64_t count, const void *A, const void *B, void *out, int fp64,
                            hipStream_t s) {
   const int64_t Cc = ipow(da + db + 1, n);
-  if (A == B && da == db) {
+  if (A == B && da == db && sq_handles(n, da, 2 * da)) {
     ComposeArgs a{};
     a.n = n;
     a.Din = da;
@@ -469,14 +606,16 @@ hipError_t launch_poly_mul(int n, int da, int db, int64_t count, const void *A, 
     a.pre = A;
     a.post = out;
     a.recs = nullptr;
+    a.part = nullptr;
     a.fp64 = fp64;
     hipError_t err = hipSuccess;
     const int d = fp64 ? sq_dispatch<double>(a, s, err) : sq_dispatch<float>(a, s, err);
-    if (err != hipSuccess) return err;
+    RET_IF(err);
     if (d == da) return hipSuccess;
   }
   const int64_t blocks = std::min<int64_t>((Cc + kBlock - 1) / kBlock, 4096);
   dim3 grid((unsigned)blocks, (unsigned)count);
+  ProfScope ps(kProfPolyMul, s, 0.0);
   if (fp64)
     hipLaunchKernelGGL(polymul_kernel<double>, grid, dim3(kBlock), 0, s, n, da, db, count, (const double *)A,
                        (const double *)B, (double *)out);

@@ -154,13 +154,84 @@ __device__ void lds_affine_fit(const double *t, int64_t C, int n, int D, int sig
   *ext = sign > 0 ? block_reduce(e, OpMax(), red) : block_reduce(e, OpMin(), red);
 }
 
+// FP32 mode: radii epsU, epsL of the stored pre-activation polynomials of
+// neuron j, i.e. the exact pre-activation lies in [L~ - epsL, U~ + epsU].
+//  * first layer: the stored FP32 coefficients against the closed form,
+//    recomputed in FP64 (its own rounding bounded by gamma);
+//  * later layers: the previous layer's post radii through W+ and W-, the
+//    FP64 accumulation of the affine map, and the exact FP32 store roundings
+//    the GEMM blocks reported.
+__device__ void pre_radii(const ConvertArgs &a, int64_t box, int j, const void *pre, double &epsU, double &epsL) {
+  if (a.layer == 0) {
+    const double *lo = a.box_lo + box * a.n, *hi = a.box_hi + box * a.n;
+    const double *w = a.W + (int64_t)j * a.n;
+    const float *p = reinterpret_cast<const float *>(pre) + (box * a.h + j) * 2 * a.C;
+    double a0 = a.b[j], sabs = fabs(a.b[j]);
+    for (int k = 0; k < a.n; ++k) {
+      a0 = fma(w[k], lo[k], a0);
+      sabs += fabs(w[k]) * (fabs(lo[k]) + fabs(hi[k] - lo[k]));
+    }
+    double r = fabs((double)p[0] - a0);
+    for (int k = 0; k < a.n; ++k) {
+      const double ak = w[k] * (hi[k] - lo[k]);
+      r += fabs((double)p[(int64_t)1 << (a.n - 1 - k)] - ak);
+    }
+    epsU = epsL = (r + gamma64(a.n + 4) * sabs) * kPadSafety;
+    return;
+  }
+  double sU = 0.0, sL = 0.0, g = fabs(a.b[j]);
+  for (int k = 0; k < a.hin; ++k) {
+    const double wk = a.W[(int64_t)j * a.hin + k];
+    const NeuronRec &P = a.prev[box * a.hin + k];
+    if (wk >= 0.0) {
+      sU += wk * P.padU;
+      sL += wk * P.padL;
+    } else {
+      sU -= wk * P.padL;
+      sL -= wk * P.padU;
+    }
+    g += fabs(wk) * (P.pl1U + P.pl1L);
+  }
+  double rU = 0.0, rL = 0.0;
+  const double *rp = a.rpart + (box * a.h + j) * 2 * a.cblocks;
+  for (int64_t cb = 0; cb < a.cblocks; ++cb) {
+    rU += rp[cb];
+    rL += rp[a.cblocks + cb];
+  }
+  const double gg = gamma64(2.0 * a.hin + 6) * g;
+  epsU = (sU + gg + rU) * kPadSafety;
+  epsL = (sL + gg + rL) * kPadSafety;
+}
+
+// Bounds from the Bernstein extrema (thread 0): in FP32 mode widened by the
+// FP64 basis-change rounding (gamma * sum|a|, the table entries lie in [0,1])
+// and the radii, then rounded outward.
+__device__ void padded_bounds(const ConvertArgs &a, int64_t box, int j, double mn, double mx, double l1L,
+                              double l1U, double &lo, double &hi, double &epsU, double &epsL) {
+  lo = mn;
+  hi = mx;
+  epsU = epsL = 0.0;
+  if (a.fp64) return;
+  pre_radii(a, box, j, a.pre, epsU, epsL);
+  const double g = gamma64((double)a.n * (a.D + 2) + 4);
+  lo = round_down(mn - g * l1L - epsL);
+  hi = round_up(mx + g * l1U + epsU);
+}
+
 // Choose the rule of one hidden neuron and fill its record (thread 0 only).
-__device__ void finish_neuron(const ConvertArgs &a, int64_t box, int j, double lo, double hi, const double *fitU,
-                              double extU, const double *fitL, double extL) {
+__device__ void finish_neuron(const ConvertArgs &a, int64_t box, int j, double lo, double hi, double epsU,
+                              double epsL, double l1U, double l1L, const double *fitU, double extU, const double *fitL,
+                              double extL) {
   NeuronRec &r = a.recs[box * a.h + j];
   r.lo = lo;
   r.hi = hi;
-  r.padU = r.padL = 0.0;
+  r.epsU = epsU;
+  r.epsL = epsL;
+  r.l1U = l1U;
+  r.l1L = l1L;
+  r.padU = r.padL = r.pl1U = r.pl1L = 0.0;
+  r.fbpadU = r.fbpadL = 0.0;
+  r.dB = 0.0;
   int code = a.L;
   if (a.plan) code = a.plan[box * a.plan_ld + a.plan_col0 + j];
   int kind, deg;
@@ -174,18 +245,41 @@ __device__ void finish_neuron(const ConvertArgs &a, int64_t box, int j, double l
 #pragma unroll
   for (int k = 0; k <= kMaxOrder; ++k) r.c[k] = 0.0;
   r.e = 0.0;
-  if (kind >= 1) relu_poly_dev(lo, hi, kind, r.c, &r.e);
+  const double mag = fabs(lo) + fabs(hi);
+  if (kind >= 1) {
+    relu_poly_dev(lo, hi, kind, r.c, &r.e);
+    if (!a.fp64) {
+      double sc = 0.0;
+      for (int k = 0; k <= kind; ++k) sc += fabs(r.c[k]);
+      double p3 = 1.0;
+      for (int k = 0; k < kind; ++k) p3 *= 3.0;
+      r.dB = mag * (gamma64(4) + gamma64(kind + 2) * p3);
+      r.e = round_up(r.e + r.dB + gamma64(2.0 * kind + 2) * sc + (hi - lo) * gamma64(3));
+    }
+  }
   if (kind == kFallback) {
-    // degree-1 approximant: upper lambda (U^ - lo), lower lambda L^; both
-    // replaced by their least-squares affine fit plus the extreme remainder.
+    // degree-1 approximant: upper lambda (U^ - lo), lower lambda L^ (with the
+    // radii folded in), each replaced by its least-squares affine fit plus
+    // the extreme remainder.
     const double lam = hi / (hi - lo);
-    double sU = 0.0, sL = 0.0;
-    for (int ax = 0; ax < a.n; ++ax) { sU += fitU[1 + ax]; sL += fitL[1 + ax]; }
-    r.fbU[0] = lam * (fitU[0] - lo - 0.5 * sU + extU);
-    r.fbL[0] = lam * (fitL[0] - 0.5 * sL + extL);
+    double sU = 0.0, sL = 0.0, aU = fabs(fitU[0]), aL = fabs(fitL[0]);
+    for (int ax = 0; ax < a.n; ++ax) {
+      sU += fitU[1 + ax];
+      sL += fitL[1 + ax];
+      aU += fabs(fitU[1 + ax]);
+      aL += fabs(fitL[1 + ax]);
+    }
+    r.fbU[0] = lam * (fitU[0] - lo - 0.5 * sU + extU + epsU);
+    r.fbL[0] = lam * (fitL[0] - 0.5 * sL + extL - epsL);
     for (int ax = 0; ax < a.n; ++ax) {
       r.fbU[1 + ax] = lam * fitU[1 + ax];
       r.fbL[1 + ax] = lam * fitL[1 + ax];
+    }
+    if (!a.fp64) {
+      const double g = gamma64((double)a.n * (a.D + 2) + 4);
+      const double ge = gamma64(a.n + 8);
+      r.fbpadU = lam * (g * l1U + ge * (aU + fabs(extU) + fabs(lo) + epsU)) + gamma64(4) * lam * (mag + hi - lo);
+      r.fbpadL = lam * (g * l1L + ge * (aL + fabs(extL) + epsL)) + gamma64(4) * lam * (mag + hi - lo);
     }
   }
   if (a.used) a.used[box * a.ld_out + a.col0 + j] = (int8_t)kind;
@@ -208,11 +302,15 @@ __global__ void __launch_bounds__(kBlock) convert_small_kernel(ConvertArgs a) {
   const bool want_fit = a.mode == 0 && a.plan && a.D > 0 && a.plan[box * a.plan_ld + a.plan_col0 + j] == 0;
   if (threadIdx.x < 2 * (kMaxInputs + 1)) fit[threadIdx.x / (kMaxInputs + 1)][threadIdx.x % (kMaxInputs + 1)] = 0.0;
   if (threadIdx.x < 2) ext[threadIdx.x] = 0.0;
-  double ext_lo = 0.0, ext_hi = 0.0;
+  double ext_lo = 0.0, ext_hi = 0.0, l1s[2] = {0.0, 0.0};
   for (int s = 1; s >= 0; --s) {  // lower first, then upper
     const T *p = reinterpret_cast<const T *>(a.pre) + (item * 2 + s) * a.C;
-    for (int64_t i = threadIdx.x; i < a.C; i += blockDim.x) t[i] = (double)p[i];
-    __syncthreads();
+    double l1 = 0.0;
+    for (int64_t i = threadIdx.x; i < a.C; i += blockDim.x) {
+      t[i] = (double)p[i];
+      l1 += fabs(t[i]);
+    }
+    l1s[s] = block_reduce(l1, OpAdd(), red);
     lds_basis_change(t, a.C, a.n, a.D, 0, a.n, tab);
     double v = s ? INFINITY : -INFINITY;
     for (int64_t i = threadIdx.x; i < a.C; i += blockDim.x) v = s ? fmin(v, t[i]) : fmax(v, t[i]);
@@ -230,13 +328,16 @@ __global__ void __launch_bounds__(kBlock) convert_small_kernel(ConvertArgs a) {
     __syncthreads();
   }
   if (threadIdx.x == 0) {
+    double lo, hi, epsU, epsL;
+    padded_bounds(a, box, j, ext_lo, ext_hi, l1s[1], l1s[0], lo, hi, epsU, epsL);
     if (a.mode == 1) {
-      a.out_lo[box * a.ld_out + a.col0 + j] = ext_lo;
-      a.out_hi[box * a.ld_out + a.col0 + j] = ext_hi;
+      a.out_lo[box * a.ld_out + a.col0 + j] = lo;
+      a.out_hi[box * a.ld_out + a.col0 + j] = hi;
     } else {
-      if (a.out_lo) a.out_lo[box * a.ld_out + a.col0 + j] = ext_lo;
-      if (a.out_hi) a.out_hi[box * a.ld_out + a.col0 + j] = ext_hi;
-      finish_neuron(a, box, j, ext_lo, ext_hi, fit[0], want_fit ? ext[0] : 0.0, fit[1], want_fit ? ext[1] : 0.0);
+      if (a.out_lo) a.out_lo[box * a.ld_out + a.col0 + j] = lo;
+      if (a.out_hi) a.out_hi[box * a.ld_out + a.col0 + j] = hi;
+      finish_neuron(a, box, j, lo, hi, epsU, epsL, l1s[0], l1s[1], fit[0], want_fit ? ext[0] : 0.0, fit[1],
+                    want_fit ? ext[1] : 0.0);
     }
   }
 }
@@ -275,7 +376,7 @@ static Split make_split(int n, int D) {
 
 // Pass A: one block per (tensor, outer slice): convert the m trailing axes.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) convert_passA_kernel(ConvertArgs a, Split sp) {
+__global__ void __launch_bounds__(kBlock) convert_passA_kernel(ConvertArgs a, Split sp, double *l1part) {
   extern __shared__ double lds[];
   const int D1 = a.D + 1;
   double *t = lds;
@@ -283,13 +384,18 @@ __global__ void __launch_bounds__(kBlock) convert_passA_kernel(ConvertArgs a, Sp
   const int64_t tensor = blockIdx.y;  // (box*h + j)*2 + s
   const int64_t o = blockIdx.x;
   fill_table(tab, a.D);
+  double *red = tab + D1 * D1;
   const T *p = reinterpret_cast<const T *>(a.pre) + tensor * a.C + o * sp.Ci;
-  for (int64_t i = threadIdx.x; i < sp.Ci; i += blockDim.x) t[i] = (double)p[i];
-  __syncthreads();
+  double l1 = 0.0;
+  for (int64_t i = threadIdx.x; i < sp.Ci; i += blockDim.x) {
+    t[i] = (double)p[i];
+    l1 += fabs(t[i]);
+  }
+  l1 = block_reduce(l1, OpAdd(), red);
   lds_basis_change(t, sp.Ci, sp.m, a.D, 0, sp.m, tab);
   double *q = a.scratch + tensor * a.C + o * sp.Ci;
   for (int64_t i = threadIdx.x; i < sp.Ci; i += blockDim.x) q[i] = t[i];
-  (void)D1;
+  if (threadIdx.x == 0) l1part[tensor * sp.Co + o] = l1;
 }
 
 // Pass B: one block per (tensor, column chunk): convert the n-m leading axes
@@ -337,16 +443,23 @@ __global__ void __launch_bounds__(kBlock) convert_passB_kernel(ConvertArgs a, Sp
 }
 
 // Fold the per-chunk extrema of both bounds of one neuron.
-__global__ void __launch_bounds__(64) convert_final_kernel(ConvertArgs a, Split sp, const double *partial) {
+__global__ void __launch_bounds__(64) convert_final_kernel(ConvertArgs a, Split sp, const double *partial,
+                                                          const double *l1part) {
   const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (item >= a.nboxes * a.h) return;
   const int64_t box = item / a.h;
   const int j = (int)(item % a.h);
-  double lo = INFINITY, hi = -INFINITY;
+  double mn = INFINITY, mx = -INFINITY, l1U = 0.0, l1L = 0.0;
   for (int64_t c = 0; c < sp.nchunk; ++c) {
-    lo = fmin(lo, partial[(item * 2 + 1) * sp.nchunk + c]);
-    hi = fmax(hi, partial[(item * 2 + 0) * sp.nchunk + c]);
+    mn = fmin(mn, partial[(item * 2 + 1) * sp.nchunk + c]);
+    mx = fmax(mx, partial[(item * 2 + 0) * sp.nchunk + c]);
   }
+  for (int64_t o = 0; o < sp.Co; ++o) {
+    l1U += l1part[(item * 2 + 0) * sp.Co + o];
+    l1L += l1part[(item * 2 + 1) * sp.Co + o];
+  }
+  double lo, hi, epsU, epsL;
+  padded_bounds(a, box, j, mn, mx, l1L, l1U, lo, hi, epsU, epsL);
   if (a.mode == 1) {
     a.out_lo[box * a.ld_out + a.col0 + j] = lo;
     a.out_hi[box * a.ld_out + a.col0 + j] = hi;
@@ -354,7 +467,7 @@ __global__ void __launch_bounds__(64) convert_final_kernel(ConvertArgs a, Split 
     if (a.out_lo) a.out_lo[box * a.ld_out + a.col0 + j] = lo;
     if (a.out_hi) a.out_hi[box * a.ld_out + a.col0 + j] = hi;
     const double zero[kMaxInputs + 1] = {0};
-    finish_neuron(a, box, j, lo, hi, zero, 0.0, zero, 0.0);
+    finish_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, zero, 0.0, zero, 0.0);
   }
 }
 
@@ -368,7 +481,8 @@ size_t convert_scratch_bytes(int n, int D, int h, int64_t nboxes) {
   if (use_small(C)) return 0;
   const Split sp = make_split(n, D);
   return align256((size_t)nboxes * h * 2 * C * sizeof(double)) +
-         align256((size_t)nboxes * h * 2 * sp.nchunk * sizeof(double));
+         align256((size_t)nboxes * h * 2 * sp.nchunk * sizeof(double)) +
+         align256((size_t)nboxes * h * 2 * sp.Co * sizeof(double));
 }
 
 hipError_t launch_convert(const ConvertArgs &a, hipStream_t s) {
@@ -377,6 +491,7 @@ hipError_t launch_convert(const ConvertArgs &a, hipStream_t s) {
     const size_t lds = (a.C + D1 * D1 + 16) * sizeof(double);
     auto k = a.fp64 ? convert_small_kernel<double> : convert_small_kernel<float>;
     RET_IF(hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.C * (a.fp64 ? 8 : 4));
     hipLaunchKernelGGL(k, dim3((unsigned)(a.nboxes * a.h)), dim3(kBlock), lds, s, a);
     return hipGetLastError();
   }
@@ -384,21 +499,28 @@ hipError_t launch_convert(const ConvertArgs &a, hipStream_t s) {
   if (sp.Co > tile_elems(a.D)) return hipErrorInvalidValue;
   double *partial = reinterpret_cast<double *>(reinterpret_cast<char *>(a.scratch) +
                                                align256((size_t)a.nboxes * a.h * 2 * a.C * sizeof(double)));
+  double *l1part = reinterpret_cast<double *>(reinterpret_cast<char *>(partial) +
+                                              align256((size_t)a.nboxes * a.h * 2 * sp.nchunk * sizeof(double)));
   const int64_t tensors = a.nboxes * a.h * 2;
   {
-    const size_t lds = (sp.Ci + D1 * D1) * sizeof(double);
+    const size_t lds = (sp.Ci + D1 * D1 + 16) * sizeof(double);
     auto k = a.fp64 ? convert_passA_kernel<double> : convert_passA_kernel<float>;
     RET_IF(hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(k, dim3((unsigned)sp.Co, (unsigned)tensors), dim3(kBlock), lds, s, a, sp);
+    ProfScope ps(kProfConvertPassA, s, (double)tensors * a.C * ((a.fp64 ? 8 : 4) + 8));
+    hipLaunchKernelGGL(k, dim3((unsigned)sp.Co, (unsigned)tensors), dim3(kBlock), lds, s, a, sp, l1part);
   }
   {
     const size_t lds = (sp.Co * sp.Q + D1 * D1 + 16) * sizeof(double);
     RET_IF(hipFuncSetAttribute((const void *)convert_passB_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    ProfScope ps(kProfConvertPassB, s, (double)tensors * a.C * 8);
     hipLaunchKernelGGL(convert_passB_kernel, dim3((unsigned)sp.nchunk, (unsigned)tensors), dim3(kBlock), lds, s, a,
                        sp, partial);
   }
-  hipLaunchKernelGGL(convert_final_kernel, dim3((unsigned)((a.nboxes * a.h + 63) / 64)), dim3(64), 0, s, a, sp,
-                     (const double *)partial);
+  {
+    ProfScope ps(kProfConvertFinal, s, (double)tensors * sp.nchunk * 8);
+    hipLaunchKernelGGL(convert_final_kernel, dim3((unsigned)((a.nboxes * a.h + 63) / 64)), dim3(64), 0, s, a, sp,
+                       (const double *)partial, (const double *)l1part);
+  }
   return hipGetLastError();
 }
 

@@ -184,3 +184,65 @@ def test_invalid_box_gives_nan_only_for_that_box():
     g = _bounds_gpu(case, sched="batched")
     assert np.all(np.isnan(g["out_lo"][1])) and np.all(np.isnan(g["neuron_hi"][1]))
     assert np.all(np.isfinite(g["out_lo"][[0, 2]]))
+
+
+# ------------------------------------------------------------ FP32 mode
+# Bar: within 1e-4 (same relative measure) of the FP64 oracle, every padded
+# bound contains the oracle's bound, and sampled network values stay inside.
+
+def _assert_fp32(g, o, nh):
+    _assert_parity(g, o, 1e-4, nh)
+    if nh:
+        assert np.all(g["neuron_lo"][:, :nh] <= o["neuron_lo"]) and np.all(g["neuron_hi"][:, :nh] >= o["neuron_hi"])
+    assert np.all(g["out_lo"] <= o["out_lo"]) and np.all(g["out_hi"] >= o["out_hi"])
+
+
+def test_plain_4_20_20_20_2_fp32_padded():
+    case = wl.cfg2()
+    g = _bounds_gpu(case, precision="fp32")
+    o = _oracle(case)
+    _assert_fp32(g, o, case.n_hidden)
+    w_pad = (g["out_hi"] - g["out_lo"]).mean()
+    w_ref = (o["out_hi"] - o["out_lo"]).mean()
+    print(f"  fp32 width / fp64 width = {w_pad / w_ref:.8f}")
+    assert w_pad / w_ref < 1.001
+
+
+@pytest.mark.parametrize("L", [1, 2, 3])
+def test_random_nets_fp32_padded(L):
+    case = wl.random_net_case([3, 7, 6, 2], seed=31 + L, n_boxes=6)
+    g = _bounds_gpu(case, L=L, precision="fp32", sched="batched")
+    o = _oracle(case, L=L)
+    _assert_fp32(g, o, case.n_hidden)
+
+
+def test_fp32_padded_sound_by_sampling():
+    case = wl.random_net_case([4, 10, 8, 2], seed=41, n_boxes=4)
+    g = _bounds_gpu(case, precision="fp32", sched="batched")
+    rng = np.random.default_rng(1)
+    for i in range(case.n_boxes):
+        _, x = H.box_points(case.box_lo[i], case.box_hi[i], 20000, rng)
+        pres = H.forward(case.Ws, case.bs, x)
+        hid = np.concatenate(pres[:-1], axis=1)
+        assert np.all(hid >= g["neuron_lo"][i]) and np.all(hid <= g["neuron_hi"][i])
+        assert np.all(pres[-1] >= g["out_lo"][i]) and np.all(pres[-1] <= g["out_hi"][i])
+
+
+def test_fp32_deterministic():
+    case = wl.random_net_case([4, 10, 10, 3], seed=5, n_boxes=5)
+    a = _bounds_gpu(case, precision="fp32", sched="batched")
+    b = _bounds_gpu(case, precision="fp32", sched="batched")
+    c = _bounds_gpu(case, precision="fp32", sched="per_box")
+    for k in ("neuron_lo", "neuron_hi", "out_lo", "out_hi"):
+        assert np.array_equal(a[k], b[k]) and np.array_equal(a[k], c[k])
+
+
+def test_large_output_two_pass_fp32_and_fp64():
+    """Output tensors above the one-block LDS size take the two-pass basis
+    change (cfg-4-like shape, one box): parity in both precisions."""
+    case = wl.cfg4(n_boxes=1)
+    o = _oracle(case)
+    g64 = _bounds_gpu(case, precision="fp64")
+    _assert_parity(g64, o, 1e-9, case.n_hidden)
+    g32 = _bounds_gpu(case, precision="fp32")
+    _assert_fp32(g32, o, case.n_hidden)
