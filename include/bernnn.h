@@ -64,10 +64,14 @@ typedef enum {
   BERN_PLAN_PLAIN = 0,   /* the paper's rule: ReLU order L for every unstable neuron,
                             all neurons of hidden layer i stored at degree L*D_i
                             (Section 5.4, elevation to the highest expected degree) */
-  BERN_PLAN_GIVEN = 1,   /* caller's int8 code per (box, hidden neuron): 1..8 = ReLU
-                            Bernstein order for that neuron if unstable, 0 = linear
-                            fallback; stable neurons keep degree D (active) or 0
-                            (inactive); each layer is stored at the largest degree  */
+  BERN_PLAN_GIVEN = 1,   /* caller's int8 code per (box, hidden neuron): k >= 1 = ReLU
+                            Bernstein order for that neuron if unstable, k <= 0 =
+                            linear fallback; stable neurons keep degree D (active)
+                            or 0 (inactive); a box's layer is stored at the largest
+                            degree of its neurons. Orders are lowered until the
+                            post degree k*D stays within the plain rule's degree
+                            at order L (opts.L) for that layer, so no tensor
+                            outgrows the plain form's                          */
   BERN_PLAN_LEARNED = 2  /* like GIVEN, with the codes chosen on the device by a
                             degree predictor (bern_pred) from each neuron's interval
                             and coefficient statistics                             */
@@ -82,11 +86,15 @@ typedef struct bern_net bern_net;   /* opaque: network on the device            
 typedef struct bern_pred bern_pred; /* opaque: degree predictor (MLP) on the device */
 
 typedef struct {
-  int32_t L;          /* ReLU approximation order of the plain rule, 1..8          */
+  int32_t L;          /* ReLU approximation order of the plain rule, 1..8; for the
+                         GIVEN / LEARNED plans the degree cap (see bern_plan)      */
   int32_t precision;  /* bern_precision                                            */
   int32_t plan;       /* bern_plan                                                 */
   int32_t sched;      /* bern_sched                                                */
   const bern_pred *pred; /* predictor for BERN_PLAN_LEARNED, else ignored           */
+  float *features;    /* optional device output [n_boxes][sum hidden][8]: the
+                         predictor's input features of every hidden neuron
+                         (written in every plan mode; for training records)      */
   int32_t max_wave;   /* upper limit on boxes per wave (0 = as many as fit)         */
   int32_t reserved[7];
 } bern_opts;
@@ -200,6 +208,48 @@ bern_status bern_prof_reset(void);
 int32_t bern_prof_classes(void);
 const char *bern_prof_name(int32_t cls);
 bern_status bern_prof_read(int32_t cls, int64_t *launches, double *ms, double *bytes);
+
+/* Degree predictor (learned plan). A small MLP 8 -> 64 -> 64 -> 4 with ReLU
+ * hidden layers maps the features of an unstable neuron to a class: 0 =
+ * linear fallback, k = 1..3 = Bernstein ReLU approximant of order k. Any class
+ * gives sound bounds (Props. 1-2 for every order, Def. 2 for the fallback),
+ * so the predictor only trades tightness for work.
+ * Parameters (FP32, bern_pred_params() = 5012 values, in this order):
+ *   mean[8], std[8] (feature normalisation), W1[64][8], b1[64], W2[64][64],
+ *   b2[64], W3[4][64], b3[4]  (row-major, output index first).
+ * Features of a neuron with interval [lo, hi], w = hi - lo, pre degree D in
+ * layer i of an H-layer net, downstream sensitivity s (sum over the network's
+ * outputs of the products of |W| from this neuron on), affine least-squares
+ * fits of its Bernstein control nets (means m_U, m_L, slopes g_U) and their
+ * remainder spreads r_U, r_L:
+ *   -lo/w, log w, i/(H-1), log(D+1), (m_U - m_L)/w, log(s w), (r_U + r_L)/w,
+ *   sum|g_U|/w.
+ * Inference inside bern_bounds rounds weights and activations to BF16. */
+int32_t bern_pred_params(void);
+/* params: host, bern_pred_params() floats; copied to the current device. */
+bern_status bern_pred_create(const float *params, int64_t n_params, bern_pred **out);
+void bern_pred_destroy(bern_pred *pred);
+
+/* Training and evaluation kernels of the predictor (FP32, deterministic),
+ * asynchronous on `stream`, all pointers device pointers:
+ *   bern_mlp_forward   logits [N][4] of features X [N][8] (bf16 != 0: the
+ *                      BF16 inference arithmetic of the pipeline)
+ *   bern_mlp_backward  mean softmax cross-entropy over labels y [N] (0..3):
+ *                      gradient G [5012] (zero on the normalisation entries)
+ *                      and the loss in loss[0]; scratch of
+ *                      bern_mlp_backward_scratch(N) bytes
+ *   bern_mlp_adam      one Adam step (bias-corrected, step >= 1) of P with G,
+ *                      moments m, v [5012] (normalisation entries untouched)
+ *   bern_mlp_classify  argmax classes [N] (int8) and logits [N][4] */
+size_t bern_mlp_backward_scratch(int64_t N);
+bern_status bern_mlp_forward(const float *P, int64_t N, const float *X, float *logits, int32_t bf16,
+                             void *stream);
+bern_status bern_mlp_backward(const float *P, int64_t N, const float *X, const int8_t *y, float *G,
+                              float *loss, void *scratch, void *stream);
+bern_status bern_mlp_adam(float *P, const float *G, float *m, float *v, int64_t step, float lr,
+                          float beta1, float beta2, float eps, void *stream);
+bern_status bern_mlp_classify(const float *P, int64_t N, const float *X, float *logits, int8_t *cls,
+                              int32_t bf16, void *stream);
 
 /* Status name and the calling thread's last error message. */
 const char *bern_status_str(int32_t status);

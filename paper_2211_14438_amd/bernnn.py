@@ -28,8 +28,8 @@ _vp = ctypes.c_void_p
 
 class bern_opts(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("precision", ctypes.c_int32), ("plan", ctypes.c_int32),
-                ("sched", ctypes.c_int32), ("pred", ctypes.c_void_p), ("max_wave", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("sched", ctypes.c_int32), ("pred", ctypes.c_void_p), ("features", ctypes.c_void_p),
+                ("max_wave", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
 
 
 class bern_stats(ctypes.Structure):
@@ -95,6 +95,24 @@ def lib():
     L.bern_prof_read.restype = i32
     L.bern_prof_read.argtypes = [i32, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_double)]
+    fp = ctypes.POINTER(ctypes.c_float)
+    L.bern_pred_params.restype = i32
+    L.bern_pred_params.argtypes = []
+    L.bern_pred_create.restype = i32
+    L.bern_pred_create.argtypes = [fp, i64, ctypes.POINTER(_vp)]
+    L.bern_pred_destroy.restype = None
+    L.bern_pred_destroy.argtypes = [_vp]
+    L.bern_mlp_backward_scratch.restype = sz
+    L.bern_mlp_backward_scratch.argtypes = [i64]
+    L.bern_mlp_forward.restype = i32
+    L.bern_mlp_forward.argtypes = [_vp, i64, _vp, _vp, i32, _vp]
+    L.bern_mlp_backward.restype = i32
+    L.bern_mlp_backward.argtypes = [_vp, i64, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.bern_mlp_adam.restype = i32
+    L.bern_mlp_adam.argtypes = [_vp, _vp, _vp, _vp, i64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                ctypes.c_float, _vp]
+    L.bern_mlp_classify.restype = i32
+    L.bern_mlp_classify.argtypes = [_vp, i64, _vp, _vp, _vp, i32, _vp]
     _LIB = L
     return L
 
@@ -102,7 +120,9 @@ def lib():
 EXPORTED = ("bern_opts_default", "bern_net_create", "bern_net_destroy", "bern_net_inputs", "bern_net_hidden",
             "bern_net_outputs", "bern_workspace_size", "bern_bounds", "bern_basis_minmax_scratch",
             "bern_basis_minmax", "bern_poly_mul", "bern_relu_poly", "bern_status_str", "bern_last_error",
-            "bern_prof_enable", "bern_prof_reset", "bern_prof_classes", "bern_prof_name", "bern_prof_read")
+            "bern_prof_enable", "bern_prof_reset", "bern_prof_classes", "bern_prof_name", "bern_prof_read",
+            "bern_pred_params", "bern_pred_create", "bern_pred_destroy", "bern_mlp_backward_scratch",
+            "bern_mlp_forward", "bern_mlp_backward", "bern_mlp_adam", "bern_mlp_classify")
 
 
 def status_str(s):
@@ -125,7 +145,7 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def make_opts(L=2, precision="fp64", plan="plain", sched="per_box", max_wave=0, pred=None):
+def make_opts(L=2, precision="fp64", plan="plain", sched="per_box", max_wave=0, pred=None, features=None):
     o = bern_opts()
     lib().bern_opts_default(ctypes.byref(o))
     o.L = int(L)
@@ -133,8 +153,70 @@ def make_opts(L=2, precision="fp64", plan="plain", sched="per_box", max_wave=0, 
     o.plan = _PLAN[plan] if isinstance(plan, str) else int(plan)
     o.sched = _SCHED[sched] if isinstance(sched, str) else int(sched)
     o.max_wave = int(max_wave)
-    o.pred = None if pred is None else pred
+    o.pred = None if pred is None else (pred.handle if isinstance(pred, Predictor) else pred)
+    o.features = None if features is None else features.data_ptr()
     return o
+
+
+N_PARAMS = 5012
+
+
+class Predictor:
+    """Degree predictor on the current device (parameters copied at creation)."""
+
+    def __init__(self, params):
+        params = np.ascontiguousarray(params, dtype=np.float32)
+        h = _vp()
+        _check(lib().bern_pred_create(params.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), params.size,
+                                      ctypes.byref(h)))
+        self.handle = h
+        self.params = params
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().bern_pred_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mlp_forward(P, X, bf16=False, stream=None):
+    import torch
+    N = X.shape[0]
+    logits = torch.empty((N, 4), dtype=torch.float32, device=X.device)
+    _check(lib().bern_mlp_forward(_ptr(P), N, _ptr(X.contiguous()), _ptr(logits), 1 if bf16 else 0, _stream(stream)))
+    return logits
+
+
+def mlp_backward(P, X, y, scratch=None, stream=None):
+    import torch
+    N = X.shape[0]
+    G = torch.empty(N_PARAMS, dtype=torch.float32, device=X.device)
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    if scratch is None:
+        scratch = torch.empty(lib().bern_mlp_backward_scratch(N), dtype=torch.uint8, device=X.device)
+    _check(lib().bern_mlp_backward(_ptr(P), N, _ptr(X.contiguous()), _ptr(y.contiguous()), _ptr(G), _ptr(loss),
+                                   _ptr(scratch), _stream(stream)))
+    return G, loss
+
+
+def mlp_adam(P, G, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(lib().bern_mlp_adam(_ptr(P), _ptr(G), _ptr(m), _ptr(v), int(step), float(lr), float(beta1),
+                               float(beta2), float(eps), _stream(stream)))
+
+
+def mlp_classify(P, X, bf16=True, stream=None):
+    import torch
+    N = X.shape[0]
+    logits = torch.empty((N, 4), dtype=torch.float32, device=X.device)
+    cls = torch.empty(N, dtype=torch.int8, device=X.device)
+    _check(lib().bern_mlp_classify(_ptr(P), N, _ptr(X.contiguous()), _ptr(logits), _ptr(cls), 1 if bf16 else 0,
+                                   _stream(stream)))
+    return cls, logits
 
 
 class Net:
@@ -174,7 +256,7 @@ class Net:
 
 
 def bounds(net, box_lo, box_hi, L=2, precision="fp64", plan="plain", sched="per_box", degree_plan=None,
-           max_wave=0, workspace=None, stream=None, outputs=None, pred=None):
+           max_wave=0, workspace=None, stream=None, outputs=None, pred=None, features=None):
     """Bounds of every box. ``box_lo``/``box_hi``: float64 CUDA tensors
     [n_boxes, n]. Returns a dict of CUDA tensors (neuron_lo/hi, out_lo/hi,
     used_plan) plus the run statistics. Asynchronous on ``stream``."""
@@ -184,7 +266,7 @@ def bounds(net, box_lo, box_hi, L=2, precision="fp64", plan="plain", sched="per_
     box_lo = box_lo.contiguous()
     box_hi = box_hi.contiguous()
     nb = box_lo.shape[0]
-    o = make_opts(L=L, precision=precision, plan=plan, sched=sched, max_wave=max_wave, pred=pred)
+    o = make_opts(L=L, precision=precision, plan=plan, sched=sched, max_wave=max_wave, pred=pred, features=features)
     if outputs is None:
         nh = max(net.n_hidden, 1)
         outputs = dict(
@@ -195,7 +277,8 @@ def bounds(net, box_lo, box_hi, L=2, precision="fp64", plan="plain", sched="per_
             used_plan=torch.empty((nb, nh), dtype=torch.int8, device=dev),
         )
     if workspace is None:
-        total, one = net.workspace_size(nb, L=L, precision=precision, plan=plan, sched=sched, max_wave=max_wave)
+        total, one = net.workspace_size(nb, L=L, precision=precision, plan=plan, sched=sched, max_wave=max_wave,
+                                        pred=pred)
         workspace = torch.empty(total + 256, dtype=torch.uint8, device=dev)
     ws_ptr = workspace.data_ptr()
     pad = (-ws_ptr) % 256

@@ -23,9 +23,9 @@ __global__ void __launch_bounds__(kBlock) layer1_kernel(Layer1Args a) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t c = i % C;
-    const int64_t bj = i / C;  // box * h + j
+    const int64_t bj = i / C;  // launch box * h + j
     const int j = (int)(bj % a.h);
-    const int64_t box = bj / a.h;
+    const int64_t box = a.bids ? a.bids[bj / a.h] : bj / a.h;
     const double *lo = a.box_lo + box * a.n;
     const double *hi = a.box_hi + box * a.n;
     const double *w = a.W + (int64_t)j * a.n;
@@ -38,7 +38,7 @@ __global__ void __launch_bounds__(kBlock) layer1_kernel(Layer1Args a) {
       const int axis = a.n - 1 - (__ffsll((unsigned long long)c) - 1);
       v = w[axis] * (hi[axis] - lo[axis]);
     }
-    T *out = reinterpret_cast<T *>(a.pre) + bj * 2 * C;
+    T *out = reinterpret_cast<T *>(a.pre) + box * a.slot + (int64_t)j * 2 * C;
     out[c] = (T)v;
     out[C + c] = (T)v;
   }
@@ -63,22 +63,47 @@ hipError_t launch_layer1(const Layer1Args &a, hipStream_t s) {
 // reports, per output neuron and bound, the sum of |fl32(y) - y| over its
 // coefficients (the exact rounding of the stored tensor), reduced in a fixed
 // order.
-template <typename T, int MB>
+template <typename T, int MB, int KU>
 __global__ void __launch_bounds__(kBlock) gemm_kernel(GemmArgs a) {
   __shared__ double red[kBlock / 64][MB][2];
   const int m0 = blockIdx.x * MB;
   const int64_t c = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
-  const int64_t box = blockIdx.z;
+  const int64_t box = a.bids ? a.bids[blockIdx.z] : blockIdx.z;
   const bool valid = c < a.C;
-  const T *X = reinterpret_cast<const T *>(a.post) + box * a.hin * 2 * a.C;
+  const T *X = reinterpret_cast<const T *>(a.post) + box * a.slot_in;
   double accM[MB], accR[MB];
 #pragma unroll
   for (int mm = 0; mm < MB; ++mm) accM[mm] = accR[mm] = 0.0;
   const int mcount = min(MB, a.h - m0);
   if (valid) {
-    for (int k = 0; k < a.hin; ++k) {
-      const double u = (double)X[(int64_t)k * 2 * a.C + c];
-      const double l = (double)X[(int64_t)k * 2 * a.C + a.C + c];
+    const T *Xc = X + c;
+    const int64_t st = 2 * a.C;
+    int k = 0;
+    // KU inputs per step: 2*KU independent loads in flight per thread
+    for (; k + KU <= a.hin; k += KU) {
+      double u[KU], l[KU];
+#pragma unroll
+      for (int q = 0; q < KU; ++q) {
+        u[q] = (double)Xc[(int64_t)(k + q) * st];
+        l[q] = (double)Xc[(int64_t)(k + q) * st + a.C];
+      }
+#pragma unroll
+      for (int q = 0; q < KU; ++q) {
+        const double M = (u[q] + l[q]) * 0.5;
+        const double R = (u[q] - l[q]) * 0.5;
+#pragma unroll
+        for (int mm = 0; mm < MB; ++mm) {
+          if (mm < mcount) {
+            const double w = a.W[(int64_t)(m0 + mm) * a.hin + k + q];
+            accM[mm] = fma(w, M, accM[mm]);
+            accR[mm] = fma(fabs(w), R, accR[mm]);
+          }
+        }
+      }
+    }
+    for (; k < a.hin; ++k) {
+      const double u = (double)Xc[(int64_t)k * st];
+      const double l = (double)Xc[(int64_t)k * st + a.C];
       const double M = (u + l) * 0.5;
       const double R = (u - l) * 0.5;
 #pragma unroll
@@ -91,7 +116,7 @@ __global__ void __launch_bounds__(kBlock) gemm_kernel(GemmArgs a) {
       }
     }
   }
-  T *Y = reinterpret_cast<T *>(a.pre) + box * a.h * 2 * a.C;
+  T *Y = reinterpret_cast<T *>(a.pre) + box * a.slot_out;
   const bool track = a.rpart != nullptr;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -125,7 +150,7 @@ __global__ void __launch_bounds__(kBlock) gemm_kernel(GemmArgs a) {
     const int mm = threadIdx.x >> 1, s = threadIdx.x & 1;
     double v = 0.0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v += red[w][mm][s];
-    a.rpart[((box * a.h + m0 + mm) * 2 + s) * a.cblocks + blockIdx.y] = v;
+    a.rpart[box * a.rpart_slot + ((int64_t)(m0 + mm) * 2 + s) * a.cblocks + blockIdx.y] = v;
   }
 }
 
@@ -134,13 +159,13 @@ int64_t gemm_cblocks(int64_t C) { return (C + kBlock - 1) / kBlock; }
 hipError_t launch_gemm(const GemmArgs &a0, hipStream_t s) {
   GemmArgs a = a0;
   a.cblocks = gemm_cblocks(a.C);
-  constexpr int MB = 32;
+  constexpr int MB = 16, KU = 2;
   dim3 grid((a.h + MB - 1) / MB, (unsigned)a.cblocks, (unsigned)a.nboxes);
   ProfScope ps(kProfGemm, s, (double)a.nboxes * (2.0 * a.hin + 2.0 * a.h) * a.C * (a.fp64 ? 8 : 4));
   if (a.fp64)
-    hipLaunchKernelGGL((gemm_kernel<double, MB>), grid, dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((gemm_kernel<double, MB, KU>), grid, dim3(kBlock), 0, s, a);
   else
-    hipLaunchKernelGGL((gemm_kernel<float, MB>), grid, dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((gemm_kernel<float, MB, KU>), grid, dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

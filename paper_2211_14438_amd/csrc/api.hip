@@ -81,9 +81,10 @@ ProfScope::~ProfScope() {
   g_prof.push_back({cls, (hipEvent_t)ev0, e, bytes});
 }
 
-static const char *kProfNames[kProfCount] = {"layer1",         "gemm",           "convert_small",  "convert_passA",
-                                             "convert_passB",  "convert_final",  "compose_simple", "compose_square",
-                                             "compose_horner", "poly_mul",       "misc"};
+static const char *kProfNames[kProfCount] = {
+    "layer1",         "gemm",         "convert_small",  "convert_passA",  "convert_passB", "convert_final",
+    "compose_scatter", "compose_fill", "compose_square", "compose_horner", "poly_mul",      "predictor",
+    "misc"};
 
 size_t device_lds_limit() {
   static std::mutex mu;
@@ -105,7 +106,7 @@ size_t device_lds_limit() {
 // Host-side plan of one network under one set of options: degree of every
 // layer's pre-activation and post tensors and the per-box workspace layout.
 struct Plan {
-  int H, n, L, Lmax;
+  int H, n, L, Lmax, mode;
   bool fp64;
   std::vector<int> Dpre, Dpost;     // per layer i = 1..H (index i-1); Dpost for hidden layers
   std::vector<int64_t> Cpre, Cpost;
@@ -123,12 +124,12 @@ struct bern_net {
   std::vector<int> widths;
   std::vector<int64_t> woff, boff, noff;  // per layer offsets into W, b and hidden neurons
   double *W64 = nullptr, *b64 = nullptr;
-  float *W32 = nullptr;
+  double *sens = nullptr;  // [nh] downstream sensitivity of every hidden neuron
   int device = 0;
 };
 
 struct bern_pred {
-  int dummy;
+  float *params = nullptr;  // device, bern_pred_params() floats
 };
 
 using namespace bern;
@@ -139,16 +140,18 @@ static bern_status plan_net(const bern_net *net, const bern_opts *o, Plan &p) {
   p.fp64 = o->precision == BERN_FP64;
   p.elem = p.fp64 ? 8 : 4;
   p.L = o->L;
-  if (o->plan == BERN_PLAN_PLAIN) {
-    if (o->L < 1 || o->L > kMaxOrder) {
-      set_error("L = %d outside 1..%d", o->L, kMaxOrder);
-      return BERN_E_DEGREE;
-    }
-    p.Lmax = o->L;
-  } else {
-    set_error("plan %d not available in this build", o->plan);
+  p.mode = o->plan;
+  if (o->L < 1 || o->L > kMaxOrder) {
+    set_error("L = %d outside 1..%d", o->L, kMaxOrder);
+    return BERN_E_DEGREE;
+  }
+  if (o->plan == BERN_PLAN_LEARNED && !o->pred) {
+    set_error("BERN_PLAN_LEARNED needs a predictor");
     return BERN_E_ARG;
   }
+  // Every box's tensors stay within the plain rule's sizes at order L (plan
+  // codes are clamped to that), so one fixed slot per box suffices.
+  p.Lmax = o->L;
   p.Dpre.assign(p.H, 0);
   p.Dpost.assign(p.H, 0);
   p.Cpre.assign(p.H, 0);
@@ -179,13 +182,22 @@ static bern_status plan_net(const bern_net *net, const bern_opts *o, Plan &p) {
       }
       p.arenaB = std::max(p.arenaB, align256((size_t)h * 2 * p.Cpost[i] * p.elem));
       p.recs = std::max(p.recs, align256((size_t)h * sizeof(NeuronRec)));
-      p.nbx[i] = compose_nbx(p.n, D, Dn, p.Cpost[i], p.fp64);
-      if (!p.fp64) p.cpart = std::max(p.cpart, align256((size_t)h * 2 * p.nbx[i] * 2 * 8));
+      int64_t nb = 0;
+      if (p.mode == BERN_PLAN_PLAIN) {
+        nb = compose_nbx(p.n, D, Dn, p.Cpost[i], p.fp64);
+      } else {
+        for (int di = 0; di <= D; ++di)
+          for (int dq = di; dq <= Dn; ++dq) nb = std::max(nb, compose_nbx(p.n, di, dq, ipow(dq + 1, p.n), p.fp64));
+      }
+      p.nbx[i] = nb;
+      if (!p.fp64) p.cpart = std::max(p.cpart, align256((size_t)h * 2 * nb * 2 * 8));
       if (p.Lmax >= 2) p.horner = std::max(p.horner, compose_scratch_bytes(p.n, D, p.Lmax, h, 1, p.fp64));
       D = Dn;
     }
   }
-  p.flags = 256;
+  // per box: validity flag, post degree, one id per (layer, phase) list, and
+  // the predicted code of every hidden neuron
+  p.flags = align256(sizeof(int) * (2 + 2 * (size_t)p.H) + (size_t)net->nh);
   return BERN_OK;
 }
 
@@ -259,22 +271,34 @@ bern_status bern_net_create(int32_t H, const int32_t *widths, const double *W, c
     net->hmax = std::max(net->hmax, widths[i]);
   }
   net->nh = (int)no;
-  std::vector<float> w32(nw);
-  for (int64_t i = 0; i < nw; ++i) w32[i] = (float)W[i];
+  // downstream sensitivity of hidden layer i: 1^T |W^(H)| ... |W^(i+1)|
+  std::vector<double> sens(std::max(1, net->nh), 0.0);
+  {
+    std::vector<double> v(widths[H], 1.0);
+    for (int i = H; i >= 2; --i) {  // v over layer i -> over layer i-1
+      const int hi_ = widths[i], hp = widths[i - 1];
+      std::vector<double> u(hp, 0.0);
+      const double *Wi = W + net->woff[i - 1];
+      for (int r = 0; r < hi_; ++r)
+        for (int c = 0; c < hp; ++c) u[c] += v[r] * std::fabs(Wi[(int64_t)r * hp + c]);
+      v.swap(u);
+      for (int c = 0; c < hp; ++c) sens[net->noff[i - 2] + c] = v[c];
+    }
+  }
   (void)hipGetDevice(&net->device);
   auto fail = [&](hipError_t e) {
     set_error("device allocation/copy failed: %s", hipGetErrorString(e));
-    (void)hipFree(net->W64); (void)hipFree(net->b64); (void)hipFree(net->W32);
+    (void)hipFree(net->W64); (void)hipFree(net->b64); (void)hipFree(net->sens);
     delete net;
     return BERN_E_DEVICE;
   };
   hipError_t e;
   if ((e = hipMalloc(&net->W64, nw * 8)) != hipSuccess) return fail(e);
-  if ((e = hipMalloc(&net->W32, nw * 4)) != hipSuccess) return fail(e);
   if ((e = hipMalloc(&net->b64, nb * 8)) != hipSuccess) return fail(e);
+  if ((e = hipMalloc(&net->sens, sens.size() * 8)) != hipSuccess) return fail(e);
   if ((e = hipMemcpy(net->W64, W, nw * 8, hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
-  if ((e = hipMemcpy(net->W32, w32.data(), nw * 4, hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
   if ((e = hipMemcpy(net->b64, b, nb * 8, hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
+  if ((e = hipMemcpy(net->sens, sens.data(), sens.size() * 8, hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
   *out = net;
   return BERN_OK;
 }
@@ -282,8 +306,8 @@ bern_status bern_net_create(int32_t H, const int32_t *widths, const double *W, c
 void bern_net_destroy(bern_net *net) {
   if (!net) return;
   (void)hipFree(net->W64);
-  (void)hipFree(net->W32);
   (void)hipFree(net->b64);
+  (void)hipFree(net->sens);
   delete net;
 }
 
@@ -351,10 +375,29 @@ __global__ void poison_kernel(int64_t nb, const int *flag, int nh, int o, double
   }
 }
 
-// Enqueue the whole launch sequence of one wave of `B` boxes.
-static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts *o, int64_t B, const double *box_lo,
-                            const double *box_hi, const int8_t *plan, double *nlo, double *nhi, double *olo,
-                            double *ohi, int8_t *used, char *ws, hipStream_t s) {
+// Largest per-neuron post degree of every box of the wave.
+__global__ void box_degree_kernel(int64_t nb, int h, const NeuronRec *recs, int *deg) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  int d = 0;
+  for (int j = 0; j < h; ++j) d = max(d, recs[b * h + j].deg);
+  deg[b] = d;
+}
+
+// Boxes of one degree class within a wave.
+struct BoxClass {
+  int Din, Dout;
+  std::vector<int> ids;
+};
+
+// Enqueue the launch sequence of one wave of `B` boxes. The plain rule keeps
+// every box at the same degrees: one class, no host round trip. Plans with
+// per-neuron degrees read each box's post degree back once per hidden layer
+// and launch each degree class of boxes on its own (a box's tensors stay
+// dense at the box's own degree inside its fixed slot).
+static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts *o, int64_t b0, int64_t B,
+                            const double *box_lo, const double *box_hi, const int8_t *plan, double *nlo, double *nhi,
+                            double *olo, double *ohi, int8_t *used, char *ws, hipStream_t s) {
   char *cur = ws;
   NeuronRec *recbuf[2];
   recbuf[0] = reinterpret_cast<NeuronRec *>(cur); cur += p.recs * B;
@@ -366,7 +409,13 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
   double *conv = reinterpret_cast<double *>(cur); cur += p.conv * B;
   void *horner = cur; cur += p.horner * B;
   int *flags = reinterpret_cast<int *>(cur);
+  int *degs = flags + B;
+  int *idlists = flags + 2 * B;  // [H][2][B]
+  int8_t *codes = reinterpret_cast<int8_t *>(idlists + (int64_t)p.H * 2 * B);  // [B][nh]
+  const bool learned = p.mode == BERN_PLAN_LEARNED;
   const int n = net->n;
+  const int64_t slotA = (int64_t)(p.arenaA / p.elem), slotB = (int64_t)(p.arenaB / p.elem);
+  const bool plain = p.mode == BERN_PLAN_PLAIN;
 
   {
     ProfScope ps(kProfMisc, s, 0.0);
@@ -375,92 +424,205 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
   }
   BERN_HIP_TRY(hipGetLastError());
 
+  // degree classes of the current layer's pre-activations
+  std::vector<BoxClass> classes(1);
+  classes[0].Din = 1;
+  classes[0].Dout = 0;
+  std::vector<int> dcur(B, 1);
+  auto upload = [&](std::vector<BoxClass> &cl, int layer, int phase, std::vector<const int *> &dev) -> bern_status {
+    dev.assign(cl.size(), nullptr);
+    if (cl.size() == 1 && (int64_t)cl[0].ids.size() == B) return BERN_OK;  // identity
+    std::vector<int> all;
+    for (auto &c : cl) all.insert(all.end(), c.ids.begin(), c.ids.end());
+    int *dst = idlists + ((int64_t)layer * 2 + phase) * B;
+    BERN_HIP_TRY(hipMemcpyAsync(dst, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    int64_t off = 0;
+    for (size_t k = 0; k < cl.size(); ++k) {
+      dev[k] = dst + off;
+      off += cl[k].ids.size();
+    }
+    return BERN_OK;
+  };
+  for (auto &c : classes) {
+    c.ids.resize(B);
+    for (int64_t b = 0; b < B; ++b) c.ids[b] = (int)b;
+  }
+
+  {
+    Layer1Args a{n, net->widths[1], B, nullptr, slotA, box_lo, box_hi, net->W64 + net->woff[0],
+                 net->b64 + net->boff[0], A, p.fp64 ? 1 : 0};
+    BERN_HIP_TRY(launch_layer1(a, s));
+  }
+
   for (int i = 0; i < p.H; ++i) {
     const int hin = net->widths[i], h = net->widths[i + 1];
     const bool last = (i == p.H - 1);
     NeuronRec *recs = recbuf[i & 1];
     const NeuronRec *prev = recbuf[(i + 1) & 1];
-    // affine map -> pre-activation tensors in arena A
-    if (i == 0) {
-      Layer1Args a{n, h, B, box_lo, box_hi, net->W64 + net->woff[0], net->b64 + net->boff[0], A, p.fp64 ? 1 : 0};
-      BERN_HIP_TRY(launch_layer1(a, s));
+    int cap = 1;
+    for (int q = 0; q <= i; ++q) cap *= p.L;
+    // bounds read-off (+ rules and approximants for hidden layers), per class
+    std::vector<const int *> cid;
+    bern_status st = upload(classes, i, 0, cid);
+    if (st != BERN_OK) return st;
+    for (size_t k = 0; k < classes.size(); ++k) {
+      const BoxClass &cl = classes[k];
+      ConvertArgs c{};
+      c.n = n;
+      c.D = cl.Din;
+      c.h = h;
+      c.L = p.L;
+      c.C = ipow(cl.Din + 1, n);
+      c.nboxes = (int64_t)cl.ids.size();
+      c.bids = cid[k];
+      c.slot = slotA;
+      c.cap = cap;
+      c.pre = A;
+      c.fp64 = p.fp64 ? 1 : 0;
+      c.recs = recs;
+      c.scratch = conv;
+      c.scratch_bytes = p.conv * B;
+      c.plan = (plain || learned) ? nullptr : plan;
+      c.learned = learned && !last;
+      c.fits = (learned || o->features) && !last;
+      c.layer = i;
+      c.hin = hin;
+      c.prev = prev;
+      c.W = net->W64 + net->woff[i];
+      c.b = net->b64 + net->boff[i];
+      c.box_lo = box_lo;
+      c.box_hi = box_hi;
+      c.rpart = gpart;
+      c.rpart_slot = (int64_t)(p.gpart / sizeof(double));
+      c.cblocks = gemm_cblocks(c.C);
+      c.plan_ld = net->nh;
+      c.plan_col0 = last ? 0 : net->noff[i];
+      if (last) {
+        c.mode = 1;
+        c.out_lo = olo;
+        c.out_hi = ohi;
+        c.ld_out = net->o;
+        c.col0 = 0;
+        c.used = nullptr;
+      } else {
+        c.mode = 0;
+        c.out_lo = nlo;
+        c.out_hi = nhi;
+        c.ld_out = net->nh;
+        c.col0 = net->noff[i];
+        c.used = used;
+      }
+      BERN_HIP_TRY(launch_convert(c, s));
+      if (!last && (learned || o->features)) {
+        LearnArgs la{};
+        la.n = n;
+        la.D = cl.Din;
+        la.h = h;
+        la.H = p.H;
+        la.layer = i;
+        la.nboxes = c.nboxes;
+        la.bids = cid[k];
+        la.recs = recs;
+        la.sens = net->sens + net->noff[i];
+        la.feat = o->features ? o->features + (size_t)b0 * net->nh * 8 : nullptr;
+        la.nh = net->nh;
+        la.noff = net->noff[i];
+        la.params = learned ? o->pred->params : nullptr;
+        la.codes = codes;
+        la.used = used;
+        la.cap = cap;
+        la.fp64 = p.fp64 ? 1 : 0;
+        la.L = p.L;
+        if (learned)
+          BERN_HIP_TRY(launch_learned_rules(la, s));
+        else
+          BERN_HIP_TRY(launch_features(la, s));
+      }
+    }
+    if (last) break;
+
+    // post degree of every box -> classes (Din, Dout)
+    std::vector<BoxClass> next;
+    if (plain) {
+      next = classes;
+      for (auto &c : next) c.Dout = p.L * c.Din;
     } else {
+      {
+        ProfScope ps(kProfMisc, s, 0.0);
+        hipLaunchKernelGGL(box_degree_kernel, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, B, h,
+                           (const NeuronRec *)recs, degs);
+      }
+      BERN_HIP_TRY(hipGetLastError());
+      std::vector<int> hd(B);
+      BERN_HIP_TRY(hipMemcpyAsync(hd.data(), degs, B * sizeof(int), hipMemcpyDeviceToHost, s));
+      BERN_HIP_TRY(hipStreamSynchronize(s));
+      for (int64_t b = 0; b < B; ++b) {
+        const int din = dcur[b], dout = std::max(hd[b], 0);
+        size_t k = 0;
+        for (; k < next.size(); ++k)
+          if (next[k].Din == din && next[k].Dout == dout) break;
+        if (k == next.size()) next.push_back(BoxClass{din, dout, {}});
+        next[k].ids.push_back((int)b);
+      }
+    }
+    std::vector<const int *> pid;
+    st = upload(next, i, 1, pid);
+    if (st != BERN_OK) return st;
+    for (size_t k = 0; k < next.size(); ++k) {
+      const BoxClass &cl = next[k];
+      // composition -> post tensors in arena B
+      ComposeArgs m{};
+      m.n = n;
+      m.Din = cl.Din;
+      m.Dout = cl.Dout;
+      m.h = h;
+      m.bids = pid[k];
+      m.slot_in = slotA;
+      m.slot_out = slotB;
+      m.nbounds = 2;
+      m.Lmax = p.Lmax;
+      m.Cin = ipow(cl.Din + 1, n);
+      m.Cout = ipow(cl.Dout + 1, n);
+      m.Cq = ipow(cl.Din * std::max(1, p.Lmax - 1) + 1, n);
+      m.nboxes = (int64_t)cl.ids.size();
+      m.pre = A;
+      m.post = Bp;
+      m.recs = recs;
+      m.fp64 = p.fp64 ? 1 : 0;
+      m.scratch = horner;
+      m.scratch_bytes = p.horner * B;
+      m.nbx = compose_nbx(n, cl.Din, cl.Dout, m.Cout, p.fp64);
+      m.part = p.fp64 ? nullptr : cpart;
+      BERN_HIP_TRY(launch_compose(m, s));
+      // affine map of the next layer -> pre-activation tensors in arena A
       GemmArgs a{};
-      a.hin = hin;
-      a.h = h;
-      a.C = p.Cpre[i];
-      a.nboxes = B;
+      a.hin = h;
+      a.h = net->widths[i + 2];
+      a.C = m.Cout;
+      a.nboxes = m.nboxes;
+      a.bids = pid[k];
+      a.slot_in = slotB;
+      a.slot_out = slotA;
       a.post = Bp;
       a.pre = A;
-      a.W = net->W64 + net->woff[i];
-      a.b = net->b64 + net->boff[i];
+      a.W = net->W64 + net->woff[i + 1];
+      a.b = net->b64 + net->boff[i + 1];
       a.fp64 = p.fp64 ? 1 : 0;
       a.rpart = p.fp64 ? nullptr : gpart;
+      a.rpart_slot = (int64_t)(p.gpart / sizeof(double));
       BERN_HIP_TRY(launch_gemm(a, s));
     }
-    // bounds read-off (+ rules and approximants for hidden layers)
-    ConvertArgs c{};
-    c.n = n;
-    c.D = p.Dpre[i];
-    c.h = h;
-    c.L = p.L;
-    c.C = p.Cpre[i];
-    c.nboxes = B;
-    c.pre = A;
-    c.fp64 = p.fp64 ? 1 : 0;
-    c.recs = recs;
-    c.scratch = conv;
-    c.scratch_bytes = p.conv * B;
-    c.plan = plan;
-    c.layer = i;
-    c.hin = hin;
-    c.prev = prev;
-    c.W = net->W64 + net->woff[i];
-    c.b = net->b64 + net->boff[i];
-    c.box_lo = box_lo;
-    c.box_hi = box_hi;
-    c.rpart = gpart;
-    c.cblocks = gemm_cblocks(p.Cpre[i]);
-    c.plan_ld = net->nh;
-    c.plan_col0 = last ? 0 : net->noff[i];
-    if (last) {
-      c.mode = 1;
-      c.out_lo = olo;
-      c.out_hi = ohi;
-      c.ld_out = net->o;
-      c.col0 = 0;
-      c.used = nullptr;
-    } else {
-      c.mode = 0;
-      c.out_lo = nlo;
-      c.out_hi = nhi;
-      c.ld_out = net->nh;
-      c.col0 = net->noff[i];
-      c.used = used;
+    // next layer's classes: by the new pre degree
+    std::vector<BoxClass> nc;
+    for (auto &cl : next) {
+      size_t k = 0;
+      for (; k < nc.size(); ++k)
+        if (nc[k].Din == cl.Dout) break;
+      if (k == nc.size()) nc.push_back(BoxClass{cl.Dout, 0, {}});
+      nc[k].ids.insert(nc[k].ids.end(), cl.ids.begin(), cl.ids.end());
+      for (int b : cl.ids) dcur[b] = cl.Dout;
     }
-    BERN_HIP_TRY(launch_convert(c, s));
-    if (last) break;
-    // composition -> post tensors in arena B
-    ComposeArgs m{};
-    m.n = n;
-    m.Din = p.Dpre[i];
-    m.Dout = p.Dpost[i];
-    m.h = h;
-    m.nbounds = 2;
-    m.Lmax = p.Lmax;
-    m.Cin = p.Cpre[i];
-    m.Cout = p.Cpost[i];
-    m.Cq = ipow(p.Dpre[i] * std::max(1, p.Lmax - 1) + 1, n);
-    m.nboxes = B;
-    m.pre = A;
-    m.post = Bp;
-    m.recs = recs;
-    m.fp64 = p.fp64 ? 1 : 0;
-    m.scratch = horner;
-    m.scratch_bytes = p.horner * B;
-    m.nbx = p.nbx[i];
-    m.part = p.fp64 ? nullptr : cpart;
-    BERN_HIP_TRY(launch_compose(m, s));
+    classes.swap(nc);
   }
   {
     ProfScope ps(kProfMisc, s, 0.0);
@@ -489,6 +651,7 @@ extern "C" bern_status bern_bounds(const bern_net *net, const bern_opts *opts, i
     set_error("BERN_PLAN_GIVEN needs a plan array");
     return BERN_E_ARG;
   }
+
   Plan p;
   if ((st = plan_net(net, opts, p)) != BERN_OK) return st;
   const size_t per_box = p.per_box();
@@ -504,7 +667,7 @@ extern "C" bern_status bern_bounds(const bern_net *net, const bern_opts *opts, i
   int nwaves = 0;
   for (int64_t b0 = 0; b0 < n_boxes; b0 += wave) {
     const int64_t B = std::min<int64_t>(wave, n_boxes - b0);
-    st = run_wave(net, p, opts, B, box_lo + b0 * net->n, box_hi + b0 * net->n,
+    st = run_wave(net, p, opts, b0, B, box_lo + b0 * net->n, box_hi + b0 * net->n,
                   plan ? plan + b0 * net->nh : nullptr, neuron_lo ? neuron_lo + b0 * net->nh : nullptr,
                   neuron_hi ? neuron_hi + b0 * net->nh : nullptr, out_lo + b0 * net->o, out_hi + b0 * net->o,
                   used_plan ? used_plan + b0 * net->nh : nullptr, reinterpret_cast<char *>(workspace), s);
@@ -609,5 +772,74 @@ extern "C" bern_status bern_relu_poly(int64_t count, int32_t L, const double *lo
     return BERN_E_ARG;
   }
   BERN_HIP_TRY(launch_relu_poly(count, L, lo, hi, c, e, reinterpret_cast<hipStream_t>(stream)));
+  return BERN_OK;
+}
+
+// ------------------------------------------------------ degree predictor
+extern "C" int32_t bern_pred_params(void) { return mlp_params(); }
+
+extern "C" bern_status bern_pred_create(const float *params, int64_t n_params, bern_pred **out) {
+  if (!out || !params || n_params != mlp_params()) {
+    set_error("bern_pred_create needs %d parameters", mlp_params());
+    return BERN_E_ARG;
+  }
+  *out = nullptr;
+  for (int64_t i = 0; i < n_params; ++i)
+    if (!std::isfinite(params[i])) {
+      set_error("non-finite predictor parameter at %lld", (long long)i);
+      return BERN_E_NUMERIC;
+    }
+  for (int f = 0; f < 8; ++f)
+    if (!(params[8 + f] > 0.f)) {
+      set_error("feature scale %d must be positive", f);
+      return BERN_E_NUMERIC;
+    }
+  bern_pred *p = new (std::nothrow) bern_pred();
+  if (!p) { set_error("out of host memory"); return BERN_E_OOM; }
+  hipError_t e = hipMalloc(&p->params, n_params * sizeof(float));
+  if (e == hipSuccess) e = hipMemcpy(p->params, params, n_params * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    set_error("predictor upload failed: %s", hipGetErrorString(e));
+    (void)hipFree(p->params);
+    delete p;
+    return BERN_E_DEVICE;
+  }
+  *out = p;
+  return BERN_OK;
+}
+
+extern "C" void bern_pred_destroy(bern_pred *p) {
+  if (!p) return;
+  (void)hipFree(p->params);
+  delete p;
+}
+
+extern "C" size_t bern_mlp_backward_scratch(int64_t N) { return mlp_backward_scratch(N); }
+
+extern "C" bern_status bern_mlp_forward(const float *P, int64_t N, const float *X, float *logits, int32_t bf16,
+                                        void *stream) {
+  if (!P || N < 1 || !X || !logits) { set_error("bad arguments"); return BERN_E_ARG; }
+  BERN_HIP_TRY(launch_mlp_forward(P, N, X, logits, nullptr, bf16, reinterpret_cast<hipStream_t>(stream)));
+  return BERN_OK;
+}
+
+extern "C" bern_status bern_mlp_backward(const float *P, int64_t N, const float *X, const int8_t *y, float *G,
+                                         float *loss, void *scratch, void *stream) {
+  if (!P || N < 1 || !X || !y || !G || !scratch) { set_error("bad arguments"); return BERN_E_ARG; }
+  BERN_HIP_TRY(launch_mlp_backward(P, N, X, y, G, loss, (float *)scratch, reinterpret_cast<hipStream_t>(stream)));
+  return BERN_OK;
+}
+
+extern "C" bern_status bern_mlp_adam(float *P, const float *G, float *m, float *v, int64_t step, float lr,
+                                     float beta1, float beta2, float eps, void *stream) {
+  if (!P || !G || !m || !v || step < 1) { set_error("bad arguments"); return BERN_E_ARG; }
+  BERN_HIP_TRY(launch_mlp_adam(P, G, m, v, step, lr, beta1, beta2, eps, reinterpret_cast<hipStream_t>(stream)));
+  return BERN_OK;
+}
+
+extern "C" bern_status bern_mlp_classify(const float *P, int64_t N, const float *X, float *logits, int8_t *cls,
+                                         int32_t bf16, void *stream) {
+  if (!P || N < 1 || !X || !logits || !cls) { set_error("bad arguments"); return BERN_E_ARG; }
+  BERN_HIP_TRY(launch_mlp_classify(P, N, X, logits, cls, bf16, reinterpret_cast<hipStream_t>(stream)));
   return BERN_OK;
 }

@@ -70,6 +70,13 @@ struct NeuronRec {
   double fbU[kMaxInputs + 1];
   double fbL[kMaxInputs + 1];
   double fbpadU, fbpadL;   // radii of the fallback's own FP64 arithmetic
+  // Least-squares affine fit l(t) = f[0] + sum_a f[1+a] (t_a - 1/2) of the
+  // Bernstein control net of U^ and L^, and the range [rmin, rmax] of the
+  // remainders b_K - l(K/D) (valid when fitted != 0).
+  double fitU[kMaxInputs + 1], fitL[kMaxInputs + 1];
+  double rmaxU, rminU, rmaxL, rminL;
+  int32_t fitted;
+  int32_t pad_;
 };
 
 // Rounding-error helpers (FP32 mode). gamma(m) = m u / (1 - m u) for FP64.
@@ -98,9 +105,11 @@ enum ProfClass : int {
   kProfConvertPassB,
   kProfConvertFinal,
   kProfComposeSimple,
+  kProfComposeFill,
   kProfComposeSquare,
   kProfComposeHorner,
   kProfPolyMul,
+  kProfPredictor,
   kProfMisc,
   kProfCount
 };
@@ -117,9 +126,15 @@ struct ProfScope {
 // Defined in the .hip files; every launcher enqueues on `stream` and returns a
 // HIP error code (no host synchronisation).
 
+// Box addressing shared by the launchers: a launch covers `nboxes` boxes of
+// one degree class; box g of the launch is wave box bids[g] (identity when
+// bids is null); each wave box owns a fixed slot of `slot_*` elements in the
+// tensor arenas, filled densely at the box's own degree.
 struct Layer1Args {
   int n, h;
   int64_t nboxes;
+  const int *bids;
+  int64_t slot;
   const double *box_lo, *box_hi;  // [B][n]
   const double *W, *b;            // W^(1) [h][n], b^(1) [h], FP64
   void *pre;                      // [B][h][2][2^n]
@@ -130,12 +145,15 @@ hipError_t launch_layer1(const Layer1Args &a, hipStream_t s);
 struct GemmArgs {
   int hin, h;
   int64_t C, nboxes;
+  const int *bids;
+  int64_t slot_in, slot_out;
   const void *post;               // [B][hin][2][C]
   void *pre;                      // [B][h][2][C]
   const double *W;                // [h][hin]
   const double *b;                // [h]
   int fp64;
-  double *rpart;                  // FP32 mode: [B][h][2][cblocks] sums of |fl32(y) - y|
+  double *rpart;                  // FP32 mode: per wave box (stride rpart_slot): [h][2][cblocks]
+  int64_t rpart_slot;             //   sums of |fl32(y) - y| per coefficient block
   int64_t cblocks;                // coefficient blocks of the launch (set by the launcher)
 };
 int64_t gemm_cblocks(int64_t C);
@@ -144,6 +162,9 @@ hipError_t launch_gemm(const GemmArgs &a, hipStream_t s);
 struct ConvertArgs {
   int n, D, h, L;                 // L: ReLU order of the plain rule
   int64_t C, nboxes;
+  const int *bids;
+  int64_t slot;
+  int cap;                        // largest post degree a neuron may take (plan codes are clamped)
   const void *pre;                // [B][h][2][C] power coefficients
   int fp64;
   NeuronRec *recs;                // [B][h] (hidden layers)
@@ -153,13 +174,16 @@ struct ConvertArgs {
   const NeuronRec *prev;          // [B][hin] records of the previous layer (layer > 0)
   const double *W, *b;            // this layer's W [h][hin] and b [h] (FP64)
   const double *box_lo, *box_hi;  // [B][n] (layer 0)
-  const double *rpart;            // GEMM rounding partials [B][h][2][cblocks] (layer > 0)
+  const double *rpart;            // GEMM rounding partials, per wave box (stride rpart_slot):
+  int64_t rpart_slot;             //   [h][2][cblocks] (layer > 0)
   int64_t cblocks;
   double *out_lo, *out_hi;        // [B][ld_out] bounds written at column col0 + j
   int64_t ld_out, col0;
   int8_t *used;                   // [B][ld_out] or null (hidden layers)
   const int8_t *plan;             // [B][plan_ld] degree codes or null (plain rule)
   int64_t plan_ld, plan_col0;
+  int learned;                    // rules are chosen later by the predictor (fits always needed)
+  int fits;                       // compute the affine fits of every hidden neuron (features)
   int mode;                       // 0 hidden layer, 1 output layer
   double *scratch;                // FP64 staging for tensors too large for LDS
   size_t scratch_bytes;
@@ -169,6 +193,8 @@ size_t convert_scratch_bytes(int n, int D, int h, int64_t nboxes);
 
 struct ComposeArgs {
   int n, Din, Dout, h;
+  const int *bids;
+  int64_t slot_in, slot_out;
   double *part;                   // FP32 mode: [B*h*nbounds][nbx][2] (rounding sum, l1 sum) per block
   int64_t nbx;                    // blocks per item of every compose launch of the layer
   int nbounds;                    // 2 (upper, lower) for the network, 1 for plain products
@@ -189,6 +215,35 @@ size_t compose_scratch_bytes(int n, int Din, int Lmax, int h, int64_t nboxes, in
 
 // Largest dynamic LDS allocation one block may use on the current device.
 size_t device_lds_limit();
+
+struct LearnArgs {
+  int n, D, h, H, layer;
+  int64_t nboxes;
+  const int *bids;
+  NeuronRec *recs;                // [B][h]
+  const double *sens;             // downstream sensitivity of this layer's neurons [h]
+  float *feat;                    // [B][nh][8] (column block noff); optional copy of the features
+  int64_t nh, noff;
+  const float *params;            // predictor parameters (FP32 master copy)
+  int8_t *codes;                  // [B][nh] predicted codes (column block noff)
+  int8_t *used;                   // [B][nh] or null
+  int cap, fp64, L;
+};
+// features -> (optional) BF16 MLP -> codes -> rules, for one class of boxes.
+hipError_t launch_learned_rules(const LearnArgs &a, hipStream_t s);
+// features only (any plan), for collecting training records.
+hipError_t launch_features(const LearnArgs &a, hipStream_t s);
+
+int mlp_params();
+hipError_t launch_mlp_forward(const float *P, int64_t N, const float *X, float *logits, float *hid, int bf16,
+                              hipStream_t s);
+hipError_t launch_mlp_backward(const float *P, int64_t N, const float *X, const int8_t *y, float *G, float *loss,
+                               float *scratch, hipStream_t s);
+size_t mlp_backward_scratch(int64_t N);
+hipError_t launch_mlp_adam(float *P, const float *G, float *m, float *v, int64_t step, float lr, float b1, float b2,
+                           float eps, hipStream_t s);
+hipError_t launch_mlp_classify(const float *P, int64_t N, const float *X, float *logits, int8_t *cls, int bf16,
+                               hipStream_t s);
 
 // Step-level primitives behind the public entry points of the same names.
 hipError_t launch_basis_minmax(int n, int D, int64_t count, const void *coef, int fp64, double *bern,

@@ -32,13 +32,25 @@ namespace bern {
 
 __host__ __device__ constexpr int cpow(int b, int e) { return e == 0 ? 1 : b * cpow(b, e - 1); }
 
-// item index of (box, neuron j, bound s)
-__device__ inline int64_t item_of(const ComposeArgs &a, int64_t box, int j, int s) {
-  return (box * a.h + j) * a.nbounds + s;
+// launch-local item index of (launch box g, neuron j, bound s)
+__device__ inline int64_t item_of(const ComposeArgs &a, int64_t g, int j, int s) {
+  return (g * a.h + j) * a.nbounds + s;
 }
 
-// Block-wide sums of (rounding, l1) in a fixed order; thread 0 writes them.
-__device__ void block_partials(const ComposeArgs &a, int64_t it, double r, double l1) {
+__device__ inline int64_t wave_box(const ComposeArgs &a, int64_t g) { return a.bids ? a.bids[g] : g; }
+
+template <typename T>
+__device__ inline const T *in_tensor(const ComposeArgs &a, int64_t box, int j, int s) {
+  return reinterpret_cast<const T *>(a.pre) + box * a.slot_in + ((int64_t)j * a.nbounds + s) * a.Cin;
+}
+template <typename T>
+__device__ inline T *out_tensor(const ComposeArgs &a, int64_t box, int j, int s) {
+  return reinterpret_cast<T *>(a.post) + box * a.slot_out + ((int64_t)j * a.nbounds + s) * a.Cout;
+}
+
+// Block-wide sums of (rounding, l1) in a fixed order; thread 0 writes them
+// to partial slot `slot` of item `it`.
+__device__ void block_partials_slot(const ComposeArgs &a, int64_t it, int64_t slot, double r, double l1) {
   __shared__ double red[kBlock / 64][2];
   for (int off = 32; off > 0; off >>= 1) {
     r += __shfl_xor(r, off, 64);
@@ -56,9 +68,13 @@ __device__ void block_partials(const ComposeArgs &a, int64_t it, double r, doubl
       sr += red[w][0];
       sl += red[w][1];
     }
-    a.part[(it * a.nbx + blockIdx.x) * 2 + 0] = sr;
-    a.part[(it * a.nbx + blockIdx.x) * 2 + 1] = sl;
+    a.part[(it * a.nbx + slot) * 2 + 0] = sr;
+    a.part[(it * a.nbx + slot) * 2 + 1] = sl;
   }
+}
+
+__device__ inline void block_partials(const ComposeArgs &a, int64_t it, double r, double l1) {
+  block_partials_slot(a, it, blockIdx.x, r, l1);
 }
 
 // Store one coefficient; track its rounding and magnitude.
@@ -113,49 +129,75 @@ struct SqGeom {
 };
 
 // Square path: nu in LDS (FP64) as rows of R = (D+1)^NI coefficients;
-// thread = one output row of the layer's post tensor.
+// thread = one output row of the layer's post tensor. Rows of nu that are
+// exactly zero are flagged while nu is staged (their products add exact
+// zeros, so skipping them leaves every result bit unchanged); output rows whose
+// outer digit sum exceeds twice the largest digit sum of a nonzero row only
+// receive such products and stay as the fill kernel left them (zero).
 template <typename T, int D, int NI>
 __global__ void __launch_bounds__(kBlock) compose_sq_kernel(ComposeArgs a) {
   using G = SqGeom<D, NI>;
   constexpr int D1 = G::D1, E1 = G::E1, R = G::R, RO = G::RO, RP = G::RP;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double *rows = reinterpret_cast<double *>(smem_raw);
+  __shared__ int tmax;
 
   const int j = blockIdx.y / a.nbounds, s = blockIdx.y % a.nbounds;
-  const int64_t box = blockIdx.z;
+  const int64_t g = blockIdx.z, box = wave_box(a, g);
   const NeuronRec *rec = a.recs ? &a.recs[box * a.h + j] : nullptr;
   if (rec && rec->kind != 2) return;
   const NuSource ns = nu_of(a, rec, s);
 
   const int no = a.n - NI;
-  const int64_t it = item_of(a, box, j, s);
-  const T *p = reinterpret_cast<const T *>(a.pre) + it * a.Cin;
+  const int64_t nrows = a.Cin / R;
+  unsigned char *nz = smem_raw + nrows * RP * sizeof(double);  // one flag per row
+  const int64_t it = item_of(a, g, j, s);
+  const T *p = in_tensor<T>(a, box, j, s);
+  if (threadIdx.x == 0) tmax = -1;
   for (int64_t i = threadIdx.x; i < a.Cin; i += blockDim.x) {
     double v = (double)p[i];
     if (i == 0) v += ns.shift - ns.lo;
     rows[(i / R) * RP + (i % R)] = v / ns.w;
   }
   __syncthreads();
+  for (int64_t r = threadIdx.x; r < nrows; r += blockDim.x) {
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < R; ++q) any |= rows[r * RP + q] != 0.0;
+    nz[r] = any ? 1 : 0;
+    if (any) {
+      int ds = 0;
+      int64_t rem = r;
+      for (int q = 0; q < no; ++q) {
+        ds += (int)(rem % D1);
+        rem /= D1;
+      }
+      atomicMax(&tmax, ds);
+    }
+  }
+  __syncthreads();
+  const int dsmax = 2 * tmax;  // -2 when nu is the zero polynomial
 
   const int Do1 = a.Dout + 1;
   int64_t Mo = 1;
   for (int q = 0; q < no; ++q) Mo *= Do1;
   const int64_t ko = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = ko < Mo;
   const int Rout = (NI == 1) ? Do1 : Do1 * Do1;
-  T *out = reinterpret_cast<T *>(a.post) + it * a.Cout + (valid ? ko : 0) * Rout;
+  T *out = out_tensor<T>(a, box, j, s) + (ko < Mo ? ko : 0) * Rout;
   double rsum = 0.0, l1sum = 0.0;
 
   // outer digits of ko (base Dout+1): per-axis pair ranges packed 4 bits/axis
   uint64_t lop = 0, hip = 0;
   int64_t rK = 0, cnt = 1;
-  bool zero = !valid, lin_ok = true, origin = true;
-  if (valid) {
+  bool work = ko < Mo, lin_ok = true, origin = true;
+  if (work) {
     int64_t rem = ko, pw = 1;
+    int dsum = 0;
     for (int q = no - 1; q >= 0; --q) {
       const int k = (int)(rem % Do1);
       rem /= Do1;
-      if (k > 2 * D) zero = true;
+      dsum += k;
+      if (k > 2 * D) work = false;
       const int l = max(0, k - D), hh = min(k, D);
       const int sh = 4 * (no - 1 - q);
       lop |= (uint64_t)(l & 15) << sh;
@@ -166,11 +208,9 @@ __global__ void __launch_bounds__(kBlock) compose_sq_kernel(ComposeArgs a) {
       if (k > D) lin_ok = false;
       if (k != 0) origin = false;
     }
+    if (dsum > dsmax && !origin) work = false;
   }
-  if (zero) {
-    if (valid)
-      for (int q = 0; q < Rout; ++q) out[q] = (T)0;
-  } else {
+  if (work) {
     double acc[RO];
 #pragma unroll
     for (int q = 0; q < RO; ++q) acc[q] = 0.0;
@@ -185,15 +225,17 @@ __global__ void __launch_bounds__(kBlock) compose_sq_kernel(ComposeArgs a) {
     uint64_t iv = lop;
     const int64_t half = cnt >> 1;
     for (int64_t t = 0; t < half; ++t) {
-      double ra[R], rb[R];
-      const double *pa = rows + rI * RP;
-      const double *pb = rows + (rK - rI) * RP;
+      if (nz[rI] & nz[rK - rI]) {
+        double ra[R], rb[R];
+        const double *pa = rows + rI * RP;
+        const double *pb = rows + (rK - rI) * RP;
 #pragma unroll
-      for (int q = 0; q < R; ++q) {
-        ra[q] = pa[q];
-        rb[q] = pb[q];
+        for (int q = 0; q < R; ++q) {
+          ra[q] = pa[q];
+          rb[q] = pb[q];
+        }
+        row_conv<D, NI>(ra, rb, acc);
       }
-      row_conv<D, NI>(ra, rb, acc);
       int64_t pw = 1;
       for (int q = no - 1; q >= 0; --q) {
         const int sh = 4 * (no - 1 - q);
@@ -211,7 +253,7 @@ __global__ void __launch_bounds__(kBlock) compose_sq_kernel(ComposeArgs a) {
     }
 #pragma unroll
     for (int q = 0; q < RO; ++q) acc[q] = acc[q] + acc[q];
-    if (cnt & 1) {  // middle pair I = K - I
+    if ((cnt & 1) && nz[rI]) {  // middle pair I = K - I
       double ra[R];
       const double *pa = rows + rI * RP;
 #pragma unroll
@@ -231,8 +273,6 @@ __global__ void __launch_bounds__(kBlock) compose_sq_kernel(ComposeArgs a) {
 #pragma unroll
       for (int q = 0; q < R; ++q) lin[q] = pl[q];
     }
-    if (a.Dout != 2 * D)
-      for (int q = 0; q < Rout; ++q) out[q] = (T)0;
     if constexpr (NI == 1) {
 #pragma unroll
       for (int q0 = 0; q0 < E1; ++q0) {
@@ -257,56 +297,82 @@ __global__ void __launch_bounds__(kBlock) compose_sq_kernel(ComposeArgs a) {
 }
 
 // ------------------------------------------------- element-wise rules
-// inactive -> 0, active -> copy, order 1 -> c1 nu + c0 (- e), fallback -> affine.
+// Zero fill of the launch's output tensors before the square kernel and the
+// scatter below write their (sparse) parts. A box's post tensors are one
+// contiguous range at the start of its 256-byte aligned slot, so the fill is
+// plain 16-byte stores over that range (the Horner kernel, for orders >= 3,
+// overwrites its own tensors whole afterwards).
+__global__ void __launch_bounds__(kBlock) compose_fill_kernel(ComposeArgs a, int64_t bytes_per_box, int elem) {
+  const int64_t g = blockIdx.y, box = wave_box(a, g);
+  char *base = reinterpret_cast<char *>(a.post) + box * a.slot_out * elem;
+  const int64_t n16 = bytes_per_box / 16;
+  int4 *v = reinterpret_cast<int4 *>(base);
+  const int4 z = make_int4(0, 0, 0, 0);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
+    v[i] = z;
+  const int64_t tail = bytes_per_box - n16 * 16;  // multiple of elem
+  if (blockIdx.x == 0 && (int64_t)threadIdx.x * elem < tail) {
+    char *t = base + n16 * 16 + (int64_t)threadIdx.x * elem;
+    if (elem == 8) *reinterpret_cast<double *>(t) = 0.0;
+    else *reinterpret_cast<float *>(t) = 0.0f;
+  }
+}
+
+// One block per (box, neuron, bound) of order <= 1: inactive (nothing to
+// add to the zero fill), active (copy of the pre tensor into the larger
+// degree), order 1 (c1 nu + c0, minus e for the lower bound) and the linear
+// fallback (n+1 affine coefficients). Writes the block's rounding and l1 sums
+// to partial slot 0 and zeros to the item's other slots.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) compose_simple_kernel(ComposeArgs a) {
+__global__ void __launch_bounds__(kBlock) compose_scatter_kernel(ComposeArgs a) {
   const int j = blockIdx.y / a.nbounds, s = blockIdx.y % a.nbounds;
-  const int64_t box = blockIdx.z;
+  const int64_t g = blockIdx.z, box = wave_box(a, g);
   const NeuronRec &r = a.recs[box * a.h + j];
   const int kind = r.kind;
   if (kind >= 2) return;
   const NuSource ns = nu_of(a, &r, s);
-  const int64_t it = item_of(a, box, j, s);
-  const T *p = reinterpret_cast<const T *>(a.pre) + it * a.Cin;
-  T *out = reinterpret_cast<T *>(a.post) + it * a.Cout;
+  const int64_t it = item_of(a, g, j, s);
+  const T *p = in_tensor<T>(a, box, j, s);
+  T *out = out_tensor<T>(a, box, j, s);
   const int Do1 = a.Dout + 1, Di1 = a.Din + 1;
   double rsum = 0.0, l1sum = 0.0;
-  for (int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; K < a.Cout; K += (int64_t)gridDim.x * blockDim.x) {
-    // digits of K in base Dout+1 -> index in the input tensor (base Din+1)
-    int64_t rem = K, idx = 0, pw = 1;
-    bool inside = true;
-    int ones = 0, one_axis = -1;
-    for (int q = a.n - 1; q >= 0; --q) {
-      const int k = (int)(rem % Do1);
-      rem /= Do1;
-      if (k > a.Din) inside = false;
-      idx += (int64_t)k * pw;
-      pw *= Di1;
-      if (k == 1) {
-        ++ones;
-        one_axis = q;
-      } else if (k != 0) {
-        ones = 100;
+  if (kind == kActive || kind == 1) {
+    for (int64_t I = threadIdx.x; I < a.Cin; I += blockDim.x) {
+      // position of input index I (base Din+1) in the output (base Dout+1)
+      int64_t rem = I, o = 0, pw = 1;
+      for (int q = a.n - 1; q >= 0; --q) {
+        const int k = (int)(rem % Di1);
+        rem /= Di1;
+        o += (int64_t)k * pw;
+        pw *= Do1;
       }
-    }
-    double v = 0.0;
-    if (kind == kActive) {
-      v = inside ? (double)p[idx] : 0.0;
-    } else if (kind == 1) {
-      if (inside) {
-        double x = (double)p[idx];
-        if (K == 0) x += ns.shift - ns.lo;
-        v = r.c[1] * (x / ns.w);
+      double v = (double)p[I];
+      if (kind == 1) {
+        if (I == 0) v += ns.shift - ns.lo;
+        v = r.c[1] * (v / ns.w);
+        if (I == 0) v += r.c[0] - (s == 1 ? r.e : 0.0);
       }
-      if (K == 0) v += r.c[0] - (s == 1 ? r.e : 0.0);
-    } else if (kind == kFallback) {
-      const double *fb = (s == 0) ? r.fbU : r.fbL;
-      if (K == 0) v = fb[0];
-      else if (ones == 1) v = fb[1 + one_axis];
+      store(out + o, v, rsum, l1sum);
     }
-    store(out + K, v, rsum, l1sum);
+  } else if (kind == kFallback) {
+    const double *fb = (s == 0) ? r.fbU : r.fbL;
+    if (threadIdx.x <= (unsigned)a.n) {
+      const int q = (int)threadIdx.x;  // 0: constant; 1 + axis: t_axis
+      int64_t o = 0;
+      if (q > 0) {
+        o = 1;
+        for (int t = 0; t < a.n - q; ++t) o *= Do1;  // position of t_(q-1)
+      }
+      store(out + o, fb[q], rsum, l1sum);
+    }
   }
-  if (a.part) block_partials(a, it, rsum, l1sum);
+  if (a.part) {
+    block_partials_slot(a, it, 0, rsum, l1sum);
+    for (int64_t b = 1 + threadIdx.x; b < a.nbx; b += blockDim.x) {
+      a.part[(it * a.nbx + b) * 2 + 0] = 0.0;
+      a.part[(it * a.nbx + b) * 2 + 1] = 0.0;
+    }
+  }
 }
 
 // ------------------------------------------------ generic Horner step
@@ -317,14 +383,14 @@ __global__ void __launch_bounds__(kBlock) compose_simple_kernel(ComposeArgs a) {
 template <typename T>
 __global__ void __launch_bounds__(kBlock) compose_horner_kernel(ComposeArgs a, int m, int sq_D) {
   const int j = blockIdx.y / a.nbounds, s = blockIdx.y % a.nbounds;
-  const int64_t box = blockIdx.z;
+  const int64_t g = blockIdx.z, box = wave_box(a, g);
   const NeuronRec &r = a.recs[box * a.h + j];
   const int L = r.kind;
   if (L < 2 || (L == 2 && sq_D == a.Din) || m > L - 1) return;
   const NuSource ns = nu_of(a, &r, s);
   const bool last = (m == L - 1);
-  const int64_t it = item_of(a, box, j, s);
-  const T *p = reinterpret_cast<const T *>(a.pre) + it * a.Cin;
+  const int64_t it = item_of(a, g, j, s);
+  const T *p = in_tensor<T>(a, box, j, s);
   const int Din = a.Din, Di1 = Din + 1;
   const int dq = m * Din;            // degree of Q^(m-1)
   const int dout_m = (m + 1) * Din;  // degree of Q^(m)
@@ -332,7 +398,7 @@ __global__ void __launch_bounds__(kBlock) compose_horner_kernel(ComposeArgs a, i
   const int64_t Ct = last ? a.Cout : ipow(dout_m + 1, a.n);
   double *scr = reinterpret_cast<double *>(a.scratch);
   double *dsts = scr + (it * 2 + (m & 1)) * a.Cq;
-  T *dstp = reinterpret_cast<T *>(a.post) + it * a.Cout;
+  T *dstp = out_tensor<T>(a, box, j, s);
   const double *qsrc = scr + (it * 2 + ((m - 1) & 1)) * a.Cq;
   const double cL = r.c[L], cL1 = r.c[L - 1], cadd = r.c[L - 1 - m];
   const int Dq1 = dq + 1;
@@ -406,7 +472,7 @@ __global__ void __launch_bounds__(kBlock) compose_horner_kernel(ComposeArgs a, i
 __global__ void post_radii_kernel(ComposeArgs a, NeuronRec *recs) {
   const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (item >= a.nboxes * a.h) return;
-  NeuronRec &r = recs[item];
+  NeuronRec &r = recs[wave_box(a, item / a.h) * a.h + item % a.h];
   const int kind = r.kind;
   for (int s = 0; s < 2; ++s) {
     const int64_t it = item * 2 + s;
@@ -499,7 +565,8 @@ static size_t sq_lds(int n, int D) {
   if (D < 1 || D > 8) return 0;
   const int NI = sq_ni(n, D);
   const int64_t R = ipow(D + 1, NI), RP = (R + 1) & ~1;
-  return (size_t)(ipow(D + 1, n) / R) * RP * sizeof(double);
+  const int64_t nrows = ipow(D + 1, n) / R;
+  return (size_t)nrows * RP * sizeof(double) + (size_t)((nrows + 15) & ~15);
 }
 
 static bool sq_handles(int n, int Din, int Dout) {
@@ -553,9 +620,18 @@ template <typename T>
 static hipError_t compose_all(const ComposeArgs &a, hipStream_t s) {
   const unsigned gx = (unsigned)a.nbx;
   {
-    dim3 grid(gx, (unsigned)(a.h * a.nbounds), (unsigned)a.nboxes);
+    const int64_t bytes = (int64_t)a.h * a.nbounds * a.Cout * (int64_t)sizeof(T);
+    const int64_t per_box_blocks = std::max<int64_t>(1, std::min<int64_t>((bytes / 16 + 4 * kBlock - 1) / (4 * kBlock),
+                                                                          std::max<int64_t>(1, 8192 / a.nboxes)));
+    dim3 grid((unsigned)per_box_blocks, (unsigned)a.nboxes);
+    ProfScope ps(kProfComposeFill, s, (double)bytes * a.nboxes);
+    hipLaunchKernelGGL(compose_fill_kernel, grid, dim3(kBlock), 0, s, a, bytes, (int)sizeof(T));
+    RET_IF(hipGetLastError());
+  }
+  {
+    dim3 grid(1, (unsigned)(a.h * a.nbounds), (unsigned)a.nboxes);
     ProfScope ps(kProfComposeSimple, s, 0.0);
-    hipLaunchKernelGGL(compose_simple_kernel<T>, grid, dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(compose_scatter_kernel<T>, grid, dim3(kBlock), 0, s, a);
     RET_IF(hipGetLastError());
   }
   hipError_t err = hipSuccess;
@@ -584,7 +660,7 @@ hipError_t launch_compose(const ComposeArgs &a, hipStream_t s) {
 }
 
 size_t compose_scratch_bytes(int n, int Din, int Lmax, int h, int64_t nboxes, int) {
-  if (Lmax < 2) return 0;
+  if (Lmax < 3) return 0;  // order 2 without a square kernel is one (final) Horner step
   const int64_t Cq = ipow(Din * (Lmax - 1) + 1, n);
   return align256((size_t)nboxes * h * 2 * 2 * Cq * sizeof(double));
 }
@@ -602,6 +678,9 @@ hipError_t launch_poly_mul(int n, int da, int db, int64_t count, const void *A, 
     a.Lmax = 2;
     a.Cin = ipow(da + 1, n);
     a.Cout = Cc;
+    a.slot_in = a.Cin;
+    a.slot_out = Cc;
+    a.bids = nullptr;
     a.nboxes = count;
     a.pre = A;
     a.post = out;

@@ -21,19 +21,12 @@
 // the power series in u = (y-lo)/(hi-lo) by forward differences,
 // c_j = C(L,j) Delta^j b_0, and its value e at y = 0 (Prop. 2).
 #include "common.hpp"
+#include "rules.hpp"
 
 namespace bern {
 
 constexpr int kSmallLds = 16384;  // FP64 elements of a tensor converted in one block (128 KiB)
 constexpr int kTileLds = 8192;    // FP64 elements per staged tile of the two-pass path
-
-__device__ inline double binom_d(int n, int k) {
-  if (k < 0 || k > n) return 0.0;
-  if (k > n - k) k = n - k;
-  double r = 1.0;
-  for (int i = 1; i <= k; ++i) r = r * (double)(n - k + i) / (double)i;
-  return rint(r);
-}
 
 // Block-wide reductions over wave64 shuffles + LDS.
 template <typename Op>
@@ -57,31 +50,6 @@ __device__ double block_reduce(double v, Op op, double *red) {
 struct OpMin { __device__ double operator()(double a, double b) const { return fmin(a, b); } };
 struct OpMax { __device__ double operator()(double a, double b) const { return fmax(a, b); } };
 struct OpAdd { __device__ double operator()(double a, double b) const { return a + b; } };
-
-// ReLU over-approximant on [lo, hi] (lo < 0 < hi) of order L: power
-// coefficients c[0..L] in u and e = value at y = 0.
-__device__ void relu_poly_dev(double lo, double hi, int L, double *c, double *e) {
-  double d[kMaxOrder + 1];
-#pragma unroll
-  for (int k = 0; k <= kMaxOrder; ++k) {
-    const double y = lo + (hi - lo) * (double)k / (double)L;
-    d[k] = (k <= L) ? fmax(y, 0.0) : 0.0;
-  }
-#pragma unroll
-  for (int j = 1; j <= kMaxOrder; ++j) {
-#pragma unroll
-    for (int k = kMaxOrder; k >= j; --k)
-      if (j <= L && k <= L) d[k] -= d[k - 1];
-  }
-#pragma unroll
-  for (int j = 0; j <= kMaxOrder; ++j) c[j] = (j <= L) ? binom_d(L, j) * d[j] : 0.0;
-  const double u0 = -lo / (hi - lo);
-  double v = 0.0;
-#pragma unroll
-  for (int j = kMaxOrder; j >= 0; --j)
-    if (j <= L) v = fma(v, u0, c[j]);
-  *e = v;
-}
 
 // In-place per-axis basis change of a tensor held in LDS (`t`, C doubles),
 // axes [ax0, n). Table tab[k*(D+1)+j] = C(k,j)/C(D,j).
@@ -116,10 +84,11 @@ __device__ void fill_table(double *tab, int D) {
 }
 
 // Least-squares affine fit of the Bernstein control net {(K/D, b_K)} and the
-// extreme remainder (linear fallback rule). Outputs beta[0] = mean,
+// range of its remainders (linear fallback rule). Outputs beta[0] = mean,
 // beta[1+a] = slope along axis a for l(t) = beta0 + sum beta_a (t_a - 1/2),
-// and *ext = max (upper, sign > 0) or min (lower) of b_K - l(K/D).
-__device__ void lds_affine_fit(const double *t, int64_t C, int n, int D, int sign, double *beta, double *ext,
+// and the largest and smallest b_K - l(K/D). On the tensor grid the centred
+// coordinates are orthogonal, so the normal equations are diagonal.
+__device__ void lds_affine_fit(const double *t, int64_t C, int n, int D, double *beta, double *rmax, double *rmin,
                                double *red) {
   const int D1 = D + 1;
   double m = 0.0;
@@ -127,7 +96,10 @@ __device__ void lds_affine_fit(const double *t, int64_t C, int n, int D, int sig
   beta[0] = block_reduce(m, OpAdd(), red) / (double)C;
   // sum over one axis of (k/D - 1/2)^2, times the other axes' sizes
   double s1 = 0.0;
-  for (int k = 0; k <= D; ++k) { const double s = (double)k / D - 0.5; s1 += s * s; }
+  for (int k = 0; k <= D; ++k) {
+    const double s = (double)k / D - 0.5;
+    s1 += s * s;
+  }
   const double ss = s1 * (double)(C / D1);
   int64_t stride = C / D1;  // stride of axis 0
   for (int a = 0; a < n; ++a) {
@@ -139,7 +111,7 @@ __device__ void lds_affine_fit(const double *t, int64_t C, int n, int D, int sig
     beta[1 + a] = block_reduce(p, OpAdd(), red) / ss;
     stride /= D1;
   }
-  double e = sign > 0 ? -INFINITY : INFINITY;
+  double hi = -INFINITY, lo = INFINITY;
   for (int64_t i = threadIdx.x; i < C; i += blockDim.x) {
     double l = beta[0];
     int64_t rem = i;
@@ -149,9 +121,11 @@ __device__ void lds_affine_fit(const double *t, int64_t C, int n, int D, int sig
       l += beta[1 + a] * ((double)k / D - 0.5);
     }
     const double r = t[i] - l;
-    e = sign > 0 ? fmax(e, r) : fmin(e, r);
+    hi = fmax(hi, r);
+    lo = fmin(lo, r);
   }
-  *ext = sign > 0 ? block_reduce(e, OpMax(), red) : block_reduce(e, OpMin(), red);
+  *rmax = block_reduce(hi, OpMax(), red);
+  *rmin = block_reduce(lo, OpMin(), red);
 }
 
 // FP32 mode: radii epsU, epsL of the stored pre-activation polynomials of
@@ -165,7 +139,7 @@ __device__ void pre_radii(const ConvertArgs &a, int64_t box, int j, const void *
   if (a.layer == 0) {
     const double *lo = a.box_lo + box * a.n, *hi = a.box_hi + box * a.n;
     const double *w = a.W + (int64_t)j * a.n;
-    const float *p = reinterpret_cast<const float *>(pre) + (box * a.h + j) * 2 * a.C;
+    const float *p = reinterpret_cast<const float *>(pre) + box * a.slot + (int64_t)j * 2 * a.C;
     double a0 = a.b[j], sabs = fabs(a.b[j]);
     for (int k = 0; k < a.n; ++k) {
       a0 = fma(w[k], lo[k], a0);
@@ -193,7 +167,7 @@ __device__ void pre_radii(const ConvertArgs &a, int64_t box, int j, const void *
     g += fabs(wk) * (P.pl1U + P.pl1L);
   }
   double rU = 0.0, rL = 0.0;
-  const double *rp = a.rpart + (box * a.h + j) * 2 * a.cblocks;
+  const double *rp = a.rpart + box * a.rpart_slot + (int64_t)j * 2 * a.cblocks;
   for (int64_t cb = 0; cb < a.cblocks; ++cb) {
     rU += rp[cb];
     rL += rp[a.cblocks + cb];
@@ -218,10 +192,11 @@ __device__ void padded_bounds(const ConvertArgs &a, int64_t box, int j, double m
   hi = round_up(mx + g * l1U + epsU);
 }
 
-// Choose the rule of one hidden neuron and fill its record (thread 0 only).
+// Record of one hidden neuron after its read-off (thread 0 only), then its
+// rule unless a predictor chooses it later.
 __device__ void finish_neuron(const ConvertArgs &a, int64_t box, int j, double lo, double hi, double epsU,
-                              double epsL, double l1U, double l1L, const double *fitU, double extU, const double *fitL,
-                              double extL) {
+                              double epsL, double l1U, double l1L, const double (*fit)[kMaxInputs + 1],
+                              const double *ext, bool fitted) {
   NeuronRec &r = a.recs[box * a.h + j];
   r.lo = lo;
   r.hi = hi;
@@ -229,60 +204,19 @@ __device__ void finish_neuron(const ConvertArgs &a, int64_t box, int j, double l
   r.epsL = epsL;
   r.l1U = l1U;
   r.l1L = l1L;
-  r.padU = r.padL = r.pl1U = r.pl1L = 0.0;
-  r.fbpadU = r.fbpadL = 0.0;
-  r.dB = 0.0;
-  int code = a.L;
-  if (a.plan) code = a.plan[box * a.plan_ld + a.plan_col0 + j];
-  int kind, deg;
-  if (!(hi > 0.0)) { kind = kInactive; deg = 0; }     // hi <= 0 (also NaN) -> zero polynomial
-  else if (lo >= 0.0) { kind = kActive; deg = a.D; }
-  else if (code >= 1) { kind = code; deg = code * a.D; }
-  else { kind = kFallback; deg = 1; }
-  if (!a.plan) deg = a.L * a.D;  // plain rule: uniform degree per layer
-  r.kind = kind;
-  r.deg = deg;
-#pragma unroll
-  for (int k = 0; k <= kMaxOrder; ++k) r.c[k] = 0.0;
-  r.e = 0.0;
-  const double mag = fabs(lo) + fabs(hi);
-  if (kind >= 1) {
-    relu_poly_dev(lo, hi, kind, r.c, &r.e);
-    if (!a.fp64) {
-      double sc = 0.0;
-      for (int k = 0; k <= kind; ++k) sc += fabs(r.c[k]);
-      double p3 = 1.0;
-      for (int k = 0; k < kind; ++k) p3 *= 3.0;
-      r.dB = mag * (gamma64(4) + gamma64(kind + 2) * p3);
-      r.e = round_up(r.e + r.dB + gamma64(2.0 * kind + 2) * sc + (hi - lo) * gamma64(3));
-    }
+  r.fitted = fitted ? 1 : 0;
+  for (int q = 0; q <= kMaxInputs; ++q) {
+    r.fitU[q] = fitted ? fit[0][q] : 0.0;
+    r.fitL[q] = fitted ? fit[1][q] : 0.0;
   }
-  if (kind == kFallback) {
-    // degree-1 approximant: upper lambda (U^ - lo), lower lambda L^ (with the
-    // radii folded in), each replaced by its least-squares affine fit plus
-    // the extreme remainder.
-    const double lam = hi / (hi - lo);
-    double sU = 0.0, sL = 0.0, aU = fabs(fitU[0]), aL = fabs(fitL[0]);
-    for (int ax = 0; ax < a.n; ++ax) {
-      sU += fitU[1 + ax];
-      sL += fitL[1 + ax];
-      aU += fabs(fitU[1 + ax]);
-      aL += fabs(fitL[1 + ax]);
-    }
-    r.fbU[0] = lam * (fitU[0] - lo - 0.5 * sU + extU + epsU);
-    r.fbL[0] = lam * (fitL[0] - 0.5 * sL + extL - epsL);
-    for (int ax = 0; ax < a.n; ++ax) {
-      r.fbU[1 + ax] = lam * fitU[1 + ax];
-      r.fbL[1 + ax] = lam * fitL[1 + ax];
-    }
-    if (!a.fp64) {
-      const double g = gamma64((double)a.n * (a.D + 2) + 4);
-      const double ge = gamma64(a.n + 8);
-      r.fbpadU = lam * (g * l1U + ge * (aU + fabs(extU) + fabs(lo) + epsU)) + gamma64(4) * lam * (mag + hi - lo);
-      r.fbpadL = lam * (g * l1L + ge * (aL + fabs(extL) + epsL)) + gamma64(4) * lam * (mag + hi - lo);
-    }
-  }
-  if (a.used) a.used[box * a.ld_out + a.col0 + j] = (int8_t)kind;
+  r.rmaxU = fitted ? ext[0] : 0.0;
+  r.rminU = fitted ? ext[1] : 0.0;
+  r.rmaxL = fitted ? ext[2] : 0.0;
+  r.rminL = fitted ? ext[3] : 0.0;
+  if (a.learned) return;
+  const int code = a.plan ? a.plan[box * a.plan_ld + a.plan_col0 + j] : a.L;
+  decide_neuron(r, code, a.plan == nullptr, a.L, a.n, a.D, a.cap, a.fp64);
+  if (a.used) a.used[box * a.ld_out + a.col0 + j] = (int8_t)r.kind;
 }
 
 // One block per (box, neuron): both bounds of the neuron, all axes in LDS.
@@ -294,17 +228,18 @@ __global__ void __launch_bounds__(kBlock) convert_small_kernel(ConvertArgs a) {
   double *tab = lds + a.C;
   double *red = tab + D1 * D1;
   __shared__ double fit[2][kMaxInputs + 1];
-  __shared__ double ext[2];
-  const int64_t item = blockIdx.x;  // box * h + j
-  const int64_t box = item / a.h;
+  __shared__ double ext[4];  // rmaxU, rminU, rmaxL, rminL
+  const int64_t item = blockIdx.x;  // launch box * h + j
+  const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
   const int j = (int)(item % a.h);
   fill_table(tab, a.D);
-  const bool want_fit = a.mode == 0 && a.plan && a.D > 0 && a.plan[box * a.plan_ld + a.plan_col0 + j] == 0;
+  const bool want_fit = a.mode == 0 && a.D > 0 &&
+                        (a.learned || a.fits || (a.plan && a.plan[box * a.plan_ld + a.plan_col0 + j] <= 0));
   if (threadIdx.x < 2 * (kMaxInputs + 1)) fit[threadIdx.x / (kMaxInputs + 1)][threadIdx.x % (kMaxInputs + 1)] = 0.0;
-  if (threadIdx.x < 2) ext[threadIdx.x] = 0.0;
+  if (threadIdx.x < 4) ext[threadIdx.x] = 0.0;
   double ext_lo = 0.0, ext_hi = 0.0, l1s[2] = {0.0, 0.0};
   for (int s = 1; s >= 0; --s) {  // lower first, then upper
-    const T *p = reinterpret_cast<const T *>(a.pre) + (item * 2 + s) * a.C;
+    const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + ((int64_t)j * 2 + s) * a.C;
     double l1 = 0.0;
     for (int64_t i = threadIdx.x; i < a.C; i += blockDim.x) {
       t[i] = (double)p[i];
@@ -318,11 +253,12 @@ __global__ void __launch_bounds__(kBlock) convert_small_kernel(ConvertArgs a) {
     if (s) ext_lo = v; else ext_hi = v;
     if (want_fit) {
       double beta[kMaxInputs + 1];
-      double e;
-      lds_affine_fit(t, a.C, a.n, a.D, s ? -1 : 1, beta, &e, red);
+      double rmax, rmin;
+      lds_affine_fit(t, a.C, a.n, a.D, beta, &rmax, &rmin, red);
       if (threadIdx.x == 0) {
         for (int ax = 0; ax <= a.n; ++ax) fit[s][ax] = beta[ax];
-        ext[s] = e;
+        ext[2 * s] = rmax;
+        ext[2 * s + 1] = rmin;
       }
     }
     __syncthreads();
@@ -336,8 +272,7 @@ __global__ void __launch_bounds__(kBlock) convert_small_kernel(ConvertArgs a) {
     } else {
       if (a.out_lo) a.out_lo[box * a.ld_out + a.col0 + j] = lo;
       if (a.out_hi) a.out_hi[box * a.ld_out + a.col0 + j] = hi;
-      finish_neuron(a, box, j, lo, hi, epsU, epsL, l1s[0], l1s[1], fit[0], want_fit ? ext[0] : 0.0, fit[1],
-                    want_fit ? ext[1] : 0.0);
+      finish_neuron(a, box, j, lo, hi, epsU, epsL, l1s[0], l1s[1], fit, ext, want_fit);
     }
   }
 }
@@ -385,7 +320,9 @@ __global__ void __launch_bounds__(kBlock) convert_passA_kernel(ConvertArgs a, Sp
   const int64_t o = blockIdx.x;
   fill_table(tab, a.D);
   double *red = tab + D1 * D1;
-  const T *p = reinterpret_cast<const T *>(a.pre) + tensor * a.C + o * sp.Ci;
+  const int64_t gb = tensor / (2 * a.h), rest = tensor % (2 * a.h);
+  const int64_t box = a.bids ? a.bids[gb] : gb;
+  const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + rest * a.C + o * sp.Ci;
   double l1 = 0.0;
   for (int64_t i = threadIdx.x; i < sp.Ci; i += blockDim.x) {
     t[i] = (double)p[i];
@@ -447,7 +384,7 @@ __global__ void __launch_bounds__(64) convert_final_kernel(ConvertArgs a, Split 
                                                           const double *l1part) {
   const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (item >= a.nboxes * a.h) return;
-  const int64_t box = item / a.h;
+  const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
   const int j = (int)(item % a.h);
   double mn = INFINITY, mx = -INFINITY, l1U = 0.0, l1L = 0.0;
   for (int64_t c = 0; c < sp.nchunk; ++c) {
@@ -466,8 +403,7 @@ __global__ void __launch_bounds__(64) convert_final_kernel(ConvertArgs a, Split 
   } else {
     if (a.out_lo) a.out_lo[box * a.ld_out + a.col0 + j] = lo;
     if (a.out_hi) a.out_hi[box * a.ld_out + a.col0 + j] = hi;
-    const double zero[kMaxInputs + 1] = {0};
-    finish_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, zero, 0.0, zero, 0.0);
+    finish_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, nullptr, nullptr, false);
   }
 }
 

@@ -1,0 +1,324 @@
+// Degree predictor: a small MLP 8 -> 64 -> 64 -> 4 (ReLU hidden layers) that
+// proposes, for each unstable neuron, the order of its Bernstein ReLU
+// approximant (classes 1, 2, 3) or the linear fallback (class 0). Any class
+// yields sound bounds (Props. 1-2 hold for every order; the fallback is
+// sound by Def. 2), so the predictor only trades tightness for work.
+//
+// Parameter vector (FP32), in this order:
+//   mean[8], std[8]            feature normalisation (not trained)
+//   W1[64][8], b1[64], W2[64][64], b2[64], W3[4][64], b3[4]
+//
+// Training kernels are FP32 and deterministic (fixed summation order): the
+// forward pass stores both hidden activations, the backward pass forms the
+// per-record deltas and then sums the weight gradients over the batch with one
+// thread per parameter. Inference inside the bounds pipeline runs in BF16
+// (weights and activations rounded to BF16, FP32 accumulation).
+#include "common.hpp"
+#include "rules.hpp"
+
+namespace bern {
+
+constexpr int kF = 8, kH = 64, kC = 4;
+constexpr int kOffMean = 0, kOffStd = 8, kOffW1 = 16, kOffB1 = kOffW1 + kH * kF, kOffW2 = kOffB1 + kH,
+              kOffB2 = kOffW2 + kH * kH, kOffW3 = kOffB2 + kH, kOffB3 = kOffW3 + kC * kH, kParams = kOffB3 + kC;
+static_assert(kParams == 5012, "parameter layout");
+
+__device__ inline float bf16_round(float x) {
+  // round to nearest even on the upper 16 bits (finite inputs)
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xffff0000u);
+}
+
+// Forward pass, one thread per record. hid (optional): [N][128] = h1 | h2.
+__global__ void __launch_bounds__(256) mlp_forward_kernel(const float *P, int64_t N, const float *X, float *logits,
+                                                          float *hid, int bf16) {
+  __shared__ float w[kParams];
+  for (int i = threadIdx.x; i < kParams; i += blockDim.x) w[i] = bf16 && i >= kOffW1 ? bf16_round(P[i]) : P[i];
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  float x[kF], h1[kH];
+  for (int f = 0; f < kF; ++f) {
+    float v = (X[r * kF + f] - w[kOffMean + f]) / w[kOffStd + f];
+    x[f] = bf16 ? bf16_round(v) : v;
+  }
+  for (int o = 0; o < kH; ++o) {
+    float s = w[kOffB1 + o];
+    for (int f = 0; f < kF; ++f) s = fmaf(w[kOffW1 + o * kF + f], x[f], s);
+    s = fmaxf(s, 0.f);
+    h1[o] = bf16 ? bf16_round(s) : s;
+    if (hid) hid[r * 2 * kH + o] = h1[o];
+  }
+  float z[kC];
+  for (int c = 0; c < kC; ++c) z[c] = w[kOffB3 + c];
+  for (int o = 0; o < kH; ++o) {
+    float s = w[kOffB2 + o];
+    for (int i = 0; i < kH; ++i) s = fmaf(w[kOffW2 + o * kH + i], h1[i], s);
+    s = fmaxf(s, 0.f);
+    if (bf16) s = bf16_round(s);
+    if (hid) hid[r * 2 * kH + kH + o] = s;
+    for (int c = 0; c < kC; ++c) z[c] = fmaf(w[kOffW3 + c * kH + o], s, z[c]);
+  }
+  for (int c = 0; c < kC; ++c) logits[r * kC + c] = z[c];
+}
+
+// Per-record deltas of the mean softmax cross-entropy:
+// dZ = (softmax(z) - onehot(y)) / N, dH2 = (W3^T dZ) * [h2 > 0],
+// dH1 = (W2^T dH2) * [h1 > 0]. Also the per-record loss terms.
+__global__ void __launch_bounds__(256) mlp_delta_kernel(const float *P, int64_t N, const float *logits,
+                                                        const int8_t *y, const float *hid, float *dz, float *dh,
+                                                        float *lossr) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  float z[kC], m = -INFINITY;
+  for (int c = 0; c < kC; ++c) {
+    z[c] = logits[r * kC + c];
+    m = fmaxf(m, z[c]);
+  }
+  float se = 0.f;
+  for (int c = 0; c < kC; ++c) se += expf(z[c] - m);
+  const int lab = y[r];
+  lossr[r] = (logf(se) + m - z[lab]) / (float)N;
+  float d[kC];
+  for (int c = 0; c < kC; ++c) {
+    d[c] = (expf(z[c] - m) / se - (c == lab ? 1.f : 0.f)) / (float)N;
+    dz[r * kC + c] = d[c];
+  }
+  const float *h1 = hid + r * 2 * kH, *h2 = h1 + kH;
+  float d2[kH];
+  for (int o = 0; o < kH; ++o) {
+    float s = 0.f;
+    for (int c = 0; c < kC; ++c) s = fmaf(P[kOffW3 + c * kH + o], d[c], s);
+    d2[o] = h2[o] > 0.f ? s : 0.f;
+    dh[r * 2 * kH + kH + o] = d2[o];
+  }
+  for (int i = 0; i < kH; ++i) {
+    float s = 0.f;
+    for (int o = 0; o < kH; ++o) s = fmaf(P[kOffW2 + o * kH + i], d2[o], s);
+    dh[r * 2 * kH + i] = h1[i] > 0.f ? s : 0.f;
+  }
+}
+
+// Weight gradients: one thread per trainable parameter, sum over the batch
+// in record order. Also the total loss (thread of parameter 0).
+__global__ void __launch_bounds__(256) mlp_grad_kernel(const float *P, int64_t N, const float *X, const float *hid,
+                                                       const float *dz, const float *dh, const float *lossr,
+                                                       float *G, float *loss) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kParams) return;
+  double s = 0.0;
+  if (p < kOffW1) {
+    s = 0.0;  // normalisation is fixed
+  } else if (p < kOffB1) {
+    const int o = (p - kOffW1) / kF, f = (p - kOffW1) % kF;
+    const float mu = P[kOffMean + f], sd = P[kOffStd + f];
+    for (int64_t r = 0; r < N; ++r) s += (double)dh[r * 2 * kH + o] * (double)((X[r * kF + f] - mu) / sd);
+  } else if (p < kOffW2) {
+    const int o = p - kOffB1;
+    for (int64_t r = 0; r < N; ++r) s += dh[r * 2 * kH + o];
+  } else if (p < kOffB2) {
+    const int o = (p - kOffW2) / kH, i = (p - kOffW2) % kH;
+    for (int64_t r = 0; r < N; ++r) s += (double)dh[r * 2 * kH + kH + o] * hid[r * 2 * kH + i];
+  } else if (p < kOffW3) {
+    const int o = p - kOffB2;
+    for (int64_t r = 0; r < N; ++r) s += dh[r * 2 * kH + kH + o];
+  } else if (p < kOffB3) {
+    const int c = (p - kOffW3) / kH, o = (p - kOffW3) % kH;
+    for (int64_t r = 0; r < N; ++r) s += (double)dz[r * kC + c] * hid[r * 2 * kH + kH + o];
+  } else {
+    const int c = p - kOffB3;
+    for (int64_t r = 0; r < N; ++r) s += dz[r * kC + c];
+  }
+  G[p] = (float)s;
+  if (p == 0 && loss) {
+    double l = 0.0;
+    for (int64_t r = 0; r < N; ++r) l += lossr[r];
+    *loss = (float)l;
+  }
+}
+
+// Adam step on the trainable parameters (normalisation entries untouched).
+__global__ void mlp_adam_kernel(float *P, const float *G, float *m, float *v, int64_t step, float lr, float b1,
+                                float b2, float eps) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < kOffW1 || p >= kParams) return;
+  const float g = G[p];
+  m[p] = b1 * m[p] + (1.f - b1) * g;
+  v[p] = b2 * v[p] + (1.f - b2) * g * g;
+  const float mh = m[p] / (1.f - powf(b1, (float)step));
+  const float vh = v[p] / (1.f - powf(b2, (float)step));
+  P[p] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+__global__ void argmax_kernel(int64_t N, const float *logits, int8_t *cls) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  int best = 0;
+  for (int c = 1; c < kC; ++c)
+    if (logits[r * kC + c] > logits[r * kC + best]) best = c;
+  cls[r] = (int8_t)best;
+}
+
+// ------------------------------------------------ predictor in the pipeline
+// Eight features of one hidden neuron from its record (interval, affine fits
+// of the Bernstein control nets) and its downstream sensitivity s_j:
+//   f0 = -lo/w (where zero sits in [lo, hi]), f1 = log w, f2 = layer/(H-1),
+//   f3 = log(D+1), f4 = mean gap of the Bernstein coefficients of U^ and L^
+//   over w, f5 = log(s_j w), f6 = spread of the fit remainders over w,
+//   f7 = slope mass of the upper fit over w;  w = hi - lo.
+__device__ void neuron_features(const LearnArgs &a, const NeuronRec &r, int j, float *f) {
+  double w = r.hi - r.lo;
+  if (!(w > 1e-300)) w = 1e-300;
+  double slope = 0.0;
+  for (int ax = 0; ax < a.n; ++ax) slope += fabs(r.fitU[1 + ax]);
+  f[0] = (float)(-r.lo / w);
+  f[1] = (float)log(w);
+  f[2] = a.H > 1 ? (float)a.layer / (float)(a.H - 1) : 0.f;
+  f[3] = (float)log((double)a.D + 1.0);
+  f[4] = r.fitted ? (float)((r.fitU[0] - r.fitL[0]) / w) : 0.f;
+  f[5] = (float)log(fmax(a.sens[j] * w, 1e-30));
+  f[6] = r.fitted ? (float)(((r.rmaxU - r.rminU) + (r.rmaxL - r.rminL)) / w) : 0.f;
+  f[7] = r.fitted ? (float)(slope / w) : 0.f;
+  for (int q = 0; q < kF; ++q)
+    if (!isfinite(f[q])) f[q] = 0.f;
+}
+
+__global__ void __launch_bounds__(256) features_kernel(LearnArgs a) {
+  const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= a.nboxes * a.h) return;
+  const int64_t box = a.bids ? a.bids[it / a.h] : it / a.h;
+  const int j = (int)(it % a.h);
+  float f[kF];
+  neuron_features(a, a.recs[box * a.h + j], j, f);
+  for (int q = 0; q < kF; ++q) a.feat[(box * a.nh + a.noff + j) * kF + q] = f[q];
+}
+
+// Features -> BF16 MLP -> class, one thread per (box, neuron). Stable neurons
+// get class -1 (their rule does not depend on the predictor).
+__global__ void __launch_bounds__(256) learned_classes_kernel(LearnArgs a) {
+  __shared__ float w[kParams];
+  for (int i = threadIdx.x; i < kParams; i += blockDim.x)
+    w[i] = i >= kOffW1 ? bf16_round(a.params[i]) : a.params[i];
+  __syncthreads();
+  const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= a.nboxes * a.h) return;
+  const int64_t box = a.bids ? a.bids[it / a.h] : it / a.h;
+  const int j = (int)(it % a.h);
+  const NeuronRec &r = a.recs[box * a.h + j];
+  float f[kF], x[kF], h1[kH], z[kC];
+  neuron_features(a, r, j, f);
+  if (a.feat)
+    for (int q = 0; q < kF; ++q) a.feat[(box * a.nh + a.noff + j) * kF + q] = f[q];
+  if (!(r.lo < 0.0 && r.hi > 0.0)) {
+    a.codes[box * a.nh + a.noff + j] = -1;
+    return;
+  }
+  for (int q = 0; q < kF; ++q) x[q] = bf16_round((f[q] - w[kOffMean + q]) / w[kOffStd + q]);
+  for (int o = 0; o < kH; ++o) {
+    float s = w[kOffB1 + o];
+    for (int q = 0; q < kF; ++q) s = fmaf(w[kOffW1 + o * kF + q], x[q], s);
+    h1[o] = bf16_round(fmaxf(s, 0.f));
+  }
+  for (int c = 0; c < kC; ++c) z[c] = w[kOffB3 + c];
+  for (int o = 0; o < kH; ++o) {
+    float s = w[kOffB2 + o];
+    for (int i = 0; i < kH; ++i) s = fmaf(w[kOffW2 + o * kH + i], h1[i], s);
+    s = bf16_round(fmaxf(s, 0.f));
+    for (int c = 0; c < kC; ++c) z[c] = fmaf(w[kOffW3 + c * kH + o], s, z[c]);
+  }
+  int best = 0;
+  for (int c = 1; c < kC; ++c)
+    if (z[c] > z[best]) best = c;
+  a.codes[box * a.nh + a.noff + j] = (int8_t)best;
+}
+
+// Per box and layer: the layer is stored at the largest degree any of its
+// neurons takes, so classes below that degree only cost tightness. Raise
+// them at no cost in tensor size: if some unstable neuron takes order >= 2,
+// the others take at least order 2; otherwise, if some takes order 1, the
+// fallback neurons take order 1. Then apply the rules (one thread per box).
+__global__ void learned_rules_kernel(LearnArgs a) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= a.nboxes) return;
+  const int64_t box = a.bids ? a.bids[g] : g;
+  int8_t *cl = a.codes + box * a.nh + a.noff;
+  int top = -1;
+  for (int j = 0; j < a.h; ++j) {
+    int c = cl[j];
+    if (c < 0) continue;
+    // class as the degree it gives: fallback (0) lowest
+    top = max(top, c);
+  }
+  for (int j = 0; j < a.h; ++j) {
+    NeuronRec &r = a.recs[box * a.h + j];
+    int c = cl[j];
+    if (c >= 0) {
+      if (top >= 2 && c < 2) c = 2;
+      else if (top == 1 && c == 0) c = 1;
+      cl[j] = (int8_t)c;
+    }
+    decide_neuron(r, c < 0 ? 1 : c, false, a.L, a.n, a.D, a.cap, a.fp64);
+    if (a.used) a.used[box * a.nh + a.noff + j] = (int8_t)r.kind;
+  }
+}
+
+hipError_t launch_learned_rules(const LearnArgs &a, hipStream_t s) {
+  {
+    ProfScope ps(kProfPredictor, s, 0.0);
+    hipLaunchKernelGGL(learned_classes_kernel, dim3((unsigned)((a.nboxes * a.h + 255) / 256)), dim3(256), 0, s, a);
+    RET_IF(hipGetLastError());
+  }
+  ProfScope ps(kProfPredictor, s, 0.0);
+  hipLaunchKernelGGL(learned_rules_kernel, dim3((unsigned)((a.nboxes + 63) / 64)), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_features(const LearnArgs &a, hipStream_t s) {
+  ProfScope ps(kProfMisc, s, 0.0);
+  hipLaunchKernelGGL(features_kernel, dim3((unsigned)((a.nboxes * a.h + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+int mlp_params() { return kParams; }
+
+hipError_t launch_mlp_forward(const float *P, int64_t N, const float *X, float *logits, float *hid, int bf16,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, P, N, X, logits, hid,
+                     bf16);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_backward(const float *P, int64_t N, const float *X, const int8_t *y, float *G, float *loss,
+                               float *scratch, hipStream_t s) {
+  float *logits = scratch;                 // [N][4]
+  float *hid = logits + N * kC;            // [N][128]
+  float *dz = hid + N * 2 * kH;            // [N][4]
+  float *dh = dz + N * kC;                 // [N][128]
+  float *lossr = dh + N * 2 * kH;          // [N]
+  RET_IF(launch_mlp_forward(P, N, X, logits, hid, 0, s));
+  hipLaunchKernelGGL(mlp_delta_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, P, N, logits, y, hid, dz,
+                     dh, lossr);
+  RET_IF(hipGetLastError());
+  hipLaunchKernelGGL(mlp_grad_kernel, dim3((kParams + 255) / 256), dim3(256), 0, s, P, N, X, hid, dz, dh, lossr, G,
+                     loss);
+  return hipGetLastError();
+}
+
+size_t mlp_backward_scratch(int64_t N) { return (size_t)N * (2 * kC + 4 * kH + 1) * sizeof(float); }
+
+hipError_t launch_mlp_adam(float *P, const float *G, float *m, float *v, int64_t step, float lr, float b1, float b2,
+                           float eps, hipStream_t s) {
+  hipLaunchKernelGGL(mlp_adam_kernel, dim3((kParams + 255) / 256), dim3(256), 0, s, P, G, m, v, step, lr, b1, b2,
+                     eps);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_classify(const float *P, int64_t N, const float *X, float *logits, int8_t *cls, int bf16,
+                               hipStream_t s) {
+  RET_IF(launch_mlp_forward(P, N, X, logits, nullptr, bf16, s));
+  hipLaunchKernelGGL(argmax_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N, logits, cls);
+  return hipGetLastError();
+}
+
+}  // namespace bern

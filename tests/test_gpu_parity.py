@@ -246,3 +246,127 @@ def test_large_output_two_pass_fp32_and_fp64():
     _assert_parity(g64, o, 1e-9, case.n_hidden)
     g32 = _bounds_gpu(case, precision="fp32")
     _assert_fp32(g32, o, case.n_hidden)
+
+
+# ------------------------------------------------- per-neuron degree plans
+# Codes stay <= L so the library's clamp to the plain degrees never acts and
+# the oracle sees the same plan.
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_given_plans_match_oracle(precision, seed):
+    case = wl.random_net_case([3, 8, 7, 2], seed=60 + seed, n_boxes=6)
+    rng = np.random.default_rng(seed)
+    plan = rng.integers(0, 4, size=(case.n_boxes, case.n_hidden)).astype(np.int8)
+    g = _bounds_gpu(case, L=3, precision=precision, sched="batched", plan=plan)
+    o = _oracle(case, plan=plan)
+    assert np.array_equal(g["used_plan"], o["used_plan"])
+    if precision == "fp64":
+        _assert_parity(g, o, 1e-9, case.n_hidden)
+    else:
+        _assert_fp32(g, o, case.n_hidden)
+
+
+def test_given_plan_uneven_box_degrees_and_schedules_agree():
+    """Boxes of one wave end at different degrees (some all-degree-1 plans,
+    some degree-3); batched, smaller waves and per-box runs agree bitwise."""
+    case = wl.random_net_case([4, 9, 9, 3], seed=70, n_boxes=8)
+    plan = np.full((case.n_boxes, case.n_hidden), 3, dtype=np.int8)
+    plan[::2] = 1
+    plan[1::4] = 0
+    a = _bounds_gpu(case, L=3, precision="fp32", sched="batched", plan=plan)
+    b = _bounds_gpu(case, L=3, precision="fp32", sched="per_box", plan=plan)
+    c = _bounds_gpu(case, L=3, precision="fp32", sched="batched", plan=plan, max_wave=3)
+    for k in ("neuron_lo", "neuron_hi", "out_lo", "out_hi", "used_plan"):
+        assert np.array_equal(a[k], b[k]) and np.array_equal(a[k], c[k])
+    o = _oracle(case, plan=plan)
+    _assert_fp32(a, o, case.n_hidden)
+
+
+def test_cfg3_subset_fp32():
+    case = wl.cfg3().subset(np.arange(6))
+    g = _bounds_gpu(case, L=3, precision="fp32", sched="batched", plan=case.plan)
+    o = _oracle(case, plan=case.plan)
+    assert np.array_equal(g["used_plan"], o["used_plan"])
+    _assert_fp32(g, o, case.n_hidden)
+
+
+# ------------------------------------------------------------ predictor MLP
+
+def _mlp_params(rng):
+    from oracle import mlp_oracle as M
+    P = np.zeros(M.N_PARAMS)
+    P[slice(*M.OFF["mean"])] = rng.standard_normal(8) * 0.1
+    P[slice(*M.OFF["std"])] = 0.5 + rng.random(8)
+    for k, s in (("W1", 0.5), ("b1", 0.1), ("W2", 0.2), ("b2", 0.1), ("W3", 0.3), ("b3", 0.1)):
+        a, b = M.OFF[k]
+        P[a:b] = rng.standard_normal(b - a) * s
+    return P.astype(np.float32)
+
+
+def test_mlp_forward_backward_match_oracle():
+    """FP32 GPU training kernels against the FP64 oracle (same FP32 inputs)."""
+    from oracle import mlp_oracle as M
+    rng = np.random.default_rng(3)
+    P = _mlp_params(rng)
+    X = rng.standard_normal((3000, 8)).astype(np.float32)
+    y = rng.integers(0, 4, 3000).astype(np.int8)
+    Pd = torch.tensor(P, device=DEV)
+    Xd = torch.tensor(X, device=DEV)
+    z = B.mlp_forward(Pd, Xd).cpu().numpy()
+    zr, _ = M.forward(P.astype(np.float64), X.astype(np.float64))
+    assert np.max(np.abs(z - zr)) <= 1e-4 * max(1.0, np.abs(zr).max())
+    G, loss = B.mlp_backward(Pd, Xd, torch.tensor(y, device=DEV))
+    Gr = M.grad(P.astype(np.float64), X.astype(np.float64), y.astype(np.int64))
+    assert abs(loss.item() - M.loss(P.astype(np.float64), X.astype(np.float64), y.astype(np.int64))) <= 1e-5
+    G = G.cpu().numpy()
+    assert np.all(G[:16] == 0.0)
+    assert np.max(np.abs(G - Gr)) <= 1e-4 * np.abs(Gr).max()
+
+
+def test_mlp_adam_reduces_loss_and_bf16_agrees():
+    rng = np.random.default_rng(4)
+    P = _mlp_params(rng)
+    X = rng.standard_normal((4096, 8)).astype(np.float32)
+    y = (X[:, 0] > 0).astype(np.int8) + 2 * (X[:, 1] > 0).astype(np.int8)
+    Pd = torch.tensor(P, device=DEV)
+    m, v = torch.zeros_like(Pd), torch.zeros_like(Pd)
+    Xd, yd = torch.tensor(X, device=DEV), torch.tensor(y, device=DEV)
+    first = None
+    for step in range(1, 301):
+        G, loss = B.mlp_backward(Pd, Xd, yd)
+        if first is None:
+            first = loss.item()
+        B.mlp_adam(Pd, G, m, v, step, 1e-2)
+    assert loss.item() < 0.3 * first
+    c32, _ = B.mlp_classify(Pd, Xd, bf16=False)
+    c16, _ = B.mlp_classify(Pd, Xd, bf16=True)
+    assert (c32 == yd).float().mean().item() > 0.9
+    assert (c16 == c32).float().mean().item() > 0.97
+
+
+def test_learned_plan_is_sound_and_matches_oracle_on_its_plan():
+    """Any predictor (here random weights) gives sound bounds; the learned run
+    equals the oracle run with the plan the predictor chose."""
+    rng = np.random.default_rng(5)
+    P = _mlp_params(rng)
+    pred = B.Predictor(P)
+    case = wl.random_net_case([3, 8, 7, 2], seed=81, n_boxes=6)
+    net = B.Net(case.Ws, case.bs)
+    lo = torch.tensor(case.box_lo, dtype=torch.float64, device=DEV)
+    hi = torch.tensor(case.box_hi, dtype=torch.float64, device=DEV)
+    for precision in ("fp64", "fp32"):
+        r = B.bounds(net, lo, hi, L=3, precision=precision, sched="batched", plan="learned", pred=pred)
+        torch.cuda.synchronize()
+        g = {k: r[k].cpu().numpy() for k in ("neuron_lo", "neuron_hi", "out_lo", "out_hi", "used_plan")}
+        used = g["used_plan"]
+        # the rule per neuron as a plan the oracle understands (stable entries are ignored there)
+        plan = np.where(used >= 1, used, np.where(used == -2, 0, 1)).astype(np.int8)
+        o = _oracle(case, plan=plan)
+        assert np.array_equal(used, o["used_plan"])
+        if precision == "fp64":
+            _assert_parity(g, o, 1e-9, case.n_hidden)
+        else:
+            _assert_fp32(g, o, case.n_hidden)
+    net.close()
+    pred.close()
