@@ -24,30 +24,54 @@ METRIC = "bounded neurons/s on 1 GPU + output-bound width: plain vs batched+lear
 PEAK_HBM_GBS = 8000.0
 PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
+# form: "plain" = the paper's rule at order L; "learned" = the degree
+# predictor's plan (timed against the plain form on the same boxes).
 WORKLOADS = {
     "cfg1": dict(k=1, form="plain", sched="per_box", precision="fp64"),
     "cfg2": dict(k=2, form="plain", sched="per_box", precision="fp64"),
     "cfg2_fp32": dict(k=2, form="plain", sched="per_box", precision="fp32"),
+    "cfg3": dict(k=3, form="given", sched="batched", precision="fp32"),
     "cfg4": dict(k=4, form="plain", sched="batched", precision="fp32"),
+    "cfg5": dict(k=5, form="learned", sched="batched", precision="fp32", plain_sched="per_box"),
+    "cfg5_batched_plain": dict(k=5, form="plain", sched="batched", precision="fp32"),
 }
 
 
-def composed_flops(case, used, L):
+def box_degrees(case, used, L, plain):
+    """Pre-activation degree of every (box, layer) reconstructed from the rule
+    each neuron took: inactive 0, active D, order k -> k D, fallback 1; a
+    layer's post degree is the largest of its neurons' (plain rule: L D)."""
+    nb = used.shape[0]
+    D = np.ones(nb, dtype=np.int64)
+    out = []
+    col = 0
+    for i in range(1, len(case.widths) - 1):
+        h = case.widths[i]
+        out.append(D.copy())
+        if plain:
+            D = D * L
+        else:
+            k = used[:, col:col + h].astype(np.int64)
+            deg = np.where(k >= 1, k * D[:, None], np.where(k == -1, D[:, None], np.where(k == -2, 1, 0)))
+            D = deg.max(axis=1)
+        col += h
+    out.append(D.copy())
+    return out  # per layer (hidden layers then output): [boxes]
+
+
+def composed_flops(case, used, L, plain=True):
     """Algorithmic FLOPs of the order-2 compositions: for every neuron-bound
     that is composed (unstable neuron, kind == 2), one symmetric square of its
     (D+1)^n-coefficient pre-activation tensor = (C^2 + C)/2 multiply-adds."""
-    n = case.n
-    widths = case.widths
+    degs = box_degrees(case, used, L, plain)
     col = 0
-    D = 1
     total = 0.0
-    for i in range(1, len(widths) - 1):
-        h = widths[i]
-        C = (D + 1) ** n
-        k2 = int((used[:, col:col + h] == 2).sum())
-        total += k2 * 2 * (C * C + C)
+    for i in range(1, len(case.widths) - 1):
+        h = case.widths[i]
+        C = (degs[i - 1].astype(np.float64) + 1.0) ** case.n
+        k2 = (used[:, col:col + h] == 2).sum(axis=1)
+        total += float((k2 * 2 * (C * C + C)).sum())
         col += h
-        D *= L
     return total
 
 
@@ -78,10 +102,11 @@ def cpu_baseline(case, budget_s=10.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cfg5", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-plain", action="store_true", help="do not time the plain form (profiling runs)")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -99,33 +124,62 @@ def main():
     net = B.Net(case.Ws, case.bs)
     lo = torch.tensor(case.box_lo, dtype=torch.float64, device=dev)
     hi = torch.tensor(case.box_hi, dtype=torch.float64, device=dev)
-    kw = dict(L=case.L, precision=spec["precision"], sched=spec["sched"])
-    total, one = net.workspace_size(case.n_boxes, **kw)
-    ws = torch.empty(total + 256, dtype=torch.uint8, device=dev)
-    r = B.bounds(net, lo, hi, workspace=ws, **kw)
-    outs = {k: r[k] for k in ("neuron_lo", "neuron_hi", "out_lo", "out_hi", "used_plan")}
-    for _ in range(args.warmup):
-        B.bounds(net, lo, hi, workspace=ws, outputs=outs, **kw)
-    torch.cuda.synchronize()
+    free, _ = torch.cuda.mem_get_info()
 
-    B.prof_reset()
-    B.prof_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        B.bounds(net, lo, hi, workspace=ws, outputs=outs, **kw)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    B.prof_enable(False)
-    prof = B.prof_read()
-    B.prof_reset()
+    def setup(form, sched):
+        kw = dict(L=case.L, precision=spec["precision"], sched=sched)
+        if form == "learned":
+            from paper_2211_14438_amd import predictor as PR
+            params, meta = PR.load()
+            kw.update(plan="learned", pred=B.Predictor(params))
+        elif form == "given":
+            kw.update(plan="given", degree_plan=torch.tensor(case.plan, dtype=torch.int8, device=dev))
+        total, one = net.workspace_size(case.n_boxes, **{k: v for k, v in kw.items() if k != "degree_plan"})
+        size = int(min(total, max(one, 0.45 * free)))
+        kw["workspace"] = torch.empty(size + 256, dtype=torch.uint8, device=dev)
+        r = B.bounds(net, lo, hi, **kw)
+        kw["outputs"] = {k: r[k] for k in ("neuron_lo", "neuron_hi", "out_lo", "out_hi", "used_plan")}
+        return kw
 
-    dt = t1 - t0
+    def timed(kw, steps, profile):
+        for _ in range(args.warmup):
+            B.bounds(net, lo, hi, **kw)
+        torch.cuda.synchronize()
+        if profile:
+            B.prof_reset()
+            B.prof_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            B.bounds(net, lo, hi, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = None
+        if profile:
+            B.prof_enable(False)
+            prof = B.prof_read()
+            B.prof_reset()
+        return dt, prof
+
+    kw = setup(spec["form"], spec["sched"])
+    dt, prof = timed(kw, args.steps, True)
+    outs = kw["outputs"]
     ms_step = dt / args.steps * 1e3
     neurons = case.n_boxes * case.bounded_neurons_per_box
     value = neurons * args.steps / dt
     used = outs["used_plan"].cpu().numpy()
     width = float((outs["out_hi"] - outs["out_lo"]).mean().item())
+    plain_line = None
+    if spec["form"] != "plain" and not args.skip_plain:
+        del kw
+        torch.cuda.empty_cache()
+        pkw = setup("plain", spec.get("plain_sched", "batched"))
+        psteps = max(1, min(args.steps, 3))
+        pdt, _ = timed(pkw, psteps, False)
+        pw = float((pkw["outputs"]["out_hi"] - pkw["outputs"]["out_lo"]).mean().item())
+        plain_line = dict(form=f"plain order-{case.L} ({spec.get('plain_sched', 'batched')})",
+                          value=neurons * psteps / pdt, ms_per_step=pdt / psteps * 1e3, mean_output_width=pw)
+        del pkw
 
     # roofline of the dominant kernel class (largest summed duration)
     kernels = {}
@@ -134,7 +188,7 @@ def main():
     dom = max(prof.items(), key=lambda kv: kv[1][1])[0]
     launches, ms, by = prof[dom]
     if dom == "compose_square":
-        flops = composed_flops(case, used, case.L) * args.steps
+        flops = composed_flops(case, used, case.L, plain=spec["form"] == "plain") * args.steps
         achieved = flops / (ms * 1e-3) / 1e12
         roof = dict(bound="alu", achieved=achieved, peak=PEAK_VALU_TFLOPS, unit="TFLOP/s",
                     frac=achieved / PEAK_VALU_TFLOPS, traffic=None, kernel=dom,
@@ -164,6 +218,10 @@ def main():
         "roofline": roof,
         "kernels": kernels,
     }
+    if plain_line is not None:
+        line["plain"] = plain_line
+        line["speedup_vs_plain"] = value / plain_line["value"]
+        line["width_ratio_vs_plain"] = width / plain_line["mean_output_width"]
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(case, args.cpu_budget)
     print(json.dumps(line), flush=True)

@@ -135,7 +135,11 @@ __device__ void lds_affine_fit(const double *t, int64_t C, int n, int D, double 
 //  * later layers: the previous layer's post radii through W+ and W-, the
 //    FP64 accumulation of the affine map, and the exact FP32 store roundings
 //    the GEMM blocks reported.
-__device__ void pre_radii(const ConvertArgs &a, int64_t box, int j, const void *pre, double &epsU, double &epsL) {
+// The sums below are split over `nt` cooperating threads (thread index tid)
+// and folded by `reduce` in a fixed order, so every thread gets the result.
+template <typename Reduce>
+__device__ void pre_radii(const ConvertArgs &a, int64_t box, int j, const void *pre, int tid, int nt, Reduce reduce,
+                          double &epsU, double &epsL) {
   if (a.layer == 0) {
     const double *lo = a.box_lo + box * a.n, *hi = a.box_hi + box * a.n;
     const double *w = a.W + (int64_t)j * a.n;
@@ -153,8 +157,8 @@ __device__ void pre_radii(const ConvertArgs &a, int64_t box, int j, const void *
     epsU = epsL = (r + gamma64(a.n + 4) * sabs) * kPadSafety;
     return;
   }
-  double sU = 0.0, sL = 0.0, g = fabs(a.b[j]);
-  for (int k = 0; k < a.hin; ++k) {
+  double sU = 0.0, sL = 0.0, g = 0.0;
+  for (int k = tid; k < a.hin; k += nt) {
     const double wk = a.W[(int64_t)j * a.hin + k];
     const NeuronRec &P = a.prev[box * a.hin + k];
     if (wk >= 0.0) {
@@ -168,25 +172,31 @@ __device__ void pre_radii(const ConvertArgs &a, int64_t box, int j, const void *
   }
   double rU = 0.0, rL = 0.0;
   const double *rp = a.rpart + box * a.rpart_slot + (int64_t)j * 2 * a.cblocks;
-  for (int64_t cb = 0; cb < a.cblocks; ++cb) {
+  for (int64_t cb = tid; cb < a.cblocks; cb += nt) {
     rU += rp[cb];
     rL += rp[a.cblocks + cb];
   }
+  sU = reduce(sU);
+  sL = reduce(sL);
+  g = reduce(g) + fabs(a.b[j]);
+  rU = reduce(rU);
+  rL = reduce(rL);
   const double gg = gamma64(2.0 * a.hin + 6) * g;
   epsU = (sU + gg + rU) * kPadSafety;
   epsL = (sL + gg + rL) * kPadSafety;
 }
 
-// Bounds from the Bernstein extrema (thread 0): in FP32 mode widened by the
-// FP64 basis-change rounding (gamma * sum|a|, the table entries lie in [0,1])
-// and the radii, then rounded outward.
-__device__ void padded_bounds(const ConvertArgs &a, int64_t box, int j, double mn, double mx, double l1L,
-                              double l1U, double &lo, double &hi, double &epsU, double &epsL) {
+// Bounds from the Bernstein extrema: in FP32 mode widened by the FP64
+// basis-change rounding (gamma * sum|a|, the table entries lie in [0,1]) and
+// the radii, then rounded outward. Called by all `nt` cooperating threads.
+template <typename Reduce>
+__device__ void padded_bounds(const ConvertArgs &a, int64_t box, int j, double mn, double mx, double l1L, double l1U,
+                              int tid, int nt, Reduce reduce, double &lo, double &hi, double &epsU, double &epsL) {
   lo = mn;
   hi = mx;
   epsU = epsL = 0.0;
   if (a.fp64) return;
-  pre_radii(a, box, j, a.pre, epsU, epsL);
+  pre_radii(a, box, j, a.pre, tid, nt, reduce, epsU, epsL);
   const double g = gamma64((double)a.n * (a.D + 2) + 4);
   lo = round_down(mn - g * l1L - epsL);
   hi = round_up(mx + g * l1U + epsU);
@@ -263,9 +273,10 @@ __global__ void __launch_bounds__(kBlock) convert_small_kernel(ConvertArgs a) {
     }
     __syncthreads();
   }
+  double lo, hi, epsU, epsL;
+  padded_bounds(a, box, j, ext_lo, ext_hi, l1s[1], l1s[0], (int)threadIdx.x, (int)blockDim.x,
+                [&](double v) { return block_reduce(v, OpAdd(), red); }, lo, hi, epsU, epsL);
   if (threadIdx.x == 0) {
-    double lo, hi, epsU, epsL;
-    padded_bounds(a, box, j, ext_lo, ext_hi, l1s[1], l1s[0], lo, hi, epsU, epsL);
     if (a.mode == 1) {
       a.out_lo[box * a.ld_out + a.col0 + j] = lo;
       a.out_hi[box * a.ld_out + a.col0 + j] = hi;
@@ -273,6 +284,131 @@ __global__ void __launch_bounds__(kBlock) convert_small_kernel(ConvertArgs a) {
       if (a.out_lo) a.out_lo[box * a.ld_out + a.col0 + j] = lo;
       if (a.out_hi) a.out_hi[box * a.ld_out + a.col0 + j] = hi;
       finish_neuron(a, box, j, lo, hi, epsU, epsL, l1s[0], l1s[1], fit, ext, want_fit);
+    }
+  }
+}
+
+// --------------------------------------------------- one wave per neuron
+// Tensors of at most kWaveC coefficients: each wave64 of a 256-thread block
+// handles one (box, neuron) with both bound tensors in its own LDS slice, so
+// every reduction is a wave shuffle and no block barrier follows the shared
+// table fill. The affine fits are computed only where a rule or the feature
+// export needs them (unstable neurons, or every neuron when exporting).
+constexpr int kWaveC = 1024;
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename Op>
+__device__ inline double wave_reduce(double v, Op op) {
+  for (int off = 32; off > 0; off >>= 1) v = op(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+__device__ void wave_basis_change(double *t, int C, int n, int D, const double *tab, int lane) {
+  const int D1 = D + 1;
+  int stride = 1;
+  for (int ax = n - 1; ax >= 0; --ax) {
+    const int fibres = C / D1;
+    for (int f = lane; f < fibres; f += 64) {
+      const int base = (f / stride) * stride * D1 + (f % stride);
+      for (int k = D; k >= 0; --k) {
+        double s = 0.0;
+        for (int j = 0; j <= k; ++j) s = fma(tab[k * D1 + j], t[base + j * stride], s);
+        t[base + k * stride] = s;
+      }
+    }
+    wave_sync();
+    stride *= D1;
+  }
+}
+
+// Same fit as lds_affine_fit, reduced over one wave.
+__device__ void wave_affine_fit(const double *t, int C, int n, int D, int lane, double *beta, double &rmax,
+                                double &rmin) {
+  const int D1 = D + 1;
+  double m = 0.0;
+  for (int i = lane; i < C; i += 64) m += t[i];
+  beta[0] = wave_reduce(m, OpAdd()) / (double)C;
+  double s1 = 0.0;
+  for (int k = 0; k <= D; ++k) {
+    const double q = (double)k / D - 0.5;
+    s1 += q * q;
+  }
+  const double ss = s1 * (double)(C / D1);
+  int stride = C / D1;
+  for (int ax = 0; ax < n; ++ax) {
+    double p = 0.0;
+    for (int i = lane; i < C; i += 64) p += t[i] * ((double)((i / stride) % D1) / D - 0.5);
+    beta[1 + ax] = wave_reduce(p, OpAdd()) / ss;
+    stride /= D1;
+  }
+  double hi = -INFINITY, lo = INFINITY;
+  for (int i = lane; i < C; i += 64) {
+    double l = beta[0];
+    int rem = i;
+    for (int ax = n - 1; ax >= 0; --ax) {
+      l += beta[1 + ax] * ((double)(rem % D1) / D - 0.5);
+      rem /= D1;
+    }
+    hi = fmax(hi, t[i] - l);
+    lo = fmin(lo, t[i] - l);
+  }
+  rmax = wave_reduce(hi, OpMax());
+  rmin = wave_reduce(lo, OpMin());
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) convert_wave_kernel(ConvertArgs a) {
+  extern __shared__ double lds[];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int D1 = a.D + 1;
+  const int C = (int)a.C;
+  double *tab = lds;
+  double *tw = lds + D1 * D1 + (int64_t)wv * 2 * C;  // [2][C]: lower, upper
+  fill_table(tab, a.D);
+  const int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + wv;
+  if (item >= a.nboxes * a.h) return;
+  const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
+  const int j = (int)(item % a.h);
+  double ext[2], l1s[2];
+  for (int s = 1; s >= 0; --s) {
+    double *t = tw + (1 - s) * C;
+    const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + ((int64_t)j * 2 + s) * a.C;
+    double l1 = 0.0;
+    for (int i = lane; i < C; i += 64) {
+      t[i] = (double)p[i];
+      l1 += fabs(t[i]);
+    }
+    l1s[s] = wave_reduce(l1, OpAdd());
+    wave_sync();
+    wave_basis_change(t, C, a.n, a.D, tab, lane);
+    double v = s ? INFINITY : -INFINITY;
+    for (int i = lane; i < C; i += 64) v = s ? fmin(v, t[i]) : fmax(v, t[i]);
+    ext[s] = s ? wave_reduce(v, OpMin()) : wave_reduce(v, OpMax());
+  }
+  double lo, hi, epsU, epsL;
+  padded_bounds(a, box, j, ext[1], ext[0], l1s[1], l1s[0], lane, 64,
+                [](double v) { return wave_reduce(v, OpAdd()); }, lo, hi, epsU, epsL);
+  bool want_fit = a.mode == 0 && a.D > 0 &&
+                  (a.learned || a.fits || (a.plan && a.plan[box * a.plan_ld + a.plan_col0 + j] <= 0));
+  if (!a.fits) want_fit = want_fit && lo < 0.0 && hi > 0.0;  // only unstable neurons take a fitted rule
+  double fit[2][kMaxInputs + 1], fx[4] = {0.0, 0.0, 0.0, 0.0};
+  if (want_fit) {
+    wave_affine_fit(tw + C, C, a.n, a.D, lane, fit[0], fx[0], fx[1]);  // upper
+    wave_affine_fit(tw, C, a.n, a.D, lane, fit[1], fx[2], fx[3]);      // lower
+  }
+  if (lane == 0) {
+    if (a.mode == 1) {
+      a.out_lo[box * a.ld_out + a.col0 + j] = lo;
+      a.out_hi[box * a.ld_out + a.col0 + j] = hi;
+    } else {
+      if (a.out_lo) a.out_lo[box * a.ld_out + a.col0 + j] = lo;
+      if (a.out_hi) a.out_hi[box * a.ld_out + a.col0 + j] = hi;
+      finish_neuron(a, box, j, lo, hi, epsU, epsL, l1s[0], l1s[1], fit, fx, want_fit);
     }
   }
 }
@@ -379,24 +515,31 @@ __global__ void __launch_bounds__(kBlock) convert_passB_kernel(ConvertArgs a, Sp
   if (threadIdx.x == 0) partial[tensor * sp.nchunk + blockIdx.x] = v;
 }
 
-// Fold the per-chunk extrema of both bounds of one neuron.
-__global__ void __launch_bounds__(64) convert_final_kernel(ConvertArgs a, Split sp, const double *partial,
-                                                          const double *l1part) {
-  const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Fold the per-chunk extrema of both bounds of one neuron: one wave each.
+__global__ void __launch_bounds__(kBlock) convert_final_kernel(ConvertArgs a, Split sp, const double *partial,
+                                                               const double *l1part) {
+  const int lane = threadIdx.x & 63;
+  const int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   if (item >= a.nboxes * a.h) return;
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
   const int j = (int)(item % a.h);
   double mn = INFINITY, mx = -INFINITY, l1U = 0.0, l1L = 0.0;
-  for (int64_t c = 0; c < sp.nchunk; ++c) {
+  for (int64_t c = lane; c < sp.nchunk; c += 64) {
     mn = fmin(mn, partial[(item * 2 + 1) * sp.nchunk + c]);
     mx = fmax(mx, partial[(item * 2 + 0) * sp.nchunk + c]);
   }
-  for (int64_t o = 0; o < sp.Co; ++o) {
+  for (int64_t o = lane; o < sp.Co; o += 64) {
     l1U += l1part[(item * 2 + 0) * sp.Co + o];
     l1L += l1part[(item * 2 + 1) * sp.Co + o];
   }
+  mn = wave_reduce(mn, OpMin());
+  mx = wave_reduce(mx, OpMax());
+  l1U = wave_reduce(l1U, OpAdd());
+  l1L = wave_reduce(l1L, OpAdd());
   double lo, hi, epsU, epsL;
-  padded_bounds(a, box, j, mn, mx, l1L, l1U, lo, hi, epsU, epsL);
+  padded_bounds(a, box, j, mn, mx, l1L, l1U, lane, 64, [](double v) { return wave_reduce(v, OpAdd()); }, lo, hi,
+                epsU, epsL);
+  if (lane != 0) return;
   if (a.mode == 1) {
     a.out_lo[box * a.ld_out + a.col0 + j] = lo;
     a.out_hi[box * a.ld_out + a.col0 + j] = hi;
@@ -423,6 +566,15 @@ size_t convert_scratch_bytes(int n, int D, int h, int64_t nboxes) {
 
 hipError_t launch_convert(const ConvertArgs &a, hipStream_t s) {
   const int D1 = a.D + 1;
+  if (a.C <= kWaveC) {
+    const size_t lds = (D1 * D1 + (kBlock / 64) * 2 * a.C) * sizeof(double);
+    auto k = a.fp64 ? convert_wave_kernel<double> : convert_wave_kernel<float>;
+    RET_IF(hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.C * (a.fp64 ? 8 : 4));
+    const int64_t items = a.nboxes * a.h;
+    hipLaunchKernelGGL(k, dim3((unsigned)((items + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), lds, s, a);
+    return hipGetLastError();
+  }
   if (use_small(a.C)) {
     const size_t lds = (a.C + D1 * D1 + 16) * sizeof(double);
     auto k = a.fp64 ? convert_small_kernel<double> : convert_small_kernel<float>;
@@ -454,7 +606,7 @@ hipError_t launch_convert(const ConvertArgs &a, hipStream_t s) {
   }
   {
     ProfScope ps(kProfConvertFinal, s, (double)tensors * sp.nchunk * 8);
-    hipLaunchKernelGGL(convert_final_kernel, dim3((unsigned)((a.nboxes * a.h + 63) / 64)), dim3(64), 0, s, a, sp,
+    hipLaunchKernelGGL(convert_final_kernel, dim3((unsigned)((a.nboxes * a.h + 3) / 4)), dim3(kBlock), 0, s, a, sp,
                        (const double *)partial, (const double *)l1part);
   }
   return hipGetLastError();
