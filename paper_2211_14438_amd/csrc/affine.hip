@@ -59,10 +59,13 @@ hipError_t launch_layer1(const Layer1Args &a, hipStream_t s) {
 // One thread per coefficient c; MB output neurons per block row. Block x
 // index runs over output-neuron chunks first so that the blocks reading the
 // same coefficient range of the previous layer run together and share L2.
-// Arithmetic is FP64 whatever the storage type; in FP32 mode each block also
-// reports, per output neuron and bound, the sum of |fl32(y) - y| over its
-// coefficients (the exact rounding of the stored tensor), reduced in a fixed
-// order.
+// The weights come from the transposed, zero-padded copy W^T[k][hp]: for one
+// input k the block's MB weights are contiguous and uniform, so they load as
+// a few wide scalar loads and no row guard sits in the inner loop; |w| is the
+// FMA's source modifier. Arithmetic is FP64 whatever the storage type; in
+// FP32 mode each block also reports, per output neuron and bound, the sum of
+// |fl32(y) - y| over its coefficients (the exact rounding of the stored
+// tensor), reduced in a fixed order.
 template <typename T, int MB, int KU>
 __global__ void __launch_bounds__(kBlock) gemm_kernel(GemmArgs a) {
   __shared__ double red[kBlock / 64][MB][2];
@@ -75,45 +78,60 @@ __global__ void __launch_bounds__(kBlock) gemm_kernel(GemmArgs a) {
 #pragma unroll
   for (int mm = 0; mm < MB; ++mm) accM[mm] = accR[mm] = 0.0;
   const int mcount = min(MB, a.h - m0);
-  if (valid) {
-    const T *Xc = X + c;
-    const int64_t st = 2 * a.C;
-    int k = 0;
-    // KU inputs per step: 2*KU independent loads in flight per thread
-    for (; k + KU <= a.hin; k += KU) {
-      double u[KU], l[KU];
+  // lanes past the tensor read its last coefficient; their sums are dropped
+  const T *Xc = X + (valid ? c : a.C - 1);
+  const int64_t st = 2 * a.C;
+  const double *wt = a.WT + m0;
+  int k = 0;
+  // KU inputs per step, the next step's 2*KU loads issued before this
+  // step's multiply-adds so that they stay in flight across them
+  T u[KU], l[KU];
+  if (KU <= a.hin) {
+#pragma unroll
+    for (int q = 0; q < KU; ++q) {
+      u[q] = Xc[(int64_t)q * st];
+      l[q] = Xc[(int64_t)q * st + a.C];
+    }
+  }
+  for (; k + KU <= a.hin; k += KU) {
+    T un[KU], ln[KU];
+    const bool more = k + 2 * KU <= a.hin;
+    if (more) {
 #pragma unroll
       for (int q = 0; q < KU; ++q) {
-        u[q] = (double)Xc[(int64_t)(k + q) * st];
-        l[q] = (double)Xc[(int64_t)(k + q) * st + a.C];
-      }
-#pragma unroll
-      for (int q = 0; q < KU; ++q) {
-        const double M = (u[q] + l[q]) * 0.5;
-        const double R = (u[q] - l[q]) * 0.5;
-#pragma unroll
-        for (int mm = 0; mm < MB; ++mm) {
-          if (mm < mcount) {
-            const double w = a.W[(int64_t)(m0 + mm) * a.hin + k + q];
-            accM[mm] = fma(w, M, accM[mm]);
-            accR[mm] = fma(fabs(w), R, accR[mm]);
-          }
-        }
+        un[q] = Xc[(int64_t)(k + KU + q) * st];
+        ln[q] = Xc[(int64_t)(k + KU + q) * st + a.C];
       }
     }
-    for (; k < a.hin; ++k) {
-      const double u = (double)Xc[(int64_t)k * st];
-      const double l = (double)Xc[(int64_t)k * st + a.C];
-      const double M = (u + l) * 0.5;
-      const double R = (u - l) * 0.5;
+#pragma unroll
+    for (int q = 0; q < KU; ++q) {
+      const double M = ((double)u[q] + (double)l[q]) * 0.5;
+      const double R = ((double)u[q] - (double)l[q]) * 0.5;
+      const double *w = wt + (int64_t)(k + q) * a.hp;
 #pragma unroll
       for (int mm = 0; mm < MB; ++mm) {
-        if (mm < mcount) {
-          const double w = a.W[(int64_t)(m0 + mm) * a.hin + k];
-          accM[mm] = fma(w, M, accM[mm]);
-          accR[mm] = fma(fabs(w), R, accR[mm]);
-        }
+        accM[mm] = fma(w[mm], M, accM[mm]);
+        accR[mm] = fma(fabs(w[mm]), R, accR[mm]);
       }
+    }
+    if (more) {
+#pragma unroll
+      for (int q = 0; q < KU; ++q) {
+        u[q] = un[q];
+        l[q] = ln[q];
+      }
+    }
+  }
+  for (; k < a.hin; ++k) {
+    const double u = (double)Xc[(int64_t)k * st];
+    const double l = (double)Xc[(int64_t)k * st + a.C];
+    const double M = (u + l) * 0.5;
+    const double R = (u - l) * 0.5;
+    const double *w = wt + (int64_t)k * a.hp;
+#pragma unroll
+    for (int mm = 0; mm < MB; ++mm) {
+      accM[mm] = fma(w[mm], M, accM[mm]);
+      accR[mm] = fma(fabs(w[mm]), R, accR[mm]);
     }
   }
   T *Y = reinterpret_cast<T *>(a.pre) + box * a.slot_out;
@@ -156,17 +174,26 @@ __global__ void __launch_bounds__(kBlock) gemm_kernel(GemmArgs a) {
 
 int64_t gemm_cblocks(int64_t C) { return (C + kBlock - 1) / kBlock; }
 
-hipError_t launch_gemm(const GemmArgs &a0, hipStream_t s) {
-  GemmArgs a = a0;
-  a.cblocks = gemm_cblocks(a.C);
-  constexpr int MB = 16, KU = 2;
+template <int MB, int KU>
+static hipError_t launch_gemm_mb(const GemmArgs &a, hipStream_t s) {
   dim3 grid((a.h + MB - 1) / MB, (unsigned)a.cblocks, (unsigned)a.nboxes);
-  ProfScope ps(kProfGemm, s, (double)a.nboxes * (2.0 * a.hin + 2.0 * a.h) * a.C * (a.fp64 ? 8 : 4));
   if (a.fp64)
     hipLaunchKernelGGL((gemm_kernel<double, MB, KU>), grid, dim3(kBlock), 0, s, a);
   else
     hipLaunchKernelGGL((gemm_kernel<float, MB, KU>), grid, dim3(kBlock), 0, s, a);
   return hipGetLastError();
+}
+
+// Narrow output layers are bound by reading the input tensors: fewer rows
+// per block and more loads in flight; wide layers by the FP64 multiply-adds.
+hipError_t launch_gemm(const GemmArgs &a0, hipStream_t s) {
+  GemmArgs a = a0;
+  a.cblocks = gemm_cblocks(a.C);
+  if (a.hp % 16 != 0 || a.hp < a.h) return hipErrorInvalidValue;
+  ProfScope ps(kProfGemm, s, (double)a.nboxes * (2.0 * a.hin + 2.0 * a.h) * a.C * (a.fp64 ? 8 : 4));
+  if (a.h <= 4) return launch_gemm_mb<4, 8>(a, s);
+  if (a.h <= 8) return launch_gemm_mb<8, 4>(a, s);
+  return launch_gemm_mb<16, 2>(a, s);
 }
 
 }  // namespace bern

@@ -124,6 +124,9 @@ struct bern_net {
   std::vector<int> widths;
   std::vector<int64_t> woff, boff, noff;  // per layer offsets into W, b and hidden neurons
   double *W64 = nullptr, *b64 = nullptr;
+  double *WT = nullptr;                   // per layer W^T [w_{i-1}][hp_i], zero-padded to hp_i columns
+  std::vector<int64_t> wtoff;
+  std::vector<int> hpad;
   double *sens = nullptr;  // [nh] downstream sensitivity of every hidden neuron
   int device = 0;
 };
@@ -285,15 +288,29 @@ bern_status bern_net_create(int32_t H, const int32_t *widths, const double *W, c
       for (int c = 0; c < hp; ++c) sens[net->noff[i - 2] + c] = v[c];
     }
   }
+  // transposed, zero-padded weights for the interval GEMM
+  std::vector<double> wt;
+  for (int i = 1; i <= H; ++i) {
+    const int h = widths[i], hin = widths[i - 1], hp = (h + 15) / 16 * 16;
+    net->wtoff.push_back((int64_t)wt.size());
+    net->hpad.push_back(hp);
+    const size_t base = wt.size();
+    wt.resize(base + (size_t)hin * hp, 0.0);
+    const double *Wi = W + net->woff[i - 1];
+    for (int r = 0; r < h; ++r)
+      for (int c = 0; c < hin; ++c) wt[base + (size_t)c * hp + r] = Wi[(int64_t)r * hin + c];
+  }
   (void)hipGetDevice(&net->device);
   auto fail = [&](hipError_t e) {
     set_error("device allocation/copy failed: %s", hipGetErrorString(e));
-    (void)hipFree(net->W64); (void)hipFree(net->b64); (void)hipFree(net->sens);
+    (void)hipFree(net->W64); (void)hipFree(net->b64); (void)hipFree(net->sens); (void)hipFree(net->WT);
     delete net;
     return BERN_E_DEVICE;
   };
   hipError_t e;
   if ((e = hipMalloc(&net->W64, nw * 8)) != hipSuccess) return fail(e);
+  if ((e = hipMalloc(&net->WT, wt.size() * 8)) != hipSuccess) return fail(e);
+  if ((e = hipMemcpy(net->WT, wt.data(), wt.size() * 8, hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
   if ((e = hipMalloc(&net->b64, nb * 8)) != hipSuccess) return fail(e);
   if ((e = hipMalloc(&net->sens, sens.size() * 8)) != hipSuccess) return fail(e);
   if ((e = hipMemcpy(net->W64, W, nw * 8, hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
@@ -308,6 +325,7 @@ void bern_net_destroy(bern_net *net) {
   (void)hipFree(net->W64);
   (void)hipFree(net->b64);
   (void)hipFree(net->sens);
+  (void)hipFree(net->WT);
   delete net;
 }
 
@@ -605,7 +623,8 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       a.slot_out = slotA;
       a.post = Bp;
       a.pre = A;
-      a.W = net->W64 + net->woff[i + 1];
+      a.WT = net->WT + net->wtoff[i + 1];
+      a.hp = net->hpad[i + 1];
       a.b = net->b64 + net->boff[i + 1];
       a.fp64 = p.fp64 ? 1 : 0;
       a.rpart = p.fp64 ? nullptr : gpart;

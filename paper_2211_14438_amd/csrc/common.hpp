@@ -149,7 +149,8 @@ struct GemmArgs {
   int64_t slot_in, slot_out;
   const void *post;               // [B][hin][2][C]
   void *pre;                      // [B][h][2][C]
-  const double *W;                // [h][hin]
+  const double *WT;               // [hin][hp]: W transposed, rows h..hp-1 zero
+  int hp;                         // h rounded up to a multiple of 16
   const double *b;                // [h]
   int fp64;
   double *rpart;                  // FP32 mode: per wave box (stride rpart_slot): [h][2][cblocks]

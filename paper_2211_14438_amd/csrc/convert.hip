@@ -413,6 +413,310 @@ __global__ void __launch_bounds__(kBlock) convert_wave_kernel(ConvertArgs a) {
   }
 }
 
+// ------------------------------------------- compile-time degree variants
+// For per-variable degrees 1..8 the ratio table C(k,j)/C(D,j) is a constant
+// of the instruction stream and each fibre of D+1 coefficients is converted
+// in registers: one LDS read and one write per coefficient and axis. The
+// fastest axis is converted straight from the global load, and the extrema
+// are taken from the registers of the last axis pass. Sums follow a fixed
+// per-thread order, so results are reproducible run to run.
+constexpr uint64_t binom_u(int n, int k) {
+  uint64_t r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (uint64_t)(n - k + i) / (uint64_t)i;
+  return r;
+}
+
+template <int D>
+struct Ratio {
+  double v[D + 1][D + 1];
+  constexpr Ratio() : v() {
+    for (int k = 0; k <= D; ++k)
+      for (int j = 0; j <= D; ++j) v[k][j] = j <= k ? (double)binom_u(k, j) / (double)binom_u(D, j) : 0.0;
+  }
+};
+
+// b_k = sum_{j<=k} C(k,j)/C(D,j) a_j in place; descending k keeps a_j (j<k).
+template <int D>
+__device__ __forceinline__ void to_bern(double (&x)[D + 1]) {
+  constexpr Ratio<D> R{};
+#pragma unroll
+  for (int k = D; k >= 0; --k) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j <= k; ++j) s = fma(R.v[k][j], x[j], s);
+    x[k] = s;
+  }
+}
+
+struct WaveTeam {
+  int tid;
+  static constexpr int nt = 64;
+  __device__ void sync() const { wave_sync(); }
+  __device__ double sum(double v) const { return wave_reduce(v, OpAdd()); }
+  __device__ double min(double v) const { return wave_reduce(v, OpMin()); }
+  __device__ double max(double v) const { return wave_reduce(v, OpMax()); }
+};
+
+struct BlockTeam {
+  int tid, nt;
+  double *red;
+  __device__ void sync() const { __syncthreads(); }
+  __device__ double sum(double v) const { return block_reduce(v, OpAdd(), red); }
+  __device__ double min(double v) const { return block_reduce(v, OpMin(), red); }
+  __device__ double max(double v) const { return block_reduce(v, OpMax(), red); }
+};
+
+// Convert axes [0, na) of a tensor already in LDS whose axis na-1 has stride
+// s0 (axis a has stride s0 (D+1)^(na-1-a)); `total` coefficients. Tracks the
+// extrema of the last pass when `track` is set.
+template <int D, class Team>
+__device__ void team_axes(double *t, int total, int s0, int na, const Team &tm, bool track, double &mn,
+                          double &mx) {
+  constexpr int D1 = D + 1;
+  const int F = total / D1;
+  int stride = s0;
+  for (int ax = na - 1; ax >= 0; --ax) {
+    tm.sync();
+    const bool last = track && ax == 0;
+    for (int f = tm.tid; f < F; f += tm.nt) {
+      const int hi = f / stride, lo = f - hi * stride;
+      const int base = hi * stride * D1 + lo;
+      double x[D1];
+#pragma unroll
+      for (int j = 0; j < D1; ++j) x[j] = t[base + j * stride];
+      to_bern<D>(x);
+#pragma unroll
+      for (int j = 0; j < D1; ++j) {
+        if (last) {
+          mn = fmin(mn, x[j]);
+          mx = fmax(mx, x[j]);
+        }
+        t[base + j * stride] = x[j];
+      }
+    }
+    stride *= D1;
+  }
+  tm.sync();
+}
+
+// Power coefficients p[0, C) (C = (D+1)^n) -> Bernstein coefficients in t.
+// Returns the team-wide sum of |p| and the extrema of the result.
+template <int D, typename T, class Team>
+__device__ void team_convert(double *t, const T *p, int C, int n, const Team &tm, double &l1, double &vmin,
+                             double &vmax) {
+  constexpr int D1 = D + 1;
+  const int F = C / D1;
+  double s = 0.0, mn = INFINITY, mx = -INFINITY;
+  for (int f = tm.tid; f < F; f += tm.nt) {
+    double x[D1];
+#pragma unroll
+    for (int j = 0; j < D1; ++j) {
+      x[j] = (double)p[f * D1 + j];
+      s += fabs(x[j]);
+    }
+    to_bern<D>(x);
+#pragma unroll
+    for (int j = 0; j < D1; ++j) {
+      if (n == 1) {
+        mn = fmin(mn, x[j]);
+        mx = fmax(mx, x[j]);
+      }
+      t[f * D1 + j] = x[j];
+    }
+  }
+  team_axes<D>(t, C, D1, n - 1, tm, true, mn, mx);
+  l1 = tm.sum(s);
+  vmin = tm.min(mn);
+  vmax = tm.max(mx);
+}
+
+// Affine least-squares fit of the control net and its remainder range (same
+// quantities as lds_affine_fit), reading fibres along the fastest axis so
+// the other axes' digits are found once per fibre with constant divisors.
+template <int D, class Team>
+__device__ void team_fit(const double *t, int C, int n, const Team &tm, double *beta, double &rmax, double &rmin) {
+  constexpr int D1 = D + 1;
+  const int F = C / D1;
+  double m = 0.0, pl = 0.0, p[kMaxInputs - 1];
+#pragma unroll
+  for (int a = 0; a < kMaxInputs - 1; ++a) p[a] = 0.0;
+  for (int f = tm.tid; f < F; f += tm.nt) {
+    double S = 0.0, Sl = 0.0;
+#pragma unroll
+    for (int k = 0; k < D1; ++k) {
+      const double x = t[f * D1 + k];
+      S += x;
+      Sl = fma(x, (double)k / D - 0.5, Sl);
+    }
+    m += S;
+    pl += Sl;
+    int q = f;
+#pragma unroll
+    for (int a = kMaxInputs - 2; a >= 0; --a) {
+      if (a <= n - 2) {
+        const int d = q % D1;
+        q /= D1;
+        p[a] = fma(S, (double)d / D - 0.5, p[a]);
+      }
+    }
+  }
+  double s1 = 0.0;
+#pragma unroll
+  for (int k = 0; k <= D; ++k) s1 += ((double)k / D - 0.5) * ((double)k / D - 0.5);
+  const double ss = s1 * (double)F;
+  beta[0] = tm.sum(m) / (double)C;
+#pragma unroll
+  for (int a = 0; a < kMaxInputs; ++a) {
+    if (a < n) beta[1 + a] = tm.sum(a < n - 1 ? p[a < kMaxInputs - 1 ? a : 0] : pl) / ss;
+  }
+  double hi = -INFINITY, lo = INFINITY;
+  for (int f = tm.tid; f < F; f += tm.nt) {
+    double lf = beta[0];
+    int q = f;
+#pragma unroll
+    for (int a = kMaxInputs - 2; a >= 0; --a) {
+      if (a <= n - 2) {
+        const int d = q % D1;
+        q /= D1;
+        lf = fma(beta[1 + a], (double)d / D - 0.5, lf);
+      }
+    }
+    const double bl = beta[n];
+#pragma unroll
+    for (int k = 0; k < D1; ++k) {
+      const double r = t[f * D1 + k] - fma(bl, (double)k / D - 0.5, lf);
+      hi = fmax(hi, r);
+      lo = fmin(lo, r);
+    }
+  }
+  rmax = tm.max(hi);
+  rmin = tm.min(lo);
+}
+
+// Bound of one side from its Bernstein extremum (FP32 mode: widened by the
+// basis-change rounding and the pre-activation radius, rounded outward).
+__device__ inline double side_lo(const ConvertArgs &a, double mn, double l1, double eps) {
+  if (a.fp64) return mn;
+  return round_down(mn - gamma64((double)a.n * (a.D + 2) + 4) * l1 - eps);
+}
+__device__ inline double side_hi(const ConvertArgs &a, double mx, double l1, double eps) {
+  if (a.fp64) return mx;
+  return round_up(mx + gamma64((double)a.n * (a.D + 2) + 4) * l1 + eps);
+}
+
+__device__ inline bool wants_fit(const ConvertArgs &a, int64_t box, int j) {
+  return a.mode == 0 && a.D > 0 && (a.learned || a.fits || (a.plan && a.plan[box * a.plan_ld + a.plan_col0 + j] <= 0));
+}
+
+__device__ inline void write_neuron(const ConvertArgs &a, int64_t box, int j, double lo, double hi, double epsU,
+                                    double epsL, double l1U, double l1L, const double (*fit)[kMaxInputs + 1],
+                                    const double *ext, bool fitted) {
+  if (a.mode == 1) {
+    a.out_lo[box * a.ld_out + a.col0 + j] = lo;
+    a.out_hi[box * a.ld_out + a.col0 + j] = hi;
+  } else {
+    if (a.out_lo) a.out_lo[box * a.ld_out + a.col0 + j] = lo;
+    if (a.out_hi) a.out_hi[box * a.ld_out + a.col0 + j] = hi;
+    finish_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fit, ext, fitted);
+  }
+}
+
+// One wave per (box, neuron), both bound tensors in the wave's LDS slice.
+template <int D, typename T>
+__global__ void __launch_bounds__(kBlock) convert_wave_t(ConvertArgs a) {
+  extern __shared__ double lds[];
+  const WaveTeam tm{(int)(threadIdx.x & 63)};
+  const int wv = threadIdx.x >> 6;
+  const int C = (int)a.C;
+  double *tw = lds + (int64_t)wv * 2 * C;  // [2][C]: lower, upper
+  const int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + wv;
+  if (item >= a.nboxes * a.h) return;
+  const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
+  const int j = (int)(item % a.h);
+  const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + (int64_t)j * 2 * a.C;
+  double l1L, l1U, mn, mx, dummy;
+  team_convert<D>(tw, p + a.C, C, a.n, tm, l1L, mn, dummy);
+  team_convert<D>(tw + C, p, C, a.n, tm, l1U, dummy, mx);
+  double epsU = 0.0, epsL = 0.0;
+  if (!a.fp64) pre_radii(a, box, j, a.pre, tm.tid, 64, [&](double v) { return tm.sum(v); }, epsU, epsL);
+  const double lo = side_lo(a, mn, l1L, epsL), hi = side_hi(a, mx, l1U, epsU);
+  const bool fitted = wants_fit(a, box, j) && (a.fits || (lo < 0.0 && hi > 0.0));
+  double fit[2][kMaxInputs + 1], fx[4] = {0.0, 0.0, 0.0, 0.0};
+  if (fitted) {
+    team_fit<D>(tw + C, C, a.n, tm, fit[0], fx[0], fx[1]);  // upper
+    team_fit<D>(tw, C, a.n, tm, fit[1], fx[2], fx[3]);      // lower
+  }
+  if (tm.tid == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fit, fx, fitted);
+}
+
+// One block per (box, neuron) for tensors up to kSmallLds coefficients, one
+// tensor in LDS at a time. The lower tensor is fitted while resident when
+// the neuron may still be unstable (its lower bound is negative); the upper
+// one once both bounds are known.
+template <int D, typename T>
+__global__ void __launch_bounds__(1024) convert_block_t(ConvertArgs a) {
+  extern __shared__ double lds[];
+  __shared__ double red[16];
+  const BlockTeam tm{(int)threadIdx.x, (int)blockDim.x, red};
+  double *t = lds;
+  const int C = (int)a.C;
+  const int64_t item = blockIdx.x;
+  const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
+  const int j = (int)(item % a.h);
+  const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + (int64_t)j * 2 * a.C;
+  double epsU = 0.0, epsL = 0.0;
+  if (!a.fp64) pre_radii(a, box, j, a.pre, tm.tid, tm.nt, [&](double v) { return tm.sum(v); }, epsU, epsL);
+  const bool want = wants_fit(a, box, j);
+  double fit[2][kMaxInputs + 1], fx[4] = {0.0, 0.0, 0.0, 0.0};
+  double l1L, l1U, mn, mx, dummy;
+  team_convert<D>(t, p + a.C, C, a.n, tm, l1L, mn, dummy);
+  const double lo = side_lo(a, mn, l1L, epsL);
+  if (want && (a.fits || lo < 0.0)) team_fit<D>(t, C, a.n, tm, fit[1], fx[2], fx[3]);
+  tm.sync();
+  team_convert<D>(t, p, C, a.n, tm, l1U, dummy, mx);
+  const double hi = side_hi(a, mx, l1U, epsU);
+  const bool fitted = want && (a.fits || (lo < 0.0 && hi > 0.0));
+  if (fitted) team_fit<D>(t, C, a.n, tm, fit[0], fx[0], fx[1]);
+  if (tm.tid == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fit, fx, fitted);
+}
+
+template <typename T, int D>
+static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
+  if (a.C <= kWaveC) {
+    const size_t lds = (size_t)(kBlock / 64) * 2 * a.C * sizeof(double);
+    RET_IF(hipFuncSetAttribute((const void *)convert_wave_t<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+    ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.C * (a.fp64 ? 8 : 4));
+    const int64_t items = a.nboxes * a.h;
+    hipLaunchKernelGGL((convert_wave_t<D, T>), dim3((unsigned)((items + kBlock / 64 - 1) / (kBlock / 64))),
+                       dim3(kBlock), lds, s, a);
+    return hipGetLastError();
+  }
+  const size_t lds = (size_t)a.C * sizeof(double);
+  RET_IF(hipFuncSetAttribute((const void *)convert_block_t<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds));
+  // a block per neuron; when few blocks share a CU's LDS, more waves each
+  const unsigned threads = lds > 40 * 1024 ? 1024 : 256;
+  ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.C * (a.fp64 ? 8 : 4));
+  hipLaunchKernelGGL((convert_block_t<D, T>), dim3((unsigned)(a.nboxes * a.h)), dim3(threads), lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_convert_fixed(const ConvertArgs &a, hipStream_t s) {
+  switch (a.D) {
+    case 1: return launch_convert_t<T, 1>(a, s);
+    case 2: return launch_convert_t<T, 2>(a, s);
+    case 3: return launch_convert_t<T, 3>(a, s);
+    case 4: return launch_convert_t<T, 4>(a, s);
+    case 5: return launch_convert_t<T, 5>(a, s);
+    case 6: return launch_convert_t<T, 6>(a, s);
+    case 7: return launch_convert_t<T, 7>(a, s);
+    case 8: return launch_convert_t<T, 8>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 // ---------------------------------------------------------- two-pass path
 struct Split {
   int m;         // trailing axes converted in pass A
@@ -566,6 +870,8 @@ size_t convert_scratch_bytes(int n, int D, int h, int64_t nboxes) {
 
 hipError_t launch_convert(const ConvertArgs &a, hipStream_t s) {
   const int D1 = a.D + 1;
+  if (a.D >= 1 && a.D <= 8 && (a.C <= kWaveC || use_small(a.C)))
+    return a.fp64 ? launch_convert_fixed<double>(a, s) : launch_convert_fixed<float>(a, s);
   if (a.C <= kWaveC) {
     const size_t lds = (D1 * D1 + (kBlock / 64) * 2 * a.C) * sizeof(double);
     auto k = a.fp64 ? convert_wave_kernel<double> : convert_wave_kernel<float>;

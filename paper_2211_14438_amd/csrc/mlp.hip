@@ -237,20 +237,18 @@ __global__ void __launch_bounds__(256) learned_classes_kernel(LearnArgs a) {
 // neurons takes, so classes below that degree only cost tightness. Raise
 // them at no cost in tensor size: if some unstable neuron takes order >= 2,
 // the others take at least order 2; otherwise, if some takes order 1, the
-// fallback neurons take order 1. Then apply the rules (one thread per box).
-__global__ void learned_rules_kernel(LearnArgs a) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// fallback neurons take order 1. Then apply the rules: one wave per box, its
+// lanes over the neurons.
+__global__ void __launch_bounds__(256) learned_rules_kernel(LearnArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (g >= a.nboxes) return;
   const int64_t box = a.bids ? a.bids[g] : g;
   int8_t *cl = a.codes + box * a.nh + a.noff;
-  int top = -1;
-  for (int j = 0; j < a.h; ++j) {
-    int c = cl[j];
-    if (c < 0) continue;
-    // class as the degree it gives: fallback (0) lowest
-    top = max(top, c);
-  }
-  for (int j = 0; j < a.h; ++j) {
+  int top = -1;  // class as the degree it gives: fallback (0) lowest
+  for (int j = lane; j < a.h; j += 64) top = max(top, (int)cl[j]);
+  for (int off = 32; off > 0; off >>= 1) top = max(top, __shfl_xor(top, off, 64));
+  for (int j = lane; j < a.h; j += 64) {
     NeuronRec &r = a.recs[box * a.h + j];
     int c = cl[j];
     if (c >= 0) {
@@ -270,7 +268,7 @@ hipError_t launch_learned_rules(const LearnArgs &a, hipStream_t s) {
     RET_IF(hipGetLastError());
   }
   ProfScope ps(kProfPredictor, s, 0.0);
-  hipLaunchKernelGGL(learned_rules_kernel, dim3((unsigned)((a.nboxes + 63) / 64)), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(learned_rules_kernel, dim3((unsigned)((a.nboxes + 3) / 4)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
