@@ -56,9 +56,77 @@ hipError_t launch_layer1(const Layer1Args &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// One thread per coefficient c; MB output neurons per block row. Block x
-// index runs over output-neuron chunks first so that the blocks reading the
-// same coefficient range of the previous layer run together and share L2.
+// Multiply-adds of the inputs in `list` (count entries) into the MB
+// accumulator pairs: X points at the thread's coefficient of input 0's upper
+// tensor, input k's tensors sit at k*st (upper) and k*st + C (lower). `on`
+// false makes every value an exact zero (loads stay in bounds). KU inputs
+// per step, the next step's loads issued before this step's multiply-adds.
+template <typename T, int MB, int KU>
+__device__ __forceinline__ void gemm_rows(const T *X, int64_t st, int64_t C, const int *list, int count, bool on,
+                                          const double *wt, int hp, double (&accM)[MB], double (&accR)[MB]) {
+  int k = 0;
+  T u[KU], l[KU];
+  if (KU <= count) {
+#pragma unroll
+    for (int q = 0; q < KU; ++q) {
+      const int64_t r = (int64_t)list[q] * st;
+      u[q] = X[r];
+      l[q] = X[r + C];
+    }
+  }
+  for (; k + KU <= count; k += KU) {
+    T un[KU], ln[KU];
+    const bool more = k + 2 * KU <= count;
+    if (more) {
+#pragma unroll
+      for (int q = 0; q < KU; ++q) {
+        const int64_t r = (int64_t)list[k + KU + q] * st;
+        un[q] = X[r];
+        ln[q] = X[r + C];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < KU; ++q) {
+      const double uu = on ? (double)u[q] : 0.0, ll = on ? (double)l[q] : 0.0;
+      const double M = (uu + ll) * 0.5;
+      const double R = (uu - ll) * 0.5;
+      const double *w = wt + (int64_t)list[k + q] * hp;
+#pragma unroll
+      for (int mm = 0; mm < MB; ++mm) {
+        accM[mm] = fma(w[mm], M, accM[mm]);
+        accR[mm] = fma(fabs(w[mm]), R, accR[mm]);
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int q = 0; q < KU; ++q) {
+        u[q] = un[q];
+        l[q] = ln[q];
+      }
+    }
+  }
+  for (; k < count; ++k) {
+    const int64_t r = (int64_t)list[k] * st;
+    const double uu = on ? (double)X[r] : 0.0, ll = on ? (double)X[r + C] : 0.0;
+    const double M = (uu + ll) * 0.5;
+    const double R = (uu - ll) * 0.5;
+    const double *w = wt + (int64_t)list[k] * hp;
+#pragma unroll
+    for (int mm = 0; mm < MB; ++mm) {
+      accM[mm] = fma(w[mm], M, accM[mm]);
+      accR[mm] = fma(fabs(w[mm]), R, accR[mm]);
+    }
+  }
+}
+
+// One thread per output coefficient c (degree Dout); MB output neurons per
+// block row. Block x index runs over output-neuron chunks first so that the
+// blocks reading the same coefficient range of the previous layer run
+// together and share L2. Only the box's live inputs are read: composed
+// neurons' full tensors at c, and the tensors of active, order-1 and
+// fallback neurons, stored at degree Ds = min(Din, Dout), at the position of
+// c's exponents in degree Ds (no term where an exponent exceeds Ds: the
+// lifted tensor is zero there).
 // The weights come from the transposed, zero-padded copy W^T[k][hp]: for one
 // input k the block's MB weights are contiguous and uniform, so they load as
 // a few wide scalar loads and no row guard sits in the inner loop; |w| is the
@@ -78,61 +146,26 @@ __global__ void __launch_bounds__(kBlock) gemm_kernel(GemmArgs a) {
 #pragma unroll
   for (int mm = 0; mm < MB; ++mm) accM[mm] = accR[mm] = 0.0;
   const int mcount = min(MB, a.h - m0);
-  // lanes past the tensor read its last coefficient; their sums are dropped
-  const T *Xc = X + (valid ? c : a.C - 1);
+  const int *lv = a.live + box * a.live_ld;
   const int64_t st = 2 * a.C;
   const double *wt = a.WT + m0;
-  int k = 0;
-  // KU inputs per step, the next step's 2*KU loads issued before this
-  // step's multiply-adds so that they stay in flight across them
-  T u[KU], l[KU];
-  if (KU <= a.hin) {
-#pragma unroll
-    for (int q = 0; q < KU; ++q) {
-      u[q] = Xc[(int64_t)q * st];
-      l[q] = Xc[(int64_t)q * st + a.C];
+  // lanes past the tensor read its last coefficient; their sums are dropped
+  const int64_t cc = valid ? c : a.C - 1;
+  gemm_rows<T, MB, KU>(X + cc, st, a.C, lv + 2, lv[0], true, wt, a.hp, accM, accR);
+  if (lv[1] > 0) {
+    // exponents of c (base Dout+1) -> index at the degree Ds = min(Din,
+    // Dout) those tensors are stored at, or none
+    const int Ds = min(a.Din, a.Dout), Do1 = a.Dout + 1;
+    int64_t rem = cc, mc = 0, pw = 1;
+    bool inside = true;
+    for (int q = 0; q < a.n; ++q) {
+      const int d = (int)(rem % Do1);
+      rem /= Do1;
+      if (d > Ds) inside = false;
+      mc += d * pw;
+      pw *= Ds + 1;
     }
-  }
-  for (; k + KU <= a.hin; k += KU) {
-    T un[KU], ln[KU];
-    const bool more = k + 2 * KU <= a.hin;
-    if (more) {
-#pragma unroll
-      for (int q = 0; q < KU; ++q) {
-        un[q] = Xc[(int64_t)(k + KU + q) * st];
-        ln[q] = Xc[(int64_t)(k + KU + q) * st + a.C];
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < KU; ++q) {
-      const double M = ((double)u[q] + (double)l[q]) * 0.5;
-      const double R = ((double)u[q] - (double)l[q]) * 0.5;
-      const double *w = wt + (int64_t)(k + q) * a.hp;
-#pragma unroll
-      for (int mm = 0; mm < MB; ++mm) {
-        accM[mm] = fma(w[mm], M, accM[mm]);
-        accR[mm] = fma(fabs(w[mm]), R, accR[mm]);
-      }
-    }
-    if (more) {
-#pragma unroll
-      for (int q = 0; q < KU; ++q) {
-        u[q] = un[q];
-        l[q] = ln[q];
-      }
-    }
-  }
-  for (; k < a.hin; ++k) {
-    const double u = (double)Xc[(int64_t)k * st];
-    const double l = (double)Xc[(int64_t)k * st + a.C];
-    const double M = (u + l) * 0.5;
-    const double R = (u - l) * 0.5;
-    const double *w = wt + (int64_t)k * a.hp;
-#pragma unroll
-    for (int mm = 0; mm < MB; ++mm) {
-      accM[mm] = fma(w[mm], M, accM[mm]);
-      accR[mm] = fma(fabs(w[mm]), R, accR[mm]);
-    }
+    gemm_rows<T, MB, KU>(X + (inside ? mc : 0), st, a.C, lv + 2 + a.hin, lv[1], inside, wt, a.hp, accM, accR);
   }
   T *Y = reinterpret_cast<T *>(a.pre) + box * a.slot_out;
   const bool track = a.rpart != nullptr;
@@ -189,7 +222,7 @@ static hipError_t launch_gemm_mb(const GemmArgs &a, hipStream_t s) {
 hipError_t launch_gemm(const GemmArgs &a0, hipStream_t s) {
   GemmArgs a = a0;
   a.cblocks = gemm_cblocks(a.C);
-  if (a.hp % 16 != 0 || a.hp < a.h) return hipErrorInvalidValue;
+  if (a.hp % 16 != 0 || a.hp < a.h || !a.live) return hipErrorInvalidValue;
   ProfScope ps(kProfGemm, s, (double)a.nboxes * (2.0 * a.hin + 2.0 * a.h) * a.C * (a.fp64 ? 8 : 4));
   if (a.h <= 4) return launch_gemm_mb<4, 8>(a, s);
   if (a.h <= 8) return launch_gemm_mb<8, 4>(a, s);

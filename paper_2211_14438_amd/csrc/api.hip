@@ -113,8 +113,8 @@ struct Plan {
   size_t elem;
   std::vector<int64_t> nbx;         // compose blocks per item, hidden layers
   // per-box bytes of each region
-  size_t recs, arenaA, arenaB, conv, horner, flags, gpart, cpart;
-  size_t per_box() const { return 2 * recs + arenaA + arenaB + conv + horner + flags + gpart + cpart; }
+  size_t recs, arenaA, arenaB, conv, horner, flags, gpart, cpart, live;
+  size_t per_box() const { return 2 * recs + arenaA + arenaB + conv + horner + flags + gpart + cpart + live; }
 };
 
 }  // namespace bern
@@ -201,6 +201,7 @@ static bern_status plan_net(const bern_net *net, const bern_opts *o, Plan &p) {
   // per box: validity flag, post degree, one id per (layer, phase) list, and
   // the predicted code of every hidden neuron
   p.flags = align256(sizeof(int) * (2 + 2 * (size_t)p.H) + (size_t)net->nh);
+  p.live = align256(sizeof(int) * (2 + 2 * (size_t)net->hmax));
   return BERN_OK;
 }
 
@@ -426,6 +427,8 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
   void *Bp = cur; cur += p.arenaB * B;
   double *conv = reinterpret_cast<double *>(cur); cur += p.conv * B;
   void *horner = cur; cur += p.horner * B;
+  int *live = reinterpret_cast<int *>(cur); cur += p.live * B;
+  const int64_t live_ld = (int64_t)(p.live / sizeof(int));
   int *flags = reinterpret_cast<int *>(cur);
   int *degs = flags + B;
   int *idlists = flags + 2 * B;  // [H][2][B]
@@ -611,6 +614,8 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       m.scratch_bytes = p.horner * B;
       m.nbx = compose_nbx(n, cl.Din, cl.Dout, m.Cout, p.fp64);
       m.part = p.fp64 ? nullptr : cpart;
+      m.live = live;
+      m.live_ld = live_ld;
       BERN_HIP_TRY(launch_compose(m, s));
       // affine map of the next layer -> pre-activation tensors in arena A
       GemmArgs a{};
@@ -623,6 +628,11 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       a.slot_out = slotA;
       a.post = Bp;
       a.pre = A;
+      a.live = live;
+      a.live_ld = live_ld;
+      a.n = n;
+      a.Din = cl.Din;
+      a.Dout = cl.Dout;
       a.WT = net->WT + net->wtoff[i + 1];
       a.hp = net->hpad[i + 1];
       a.b = net->b64 + net->boff[i + 1];

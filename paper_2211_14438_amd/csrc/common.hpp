@@ -149,6 +149,13 @@ struct GemmArgs {
   int64_t slot_in, slot_out;
   const void *post;               // [B][hin][2][C]
   void *pre;                      // [B][h][2][C]
+  // Per box input lists (null: every input is a full tensor): live[0] full
+  // tensors (composed neurons) at the launch degree, indices at live[2..];
+  // live[1] tensors stored at degree Din (active, order 1, fallback),
+  // indices at live[2 + hin..]. Inactive neurons contribute nothing.
+  const int *live;
+  int64_t live_ld;
+  int n, Din, Dout;                // Dout: degree of the input post tensors (= of C)
   const double *WT;               // [hin][hp]: W transposed, rows h..hp-1 zero
   int hp;                         // h rounded up to a multiple of 16
   const double *b;                // [h]
@@ -208,6 +215,8 @@ struct ComposeArgs {
   int fp64;
   void *scratch;                  // Horner intermediates for orders >= 3
   size_t scratch_bytes;
+  int *live;                      // per box input lists for the next affine map (GemmArgs::live)
+  int64_t live_ld;
 };
 hipError_t launch_compose(const ComposeArgs &a, hipStream_t s);
 // Blocks per item the compose launches of a layer use (partials stride).

@@ -16,9 +16,10 @@
 //    row-by-row convolutions of its (I, K-I) outer pairs in registers.
 //  * order >= 3 (and degrees without a specialised kernel): Horner steps
 //    Q <- nu * Q + c_j, one launch per step, generic runtime degrees.
-//  * order 1, active (identity), inactive (zero) and the linear fallback are
-//    element-wise writes.
-// Every result is written at the layer's post degree Dout (zero padded).
+//  * order 1, active (identity) and the linear fallback are element-wise
+//    writes at the input degree; inactive neurons (zero) store nothing and
+//    are left out of the next affine map's input lists.
+// Composed results are written whole at the layer's post degree Dout.
 //
 // Arithmetic is FP64 for both storage types: with packed FP32 math off, FP32
 // and FP64 FMAs issue at the same rate on gfx950, and FP64 keeps the rounding
@@ -133,7 +134,7 @@ struct SqGeom {
 // exactly zero are flagged while nu is staged (their products add exact
 // zeros, so skipping them leaves every result bit unchanged); output rows whose
 // outer digit sum exceeds twice the largest digit sum of a nonzero row only
-// receive such products and stay as the fill kernel left them (zero).
+// receive such products and are written as zeros without the loop.
 template <typename T, int D, int NI>
 __global__ void __launch_bounds__(kBlock) compose_sq_kernel(ComposeArgs a) {
   using G = SqGeom<D, NI>;
@@ -210,6 +211,20 @@ __global__ void __launch_bounds__(kBlock) compose_sq_kernel(ComposeArgs a) {
     }
     if (dsum > dsmax && !origin) work = false;
   }
+  {
+    // Rows that only receive exact-zero products (or lie past degree 2D) are
+    // zero: written by the whole block with coalesced stores over its
+    // contiguous range of rows.
+    __shared__ unsigned char busy[kBlock];
+    busy[threadIdx.x] = (work || ko >= Mo) ? 1 : 0;
+    __syncthreads();
+    const int64_t ko0 = (int64_t)blockIdx.x * blockDim.x;
+    const int nr = (int)min((int64_t)blockDim.x, Mo - ko0);
+    const unsigned magic = 0xFFFFFFFFu / (unsigned)Rout + 1u;  // e / Rout = umulhi(e, magic) for e < 2^32 / Rout
+    T *base = out_tensor<T>(a, box, j, s) + ko0 * Rout;
+    for (unsigned e = threadIdx.x; e < (unsigned)(nr * Rout); e += blockDim.x)
+      if (!busy[Rout == 1 ? e : __umulhi(e, magic)]) base[e] = (T)0;
+  }
   if (work) {
     double acc[RO];
 #pragma unroll
@@ -281,7 +296,13 @@ __global__ void __launch_bounds__(kBlock) compose_sq_kernel(ComposeArgs a) {
         if (origin && q0 == 0) v += cst;
         store(out + q0, v, rsum, l1sum);
       }
+      for (int q0 = E1; q0 < Do1; ++q0) out[q0] = (T)0;  // layer degree above 2D
     } else {
+      if (Do1 > E1) {
+        for (int q0 = 0; q0 < Do1; ++q0)
+          for (int q1 = 0; q1 < Do1; ++q1)
+            if (q0 >= E1 || q1 >= E1) out[q0 * Do1 + q1] = (T)0;
+      }
 #pragma unroll
       for (int q0 = 0; q0 < E1; ++q0)
 #pragma unroll
@@ -297,32 +318,42 @@ __global__ void __launch_bounds__(kBlock) compose_sq_kernel(ComposeArgs a) {
 }
 
 // ------------------------------------------------- element-wise rules
-// Zero fill of the launch's output tensors before the square kernel and the
-// scatter below write their (sparse) parts. A box's post tensors are one
-// contiguous range at the start of its 256-byte aligned slot, so the fill is
-// plain 16-byte stores over that range (the Horner kernel, for orders >= 3,
-// overwrites its own tensors whole afterwards).
-__global__ void __launch_bounds__(kBlock) compose_fill_kernel(ComposeArgs a, int64_t bytes_per_box, int elem) {
-  const int64_t g = blockIdx.y, box = wave_box(a, g);
-  char *base = reinterpret_cast<char *>(a.post) + box * a.slot_out * elem;
-  const int64_t n16 = bytes_per_box / 16;
-  int4 *v = reinterpret_cast<int4 *>(base);
-  const int4 z = make_int4(0, 0, 0, 0);
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
-    v[i] = z;
-  const int64_t tail = bytes_per_box - n16 * 16;  // multiple of elem
-  if (blockIdx.x == 0 && (int64_t)threadIdx.x * elem < tail) {
-    char *t = base + n16 * 16 + (int64_t)threadIdx.x * elem;
-    if (elem == 8) *reinterpret_cast<double *>(t) = 0.0;
-    else *reinterpret_cast<float *>(t) = 0.0f;
+// Input lists of the next affine map, one wave per box: composed neurons
+// (order >= 2, full tensors at the layer's post degree) and neurons whose
+// post polynomial keeps the pre-activation degree (active, order 1,
+// fallback: tensors stored at degree Din). Inactive neurons are left out.
+__global__ void __launch_bounds__(kBlock) live_kernel(ComposeArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t g = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (g >= a.nboxes) return;
+  const int64_t box = wave_box(a, g);
+  int *lv = a.live + box * a.live_ld;
+  const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  int nf = 0, ns = 0;
+  for (int j0 = 0; j0 < a.h; j0 += 64) {
+    const int j = j0 + lane;
+    const int kind = j < a.h ? a.recs[box * a.h + j].kind : (int)kInactive;
+    const bool full = kind >= 2;
+    const bool small = kind == kActive || kind == 1 || kind == kFallback;
+    const unsigned long long bf = __ballot(full), bs = __ballot(small);
+    if (full) lv[2 + nf + __popcll(bf & below)] = j;
+    if (small) lv[2 + a.h + ns + __popcll(bs & below)] = j;
+    nf += __popcll(bf);
+    ns += __popcll(bs);
+  }
+  if (lane == 0) {
+    lv[0] = nf;
+    lv[1] = ns;
   }
 }
 
-// One block per (box, neuron, bound) of order <= 1: inactive (nothing to
-// add to the zero fill), active (copy of the pre tensor into the larger
-// degree), order 1 (c1 nu + c0, minus e for the lower bound) and the linear
-// fallback (n+1 affine coefficients). Writes the block's rounding and l1 sums
-// to partial slot 0 and zeros to the item's other slots.
+// One block per (box, neuron, bound) whose post polynomial keeps degree Din:
+// active (copy of the pre tensor), order 1 (c1 nu + c0, minus e for the lower
+// bound) and the linear fallback (n+1 affine coefficients), each stored at
+// degree Ds = min(Din, Dout) at the start of its post tensor; the affine map
+// reads them through the degree change of its index. Inactive neurons
+// store nothing. Writes the block's rounding and l1 sums to partial slot 0
+// and zeros to the item's other slots.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) compose_scatter_kernel(ComposeArgs a) {
   const int j = blockIdx.y / a.nbounds, s = blockIdx.y % a.nbounds;
@@ -334,34 +365,32 @@ __global__ void __launch_bounds__(kBlock) compose_scatter_kernel(ComposeArgs a) 
   const int64_t it = item_of(a, g, j, s);
   const T *p = in_tensor<T>(a, box, j, s);
   T *out = out_tensor<T>(a, box, j, s);
-  const int Do1 = a.Dout + 1, Di1 = a.Din + 1;
+  // storage degree: Din, or the layer's post degree when that is lower (only
+  // fallback and inactive neurons then)
+  const int Ds = min(a.Din, a.Dout);
+  int64_t Cs = 1;
+  for (int q = 0; q < a.n; ++q) Cs *= Ds + 1;
   double rsum = 0.0, l1sum = 0.0;
-  if (kind == kActive || kind == 1) {
+  if ((kind == kActive || kind == 1) && Ds == a.Din) {  // these neurons take degree Din <= Dout
     for (int64_t I = threadIdx.x; I < a.Cin; I += blockDim.x) {
-      // position of input index I (base Din+1) in the output (base Dout+1)
-      int64_t rem = I, o = 0, pw = 1;
-      for (int q = a.n - 1; q >= 0; --q) {
-        const int k = (int)(rem % Di1);
-        rem /= Di1;
-        o += (int64_t)k * pw;
-        pw *= Do1;
-      }
       double v = (double)p[I];
       if (kind == 1) {
         if (I == 0) v += ns.shift - ns.lo;
         v = r.c[1] * (v / ns.w);
         if (I == 0) v += r.c[0] - (s == 1 ? r.e : 0.0);
       }
-      store(out + o, v, rsum, l1sum);
+      store(out + I, v, rsum, l1sum);
     }
   } else if (kind == kFallback) {
     const double *fb = (s == 0) ? r.fbU : r.fbL;
-    if (threadIdx.x <= (unsigned)a.n) {
+    for (int64_t I = threadIdx.x; I < Cs; I += blockDim.x) out[I] = (T)0;
+    __syncthreads();
+    if (threadIdx.x <= (unsigned)a.n && (threadIdx.x == 0 || Ds >= 1)) {
       const int q = (int)threadIdx.x;  // 0: constant; 1 + axis: t_axis
       int64_t o = 0;
       if (q > 0) {
         o = 1;
-        for (int t = 0; t < a.n - q; ++t) o *= Do1;  // position of t_(q-1)
+        for (int t = 0; t < a.n - q; ++t) o *= Ds + 1;  // position of t_(q-1)
       }
       store(out + o, fb[q], rsum, l1sum);
     }
@@ -619,13 +648,10 @@ static int sq_dispatch(const ComposeArgs &a, hipStream_t s, hipError_t &err) {
 template <typename T>
 static hipError_t compose_all(const ComposeArgs &a, hipStream_t s) {
   const unsigned gx = (unsigned)a.nbx;
-  {
-    const int64_t bytes = (int64_t)a.h * a.nbounds * a.Cout * (int64_t)sizeof(T);
-    const int64_t per_box_blocks = std::max<int64_t>(1, std::min<int64_t>((bytes / 16 + 4 * kBlock - 1) / (4 * kBlock),
-                                                                          std::max<int64_t>(1, 8192 / a.nboxes)));
-    dim3 grid((unsigned)per_box_blocks, (unsigned)a.nboxes);
-    ProfScope ps(kProfComposeFill, s, (double)bytes * a.nboxes);
-    hipLaunchKernelGGL(compose_fill_kernel, grid, dim3(kBlock), 0, s, a, bytes, (int)sizeof(T));
+  if (a.live) {
+    ProfScope ps(kProfMisc, s, 0.0);
+    hipLaunchKernelGGL(live_kernel, dim3((unsigned)((a.nboxes + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), 0,
+                       s, a);
     RET_IF(hipGetLastError());
   }
   {

@@ -203,10 +203,10 @@ __device__ void padded_bounds(const ConvertArgs &a, int64_t box, int j, double m
 }
 
 // Record of one hidden neuron after its read-off (thread 0 only), then its
-// rule unless a predictor chooses it later.
-__device__ void finish_neuron(const ConvertArgs &a, int64_t box, int j, double lo, double hi, double epsU,
-                              double epsL, double l1U, double l1L, const double (*fit)[kMaxInputs + 1],
-                              const double *ext, bool fitted) {
+// rule unless a predictor chooses it later. Fitted neurons' affine fits are
+// already in the record; the others get zeros.
+__device__ void record_neuron(const ConvertArgs &a, int64_t box, int j, double lo, double hi, double epsU,
+                              double epsL, double l1U, double l1L, const double *ext, bool fitted) {
   NeuronRec &r = a.recs[box * a.h + j];
   r.lo = lo;
   r.hi = hi;
@@ -215,9 +215,8 @@ __device__ void finish_neuron(const ConvertArgs &a, int64_t box, int j, double l
   r.l1U = l1U;
   r.l1L = l1L;
   r.fitted = fitted ? 1 : 0;
-  for (int q = 0; q <= kMaxInputs; ++q) {
-    r.fitU[q] = fitted ? fit[0][q] : 0.0;
-    r.fitL[q] = fitted ? fit[1][q] : 0.0;
+  if (!fitted) {
+    for (int q = 0; q <= kMaxInputs; ++q) r.fitU[q] = r.fitL[q] = 0.0;
   }
   r.rmaxU = fitted ? ext[0] : 0.0;
   r.rminU = fitted ? ext[1] : 0.0;
@@ -227,6 +226,19 @@ __device__ void finish_neuron(const ConvertArgs &a, int64_t box, int j, double l
   const int code = a.plan ? a.plan[box * a.plan_ld + a.plan_col0 + j] : a.L;
   decide_neuron(r, code, a.plan == nullptr, a.L, a.n, a.D, a.cap, a.fp64);
   if (a.used) a.used[box * a.ld_out + a.col0 + j] = (int8_t)r.kind;
+}
+
+__device__ void finish_neuron(const ConvertArgs &a, int64_t box, int j, double lo, double hi, double epsU,
+                              double epsL, double l1U, double l1L, const double (*fit)[kMaxInputs + 1],
+                              const double *ext, bool fitted) {
+  if (fitted) {
+    NeuronRec &r = a.recs[box * a.h + j];
+    for (int q = 0; q <= kMaxInputs; ++q) {
+      r.fitU[q] = fit[0][q];
+      r.fitL[q] = fit[1][q];
+    }
+  }
+  record_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, ext, fitted);
 }
 
 // One block per (box, neuron): both bounds of the neuron, all axes in LDS.
@@ -474,16 +486,16 @@ __device__ void team_axes(double *t, int total, int s0, int na, const Team &tm, 
                           double &mx) {
   constexpr int D1 = D + 1;
   const int F = total / D1;
-  int stride = s0;
+  unsigned stride = (unsigned)s0;
   for (int ax = na - 1; ax >= 0; --ax) {
     tm.sync();
     const bool last = track && ax == 0;
     for (int f = tm.tid; f < F; f += tm.nt) {
-      const int hi = f / stride, lo = f - hi * stride;
-      const int base = hi * stride * D1 + lo;
+      const unsigned hi = (unsigned)f / stride, lo = (unsigned)f - hi * stride;
+      const int base = (int)(hi * stride * D1 + lo);
       double x[D1];
 #pragma unroll
-      for (int j = 0; j < D1; ++j) x[j] = t[base + j * stride];
+      for (int j = 0; j < D1; ++j) x[j] = t[base + j * (int)stride];
       to_bern<D>(x);
 #pragma unroll
       for (int j = 0; j < D1; ++j) {
@@ -491,7 +503,7 @@ __device__ void team_axes(double *t, int total, int s0, int na, const Team &tm, 
           mn = fmin(mn, x[j]);
           mx = fmax(mx, x[j]);
         }
-        t[base + j * stride] = x[j];
+        t[base + j * (int)stride] = x[j];
       }
     }
     stride *= D1;
@@ -505,23 +517,39 @@ template <int D, typename T, class Team>
 __device__ void team_convert(double *t, const T *p, int C, int n, const Team &tm, double &l1, double &vmin,
                              double &vmax) {
   constexpr int D1 = D + 1;
+  constexpr int NR = 24 / D1 > 0 ? 24 / D1 : 1;  // fibres per thread whose loads are in flight together
   const int F = C / D1;
   double s = 0.0, mn = INFINITY, mx = -INFINITY;
-  for (int f = tm.tid; f < F; f += tm.nt) {
-    double x[D1];
+  for (int f0 = tm.tid; f0 < F; f0 += NR * tm.nt) {
+    T r[NR][D1];
 #pragma unroll
-    for (int j = 0; j < D1; ++j) {
-      x[j] = (double)p[f * D1 + j];
-      s += fabs(x[j]);
-    }
-    to_bern<D>(x);
+    for (int u = 0; u < NR; ++u) {
+      const int f = f0 + u * tm.nt;
+      if (f < F) {
 #pragma unroll
-    for (int j = 0; j < D1; ++j) {
-      if (n == 1) {
-        mn = fmin(mn, x[j]);
-        mx = fmax(mx, x[j]);
+        for (int j = 0; j < D1; ++j) r[u][j] = p[f * D1 + j];
       }
-      t[f * D1 + j] = x[j];
+    }
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+      const int f = f0 + u * tm.nt;
+      if (f < F) {
+        double x[D1];
+#pragma unroll
+        for (int j = 0; j < D1; ++j) {
+          x[j] = (double)r[u][j];
+          s += fabs(x[j]);
+        }
+        to_bern<D>(x);
+#pragma unroll
+        for (int j = 0; j < D1; ++j) {
+          if (n == 1) {
+            mn = fmin(mn, x[j]);
+            mx = fmax(mx, x[j]);
+          }
+          t[f * D1 + j] = x[j];
+        }
+      }
     }
   }
   team_axes<D>(t, C, D1, n - 1, tm, true, mn, mx);
@@ -533,8 +561,11 @@ __device__ void team_convert(double *t, const T *p, int C, int n, const Team &tm
 // Affine least-squares fit of the control net and its remainder range (same
 // quantities as lds_affine_fit), reading fibres along the fastest axis so
 // the other axes' digits are found once per fibre with constant divisors.
+// Thread 0 writes beta (mean, then the slope of every axis) to `beta_out`;
+// every thread gets the remainder extrema.
 template <int D, class Team>
-__device__ void team_fit(const double *t, int C, int n, const Team &tm, double *beta, double &rmax, double &rmin) {
+__device__ void team_fit(const double *t, int C, int n, const Team &tm, double *beta_out, double &rmax,
+                         double &rmin) {
   constexpr int D1 = D + 1;
   const int F = C / D1;
   double m = 0.0, pl = 0.0, p[kMaxInputs - 1];
@@ -564,24 +595,30 @@ __device__ void team_fit(const double *t, int C, int n, const Team &tm, double *
 #pragma unroll
   for (int k = 0; k <= D; ++k) s1 += ((double)k / D - 0.5) * ((double)k / D - 0.5);
   const double ss = s1 * (double)F;
-  beta[0] = tm.sum(m) / (double)C;
+  const double b0 = tm.sum(m) / (double)C;
+  const double bl = tm.sum(pl) / ss;  // slope along the last axis
+  double bs[kMaxInputs - 1];          // slopes along axes 0..n-2
 #pragma unroll
-  for (int a = 0; a < kMaxInputs; ++a) {
-    if (a < n) beta[1 + a] = tm.sum(a < n - 1 ? p[a < kMaxInputs - 1 ? a : 0] : pl) / ss;
+  for (int a = 0; a < kMaxInputs - 1; ++a) bs[a] = (a <= n - 2) ? tm.sum(p[a]) / ss : 0.0;
+  if (tm.tid == 0) {
+    beta_out[0] = b0;
+#pragma unroll
+    for (int a = 0; a < kMaxInputs - 1; ++a)
+      if (a <= n - 2) beta_out[1 + a] = bs[a];
+    beta_out[n] = bl;
   }
   double hi = -INFINITY, lo = INFINITY;
   for (int f = tm.tid; f < F; f += tm.nt) {
-    double lf = beta[0];
+    double lf = b0;
     int q = f;
 #pragma unroll
     for (int a = kMaxInputs - 2; a >= 0; --a) {
       if (a <= n - 2) {
         const int d = q % D1;
         q /= D1;
-        lf = fma(beta[1 + a], (double)d / D - 0.5, lf);
+        lf = fma(bs[a], (double)d / D - 0.5, lf);
       }
     }
-    const double bl = beta[n];
 #pragma unroll
     for (int k = 0; k < D1; ++k) {
       const double r = t[f * D1 + k] - fma(bl, (double)k / D - 0.5, lf);
@@ -609,15 +646,14 @@ __device__ inline bool wants_fit(const ConvertArgs &a, int64_t box, int j) {
 }
 
 __device__ inline void write_neuron(const ConvertArgs &a, int64_t box, int j, double lo, double hi, double epsU,
-                                    double epsL, double l1U, double l1L, const double (*fit)[kMaxInputs + 1],
-                                    const double *ext, bool fitted) {
+                                    double epsL, double l1U, double l1L, const double *ext, bool fitted) {
   if (a.mode == 1) {
     a.out_lo[box * a.ld_out + a.col0 + j] = lo;
     a.out_hi[box * a.ld_out + a.col0 + j] = hi;
   } else {
     if (a.out_lo) a.out_lo[box * a.ld_out + a.col0 + j] = lo;
     if (a.out_hi) a.out_hi[box * a.ld_out + a.col0 + j] = hi;
-    finish_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fit, ext, fitted);
+    record_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, ext, fitted);
   }
 }
 
@@ -641,12 +677,13 @@ __global__ void __launch_bounds__(kBlock) convert_wave_t(ConvertArgs a) {
   if (!a.fp64) pre_radii(a, box, j, a.pre, tm.tid, 64, [&](double v) { return tm.sum(v); }, epsU, epsL);
   const double lo = side_lo(a, mn, l1L, epsL), hi = side_hi(a, mx, l1U, epsU);
   const bool fitted = wants_fit(a, box, j) && (a.fits || (lo < 0.0 && hi > 0.0));
-  double fit[2][kMaxInputs + 1], fx[4] = {0.0, 0.0, 0.0, 0.0};
+  double fx[4] = {0.0, 0.0, 0.0, 0.0};
   if (fitted) {
-    team_fit<D>(tw + C, C, a.n, tm, fit[0], fx[0], fx[1]);  // upper
-    team_fit<D>(tw, C, a.n, tm, fit[1], fx[2], fx[3]);      // lower
+    NeuronRec &r = a.recs[box * a.h + j];
+    team_fit<D>(tw + C, C, a.n, tm, r.fitU, fx[0], fx[1]);  // upper
+    team_fit<D>(tw, C, a.n, tm, r.fitL, fx[2], fx[3]);      // lower
   }
-  if (tm.tid == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fit, fx, fitted);
+  if (tm.tid == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted);
 }
 
 // One block per (box, neuron) for tensors up to kSmallLds coefficients, one
@@ -667,17 +704,18 @@ __global__ void __launch_bounds__(1024) convert_block_t(ConvertArgs a) {
   double epsU = 0.0, epsL = 0.0;
   if (!a.fp64) pre_radii(a, box, j, a.pre, tm.tid, tm.nt, [&](double v) { return tm.sum(v); }, epsU, epsL);
   const bool want = wants_fit(a, box, j);
-  double fit[2][kMaxInputs + 1], fx[4] = {0.0, 0.0, 0.0, 0.0};
+  NeuronRec *rec = want ? &a.recs[box * a.h + j] : nullptr;
+  double fx[4] = {0.0, 0.0, 0.0, 0.0};
   double l1L, l1U, mn, mx, dummy;
   team_convert<D>(t, p + a.C, C, a.n, tm, l1L, mn, dummy);
   const double lo = side_lo(a, mn, l1L, epsL);
-  if (want && (a.fits || lo < 0.0)) team_fit<D>(t, C, a.n, tm, fit[1], fx[2], fx[3]);
+  if (want && (a.fits || lo < 0.0)) team_fit<D>(t, C, a.n, tm, rec->fitL, fx[2], fx[3]);
   tm.sync();
   team_convert<D>(t, p, C, a.n, tm, l1U, dummy, mx);
   const double hi = side_hi(a, mx, l1U, epsU);
   const bool fitted = want && (a.fits || (lo < 0.0 && hi > 0.0));
-  if (fitted) team_fit<D>(t, C, a.n, tm, fit[0], fx[0], fx[1]);
-  if (tm.tid == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fit, fx, fitted);
+  if (fitted) team_fit<D>(t, C, a.n, tm, rec->fitU, fx[0], fx[1]);
+  if (tm.tid == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted);
 }
 
 template <typename T, int D>
