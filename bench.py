@@ -99,6 +99,47 @@ def cpu_baseline(case, budget_s=10.0):
                        f"in {dt:.1f} s, FP64 Bernstein-literal oracle")
 
 
+def measured_traffic(workload, cls):
+    """HBM bytes per launch of kernel class `cls` on `workload`, from the
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary under profiles/ (scaled by the
+    copy calibration recorded there), or None when there is none or when the
+    kernel sources have changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{workload}.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if not line.startswith("TRAFFIC "):
+            continue
+        rec = json.loads(line[len("TRAFFIC "):])
+        if rec.get("class") != cls:
+            continue
+        h = hashlib.sha256()
+        for f in rec["sources"]:
+            with open(os.path.join(ROOT, "paper_2211_14438_amd", "csrc", f), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest()[:16] != rec["source_sha256_16"]:
+            return None
+        return rec["hbm_bytes_per_launch"]
+    return None
+
+
+def copy_calibration(torch, nbytes=1 << 30, reps=5):
+    """A plain device-to-device copy of `nbytes` bytes, `reps` times: the
+    HBM byte counters read on it give the factor between counted and moved
+    bytes (it moves 2 * nbytes per launch: one read, one write)."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": reps,
+                      "GB_per_s": 2 * nbytes / dt / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,13 +149,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-plain", action="store_true", help="do not time the plain form (profiling runs)")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only time a plain device copy of 1 GiB (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: the boxes of a workload are independent and this build "
-              "measures one GPU's share; --gpus N > 1 is not supported", file=sys.stderr)
+        print("bench.py runs on one GPU only: the boxes of a workload are independent, so one GPU's share "
+              "is what is measured; --gpus N > 1 is not supported", file=sys.stderr)
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
     from paper_2211_14438_amd import bernnn as B
     from paper_2211_14438_amd import workloads as wl
 
@@ -191,12 +237,12 @@ def main():
         flops = composed_flops(case, used, case.L, plain=spec["form"] == "plain") * args.steps
         achieved = flops / (ms * 1e-3) / 1e12
         roof = dict(bound="alu", achieved=achieved, peak=PEAK_VALU_TFLOPS, unit="TFLOP/s",
-                    frac=achieved / PEAK_VALU_TFLOPS, traffic=None, kernel=dom,
+                    frac=achieved / PEAK_VALU_TFLOPS, traffic=measured_traffic(case.name, dom), kernel=dom,
                     per_launch_flops=flops / launches, avg_launch_us=ms / launches * 1e3)
     else:
         achieved = by / (ms * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s", frac=achieved / PEAK_HBM_GBS,
-                    traffic=None, kernel=dom, per_launch_bytes=by / launches, avg_launch_us=ms / launches * 1e3)
+                    traffic=measured_traffic(case.name, dom), kernel=dom, per_launch_bytes=by / launches, avg_launch_us=ms / launches * 1e3)
 
     line = {
         "metric": METRIC,
