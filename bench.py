@@ -149,6 +149,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-plain", action="store_true", help="do not time the plain form (profiling runs)")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the built-in kernel variants")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay the plain rule's launch sequence as one captured graph")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only time a plain device copy of 1 GiB (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -185,7 +188,16 @@ def main():
         kw["workspace"] = torch.empty(size + 256, dtype=torch.uint8, device=dev)
         r = B.bounds(net, lo, hi, **kw)
         kw["outputs"] = {k: r[k] for k in ("neuron_lo", "neuron_hi", "out_lo", "out_hi", "used_plan")}
+        if form == "plain" and sched == "batched" and args.graph:
+            kw["graph"] = True
         return kw
+
+    def autotune(kw):
+        # one-time setup, outside the timed region: kernel variants for this net and workload
+        tkw = {k: v for k, v in kw.items() if k not in ("graph",)}
+        t0 = time.perf_counter()
+        choice, tms = B.autotune(net, lo, hi, reps=2, **tkw)
+        return dict(choice=choice, seconds=time.perf_counter() - t0, ms_per_pass=tms)
 
     def timed(kw, steps, profile):
         for _ in range(args.warmup):
@@ -208,7 +220,13 @@ def main():
         return dt, prof
 
     kw = setup(spec["form"], spec["sched"])
-    dt, prof = timed(kw, args.steps, True)
+    tuned = None if args.no_autotune else autotune(kw)
+    graph = bool(kw.get("graph"))
+    dt, prof = timed(kw, args.steps, not graph)
+    if graph:
+        # a captured sequence carries no per-kernel timing events: the kernel
+        # classes are timed on the same sequence launched eagerly, right after
+        _, prof = timed({k: v for k, v in kw.items() if k != "graph"}, args.steps, True)
     outs = kw["outputs"]
     ms_step = dt / args.steps * 1e3
     neurons = case.n_boxes * case.bounded_neurons_per_box
@@ -264,6 +282,10 @@ def main():
         "roofline": roof,
         "kernels": kernels,
     }
+    if tuned is not None:
+        line["autotune"] = tuned
+    if graph:
+        line["launch"] = "one captured graph per pass (kernel classes timed on eager launches of the same sequence)"
     if plain_line is not None:
         line["plain"] = plain_line
         line["speedup_vs_plain"] = value / plain_line["value"]

@@ -79,7 +79,8 @@ typedef enum {
 
 typedef enum {
   BERN_SCHED_PER_BOX = 0, /* one launch sequence per box (the plain form)            */
-  BERN_SCHED_BATCHED = 1  /* all boxes of a wave in one captured HIP graph launch    */
+  BERN_SCHED_BATCHED = 1  /* as many boxes per launch sequence (wave) as the
+                             workspace holds; with opts.graph, one graph launch     */
 } bern_sched;
 
 typedef struct bern_net bern_net;   /* opaque: network on the device               */
@@ -96,7 +97,10 @@ typedef struct {
                          predictor's input features of every hidden neuron
                          (written in every plan mode; for training records)      */
   int32_t max_wave;   /* upper limit on boxes per wave (0 = as many as fit)         */
-  int32_t reserved[7];
+  int32_t graph;      /* nonzero: runs with no host round trip (BERN_PLAN_PLAIN) are
+                         captured once per distinct argument set into a HIP graph
+                         and replayed as one graph launch; other plans run eagerly */
+  int32_t reserved[6];
 } bern_opts;
 
 typedef struct {
@@ -161,6 +165,34 @@ bern_status bern_bounds(const bern_net *net, const bern_opts *opts, int64_t n_bo
                         double *neuron_lo, double *neuron_hi, double *out_lo, double *out_hi,
                         int8_t *used_plan, void *workspace, size_t ws_bytes, void *stream,
                         bern_stats *stats);
+
+/* Kernel variants and their autotuner (the box-batch scheduler's tile
+ * choices; not in the paper). The library has kTune = bern_tune_params()
+ * tuning parameters, parameter q having bern_tune_variants(q) variants
+ * (0 = the built-in choice): 0 rows per block and inputs per step of the
+ * affine kernel for layers wider than 8 neurons, 1 the same for layers of at
+ * most 4 neurons, 2 threads of the block-per-neuron conversion, 3 whether
+ * tensors of at most 1024 coefficients are converted one wave or one block
+ * per neuron. The choice is stored in the network handle and used by every
+ * later call on it; every variant computes the same bounds up to the order
+ * of floating-point sums.
+ *   bern_tune_get / bern_tune_set -- read / write `choice` (host,
+ *     [bern_tune_params()] ints); set rejects out-of-range variants.
+ *   bern_autotune -- takes the arguments of bern_bounds plus `reps`; for
+ *     each parameter in turn it times reps runs of bern_bounds under every
+ *     variant (the others at their current choice) and keeps the fastest.
+ *     Synchronous: it waits for `stream`. On return `choice` (host, nullable)
+ *     holds the chosen variants and `best_ms` (host, nullable) the mean time
+ *     of one run under them; the outputs hold the last run's results. Not
+ *     thread-safe with other calls on the same network. */
+int32_t bern_tune_params(void);
+int32_t bern_tune_variants(int32_t param);
+bern_status bern_tune_get(const bern_net *net, int32_t *choice);
+bern_status bern_tune_set(bern_net *net, const int32_t *choice);
+bern_status bern_autotune(bern_net *net, const bern_opts *opts, int64_t n_boxes, const double *box_lo,
+                          const double *box_hi, const int8_t *plan, double *neuron_lo, double *neuron_hi,
+                          double *out_lo, double *out_hi, int8_t *used_plan, void *workspace,
+                          size_t ws_bytes, void *stream, int32_t reps, int32_t *choice, float *best_ms);
 
 /* Step-level entry points. Each runs one kernel of the hot path on
  * caller-provided device buffers, asynchronously on `stream`; the tests use

@@ -29,7 +29,7 @@ _vp = ctypes.c_void_p
 class bern_opts(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("precision", ctypes.c_int32), ("plan", ctypes.c_int32),
                 ("sched", ctypes.c_int32), ("pred", ctypes.c_void_p), ("features", ctypes.c_void_p),
-                ("max_wave", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("max_wave", ctypes.c_int32), ("graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
 class bern_stats(ctypes.Structure):
@@ -111,6 +111,17 @@ def lib():
     L.bern_mlp_adam.restype = i32
     L.bern_mlp_adam.argtypes = [_vp, _vp, _vp, _vp, i64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float, _vp]
+    L.bern_tune_params.restype = i32
+    L.bern_tune_params.argtypes = []
+    L.bern_tune_variants.restype = i32
+    L.bern_tune_variants.argtypes = [i32]
+    L.bern_tune_get.restype = i32
+    L.bern_tune_get.argtypes = [_vp, ctypes.POINTER(i32)]
+    L.bern_tune_set.restype = i32
+    L.bern_tune_set.argtypes = [_vp, ctypes.POINTER(i32)]
+    L.bern_autotune.restype = i32
+    L.bern_autotune.argtypes = [_vp, ctypes.POINTER(bern_opts), i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                sz, _vp, i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float)]
     L.bern_mlp_classify.restype = i32
     L.bern_mlp_classify.argtypes = [_vp, i64, _vp, _vp, _vp, i32, _vp]
     _LIB = L
@@ -122,7 +133,8 @@ EXPORTED = ("bern_opts_default", "bern_net_create", "bern_net_destroy", "bern_ne
             "bern_basis_minmax", "bern_poly_mul", "bern_relu_poly", "bern_status_str", "bern_last_error",
             "bern_prof_enable", "bern_prof_reset", "bern_prof_classes", "bern_prof_name", "bern_prof_read",
             "bern_pred_params", "bern_pred_create", "bern_pred_destroy", "bern_mlp_backward_scratch",
-            "bern_mlp_forward", "bern_mlp_backward", "bern_mlp_adam", "bern_mlp_classify")
+            "bern_mlp_forward", "bern_mlp_backward", "bern_mlp_adam", "bern_mlp_classify", "bern_tune_params",
+            "bern_tune_variants", "bern_tune_get", "bern_tune_set", "bern_autotune")
 
 
 def status_str(s):
@@ -145,7 +157,8 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def make_opts(L=2, precision="fp64", plan="plain", sched="per_box", max_wave=0, pred=None, features=None):
+def make_opts(L=2, precision="fp64", plan="plain", sched="per_box", max_wave=0, pred=None, features=None,
+              graph=False):
     o = bern_opts()
     lib().bern_opts_default(ctypes.byref(o))
     o.L = int(L)
@@ -155,6 +168,7 @@ def make_opts(L=2, precision="fp64", plan="plain", sched="per_box", max_wave=0, 
     o.max_wave = int(max_wave)
     o.pred = None if pred is None else (pred.handle if isinstance(pred, Predictor) else pred)
     o.features = None if features is None else features.data_ptr()
+    o.graph = 1 if graph else 0
     return o
 
 
@@ -255,18 +269,16 @@ class Net:
         return total.value, one.value
 
 
-def bounds(net, box_lo, box_hi, L=2, precision="fp64", plan="plain", sched="per_box", degree_plan=None,
-           max_wave=0, workspace=None, stream=None, outputs=None, pred=None, features=None):
-    """Bounds of every box. ``box_lo``/``box_hi``: float64 CUDA tensors
-    [n_boxes, n]. Returns a dict of CUDA tensors (neuron_lo/hi, out_lo/hi,
-    used_plan) plus the run statistics. Asynchronous on ``stream``."""
+def _prepare(net, box_lo, box_hi, L, precision, plan, sched, degree_plan, max_wave, workspace, outputs, pred,
+             features, graph):
     import torch
     dev = box_lo.device
     assert box_lo.dtype == torch.float64 and box_hi.dtype == torch.float64
     box_lo = box_lo.contiguous()
     box_hi = box_hi.contiguous()
     nb = box_lo.shape[0]
-    o = make_opts(L=L, precision=precision, plan=plan, sched=sched, max_wave=max_wave, pred=pred, features=features)
+    o = make_opts(L=L, precision=precision, plan=plan, sched=sched, max_wave=max_wave, pred=pred, features=features,
+                  graph=graph)
     if outputs is None:
         nh = max(net.n_hidden, 1)
         outputs = dict(
@@ -283,18 +295,62 @@ def bounds(net, box_lo, box_hi, L=2, precision="fp64", plan="plain", sched="per_
     ws_ptr = workspace.data_ptr()
     pad = (-ws_ptr) % 256
     ws_bytes = workspace.numel() - pad
-    st = bern_stats()
     if degree_plan is not None:
         degree_plan = degree_plan.contiguous()
-    _check(lib().bern_bounds(net.handle, ctypes.byref(o), nb, _ptr(box_lo), _ptr(box_hi), _ptr(degree_plan),
-                             _ptr(outputs["neuron_lo"]), _ptr(outputs["neuron_hi"]), _ptr(outputs["out_lo"]),
-                             _ptr(outputs["out_hi"]), _ptr(outputs.get("used_plan")), ctypes.c_void_p(ws_ptr + pad),
-                             ws_bytes, _stream(stream), ctypes.byref(st)))
-    res = dict(outputs)
+    args = [net.handle, ctypes.byref(o), nb, _ptr(box_lo), _ptr(box_hi), _ptr(degree_plan),
+            _ptr(outputs["neuron_lo"]), _ptr(outputs["neuron_hi"]), _ptr(outputs["out_lo"]), _ptr(outputs["out_hi"]),
+            _ptr(outputs.get("used_plan")), ctypes.c_void_p(ws_ptr + pad), ws_bytes]
+    # keep the tensors the pointers refer to alive for the call
+    return args, dict(outputs), workspace, (o, box_lo, box_hi, degree_plan)
+
+
+def bounds(net, box_lo, box_hi, L=2, precision="fp64", plan="plain", sched="per_box", degree_plan=None,
+           max_wave=0, workspace=None, stream=None, outputs=None, pred=None, features=None, graph=False):
+    """Bounds of every box. ``box_lo``/``box_hi``: float64 CUDA tensors
+    [n_boxes, n]. Returns a dict of CUDA tensors (neuron_lo/hi, out_lo/hi,
+    used_plan) plus the run statistics. Asynchronous on ``stream``. With
+    ``graph`` the plain rule's launch sequence is captured once and replayed
+    as one graph launch."""
+    args, res, workspace, keep = _prepare(net, box_lo, box_hi, L, precision, plan, sched, degree_plan, max_wave,
+                                          workspace, outputs, pred, features, graph)
+    st = bern_stats()
+    _check(lib().bern_bounds(*args, _stream(stream), ctypes.byref(st)))
     res["stats"] = dict(n_waves=st.n_waves, boxes_per_wave=st.boxes_per_wave, out_degree=st.out_degree,
                         workspace_used=st.workspace_used)
     res["workspace"] = workspace
     return res
+
+
+def autotune(net, box_lo, box_hi, reps=3, L=2, precision="fp64", plan="plain", sched="batched", degree_plan=None,
+             max_wave=0, workspace=None, stream=None, outputs=None, pred=None):
+    """Pick the fastest kernel variants for this network and workload (stored
+    in the network handle). Returns (choice list, mean ms per run)."""
+    args, res, workspace, keep = _prepare(net, box_lo, box_hi, L, precision, plan, sched, degree_plan, max_wave,
+                                          workspace, outputs, pred, None, False)
+    L_ = lib()
+    k = L_.bern_tune_params()
+    choice = (ctypes.c_int32 * k)()
+    ms = ctypes.c_float()
+    _check(L_.bern_autotune(*args, _stream(stream), int(reps), choice, ctypes.byref(ms)))
+    return list(choice), ms.value
+
+
+def tune_get(net):
+    L_ = lib()
+    choice = (ctypes.c_int32 * L_.bern_tune_params())()
+    _check(L_.bern_tune_get(net.handle, choice))
+    return list(choice)
+
+
+def tune_set(net, choice):
+    L_ = lib()
+    c = (ctypes.c_int32 * L_.bern_tune_params())(*[int(v) for v in choice])
+    _check(L_.bern_tune_set(net.handle, c))
+
+
+def tune_variants():
+    L_ = lib()
+    return [L_.bern_tune_variants(q) for q in range(L_.bern_tune_params())]
 
 
 def prof_enable(on=True):

@@ -224,9 +224,20 @@ hipError_t launch_gemm(const GemmArgs &a0, hipStream_t s) {
   a.cblocks = gemm_cblocks(a.C);
   if (a.hp % 16 != 0 || a.hp < a.h || !a.live) return hipErrorInvalidValue;
   ProfScope ps(kProfGemm, s, (double)a.nboxes * (2.0 * a.hin + 2.0 * a.h) * a.C * (a.fp64 ? 8 : 4));
-  if (a.h <= 4) return launch_gemm_mb<4, 8>(a, s);
+  if (a.h <= 4) {
+    switch (a.tune.gemm_narrow) {
+      case 1: return launch_gemm_mb<4, 4>(a, s);
+      case 2: return launch_gemm_mb<4, 16>(a, s);
+      default: return launch_gemm_mb<4, 8>(a, s);
+    }
+  }
   if (a.h <= 8) return launch_gemm_mb<8, 4>(a, s);
-  return launch_gemm_mb<16, 2>(a, s);
+  switch (a.tune.gemm_wide) {
+    case 1: return launch_gemm_mb<16, 4>(a, s);
+    case 2: return launch_gemm_mb<8, 2>(a, s);
+    case 3: return launch_gemm_mb<8, 4>(a, s);
+    default: return launch_gemm_mb<16, 2>(a, s);
+  }
 }
 
 }  // namespace bern

@@ -129,6 +129,15 @@ struct bern_net {
   std::vector<int> hpad;
   double *sens = nullptr;  // [nh] downstream sensitivity of every hidden neuron
   int device = 0;
+  bern::Tune tune;         // kernel variants (autotuner)
+  // captured launch sequences of sync-free runs, keyed by every argument
+  struct GraphEntry {
+    std::vector<uint64_t> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::vector<GraphEntry> graphs;
+  hipStream_t capture = nullptr;  // stream the sequences are captured on
 };
 
 struct bern_pred {
@@ -327,6 +336,11 @@ void bern_net_destroy(bern_net *net) {
   (void)hipFree(net->b64);
   (void)hipFree(net->sens);
   (void)hipFree(net->WT);
+  for (auto &g : net->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
+  if (net->capture) (void)hipStreamDestroy(net->capture);
   delete net;
 }
 
@@ -516,6 +530,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       c.rpart = gpart;
       c.rpart_slot = (int64_t)(p.gpart / sizeof(double));
       c.cblocks = gemm_cblocks(c.C);
+      c.tune = net->tune;
       c.plan_ld = net->nh;
       c.plan_col0 = last ? 0 : net->noff[i];
       if (last) {
@@ -633,6 +648,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       a.n = n;
       a.Din = cl.Din;
       a.Dout = cl.Dout;
+      a.tune = net->tune;
       a.WT = net->WT + net->wtoff[i + 1];
       a.hp = net->hpad[i + 1];
       a.b = net->b64 + net->boff[i + 1];
@@ -659,6 +675,57 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
                        nlo, nhi, olo, ohi);
   }
   BERN_HIP_TRY(hipGetLastError());
+  return BERN_OK;
+}
+
+// Capture the launch sequence `run` once per distinct argument set on the
+// network's own capture stream, then replay it on `s` as one graph launch.
+template <typename Run>
+static bern_status run_graph(bern_net *net, const bern_opts *o, int64_t n_boxes, std::vector<uint64_t> key,
+                             Run &run, hipStream_t s) {
+  key.push_back((uint64_t)n_boxes);
+  key.push_back((uint64_t)o->L);
+  key.push_back((uint64_t)o->precision);
+  key.push_back((uint64_t)o->sched);
+  key.push_back((uint64_t)o->max_wave);
+  key.push_back((uint64_t)(uintptr_t)o->features);
+  key.push_back((uint64_t)net->tune.gemm_wide | (uint64_t)net->tune.gemm_narrow << 8 |
+                (uint64_t)net->tune.conv_block << 16 | (uint64_t)net->tune.conv_wave << 24);
+  int dev = 0;
+  BERN_HIP_TRY(hipGetDevice(&dev));
+  key.push_back((uint64_t)dev);
+  for (auto &g : net->graphs) {
+    if (g.key == key) {
+      BERN_HIP_TRY(hipGraphLaunch(g.exec, s));
+      return BERN_OK;
+    }
+  }
+  if (!net->capture) BERN_HIP_TRY(hipStreamCreateWithFlags(&net->capture, hipStreamNonBlocking));
+  const bool prof = g_prof_on;
+  g_prof_on = false;  // no timing events inside a captured sequence
+  BERN_HIP_TRY(hipStreamBeginCapture(net->capture, hipStreamCaptureModeRelaxed));
+  bern_status st = run(net->capture);
+  hipGraph_t graph = nullptr;
+  const hipError_t ce = hipStreamEndCapture(net->capture, &graph);
+  g_prof_on = prof;
+  if (st != BERN_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  BERN_HIP_TRY(ce);
+  hipGraphExec_t exec = nullptr;
+  if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    set_error("graph instantiation failed");
+    return BERN_E_DEVICE;
+  }
+  if (net->graphs.size() >= 8) {  // keep the most recent few
+    (void)hipGraphExecDestroy(net->graphs.front().exec);
+    (void)hipGraphDestroy(net->graphs.front().graph);
+    net->graphs.erase(net->graphs.begin());
+  }
+  net->graphs.push_back({key, graph, exec});
+  BERN_HIP_TRY(hipGraphLaunch(exec, s));
   return BERN_OK;
 }
 
@@ -693,16 +760,33 @@ extern "C" bern_status bern_bounds(const bern_net *net, const bern_opts *opts, i
   if (opts->max_wave > 0) wave = std::min<int64_t>(wave, opts->max_wave);
   wave = std::min<int64_t>(wave, std::min<int64_t>(n_boxes, 65535));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  int nwaves = 0;
-  for (int64_t b0 = 0; b0 < n_boxes; b0 += wave) {
-    const int64_t B = std::min<int64_t>(wave, n_boxes - b0);
-    st = run_wave(net, p, opts, b0, B, box_lo + b0 * net->n, box_hi + b0 * net->n,
-                  plan ? plan + b0 * net->nh : nullptr, neuron_lo ? neuron_lo + b0 * net->nh : nullptr,
-                  neuron_hi ? neuron_hi + b0 * net->nh : nullptr, out_lo + b0 * net->o, out_hi + b0 * net->o,
-                  used_plan ? used_plan + b0 * net->nh : nullptr, reinterpret_cast<char *>(workspace), s);
-    if (st != BERN_OK) return st;
-    ++nwaves;
+  const int nwaves = (int)((n_boxes + wave - 1) / wave);
+  auto run_all = [&](hipStream_t rs) -> bern_status {
+    for (int64_t b0 = 0; b0 < n_boxes; b0 += wave) {
+      const int64_t B = std::min<int64_t>(wave, n_boxes - b0);
+      bern_status r = run_wave(net, p, opts, b0, B, box_lo + b0 * net->n, box_hi + b0 * net->n,
+                               plan ? plan + b0 * net->nh : nullptr, neuron_lo ? neuron_lo + b0 * net->nh : nullptr,
+                               neuron_hi ? neuron_hi + b0 * net->nh : nullptr, out_lo + b0 * net->o,
+                               out_hi + b0 * net->o, used_plan ? used_plan + b0 * net->nh : nullptr,
+                               reinterpret_cast<char *>(workspace), rs);
+      if (r != BERN_OK) return r;
+    }
+    return BERN_OK;
+  };
+  // Runs with no host round trip (the plain rule) can be captured once and
+  // replayed as one graph launch; plans with per-neuron degrees read every
+  // box's degree back once per hidden layer and always run eagerly.
+  if (opts->graph && p.mode == BERN_PLAN_PLAIN) {
+    st = run_graph(const_cast<bern_net *>(net), opts, n_boxes,
+                   {(uint64_t)(uintptr_t)box_lo, (uint64_t)(uintptr_t)box_hi, (uint64_t)(uintptr_t)neuron_lo,
+                    (uint64_t)(uintptr_t)neuron_hi, (uint64_t)(uintptr_t)out_lo, (uint64_t)(uintptr_t)out_hi,
+                    (uint64_t)(uintptr_t)used_plan, (uint64_t)(uintptr_t)workspace, (uint64_t)ws_bytes,
+                    (uint64_t)wave},
+                   run_all, s);
+  } else {
+    st = run_all(s);
   }
+  if (st != BERN_OK) return st;
   if (stats) {
     memset(stats, 0, sizeof(*stats));
     stats->n_waves = nwaves;
@@ -710,6 +794,108 @@ extern "C" bern_status bern_bounds(const bern_net *net, const bern_opts *opts, i
     stats->out_degree = p.Dpre[p.H - 1];
     stats->workspace_used = per_box * (size_t)wave;
   }
+  return BERN_OK;
+}
+
+// --------------------------------------------------------------- autotuner
+static void tune_to(const Tune &t, int32_t *v) {
+  v[0] = t.gemm_wide;
+  v[1] = t.gemm_narrow;
+  v[2] = t.conv_block;
+  v[3] = t.conv_wave;
+}
+static void tune_from(const int32_t *v, Tune &t) {
+  t.gemm_wide = v[0];
+  t.gemm_narrow = v[1];
+  t.conv_block = v[2];
+  t.conv_wave = v[3];
+}
+
+extern "C" int32_t bern_tune_params(void) { return kTuneParams; }
+
+extern "C" int32_t bern_tune_variants(int32_t param) {
+  return (param >= 0 && param < kTuneParams) ? kTuneVariants[param] : 0;
+}
+
+extern "C" bern_status bern_tune_get(const bern_net *net, int32_t *choice) {
+  if (!net || !choice) { set_error("null argument"); return BERN_E_ARG; }
+  tune_to(net->tune, choice);
+  return BERN_OK;
+}
+
+extern "C" bern_status bern_tune_set(bern_net *net, const int32_t *choice) {
+  if (!net || !choice) { set_error("null argument"); return BERN_E_ARG; }
+  for (int q = 0; q < kTuneParams; ++q)
+    if (choice[q] < 0 || choice[q] >= kTuneVariants[q]) {
+      set_error("tuning parameter %d: variant %d outside 0..%d", q, choice[q], kTuneVariants[q] - 1);
+      return BERN_E_ARG;
+    }
+  tune_from(choice, net->tune);
+  return BERN_OK;
+}
+
+// Coordinate search over the kernel variants: for each parameter in turn,
+// time `reps` full runs of bern_bounds under every variant (the others at
+// their current choice) with events on `stream`, keep the fastest. The
+// arguments are those of bern_bounds; the outputs hold the last run's
+// results. Synchronises `stream`.
+extern "C" bern_status bern_autotune(bern_net *net, const bern_opts *opts, int64_t n_boxes, const double *box_lo,
+                                     const double *box_hi, const int8_t *plan, double *neuron_lo, double *neuron_hi,
+                                     double *out_lo, double *out_hi, int8_t *used_plan, void *workspace,
+                                     size_t ws_bytes, void *stream, int32_t reps, int32_t *choice, float *best_ms) {
+  if (!net || !opts || reps < 1) { set_error("bad arguments"); return BERN_E_ARG; }
+  bern_opts o = *opts;
+  o.graph = 0;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  BERN_HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    set_error("event creation failed");
+    return BERN_E_DEVICE;
+  }
+  auto timed = [&](float &ms) -> bern_status {
+    bern_status st = bern_bounds(net, &o, n_boxes, box_lo, box_hi, plan, neuron_lo, neuron_hi, out_lo, out_hi,
+                                 used_plan, workspace, ws_bytes, stream, nullptr);  // warm-up
+    if (st != BERN_OK) return st;
+    BERN_HIP_TRY(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) {
+      st = bern_bounds(net, &o, n_boxes, box_lo, box_hi, plan, neuron_lo, neuron_hi, out_lo, out_hi, used_plan,
+                       workspace, ws_bytes, stream, nullptr);
+      if (st != BERN_OK) return st;
+    }
+    BERN_HIP_TRY(hipEventRecord(e1, s));
+    BERN_HIP_TRY(hipEventSynchronize(e1));
+    BERN_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    ms /= (float)reps;
+    return BERN_OK;
+  };
+  int32_t cur[kTuneParams];
+  tune_to(net->tune, cur);
+  float best = 0.0f;
+  bern_status st = timed(best);
+  for (int q = 0; q < kTuneParams && st == BERN_OK; ++q) {
+    const int keep = cur[q];
+    int pick = keep;
+    for (int v = 0; v < kTuneVariants[q] && st == BERN_OK; ++v) {
+      if (v == keep) continue;
+      cur[q] = v;
+      tune_from(cur, net->tune);
+      float ms = 0.0f;
+      st = timed(ms);
+      if (st == BERN_OK && ms < best) {
+        best = ms;
+        pick = v;
+      }
+    }
+    cur[q] = pick;
+    tune_from(cur, net->tune);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != BERN_OK) return st;
+  if (choice) tune_to(net->tune, choice);
+  if (best_ms) *best_ms = best;
   return BERN_OK;
 }
 

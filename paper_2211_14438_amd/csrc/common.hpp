@@ -122,6 +122,16 @@ struct ProfScope {
   void *ev0;
 };
 
+// Kernel variants an autotuner may pick; 0 everywhere is the built-in choice.
+struct Tune {
+  int gemm_wide = 0;    // layers wider than 8: 0 16 rows x 2 inputs/step, 1 16x4, 2 8x2, 3 8x4
+  int gemm_narrow = 0;  // layers of <= 4 neurons: 0 4 rows x 8 inputs/step, 1 4x4, 2 4x16
+  int conv_block = 0;   // threads of the block-per-neuron conversion: 0 by LDS use, 1 256, 2 512, 3 1024
+  int conv_wave = 0;    // tensors <= 1024 coefficients: 0 one wave per neuron, 1 one block per neuron
+};
+constexpr int kTuneParams = 4;
+constexpr int kTuneVariants[kTuneParams] = {4, 3, 4, 2};
+
 // ----------------------------------------------------------- kernel launchers
 // Defined in the .hip files; every launcher enqueues on `stream` and returns a
 // HIP error code (no host synchronisation).
@@ -163,6 +173,7 @@ struct GemmArgs {
   double *rpart;                  // FP32 mode: per wave box (stride rpart_slot): [h][2][cblocks]
   int64_t rpart_slot;             //   sums of |fl32(y) - y| per coefficient block
   int64_t cblocks;                // coefficient blocks of the launch (set by the launcher)
+  Tune tune;
 };
 int64_t gemm_cblocks(int64_t C);
 hipError_t launch_gemm(const GemmArgs &a, hipStream_t s);
@@ -195,6 +206,7 @@ struct ConvertArgs {
   int mode;                       // 0 hidden layer, 1 output layer
   double *scratch;                // FP64 staging for tensors too large for LDS
   size_t scratch_bytes;
+  Tune tune;
 };
 hipError_t launch_convert(const ConvertArgs &a, hipStream_t s);
 size_t convert_scratch_bytes(int n, int D, int h, int64_t nboxes);

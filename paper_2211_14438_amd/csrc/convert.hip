@@ -720,7 +720,7 @@ __global__ void __launch_bounds__(1024) convert_block_t(ConvertArgs a) {
 
 template <typename T, int D>
 static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
-  if (a.C <= kWaveC) {
+  if (a.C <= kWaveC && a.tune.conv_wave == 0) {
     const size_t lds = (size_t)(kBlock / 64) * 2 * a.C * sizeof(double);
     RET_IF(hipFuncSetAttribute((const void *)convert_wave_t<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
@@ -734,7 +734,9 @@ static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
   RET_IF(hipFuncSetAttribute((const void *)convert_block_t<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)lds));
   // a block per neuron; when few blocks share a CU's LDS, more waves each
-  const unsigned threads = lds > 40 * 1024 ? 1024 : 256;
+  static const unsigned kThreads[4] = {0, 256, 512, 1024};
+  const unsigned threads = a.tune.conv_block > 0 && a.tune.conv_block < 4 ? kThreads[a.tune.conv_block]
+                                                                          : (lds > 40 * 1024 ? 1024 : 256);
   ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.C * (a.fp64 ? 8 : 4));
   hipLaunchKernelGGL((convert_block_t<D, T>), dim3((unsigned)(a.nboxes * a.h)), dim3(threads), lds, s, a);
   return hipGetLastError();
@@ -908,7 +910,7 @@ size_t convert_scratch_bytes(int n, int D, int h, int64_t nboxes) {
 
 hipError_t launch_convert(const ConvertArgs &a, hipStream_t s) {
   const int D1 = a.D + 1;
-  if (a.D >= 1 && a.D <= 8 && (a.C <= kWaveC || use_small(a.C)))
+  if (a.D >= 1 && a.D <= 8 && ((a.C <= kWaveC && a.tune.conv_wave == 0) || use_small(a.C)))
     return a.fp64 ? launch_convert_fixed<double>(a, s) : launch_convert_fixed<float>(a, s);
   if (a.C <= kWaveC) {
     const size_t lds = (D1 * D1 + (kBlock / 64) * 2 * a.C) * sizeof(double);
