@@ -2,23 +2,24 @@
 //
 //  * layer-1 pre-activation in closed form (Section 5.3 input initialisation
 //    followed by eqs. upper/lower_bounds_layer): with x_a = d_lo_a + w_a t_a the
-//    pre-activation W x + b is affine in t, so its power tensor at degree
-//    (1,...,1) has the constant b + W d_lo at index 0 and W_ja w_a at the index
-//    with a single 1 on axis a; upper = lower.
+//    pre-activation W x + b is affine in t: the constant b + W d_lo and the
+//    coefficient W_ja w_a of t_a, ranks 0 and 1 + a of the total-degree
+//    layout (simplex.hpp) at degree 1; upper = lower.
 //  * interval affine map of a hidden/output layer (eqs. upper_bounds_layer,
 //    lower_bounds_layer): U^ = W+ U + W- L + b, L^ = W+ L + W- U + b, computed
 //    in midpoint-radius form U^, L^ = W M +- |W| R + b with M = (U+L)/2 and
 //    R = (U-L)/2 (equal in exact arithmetic, half the multiply-adds). In the
 //    power basis the bias only touches the constant coefficient.
 //
-// Layout: tensors [box][neuron][bound 0=upper,1=lower][coefficient].
+// Layout: tensors [box][neuron][bound 0=upper,1=lower][coefficient], the
+// coefficients in the total-degree layout of simplex.hpp.
 #include "common.hpp"
 
 namespace bern {
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) layer1_kernel(Layer1Args a) {
-  const int64_t C = (int64_t)1 << a.n;
+  const int64_t C = a.n + 1;  // total-degree layout at degree 1: constant, then t_1 .. t_n
   const int64_t total = a.nboxes * a.h * C;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -29,13 +30,12 @@ __global__ void __launch_bounds__(kBlock) layer1_kernel(Layer1Args a) {
     const double *lo = a.box_lo + box * a.n;
     const double *hi = a.box_hi + box * a.n;
     const double *w = a.W + (int64_t)j * a.n;
-    double v = 0.0;
+    double v;
     if (c == 0) {
       v = a.b[j];
       for (int k = 0; k < a.n; ++k) v = fma(w[k], lo[k], v);
-    } else if ((c & (c - 1)) == 0) {
-      // single set bit: axis a with position 2^(n-1-a)
-      const int axis = a.n - 1 - (__ffsll((unsigned long long)c) - 1);
+    } else {
+      const int axis = (int)c - 1;
       v = w[axis] * (hi[axis] - lo[axis]);
     }
     T *out = reinterpret_cast<T *>(a.pre) + box * a.slot + (int64_t)j * 2 * C;
@@ -45,7 +45,7 @@ __global__ void __launch_bounds__(kBlock) layer1_kernel(Layer1Args a) {
 }
 
 hipError_t launch_layer1(const Layer1Args &a, hipStream_t s) {
-  const int64_t total = a.nboxes * a.h * ((int64_t)1 << a.n);
+  const int64_t total = a.nboxes * a.h * (int64_t)(a.n + 1);
   const int64_t blocks = (total + kBlock - 1) / kBlock;
   const unsigned grid = (unsigned)std::min<int64_t>(blocks, 65536);
   ProfScope ps(kProfLayer1, s, (double)total * 2 * (a.fp64 ? 8 : 4));
@@ -123,10 +123,9 @@ __device__ __forceinline__ void gemm_rows(const T *X, int64_t st, int64_t C, con
 // block row. Block x index runs over output-neuron chunks first so that the
 // blocks reading the same coefficient range of the previous layer run
 // together and share L2. Only the box's live inputs are read: composed
-// neurons' full tensors at c, and the tensors of active, order-1 and
-// fallback neurons, stored at degree Ds = min(Din, Dout), at the position of
-// c's exponents in degree Ds (no term where an exponent exceeds Ds: the
-// lifted tensor is zero there).
+// neurons' full tensors, and the tensors of active, order-1 and fallback
+// neurons, which hold only the coefficients of their own degree (a prefix
+// in the total-degree layout).
 // The weights come from the transposed, zero-padded copy W^T[k][hp]: for one
 // input k the block's MB weights are contiguous and uniform, so they load as
 // a few wide scalar loads and no row guard sits in the inner loop; |w| is the
@@ -153,19 +152,10 @@ __global__ void __launch_bounds__(kBlock) gemm_kernel(GemmArgs a) {
   const int64_t cc = valid ? c : a.C - 1;
   gemm_rows<T, MB, KU>(X + cc, st, a.C, lv + 2, lv[0], true, wt, a.hp, accM, accR);
   if (lv[1] > 0) {
-    // exponents of c (base Dout+1) -> index at the degree Ds = min(Din,
-    // Dout) those tensors are stored at, or none
-    const int Ds = min(a.Din, a.Dout), Do1 = a.Dout + 1;
-    int64_t rem = cc, mc = 0, pw = 1;
-    bool inside = true;
-    for (int q = 0; q < a.n; ++q) {
-      const int d = (int)(rem % Do1);
-      rem /= Do1;
-      if (d > Ds) inside = false;
-      mc += d * pw;
-      pw *= Ds + 1;
-    }
-    gemm_rows<T, MB, KU>(X + (inside ? mc : 0), st, a.C, lv + 2 + a.hin, lv[1], inside, wt, a.hp, accM, accR);
+    // degree-preserving inputs hold the first Cs coefficients (graded order:
+    // the monomials of their degree); beyond, their lifted tensor is zero
+    const bool inside = cc < a.Cs;
+    gemm_rows<T, MB, KU>(X + (inside ? cc : 0), st, a.C, lv + 2 + a.hin, lv[1], inside, wt, a.hp, accM, accR);
   }
   T *Y = reinterpret_cast<T *>(a.pre) + box * a.slot_out;
   const bool track = a.rpart != nullptr;
@@ -222,7 +212,7 @@ static hipError_t launch_gemm_mb(const GemmArgs &a, hipStream_t s) {
 hipError_t launch_gemm(const GemmArgs &a0, hipStream_t s) {
   GemmArgs a = a0;
   a.cblocks = gemm_cblocks(a.C);
-  if (a.hp % 16 != 0 || a.hp < a.h || !a.live) return hipErrorInvalidValue;
+  if (a.hp % 16 != 0 || a.hp < a.h || !a.live || a.Cs > a.C) return hipErrorInvalidValue;
   ProfScope ps(kProfGemm, s, (double)a.nboxes * (2.0 * a.hin + 2.0 * a.h) * a.C * (a.fp64 ? 8 : 4));
   if (a.h <= 4) {
     switch (a.tune.gemm_narrow) {

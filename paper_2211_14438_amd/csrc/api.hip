@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "simplex.hpp"
 
 namespace bern {
 
@@ -138,6 +139,7 @@ struct bern_net {
   };
   std::vector<GraphEntry> graphs;
   hipStream_t capture = nullptr;  // stream the sequences are captured on
+  bern::SimplexTables *tab = nullptr;  // index tables of the total-degree layout (built on demand)
 };
 
 struct bern_pred {
@@ -175,8 +177,10 @@ static bern_status plan_net(const bern_net *net, const bern_opts *o, Plan &p) {
   for (int i = 0; i < p.H; ++i) {
     const int h = net->widths[i + 1];
     p.Dpre[i] = D;
-    p.Cpre[i] = tsize(p.n, D, cap);
-    if (p.Cpre[i] < 0) {
+    // stored coefficients (total-degree layout); the read-off still expands
+    // them to the dense (D+1)^n tensor
+    p.Cpre[i] = ssize(p.n, D, cap);
+    if (p.Cpre[i] < 0 || tsize(p.n, D, cap) < 0) {
       set_error("layer %d: (%d+1)^%d coefficients overflow", i + 1, D, p.n);
       return BERN_E_TOO_LARGE;
     }
@@ -187,23 +191,25 @@ static bern_status plan_net(const bern_net *net, const bern_opts *o, Plan &p) {
     if (i < p.H - 1) {
       const int Dn = p.Lmax * D;
       p.Dpost[i] = Dn;
-      p.Cpost[i] = tsize(p.n, Dn, cap);
+      p.Cpost[i] = ssize(p.n, Dn, cap);
       if (p.Cpost[i] < 0) {
-        set_error("layer %d post: (%d+1)^%d coefficients overflow", i + 1, Dn, p.n);
+        set_error("layer %d post: degree %d in %d variables overflows", i + 1, Dn, p.n);
         return BERN_E_TOO_LARGE;
       }
       p.arenaB = std::max(p.arenaB, align256((size_t)h * 2 * p.Cpost[i] * p.elem));
       p.recs = std::max(p.recs, align256((size_t)h * sizeof(NeuronRec)));
-      int64_t nb = 0;
-      if (p.mode == BERN_PLAN_PLAIN) {
-        nb = compose_nbx(p.n, D, Dn, p.Cpost[i], p.fp64);
-      } else {
-        for (int di = 0; di <= D; ++di)
-          for (int dq = di; dq <= Dn; ++dq) nb = std::max(nb, compose_nbx(p.n, di, dq, ipow(dq + 1, p.n), p.fp64));
-      }
+      // blocks per item: every class of the layer stores at most Cpost coefficients
+      const int64_t nb = compose_nbx(p.Cpost[i]);
       p.nbx[i] = nb;
       if (!p.fp64) p.cpart = std::max(p.cpart, align256((size_t)h * 2 * nb * 2 * 8));
-      if (p.Lmax >= 2) p.horner = std::max(p.horner, compose_scratch_bytes(p.n, D, p.Lmax, h, 1, p.fp64));
+      if (p.Lmax >= 3) {
+        const int64_t Cq = ssize(p.n, (p.Lmax - 1) * D, cap);
+        if (Cq < 0) {
+          set_error("layer %d: Horner intermediates of degree %d overflow", i + 1, (p.Lmax - 1) * D);
+          return BERN_E_TOO_LARGE;
+        }
+        p.horner = std::max(p.horner, compose_scratch_bytes(Cq, p.Lmax, h, 1));
+      }
       D = Dn;
     }
   }
@@ -311,9 +317,17 @@ bern_status bern_net_create(int32_t H, const int32_t *widths, const double *W, c
       for (int c = 0; c < hin; ++c) wt[base + (size_t)c * hp + r] = Wi[(int64_t)r * hin + c];
   }
   (void)hipGetDevice(&net->device);
+  net->tab = new (std::nothrow) bern::SimplexTables();
+  if (!net->tab) {
+    delete net;
+    set_error("out of host memory");
+    return BERN_E_OOM;
+  }
+  net->tab->n = net->n;
   auto fail = [&](hipError_t e) {
     set_error("device allocation/copy failed: %s", hipGetErrorString(e));
     (void)hipFree(net->W64); (void)hipFree(net->b64); (void)hipFree(net->sens); (void)hipFree(net->WT);
+    delete net->tab;
     delete net;
     return BERN_E_DEVICE;
   };
@@ -341,6 +355,7 @@ void bern_net_destroy(bern_net *net) {
     if (g.graph) (void)hipGraphDestroy(g.graph);
   }
   if (net->capture) (void)hipStreamDestroy(net->capture);
+  delete net->tab;
   delete net;
 }
 
@@ -415,6 +430,31 @@ __global__ void box_degree_kernel(int64_t nb, int h, const NeuronRec *recs, int 
   int d = 0;
   for (int j = 0; j < h; ++j) d = max(d, recs[b * h + j].deg);
   deg[b] = d;
+}
+
+// Index tables of one layer's degree class: the dense positions for the
+// read-off at Din and, for compositions, the square table (Din, Din) and the
+// Horner tables (Din, m Din), m = 1 .. Lmax - 1. Built once per network.
+struct LayerTables {
+  const int *didx = nullptr;
+  const ProdTable *sq = nullptr;
+  const ProdTable *hz[kMaxOrder] = {};
+};
+
+static bern_status layer_tables(const bern_net *net, int Din, int Lmax, bool compose, LayerTables &t) {
+  hipError_t e = dense_index_table(*net->tab, Din, &t.didx);
+  if (e == hipSuccess && compose && Lmax >= 2) e = product_table(*net->tab, Din, Din, true, &t.sq);
+  for (int m = 1; e == hipSuccess && compose && m <= Lmax - 1 && Lmax >= 3; ++m)
+    e = product_table(*net->tab, Din, m * Din, false, &t.hz[m]);
+  if (e == hipErrorInvalidValue) {
+    set_error("index tables for degree %d in %d variables exceed their limits", Din, net->n);
+    return BERN_E_TOO_LARGE;
+  }
+  if (e != hipSuccess) {
+    set_error("index tables: %s", hipGetErrorString(e));
+    return BERN_E_DEVICE;
+  }
+  return BERN_OK;
 }
 
 // Boxes of one degree class within a wave.
@@ -507,7 +547,12 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       c.D = cl.Din;
       c.h = h;
       c.L = p.L;
+      LayerTables lt;
+      st = layer_tables(net, cl.Din, p.Lmax, false, lt);
+      if (st != BERN_OK) return st;
       c.C = ipow(cl.Din + 1, n);
+      c.S = ssize(n, cl.Din);
+      c.didx = lt.didx;
       c.nboxes = (int64_t)cl.ids.size();
       c.bids = cid[k];
       c.slot = slotA;
@@ -529,7 +574,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       c.box_hi = box_hi;
       c.rpart = gpart;
       c.rpart_slot = (int64_t)(p.gpart / sizeof(double));
-      c.cblocks = gemm_cblocks(c.C);
+      c.cblocks = gemm_cblocks(c.S);
       c.tune = net->tune;
       c.plan_ld = net->nh;
       c.plan_col0 = last ? 0 : net->noff[i];
@@ -617,9 +662,24 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       m.slot_out = slotB;
       m.nbounds = 2;
       m.Lmax = p.Lmax;
-      m.Cin = ipow(cl.Din + 1, n);
-      m.Cout = ipow(cl.Dout + 1, n);
-      m.Cq = ipow(cl.Din * std::max(1, p.Lmax - 1) + 1, n);
+      LayerTables lt;
+      st = layer_tables(net, cl.Din, p.Lmax, true, lt);
+      if (st != BERN_OK) return st;
+      m.Cin = ssize(n, cl.Din);
+      m.Cout = ssize(n, cl.Dout);
+      m.Cs = ssize(n, std::min(cl.Din, cl.Dout));
+      for (int q = 0; q <= kMaxOrder; ++q) m.Sm[q] = q <= p.Lmax ? ssize(n, q * cl.Din) : 0;
+      m.Cq = p.Lmax >= 3 ? ssize(n, (p.Lmax - 1) * cl.Din) : 0;
+      if (lt.sq) {
+        m.sq_off = lt.sq->off;
+        m.sq_pairs = lt.sq->pairs;
+        m.sq_diag = lt.sq->diag;
+      }
+      for (int q = 1; q < kMaxOrder; ++q)
+        if (lt.hz[q]) {
+          m.hz_off[q] = lt.hz[q]->off;
+          m.hz_pairs[q] = lt.hz[q]->pairs;
+        }
       m.nboxes = (int64_t)cl.ids.size();
       m.pre = A;
       m.post = Bp;
@@ -627,7 +687,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       m.fp64 = p.fp64 ? 1 : 0;
       m.scratch = horner;
       m.scratch_bytes = p.horner * B;
-      m.nbx = compose_nbx(n, cl.Din, cl.Dout, m.Cout, p.fp64);
+      m.nbx = compose_nbx(m.Cout);
       m.part = p.fp64 ? nullptr : cpart;
       m.live = live;
       m.live_ld = live_ld;
@@ -645,9 +705,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       a.pre = A;
       a.live = live;
       a.live_ld = live_ld;
-      a.n = n;
-      a.Din = cl.Din;
-      a.Dout = cl.Dout;
+      a.Cs = m.Cs;
       a.tune = net->tune;
       a.WT = net->WT + net->wtoff[i + 1];
       a.hp = net->hpad[i + 1];
@@ -777,6 +835,12 @@ extern "C" bern_status bern_bounds(const bern_net *net, const bern_opts *opts, i
   // replayed as one graph launch; plans with per-neuron degrees read every
   // box's degree back once per hidden layer and always run eagerly.
   if (opts->graph && p.mode == BERN_PLAN_PLAIN) {
+    // index tables are built (device allocations) before any capture
+    for (int i = 0; i < p.H; ++i) {
+      LayerTables lt;
+      st = layer_tables(net, p.Dpre[i], p.Lmax, i < p.H - 1, lt);
+      if (st != BERN_OK) return st;
+    }
     st = run_graph(const_cast<bern_net *>(net), opts, n_boxes,
                    {(uint64_t)(uintptr_t)box_lo, (uint64_t)(uintptr_t)box_hi, (uint64_t)(uintptr_t)neuron_lo,
                     (uint64_t)(uintptr_t)neuron_hi, (uint64_t)(uintptr_t)out_lo, (uint64_t)(uintptr_t)out_hi,

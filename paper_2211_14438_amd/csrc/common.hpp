@@ -147,7 +147,7 @@ struct Layer1Args {
   int64_t slot;
   const double *box_lo, *box_hi;  // [B][n]
   const double *W, *b;            // W^(1) [h][n], b^(1) [h], FP64
-  void *pre;                      // [B][h][2][2^n]
+  void *pre;                      // [B][h][2][n+1] (total-degree layout at degree 1)
   int fp64;
 };
 hipError_t launch_layer1(const Layer1Args &a, hipStream_t s);
@@ -159,13 +159,14 @@ struct GemmArgs {
   int64_t slot_in, slot_out;
   const void *post;               // [B][hin][2][C]
   void *pre;                      // [B][h][2][C]
-  // Per box input lists (null: every input is a full tensor): live[0] full
-  // tensors (composed neurons) at the launch degree, indices at live[2..];
-  // live[1] tensors stored at degree Din (active, order 1, fallback),
-  // indices at live[2 + hin..]. Inactive neurons contribute nothing.
+  // Per box input lists: live[0] full tensors (composed neurons) of C
+  // coefficients, indices at live[2..]; live[1] tensors of degree-preserving
+  // neurons (active, order 1, fallback) stored with their first Cs
+  // coefficients only, indices at live[2 + hin..]. Inactive neurons
+  // contribute nothing.
   const int *live;
   int64_t live_ld;
-  int n, Din, Dout;                // Dout: degree of the input post tensors (= of C)
+  int64_t Cs;
   const double *WT;               // [hin][hp]: W transposed, rows h..hp-1 zero
   int hp;                         // h rounded up to a multiple of 16
   const double *b;                // [h]
@@ -180,11 +181,13 @@ hipError_t launch_gemm(const GemmArgs &a, hipStream_t s);
 
 struct ConvertArgs {
   int n, D, h, L;                 // L: ReLU order of the plain rule
-  int64_t C, nboxes;
+  int64_t C, nboxes;              // C: (D+1)^n, the dense tensor the basis change runs on
+  int64_t S;                      // stored coefficients per tensor (total-degree layout)
+  const int *didx;                // [S] position of each stored coefficient in the dense tensor
   const int *bids;
   int64_t slot;
   int cap;                        // largest post degree a neuron may take (plan codes are clamped)
-  const void *pre;                // [B][h][2][C] power coefficients
+  const void *pre;                // [B][h][2][S] power coefficients
   int fp64;
   NeuronRec *recs;                // [B][h] (hidden layers)
   // FP32 mode: inputs of the pre-activation radii
@@ -219,8 +222,15 @@ struct ComposeArgs {
   int64_t nbx;                    // blocks per item of every compose launch of the layer
   int nbounds;                    // 2 (upper, lower) for the network, 1 for plain products
   int Lmax;                       // largest ReLU order any neuron of the launch may use
-  int64_t Cin, Cout, nboxes;
+  int64_t Cin, Cout, nboxes;      // stored coefficients at degrees Din and Dout
+  int64_t Cs;                     // stored coefficients of degree-preserving posts (degree min(Din, Dout))
   int64_t Cq;                     // coefficients per Horner intermediate buffer
+  int64_t Sm[kMaxOrder + 1];      // Sm[m]: coefficients at degree m * Din
+  const int *sq_off;              // square table (Din, Din) (simplex.hpp)
+  const int2 *sq_pairs;
+  const int *sq_diag;
+  const int *hz_off[kMaxOrder];   // product tables (Din, m Din), m = 1 .. Lmax - 1
+  const int2 *hz_pairs[kMaxOrder];
   const void *pre;                // [B][h][2][Cin]
   void *post;                     // [B][h][2][Cout]
   const NeuronRec *recs;          // [B][h]
@@ -232,8 +242,8 @@ struct ComposeArgs {
 };
 hipError_t launch_compose(const ComposeArgs &a, hipStream_t s);
 // Blocks per item the compose launches of a layer use (partials stride).
-int64_t compose_nbx(int n, int Din, int Dout, int64_t Cout, int fp64);
-size_t compose_scratch_bytes(int n, int Din, int Lmax, int h, int64_t nboxes, int fp64);
+int64_t compose_nbx(int64_t Cout);
+size_t compose_scratch_bytes(int64_t Cq, int Lmax, int h, int64_t nboxes);
 
 // Largest dynamic LDS allocation one block may use on the current device.
 size_t device_lds_limit();

@@ -4,22 +4,24 @@
 // For an unstable neuron with pre-activation interval [lo, hi] and ReLU order
 // L, with nu(P) = (P - lo)/(hi - lo) and the power series c_0..c_L of Step 2:
 //     U = sum_j c_j nu(U^)^j,        L = sum_j c_j nu(L^)^j - e.
-// Powers of a polynomial are products "Prod" (Section 4.2): dense n-d
-// convolutions of power-coefficient tensors. In the power basis, lifting a
-// tensor to a higher degree (Prop. 4 elevation) is a zero pad, and adding a
-// constant only touches the constant coefficient.
+// Powers of a polynomial are products "Prod" (Section 4.2): n-d convolutions
+// of coefficient tensors. In the power basis, lifting a tensor to a higher
+// degree (Prop. 4 elevation) is a zero pad, and adding a constant only
+// touches the constant coefficient.
 //
-//  * order 2 (the common case): U = c_2 nu^2 + c_1 nu + c_0. The square nu^2
-//    is a symmetric convolution, computed over half of the index pairs. The
-//    tensor is split into outer axes and NI trailing "row" axes; nu sits in
-//    LDS row by row, each thread owns one output row and accumulates the
-//    row-by-row convolutions of its (I, K-I) outer pairs in registers.
-//  * order >= 3 (and degrees without a specialised kernel): Horner steps
-//    Q <- nu * Q + c_j, one launch per step, generic runtime degrees.
+// The network's tensors are stored in the total-degree layout (simplex.hpp),
+// so a product runs over the index pairs (I, J) of stored coefficients with
+// I + J = K, listed per output coefficient K in a table built once per
+// degree pair:
+//  * order 2 (the common case): U = c_2 nu^2 + c_1 nu + c_0 over the square
+//    table (pairs I < J once, doubled, plus the diagonal);
+//  * order >= 3: Horner steps Q <- nu * Q + c_j, one launch per step;
 //  * order 1, active (identity) and the linear fallback are element-wise
 //    writes at the input degree; inactive neurons (zero) store nothing and
 //    are left out of the next affine map's input lists.
 // Composed results are written whole at the layer's post degree Dout.
+// The dense per-variable-degree square kernel below serves the step-level
+// product entry point, whose tensors are dense.
 //
 // Arithmetic is FP64 for both storage types: with packed FP32 math off, FP32
 // and FP64 FMAs issue at the same rate on gfx950, and FP64 keeps the rounding
@@ -366,10 +368,9 @@ __global__ void __launch_bounds__(kBlock) compose_scatter_kernel(ComposeArgs a) 
   const T *p = in_tensor<T>(a, box, j, s);
   T *out = out_tensor<T>(a, box, j, s);
   // storage degree: Din, or the layer's post degree when that is lower (only
-  // fallback and inactive neurons then)
+  // fallback and inactive neurons then); a prefix of the total-degree layout
   const int Ds = min(a.Din, a.Dout);
-  int64_t Cs = 1;
-  for (int q = 0; q < a.n; ++q) Cs *= Ds + 1;
+  const int64_t Cs = a.Cs;
   double rsum = 0.0, l1sum = 0.0;
   if ((kind == kActive || kind == 1) && Ds == a.Din) {  // these neurons take degree Din <= Dout
     for (int64_t I = threadIdx.x; I < a.Cin; I += blockDim.x) {
@@ -386,13 +387,8 @@ __global__ void __launch_bounds__(kBlock) compose_scatter_kernel(ComposeArgs a) 
     for (int64_t I = threadIdx.x; I < Cs; I += blockDim.x) out[I] = (T)0;
     __syncthreads();
     if (threadIdx.x <= (unsigned)a.n && (threadIdx.x == 0 || Ds >= 1)) {
-      const int q = (int)threadIdx.x;  // 0: constant; 1 + axis: t_axis
-      int64_t o = 0;
-      if (q > 0) {
-        o = 1;
-        for (int t = 0; t < a.n - q; ++t) o *= Ds + 1;  // position of t_(q-1)
-      }
-      store(out + o, fb[q], rsum, l1sum);
+      const int q = (int)threadIdx.x;  // rank 0: constant; rank 1 + axis: t_axis
+      store(out + q, fb[q], rsum, l1sum);
     }
   }
   if (a.part) {
@@ -404,87 +400,94 @@ __global__ void __launch_bounds__(kBlock) compose_scatter_kernel(ComposeArgs a) 
   }
 }
 
-// ------------------------------------------------ generic Horner step
-// Step m (1 <= m <= L-1) of Q^(m) = nu * Q^(m-1) + c_{L-1-m}, where
-// Q^(0) = c_L nu + c_{L-1}; Q^(m) has degree (m+1) Din. Intermediates stay in
-// FP64 scratch; the last step adds -e (lower bound) and writes the post
-// tensor at degree Dout.
+// ---------------------------------------------- total-degree products
+// Load nu = (p + shift [K = 0] - lo) / (hi - lo) of the item into LDS (FP64).
 template <typename T>
-__global__ void __launch_bounds__(kBlock) compose_horner_kernel(ComposeArgs a, int m, int sq_D) {
+__device__ inline void load_nu(const ComposeArgs &a, const T *p, const NuSource &ns, double *nu) {
+  for (int64_t i = threadIdx.x; i < a.Cin; i += blockDim.x) {
+    double v = (double)p[i];
+    if (i == 0) v += ns.shift - ns.lo;
+    nu[i] = v / ns.w;
+  }
+  __syncthreads();
+}
+
+// Order 2 (the common case): U = c2 nu^2 + c1 nu + c0, minus e for the
+// lower bound. One thread per output coefficient K at the layer's degree;
+// the pairs (I, J) with I + J = K come from the square table: pairs with
+// I < J listed once and doubled, plus the diagonal term. Coefficients past
+// degree 2 Din (a layer stored at a higher degree) are zero.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) compose_sq2_kernel(ComposeArgs a) {
+  extern __shared__ double nu[];
+  const int j = blockIdx.y / a.nbounds, s = blockIdx.y % a.nbounds;
+  const int64_t g = blockIdx.z, box = wave_box(a, g);
+  const NeuronRec &r = a.recs[box * a.h + j];
+  if (r.kind != 2) return;
+  load_nu(a, in_tensor<T>(a, box, j, s), nu_of(a, &r, s), nu);
+  const int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double rsum = 0.0, l1sum = 0.0;
+  if (K < a.Cout) {
+    double v = 0.0;
+    if (K < a.Sm[2]) {
+      double acc = 0.0;
+      const int e = a.sq_off[K + 1];
+      for (int q = a.sq_off[K]; q < e; ++q) {
+        const int2 pr = a.sq_pairs[q];
+        acc = fma(nu[pr.x], nu[pr.y], acc);
+      }
+      acc = acc + acc;
+      const int d = a.sq_diag[K];
+      if (d >= 0) acc = fma(nu[d], nu[d], acc);
+      v = r.c[2] * acc;
+      if (K < a.Cin) v = fma(r.c[1], nu[K], v);
+      if (K == 0) v += r.c[0] - (s == 1 ? r.e : 0.0);
+    }
+    store(out_tensor<T>(a, box, j, s) + K, v, rsum, l1sum);
+  }
+  if (a.part) block_partials(a, item_of(a, g, j, s), rsum, l1sum);
+}
+
+// Orders L >= 3: Horner steps Q^(m) = nu Q^(m-1) + c_{L-1-m}, m = 1 .. L-1,
+// with Q^(0) = c_L nu + c_{L-1}; Q^(m) has degree (m+1) Din and step m reads
+// the product table (Din, m Din). Intermediates stay in FP64 scratch; the
+// last step subtracts e for the lower bound and stores the post tensor.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) compose_hz_kernel(ComposeArgs a, int m) {
+  extern __shared__ double nu[];
   const int j = blockIdx.y / a.nbounds, s = blockIdx.y % a.nbounds;
   const int64_t g = blockIdx.z, box = wave_box(a, g);
   const NeuronRec &r = a.recs[box * a.h + j];
   const int L = r.kind;
-  if (L < 2 || (L == 2 && sq_D == a.Din) || m > L - 1) return;
-  const NuSource ns = nu_of(a, &r, s);
+  if (L < 3 || m > L - 1) return;
+  load_nu(a, in_tensor<T>(a, box, j, s), nu_of(a, &r, s), nu);
   const bool last = (m == L - 1);
   const int64_t it = item_of(a, g, j, s);
-  const T *p = in_tensor<T>(a, box, j, s);
-  const int Din = a.Din, Di1 = Din + 1;
-  const int dq = m * Din;            // degree of Q^(m-1)
-  const int dout_m = (m + 1) * Din;  // degree of Q^(m)
-  const int Dt = last ? a.Dout : dout_m;
-  const int64_t Ct = last ? a.Cout : ipow(dout_m + 1, a.n);
   double *scr = reinterpret_cast<double *>(a.scratch);
-  double *dsts = scr + (it * 2 + (m & 1)) * a.Cq;
-  T *dstp = out_tensor<T>(a, box, j, s);
-  const double *qsrc = scr + (it * 2 + ((m - 1) & 1)) * a.Cq;
+  const double *qprev = scr + (it * 2 + ((m - 1) & 1)) * a.Cq;
+  double *qcur = scr + (it * 2 + (m & 1)) * a.Cq;
   const double cL = r.c[L], cL1 = r.c[L - 1], cadd = r.c[L - 1 - m];
-  const int Dq1 = dq + 1;
+  const int64_t Sq = a.Sm[m + 1];  // coefficients of Q^(m)
+  const int64_t Ct = last ? a.Cout : Sq;
+  const int *off = a.hz_off[m];
+  const int2 *pairs = a.hz_pairs[m];
+  const int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double rsum = 0.0, l1sum = 0.0;
-  for (int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; K < Ct; K += (int64_t)gridDim.x * blockDim.x) {
-    int k[kMaxInputs];
-    int64_t rem = K;
-    bool inside = true;
-    for (int q = a.n - 1; q >= 0; --q) {
-      k[q] = (int)(rem % (Dt + 1));
-      rem /= (Dt + 1);
-      if (k[q] > dout_m) inside = false;
-    }
+  if (K < Ct) {
     double v = 0.0;
-    if (inside) {
-      int lo_[kMaxInputs], hi_[kMaxInputs], i[kMaxInputs];
-      bool any = true;
-      for (int q = 0; q < a.n; ++q) {
-        lo_[q] = max(0, k[q] - dq);
-        hi_[q] = min(k[q], Din);
-        i[q] = lo_[q];
-        if (lo_[q] > hi_[q]) any = false;
-      }
-      while (any) {
-        int64_t iI = 0, iJ = 0;
-        for (int q = 0; q < a.n; ++q) {
-          iI = iI * Di1 + i[q];
-          iJ = iJ * Dq1 + (k[q] - i[q]);
-        }
-        double nu = (double)p[iI];
-        if (iI == 0) nu += ns.shift - ns.lo;
-        nu /= ns.w;
-        double qv;
-        if (m == 1) {
-          double x = (double)p[iJ];
-          if (iJ == 0) x += ns.shift - ns.lo;
-          qv = cL * (x / ns.w) + (iJ == 0 ? cL1 : 0.0);
-        } else {
-          qv = qsrc[iJ];
-        }
-        v = fma(nu, qv, v);
-        int q = a.n - 1;
-        for (; q >= 0; --q) {
-          if (i[q] < hi_[q]) {
-            ++i[q];
-            break;
-          }
-          i[q] = lo_[q];
-        }
-        if (q < 0) any = false;
+    if (K < Sq) {
+      const int e = off[K + 1];
+      for (int q = off[K]; q < e; ++q) {
+        const int2 pr = pairs[q];
+        const double qv = (m == 1) ? fma(cL, nu[pr.y], pr.y == 0 ? cL1 : 0.0) : qprev[pr.y];
+        v = fma(nu[pr.x], qv, v);
       }
       if (K == 0) v += cadd - ((last && s == 1) ? r.e : 0.0);
     }
     if (last)
-      store(dstp + K, v, rsum, l1sum);
+      store(out_tensor<T>(a, box, j, s) + K, v, rsum, l1sum);
     else
-      dsts[K] = v;
+      qcur[K] = v;
   }
   if (last && a.part) block_partials(a, it, rsum, l1sum);
 }
@@ -603,13 +606,7 @@ static bool sq_handles(int n, int Din, int Dout) {
   return l > 0 && l <= device_lds_limit() && Dout >= 2 * Din;
 }
 
-int64_t compose_nbx(int n, int Din, int Dout, int64_t Cout, int) {
-  if (sq_handles(n, Din, Dout)) {
-    const int64_t Mo = ipow(Dout + 1, n - sq_ni(n, Din));
-    return (Mo + kBlock - 1) / kBlock;
-  }
-  return std::min<int64_t>((Cout + kBlock - 1) / kBlock, 4096);
-}
+int64_t compose_nbx(int64_t Cout) { return std::max<int64_t>(1, (Cout + kBlock - 1) / kBlock); }
 
 template <typename T, int D, int NI>
 static hipError_t launch_sq(const ComposeArgs &a, hipStream_t s) {
@@ -660,15 +657,24 @@ static hipError_t compose_all(const ComposeArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(compose_scatter_kernel<T>, grid, dim3(kBlock), 0, s, a);
     RET_IF(hipGetLastError());
   }
-  hipError_t err = hipSuccess;
-  const int sqD = sq_dispatch<T>(a, s, err);
-  RET_IF(err);
-  const int Lmax = a.Lmax;
-  if (Lmax >= 3 || (Lmax == 2 && sqD != a.Din)) {
-    for (int m = 1; m <= Lmax - 1; ++m) {
+  const size_t lds = (size_t)a.Cin * sizeof(double);
+  if (a.Lmax >= 2) {
+    if (!a.sq_off || lds > device_lds_limit() || (int64_t)gx * kBlock < a.Cout) return hipErrorInvalidValue;
+    RET_IF(hipFuncSetAttribute((const void *)compose_sq2_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+    dim3 grid(gx, (unsigned)(a.h * a.nbounds), (unsigned)a.nboxes);
+    ProfScope ps(kProfComposeSquare, s, 0.0);
+    hipLaunchKernelGGL(compose_sq2_kernel<T>, grid, dim3(kBlock), lds, s, a);
+    RET_IF(hipGetLastError());
+  }
+  if (a.Lmax >= 3) {
+    RET_IF(hipFuncSetAttribute((const void *)compose_hz_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+    for (int m = 1; m <= a.Lmax - 1; ++m) {
+      if (!a.hz_off[m]) return hipErrorInvalidValue;
       dim3 grid(gx, (unsigned)(a.h * a.nbounds), (unsigned)a.nboxes);
       ProfScope ps(kProfComposeHorner, s, 0.0);
-      hipLaunchKernelGGL(compose_horner_kernel<T>, grid, dim3(kBlock), 0, s, a, m, sqD);
+      hipLaunchKernelGGL(compose_hz_kernel<T>, grid, dim3(kBlock), lds, s, a, m);
       RET_IF(hipGetLastError());
     }
   }
@@ -685,9 +691,8 @@ hipError_t launch_compose(const ComposeArgs &a, hipStream_t s) {
   return a.fp64 ? compose_all<double>(a, s) : compose_all<float>(a, s);
 }
 
-size_t compose_scratch_bytes(int n, int Din, int Lmax, int h, int64_t nboxes, int) {
-  if (Lmax < 3) return 0;  // order 2 without a square kernel is one (final) Horner step
-  const int64_t Cq = ipow(Din * (Lmax - 1) + 1, n);
+size_t compose_scratch_bytes(int64_t Cq, int Lmax, int h, int64_t nboxes) {
+  if (Lmax < 3) return 0;
   return align256((size_t)nboxes * h * 2 * 2 * Cq * sizeof(double));
 }
 

@@ -2,7 +2,9 @@
 // (Step 2) on gfx950.
 //
 // A pre-activation polynomial of per-variable degree D arrives as power
-// coefficients a_J in the box coordinate t. Its Bernstein coefficients at
+// coefficients a_J in the box coordinate t, stored in the total-degree layout
+// (simplex.hpp: only |J| <= D); they are scattered into the dense (D+1)^n
+// tensor in LDS, whose other entries are zero. Its Bernstein coefficients at
 // degree D follow from the identity t^j = sum_{k>=j} C(k,j)/C(D,j) B_{k,D}(t)
 // applied along every variable: a triangular (D+1)x(D+1) contraction per
 // axis, b_k = sum_{j<=k} C(k,j)/C(D,j) a_j. The range enclosure (Def. 2) then
@@ -143,7 +145,7 @@ __device__ void pre_radii(const ConvertArgs &a, int64_t box, int j, const void *
   if (a.layer == 0) {
     const double *lo = a.box_lo + box * a.n, *hi = a.box_hi + box * a.n;
     const double *w = a.W + (int64_t)j * a.n;
-    const float *p = reinterpret_cast<const float *>(pre) + box * a.slot + (int64_t)j * 2 * a.C;
+    const float *p = reinterpret_cast<const float *>(pre) + box * a.slot + (int64_t)j * 2 * a.S;
     double a0 = a.b[j], sabs = fabs(a.b[j]);
     for (int k = 0; k < a.n; ++k) {
       a0 = fma(w[k], lo[k], a0);
@@ -152,7 +154,7 @@ __device__ void pre_radii(const ConvertArgs &a, int64_t box, int j, const void *
     double r = fabs((double)p[0] - a0);
     for (int k = 0; k < a.n; ++k) {
       const double ak = w[k] * (hi[k] - lo[k]);
-      r += fabs((double)p[(int64_t)1 << (a.n - 1 - k)] - ak);
+      r += fabs((double)p[1 + k] - ak);  // coefficient of t_k
     }
     epsU = epsL = (r + gamma64(a.n + 4) * sabs) * kPadSafety;
     return;
@@ -261,11 +263,14 @@ __global__ void __launch_bounds__(kBlock) convert_small_kernel(ConvertArgs a) {
   if (threadIdx.x < 4) ext[threadIdx.x] = 0.0;
   double ext_lo = 0.0, ext_hi = 0.0, l1s[2] = {0.0, 0.0};
   for (int s = 1; s >= 0; --s) {  // lower first, then upper
-    const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + ((int64_t)j * 2 + s) * a.C;
+    const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + ((int64_t)j * 2 + s) * a.S;
+    for (int64_t i = threadIdx.x; i < a.C; i += blockDim.x) t[i] = 0.0;
+    __syncthreads();
     double l1 = 0.0;
-    for (int64_t i = threadIdx.x; i < a.C; i += blockDim.x) {
-      t[i] = (double)p[i];
-      l1 += fabs(t[i]);
+    for (int64_t i = threadIdx.x; i < a.S; i += blockDim.x) {
+      const double v = (double)p[i];
+      t[a.didx[i]] = v;
+      l1 += fabs(v);
     }
     l1s[s] = block_reduce(l1, OpAdd(), red);
     lds_basis_change(t, a.C, a.n, a.D, 0, a.n, tab);
@@ -389,11 +394,14 @@ __global__ void __launch_bounds__(kBlock) convert_wave_kernel(ConvertArgs a) {
   double ext[2], l1s[2];
   for (int s = 1; s >= 0; --s) {
     double *t = tw + (1 - s) * C;
-    const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + ((int64_t)j * 2 + s) * a.C;
+    const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + ((int64_t)j * 2 + s) * a.S;
+    for (int i = lane; i < C; i += 64) t[i] = 0.0;
+    wave_sync();
     double l1 = 0.0;
-    for (int i = lane; i < C; i += 64) {
-      t[i] = (double)p[i];
-      l1 += fabs(t[i]);
+    for (int i = lane; i < (int)a.S; i += 64) {
+      const double v = (double)p[i];
+      t[a.didx[i]] = v;
+      l1 += fabs(v);
     }
     l1s[s] = wave_reduce(l1, OpAdd());
     wave_sync();
@@ -511,48 +519,21 @@ __device__ void team_axes(double *t, int total, int s0, int na, const Team &tm, 
   tm.sync();
 }
 
-// Power coefficients p[0, C) (C = (D+1)^n) -> Bernstein coefficients in t.
-// Returns the team-wide sum of |p| and the extrema of the result.
+// Stored power coefficients p[0, S) -> dense Bernstein tensor t[0, C)
+// (C = (D+1)^n; didx gives each stored coefficient's dense position, the
+// others are zero). Returns the team-wide sum of |p| and the extrema.
 template <int D, typename T, class Team>
-__device__ void team_convert(double *t, const T *p, int C, int n, const Team &tm, double &l1, double &vmin,
-                             double &vmax) {
-  constexpr int D1 = D + 1;
-  constexpr int NR = 24 / D1 > 0 ? 24 / D1 : 1;  // fibres per thread whose loads are in flight together
-  const int F = C / D1;
+__device__ void team_convert(double *t, const T *p, const int *didx, int C, int S, int n, const Team &tm,
+                             double &l1, double &vmin, double &vmax) {
+  for (int i = tm.tid; i < C; i += tm.nt) t[i] = 0.0;
+  tm.sync();
   double s = 0.0, mn = INFINITY, mx = -INFINITY;
-  for (int f0 = tm.tid; f0 < F; f0 += NR * tm.nt) {
-    T r[NR][D1];
-#pragma unroll
-    for (int u = 0; u < NR; ++u) {
-      const int f = f0 + u * tm.nt;
-      if (f < F) {
-#pragma unroll
-        for (int j = 0; j < D1; ++j) r[u][j] = p[f * D1 + j];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < NR; ++u) {
-      const int f = f0 + u * tm.nt;
-      if (f < F) {
-        double x[D1];
-#pragma unroll
-        for (int j = 0; j < D1; ++j) {
-          x[j] = (double)r[u][j];
-          s += fabs(x[j]);
-        }
-        to_bern<D>(x);
-#pragma unroll
-        for (int j = 0; j < D1; ++j) {
-          if (n == 1) {
-            mn = fmin(mn, x[j]);
-            mx = fmax(mx, x[j]);
-          }
-          t[f * D1 + j] = x[j];
-        }
-      }
-    }
+  for (int i = tm.tid; i < S; i += tm.nt) {
+    const double x = (double)p[i];
+    t[didx[i]] = x;
+    s += fabs(x);
   }
-  team_axes<D>(t, C, D1, n - 1, tm, true, mn, mx);
+  team_axes<D>(t, C, 1, n, tm, true, mn, mx);
   l1 = tm.sum(s);
   vmin = tm.min(mn);
   vmax = tm.max(mx);
@@ -669,10 +650,11 @@ __global__ void __launch_bounds__(kBlock) convert_wave_t(ConvertArgs a) {
   if (item >= a.nboxes * a.h) return;
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
   const int j = (int)(item % a.h);
-  const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + (int64_t)j * 2 * a.C;
+  const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + (int64_t)j * 2 * a.S;
+  const int S = (int)a.S;
   double l1L, l1U, mn, mx, dummy;
-  team_convert<D>(tw, p + a.C, C, a.n, tm, l1L, mn, dummy);
-  team_convert<D>(tw + C, p, C, a.n, tm, l1U, dummy, mx);
+  team_convert<D>(tw, p + S, a.didx, C, S, a.n, tm, l1L, mn, dummy);
+  team_convert<D>(tw + C, p, a.didx, C, S, a.n, tm, l1U, dummy, mx);
   double epsU = 0.0, epsL = 0.0;
   if (!a.fp64) pre_radii(a, box, j, a.pre, tm.tid, 64, [&](double v) { return tm.sum(v); }, epsU, epsL);
   const double lo = side_lo(a, mn, l1L, epsL), hi = side_hi(a, mx, l1U, epsU);
@@ -700,18 +682,19 @@ __global__ void __launch_bounds__(1024) convert_block_t(ConvertArgs a) {
   const int64_t item = blockIdx.x;
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
   const int j = (int)(item % a.h);
-  const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + (int64_t)j * 2 * a.C;
+  const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + (int64_t)j * 2 * a.S;
+  const int S = (int)a.S;
   double epsU = 0.0, epsL = 0.0;
   if (!a.fp64) pre_radii(a, box, j, a.pre, tm.tid, tm.nt, [&](double v) { return tm.sum(v); }, epsU, epsL);
   const bool want = wants_fit(a, box, j);
   NeuronRec *rec = want ? &a.recs[box * a.h + j] : nullptr;
   double fx[4] = {0.0, 0.0, 0.0, 0.0};
   double l1L, l1U, mn, mx, dummy;
-  team_convert<D>(t, p + a.C, C, a.n, tm, l1L, mn, dummy);
+  team_convert<D>(t, p + S, a.didx, C, S, a.n, tm, l1L, mn, dummy);
   const double lo = side_lo(a, mn, l1L, epsL);
   if (want && (a.fits || lo < 0.0)) team_fit<D>(t, C, a.n, tm, rec->fitL, fx[2], fx[3]);
   tm.sync();
-  team_convert<D>(t, p, C, a.n, tm, l1U, dummy, mx);
+  team_convert<D>(t, p, a.didx, C, S, a.n, tm, l1U, dummy, mx);
   const double hi = side_hi(a, mx, l1U, epsU);
   const bool fitted = want && (a.fits || (lo < 0.0 && hi > 0.0));
   if (fitted) team_fit<D>(t, C, a.n, tm, rec->fitU, fx[0], fx[1]);
@@ -724,7 +707,7 @@ static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
     const size_t lds = (size_t)(kBlock / 64) * 2 * a.C * sizeof(double);
     RET_IF(hipFuncSetAttribute((const void *)convert_wave_t<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
-    ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.C * (a.fp64 ? 8 : 4));
+    ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4));
     const int64_t items = a.nboxes * a.h;
     hipLaunchKernelGGL((convert_wave_t<D, T>), dim3((unsigned)((items + kBlock / 64 - 1) / (kBlock / 64))),
                        dim3(kBlock), lds, s, a);
@@ -737,7 +720,7 @@ static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
   static const unsigned kThreads[4] = {0, 256, 512, 1024};
   const unsigned threads = a.tune.conv_block > 0 && a.tune.conv_block < 4 ? kThreads[a.tune.conv_block]
                                                                           : (lds > 40 * 1024 ? 1024 : 256);
-  ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.C * (a.fp64 ? 8 : 4));
+  ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4));
   hipLaunchKernelGGL((convert_block_t<D, T>), dim3((unsigned)(a.nboxes * a.h)), dim3(threads), lds, s, a);
   return hipGetLastError();
 }
@@ -802,11 +785,18 @@ __global__ void __launch_bounds__(kBlock) convert_passA_kernel(ConvertArgs a, Sp
   double *red = tab + D1 * D1;
   const int64_t gb = tensor / (2 * a.h), rest = tensor % (2 * a.h);
   const int64_t box = a.bids ? a.bids[gb] : gb;
-  const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + rest * a.C + o * sp.Ci;
+  const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + rest * a.S;
+  for (int64_t i = threadIdx.x; i < sp.Ci; i += blockDim.x) t[i] = 0.0;
+  __syncthreads();
+  // the stored coefficients whose leading (outer) digits are those of slice o
   double l1 = 0.0;
-  for (int64_t i = threadIdx.x; i < sp.Ci; i += blockDim.x) {
-    t[i] = (double)p[i];
-    l1 += fabs(t[i]);
+  for (int64_t i = threadIdx.x; i < a.S; i += blockDim.x) {
+    const int64_t d = a.didx[i];
+    if (d / sp.Ci == o) {
+      const double v = (double)p[i];
+      t[d - o * sp.Ci] = v;
+      l1 += fabs(v);
+    }
   }
   l1 = block_reduce(l1, OpAdd(), red);
   lds_basis_change(t, sp.Ci, sp.m, a.D, 0, sp.m, tab);
@@ -916,7 +906,7 @@ hipError_t launch_convert(const ConvertArgs &a, hipStream_t s) {
     const size_t lds = (D1 * D1 + (kBlock / 64) * 2 * a.C) * sizeof(double);
     auto k = a.fp64 ? convert_wave_kernel<double> : convert_wave_kernel<float>;
     RET_IF(hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.C * (a.fp64 ? 8 : 4));
+    ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4));
     const int64_t items = a.nboxes * a.h;
     hipLaunchKernelGGL(k, dim3((unsigned)((items + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), lds, s, a);
     return hipGetLastError();
@@ -925,7 +915,7 @@ hipError_t launch_convert(const ConvertArgs &a, hipStream_t s) {
     const size_t lds = (a.C + D1 * D1 + 16) * sizeof(double);
     auto k = a.fp64 ? convert_small_kernel<double> : convert_small_kernel<float>;
     RET_IF(hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.C * (a.fp64 ? 8 : 4));
+    ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4));
     hipLaunchKernelGGL(k, dim3((unsigned)(a.nboxes * a.h)), dim3(kBlock), lds, s, a);
     return hipGetLastError();
   }
@@ -940,7 +930,7 @@ hipError_t launch_convert(const ConvertArgs &a, hipStream_t s) {
     const size_t lds = (sp.Ci + D1 * D1 + 16) * sizeof(double);
     auto k = a.fp64 ? convert_passA_kernel<double> : convert_passA_kernel<float>;
     RET_IF(hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    ProfScope ps(kProfConvertPassA, s, (double)tensors * a.C * ((a.fp64 ? 8 : 4) + 8));
+    ProfScope ps(kProfConvertPassA, s, (double)tensors * (a.S * (a.fp64 ? 8 : 4) + a.C * 8));
     hipLaunchKernelGGL(k, dim3((unsigned)sp.Co, (unsigned)tensors), dim3(kBlock), lds, s, a, sp, l1part);
   }
   {

@@ -1,0 +1,163 @@
+// Host-side index tables of the total-degree coefficient layout.
+#include "simplex.hpp"
+#include "common.hpp"
+
+#include <algorithm>
+
+namespace bern {
+
+static int64_t binom64(int64_t n, int64_t k) {
+  if (k < 0 || n < 0 || k > n) return 0;
+  if (k > n - k) k = n - k;
+  int64_t r = 1;
+  for (int64_t i = 1; i <= k; ++i) r = r * (n - k + i) / i;  // exact at every step
+  return r;
+}
+
+int64_t ssize(int n, int D, int64_t cap) {
+  if (D < 0) return 0;
+  // C(n + D, n) = prod_{i=1..k} (n + D - k + i) / i, k = min(n, D); every
+  // partial product is itself a binomial coefficient, so the division is
+  // exact, and r <= cap < 2^41 keeps r * f far from overflow
+  int64_t r = 1;
+  const int k = std::min(n, D);
+  for (int i = 1; i <= k; ++i) {
+    r = r * ((int64_t)n + D - k + i) / i;
+    if (r > cap) return -1;
+  }
+  return r;
+}
+
+static void enum_degree(int n, int d, int pos, std::vector<uint16_t> &cur, std::vector<uint16_t> &out) {
+  if (pos == n - 1) {
+    cur[pos] = (uint16_t)d;
+    out.insert(out.end(), cur.begin(), cur.end());
+    return;
+  }
+  for (int v = d; v >= 0; --v) {  // descending lexicographic
+    cur[pos] = (uint16_t)v;
+    enum_degree(n, d - v, pos + 1, cur, out);
+  }
+}
+
+std::vector<uint16_t> simplex_exponents(int n, int D) {
+  std::vector<uint16_t> out, cur(n, 0);
+  for (int d = 0; d <= D; ++d) enum_degree(n, d, 0, cur, out);
+  return out;
+}
+
+int64_t simplex_rank(int n, const uint16_t *e) {
+  int d = 0;
+  for (int i = 0; i < n; ++i) d += e[i];
+  int64_t r = d > 0 ? binom64(n + d - 1, n) : 0;  // all monomials of total degree < d
+  int rem = d;
+  for (int i = 0; i + 1 < n; ++i) {
+    const int m = n - 2 - i;  // digits after position i, minus the last
+    for (int v = e[i] + 1; v <= rem; ++v) r += binom64(rem - v + m, m);
+    rem -= e[i];
+  }
+  return r;
+}
+
+SimplexTables::~SimplexTables() {
+  for (auto &kv : dense) (void)hipFree(kv.second);
+  for (auto &kv : prod) {
+    (void)hipFree(kv.second.off);
+    (void)hipFree(kv.second.pairs);
+    (void)hipFree(kv.second.diag);
+  }
+}
+
+hipError_t dense_index_table(SimplexTables &t, int D, const int **out) {
+  std::lock_guard<std::mutex> g(t.mu);
+  auto it = t.dense.find(D);
+  if (it != t.dense.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  const int n = t.n;
+  const int64_t S = ssize(n, D, (int64_t)1 << 31);
+  if (S < 0) return hipErrorInvalidValue;
+  double dense = 1.0;
+  for (int a = 0; a < n; ++a) dense *= D + 1;
+  if (dense > 2147483647.0) return hipErrorInvalidValue;
+  const std::vector<uint16_t> e = simplex_exponents(n, D);
+  std::vector<int> idx(S);
+  for (int64_t r = 0; r < S; ++r) {
+    int64_t v = 0;
+    for (int a = 0; a < n; ++a) v = v * (D + 1) + e[r * n + a];
+    idx[r] = (int)v;
+  }
+  int *d = nullptr;
+  RET_IF(hipMalloc(&d, S * sizeof(int)));
+  hipError_t err = hipMemcpy(d, idx.data(), S * sizeof(int), hipMemcpyHostToDevice);
+  if (err != hipSuccess) {
+    (void)hipFree(d);
+    return err;
+  }
+  t.dense[D] = d;
+  *out = d;
+  return hipSuccess;
+}
+
+hipError_t product_table(SimplexTables &t, int da, int db, bool sym, const ProdTable **out) {
+  std::lock_guard<std::mutex> g(t.mu);
+  const auto key = std::make_tuple(da, db, sym ? 1 : 0);
+  auto it = t.prod.find(key);
+  if (it != t.prod.end()) {
+    *out = &it->second;
+    return hipSuccess;
+  }
+  if (sym && da != db) return hipErrorInvalidValue;
+  const int n = t.n;
+  const int64_t Sa = ssize(n, da, (int64_t)1 << 31), Sb = ssize(n, db, (int64_t)1 << 31);
+  const int64_t Sc = ssize(n, da + db, (int64_t)1 << 31);
+  if (Sa < 0 || Sb < 0 || Sc < 0 || (sym ? Sa * (Sa - 1) / 2 : Sa * Sb) > kMaxPairs) return hipErrorInvalidValue;
+  const std::vector<uint16_t> ea = simplex_exponents(n, da), eb = simplex_exponents(n, db);
+  std::vector<int64_t> cnt(Sc + 1, 0);
+  std::vector<int> diag(sym ? Sc : 0, -1);
+  std::vector<uint16_t> k(n);
+  std::vector<int> rk((size_t)Sa * (size_t)Sb, -1);  // output rank of every listed pair
+  for (int64_t i = 0; i < Sa; ++i) {
+    for (int64_t j = sym ? i : 0; j < Sb; ++j) {
+      for (int q = 0; q < n; ++q) k[q] = (uint16_t)(ea[i * n + q] + eb[j * n + q]);
+      const int64_t r = simplex_rank(n, k.data());
+      if (sym && i == j) {
+        diag[r] = (int)i;
+        continue;
+      }
+      rk[(size_t)i * Sb + j] = (int)r;
+      ++cnt[r + 1];
+    }
+  }
+  for (int64_t r = 0; r < Sc; ++r) cnt[r + 1] += cnt[r];
+  const int64_t P = cnt[Sc];
+  std::vector<int> off(Sc + 1);
+  for (int64_t r = 0; r <= Sc; ++r) off[r] = (int)cnt[r];
+  std::vector<int2> pairs(std::max<int64_t>(P, 1));
+  std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+  for (int64_t i = 0; i < Sa; ++i)
+    for (int64_t j = sym ? i + 1 : 0; j < Sb; ++j) {
+      const int r = rk[(size_t)i * Sb + j];
+      pairs[fill[r]++] = make_int2((int)i, (int)j);
+    }
+  ProdTable pt;
+  pt.npairs = P;
+  hipError_t err = hipMalloc(&pt.off, (Sc + 1) * sizeof(int));
+  if (err == hipSuccess) err = hipMalloc(&pt.pairs, pairs.size() * sizeof(int2));
+  if (err == hipSuccess && sym) err = hipMalloc(&pt.diag, Sc * sizeof(int));
+  if (err == hipSuccess) err = hipMemcpy(pt.off, off.data(), (Sc + 1) * sizeof(int), hipMemcpyHostToDevice);
+  if (err == hipSuccess) err = hipMemcpy(pt.pairs, pairs.data(), pairs.size() * sizeof(int2), hipMemcpyHostToDevice);
+  if (err == hipSuccess && sym) err = hipMemcpy(pt.diag, diag.data(), Sc * sizeof(int), hipMemcpyHostToDevice);
+  if (err != hipSuccess) {
+    (void)hipFree(pt.off);
+    (void)hipFree(pt.pairs);
+    (void)hipFree(pt.diag);
+    return err;
+  }
+  auto res = t.prod.emplace(key, pt);
+  *out = &res.first->second;
+  return hipSuccess;
+}
+
+}  // namespace bern

@@ -1,0 +1,60 @@
+"""What the trained degree predictor gains, on the held-out network of the
+predictor workload ([6,64,64,64,4], half-width 0.05, L = 2), on 256 of its
+boxes: batched runs under the learned plan, under a fixed order 1 for every
+unstable neuron and under a fixed order 2 (the stable-neuron rule of the
+plain method). The learned plan must sit on the good side of both: within
+10 % of the fixed-order-2 mean output width at a fraction of its time, and
+tighter than fixed order 1."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2211_14438_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2211_14438_amd import bernnn as B  # noqa: E402
+from paper_2211_14438_amd import predictor as PR  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _run(net, lo, hi, reps, **kw):
+    r = B.bounds(net, lo, hi, L=2, precision="fp32", sched="batched", **kw)  # warm-up, buffers
+    kw.update(outputs={k: r[k] for k in ("neuron_lo", "neuron_hi", "out_lo", "out_hi", "used_plan")},
+              workspace=r["workspace"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        B.bounds(net, lo, hi, L=2, precision="fp32", sched="batched", **kw)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    width = float((r["out_hi"] - r["out_lo"]).mean().item())
+    return ms, width
+
+
+def test_learned_plan_beats_fixed_orders():
+    case = wl.cfg5(n_boxes=256)
+    print(f"case {case.name}", flush=True)
+    net = B.Net(case.Ws, case.bs)
+    lo = torch.tensor(case.box_lo, dtype=torch.float64, device=DEV)
+    hi = torch.tensor(case.box_hi, dtype=torch.float64, device=DEV)
+    pred = B.Predictor(PR.load()[0])
+    shape = (case.n_boxes, sum(case.widths[1:-1]))
+    res = {}
+    res["learned"] = _run(net, lo, hi, 5, plan="learned", pred=pred)
+    for k in (1, 2):
+        plan = torch.full(shape, k, dtype=torch.int8, device=DEV)
+        res[f"fixed{k}"] = _run(net, lo, hi, 2 if k == 2 else 5, plan="given", degree_plan=plan)
+    print({k: (round(v[0], 2), round(v[1], 5)) for k, v in res.items()}, flush=True)
+    (t_l, w_l), (t_1, w_1), (t_2, w_2) = res["learned"], res["fixed1"], res["fixed2"]
+    assert w_l <= 1.10 * w_2
+    assert t_l < 0.5 * t_2
+    assert w_l < w_1
+    pred.close()
+    net.close()
