@@ -83,9 +83,9 @@ ProfScope::~ProfScope() {
 }
 
 static const char *kProfNames[kProfCount] = {
-    "layer1",         "gemm",         "convert_small",  "convert_passA",  "convert_passB", "convert_final",
-    "compose_scatter", "compose_fill", "compose_square", "compose_horner", "poly_mul",      "predictor",
-    "misc"};
+    "layer1",          "gemm",         "convert_small",  "convert_passA",  "convert_passB", "convert_final",
+    "convert_chunk",   "compose_scatter", "compose_fill", "compose_square", "compose_horner", "poly_mul",
+    "predictor",       "misc"};
 
 size_t device_lds_limit() {
   static std::mutex mu;
@@ -437,12 +437,15 @@ __global__ void box_degree_kernel(int64_t nb, int h, const NeuronRec *recs, int 
 // Horner tables (Din, m Din), m = 1 .. Lmax - 1. Built once per network.
 struct LayerTables {
   const int *didx = nullptr;
+  const SliceTable *sl = nullptr;
   const ProdTable *sq = nullptr;
   const ProdTable *hz[kMaxOrder] = {};
 };
 
 static bern_status layer_tables(const bern_net *net, int Din, int Lmax, bool compose, LayerTables &t) {
   hipError_t e = dense_index_table(*net->tab, Din, &t.didx);
+  const int tm = convert_tile_m(net->n, Din);
+  if (e == hipSuccess && tm >= 0) e = slice_table(*net->tab, Din, tm, &t.sl);
   if (e == hipSuccess && compose && Lmax >= 2) e = product_table(*net->tab, Din, Din, true, &t.sq);
   for (int m = 1; e == hipSuccess && compose && m <= Lmax - 1 && Lmax >= 3; ++m)
     e = product_table(*net->tab, Din, m * Din, false, &t.hz[m]);
@@ -553,6 +556,11 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       c.C = ipow(cl.Din + 1, n);
       c.S = ssize(n, cl.Din);
       c.didx = lt.didx;
+      if (lt.sl) {
+        c.sl_off = lt.sl->off;
+        c.sl_rank = lt.sl->rank;
+        c.sl_dig = lt.sl->dig;
+      }
       c.nboxes = (int64_t)cl.ids.size();
       c.bids = cid[k];
       c.slot = slotA;

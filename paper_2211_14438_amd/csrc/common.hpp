@@ -104,6 +104,7 @@ enum ProfClass : int {
   kProfConvertPassA,
   kProfConvertPassB,
   kProfConvertFinal,
+  kProfConvertChunk,
   kProfComposeSimple,
   kProfComposeFill,
   kProfComposeSquare,
@@ -207,12 +208,20 @@ struct ConvertArgs {
   int learned;                    // rules are chosen later by the predictor (fits always needed)
   int fits;                       // compute the affine fits of every hidden neuron (features)
   int mode;                       // 0 hidden layer, 1 output layer
-  double *scratch;                // FP64 staging for tensors too large for LDS
+  double *scratch;                // staging and partial extrema for tensors too large for LDS
   size_t scratch_bytes;
   Tune tune;
+  // tensors beyond LDS: stored coefficients grouped by leading exponents
+  // (simplex.hpp SliceTable for the split convert_tile_m(n, D)), or null
+  const int *sl_off;
+  const int *sl_rank;
+  const unsigned long long *sl_dig;
+  int gextra;                     // rounding steps beyond the per-axis basis change (set by the launcher)
 };
 hipError_t launch_convert(const ConvertArgs &a, hipStream_t s);
 size_t convert_scratch_bytes(int n, int D, int h, int64_t nboxes);
+// Trailing axes of the staging-free path for tensors beyond LDS, or -1.
+int convert_tile_m(int n, int D);
 
 struct ComposeArgs {
   int n, Din, Dout, h;

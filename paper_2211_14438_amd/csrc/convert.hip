@@ -24,6 +24,7 @@
 // c_j = C(L,j) Delta^j b_0, and its value e at y = 0 (Prop. 2).
 #include "common.hpp"
 #include "rules.hpp"
+#include "simplex.hpp"
 
 namespace bern {
 
@@ -199,7 +200,7 @@ __device__ void padded_bounds(const ConvertArgs &a, int64_t box, int j, double m
   epsU = epsL = 0.0;
   if (a.fp64) return;
   pre_radii(a, box, j, a.pre, tid, nt, reduce, epsU, epsL);
-  const double g = gamma64((double)a.n * (a.D + 2) + 4);
+  const double g = gamma64((double)a.n * (a.D + 2) + 4 + a.gextra);
   lo = round_down(mn - g * l1L - epsL);
   hi = round_up(mx + g * l1U + epsU);
 }
@@ -615,11 +616,11 @@ __device__ void team_fit(const double *t, int C, int n, const Team &tm, double *
 // basis-change rounding and the pre-activation radius, rounded outward).
 __device__ inline double side_lo(const ConvertArgs &a, double mn, double l1, double eps) {
   if (a.fp64) return mn;
-  return round_down(mn - gamma64((double)a.n * (a.D + 2) + 4) * l1 - eps);
+  return round_down(mn - gamma64((double)a.n * (a.D + 2) + 4 + a.gextra) * l1 - eps);
 }
 __device__ inline double side_hi(const ConvertArgs &a, double mx, double l1, double eps) {
   if (a.fp64) return mx;
-  return round_up(mx + gamma64((double)a.n * (a.D + 2) + 4) * l1 + eps);
+  return round_up(mx + gamma64((double)a.n * (a.D + 2) + 4 + a.gextra) * l1 + eps);
 }
 
 __device__ inline bool wants_fit(const ConvertArgs &a, int64_t box, int j) {
@@ -699,6 +700,106 @@ __global__ void __launch_bounds__(1024) convert_block_t(ConvertArgs a) {
   const bool fitted = want && (a.fits || (lo < 0.0 && hi > 0.0));
   if (fitted) team_fit<D>(t, C, a.n, tm, rec->fitU, fx[0], fx[1]);
   if (tm.tid == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted);
+}
+
+// Tensors beyond one block's LDS, without staging: the first m axes are
+// fixed per block (chunk k = the dense index of their exponents) and the
+// block converts the (D+1)^(n-m) tensor of the trailing axes in LDS. The
+// basis change is a product over axes, so the chunk's slice of Bernstein
+// coefficients is the trailing-axes basis change of
+//   g(c) = sum over stored J with trailing exponents c of
+//          a_J prod_{i<m} C(k_i, j_i) / C(D, j_i)
+// (the cell table lists the J of each c; a factor with j_i > k_i is zero).
+// Its extremum goes to the partials, the l1 norm once per tensor. The sums
+// over J add at most S rounding steps (ConvertArgs::gextra).
+struct Chunking {
+  int lead;       // axes fixed per block
+  int64_t cells;  // (D+1)^(n - lead)
+  int64_t nchunk; // (D+1)^lead
+};
+
+template <int D, typename T>
+__global__ void __launch_bounds__(1024) convert_chunk_t(ConvertArgs a, Chunking ck, double *partial,
+                                                        double *l1part) {
+  extern __shared__ double lds[];
+  __shared__ double red[16];
+  constexpr int D1 = D + 1;
+  const BlockTeam tm{(int)threadIdx.x, (int)blockDim.x, red};
+  const int Ct = (int)ck.cells, S = (int)a.S;
+  double *t = lds;          // [Ct]
+  double *av = t + Ct;      // [S]
+  double *tab = av + S;     // [D1][D1] C(k,j)/C(D,j)
+  const int64_t tensor = blockIdx.y;
+  const int s = (int)(tensor & 1);
+  const int64_t k = blockIdx.x;
+  const int64_t gb = tensor / (2 * a.h), rest = tensor % (2 * a.h);
+  const int64_t box = a.bids ? a.bids[gb] : gb;
+  const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + rest * a.S;
+  double l1 = 0.0;
+  for (int i = tm.tid; i < S; i += tm.nt) {
+    const double v = (double)p[i];
+    av[i] = v;
+    l1 += fabs(v);
+  }
+  for (int i = tm.tid; i < D1 * D1; i += tm.nt) {
+    const int kk = i / D1, jj = i % D1;
+    tab[i] = jj <= kk ? binom_d(kk, jj) / binom_d(D, jj) : 0.0;
+  }
+  unsigned long long kq = 0;  // exponents of the fixed axes, axis i at bits 4i
+  {
+    int64_t rem = k;
+    for (int i = ck.lead - 1; i >= 0; --i) {
+      kq |= (unsigned long long)(rem % D1) << (4 * i);
+      rem /= D1;
+    }
+  }
+  tm.sync();
+  for (int c = tm.tid; c < Ct; c += tm.nt) {
+    double g = 0.0;
+    const int end = a.sl_off[c + 1];
+    for (int te = a.sl_off[c]; te < end; ++te) {
+      const unsigned long long jq = a.sl_dig[te];
+      double w = av[a.sl_rank[te]];
+      for (int i = 0; i < ck.lead; ++i) w *= tab[(int)((kq >> (4 * i)) & 15) * D1 + (int)((jq >> (4 * i)) & 15)];
+      g += w;
+    }
+    t[c] = g;
+  }
+  double mn = INFINITY, mx = -INFINITY;
+  team_axes<D>(t, Ct, 1, a.n - ck.lead, tm, true, mn, mx);
+  const double v = s ? tm.min(mn) : tm.max(mx);
+  if (tm.tid == 0) partial[tensor * ck.nchunk + k] = v;
+  if (k == 0) {
+    l1 = tm.sum(l1);
+    if (tm.tid == 0) l1part[tensor] = l1;
+  }
+}
+
+template <typename T, int D>
+static hipError_t launch_chunk_t(const ConvertArgs &a, const Chunking &ck, size_t lds, double *partial,
+                                 double *l1part, hipStream_t s) {
+  RET_IF(hipFuncSetAttribute((const void *)convert_chunk_t<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds));
+  const unsigned threads = lds > 40 * 1024 ? 1024 : 256;
+  hipLaunchKernelGGL((convert_chunk_t<D, T>), dim3((unsigned)ck.nchunk, (unsigned)(a.nboxes * a.h * 2)),
+                     dim3(threads), lds, s, a, ck, partial, l1part);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_chunk(const ConvertArgs &a, const Chunking &ck, size_t lds, double *partial, double *l1part,
+                               hipStream_t s) {
+  switch (a.D) {
+    case 1: return launch_chunk_t<T, 1>(a, ck, lds, partial, l1part, s);
+    case 2: return launch_chunk_t<T, 2>(a, ck, lds, partial, l1part, s);
+    case 3: return launch_chunk_t<T, 3>(a, ck, lds, partial, l1part, s);
+    case 4: return launch_chunk_t<T, 4>(a, ck, lds, partial, l1part, s);
+    case 5: return launch_chunk_t<T, 5>(a, ck, lds, partial, l1part, s);
+    case 6: return launch_chunk_t<T, 6>(a, ck, lds, partial, l1part, s);
+    case 7: return launch_chunk_t<T, 7>(a, ck, lds, partial, l1part, s);
+    case 8: return launch_chunk_t<T, 8>(a, ck, lds, partial, l1part, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <typename T, int D>
@@ -889,9 +990,47 @@ static bool use_small(int64_t C) {
   return C <= kSmallLds && C <= fit;
 }
 
+// Chunking of the staging-free path for tensors beyond one block's LDS:
+// the fewest leading axes whose fixing leaves a trailing tensor of at most
+// kSmallLds coefficients that fits LDS with the stored coefficients and the
+// ratio table. lead = 0 when the path does not apply (D > 8 or too large).
+static Chunking chunking(int n, int D) {
+  Chunking ck{0, 0, 0};
+  if (D < 1 || D > 8) return ck;
+  const int64_t S = ssize(n, D, (int64_t)1 << 31);
+  if (S < 0) return ck;
+  const size_t limit = device_lds_limit();
+  for (int lead = 1; lead < n && lead <= 16; ++lead) {
+    const int64_t cells = ipow(D + 1, n - lead);
+    const size_t bytes = (size_t)(cells + S + (D + 1) * (D + 1)) * sizeof(double);
+    if (cells <= kSmallLds && bytes <= limit) {
+      ck.lead = lead;
+      ck.cells = cells;
+      ck.nchunk = ipow(D + 1, lead);
+      return ck;
+    }
+  }
+  return ck;
+}
+
+static size_t chunk_lds(const Chunking &ck, int64_t S, int D) {
+  return (size_t)(ck.cells + S + (D + 1) * (D + 1)) * sizeof(double);
+}
+
+int convert_tile_m(int n, int D) {
+  const int64_t C = tsize(n, D);
+  if (C < 0 || use_small(C)) return -1;
+  const Chunking ck = chunking(n, D);
+  return ck.lead > 0 ? ck.lead : -1;
+}
+
 size_t convert_scratch_bytes(int n, int D, int h, int64_t nboxes) {
   const int64_t C = ipow(D + 1, n);
   if (use_small(C)) return 0;
+  const Chunking ck = chunking(n, D);
+  if (ck.lead > 0)
+    return align256((size_t)nboxes * h * 2 * ck.nchunk * sizeof(double)) +
+           align256((size_t)nboxes * h * 2 * sizeof(double));
   const Split sp = make_split(n, D);
   return align256((size_t)nboxes * h * 2 * C * sizeof(double)) +
          align256((size_t)nboxes * h * 2 * sp.nchunk * sizeof(double)) +
@@ -919,13 +1058,34 @@ hipError_t launch_convert(const ConvertArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k, dim3((unsigned)(a.nboxes * a.h)), dim3(kBlock), lds, s, a);
     return hipGetLastError();
   }
+  const int64_t tensors = a.nboxes * a.h * 2;
+  const Chunking ck = chunking(a.n, a.D);
+  if (ck.lead > 0) {  // the workspace holds no staging for this shape
+    if (!a.sl_off) return hipErrorInvalidValue;
+    ConvertArgs b = a;
+    b.gextra = (int)a.S;
+    double *partial = a.scratch;
+    double *l1part = reinterpret_cast<double *>(reinterpret_cast<char *>(partial) +
+                                                align256((size_t)a.nboxes * a.h * 2 * ck.nchunk * sizeof(double)));
+    {
+      ProfScope ps(kProfConvertChunk, s, (double)tensors * a.S * (a.fp64 ? 8 : 4));
+      RET_IF(a.fp64 ? launch_chunk<double>(b, ck, chunk_lds(ck, a.S, a.D), partial, l1part, s)
+                    : launch_chunk<float>(b, ck, chunk_lds(ck, a.S, a.D), partial, l1part, s));
+    }
+    Split fsp{};
+    fsp.nchunk = ck.nchunk;
+    fsp.Co = 1;
+    ProfScope ps(kProfConvertFinal, s, (double)tensors * ck.nchunk * 8);
+    hipLaunchKernelGGL(convert_final_kernel, dim3((unsigned)((a.nboxes * a.h + 3) / 4)), dim3(kBlock), 0, s, b, fsp,
+                       (const double *)partial, (const double *)l1part);
+    return hipGetLastError();
+  }
   const Split sp = make_split(a.n, a.D);
   if (sp.Co > tile_elems(a.D)) return hipErrorInvalidValue;
   double *partial = reinterpret_cast<double *>(reinterpret_cast<char *>(a.scratch) +
                                                align256((size_t)a.nboxes * a.h * 2 * a.C * sizeof(double)));
   double *l1part = reinterpret_cast<double *>(reinterpret_cast<char *>(partial) +
                                               align256((size_t)a.nboxes * a.h * 2 * sp.nchunk * sizeof(double)));
-  const int64_t tensors = a.nboxes * a.h * 2;
   {
     const size_t lds = (sp.Ci + D1 * D1 + 16) * sizeof(double);
     auto k = a.fp64 ? convert_passA_kernel<double> : convert_passA_kernel<float>;

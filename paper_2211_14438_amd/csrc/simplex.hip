@@ -66,6 +66,66 @@ SimplexTables::~SimplexTables() {
     (void)hipFree(kv.second.pairs);
     (void)hipFree(kv.second.diag);
   }
+  for (auto &kv : slices) {
+    (void)hipFree(kv.second.off);
+    (void)hipFree(kv.second.rank);
+    (void)hipFree(kv.second.dig);
+  }
+}
+
+hipError_t slice_table(SimplexTables &t, int D, int m, const SliceTable **out) {
+  std::lock_guard<std::mutex> g(t.mu);
+  const auto key = std::make_pair(D, m);
+  auto it = t.slices.find(key);
+  if (it != t.slices.end()) {
+    *out = &it->second;
+    return hipSuccess;
+  }
+  const int n = t.n;
+  if (D > 15 || m < 0 || m > n || m > 16) return hipErrorInvalidValue;
+  const int64_t S = ssize(n, D, (int64_t)1 << 31);
+  double cc = 1.0;
+  for (int a = m; a < n; ++a) cc *= D + 1;
+  if (S < 0 || cc > 2147483647.0) return hipErrorInvalidValue;
+  const int64_t Cc = (int64_t)cc;
+  const std::vector<uint16_t> e = simplex_exponents(n, D);
+  std::vector<int64_t> cnt(Cc + 1, 0);
+  std::vector<int64_t> cell(S);
+  for (int64_t r = 0; r < S; ++r) {
+    int64_t c = 0;
+    for (int a = m; a < n; ++a) c = c * (D + 1) + e[r * n + a];
+    cell[r] = c;
+    ++cnt[c + 1];
+  }
+  for (int64_t c = 0; c < Cc; ++c) cnt[c + 1] += cnt[c];
+  std::vector<int> off(Cc + 1), rank(std::max<int64_t>(S, 1));
+  std::vector<unsigned long long> dig(std::max<int64_t>(S, 1));
+  for (int64_t c = 0; c <= Cc; ++c) off[c] = (int)cnt[c];
+  std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+  for (int64_t r = 0; r < S; ++r) {
+    unsigned long long pk = 0;
+    for (int i = 0; i < m; ++i) pk |= (unsigned long long)e[r * n + i] << (4 * i);
+    const int64_t at = fill[cell[r]]++;
+    rank[at] = (int)r;
+    dig[at] = pk;
+  }
+  SliceTable st;
+  hipError_t err = hipMalloc(&st.off, (Cc + 1) * sizeof(int));
+  if (err == hipSuccess) err = hipMalloc(&st.rank, rank.size() * sizeof(int));
+  if (err == hipSuccess) err = hipMalloc(&st.dig, dig.size() * sizeof(unsigned long long));
+  if (err == hipSuccess) err = hipMemcpy(st.off, off.data(), (Cc + 1) * sizeof(int), hipMemcpyHostToDevice);
+  if (err == hipSuccess) err = hipMemcpy(st.rank, rank.data(), rank.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (err == hipSuccess)
+    err = hipMemcpy(st.dig, dig.data(), dig.size() * sizeof(unsigned long long), hipMemcpyHostToDevice);
+  if (err != hipSuccess) {
+    (void)hipFree(st.off);
+    (void)hipFree(st.rank);
+    (void)hipFree(st.dig);
+    return err;
+  }
+  auto res = t.slices.emplace(key, st);
+  *out = &res.first->second;
+  return hipSuccess;
 }
 
 hipError_t dense_index_table(SimplexTables &t, int D, const int **out) {

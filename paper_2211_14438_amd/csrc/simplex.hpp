@@ -50,11 +50,23 @@ struct ProdTable {
   int64_t npairs = 0;
 };
 
+// Stored coefficients of degree D grouped by their trailing n-m exponents
+// (cell c = the dense index of those exponents in the (D+1)^(n-m) tensor of
+// the trailing axes): entries off[c] .. off[c+1] give the coefficient's rank
+// and its m leading exponents packed four bits each, axis i at bits 4i.
+// For D <= 15 and m <= 16.
+struct SliceTable {
+  int *off = nullptr;
+  int *rank = nullptr;
+  unsigned long long *dig = nullptr;
+};
+
 struct SimplexTables {
   int n = 0;
   std::mutex mu;
   std::map<int, int *> dense;                      // D -> [S(n,D)] index in the (D+1)^n tensor
   std::map<std::tuple<int, int, int>, ProdTable> prod;  // (da, db, sym)
+  std::map<std::pair<int, int>, SliceTable> slices;     // (D, m leading axes)
   ~SimplexTables();
 };
 
@@ -65,5 +77,6 @@ constexpr int64_t kMaxPairs = (int64_t)1 << 25;
 // table would exceed its limit, or the allocation / copy error.
 hipError_t dense_index_table(SimplexTables &t, int D, const int **out);
 hipError_t product_table(SimplexTables &t, int da, int db, bool sym, const ProdTable **out);
+hipError_t slice_table(SimplexTables &t, int D, int m, const SliceTable **out);
 
 }  // namespace bern
