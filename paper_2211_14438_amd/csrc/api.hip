@@ -557,6 +557,8 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       c.S = ssize(n, cl.Din);
       c.didx = lt.didx;
       if (lt.sl) {
+        c.sl_ncell = lt.sl->ncell;
+        c.sl_cell = lt.sl->cell;
         c.sl_off = lt.sl->off;
         c.sl_rank = lt.sl->rank;
         c.sl_dig = lt.sl->dig;

@@ -213,6 +213,8 @@ struct ConvertArgs {
   Tune tune;
   // tensors beyond LDS: stored coefficients grouped by leading exponents
   // (simplex.hpp SliceTable for the split convert_tile_m(n, D)), or null
+  int sl_ncell;
+  const int *sl_cell;
   const int *sl_off;
   const int *sl_rank;
   const unsigned long long *sl_dig;

@@ -487,6 +487,32 @@ struct BlockTeam {
   __device__ double max(double v) const { return block_reduce(v, OpMax(), red); }
 };
 
+// One axis pass: every fibre of D+1 coefficients at stride `st` converted in
+// registers. Fibre f has base (f / st) st (D+1) + f % st = f + (f / st) st D;
+// the quotient is one multiply-high by magic = floor((2^32 - 1) / st) + 1,
+// exact for f < 2^32 / st.
+template <int D, bool kTrack, class Team>
+__device__ __forceinline__ void axis_pass(double *t, int F, unsigned st, unsigned magic, const Team &tm, double &mn,
+                                          double &mx) {
+  constexpr int D1 = D + 1;
+  for (int f = tm.tid; f < F; f += tm.nt) {
+    const unsigned hi = st == 1 ? (unsigned)f : __umulhi((unsigned)f, magic);
+    const int base = f + (int)(hi * st) * D;
+    double x[D1];
+#pragma unroll
+    for (int j = 0; j < D1; ++j) x[j] = t[base + j * (int)st];
+    to_bern<D>(x);
+#pragma unroll
+    for (int j = 0; j < D1; ++j) {
+      if (kTrack) {
+        mn = fmin(mn, x[j]);
+        mx = fmax(mx, x[j]);
+      }
+      t[base + j * (int)st] = x[j];
+    }
+  }
+}
+
 // Convert axes [0, na) of a tensor already in LDS whose axis na-1 has stride
 // s0 (axis a has stride s0 (D+1)^(na-1-a)); `total` coefficients. Tracks the
 // extrema of the last pass when `track` is set.
@@ -498,23 +524,11 @@ __device__ void team_axes(double *t, int total, int s0, int na, const Team &tm, 
   unsigned stride = (unsigned)s0;
   for (int ax = na - 1; ax >= 0; --ax) {
     tm.sync();
-    const bool last = track && ax == 0;
-    for (int f = tm.tid; f < F; f += tm.nt) {
-      const unsigned hi = (unsigned)f / stride, lo = (unsigned)f - hi * stride;
-      const int base = (int)(hi * stride * D1 + lo);
-      double x[D1];
-#pragma unroll
-      for (int j = 0; j < D1; ++j) x[j] = t[base + j * (int)stride];
-      to_bern<D>(x);
-#pragma unroll
-      for (int j = 0; j < D1; ++j) {
-        if (last) {
-          mn = fmin(mn, x[j]);
-          mx = fmax(mx, x[j]);
-        }
-        t[base + j * (int)stride] = x[j];
-      }
-    }
+    const unsigned magic = stride > 1 ? 0xFFFFFFFFu / stride + 1u : 0u;
+    if (track && ax == 0)
+      axis_pass<D, true>(t, F, stride, magic, tm, mn, mx);
+    else
+      axis_pass<D, false>(t, F, stride, magic, tm, mn, mx);
     stride *= D1;
   }
   tm.sync();
@@ -709,13 +723,16 @@ __global__ void __launch_bounds__(1024) convert_block_t(ConvertArgs a) {
 // coefficients is the trailing-axes basis change of
 //   g(c) = sum over stored J with trailing exponents c of
 //          a_J prod_{i<m} C(k_i, j_i) / C(D, j_i)
-// (the cell table lists the J of each c; a factor with j_i > k_i is zero).
+// (the slice table lists the cells c that hold any J, and their J; a factor
+// with j_i > k_i is zero).
 // Its extremum goes to the partials, the l1 norm once per tensor. The sums
 // over J add at most S rounding steps (ConvertArgs::gextra).
 struct Chunking {
-  int lead;       // axes fixed per block
+  int lead;       // axes fixed per chunk
   int64_t cells;  // (D+1)^(n - lead)
   int64_t nchunk; // (D+1)^lead
+  int64_t per;    // chunks per block (set by the launcher)
+  int64_t groups; // blocks per tensor
 };
 
 template <int D, typename T>
@@ -729,9 +746,9 @@ __global__ void __launch_bounds__(1024) convert_chunk_t(ConvertArgs a, Chunking 
   double *t = lds;          // [Ct]
   double *av = t + Ct;      // [S]
   double *tab = av + S;     // [D1][D1] C(k,j)/C(D,j)
+  constexpr Ratio<D> R{};
   const int64_t tensor = blockIdx.y;
   const int s = (int)(tensor & 1);
-  const int64_t k = blockIdx.x;
   const int64_t gb = tensor / (2 * a.h), rest = tensor % (2 * a.h);
   const int64_t box = a.bids ? a.bids[gb] : gb;
   const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + rest * a.S;
@@ -741,35 +758,38 @@ __global__ void __launch_bounds__(1024) convert_chunk_t(ConvertArgs a, Chunking 
     av[i] = v;
     l1 += fabs(v);
   }
-  for (int i = tm.tid; i < D1 * D1; i += tm.nt) {
-    const int kk = i / D1, jj = i % D1;
-    tab[i] = jj <= kk ? binom_d(kk, jj) / binom_d(D, jj) : 0.0;
-  }
-  unsigned long long kq = 0;  // exponents of the fixed axes, axis i at bits 4i
-  {
-    int64_t rem = k;
-    for (int i = ck.lead - 1; i >= 0; --i) {
-      kq |= (unsigned long long)(rem % D1) << (4 * i);
-      rem /= D1;
-    }
-  }
-  tm.sync();
-  for (int c = tm.tid; c < Ct; c += tm.nt) {
-    double g = 0.0;
-    const int end = a.sl_off[c + 1];
-    for (int te = a.sl_off[c]; te < end; ++te) {
-      const unsigned long long jq = a.sl_dig[te];
-      double w = av[a.sl_rank[te]];
-      for (int i = 0; i < ck.lead; ++i) w *= tab[(int)((kq >> (4 * i)) & 15) * D1 + (int)((jq >> (4 * i)) & 15)];
-      g += w;
-    }
-    t[c] = g;
-  }
+  for (int i = tm.tid; i < D1 * D1; i += tm.nt) tab[i] = R.v[i / D1][i % D1];
   double mn = INFINITY, mx = -INFINITY;
-  team_axes<D>(t, Ct, 1, a.n - ck.lead, tm, true, mn, mx);
+  const int k0 = (int)(blockIdx.x * ck.per), k1 = (int)min(ck.nchunk, (int64_t)k0 + ck.per);
+  for (int k = k0; k < k1; ++k) {
+    unsigned long long kq = 0;  // exponents of the fixed axes, axis i at bits 4i
+    {
+      unsigned rem = (unsigned)k;
+      for (int i = ck.lead - 1; i >= 0; --i) {
+        kq |= (unsigned long long)(rem % D1) << (4 * i);
+        rem /= D1;
+      }
+    }
+    for (int c = tm.tid; c < Ct; c += tm.nt) t[c] = 0.0;
+    tm.sync();
+    // only the cells that hold stored coefficients receive a sum
+    for (int gi = tm.tid; gi < a.sl_ncell; gi += tm.nt) {
+      double g = 0.0;
+      const int end = a.sl_off[gi + 1];
+      for (int te = a.sl_off[gi]; te < end; ++te) {
+        const unsigned long long jq = a.sl_dig[te];
+        double w = av[a.sl_rank[te]];
+        for (int i = 0; i < ck.lead; ++i)
+          w *= tab[(int)((kq >> (4 * i)) & 15) * D1 + (int)((jq >> (4 * i)) & 15)];
+        g += w;
+      }
+      t[a.sl_cell[gi]] = g;
+    }
+    team_axes<D>(t, Ct, 1, a.n - ck.lead, tm, true, mn, mx);  // ends with a barrier
+  }
   const double v = s ? tm.min(mn) : tm.max(mx);
-  if (tm.tid == 0) partial[tensor * ck.nchunk + k] = v;
-  if (k == 0) {
+  if (tm.tid == 0) partial[tensor * ck.groups + blockIdx.x] = v;
+  if (blockIdx.x == 0) {
     l1 = tm.sum(l1);
     if (tm.tid == 0) l1part[tensor] = l1;
   }
@@ -781,7 +801,7 @@ static hipError_t launch_chunk_t(const ConvertArgs &a, const Chunking &ck, size_
   RET_IF(hipFuncSetAttribute((const void *)convert_chunk_t<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)lds));
   const unsigned threads = lds > 40 * 1024 ? 1024 : 256;
-  hipLaunchKernelGGL((convert_chunk_t<D, T>), dim3((unsigned)ck.nchunk, (unsigned)(a.nboxes * a.h * 2)),
+  hipLaunchKernelGGL((convert_chunk_t<D, T>), dim3((unsigned)ck.groups, (unsigned)(a.nboxes * a.h * 2)),
                      dim3(threads), lds, s, a, ck, partial, l1part);
   return hipGetLastError();
 }
@@ -995,7 +1015,7 @@ static bool use_small(int64_t C) {
 // kSmallLds coefficients that fits LDS with the stored coefficients and the
 // ratio table. lead = 0 when the path does not apply (D > 8 or too large).
 static Chunking chunking(int n, int D) {
-  Chunking ck{0, 0, 0};
+  Chunking ck{0, 0, 0, 1, 0};
   if (D < 1 || D > 8) return ck;
   const int64_t S = ssize(n, D, (int64_t)1 << 31);
   if (S < 0) return ck;
@@ -1007,6 +1027,7 @@ static Chunking chunking(int n, int D) {
       ck.lead = lead;
       ck.cells = cells;
       ck.nchunk = ipow(D + 1, lead);
+      ck.groups = ck.nchunk;
       return ck;
     }
   }
@@ -1059,9 +1080,13 @@ hipError_t launch_convert(const ConvertArgs &a, hipStream_t s) {
     return hipGetLastError();
   }
   const int64_t tensors = a.nboxes * a.h * 2;
-  const Chunking ck = chunking(a.n, a.D);
+  Chunking ck = chunking(a.n, a.D);
   if (ck.lead > 0) {  // the workspace holds no staging for this shape
     if (!a.sl_off) return hipErrorInvalidValue;
+    // several chunks per block, keeping some 8k blocks in flight
+    ck.groups = std::min<int64_t>(ck.nchunk, std::max<int64_t>(1, (8192 + tensors - 1) / tensors));
+    ck.per = (ck.nchunk + ck.groups - 1) / ck.groups;
+    ck.groups = (ck.nchunk + ck.per - 1) / ck.per;
     ConvertArgs b = a;
     b.gextra = (int)a.S;
     double *partial = a.scratch;
@@ -1073,7 +1098,7 @@ hipError_t launch_convert(const ConvertArgs &a, hipStream_t s) {
                     : launch_chunk<float>(b, ck, chunk_lds(ck, a.S, a.D), partial, l1part, s));
     }
     Split fsp{};
-    fsp.nchunk = ck.nchunk;
+    fsp.nchunk = ck.groups;
     fsp.Co = 1;
     ProfScope ps(kProfConvertFinal, s, (double)tensors * ck.nchunk * 8);
     hipLaunchKernelGGL(convert_final_kernel, dim3((unsigned)((a.nboxes * a.h + 3) / 4)), dim3(kBlock), 0, s, b, fsp,

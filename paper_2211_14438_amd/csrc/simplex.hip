@@ -67,6 +67,7 @@ SimplexTables::~SimplexTables() {
     (void)hipFree(kv.second.diag);
   }
   for (auto &kv : slices) {
+    (void)hipFree(kv.second.cell);
     (void)hipFree(kv.second.off);
     (void)hipFree(kv.second.rank);
     (void)hipFree(kv.second.dig);
@@ -87,37 +88,40 @@ hipError_t slice_table(SimplexTables &t, int D, int m, const SliceTable **out) {
   double cc = 1.0;
   for (int a = m; a < n; ++a) cc *= D + 1;
   if (S < 0 || cc > 2147483647.0) return hipErrorInvalidValue;
-  const int64_t Cc = (int64_t)cc;
   const std::vector<uint16_t> e = simplex_exponents(n, D);
-  std::vector<int64_t> cnt(Cc + 1, 0);
-  std::vector<int64_t> cell(S);
+  std::map<int64_t, std::vector<int64_t>> groups;  // dense trailing index -> ranks, in rank order
   for (int64_t r = 0; r < S; ++r) {
     int64_t c = 0;
     for (int a = m; a < n; ++a) c = c * (D + 1) + e[r * n + a];
-    cell[r] = c;
-    ++cnt[c + 1];
+    groups[c].push_back(r);
   }
-  for (int64_t c = 0; c < Cc; ++c) cnt[c + 1] += cnt[c];
-  std::vector<int> off(Cc + 1), rank(std::max<int64_t>(S, 1));
-  std::vector<unsigned long long> dig(std::max<int64_t>(S, 1));
-  for (int64_t c = 0; c <= Cc; ++c) off[c] = (int)cnt[c];
-  std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
-  for (int64_t r = 0; r < S; ++r) {
-    unsigned long long pk = 0;
-    for (int i = 0; i < m; ++i) pk |= (unsigned long long)e[r * n + i] << (4 * i);
-    const int64_t at = fill[cell[r]]++;
-    rank[at] = (int)r;
-    dig[at] = pk;
+  std::vector<int> cells, off(1, 0), rank;
+  std::vector<unsigned long long> dig;
+  for (auto &kv : groups) {
+    cells.push_back((int)kv.first);
+    for (int64_t r : kv.second) {
+      unsigned long long pk = 0;
+      for (int i = 0; i < m; ++i) pk |= (unsigned long long)e[r * n + i] << (4 * i);
+      rank.push_back((int)r);
+      dig.push_back(pk);
+    }
+    off.push_back((int)rank.size());
   }
   SliceTable st;
-  hipError_t err = hipMalloc(&st.off, (Cc + 1) * sizeof(int));
-  if (err == hipSuccess) err = hipMalloc(&st.rank, rank.size() * sizeof(int));
-  if (err == hipSuccess) err = hipMalloc(&st.dig, dig.size() * sizeof(unsigned long long));
-  if (err == hipSuccess) err = hipMemcpy(st.off, off.data(), (Cc + 1) * sizeof(int), hipMemcpyHostToDevice);
-  if (err == hipSuccess) err = hipMemcpy(st.rank, rank.data(), rank.size() * sizeof(int), hipMemcpyHostToDevice);
-  if (err == hipSuccess)
+  st.ncell = (int)cells.size();
+  hipError_t err = hipMalloc(&st.cell, std::max<size_t>(cells.size(), 1) * sizeof(int));
+  if (err == hipSuccess) err = hipMalloc(&st.off, off.size() * sizeof(int));
+  if (err == hipSuccess) err = hipMalloc(&st.rank, std::max<size_t>(rank.size(), 1) * sizeof(int));
+  if (err == hipSuccess) err = hipMalloc(&st.dig, std::max<size_t>(dig.size(), 1) * sizeof(unsigned long long));
+  if (err == hipSuccess && !cells.empty())
+    err = hipMemcpy(st.cell, cells.data(), cells.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (err == hipSuccess) err = hipMemcpy(st.off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (err == hipSuccess && !rank.empty())
+    err = hipMemcpy(st.rank, rank.data(), rank.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (err == hipSuccess && !dig.empty())
     err = hipMemcpy(st.dig, dig.data(), dig.size() * sizeof(unsigned long long), hipMemcpyHostToDevice);
   if (err != hipSuccess) {
+    (void)hipFree(st.cell);
     (void)hipFree(st.off);
     (void)hipFree(st.rank);
     (void)hipFree(st.dig);

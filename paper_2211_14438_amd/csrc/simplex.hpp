@@ -50,12 +50,14 @@ struct ProdTable {
   int64_t npairs = 0;
 };
 
-// Stored coefficients of degree D grouped by their trailing n-m exponents
-// (cell c = the dense index of those exponents in the (D+1)^(n-m) tensor of
-// the trailing axes): entries off[c] .. off[c+1] give the coefficient's rank
-// and its m leading exponents packed four bits each, axis i at bits 4i.
-// For D <= 15 and m <= 16.
+// Stored coefficients of degree D grouped by their trailing n-m exponents.
+// The ncell groups are the cells of the (D+1)^(n-m) tensor of the trailing
+// axes that hold any: group g has dense index cell[g] there, and entries
+// off[g] .. off[g+1] give each coefficient's rank and its m leading
+// exponents packed four bits each, axis i at bits 4i. For D <= 15, m <= 16.
 struct SliceTable {
+  int ncell = 0;
+  int *cell = nullptr;
   int *off = nullptr;
   int *rank = nullptr;
   unsigned long long *dig = nullptr;
