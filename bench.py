@@ -37,44 +37,6 @@ WORKLOADS = {
 }
 
 
-def box_degrees(case, used, L, plain):
-    """Pre-activation degree of every (box, layer) reconstructed from the rule
-    each neuron took: inactive 0, active D, order k -> k D, fallback 1; a
-    layer's post degree is the largest of its neurons' (plain rule: L D)."""
-    nb = used.shape[0]
-    D = np.ones(nb, dtype=np.int64)
-    out = []
-    col = 0
-    for i in range(1, len(case.widths) - 1):
-        h = case.widths[i]
-        out.append(D.copy())
-        if plain:
-            D = D * L
-        else:
-            k = used[:, col:col + h].astype(np.int64)
-            deg = np.where(k >= 1, k * D[:, None], np.where(k == -1, D[:, None], np.where(k == -2, 1, 0)))
-            D = deg.max(axis=1)
-        col += h
-    out.append(D.copy())
-    return out  # per layer (hidden layers then output): [boxes]
-
-
-def composed_flops(case, used, L, plain=True):
-    """Algorithmic FLOPs of the order-2 compositions: for every neuron-bound
-    that is composed (unstable neuron, kind == 2), one symmetric square of its
-    (D+1)^n-coefficient pre-activation tensor = (C^2 + C)/2 multiply-adds."""
-    degs = box_degrees(case, used, L, plain)
-    col = 0
-    total = 0.0
-    for i in range(1, len(case.widths) - 1):
-        h = case.widths[i]
-        C = (degs[i - 1].astype(np.float64) + 1.0) ** case.n
-        k2 = (used[:, col:col + h] == 2).sum(axis=1)
-        total += float((k2 * 2 * (C * C + C)).sum())
-        col += h
-    return total
-
-
 def cpu_baseline(case, budget_s=10.0):
     """The oracle, as it stands, on the host cores: repeated passes over boxes
     of the workload until about `budget_s` seconds of CPU work."""
@@ -245,22 +207,25 @@ def main():
                           value=neurons * psteps / pdt, ms_per_step=pdt / psteps * 1e3, mean_output_width=pw)
         del pkw
 
-    # roofline of the dominant kernel class (largest summed duration)
+    # roofline of the dominant kernel class (largest summed duration): the
+    # FP64 vector-ALU roof when its algorithmic flops per byte exceed the ridge
+    # point, the HBM roof otherwise
     kernels = {}
-    for name, (launches, ms, by) in prof.items():
+    for name, (launches, ms, by, fl) in prof.items():
         kernels[name] = dict(launches=launches, avg_us=ms / launches * 1e3, total_ms=ms)
     dom = max(prof.items(), key=lambda kv: kv[1][1])[0]
-    launches, ms, by = prof[dom]
-    if dom == "compose_square":
-        flops = composed_flops(case, used, case.L, plain=spec["form"] == "plain") * args.steps
-        achieved = flops / (ms * 1e-3) / 1e12
+    launches, ms, by, fl = prof[dom]
+    ridge = PEAK_VALU_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
+    if fl > 0 and (by <= 0 or fl / by > ridge):
+        achieved = fl / (ms * 1e-3) / 1e12
         roof = dict(bound="alu", achieved=achieved, peak=PEAK_VALU_TFLOPS, unit="TFLOP/s",
                     frac=achieved / PEAK_VALU_TFLOPS, traffic=measured_traffic(case.name, dom), kernel=dom,
-                    per_launch_flops=flops / launches, avg_launch_us=ms / launches * 1e3)
+                    per_launch_flops=fl / launches, per_launch_bytes=by / launches, avg_launch_us=ms / launches * 1e3)
     else:
         achieved = by / (ms * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s", frac=achieved / PEAK_HBM_GBS,
-                    traffic=measured_traffic(case.name, dom), kernel=dom, per_launch_bytes=by / launches, avg_launch_us=ms / launches * 1e3)
+                    traffic=measured_traffic(case.name, dom), kernel=dom, per_launch_bytes=by / launches,
+                    avg_launch_us=ms / launches * 1e3)
 
     line = {
         "metric": METRIC,

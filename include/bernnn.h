@@ -232,14 +232,18 @@ bern_status bern_relu_poly(int64_t count, int32_t L, const double *lo, const dou
  * (process-wide setting; not for use while a stream is being captured).
  * bern_prof_read waits for the recorded events and returns, for one kernel
  * class (0 .. bern_prof_classes()-1, named by bern_prof_name), the number of
- * launches, their summed duration in milliseconds and their summed
- * algorithmic HBM bytes where the launch shape alone fixes them (else 0).
- * bern_prof_reset forgets every record. */
+ * launches, their summed duration in milliseconds, their summed algorithmic
+ * HBM bytes and their summed algorithmic floating-point operations, where the
+ * launch shape alone fixes them (else 0; `flops` may be NULL). Algorithmic
+ * counts are those of the method on its stored tensors: the basis change
+ * counts n (D+1)^n (D+2) flops per tensor (all per-axis triangular sums of
+ * the dense degree-D tensor), the affine map 4 h h_in C per box (every
+ * input, upper and lower). bern_prof_reset forgets every record. */
 bern_status bern_prof_enable(int32_t on);
 bern_status bern_prof_reset(void);
 int32_t bern_prof_classes(void);
 const char *bern_prof_name(int32_t cls);
-bern_status bern_prof_read(int32_t cls, int64_t *launches, double *ms, double *bytes);
+bern_status bern_prof_read(int32_t cls, int64_t *launches, double *ms, double *bytes, double *flops);
 
 /* Degree predictor (learned plan). A small MLP 8 -> 64 -> 64 -> 4 with ReLU
  * hidden layers maps the features of an unstable neuron to a class: 0 =

@@ -94,7 +94,7 @@ def lib():
     L.bern_prof_name.argtypes = [i32]
     L.bern_prof_read.restype = i32
     L.bern_prof_read.argtypes = [i32, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
-                                 ctypes.POINTER(ctypes.c_double)]
+                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     fp = ctypes.POINTER(ctypes.c_float)
     L.bern_pred_params.restype = i32
     L.bern_pred_params.argtypes = []
@@ -362,15 +362,15 @@ def prof_reset():
 
 
 def prof_read():
-    """{kernel class: (launches, total ms, algorithmic bytes)} of the
-    launches recorded since the last reset (waits for them)."""
+    """{kernel class: (launches, total ms, algorithmic bytes, algorithmic
+    flops)} of the launches recorded since the last reset (waits for them)."""
     L = lib()
     out = {}
     for c in range(L.bern_prof_classes()):
-        n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
-        _check(L.bern_prof_read(c, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+        n, ms, by, fl = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(L.bern_prof_read(c, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by), ctypes.byref(fl)))
         if n.value:
-            out[L.bern_prof_name(c).decode()] = (n.value, ms.value, by.value)
+            out[L.bern_prof_name(c).decode()] = (n.value, ms.value, by.value, fl.value)
     return out
 
 

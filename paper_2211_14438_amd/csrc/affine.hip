@@ -213,7 +213,8 @@ hipError_t launch_gemm(const GemmArgs &a0, hipStream_t s) {
   GemmArgs a = a0;
   a.cblocks = gemm_cblocks(a.C);
   if (a.hp % 16 != 0 || a.hp < a.h || !a.live || a.Cs > a.C) return hipErrorInvalidValue;
-  ProfScope ps(kProfGemm, s, (double)a.nboxes * (2.0 * a.hin + 2.0 * a.h) * a.C * (a.fp64 ? 8 : 4));
+  ProfScope ps(kProfGemm, s, (double)a.nboxes * (2.0 * a.hin + 2.0 * a.h) * a.C * (a.fp64 ? 8 : 4),
+               4.0 * a.nboxes * a.h * a.hin * a.C);
   if (a.h <= 4) {
     switch (a.tune.gemm_narrow) {
       case 1: return launch_gemm_mb<4, 4>(a, s);

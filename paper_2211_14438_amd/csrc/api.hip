@@ -31,7 +31,7 @@ static bool g_prof_on = false;
 struct ProfRec {
   int cls;
   hipEvent_t a, b;
-  double bytes;
+  double bytes, flops;
 };
 static std::vector<ProfRec> g_prof;
 static std::vector<hipEvent_t> g_pool;  // idle events, created ahead of the timed work
@@ -57,7 +57,8 @@ static void pool_fill(size_t n) {
   }
 }
 
-ProfScope::ProfScope(int c, hipStream_t st, double by) : cls(c), s(st), bytes(by), ev0(nullptr) {
+ProfScope::ProfScope(int c, hipStream_t st, double by, double fl)
+    : cls(c), s(st), bytes(by), flops(fl), ev0(nullptr) {
   if (!g_prof_on) return;
   hipEvent_t e = pool_get();
   if (!e) return;
@@ -79,7 +80,7 @@ ProfScope::~ProfScope() {
     return;
   }
   std::lock_guard<std::mutex> g(g_prof_mu);
-  g_prof.push_back({cls, (hipEvent_t)ev0, e, bytes});
+  g_prof.push_back({cls, (hipEvent_t)ev0, e, bytes, flops});
 }
 
 static const char *kProfNames[kProfCount] = {
@@ -997,14 +998,14 @@ extern "C" const char *bern_prof_name(int32_t cls) {
   return (cls >= 0 && cls < kProfCount) ? kProfNames[cls] : "";
 }
 
-extern "C" bern_status bern_prof_read(int32_t cls, int64_t *launches, double *ms, double *bytes) {
+extern "C" bern_status bern_prof_read(int32_t cls, int64_t *launches, double *ms, double *bytes, double *flops) {
   if (cls < 0 || cls >= kProfCount || !launches || !ms || !bytes) {
     set_error("bad arguments");
     return BERN_E_ARG;
   }
   std::lock_guard<std::mutex> g(g_prof_mu);
   int64_t n = 0;
-  double t = 0.0, by = 0.0;
+  double t = 0.0, by = 0.0, fl = 0.0;
   for (auto &r : g_prof) {
     if (r.cls != cls) continue;
     BERN_HIP_TRY(hipEventSynchronize(r.b));
@@ -1013,10 +1014,12 @@ extern "C" bern_status bern_prof_read(int32_t cls, int64_t *launches, double *ms
     ++n;
     t += e;
     by += r.bytes;
+    fl += r.flops;
   }
   *launches = n;
   *ms = t;
   *bytes = by;
+  if (flops) *flops = fl;
   return BERN_OK;
 }
 

@@ -115,11 +115,11 @@ enum ProfClass : int {
   kProfCount
 };
 struct ProfScope {
-  ProfScope(int cls, hipStream_t s, double bytes);
+  ProfScope(int cls, hipStream_t s, double bytes, double flops = 0.0);
   ~ProfScope();
   int cls;
   hipStream_t s;
-  double bytes;
+  double bytes, flops;
   void *ev0;
 };
 

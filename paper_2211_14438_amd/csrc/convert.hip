@@ -828,7 +828,8 @@ static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
     const size_t lds = (size_t)(kBlock / 64) * 2 * a.C * sizeof(double);
     RET_IF(hipFuncSetAttribute((const void *)convert_wave_t<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
-    ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4));
+    ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4),
+                 (double)a.nboxes * a.h * 2 * a.n * a.C * (a.D + 2));
     const int64_t items = a.nboxes * a.h;
     hipLaunchKernelGGL((convert_wave_t<D, T>), dim3((unsigned)((items + kBlock / 64 - 1) / (kBlock / 64))),
                        dim3(kBlock), lds, s, a);
@@ -841,7 +842,8 @@ static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
   static const unsigned kThreads[4] = {0, 256, 512, 1024};
   const unsigned threads = a.tune.conv_block > 0 && a.tune.conv_block < 4 ? kThreads[a.tune.conv_block]
                                                                           : (lds > 40 * 1024 ? 1024 : 256);
-  ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4));
+  ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4),
+                 (double)a.nboxes * a.h * 2 * a.n * a.C * (a.D + 2));
   hipLaunchKernelGGL((convert_block_t<D, T>), dim3((unsigned)(a.nboxes * a.h)), dim3(threads), lds, s, a);
   return hipGetLastError();
 }
@@ -1066,7 +1068,8 @@ hipError_t launch_convert(const ConvertArgs &a, hipStream_t s) {
     const size_t lds = (D1 * D1 + (kBlock / 64) * 2 * a.C) * sizeof(double);
     auto k = a.fp64 ? convert_wave_kernel<double> : convert_wave_kernel<float>;
     RET_IF(hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4));
+    ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4),
+                 (double)a.nboxes * a.h * 2 * a.n * a.C * (a.D + 2));
     const int64_t items = a.nboxes * a.h;
     hipLaunchKernelGGL(k, dim3((unsigned)((items + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), lds, s, a);
     return hipGetLastError();
@@ -1075,7 +1078,8 @@ hipError_t launch_convert(const ConvertArgs &a, hipStream_t s) {
     const size_t lds = (a.C + D1 * D1 + 16) * sizeof(double);
     auto k = a.fp64 ? convert_small_kernel<double> : convert_small_kernel<float>;
     RET_IF(hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4));
+    ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4),
+                 (double)a.nboxes * a.h * 2 * a.n * a.C * (a.D + 2));
     hipLaunchKernelGGL(k, dim3((unsigned)(a.nboxes * a.h)), dim3(kBlock), lds, s, a);
     return hipGetLastError();
   }
@@ -1093,7 +1097,8 @@ hipError_t launch_convert(const ConvertArgs &a, hipStream_t s) {
     double *l1part = reinterpret_cast<double *>(reinterpret_cast<char *>(partial) +
                                                 align256((size_t)a.nboxes * a.h * 2 * ck.nchunk * sizeof(double)));
     {
-      ProfScope ps(kProfConvertChunk, s, (double)tensors * a.S * (a.fp64 ? 8 : 4));
+      ProfScope ps(kProfConvertChunk, s, (double)tensors * a.S * (a.fp64 ? 8 : 4),
+                   (double)tensors * a.n * a.C * (a.D + 2));
       RET_IF(a.fp64 ? launch_chunk<double>(b, ck, chunk_lds(ck, a.S, a.D), partial, l1part, s)
                     : launch_chunk<float>(b, ck, chunk_lds(ck, a.S, a.D), partial, l1part, s));
     }
