@@ -439,6 +439,8 @@ __global__ void box_degree_kernel(int64_t nb, int h, const NeuronRec *recs, int 
 struct LayerTables {
   const int *didx = nullptr;
   const SliceTable *sl = nullptr;
+  const int *plist = nullptr;
+  int plist_len = 0;
   const ProdTable *sq = nullptr;
   const ProdTable *hz[kMaxOrder] = {};
 };
@@ -447,6 +449,8 @@ static bern_status layer_tables(const bern_net *net, int Din, int Lmax, bool com
   hipError_t e = dense_index_table(*net->tab, Din, &t.didx);
   const int tm = convert_tile_m(net->n, Din);
   if (e == hipSuccess && tm >= 0) e = slice_table(*net->tab, Din, tm, &t.sl);
+  if (e == hipSuccess && Din >= 1 && Din <= 8)
+    e = prefix_table(*net->tab, Din, tm >= 0 ? net->n - tm : net->n, &t.plist, &t.plist_len);
   if (e == hipSuccess && compose && Lmax >= 2) e = product_table(*net->tab, Din, Din, true, &t.sq);
   for (int m = 1; e == hipSuccess && compose && m <= Lmax - 1 && Lmax >= 3; ++m)
     e = product_table(*net->tab, Din, m * Din, false, &t.hz[m]);
@@ -557,6 +561,8 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       c.C = ipow(cl.Din + 1, n);
       c.S = ssize(n, cl.Din);
       c.didx = lt.didx;
+      c.plist = lt.plist;
+      c.plist_len = lt.plist_len;
       if (lt.sl) {
         c.sl_ncell = lt.sl->ncell;
         c.sl_cell = lt.sl->cell;

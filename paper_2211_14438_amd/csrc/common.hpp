@@ -219,6 +219,10 @@ struct ConvertArgs {
   const int *sl_rank;
   const unsigned long long *sl_dig;
   int gextra;                     // rounding steps beyond the per-axis basis change (set by the launcher)
+  // simplex.hpp prefix_table for (D, n), or (D, n - convert_tile_m(n, D)) for
+  // tensors beyond LDS; null for degrees without a compile-time kernel
+  const int *plist;
+  int plist_len;
 };
 hipError_t launch_convert(const ConvertArgs &a, hipStream_t s);
 size_t convert_scratch_bytes(int n, int D, int h, int64_t nboxes);

@@ -513,25 +513,72 @@ __device__ __forceinline__ void axis_pass(double *t, int F, unsigned st, unsigne
   }
 }
 
+// The same pass over the fibres whose leading exponents (axes before the
+// one converted) are listed in `list` (np dense prefixes): the others are
+// zero and stay zero.
+template <int D, bool kTrack, class Team>
+__device__ __forceinline__ void axis_pass_list(double *t, const int *list, int np, unsigned st, unsigned magic,
+                                               const Team &tm, double &mn, double &mx) {
+  constexpr int D1 = D + 1;
+  const int W = np * (int)st;
+  for (int w = tm.tid; w < W; w += tm.nt) {
+    const unsigned pi = st == 1 ? (unsigned)w : __umulhi((unsigned)w, magic);
+    const unsigned lo = (unsigned)w - pi * st;
+    const int base = (int)((unsigned)list[pi] * (unsigned)D1 * st + lo);
+    double x[D1];
+#pragma unroll
+    for (int j = 0; j < D1; ++j) x[j] = t[base + j * (int)st];
+    to_bern<D>(x);
+#pragma unroll
+    for (int j = 0; j < D1; ++j) {
+      if (kTrack) {
+        mn = fmin(mn, x[j]);
+        mx = fmax(mx, x[j]);
+      }
+      t[base + j * (int)st] = x[j];
+    }
+  }
+}
+
 // Convert axes [0, na) of a tensor already in LDS whose axis na-1 has stride
 // s0 (axis a has stride s0 (D+1)^(na-1-a)); `total` coefficients. Tracks the
-// extrema of the last pass when `track` is set.
+// extrema of the last pass when `track` is set. With a prefix table `pl`
+// (simplex.hpp prefix_table for (D, na), in LDS) only the fibres that can be
+// nonzero are converted: valid when every nonzero coefficient of the tensor
+// has exponent sum <= D.
 template <int D, class Team>
 __device__ void team_axes(double *t, int total, int s0, int na, const Team &tm, bool track, double &mn,
-                          double &mx) {
+                          double &mx, const int *pl = nullptr) {
   constexpr int D1 = D + 1;
   const int F = total / D1;
   unsigned stride = (unsigned)s0;
   for (int ax = na - 1; ax >= 0; --ax) {
     tm.sync();
     const unsigned magic = stride > 1 ? 0xFFFFFFFFu / stride + 1u : 0u;
-    if (track && ax == 0)
-      axis_pass<D, true>(t, F, stride, magic, tm, mn, mx);
-    else
-      axis_pass<D, false>(t, F, stride, magic, tm, mn, mx);
+    const bool last = track && ax == 0;
+    if (pl) {
+      const int np = pl[ax + 1] - pl[ax];
+      if (last)
+        axis_pass_list<D, true>(t, pl + pl[ax], np, stride, magic, tm, mn, mx);
+      else
+        axis_pass_list<D, false>(t, pl + pl[ax], np, stride, magic, tm, mn, mx);
+    } else {
+      if (last)
+        axis_pass<D, true>(t, F, stride, magic, tm, mn, mx);
+      else
+        axis_pass<D, false>(t, F, stride, magic, tm, mn, mx);
+    }
     stride *= D1;
   }
   tm.sync();
+}
+
+// Copy the prefix table into LDS (all threads of the block, then a barrier).
+__device__ inline const int *stage_prefixes(const ConvertArgs &a, int *dst) {
+  if (!a.plist) return nullptr;
+  for (int i = threadIdx.x; i < a.plist_len; i += blockDim.x) dst[i] = a.plist[i];
+  __syncthreads();
+  return dst;
 }
 
 // Stored power coefficients p[0, S) -> dense Bernstein tensor t[0, C)
@@ -539,7 +586,7 @@ __device__ void team_axes(double *t, int total, int s0, int na, const Team &tm, 
 // others are zero). Returns the team-wide sum of |p| and the extrema.
 template <int D, typename T, class Team>
 __device__ void team_convert(double *t, const T *p, const int *didx, int C, int S, int n, const Team &tm,
-                             double &l1, double &vmin, double &vmax) {
+                             double &l1, double &vmin, double &vmax, const int *pl) {
   for (int i = tm.tid; i < C; i += tm.nt) t[i] = 0.0;
   tm.sync();
   double s = 0.0, mn = INFINITY, mx = -INFINITY;
@@ -548,7 +595,7 @@ __device__ void team_convert(double *t, const T *p, const int *didx, int C, int 
     t[didx[i]] = x;
     s += fabs(x);
   }
-  team_axes<D>(t, C, 1, n, tm, true, mn, mx);
+  team_axes<D>(t, C, 1, n, tm, true, mn, mx, pl);
   l1 = tm.sum(s);
   vmin = tm.min(mn);
   vmax = tm.max(mx);
@@ -660,7 +707,8 @@ __global__ void __launch_bounds__(kBlock) convert_wave_t(ConvertArgs a) {
   const WaveTeam tm{(int)(threadIdx.x & 63)};
   const int wv = threadIdx.x >> 6;
   const int C = (int)a.C;
-  double *tw = lds + (int64_t)wv * 2 * C;  // [2][C]: lower, upper
+  const int *pl = stage_prefixes(a, reinterpret_cast<int *>(lds));
+  double *tw = lds + (a.plist_len + 1) / 2 + (int64_t)wv * 2 * C;  // [2][C]: lower, upper
   const int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + wv;
   if (item >= a.nboxes * a.h) return;
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
@@ -668,8 +716,8 @@ __global__ void __launch_bounds__(kBlock) convert_wave_t(ConvertArgs a) {
   const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + (int64_t)j * 2 * a.S;
   const int S = (int)a.S;
   double l1L, l1U, mn, mx, dummy;
-  team_convert<D>(tw, p + S, a.didx, C, S, a.n, tm, l1L, mn, dummy);
-  team_convert<D>(tw + C, p, a.didx, C, S, a.n, tm, l1U, dummy, mx);
+  team_convert<D>(tw, p + S, a.didx, C, S, a.n, tm, l1L, mn, dummy, pl);
+  team_convert<D>(tw + C, p, a.didx, C, S, a.n, tm, l1U, dummy, mx, pl);
   double epsU = 0.0, epsL = 0.0;
   if (!a.fp64) pre_radii(a, box, j, a.pre, tm.tid, 64, [&](double v) { return tm.sum(v); }, epsU, epsL);
   const double lo = side_lo(a, mn, l1L, epsL), hi = side_hi(a, mx, l1U, epsU);
@@ -692,7 +740,8 @@ __global__ void __launch_bounds__(1024) convert_block_t(ConvertArgs a) {
   extern __shared__ double lds[];
   __shared__ double red[16];
   const BlockTeam tm{(int)threadIdx.x, (int)blockDim.x, red};
-  double *t = lds;
+  const int *pl = stage_prefixes(a, reinterpret_cast<int *>(lds));
+  double *t = lds + (a.plist_len + 1) / 2;
   const int C = (int)a.C;
   const int64_t item = blockIdx.x;
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
@@ -705,11 +754,11 @@ __global__ void __launch_bounds__(1024) convert_block_t(ConvertArgs a) {
   NeuronRec *rec = want ? &a.recs[box * a.h + j] : nullptr;
   double fx[4] = {0.0, 0.0, 0.0, 0.0};
   double l1L, l1U, mn, mx, dummy;
-  team_convert<D>(t, p + S, a.didx, C, S, a.n, tm, l1L, mn, dummy);
+  team_convert<D>(t, p + S, a.didx, C, S, a.n, tm, l1L, mn, dummy, pl);
   const double lo = side_lo(a, mn, l1L, epsL);
   if (want && (a.fits || lo < 0.0)) team_fit<D>(t, C, a.n, tm, rec->fitL, fx[2], fx[3]);
   tm.sync();
-  team_convert<D>(t, p, a.didx, C, S, a.n, tm, l1U, dummy, mx);
+  team_convert<D>(t, p, a.didx, C, S, a.n, tm, l1U, dummy, mx, pl);
   const double hi = side_hi(a, mx, l1U, epsU);
   const bool fitted = want && (a.fits || (lo < 0.0 && hi > 0.0));
   if (fitted) team_fit<D>(t, C, a.n, tm, rec->fitU, fx[0], fx[1]);
@@ -743,7 +792,8 @@ __global__ void __launch_bounds__(1024) convert_chunk_t(ConvertArgs a, Chunking 
   constexpr int D1 = D + 1;
   const BlockTeam tm{(int)threadIdx.x, (int)blockDim.x, red};
   const int Ct = (int)ck.cells, S = (int)a.S;
-  double *t = lds;          // [Ct]
+  const int *pl = stage_prefixes(a, reinterpret_cast<int *>(lds));
+  double *t = lds + (a.plist_len + 1) / 2;  // [Ct]
   double *av = t + Ct;      // [S]
   double *tab = av + S;     // [D1][D1] C(k,j)/C(D,j)
   constexpr Ratio<D> R{};
@@ -785,7 +835,7 @@ __global__ void __launch_bounds__(1024) convert_chunk_t(ConvertArgs a, Chunking 
       }
       t[a.sl_cell[gi]] = g;
     }
-    team_axes<D>(t, Ct, 1, a.n - ck.lead, tm, true, mn, mx);  // ends with a barrier
+    team_axes<D>(t, Ct, 1, a.n - ck.lead, tm, true, mn, mx, pl);  // ends with a barrier
   }
   const double v = s ? tm.min(mn) : tm.max(mx);
   if (tm.tid == 0) partial[tensor * ck.groups + blockIdx.x] = v;
@@ -824,8 +874,9 @@ static hipError_t launch_chunk(const ConvertArgs &a, const Chunking &ck, size_t 
 
 template <typename T, int D>
 static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
+  const size_t plb = (size_t)((a.plist_len + 1) / 2) * sizeof(double);
   if (a.C <= kWaveC && a.tune.conv_wave == 0) {
-    const size_t lds = (size_t)(kBlock / 64) * 2 * a.C * sizeof(double);
+    const size_t lds = (size_t)(kBlock / 64) * 2 * a.C * sizeof(double) + plb;
     RET_IF(hipFuncSetAttribute((const void *)convert_wave_t<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
     ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4),
@@ -835,7 +886,8 @@ static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
                        dim3(kBlock), lds, s, a);
     return hipGetLastError();
   }
-  const size_t lds = (size_t)a.C * sizeof(double);
+  const size_t lds = (size_t)a.C * sizeof(double) + plb;
+  if (lds + 256 > device_lds_limit()) return hipErrorInvalidValue;
   RET_IF(hipFuncSetAttribute((const void *)convert_block_t<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)lds));
   // a block per neuron; when few blocks share a CU's LDS, more waves each
@@ -1016,6 +1068,9 @@ static bool use_small(int64_t C) {
 // the fewest leading axes whose fixing leaves a trailing tensor of at most
 // kSmallLds coefficients that fits LDS with the stored coefficients and the
 // ratio table. lead = 0 when the path does not apply (D > 8 or too large).
+// Ints of the prefix table for (D, na): offsets plus C(D + na, na - 1) prefixes.
+static int64_t plist_ints(int na, int D) { return (na + 1) + ssize(na - 1, D + 1); }
+
 static Chunking chunking(int n, int D) {
   Chunking ck{0, 0, 0, 1, 0};
   if (D < 1 || D > 8) return ck;
@@ -1024,7 +1079,8 @@ static Chunking chunking(int n, int D) {
   const size_t limit = device_lds_limit();
   for (int lead = 1; lead < n && lead <= 16; ++lead) {
     const int64_t cells = ipow(D + 1, n - lead);
-    const size_t bytes = (size_t)(cells + S + (D + 1) * (D + 1)) * sizeof(double);
+    const size_t bytes =
+        (size_t)(cells + S + (D + 1) * (D + 1) + (plist_ints(n - lead, D) + 1) / 2) * sizeof(double);
     if (cells <= kSmallLds && bytes <= limit) {
       ck.lead = lead;
       ck.cells = cells;
@@ -1036,8 +1092,8 @@ static Chunking chunking(int n, int D) {
   return ck;
 }
 
-static size_t chunk_lds(const Chunking &ck, int64_t S, int D) {
-  return (size_t)(ck.cells + S + (D + 1) * (D + 1)) * sizeof(double);
+static size_t chunk_lds(const Chunking &ck, int64_t S, int D, int plist_len) {
+  return (size_t)(ck.cells + S + (D + 1) * (D + 1) + (plist_len + 1) / 2) * sizeof(double);
 }
 
 int convert_tile_m(int n, int D) {
@@ -1099,8 +1155,8 @@ hipError_t launch_convert(const ConvertArgs &a, hipStream_t s) {
     {
       ProfScope ps(kProfConvertChunk, s, (double)tensors * a.S * (a.fp64 ? 8 : 4),
                    (double)tensors * a.n * a.C * (a.D + 2));
-      RET_IF(a.fp64 ? launch_chunk<double>(b, ck, chunk_lds(ck, a.S, a.D), partial, l1part, s)
-                    : launch_chunk<float>(b, ck, chunk_lds(ck, a.S, a.D), partial, l1part, s));
+      RET_IF(a.fp64 ? launch_chunk<double>(b, ck, chunk_lds(ck, a.S, a.D, a.plist_len), partial, l1part, s)
+                    : launch_chunk<float>(b, ck, chunk_lds(ck, a.S, a.D, a.plist_len), partial, l1part, s));
     }
     Split fsp{};
     fsp.nchunk = ck.groups;

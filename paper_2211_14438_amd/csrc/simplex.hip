@@ -66,6 +66,7 @@ SimplexTables::~SimplexTables() {
     (void)hipFree(kv.second.pairs);
     (void)hipFree(kv.second.diag);
   }
+  for (auto &kv : prefixes) (void)hipFree(kv.second.first);
   for (auto &kv : slices) {
     (void)hipFree(kv.second.cell);
     (void)hipFree(kv.second.off);
@@ -221,6 +222,49 @@ hipError_t product_table(SimplexTables &t, int da, int db, bool sym, const ProdT
   }
   auto res = t.prod.emplace(key, pt);
   *out = &res.first->second;
+  return hipSuccess;
+}
+
+hipError_t prefix_table(SimplexTables &t, int D, int na, const int **out, int *len) {
+  std::lock_guard<std::mutex> g(t.mu);
+  const auto key = std::make_pair(D, na);
+  auto it = t.prefixes.find(key);
+  if (it != t.prefixes.end()) {
+    *out = it->second.first;
+    *len = it->second.second;
+    return hipSuccess;
+  }
+  if (na < 1 || D < 0) return hipErrorInvalidValue;
+  std::vector<int> off(na + 1), vals;
+  for (int a = 0; a < na; ++a) {
+    off[a] = (int)vals.size();
+    double lim = 1.0;
+    for (int q = 0; q < a; ++q) lim *= D + 1;
+    if (lim > 1e7) return hipErrorInvalidValue;
+    for (int64_t v = 0; v < (int64_t)lim; ++v) {
+      int64_t r = v;
+      int sum = 0;
+      for (int q = 0; q < a; ++q) {
+        sum += (int)(r % (D + 1));
+        r /= D + 1;
+      }
+      if (sum <= D) vals.push_back((int)v);
+    }
+  }
+  off[na] = (int)vals.size();
+  std::vector<int> all(off);
+  for (size_t q = 0; q < all.size(); ++q) all[q] += na + 1;  // offsets into the whole table
+  all.insert(all.end(), vals.begin(), vals.end());
+  int *d = nullptr;
+  RET_IF(hipMalloc(&d, all.size() * sizeof(int)));
+  hipError_t err = hipMemcpy(d, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (err != hipSuccess) {
+    (void)hipFree(d);
+    return err;
+  }
+  t.prefixes[key] = std::make_pair(d, (int)all.size());
+  *out = d;
+  *len = (int)all.size();
   return hipSuccess;
 }
 

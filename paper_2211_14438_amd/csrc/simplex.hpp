@@ -69,6 +69,7 @@ struct SimplexTables {
   std::map<int, int *> dense;                      // D -> [S(n,D)] index in the (D+1)^n tensor
   std::map<std::tuple<int, int, int>, ProdTable> prod;  // (da, db, sym)
   std::map<std::pair<int, int>, SliceTable> slices;     // (D, m leading axes)
+  std::map<std::pair<int, int>, std::pair<int *, int>> prefixes;  // (D, na) -> (table, ints)
   ~SimplexTables();
 };
 
@@ -80,5 +81,13 @@ constexpr int64_t kMaxPairs = (int64_t)1 << 25;
 hipError_t dense_index_table(SimplexTables &t, int D, const int **out);
 hipError_t product_table(SimplexTables &t, int da, int db, bool sym, const ProdTable **out);
 hipError_t slice_table(SimplexTables &t, int D, int m, const SliceTable **out);
+
+// Valid fibre prefixes of the per-axis basis change of a tensor whose
+// nonzero coefficients all have exponent sum <= D: converting axis a (axes
+// after a already converted), a fibre is zero unless the exponents of the
+// axes before a sum to at most D. Table of ints: off[0 .. na] (off[a] =
+// start of the list for a leading axes, off[na] = end), then the lists: the
+// dense indices (base D+1, a digits) of those leading exponents, ascending.
+hipError_t prefix_table(SimplexTables &t, int D, int na, const int **out, int *len);
 
 }  // namespace bern
