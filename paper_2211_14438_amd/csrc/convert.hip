@@ -700,7 +700,10 @@ __device__ inline void write_neuron(const ConvertArgs &a, int64_t box, int j, do
   }
 }
 
-// One wave per (box, neuron), both bound tensors in the wave's LDS slice.
+// One wave per (box, neuron), one bound tensor at a time in the wave's LDS
+// slice (lower first, then upper). The lower tensor is fitted while resident
+// when the neuron may still be unstable (its lower bound is negative); the
+// upper one once both bounds are known.
 template <int D, typename T>
 __global__ void __launch_bounds__(kBlock) convert_wave_t(ConvertArgs a) {
   extern __shared__ double lds[];
@@ -708,26 +711,27 @@ __global__ void __launch_bounds__(kBlock) convert_wave_t(ConvertArgs a) {
   const int wv = threadIdx.x >> 6;
   const int C = (int)a.C;
   const int *pl = stage_prefixes(a, reinterpret_cast<int *>(lds));
-  double *tw = lds + (a.plist_len + 1) / 2 + (int64_t)wv * 2 * C;  // [2][C]: lower, upper
+  double *tw = lds + (a.plist_len + 1) / 2 + (int64_t)wv * C;
   const int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + wv;
   if (item >= a.nboxes * a.h) return;
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
   const int j = (int)(item % a.h);
   const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + (int64_t)j * 2 * a.S;
   const int S = (int)a.S;
-  double l1L, l1U, mn, mx, dummy;
-  team_convert<D>(tw, p + S, a.didx, C, S, a.n, tm, l1L, mn, dummy, pl);
-  team_convert<D>(tw + C, p, a.didx, C, S, a.n, tm, l1U, dummy, mx, pl);
   double epsU = 0.0, epsL = 0.0;
   if (!a.fp64) pre_radii(a, box, j, a.pre, tm.tid, 64, [&](double v) { return tm.sum(v); }, epsU, epsL);
-  const double lo = side_lo(a, mn, l1L, epsL), hi = side_hi(a, mx, l1U, epsU);
-  const bool fitted = wants_fit(a, box, j) && (a.fits || (lo < 0.0 && hi > 0.0));
+  const bool want = wants_fit(a, box, j);
+  NeuronRec *rec = want ? &a.recs[box * a.h + j] : nullptr;
   double fx[4] = {0.0, 0.0, 0.0, 0.0};
-  if (fitted) {
-    NeuronRec &r = a.recs[box * a.h + j];
-    team_fit<D>(tw + C, C, a.n, tm, r.fitU, fx[0], fx[1]);  // upper
-    team_fit<D>(tw, C, a.n, tm, r.fitL, fx[2], fx[3]);      // lower
-  }
+  double l1L, l1U, mn, mx, dummy;
+  team_convert<D>(tw, p + S, a.didx, C, S, a.n, tm, l1L, mn, dummy, pl);
+  const double lo = side_lo(a, mn, l1L, epsL);
+  if (want && (a.fits || lo < 0.0)) team_fit<D>(tw, C, a.n, tm, rec->fitL, fx[2], fx[3]);
+  tm.sync();
+  team_convert<D>(tw, p, a.didx, C, S, a.n, tm, l1U, dummy, mx, pl);
+  const double hi = side_hi(a, mx, l1U, epsU);
+  const bool fitted = want && (a.fits || (lo < 0.0 && hi > 0.0));
+  if (fitted) team_fit<D>(tw, C, a.n, tm, rec->fitU, fx[0], fx[1]);
   if (tm.tid == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted);
 }
 
@@ -876,7 +880,7 @@ template <typename T, int D>
 static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
   const size_t plb = (size_t)((a.plist_len + 1) / 2) * sizeof(double);
   if (a.C <= kWaveC && a.tune.conv_wave == 0) {
-    const size_t lds = (size_t)(kBlock / 64) * 2 * a.C * sizeof(double) + plb;
+    const size_t lds = (size_t)(kBlock / 64) * a.C * sizeof(double) + plb;
     RET_IF(hipFuncSetAttribute((const void *)convert_wave_t<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
     ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4),
