@@ -123,9 +123,9 @@ __device__ __forceinline__ void gemm_rows(const T *X, int64_t st, int64_t C, con
 // block row. Block x index runs over output-neuron chunks first so that the
 // blocks reading the same coefficient range of the previous layer run
 // together and share L2. Only the box's live inputs are read: composed
-// neurons' full tensors, and the tensors of active, order-1 and fallback
-// neurons, which hold only the coefficients of their own degree (a prefix
-// in the total-degree layout).
+// neurons' full tensors, the tensors of order-1 and fallback neurons, which
+// hold only the coefficients of their own degree (a prefix in the
+// total-degree layout), and active neurons' pre-activation tensors in place.
 // The weights come from the transposed, zero-padded copy W^T[k][hp]: for one
 // input k the block's MB weights are contiguous and uniform, so they load as
 // a few wide scalar loads and no row guard sits in the inner loop; |w| is the
@@ -150,12 +150,19 @@ __global__ void __launch_bounds__(kBlock) gemm_kernel(GemmArgs a) {
   const double *wt = a.WT + m0;
   // lanes past the tensor read its last coefficient; their sums are dropped
   const int64_t cc = valid ? c : a.C - 1;
-  gemm_rows<T, MB, KU>(X + cc, st, a.C, lv + 2, lv[0], true, wt, a.hp, accM, accR);
+  gemm_rows<T, MB, KU>(X + cc, st, a.C, lv + 3, lv[0], true, wt, a.hp, accM, accR);
   if (lv[1] > 0) {
     // degree-preserving inputs hold the first Cs coefficients (graded order:
     // the monomials of their degree); beyond, their lifted tensor is zero
     const bool inside = cc < a.Cs;
-    gemm_rows<T, MB, KU>(X + (inside ? cc : 0), st, a.C, lv + 2 + a.hin, lv[1], inside, wt, a.hp, accM, accR);
+    gemm_rows<T, MB, KU>(X + (inside ? cc : 0), st, a.C, lv + 3 + a.hin, lv[1], inside, wt, a.hp, accM, accR);
+  }
+  if (lv[2] > 0) {
+    // active neurons: post = pre, read from the previous pre-activation arena
+    const bool inside = cc < a.Cact;
+    const T *Xa = reinterpret_cast<const T *>(a.act) + box * a.act_slot;
+    gemm_rows<T, MB, KU>(Xa + (inside ? cc : 0), 2 * a.Cact, a.Cact, lv + 3 + 2 * a.hin, lv[2], inside, wt, a.hp, accM,
+                         accR);
   }
   T *Y = reinterpret_cast<T *>(a.pre) + box * a.slot_out;
   const bool track = a.rpart != nullptr;
@@ -212,7 +219,7 @@ static hipError_t launch_gemm_mb(const GemmArgs &a, hipStream_t s) {
 hipError_t launch_gemm(const GemmArgs &a0, hipStream_t s) {
   GemmArgs a = a0;
   a.cblocks = gemm_cblocks(a.C);
-  if (a.hp % 16 != 0 || a.hp < a.h || !a.live || a.Cs > a.C) return hipErrorInvalidValue;
+  if (a.hp % 16 != 0 || a.hp < a.h || !a.live || a.Cs > a.C || !a.act) return hipErrorInvalidValue;
   ProfScope ps(kProfGemm, s, (double)a.nboxes * (2.0 * a.hin + 2.0 * a.h) * a.C * (a.fp64 ? 8 : 4),
                4.0 * a.nboxes * a.h * a.hin * a.C);
   if (a.h <= 4) {

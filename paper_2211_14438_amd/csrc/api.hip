@@ -116,7 +116,7 @@ struct Plan {
   std::vector<int64_t> nbx;         // compose blocks per item, hidden layers
   // per-box bytes of each region
   size_t recs, arenaA, arenaB, conv, horner, flags, gpart, cpart, live;
-  size_t per_box() const { return 2 * recs + arenaA + arenaB + conv + horner + flags + gpart + cpart + live; }
+  size_t per_box() const { return 2 * recs + 2 * arenaA + arenaB + conv + horner + flags + gpart + cpart + live; }
 };
 
 }  // namespace bern
@@ -217,7 +217,7 @@ static bern_status plan_net(const bern_net *net, const bern_opts *o, Plan &p) {
   // per box: validity flag, post degree, one id per (layer, phase) list, and
   // the predicted code of every hidden neuron
   p.flags = align256(sizeof(int) * (2 + 2 * (size_t)p.H) + (size_t)net->nh);
-  p.live = align256(sizeof(int) * (2 + 2 * (size_t)net->hmax));
+  p.live = align256(sizeof(int) * (3 + 3 * (size_t)net->hmax));
   return BERN_OK;
 }
 
@@ -485,7 +485,11 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
   recbuf[1] = reinterpret_cast<NeuronRec *>(cur); cur += p.recs * B;
   double *gpart = reinterpret_cast<double *>(cur); cur += p.gpart * B;
   double *cpart = reinterpret_cast<double *>(cur); cur += p.cpart * B;
-  void *A = cur; cur += p.arenaA * B;
+  // pre-activation arenas alternate between layers: the affine map of layer
+  // i+1 reads active neurons' pre-activations of layer i in place
+  void *Aa[2];
+  Aa[0] = cur; cur += p.arenaA * B;
+  Aa[1] = cur; cur += p.arenaA * B;
   void *Bp = cur; cur += p.arenaB * B;
   double *conv = reinterpret_cast<double *>(cur); cur += p.conv * B;
   void *horner = cur; cur += p.horner * B;
@@ -533,7 +537,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
 
   {
     Layer1Args a{n, net->widths[1], B, nullptr, slotA, box_lo, box_hi, net->W64 + net->woff[0],
-                 net->b64 + net->boff[0], A, p.fp64 ? 1 : 0};
+                 net->b64 + net->boff[0], Aa[0], p.fp64 ? 1 : 0};
     BERN_HIP_TRY(launch_layer1(a, s));
   }
 
@@ -574,7 +578,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       c.bids = cid[k];
       c.slot = slotA;
       c.cap = cap;
-      c.pre = A;
+      c.pre = Aa[i & 1];
       c.fp64 = p.fp64 ? 1 : 0;
       c.recs = recs;
       c.scratch = conv;
@@ -698,7 +702,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
           m.hz_pairs[q] = lt.hz[q]->pairs;
         }
       m.nboxes = (int64_t)cl.ids.size();
-      m.pre = A;
+      m.pre = Aa[i & 1];
       m.post = Bp;
       m.recs = recs;
       m.fp64 = p.fp64 ? 1 : 0;
@@ -719,7 +723,10 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       a.slot_in = slotB;
       a.slot_out = slotA;
       a.post = Bp;
-      a.pre = A;
+      a.pre = Aa[(i + 1) & 1];
+      a.act = Aa[i & 1];
+      a.act_slot = slotA;
+      a.Cact = m.Cin;
       a.live = live;
       a.live_ld = live_ld;
       a.Cs = m.Cs;

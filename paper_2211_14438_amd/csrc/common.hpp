@@ -55,17 +55,18 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // pre-activation bounds were read (Step 1) and its rule chosen (Step 2).
 // FP32 mode: every stored polynomial p~ carries a radius eps such that the
 // exact neuron value stays within [L~(t) - epsL, U~(t) + epsU] on the box.
-struct NeuronRec {
+struct alignas(64) NeuronRec {
+  // read by the next layer for every box neuron: kept in the first 64 bytes
+  double padU, padL;       // radii of the stored post polynomials
+  double pl1U, pl1L;       // sum of |coefficients| of the stored post polynomials
   double lo, hi;           // pre-activation interval [lo, hi] (padded in FP32 mode)
+  int32_t kind;            // 0 inactive, -1 active, -2 linear fallback, k >= 1 order k
+  int32_t deg;             // per-variable degree of the post polynomials
   double c[kMaxOrder + 1]; // over-approximant, power series in u = (y-lo)/(hi-lo)
   double e;                // its value at y = 0 (Prop. 2 shift), rounded up in FP32 mode
   double dB;               // FP32 mode: bound on the rounding of c (sup over u in [0,1])
   double epsU, epsL;       // radii of the stored pre-activation polynomials
   double l1U, l1L;         // sum of |coefficients| of the stored pre-activation polynomials
-  double padU, padL;       // radii of the stored post polynomials
-  double pl1U, pl1L;       // sum of |coefficients| of the stored post polynomials
-  int32_t kind;            // 0 inactive, -1 active, -2 linear fallback, k >= 1 order k
-  int32_t deg;             // per-variable degree of the post polynomials
   // Linear fallback: affine post polynomials a0 + sum_a a_{1+a} t_a (power basis).
   double fbU[kMaxInputs + 1];
   double fbL[kMaxInputs + 1];
@@ -160,14 +161,17 @@ struct GemmArgs {
   int64_t slot_in, slot_out;
   const void *post;               // [B][hin][2][C]
   void *pre;                      // [B][h][2][C]
-  // Per box input lists: live[0] full tensors (composed neurons) of C
-  // coefficients, indices at live[2..]; live[1] tensors of degree-preserving
-  // neurons (active, order 1, fallback) stored with their first Cs
-  // coefficients only, indices at live[2 + hin..]. Inactive neurons
-  // contribute nothing.
+  // Per box input lists: live[0] full post tensors (composed neurons) of C
+  // coefficients, indices at live[3..]; live[1] post tensors of order-1 and
+  // fallback neurons stored with their first Cs coefficients only, indices
+  // at live[3 + hin..]; live[2] active neurons, read in place from their
+  // pre-activation tensors (first Cact coefficients, arena `act`), indices at
+  // live[3 + 2 hin..]. Inactive neurons contribute nothing.
   const int *live;
   int64_t live_ld;
   int64_t Cs;
+  const void *act;                // [B][hin][2][Cact] pre-activations of the previous layer
+  int64_t act_slot, Cact;
   const double *WT;               // [hin][hp]: W transposed, rows h..hp-1 zero
   int hp;                         // h rounded up to a multiple of 16
   const double *b;                // [h]

@@ -321,9 +321,10 @@ __global__ void __launch_bounds__(kBlock) compose_sq_kernel(ComposeArgs a) {
 
 // ------------------------------------------------- element-wise rules
 // Input lists of the next affine map, one wave per box: composed neurons
-// (order >= 2, full tensors at the layer's post degree) and neurons whose
-// post polynomial keeps the pre-activation degree (active, order 1,
-// fallback: tensors stored at degree Din). Inactive neurons are left out.
+// (order >= 2, full tensors at the layer's post degree), order-1 and
+// fallback neurons (post tensors stored at degree Din), and active neurons
+// (post = pre, read in place from the pre-activation arena). Inactive
+// neurons are left out.
 __global__ void __launch_bounds__(kBlock) live_kernel(ComposeArgs a) {
   const int lane = threadIdx.x & 63;
   const int64_t g = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
@@ -331,38 +332,41 @@ __global__ void __launch_bounds__(kBlock) live_kernel(ComposeArgs a) {
   const int64_t box = wave_box(a, g);
   int *lv = a.live + box * a.live_ld;
   const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  int nf = 0, ns = 0;
+  int nf = 0, ns = 0, na = 0;
   for (int j0 = 0; j0 < a.h; j0 += 64) {
     const int j = j0 + lane;
     const int kind = j < a.h ? a.recs[box * a.h + j].kind : (int)kInactive;
     const bool full = kind >= 2;
-    const bool small = kind == kActive || kind == 1 || kind == kFallback;
-    const unsigned long long bf = __ballot(full), bs = __ballot(small);
-    if (full) lv[2 + nf + __popcll(bf & below)] = j;
-    if (small) lv[2 + a.h + ns + __popcll(bs & below)] = j;
+    const bool small = kind == 1 || kind == kFallback;
+    const bool act = kind == kActive;
+    const unsigned long long bf = __ballot(full), bs = __ballot(small), ba = __ballot(act);
+    if (full) lv[3 + nf + __popcll(bf & below)] = j;
+    if (small) lv[3 + a.h + ns + __popcll(bs & below)] = j;
+    if (act) lv[3 + 2 * a.h + na + __popcll(ba & below)] = j;
     nf += __popcll(bf);
     ns += __popcll(bs);
+    na += __popcll(ba);
   }
   if (lane == 0) {
     lv[0] = nf;
     lv[1] = ns;
+    lv[2] = na;
   }
 }
 
-// One block per (box, neuron, bound) whose post polynomial keeps degree Din:
-// active (copy of the pre tensor), order 1 (c1 nu + c0, minus e for the lower
-// bound) and the linear fallback (n+1 affine coefficients), each stored at
-// degree Ds = min(Din, Dout) at the start of its post tensor; the affine map
-// reads them through the degree change of its index. Inactive neurons
-// store nothing. Writes the block's rounding and l1 sums to partial slot 0
-// and zeros to the item's other slots.
+// One block per (box, neuron, bound) of order 1 (c1 nu + c0, minus e for the
+// lower bound) or the linear fallback (n+1 affine coefficients), each stored
+// at degree Ds = min(Din, Dout) at the start of its post tensor. Active
+// neurons (post = pre, read in place by the next affine map) and inactive
+// ones store nothing. Writes the block's rounding and l1 sums to partial
+// slot 0 and zeros to the item's other slots.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) compose_scatter_kernel(ComposeArgs a) {
   const int j = blockIdx.y / a.nbounds, s = blockIdx.y % a.nbounds;
   const int64_t g = blockIdx.z, box = wave_box(a, g);
   const NeuronRec &r = a.recs[box * a.h + j];
   const int kind = r.kind;
-  if (kind >= 2) return;
+  if (kind >= 2 || kind == kActive || kind == kInactive) return;  // partials of these are not read
   const NuSource ns = nu_of(a, &r, s);
   const int64_t it = item_of(a, g, j, s);
   const T *p = in_tensor<T>(a, box, j, s);
@@ -372,14 +376,12 @@ __global__ void __launch_bounds__(kBlock) compose_scatter_kernel(ComposeArgs a) 
   const int Ds = min(a.Din, a.Dout);
   const int64_t Cs = a.Cs;
   double rsum = 0.0, l1sum = 0.0;
-  if ((kind == kActive || kind == 1) && Ds == a.Din) {  // these neurons take degree Din <= Dout
+  if (kind == 1 && Ds == a.Din) {  // these neurons take degree Din <= Dout
     for (int64_t I = threadIdx.x; I < a.Cin; I += blockDim.x) {
       double v = (double)p[I];
-      if (kind == 1) {
-        if (I == 0) v += ns.shift - ns.lo;
-        v = r.c[1] * (v / ns.w);
-        if (I == 0) v += r.c[0] - (s == 1 ? r.e : 0.0);
-      }
+      if (I == 0) v += ns.shift - ns.lo;
+      v = r.c[1] * (v / ns.w);
+      if (I == 0) v += r.c[0] - (s == 1 ? r.e : 0.0);
       store(out + I, v, rsum, l1sum);
     }
   } else if (kind == kFallback) {
@@ -509,9 +511,11 @@ __global__ void post_radii_kernel(ComposeArgs a, NeuronRec *recs) {
   for (int s = 0; s < 2; ++s) {
     const int64_t it = item * 2 + s;
     double rs = 0.0, l1 = 0.0;
-    for (int64_t b = 0; b < a.nbx; ++b) {
-      rs += a.part[(it * a.nbx + b) * 2 + 0];
-      l1 += a.part[(it * a.nbx + b) * 2 + 1];
+    if (kind != kActive && kind != kInactive) {  // stored by one of the kernels above
+      for (int64_t b = 0; b < a.nbx; ++b) {
+        rs += a.part[(it * a.nbx + b) * 2 + 0];
+        l1 += a.part[(it * a.nbx + b) * 2 + 1];
+      }
     }
     const double eps_pre = s == 0 ? r.epsU : r.epsL;
     const double l1_pre = s == 0 ? r.l1U : r.l1L;
