@@ -701,9 +701,7 @@ __device__ inline void write_neuron(const ConvertArgs &a, int64_t box, int j, do
 }
 
 // One wave per (box, neuron), one bound tensor at a time in the wave's LDS
-// slice (lower first, then upper). The lower tensor is fitted while resident
-// when the neuron may still be unstable (its lower bound is negative); the
-// upper one once both bounds are known.
+// slice.
 template <int D, typename T>
 __global__ void __launch_bounds__(kBlock) convert_wave_t(ConvertArgs a) {
   extern __shared__ double lds[];
@@ -724,21 +722,52 @@ __global__ void __launch_bounds__(kBlock) convert_wave_t(ConvertArgs a) {
   NeuronRec *rec = want ? &a.recs[box * a.h + j] : nullptr;
   double fx[4] = {0.0, 0.0, 0.0, 0.0};
   double l1L, l1U, mn, mx, dummy;
-  team_convert<D>(tw, p + S, a.didx, C, S, a.n, tm, l1L, mn, dummy, pl);
+  // Lower tensor first. It is fitted while resident if the neuron can still
+  // take a fitted rule: lower bound negative and an upper bound of the upper
+  // tensor's largest Bernstein coefficient (its constant plus its positive
+  // coefficients, the ratio table lying in [0,1]) positive.
+  bool lower_fitted = false;
+  if (want && !a.fits) {
+    double hub = 0.0, l1u = 0.0;
+    for (int i = tm.tid; i < S; i += tm.nt) {
+      const double v = (double)p[i];
+      l1u += fabs(v);
+      hub += i == 0 ? v : fmax(v, 0.0);
+    }
+    hub = tm.sum(hub);
+    l1u = tm.sum(l1u);
+    const double hib = side_hi(a, hub + 1e-12 * l1u, l1u, epsU);
+    team_convert<D>(tw, p + S, a.didx, C, S, a.n, tm, l1L, mn, dummy, pl);
+    if (side_lo(a, mn, l1L, epsL) < 0.0 && hib > 0.0) {
+      team_fit<D>(tw, C, a.n, tm, rec->fitL, fx[2], fx[3]);
+      lower_fitted = true;
+    }
+  } else {
+    team_convert<D>(tw, p + S, a.didx, C, S, a.n, tm, l1L, mn, dummy, pl);
+    if (want) {
+      team_fit<D>(tw, C, a.n, tm, rec->fitL, fx[2], fx[3]);
+      lower_fitted = true;
+    }
+  }
   const double lo = side_lo(a, mn, l1L, epsL);
-  if (want && (a.fits || lo < 0.0)) team_fit<D>(tw, C, a.n, tm, rec->fitL, fx[2], fx[3]);
   tm.sync();
   team_convert<D>(tw, p, a.didx, C, S, a.n, tm, l1U, dummy, mx, pl);
   const double hi = side_hi(a, mx, l1U, epsU);
   const bool fitted = want && (a.fits || (lo < 0.0 && hi > 0.0));
-  if (fitted) team_fit<D>(tw, C, a.n, tm, rec->fitU, fx[0], fx[1]);
+  if (fitted) {
+    team_fit<D>(tw, C, a.n, tm, rec->fitU, fx[0], fx[1]);
+    if (!lower_fitted) {  // not expected: the filter above is an upper bound of hi
+      tm.sync();
+      double u1, u2, u3;
+      team_convert<D>(tw, p + S, a.didx, C, S, a.n, tm, u1, u2, u3, pl);
+      team_fit<D>(tw, C, a.n, tm, rec->fitL, fx[2], fx[3]);
+    }
+  }
   if (tm.tid == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted);
 }
 
 // One block per (box, neuron) for tensors up to kSmallLds coefficients, one
-// tensor in LDS at a time. The lower tensor is fitted while resident when
-// the neuron may still be unstable (its lower bound is negative); the upper
-// one once both bounds are known.
+// tensor in LDS at a time.
 template <int D, typename T>
 __global__ void __launch_bounds__(1024) convert_block_t(ConvertArgs a) {
   extern __shared__ double lds[];
@@ -758,14 +787,47 @@ __global__ void __launch_bounds__(1024) convert_block_t(ConvertArgs a) {
   NeuronRec *rec = want ? &a.recs[box * a.h + j] : nullptr;
   double fx[4] = {0.0, 0.0, 0.0, 0.0};
   double l1L, l1U, mn, mx, dummy;
-  team_convert<D>(t, p + S, a.didx, C, S, a.n, tm, l1L, mn, dummy, pl);
+  // Lower tensor first. It is fitted while resident if the neuron can still
+  // take a fitted rule: lower bound negative and an upper bound of the upper
+  // tensor's largest Bernstein coefficient (its constant plus its positive
+  // coefficients, the ratio table lying in [0,1]) positive.
+  bool lower_fitted = false;
+  if (want && !a.fits) {
+    double hub = 0.0, l1u = 0.0;
+    for (int i = tm.tid; i < S; i += tm.nt) {
+      const double v = (double)p[i];
+      l1u += fabs(v);
+      hub += i == 0 ? v : fmax(v, 0.0);
+    }
+    hub = tm.sum(hub);
+    l1u = tm.sum(l1u);
+    const double hib = side_hi(a, hub + 1e-12 * l1u, l1u, epsU);
+    team_convert<D>(t, p + S, a.didx, C, S, a.n, tm, l1L, mn, dummy, pl);
+    if (side_lo(a, mn, l1L, epsL) < 0.0 && hib > 0.0) {
+      team_fit<D>(t, C, a.n, tm, rec->fitL, fx[2], fx[3]);
+      lower_fitted = true;
+    }
+  } else {
+    team_convert<D>(t, p + S, a.didx, C, S, a.n, tm, l1L, mn, dummy, pl);
+    if (want) {
+      team_fit<D>(t, C, a.n, tm, rec->fitL, fx[2], fx[3]);
+      lower_fitted = true;
+    }
+  }
   const double lo = side_lo(a, mn, l1L, epsL);
-  if (want && (a.fits || lo < 0.0)) team_fit<D>(t, C, a.n, tm, rec->fitL, fx[2], fx[3]);
   tm.sync();
   team_convert<D>(t, p, a.didx, C, S, a.n, tm, l1U, dummy, mx, pl);
   const double hi = side_hi(a, mx, l1U, epsU);
   const bool fitted = want && (a.fits || (lo < 0.0 && hi > 0.0));
-  if (fitted) team_fit<D>(t, C, a.n, tm, rec->fitU, fx[0], fx[1]);
+  if (fitted) {
+    team_fit<D>(t, C, a.n, tm, rec->fitU, fx[0], fx[1]);
+    if (!lower_fitted) {  // not expected: the filter above is an upper bound of hi
+      tm.sync();
+      double u1, u2, u3;
+      team_convert<D>(t, p + S, a.didx, C, S, a.n, tm, u1, u2, u3, pl);
+      team_fit<D>(t, C, a.n, tm, rec->fitL, fx[2], fx[3]);
+    }
+  }
   if (tm.tid == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted);
 }
 
