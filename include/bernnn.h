@@ -8,9 +8,13 @@
  * hidden neuron (Step 1 of Section 5.1) and the output interval of each network
  * output (Def. 2 applied to the output polynomials).
  *
- * Polynomials live on the GPU as dense power-basis coefficient tensors in the
- * box-normalised coordinate t in [0,1]^n (x = d_lo + (d_hi - d_lo) t); a
- * polynomial of per-variable degree D has (D+1)^n coefficients, last variable
+ * Polynomials live on the GPU as power-basis coefficients in the
+ * box-normalised coordinate t in [0,1]^n (x = d_lo + (d_hi - d_lo) t). A
+ * polynomial of per-variable degree D on the path has total degree at most D,
+ * so only its C(n+D, n) coefficients of exponent sum <= D are stored (graded
+ * order); bounds are read from the full tensor-product Bernstein form of
+ * per-variable degree D (Section 4.1, Def. 2), expanded on the fly. The
+ * step-level entry points below take dense (D+1)^n tensors, last variable
  * fastest (the layout of Section 4.1, Example 1, in the power basis).
  *
  * Conventions for every entry point below:
@@ -19,8 +23,10 @@
  *   - Calls taking a `stream` (a hipStream_t passed as void*, NULL = the
  *     default stream) are asynchronous with respect to the host: they only
  *     enqueue work. Their results are valid once the stream has completed.
- *     They never allocate device memory: scratch comes from the caller's
- *     workspace.
+ *     Scratch comes from the caller's workspace; the only device memory the
+ *     library allocates is owned by handles (the network's weights, and its
+ *     index tables of the total-degree layout, built synchronously the first
+ *     time a call meets a new degree and freed by bern_net_destroy).
  *   - The caller owns every array it passes. The library owns the handles it
  *     returns and the device copies of the weights made at creation; it keeps
  *     no caller pointer after the call returns (the enqueued work still reads
