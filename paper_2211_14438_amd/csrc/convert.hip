@@ -602,75 +602,72 @@ __device__ void team_convert(double *t, const T *p, const int *didx, int C, int 
 }
 
 // Affine least-squares fit of the control net and its remainder range (same
-// quantities as lds_affine_fit), reading fibres along the fastest axis so
-// the other axes' digits are found once per fibre with constant divisors.
-// Thread 0 writes beta (mean, then the slope of every axis) to `beta_out`;
-// every thread gets the remainder extrema.
+// quantities as lds_affine_fit). The mean and the slope along the last axis
+// come from one pass over the fibres along that axis; the slope along every
+// other axis from a pass of its own (one accumulator each, the fibre's digit
+// for that axis by a multiply-high division). The coefficients go through
+// `bl` (LDS, n+1 doubles of the team) to every thread for the remainder pass;
+// thread 0 writes them to `beta_out` (mean, then the slope of every axis).
 template <int D, class Team>
 __device__ void team_fit(const double *t, int C, int n, const Team &tm, double *beta_out, double &rmax,
-                         double &rmin) {
+                         double &rmin, double *bl) {
   constexpr int D1 = D + 1;
   const int F = C / D1;
-  double m = 0.0, pl = 0.0, p[kMaxInputs - 1];
-#pragma unroll
-  for (int a = 0; a < kMaxInputs - 1; ++a) p[a] = 0.0;
-  for (int f = tm.tid; f < F; f += tm.nt) {
-    double S = 0.0, Sl = 0.0;
-#pragma unroll
-    for (int k = 0; k < D1; ++k) {
-      const double x = t[f * D1 + k];
-      S += x;
-      Sl = fma(x, (double)k / D - 0.5, Sl);
-    }
-    m += S;
-    pl += Sl;
-    int q = f;
-#pragma unroll
-    for (int a = kMaxInputs - 2; a >= 0; --a) {
-      if (a <= n - 2) {
-        const int d = q % D1;
-        q /= D1;
-        p[a] = fma(S, (double)d / D - 0.5, p[a]);
-      }
-    }
-  }
   double s1 = 0.0;
 #pragma unroll
   for (int k = 0; k <= D; ++k) s1 += ((double)k / D - 0.5) * ((double)k / D - 0.5);
   const double ss = s1 * (double)F;
-  const double b0 = tm.sum(m) / (double)C;
-  const double bl = tm.sum(pl) / ss;  // slope along the last axis
-  double bs[kMaxInputs - 1];          // slopes along axes 0..n-2
+  double m = 0.0, pl = 0.0;
+  for (int f = tm.tid; f < F; f += tm.nt) {
 #pragma unroll
-  for (int a = 0; a < kMaxInputs - 1; ++a) bs[a] = (a <= n - 2) ? tm.sum(p[a]) / ss : 0.0;
-  if (tm.tid == 0) {
-    beta_out[0] = b0;
-#pragma unroll
-    for (int a = 0; a < kMaxInputs - 1; ++a)
-      if (a <= n - 2) beta_out[1 + a] = bs[a];
-    beta_out[n] = bl;
+    for (int k = 0; k < D1; ++k) {
+      const double x = t[f * D1 + k];
+      m += x;
+      pl = fma(x, (double)k / D - 0.5, pl);
+    }
   }
+  const double b0 = tm.sum(m) / (double)C;
+  const double bL = tm.sum(pl) / ss;
+  unsigned pw = 1;  // D1^(n-2-a): stride of axis a's digit in the fibre index
+  for (int a = n - 2; a >= 0; --a) {
+    const unsigned magic = pw > 1 ? 0xFFFFFFFFu / pw + 1u : 0u;
+    double pa = 0.0;
+    for (int f = tm.tid; f < F; f += tm.nt) {
+      double S = 0.0;
+#pragma unroll
+      for (int k = 0; k < D1; ++k) S += t[f * D1 + k];
+      const unsigned q = pw == 1 ? (unsigned)f : __umulhi((unsigned)f, magic);
+      pa = fma(S, (double)(q % D1) / D - 0.5, pa);
+    }
+    const double ba = tm.sum(pa) / ss;
+    if (tm.tid == 0) bl[1 + a] = ba;
+    pw *= D1;
+  }
+  if (tm.tid == 0) {
+    bl[0] = b0;
+    bl[n] = bL;
+    for (int a = 0; a <= n; ++a) beta_out[a] = bl[a];
+  }
+  tm.sync();
   double hi = -INFINITY, lo = INFINITY;
   for (int f = tm.tid; f < F; f += tm.nt) {
     double lf = b0;
-    int q = f;
-#pragma unroll
-    for (int a = kMaxInputs - 2; a >= 0; --a) {
-      if (a <= n - 2) {
-        const int d = q % D1;
-        q /= D1;
-        lf = fma(bs[a], (double)d / D - 0.5, lf);
-      }
+    unsigned q = (unsigned)f;
+    for (int a = n - 2; a >= 0; --a) {
+      const unsigned d = q % D1;
+      q /= D1;
+      lf = fma(bl[1 + a], (double)d / D - 0.5, lf);
     }
 #pragma unroll
     for (int k = 0; k < D1; ++k) {
-      const double r = t[f * D1 + k] - fma(bl, (double)k / D - 0.5, lf);
+      const double r = t[f * D1 + k] - fma(bL, (double)k / D - 0.5, lf);
       hi = fmax(hi, r);
       lo = fmin(lo, r);
     }
   }
   rmax = tm.max(hi);
   rmin = tm.min(lo);
+  tm.sync();
 }
 
 // Bound of one side from its Bernstein extremum (FP32 mode: widened by the
@@ -703,13 +700,14 @@ __device__ inline void write_neuron(const ConvertArgs &a, int64_t box, int j, do
 // One wave per (box, neuron), one bound tensor at a time in the wave's LDS
 // slice.
 template <int D, typename T>
-__global__ void __launch_bounds__(kBlock) convert_wave_t(ConvertArgs a) {
+__global__ void __launch_bounds__(kBlock, 6) convert_wave_t(ConvertArgs a) {
   extern __shared__ double lds[];
   const WaveTeam tm{(int)(threadIdx.x & 63)};
   const int wv = threadIdx.x >> 6;
   const int C = (int)a.C;
   const int *pl = stage_prefixes(a, reinterpret_cast<int *>(lds));
-  double *tw = lds + (a.plist_len + 1) / 2 + (int64_t)wv * C;
+  double *tw = lds + (a.plist_len + 1) / 2 + (int64_t)wv * (C + kMaxInputs + 1);
+  double *bl = tw + C;  // fit coefficients of the wave
   const int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + wv;
   if (item >= a.nboxes * a.h) return;
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
@@ -739,13 +737,13 @@ __global__ void __launch_bounds__(kBlock) convert_wave_t(ConvertArgs a) {
     const double hib = side_hi(a, hub + 1e-12 * l1u, l1u, epsU);
     team_convert<D>(tw, p + S, a.didx, C, S, a.n, tm, l1L, mn, dummy, pl);
     if (side_lo(a, mn, l1L, epsL) < 0.0 && hib > 0.0) {
-      team_fit<D>(tw, C, a.n, tm, rec->fitL, fx[2], fx[3]);
+      team_fit<D>(tw, C, a.n, tm, rec->fitL, fx[2], fx[3], bl);
       lower_fitted = true;
     }
   } else {
     team_convert<D>(tw, p + S, a.didx, C, S, a.n, tm, l1L, mn, dummy, pl);
     if (want) {
-      team_fit<D>(tw, C, a.n, tm, rec->fitL, fx[2], fx[3]);
+      team_fit<D>(tw, C, a.n, tm, rec->fitL, fx[2], fx[3], bl);
       lower_fitted = true;
     }
   }
@@ -755,12 +753,12 @@ __global__ void __launch_bounds__(kBlock) convert_wave_t(ConvertArgs a) {
   const double hi = side_hi(a, mx, l1U, epsU);
   const bool fitted = want && (a.fits || (lo < 0.0 && hi > 0.0));
   if (fitted) {
-    team_fit<D>(tw, C, a.n, tm, rec->fitU, fx[0], fx[1]);
+    team_fit<D>(tw, C, a.n, tm, rec->fitU, fx[0], fx[1], bl);
     if (!lower_fitted) {  // not expected: the filter above is an upper bound of hi
       tm.sync();
       double u1, u2, u3;
       team_convert<D>(tw, p + S, a.didx, C, S, a.n, tm, u1, u2, u3, pl);
-      team_fit<D>(tw, C, a.n, tm, rec->fitL, fx[2], fx[3]);
+      team_fit<D>(tw, C, a.n, tm, rec->fitL, fx[2], fx[3], bl);
     }
   }
   if (tm.tid == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted);
@@ -776,6 +774,7 @@ __global__ void __launch_bounds__(1024) convert_block_t(ConvertArgs a) {
   const int *pl = stage_prefixes(a, reinterpret_cast<int *>(lds));
   double *t = lds + (a.plist_len + 1) / 2;
   const int C = (int)a.C;
+  double *bl = t + C;  // fit coefficients of the block
   const int64_t item = blockIdx.x;
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
   const int j = (int)(item % a.h);
@@ -804,13 +803,13 @@ __global__ void __launch_bounds__(1024) convert_block_t(ConvertArgs a) {
     const double hib = side_hi(a, hub + 1e-12 * l1u, l1u, epsU);
     team_convert<D>(t, p + S, a.didx, C, S, a.n, tm, l1L, mn, dummy, pl);
     if (side_lo(a, mn, l1L, epsL) < 0.0 && hib > 0.0) {
-      team_fit<D>(t, C, a.n, tm, rec->fitL, fx[2], fx[3]);
+      team_fit<D>(t, C, a.n, tm, rec->fitL, fx[2], fx[3], bl);
       lower_fitted = true;
     }
   } else {
     team_convert<D>(t, p + S, a.didx, C, S, a.n, tm, l1L, mn, dummy, pl);
     if (want) {
-      team_fit<D>(t, C, a.n, tm, rec->fitL, fx[2], fx[3]);
+      team_fit<D>(t, C, a.n, tm, rec->fitL, fx[2], fx[3], bl);
       lower_fitted = true;
     }
   }
@@ -820,12 +819,12 @@ __global__ void __launch_bounds__(1024) convert_block_t(ConvertArgs a) {
   const double hi = side_hi(a, mx, l1U, epsU);
   const bool fitted = want && (a.fits || (lo < 0.0 && hi > 0.0));
   if (fitted) {
-    team_fit<D>(t, C, a.n, tm, rec->fitU, fx[0], fx[1]);
+    team_fit<D>(t, C, a.n, tm, rec->fitU, fx[0], fx[1], bl);
     if (!lower_fitted) {  // not expected: the filter above is an upper bound of hi
       tm.sync();
       double u1, u2, u3;
       team_convert<D>(t, p + S, a.didx, C, S, a.n, tm, u1, u2, u3, pl);
-      team_fit<D>(t, C, a.n, tm, rec->fitL, fx[2], fx[3]);
+      team_fit<D>(t, C, a.n, tm, rec->fitL, fx[2], fx[3], bl);
     }
   }
   if (tm.tid == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted);
@@ -942,7 +941,7 @@ template <typename T, int D>
 static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
   const size_t plb = (size_t)((a.plist_len + 1) / 2) * sizeof(double);
   if (a.C <= kWaveC && a.tune.conv_wave == 0) {
-    const size_t lds = (size_t)(kBlock / 64) * a.C * sizeof(double) + plb;
+    const size_t lds = (size_t)(kBlock / 64) * (a.C + kMaxInputs + 1) * sizeof(double) + plb;
     RET_IF(hipFuncSetAttribute((const void *)convert_wave_t<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
     ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4),
@@ -952,7 +951,7 @@ static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
                        dim3(kBlock), lds, s, a);
     return hipGetLastError();
   }
-  const size_t lds = (size_t)a.C * sizeof(double) + plb;
+  const size_t lds = (size_t)(a.C + kMaxInputs + 1) * sizeof(double) + plb;
   if (lds + 256 > device_lds_limit()) return hipErrorInvalidValue;
   RET_IF(hipFuncSetAttribute((const void *)convert_block_t<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)lds));
