@@ -540,15 +540,49 @@ __device__ __forceinline__ void axis_pass_list(double *t, const int *list, int n
   }
 }
 
+// Last pass (axis 0, stride st = (D+1)^(n-1), fibre f = the digits of axes
+// 1 .. n-1) with the extrema of the coefficients and of the remainders
+// b_K - l(K/D) of an affine fit l (bl: beta_0, then the slope of every axis,
+// each about the box centre). The results are not stored back.
+template <int D, class Team>
+__device__ __forceinline__ void last_pass_fit(const double *t, int st, int n, const Team &tm, const double *bl,
+                                              double &mn, double &mx, double &rmn, double &rmx) {
+  constexpr int D1 = D + 1;
+  const double b1 = bl[1];
+  for (int f = tm.tid; f < st; f += tm.nt) {
+    double x[D1];
+#pragma unroll
+    for (int j = 0; j < D1; ++j) x[j] = t[f + j * st];
+    to_bern<D>(x);
+    double c = bl[0];
+    unsigned q = (unsigned)f;
+    for (int ax = n - 1; ax >= 1; --ax) {
+      c = fma(bl[1 + ax], (double)(q % D1) / D - 0.5, c);
+      q /= D1;
+    }
+#pragma unroll
+    for (int j = 0; j < D1; ++j) {
+      mn = fmin(mn, x[j]);
+      mx = fmax(mx, x[j]);
+      const double r = x[j] - fma(b1, (double)j / D - 0.5, c);
+      rmn = fmin(rmn, r);
+      rmx = fmax(rmx, r);
+    }
+  }
+}
+
 // Convert axes [0, na) of a tensor already in LDS whose axis na-1 has stride
 // s0 (axis a has stride s0 (D+1)^(na-1-a)); `total` coefficients. Tracks the
 // extrema of the last pass when `track` is set. With a prefix table `pl`
 // (simplex.hpp prefix_table for (D, na), in LDS) only the fibres that can be
 // nonzero are converted: valid when every nonzero coefficient of the tensor
-// has exponent sum <= D.
+// has exponent sum <= D. With a fit `bl` (whole tensor: s0 = 1, na = n) the
+// last pass also tracks the remainder extrema into rmn / rmx and leaves axis
+// 0 unconverted in LDS.
 template <int D, class Team>
 __device__ void team_axes(double *t, int total, int s0, int na, const Team &tm, bool track, double &mn,
-                          double &mx, const int *pl = nullptr) {
+                          double &mx, const int *pl = nullptr, const double *bl = nullptr,
+                          double *rmn = nullptr, double *rmx = nullptr) {
   constexpr int D1 = D + 1;
   const int F = total / D1;
   unsigned stride = (unsigned)s0;
@@ -556,7 +590,9 @@ __device__ void team_axes(double *t, int total, int s0, int na, const Team &tm, 
     tm.sync();
     const unsigned magic = stride > 1 ? 0xFFFFFFFFu / stride + 1u : 0u;
     const bool last = track && ax == 0;
-    if (pl) {
+    if (last && bl) {
+      last_pass_fit<D>(t, (int)stride, na, tm, bl, mn, mx, *rmn, *rmx);
+    } else if (pl) {
       const int np = pl[ax + 1] - pl[ax];
       if (last)
         axis_pass_list<D, true>(t, pl + pl[ax], np, stride, magic, tm, mn, mx);
@@ -584,90 +620,97 @@ __device__ inline const int *stage_prefixes(const ConvertArgs &a, int *dst) {
 // Stored power coefficients p[0, S) -> dense Bernstein tensor t[0, C)
 // (C = (D+1)^n; didx gives each stored coefficient's dense position, the
 // others are zero). Returns the team-wide sum of |p| and the extrema.
+// With a fit `bl` (LDS) also the remainder range of the fit, ext[0] = max and
+// ext[1] = min, and axis 0 is then left unconverted in t.
 template <int D, typename T, class Team>
 __device__ void team_convert(double *t, const T *p, const int *didx, int C, int S, int n, const Team &tm,
-                             double &l1, double &vmin, double &vmax, const int *pl) {
+                             double &l1, double &vmin, double &vmax, const int *pl, const double *bl = nullptr,
+                             double *ext = nullptr) {
   for (int i = tm.tid; i < C; i += tm.nt) t[i] = 0.0;
   tm.sync();
-  double s = 0.0, mn = INFINITY, mx = -INFINITY;
+  double s = 0.0, mn = INFINITY, mx = -INFINITY, rmn = INFINITY, rmx = -INFINITY;
   for (int i = tm.tid; i < S; i += tm.nt) {
     const double x = (double)p[i];
     t[didx[i]] = x;
     s += fabs(x);
   }
-  team_axes<D>(t, C, 1, n, tm, true, mn, mx, pl);
+  team_axes<D>(t, C, 1, n, tm, true, mn, mx, pl, bl, &rmn, &rmx);
   l1 = tm.sum(s);
   vmin = tm.min(mn);
   vmax = tm.max(mx);
+  if (bl) {
+    ext[0] = tm.max(rmx);
+    ext[1] = tm.min(rmn);
+  }
 }
 
-// Affine least-squares fit of the control net and its remainder range (same
-// quantities as lds_affine_fit). The mean and the slope along the last axis
-// come from one pass over the fibres along that axis; the slope along every
-// other axis from a pass of its own (one accumulator each, the fibre's digit
-// for that axis by a multiply-high division). The coefficients go through
-// `bl` (LDS, n+1 doubles of the team) to every thread for the remainder pass;
-// thread 0 writes them to `beta_out` (mean, then the slope of every axis).
+// Least-squares affine fit l(x) = beta_0 + sum_a beta_a (x_a - 1/2) of the
+// control net {(K/D, b_K)} (same quantities as lds_affine_fit), from the
+// stored coefficients a_J instead of the dense net. The centred grid
+// coordinates are orthogonal, so beta_0 is the mean of the b_K and beta_a
+// their first moment along axis a over sum_K (k_a/D - 1/2)^2. With
+// b_K = sum_J a_J prod_i C(k_i, j_i) / C(D, j_i) both sums factor over the
+// axes, and the one-axis sums over k = j .. D have closed forms
+// (hockey-stick identity): sum_k C(k,j)/C(D,j) = (D+1)/(j+1),
+// sum_k C(k,j)/C(D,j) (k/D - 1/2) = (D+1)/(j+1) * j (D+2) / (2 D (j+2)), and
+// sum_k (k/D - 1/2)^2 = (D+1)(D+2) / (12 D). What remains is
+//   beta_0 = sum_J w_J,   beta_a = 6 sum_J w_J j_a / (j_a + 2),
+//   w_J = a_J / prod_i (j_i + 1),
+// independent of D. One wave computes it (didx gives each J's digits, axis
+// n-1 fastest) into bl[0 .. n] in LDS; the caller's barrier publishes it.
+template <typename T>
+__device__ void wave_fit(const T *p, const int *didx, int S, int n, int D, int lane, double *bl) {
+  const unsigned D1 = (unsigned)D + 1u;
+  for (int base = 0; base < S; base += 64) {
+    const int i = base + lane;
+    double w = 0.0;
+    unsigned dig = 0u;
+    if (i < S) {
+      dig = (unsigned)didx[i];
+      double den = 1.0;
+      unsigned d = dig;
+      for (int ax = 0; ax < n; ++ax) {
+        den *= (double)(d % D1 + 1u);
+        d /= D1;
+      }
+      w = (double)p[i] / den;
+    }
+    const double b0 = wave_reduce(w, OpAdd());
+    for (int ax = n - 1; ax >= 0; --ax) {
+      const double k = (double)(dig % D1);
+      dig /= D1;
+      const double ba = wave_reduce(6.0 * w * k / (k + 2.0), OpAdd());
+      if (lane == 0) bl[1 + ax] = base == 0 ? ba : bl[1 + ax] + ba;
+    }
+    if (lane == 0) bl[0] = base == 0 ? b0 : bl[0] + b0;
+  }
+}
+
+// Remainder range of the fit bl over the converted tensor in LDS (rmax =
+// max_K b_K - l(K/D), rmin = min): one pass over the fibres along axis 0.
 template <int D, class Team>
-__device__ void team_fit(const double *t, int C, int n, const Team &tm, double *beta_out, double &rmax,
-                         double &rmin, double *bl) {
+__device__ void team_remainder(const double *t, int C, int n, const Team &tm, const double *bl, double &rmax,
+                               double &rmin) {
   constexpr int D1 = D + 1;
-  const int F = C / D1;
-  double s1 = 0.0;
-#pragma unroll
-  for (int k = 0; k <= D; ++k) s1 += ((double)k / D - 0.5) * ((double)k / D - 0.5);
-  const double ss = s1 * (double)F;
-  double m = 0.0, pl = 0.0;
-  for (int f = tm.tid; f < F; f += tm.nt) {
-#pragma unroll
-    for (int k = 0; k < D1; ++k) {
-      const double x = t[f * D1 + k];
-      m += x;
-      pl = fma(x, (double)k / D - 0.5, pl);
-    }
-  }
-  const double b0 = tm.sum(m) / (double)C;
-  const double bL = tm.sum(pl) / ss;
-  unsigned pw = 1;  // D1^(n-2-a): stride of axis a's digit in the fibre index
-  for (int a = n - 2; a >= 0; --a) {
-    const unsigned magic = pw > 1 ? 0xFFFFFFFFu / pw + 1u : 0u;
-    double pa = 0.0;
-    for (int f = tm.tid; f < F; f += tm.nt) {
-      double S = 0.0;
-#pragma unroll
-      for (int k = 0; k < D1; ++k) S += t[f * D1 + k];
-      const unsigned q = pw == 1 ? (unsigned)f : __umulhi((unsigned)f, magic);
-      pa = fma(S, (double)(q % D1) / D - 0.5, pa);
-    }
-    const double ba = tm.sum(pa) / ss;
-    if (tm.tid == 0) bl[1 + a] = ba;
-    pw *= D1;
-  }
-  if (tm.tid == 0) {
-    bl[0] = b0;
-    bl[n] = bL;
-    for (int a = 0; a <= n; ++a) beta_out[a] = bl[a];
-  }
-  tm.sync();
+  const int st = C / D1;
+  const double b1 = bl[1];
   double hi = -INFINITY, lo = INFINITY;
-  for (int f = tm.tid; f < F; f += tm.nt) {
-    double lf = b0;
+  for (int f = tm.tid; f < st; f += tm.nt) {
+    double c = bl[0];
     unsigned q = (unsigned)f;
-    for (int a = n - 2; a >= 0; --a) {
-      const unsigned d = q % D1;
+    for (int ax = n - 1; ax >= 1; --ax) {
+      c = fma(bl[1 + ax], (double)(q % D1) / D - 0.5, c);
       q /= D1;
-      lf = fma(bl[1 + a], (double)d / D - 0.5, lf);
     }
 #pragma unroll
-    for (int k = 0; k < D1; ++k) {
-      const double r = t[f * D1 + k] - fma(bL, (double)k / D - 0.5, lf);
+    for (int j = 0; j < D1; ++j) {
+      const double r = t[f + j * st] - fma(b1, (double)j / D - 0.5, c);
       hi = fmax(hi, r);
       lo = fmin(lo, r);
     }
   }
   rmax = tm.max(hi);
   rmin = tm.min(lo);
-  tm.sync();
 }
 
 // Bound of one side from its Bernstein extremum (FP32 mode: widened by the
@@ -697,6 +740,73 @@ __device__ inline void write_neuron(const ConvertArgs &a, int64_t box, int j, do
   }
 }
 
+// Both bound tensors of neuron (box, j) by one team with `t` (C doubles) and
+// `bl` (n+1 doubles) in LDS; `fitter` marks the team's first wave, which
+// computes the fits. Lower tensor first: it is fitted while resident if the
+// neuron can still take a fitted rule, i.e. its lower bound is negative and
+// an upper bound of the upper tensor's largest Bernstein coefficient (its
+// constant plus its positive coefficients, the ratio table lying in [0,1])
+// is positive. The upper tensor's fit is then computed before its read-off,
+// whose last pass also gives the remainder range.
+template <int D, typename T, class Team>
+__device__ void readoff_pair(const ConvertArgs &a, const Team &tm, bool fitter, int lane, double *t, double *bl,
+                             const int *pl, int64_t box, int j) {
+  const int C = (int)a.C, S = (int)a.S;
+  const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + (int64_t)j * 2 * a.S;
+  double epsU = 0.0, epsL = 0.0;
+  if (!a.fp64) pre_radii(a, box, j, a.pre, tm.tid, tm.nt, [&](double v) { return tm.sum(v); }, epsU, epsL);
+  const bool want = wants_fit(a, box, j);
+  NeuronRec *rec = want ? &a.recs[box * a.h + j] : nullptr;
+  double fx[4] = {0.0, 0.0, 0.0, 0.0};  // rmaxU, rminU, rmaxL, rminL
+  double l1L, l1U, mn, mx, dummy;
+  double hib = INFINITY;
+  if (want && !a.fits) {
+    double hub = 0.0, l1u = 0.0;
+    for (int i = tm.tid; i < S; i += tm.nt) {
+      const double v = (double)p[i];
+      l1u += fabs(v);
+      hub += i == 0 ? v : fmax(v, 0.0);
+    }
+    hub = tm.sum(hub);
+    l1u = tm.sum(l1u);
+    hib = side_hi(a, hub + 1e-12 * l1u, l1u, epsU);
+  }
+  team_convert<D>(t, p + S, a.didx, C, S, a.n, tm, l1L, mn, dummy, pl);
+  const double lo = side_lo(a, mn, l1L, epsL);
+  const bool lower_fitted = want && (a.fits || (lo < 0.0 && hib > 0.0));
+  if (lower_fitted) {
+    if (fitter) wave_fit(p + S, a.didx, S, a.n, D, lane, bl);
+    tm.sync();
+    team_remainder<D>(t, C, a.n, tm, bl, fx[2], fx[3]);
+    if (tm.tid == 0)
+      for (int q = 0; q <= a.n; ++q) rec->fitL[q] = bl[q];
+    tm.sync();
+    if (fitter) wave_fit(p, a.didx, S, a.n, D, lane, bl);
+  }
+  tm.sync();
+  team_convert<D>(t, p, a.didx, C, S, a.n, tm, l1U, dummy, mx, pl, lower_fitted ? bl : nullptr, fx);
+  const double hi = side_hi(a, mx, l1U, epsU);
+  const bool fitted = want && (a.fits || (lo < 0.0 && hi > 0.0));
+  if (fitted && !lower_fitted) {  // not expected: the filter above is an upper bound of hi
+    double u1, u2, u3;
+    if (fitter) wave_fit(p, a.didx, S, a.n, D, lane, bl);
+    tm.sync();
+    team_convert<D>(t, p, a.didx, C, S, a.n, tm, u1, u2, u3, pl, bl, fx);
+    if (tm.tid == 0)
+      for (int q = 0; q <= a.n; ++q) rec->fitU[q] = bl[q];
+    tm.sync();
+    team_convert<D>(t, p + S, a.didx, C, S, a.n, tm, u1, u2, u3, pl);
+    if (fitter) wave_fit(p + S, a.didx, S, a.n, D, lane, bl);
+    tm.sync();
+    team_remainder<D>(t, C, a.n, tm, bl, fx[2], fx[3]);
+    if (tm.tid == 0)
+      for (int q = 0; q <= a.n; ++q) rec->fitL[q] = bl[q];
+  } else if (fitted && tm.tid == 0) {
+    for (int q = 0; q <= a.n; ++q) rec->fitU[q] = bl[q];
+  }
+  if (tm.tid == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted);
+}
+
 // One wave per (box, neuron), one bound tensor at a time in the wave's LDS
 // slice.
 template <int D, typename T>
@@ -707,61 +817,10 @@ __global__ void __launch_bounds__(kBlock, 6) convert_wave_t(ConvertArgs a) {
   const int C = (int)a.C;
   const int *pl = stage_prefixes(a, reinterpret_cast<int *>(lds));
   double *tw = lds + (a.plist_len + 1) / 2 + (int64_t)wv * (C + kMaxInputs + 1);
-  double *bl = tw + C;  // fit coefficients of the wave
   const int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + wv;
   if (item >= a.nboxes * a.h) return;
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
-  const int j = (int)(item % a.h);
-  const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + (int64_t)j * 2 * a.S;
-  const int S = (int)a.S;
-  double epsU = 0.0, epsL = 0.0;
-  if (!a.fp64) pre_radii(a, box, j, a.pre, tm.tid, 64, [&](double v) { return tm.sum(v); }, epsU, epsL);
-  const bool want = wants_fit(a, box, j);
-  NeuronRec *rec = want ? &a.recs[box * a.h + j] : nullptr;
-  double fx[4] = {0.0, 0.0, 0.0, 0.0};
-  double l1L, l1U, mn, mx, dummy;
-  // Lower tensor first. It is fitted while resident if the neuron can still
-  // take a fitted rule: lower bound negative and an upper bound of the upper
-  // tensor's largest Bernstein coefficient (its constant plus its positive
-  // coefficients, the ratio table lying in [0,1]) positive.
-  bool lower_fitted = false;
-  if (want && !a.fits) {
-    double hub = 0.0, l1u = 0.0;
-    for (int i = tm.tid; i < S; i += tm.nt) {
-      const double v = (double)p[i];
-      l1u += fabs(v);
-      hub += i == 0 ? v : fmax(v, 0.0);
-    }
-    hub = tm.sum(hub);
-    l1u = tm.sum(l1u);
-    const double hib = side_hi(a, hub + 1e-12 * l1u, l1u, epsU);
-    team_convert<D>(tw, p + S, a.didx, C, S, a.n, tm, l1L, mn, dummy, pl);
-    if (side_lo(a, mn, l1L, epsL) < 0.0 && hib > 0.0) {
-      team_fit<D>(tw, C, a.n, tm, rec->fitL, fx[2], fx[3], bl);
-      lower_fitted = true;
-    }
-  } else {
-    team_convert<D>(tw, p + S, a.didx, C, S, a.n, tm, l1L, mn, dummy, pl);
-    if (want) {
-      team_fit<D>(tw, C, a.n, tm, rec->fitL, fx[2], fx[3], bl);
-      lower_fitted = true;
-    }
-  }
-  const double lo = side_lo(a, mn, l1L, epsL);
-  tm.sync();
-  team_convert<D>(tw, p, a.didx, C, S, a.n, tm, l1U, dummy, mx, pl);
-  const double hi = side_hi(a, mx, l1U, epsU);
-  const bool fitted = want && (a.fits || (lo < 0.0 && hi > 0.0));
-  if (fitted) {
-    team_fit<D>(tw, C, a.n, tm, rec->fitU, fx[0], fx[1], bl);
-    if (!lower_fitted) {  // not expected: the filter above is an upper bound of hi
-      tm.sync();
-      double u1, u2, u3;
-      team_convert<D>(tw, p + S, a.didx, C, S, a.n, tm, u1, u2, u3, pl);
-      team_fit<D>(tw, C, a.n, tm, rec->fitL, fx[2], fx[3], bl);
-    }
-  }
-  if (tm.tid == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted);
+  readoff_pair<D, T>(a, tm, true, tm.tid, tw, tw + C, pl, box, (int)(item % a.h));
 }
 
 // One block per (box, neuron) for tensors up to kSmallLds coefficients, one
@@ -773,61 +832,9 @@ __global__ void __launch_bounds__(1024) convert_block_t(ConvertArgs a) {
   const BlockTeam tm{(int)threadIdx.x, (int)blockDim.x, red};
   const int *pl = stage_prefixes(a, reinterpret_cast<int *>(lds));
   double *t = lds + (a.plist_len + 1) / 2;
-  const int C = (int)a.C;
-  double *bl = t + C;  // fit coefficients of the block
   const int64_t item = blockIdx.x;
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
-  const int j = (int)(item % a.h);
-  const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + (int64_t)j * 2 * a.S;
-  const int S = (int)a.S;
-  double epsU = 0.0, epsL = 0.0;
-  if (!a.fp64) pre_radii(a, box, j, a.pre, tm.tid, tm.nt, [&](double v) { return tm.sum(v); }, epsU, epsL);
-  const bool want = wants_fit(a, box, j);
-  NeuronRec *rec = want ? &a.recs[box * a.h + j] : nullptr;
-  double fx[4] = {0.0, 0.0, 0.0, 0.0};
-  double l1L, l1U, mn, mx, dummy;
-  // Lower tensor first. It is fitted while resident if the neuron can still
-  // take a fitted rule: lower bound negative and an upper bound of the upper
-  // tensor's largest Bernstein coefficient (its constant plus its positive
-  // coefficients, the ratio table lying in [0,1]) positive.
-  bool lower_fitted = false;
-  if (want && !a.fits) {
-    double hub = 0.0, l1u = 0.0;
-    for (int i = tm.tid; i < S; i += tm.nt) {
-      const double v = (double)p[i];
-      l1u += fabs(v);
-      hub += i == 0 ? v : fmax(v, 0.0);
-    }
-    hub = tm.sum(hub);
-    l1u = tm.sum(l1u);
-    const double hib = side_hi(a, hub + 1e-12 * l1u, l1u, epsU);
-    team_convert<D>(t, p + S, a.didx, C, S, a.n, tm, l1L, mn, dummy, pl);
-    if (side_lo(a, mn, l1L, epsL) < 0.0 && hib > 0.0) {
-      team_fit<D>(t, C, a.n, tm, rec->fitL, fx[2], fx[3], bl);
-      lower_fitted = true;
-    }
-  } else {
-    team_convert<D>(t, p + S, a.didx, C, S, a.n, tm, l1L, mn, dummy, pl);
-    if (want) {
-      team_fit<D>(t, C, a.n, tm, rec->fitL, fx[2], fx[3], bl);
-      lower_fitted = true;
-    }
-  }
-  const double lo = side_lo(a, mn, l1L, epsL);
-  tm.sync();
-  team_convert<D>(t, p, a.didx, C, S, a.n, tm, l1U, dummy, mx, pl);
-  const double hi = side_hi(a, mx, l1U, epsU);
-  const bool fitted = want && (a.fits || (lo < 0.0 && hi > 0.0));
-  if (fitted) {
-    team_fit<D>(t, C, a.n, tm, rec->fitU, fx[0], fx[1], bl);
-    if (!lower_fitted) {  // not expected: the filter above is an upper bound of hi
-      tm.sync();
-      double u1, u2, u3;
-      team_convert<D>(t, p + S, a.didx, C, S, a.n, tm, u1, u2, u3, pl);
-      team_fit<D>(t, C, a.n, tm, rec->fitL, fx[2], fx[3], bl);
-    }
-  }
-  if (tm.tid == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted);
+  readoff_pair<D, T>(a, tm, threadIdx.x < 64, (int)(threadIdx.x & 63), t, t + a.C, pl, box, (int)(item % a.h));
 }
 
 // Tensors beyond one block's LDS, without staging: the first m axes are
