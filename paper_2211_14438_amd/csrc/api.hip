@@ -438,7 +438,7 @@ __global__ void box_degree_kernel(int64_t nb, int h, const NeuronRec *recs, int 
 // Horner tables (Din, m Din), m = 1 .. Lmax - 1. Built once per network.
 struct LayerTables {
   const int *didx = nullptr;
-  const SliceTable *sl = nullptr;
+  const TreeTable *tree = nullptr;
   const int *plist = nullptr;
   int plist_len = 0;
   const ProdTable *sq = nullptr;
@@ -447,10 +447,9 @@ struct LayerTables {
 
 static bern_status layer_tables(const bern_net *net, int Din, int Lmax, bool compose, LayerTables &t) {
   hipError_t e = dense_index_table(*net->tab, Din, &t.didx);
-  const int tm = convert_tile_m(net->n, Din);
-  if (e == hipSuccess && tm >= 0) e = slice_table(*net->tab, Din, tm, &t.sl);
-  if (e == hipSuccess && Din >= 1 && Din <= 8)
-    e = prefix_table(*net->tab, Din, tm >= 0 ? net->n - tm : net->n, &t.plist, &t.plist_len);
+  const bool tree = convert_tree(net->n, Din);
+  if (e == hipSuccess && tree) e = tree_table(*net->tab, Din, &t.tree);
+  if (e == hipSuccess && !tree && Din >= 1 && Din <= 8) e = prefix_table(*net->tab, Din, net->n, &t.plist, &t.plist_len);
   if (e == hipSuccess && compose && Lmax >= 2) e = product_table(*net->tab, Din, Din, true, &t.sq);
   for (int m = 1; e == hipSuccess && compose && m <= Lmax - 1 && Lmax >= 3; ++m)
     e = product_table(*net->tab, Din, m * Din, false, &t.hz[m]);
@@ -567,12 +566,10 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       c.didx = lt.didx;
       c.plist = lt.plist;
       c.plist_len = lt.plist_len;
-      if (lt.sl) {
-        c.sl_ncell = lt.sl->ncell;
-        c.sl_cell = lt.sl->cell;
-        c.sl_off = lt.sl->off;
-        c.sl_rank = lt.sl->rank;
-        c.sl_dig = lt.sl->dig;
+      if (lt.tree) {
+        c.tree = lt.tree->buf;
+        c.tree_len = lt.tree->len;
+        for (int d = 0; d <= n && d < 17; ++d) c.tree_base[d] = lt.tree->base[d];
       }
       c.nboxes = (int64_t)cl.ids.size();
       c.bids = cid[k];

@@ -215,23 +215,23 @@ struct ConvertArgs {
   double *scratch;                // staging and partial extrema for tensors too large for LDS
   size_t scratch_bytes;
   Tune tune;
-  // tensors beyond LDS: stored coefficients grouped by leading exponents
-  // (simplex.hpp SliceTable for the split convert_tile_m(n, D)), or null
-  int sl_ncell;
-  const int *sl_cell;
-  const int *sl_off;
-  const int *sl_rank;
-  const unsigned long long *sl_dig;
+  // tensors beyond LDS: the child tables of the tree read-off (simplex.hpp
+  // TreeTable for degree D), or null
+  const int *tree;
+  int tree_len;
+  int tree_base[17];
   int gextra;                     // rounding steps beyond the per-axis basis change (set by the launcher)
-  // simplex.hpp prefix_table for (D, n), or (D, n - convert_tile_m(n, D)) for
-  // tensors beyond LDS; null for degrees without a compile-time kernel
+  // simplex.hpp prefix_table for (D, n), or (D, m) of the split
+  // convert_nest(n, D) for tensors beyond LDS; null for degrees without a
+  // compile-time kernel
   const int *plist;
   int plist_len;
 };
 hipError_t launch_convert(const ConvertArgs &a, hipStream_t s);
 size_t convert_scratch_bytes(int n, int D, int h, int64_t nboxes);
-// Trailing axes of the staging-free path for tensors beyond LDS, or -1.
-int convert_tile_m(int n, int D);
+// Whether tensors of n variables and degree D take the tree read-off (they
+// then need the TreeTable of degree D).
+bool convert_tree(int n, int D);
 
 struct ComposeArgs {
   int n, Din, Dout, h;

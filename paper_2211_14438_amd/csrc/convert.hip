@@ -26,6 +26,8 @@
 #include "rules.hpp"
 #include "simplex.hpp"
 
+#include <type_traits>
+
 namespace bern {
 
 constexpr int kSmallLds = 16384;  // FP64 elements of a tensor converted in one block (128 KiB)
@@ -837,109 +839,312 @@ __global__ void __launch_bounds__(1024) convert_block_t(ConvertArgs a) {
   readoff_pair<D, T>(a, tm, threadIdx.x < 64, (int)(threadIdx.x & 63), t, t + a.C, pl, box, (int)(item % a.h));
 }
 
-// Tensors beyond one block's LDS, without staging: the first m axes are
-// fixed per block (chunk k = the dense index of their exponents) and the
-// block converts the (D+1)^(n-m) tensor of the trailing axes in LDS. The
-// basis change is a product over axes, so the chunk's slice of Bernstein
-// coefficients is the trailing-axes basis change of
-//   g(c) = sum over stored J with trailing exponents c of
-//          a_J prod_{i<m} C(k_i, j_i) / C(D, j_i)
-// (the slice table lists the cells c that hold any J, and their J; a factor
-// with j_i > k_i is zero).
-// Its extremum goes to the partials, the l1 norm once per tensor. The sums
-// over J add at most S rounding steps (ConvertArgs::gextra).
-struct Chunking {
-  int lead;       // axes fixed per chunk
-  int64_t cells;  // (D+1)^(n - lead)
-  int64_t nchunk; // (D+1)^lead
-  int64_t per;    // chunks per block (set by the launcher)
-  int64_t groups; // blocks per tensor
+// Tensors beyond one block's LDS: the tree read-off. The basis change is a
+// product over variables, so fixing the leading variable of a polynomial at
+// Bernstein index k leaves the polynomial in the other variables
+//   q_k(rest) = sum_j C(k, j) / C(D, j) p_j(rest)
+// where p_j collects the terms with exponent j of the leading variable; its
+// total degree stays <= D, so q_k is stored in the (d-1)-variable layout
+// (the child table of simplex.hpp TreeTable gives the parent rank of every
+// (j, rest)). Applying this to the leading n - M variables, one at a time,
+// yields for every Bernstein index of those variables an M-variable
+// polynomial whose own basis change gives exactly the Bernstein
+// coefficients at that index; no dense tensor is formed.
+//
+// A block owns one tensor and the first lo leading indices (ko); it folds
+// them once, then runs (D+1)^q rounds over the next q indices (a chain of
+// single folds, refolded from the first changed index on), and in each round
+// expands the following e-1 variables into all (D+1)^(e-1) index
+// combinations in LDS; finally each lane folds the last one at its own index
+// and converts its (D+1)^M tile in registers, tracking the extremum of the
+// tensor's side. Every step applies one ratio per variable in a sum of at
+// most D+1 terms, within the n(D+2) rounding steps of the per-axis change.
+constexpr int tree_tile_axes(int D) { return D == 1 ? 5 : D == 2 ? 3 : D <= 5 ? 2 : 1; }
+
+constexpr int cpow(int b, int e) {
+  int r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+
+// Calls f(std::integral_constant<int, I>) for I = B .. E-1, unrolled.
+template <int B, int E>
+struct Unroll {
+  template <class F>
+  __device__ static __forceinline__ void run(F &&f) {
+    f(std::integral_constant<int, B>{});
+    Unroll<B + 1, E>::run(f);
+  }
+};
+template <int E>
+struct Unroll<E, E> {
+  template <class F>
+  __device__ static __forceinline__ void run(F &&) {}
 };
 
-template <int D, typename T>
-__global__ void __launch_bounds__(1024) convert_chunk_t(ConvertArgs a, Chunking ck, double *partial,
-                                                        double *l1part) {
+// The layout of NV variables of degree D (as simplex.hpp: graded by total
+// degree, descending lexicographic within a degree) at compile time.
+template <int D, int NV>
+struct CSimplex {
+  static constexpr int D1 = D + 1, dense = cpow(D + 1, NV), count = (int)binom_u(NV + D, D);
+  int dense_of[count];  // dense index (variable 0 most significant) of each rank
+  static constexpr int dsum(int v) {
+    int s = 0;
+    for (; v > 0; v /= D1) s += v % D1;
+    return s;
+  }
+  constexpr CSimplex() : dense_of() {
+    int r = 0;
+    for (int t = 0; t <= D; ++t)
+      for (int v = dense - 1; v >= 0; --v)
+        if (dsum(v) == t) dense_of[r++] = v;
+  }
+  constexpr int rank_of(int v) const {
+    for (int r = 0; r < count; ++r)
+      if (dense_of[r] == v) return r;
+    return -1;
+  }
+};
+
+// The lane's last fold: for each coefficient c of its M-variable polynomial
+// (dense tile index dl, degree budget deg = D - |c|) the parent ranks of
+// (j, c), j = 0 .. deg, in the (M+1)-variable layout.
+template <int D, int M>
+struct LaneTab {
+  static constexpr int NC = CSimplex<D, M>::count;
+  int dl[NC], deg[NC], pr[NC][D + 1];
+  constexpr LaneTab() : dl(), deg(), pr() {
+    const CSimplex<D, M> cm{};
+    const CSimplex<D, M + 1> cp{};
+    for (int c = 0; c < NC; ++c) {
+      dl[c] = cm.dense_of[c];
+      deg[c] = D - CSimplex<D, M>::dsum(dl[c]);
+      for (int j = 0; j <= D; ++j) pr[c][j] = j <= deg[c] ? cp.rank_of(j * cpow(D + 1, M) + dl[c]) : 0;
+    }
+  }
+};
+template <int D, int M>
+struct LaneTabs {
+  static constexpr LaneTab<D, M> t{};
+};
+
+// Basis change of an in-register block x (local index: its variables'
+// digits, the first slowest) along each of its SZ variables.
+template <int D, int SZ, int N>
+__device__ __forceinline__ void block_to_bern(double (&x)[N]) {
+  constexpr int D1 = D + 1;
+  static_assert(cpow(D + 1, SZ) == N, "block size");
+  Unroll<0, SZ>::run([&](auto Q) {
+    constexpr int s = cpow(D + 1, SZ - 1 - Q.value);  // local stride of the variable
+    Unroll<0, N / D1>::run([&](auto L) {
+      constexpr int line = (L.value / s) * s * D1 + L.value % s;
+      double y[D1];
+#pragma unroll
+      for (int j = 0; j < D1; ++j) y[j] = x[line + j * s];
+      to_bern<D>(y);
+#pragma unroll
+      for (int j = 0; j < D1; ++j) x[line + j * s] = y[j];
+    });
+  });
+}
+
+// Lane stage: fold the parent's leading variable at the lane's index (ratio
+// row rk), convert the M-variable tile, fold its extremum into ext.
+template <int D, int M, bool kMax>
+__device__ __forceinline__ void tree_lane(const double *par, const double (&rk)[D + 1], double &ext) {
+  using LT = LaneTabs<D, M>;
+  constexpr int N = cpow(D + 1, M);
+  double x[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) x[q] = 0.0;
+  Unroll<0, LaneTab<D, M>::NC>::run([&](auto C) {
+    constexpr int c = C.value;
+    double g = 0.0;
+    Unroll<0, LT::t.deg[c] + 1>::run([&](auto J) { g = fma(rk[J.value], par[LT::t.pr[c][J.value]], g); });
+    x[LT::t.dl[c]] = g;
+  });
+  block_to_bern<D, M>(x);
+#pragma unroll
+  for (int q = 0; q < N; ++q) ext = kMax ? fmax(ext, x[q]) : fmin(ext, x[q]);
+}
+
+// One fold of a single polynomial of d variables (in) at index k into the
+// d-1 variables' layout (out, Sc coefficients); off: dimension d's offsets.
+__device__ __forceinline__ void tree_fold(const double *in, double *out, const int *tb, const int *off, int Sc,
+                                          const double *rk, int k, int tid, int nt) {
+  for (int r = tid; r < Sc; r += nt) {
+    const int b = off[r], cnt = min(off[r + 1] - b, k + 1);
+    double s = 0.0;
+    for (int j = 0; j < cnt; ++j) s = fma(rk[j], in[tb[b + j]], s);
+    out[r] = s;
+  }
+}
+
+// V polynomials of d variables (Sp coefficients each) into V (D+1) of d-1
+// variables (Sc each): out variant v (D+1) + k is in variant v at index k.
+// A thread takes one (v, r): the parents (j, r), j <= D - |r|, zero-padded
+// to D+1 values, give all D+1 indices at once by the one-variable basis
+// change.
+template <int D>
+__device__ __forceinline__ void tree_expand(const double *in, double *out, const int *tb, const int *off, int Sp,
+                                            int Sc, int V, int tid, int nt) {
+  constexpr int D1 = D + 1;
+  const unsigned magic = Sc > 1 ? 0xFFFFFFFFu / (unsigned)Sc + 1u : 0u;
+  const int total = V * Sc;
+  for (int o = tid; o < total; o += nt) {
+    const int v = Sc == 1 ? o : (int)__umulhi((unsigned)o, magic);
+    const int r = o - v * Sc;
+    const int b = off[r], cnt = off[r + 1] - b;
+    const double *src = in + (int64_t)v * Sp;
+    double x[D1];
+#pragma unroll
+    for (int j = 0; j < D1; ++j) x[j] = j < cnt ? src[tb[b + j]] : 0.0;
+    to_bern<D>(x);
+    double *dst = out + (int64_t)v * D1 * Sc + r;
+#pragma unroll
+    for (int k = 0; k < D1; ++k) dst[k * Sc] = x[k];
+  }
+}
+
+struct TreePlan {
+  int lo = -1, q = 0, e = 0;  // indices fixed per block, per round (chain), expanded per round
+  int64_t nchunk = 0;         // (D+1)^lo blocks, and partials, per tensor
+  int rounds = 0, lanes = 0, threads = 0;
+  int S[kMaxInputs + 1] = {};  // S(d, D), d = 0 .. n
+};
+
+template <int D, int M, typename T>
+__global__ void __launch_bounds__(1024) convert_tree_t(ConvertArgs a, TreePlan tp, double *partial,
+                                                       double *l1part) {
   extern __shared__ double lds[];
   __shared__ double red[16];
   constexpr int D1 = D + 1;
-  const BlockTeam tm{(int)threadIdx.x, (int)blockDim.x, red};
-  const int Ct = (int)ck.cells, S = (int)a.S;
-  const int *pl = stage_prefixes(a, reinterpret_cast<int *>(lds));
-  double *t = lds + (a.plist_len + 1) / 2;  // [Ct]
-  double *av = t + Ct;      // [S]
-  double *tab = av + S;     // [D1][D1] C(k,j)/C(D,j)
   constexpr Ratio<D> R{};
+  const int tid = threadIdx.x, nt = blockDim.x, n = a.n;
+  const BlockTeam bt{tid, nt, red};
+  // LDS: child tables (ints), ratio table, root, chain levels, expansions
+  int *tb = reinterpret_cast<int *>(lds);
+  for (int i = tid; i < a.tree_len; i += nt) tb[i] = a.tree[i];
+  double *tab = lds + (a.tree_len + 1) / 2;
+  double *chain = tab + D1 * D1;  // levels 1 .. lo + q
+  int nchain = tp.lo + tp.q, cdim = n - nchain;
+  int chain_size = 0;
+  for (int i = 1; i <= nchain; ++i) chain_size += tp.S[n - i];
+  // the stored coefficients: when the block fixes indices (lo >= 1) they are
+  // read only by its first fold and share the expansions' area; otherwise
+  // the rounds refold from them and they get their own
+  double *root = chain + chain_size;
+  double *expd = tp.lo >= 1 ? root : root + tp.S[n];  // expansions 1 .. e - 1
+  if (tid == 0) {
+#pragma unroll
+    for (int i = 0; i < D1 * D1; ++i) tab[i] = R.v[i / D1][i % D1];
+  }
   const int64_t tensor = blockIdx.y;
-  const int s = (int)(tensor & 1);
+  const int side = (int)(tensor & 1);  // 1: lower bound tensor (minimum), 0: upper (maximum)
   const int64_t gb = tensor / (2 * a.h), rest = tensor % (2 * a.h);
   const int64_t box = a.bids ? a.bids[gb] : gb;
   const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + rest * a.S;
   double l1 = 0.0;
-  for (int i = tm.tid; i < S; i += tm.nt) {
+  for (int i = tid; i < tp.S[n]; i += nt) {
     const double v = (double)p[i];
-    av[i] = v;
+    root[i] = v;
     l1 += fabs(v);
   }
-  for (int i = tm.tid; i < D1 * D1; i += tm.nt) tab[i] = R.v[i / D1][i % D1];
-  double mn = INFINITY, mx = -INFINITY;
-  const int k0 = (int)(blockIdx.x * ck.per), k1 = (int)min(ck.nchunk, (int64_t)k0 + ck.per);
-  for (int k = k0; k < k1; ++k) {
-    unsigned long long kq = 0;  // exponents of the fixed axes, axis i at bits 4i
-    {
-      unsigned rem = (unsigned)k;
-      for (int i = ck.lead - 1; i >= 0; --i) {
-        kq |= (unsigned long long)(rem % D1) << (4 * i);
-        rem /= D1;
-      }
-    }
-    for (int c = tm.tid; c < Ct; c += tm.nt) t[c] = 0.0;
-    tm.sync();
-    // only the cells that hold stored coefficients receive a sum
-    for (int gi = tm.tid; gi < a.sl_ncell; gi += tm.nt) {
-      double g = 0.0;
-      const int end = a.sl_off[gi + 1];
-      for (int te = a.sl_off[gi]; te < end; ++te) {
-        const unsigned long long jq = a.sl_dig[te];
-        double w = av[a.sl_rank[te]];
-        for (int i = 0; i < ck.lead; ++i)
-          w *= tab[(int)((kq >> (4 * i)) & 15) * D1 + (int)((jq >> (4 * i)) & 15)];
-        g += w;
-      }
-      t[a.sl_cell[gi]] = g;
-    }
-    team_axes<D>(t, Ct, 1, a.n - ck.lead, tm, true, mn, mx, pl);  // ends with a barrier
-  }
-  const double v = s ? tm.min(mn) : tm.max(mx);
-  if (tm.tid == 0) partial[tensor * ck.groups + blockIdx.x] = v;
   if (blockIdx.x == 0) {
-    l1 = tm.sum(l1);
-    if (tm.tid == 0) l1part[tensor] = l1;
+    l1 = bt.sum(l1);
+    if (tid == 0) l1part[tensor] = l1;
   }
+  __syncthreads();
+  // level offsets of the chain: level i (1-based) at chain + cofs(i)
+  auto level = [&](int i) -> double * {  // i = 0: root
+    if (i == 0) return root;
+    double *q = chain;
+    for (int l = 1; l < i; ++l) q += tp.S[n - l];
+    return q;
+  };
+  // the block's fixed indices
+  for (int i = 0; i < tp.lo; ++i) {
+    unsigned k = blockIdx.x;
+    for (int s2 = tp.lo - 1; s2 > i; --s2) k /= D1;
+    k %= D1;
+    tree_fold(level(i), level(i + 1), tb, tb + a.tree_base[n - i], tp.S[n - i - 1], tab + k * D1, (int)k, tid, nt);
+    __syncthreads();
+  }
+  // the lane's index and parent variant
+  const int lane_k = tid % D1, pv = tid / D1;
+  double rk[D1];
+#pragma unroll
+  for (int j = 0; j < D1; ++j) rk[j] = tab[lane_k * D1 + j];
+  double ext = side ? INFINITY : -INFINITY;
+  for (int rho = 0; rho < tp.rounds; ++rho) {
+    // chain indices of the round (q digits, the first most significant);
+    // refold from the first that changed
+    int first = 0;
+    if (rho > 0) {
+      int a0 = rho, a1 = rho - 1;
+      for (int i = tp.q - 1; i >= 0; --i) {
+        if (a0 % D1 != a1 % D1) first = i;
+        a0 /= D1;
+        a1 /= D1;
+      }
+    }
+    for (int i = first; i < tp.q; ++i) {
+      int k = rho;
+      for (int s2 = tp.q - 1; s2 > i; --s2) k /= D1;
+      k %= D1;
+      const int lv = tp.lo + i;
+      tree_fold(level(lv), level(lv + 1), tb, tb + a.tree_base[n - lv], tp.S[n - lv - 1], tab + k * D1, k, tid,
+                nt);
+      __syncthreads();
+    }
+    // expansions into all index combinations of the next e - 1 variables
+    const double *par = level(nchain);
+    double *out = expd;
+    int V = 1;
+    for (int i = 1; i < tp.e; ++i) {
+      const int d = cdim - i + 1;  // variables of the input
+      tree_expand<D>(par, out, tb, tb + a.tree_base[d], tp.S[d], tp.S[d - 1], V, tid, nt);
+      __syncthreads();
+      par = out;
+      out += (int64_t)V * D1 * tp.S[d - 1];
+      V *= D1;
+    }
+    if (tid < tp.lanes) {
+      const double *pp = par + (int64_t)pv * tp.S[M + 1];
+      if (side)
+        tree_lane<D, M, false>(pp, rk, ext);
+      else
+        tree_lane<D, M, true>(pp, rk, ext);
+    }
+    __syncthreads();
+  }
+  const double v = side ? bt.min(ext) : bt.max(ext);
+  if (tid == 0) partial[tensor * tp.nchunk + blockIdx.x] = v;
 }
 
 template <typename T, int D>
-static hipError_t launch_chunk_t(const ConvertArgs &a, const Chunking &ck, size_t lds, double *partial,
-                                 double *l1part, hipStream_t s) {
-  RET_IF(hipFuncSetAttribute((const void *)convert_chunk_t<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+static hipError_t launch_tree_t(const ConvertArgs &a, const TreePlan &tp, size_t lds, double *partial,
+                                double *l1part, hipStream_t s) {
+  constexpr int M = tree_tile_axes(D);
+  RET_IF(hipFuncSetAttribute((const void *)convert_tree_t<D, M, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)lds));
-  const unsigned threads = lds > 40 * 1024 ? 1024 : 256;
-  hipLaunchKernelGGL((convert_chunk_t<D, T>), dim3((unsigned)ck.groups, (unsigned)(a.nboxes * a.h * 2)),
-                     dim3(threads), lds, s, a, ck, partial, l1part);
+  hipLaunchKernelGGL((convert_tree_t<D, M, T>), dim3((unsigned)tp.nchunk, (unsigned)(a.nboxes * a.h * 2)),
+                     dim3((unsigned)tp.threads), lds, s, a, tp, partial, l1part);
   return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t launch_chunk(const ConvertArgs &a, const Chunking &ck, size_t lds, double *partial, double *l1part,
-                               hipStream_t s) {
+static hipError_t launch_tree(const ConvertArgs &a, const TreePlan &tp, size_t lds, double *partial, double *l1part,
+                              hipStream_t s) {
   switch (a.D) {
-    case 1: return launch_chunk_t<T, 1>(a, ck, lds, partial, l1part, s);
-    case 2: return launch_chunk_t<T, 2>(a, ck, lds, partial, l1part, s);
-    case 3: return launch_chunk_t<T, 3>(a, ck, lds, partial, l1part, s);
-    case 4: return launch_chunk_t<T, 4>(a, ck, lds, partial, l1part, s);
-    case 5: return launch_chunk_t<T, 5>(a, ck, lds, partial, l1part, s);
-    case 6: return launch_chunk_t<T, 6>(a, ck, lds, partial, l1part, s);
-    case 7: return launch_chunk_t<T, 7>(a, ck, lds, partial, l1part, s);
-    case 8: return launch_chunk_t<T, 8>(a, ck, lds, partial, l1part, s);
+    case 1: return launch_tree_t<T, 1>(a, tp, lds, partial, l1part, s);
+    case 2: return launch_tree_t<T, 2>(a, tp, lds, partial, l1part, s);
+    case 3: return launch_tree_t<T, 3>(a, tp, lds, partial, l1part, s);
+    case 4: return launch_tree_t<T, 4>(a, tp, lds, partial, l1part, s);
+    case 5: return launch_tree_t<T, 5>(a, tp, lds, partial, l1part, s);
+    case 6: return launch_tree_t<T, 6>(a, tp, lds, partial, l1part, s);
+    case 7: return launch_tree_t<T, 7>(a, tp, lds, partial, l1part, s);
+    case 8: return launch_tree_t<T, 8>(a, tp, lds, partial, l1part, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1136,51 +1341,84 @@ static bool use_small(int64_t C) {
   return C <= kSmallLds && C <= fit;
 }
 
-// Chunking of the staging-free path for tensors beyond one block's LDS:
-// the fewest leading axes whose fixing leaves a trailing tensor of at most
-// kSmallLds coefficients that fits LDS with the stored coefficients and the
-// ratio table. lead = 0 when the path does not apply (D > 8 or too large).
-// Ints of the prefix table for (D, na): offsets plus C(D + na, na - 1) prefixes.
-static int64_t plist_ints(int na, int D) { return (na + 1) + ssize(na - 1, D + 1); }
 
-static Chunking chunking(int n, int D) {
-  Chunking ck{0, 0, 0, 1, 0};
-  if (D < 1 || D > 8) return ck;
-  const int64_t S = ssize(n, D, (int64_t)1 << 31);
-  if (S < 0) return ck;
-  const size_t limit = device_lds_limit();
-  for (int lead = 1; lead < n && lead <= 16; ++lead) {
-    const int64_t cells = ipow(D + 1, n - lead);
-    const size_t bytes =
-        (size_t)(cells + S + (D + 1) * (D + 1) + (plist_ints(n - lead, D) + 1) / 2) * sizeof(double);
-    if (cells <= kSmallLds && bytes <= limit) {
-      ck.lead = lead;
-      ck.cells = cells;
-      ck.nchunk = ipow(D + 1, lead);
-      ck.groups = ck.nchunk;
-      return ck;
+// Ints of the tree table of n variables and degree D.
+static int64_t tree_ints(int n, int D) {
+  int64_t t = 0;
+  for (int d = 2; d <= n; ++d) t += ssize(d - 1, D) + 1 + ssize(d, D);
+  return t;
+}
+
+// LDS of a plan: tables, ratio table, chain levels, the stored coefficients
+// and the expansions (sharing one area when lo >= 1).
+static size_t tree_lds(const TreePlan &tp, int n, int D) {
+  const int D1 = D + 1;
+  int64_t dbl = (tree_ints(n, D) + 1) / 2 + D1 * D1, ex = 0;
+  for (int i = 1; i <= tp.lo + tp.q; ++i) dbl += tp.S[n - i];
+  int64_t V = 1;
+  for (int i = 1; i < tp.e; ++i) {
+    V *= D1;
+    ex += V * tp.S[n - tp.lo - tp.q - i];
+  }
+  return (size_t)(dbl + (tp.lo >= 1 ? std::max<int64_t>(ex, tp.S[n]) : ex + tp.S[n])) * sizeof(double);
+}
+
+// Blocks the tree read-off aims for (some 32 per CU); the partials stay
+// within tensors + kTreeBlocks (D+1).
+constexpr int64_t kTreeBlocks = 8192;
+
+// Plan of the tree read-off: lanes per round (D+1)^e, the count that fills
+// whole waves best (the smaller of equals), then the fewest block-fixed
+// indices giving kTreeBlocks blocks, the rest folded per round. e shrinks
+// until the levels fit LDS. lo < 0 when the path does not apply.
+static TreePlan tree_plan(int n, int D, int64_t tensors) {
+  TreePlan none;
+  if (D < 1 || D > 8 || n < 2 || n > kMaxInputs) return none;
+  const int M = tree_tile_axes(D), D1 = D + 1, lead = n - M;
+  if (lead < 1 || ssize(n, D, (int64_t)1 << 24) < 0) return none;
+  TreePlan tp;
+  for (int d = 0; d <= n; ++d) tp.S[d] = (int)ssize(d, D);
+  // e: the most busy lanes per CU (blocks resident by LDS, at most 32
+  // waves), counting blocks beyond four waves at half (their barriers wait
+  // on more waves), the smaller e of equals
+  TreePlan best;
+  double best_score = 0.0;
+  for (int e = 1; e <= lead; ++e) {
+    const int64_t lanes = ipow(D1, e);
+    if (lanes > 1024) break;
+    TreePlan c = tp;
+    c.e = e;
+    c.lanes = (int)lanes;
+    c.threads = (int)std::max<int64_t>(64, (lanes + 63) / 64 * 64);
+    c.lo = 0;
+    while (c.lo < lead - e && tensors * ipow(D1, c.lo) < kTreeBlocks) ++c.lo;
+    c.q = lead - e - c.lo;
+    c.rounds = (int)ipow(D1, c.q);
+    c.nchunk = ipow(D1, c.lo);
+    const size_t lds = tree_lds(c, n, D);
+    if (lds > device_lds_limit()) continue;
+    const int64_t wpb = c.threads / 64;
+    const int64_t blocks = std::min<int64_t>(device_lds_limit() / lds, 32 / wpb);
+    const double score = (double)(blocks * lanes) * (wpb > 4 ? 0.5 : 1.0);
+    if (blocks >= 1 && score > best_score * 1.05) {
+      best_score = score;
+      best = c;
     }
   }
-  return ck;
+  return best;
 }
 
-static size_t chunk_lds(const Chunking &ck, int64_t S, int D, int plist_len) {
-  return (size_t)(ck.cells + S + (D + 1) * (D + 1) + (plist_len + 1) / 2) * sizeof(double);
-}
-
-int convert_tile_m(int n, int D) {
+bool convert_tree(int n, int D) {
   const int64_t C = tsize(n, D);
-  if (C < 0 || use_small(C)) return -1;
-  const Chunking ck = chunking(n, D);
-  return ck.lead > 0 ? ck.lead : -1;
+  if (C < 0 || use_small(C)) return false;
+  return tree_plan(n, D, 1).lo >= 0;
 }
 
 size_t convert_scratch_bytes(int n, int D, int h, int64_t nboxes) {
   const int64_t C = ipow(D + 1, n);
   if (use_small(C)) return 0;
-  const Chunking ck = chunking(n, D);
-  if (ck.lead > 0)
-    return align256((size_t)nboxes * h * 2 * ck.nchunk * sizeof(double)) +
+  if (tree_plan(n, D, nboxes * h * 2).lo >= 0)
+    return align256(((size_t)nboxes * h * 2 + kTreeBlocks * (D + 1)) * sizeof(double)) +
            align256((size_t)nboxes * h * 2 * sizeof(double));
   const Split sp = make_split(n, D);
   return align256((size_t)nboxes * h * 2 * C * sizeof(double)) +
@@ -1212,28 +1450,27 @@ hipError_t launch_convert(const ConvertArgs &a, hipStream_t s) {
     return hipGetLastError();
   }
   const int64_t tensors = a.nboxes * a.h * 2;
-  Chunking ck = chunking(a.n, a.D);
-  if (ck.lead > 0) {  // the workspace holds no staging for this shape
-    if (!a.sl_off) return hipErrorInvalidValue;
-    // several chunks per block, keeping some 8k blocks in flight
-    ck.groups = std::min<int64_t>(ck.nchunk, std::max<int64_t>(1, (8192 + tensors - 1) / tensors));
-    ck.per = (ck.nchunk + ck.groups - 1) / ck.groups;
-    ck.groups = (ck.nchunk + ck.per - 1) / ck.per;
+  const TreePlan tp = tree_plan(a.n, a.D, tensors);
+  if (tp.lo >= 0) {  // the workspace holds no staging for this shape
+    if (!a.tree || a.tree_len != (int)tree_ints(a.n, a.D) || tensors * tp.nchunk > tensors + kTreeBlocks * (a.D + 1))
+      return hipErrorInvalidValue;
+    const size_t lds = tree_lds(tp, a.n, a.D);
     ConvertArgs b = a;
-    b.gextra = (int)a.S;
+    b.gextra = 0;  // one ratio per variable and step: within the per-axis count
     double *partial = a.scratch;
-    double *l1part = reinterpret_cast<double *>(reinterpret_cast<char *>(partial) +
-                                                align256((size_t)a.nboxes * a.h * 2 * ck.nchunk * sizeof(double)));
+    double *l1part = reinterpret_cast<double *>(
+        reinterpret_cast<char *>(partial) +
+        align256(((size_t)a.nboxes * a.h * 2 + kTreeBlocks * (a.D + 1)) * sizeof(double)));
     {
       ProfScope ps(kProfConvertChunk, s, (double)tensors * a.S * (a.fp64 ? 8 : 4),
                    (double)tensors * a.n * a.C * (a.D + 2));
-      RET_IF(a.fp64 ? launch_chunk<double>(b, ck, chunk_lds(ck, a.S, a.D, a.plist_len), partial, l1part, s)
-                    : launch_chunk<float>(b, ck, chunk_lds(ck, a.S, a.D, a.plist_len), partial, l1part, s));
+      RET_IF(a.fp64 ? launch_tree<double>(b, tp, lds, partial, l1part, s)
+                    : launch_tree<float>(b, tp, lds, partial, l1part, s));
     }
     Split fsp{};
-    fsp.nchunk = ck.groups;
+    fsp.nchunk = tp.nchunk;
     fsp.Co = 1;
-    ProfScope ps(kProfConvertFinal, s, (double)tensors * ck.nchunk * 8);
+    ProfScope ps(kProfConvertFinal, s, (double)tensors * tp.nchunk * 8);
     hipLaunchKernelGGL(convert_final_kernel, dim3((unsigned)((a.nboxes * a.h + 3) / 4)), dim3(kBlock), 0, s, b, fsp,
                        (const double *)partial, (const double *)l1part);
     return hipGetLastError();

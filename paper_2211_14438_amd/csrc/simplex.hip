@@ -67,68 +67,50 @@ SimplexTables::~SimplexTables() {
     (void)hipFree(kv.second.diag);
   }
   for (auto &kv : prefixes) (void)hipFree(kv.second.first);
-  for (auto &kv : slices) {
-    (void)hipFree(kv.second.cell);
-    (void)hipFree(kv.second.off);
-    (void)hipFree(kv.second.rank);
-    (void)hipFree(kv.second.dig);
-  }
+  for (auto &kv : trees) (void)hipFree(kv.second.buf);
 }
 
-hipError_t slice_table(SimplexTables &t, int D, int m, const SliceTable **out) {
+hipError_t tree_table(SimplexTables &t, int D, const TreeTable **out) {
   std::lock_guard<std::mutex> g(t.mu);
-  const auto key = std::make_pair(D, m);
-  auto it = t.slices.find(key);
-  if (it != t.slices.end()) {
+  auto it = t.trees.find(D);
+  if (it != t.trees.end()) {
     *out = &it->second;
     return hipSuccess;
   }
   const int n = t.n;
-  if (D > 15 || m < 0 || m > n || m > 16) return hipErrorInvalidValue;
-  const int64_t S = ssize(n, D, (int64_t)1 << 31);
-  double cc = 1.0;
-  for (int a = m; a < n; ++a) cc *= D + 1;
-  if (S < 0 || cc > 2147483647.0) return hipErrorInvalidValue;
-  const std::vector<uint16_t> e = simplex_exponents(n, D);
-  std::map<int64_t, std::vector<int64_t>> groups;  // dense trailing index -> ranks, in rank order
-  for (int64_t r = 0; r < S; ++r) {
-    int64_t c = 0;
-    for (int a = m; a < n; ++a) c = c * (D + 1) + e[r * n + a];
-    groups[c].push_back(r);
-  }
-  std::vector<int> cells, off(1, 0), rank;
-  std::vector<unsigned long long> dig;
-  for (auto &kv : groups) {
-    cells.push_back((int)kv.first);
-    for (int64_t r : kv.second) {
-      unsigned long long pk = 0;
-      for (int i = 0; i < m; ++i) pk |= (unsigned long long)e[r * n + i] << (4 * i);
-      rank.push_back((int)r);
-      dig.push_back(pk);
+  if (D < 1 || D > 15 || n < 2 || n > kMaxTreeDims) return hipErrorInvalidValue;
+  if (ssize(n, D, (int64_t)1 << 24) < 0) return hipErrorInvalidValue;
+  TreeTable tt;
+  std::vector<int> buf;
+  for (int d = 2; d <= n; ++d) {
+    const std::vector<uint16_t> ec = simplex_exponents(d - 1, D);
+    const int64_t Sc = ssize(d - 1, D);
+    tt.base[d] = (int)buf.size();
+    const size_t off0 = buf.size();
+    buf.resize(buf.size() + (size_t)Sc + 1);
+    std::vector<uint16_t> tup((size_t)d);
+    for (int64_t r = 0; r < Sc; ++r) {
+      buf[off0 + (size_t)r] = (int)buf.size();
+      int deg = 0;
+      for (int a = 0; a < d - 1; ++a) {
+        tup[(size_t)a + 1] = ec[(size_t)(r * (d - 1) + a)];
+        deg += tup[(size_t)a + 1];
+      }
+      for (int j = 0; j + deg <= D; ++j) {
+        tup[0] = (uint16_t)j;
+        buf.push_back((int)simplex_rank(d, tup.data()));
+      }
     }
-    off.push_back((int)rank.size());
+    buf[off0 + (size_t)Sc] = (int)buf.size();
   }
-  SliceTable st;
-  st.ncell = (int)cells.size();
-  hipError_t err = hipMalloc(&st.cell, std::max<size_t>(cells.size(), 1) * sizeof(int));
-  if (err == hipSuccess) err = hipMalloc(&st.off, off.size() * sizeof(int));
-  if (err == hipSuccess) err = hipMalloc(&st.rank, std::max<size_t>(rank.size(), 1) * sizeof(int));
-  if (err == hipSuccess) err = hipMalloc(&st.dig, std::max<size_t>(dig.size(), 1) * sizeof(unsigned long long));
-  if (err == hipSuccess && !cells.empty())
-    err = hipMemcpy(st.cell, cells.data(), cells.size() * sizeof(int), hipMemcpyHostToDevice);
-  if (err == hipSuccess) err = hipMemcpy(st.off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice);
-  if (err == hipSuccess && !rank.empty())
-    err = hipMemcpy(st.rank, rank.data(), rank.size() * sizeof(int), hipMemcpyHostToDevice);
-  if (err == hipSuccess && !dig.empty())
-    err = hipMemcpy(st.dig, dig.data(), dig.size() * sizeof(unsigned long long), hipMemcpyHostToDevice);
+  tt.len = (int)buf.size();
+  hipError_t err = hipMalloc(&tt.buf, buf.size() * sizeof(int));
+  if (err == hipSuccess) err = hipMemcpy(tt.buf, buf.data(), buf.size() * sizeof(int), hipMemcpyHostToDevice);
   if (err != hipSuccess) {
-    (void)hipFree(st.cell);
-    (void)hipFree(st.off);
-    (void)hipFree(st.rank);
-    (void)hipFree(st.dig);
+    (void)hipFree(tt.buf);
     return err;
   }
-  auto res = t.slices.emplace(key, st);
+  auto res = t.trees.emplace(D, tt);
   *out = &res.first->second;
   return hipSuccess;
 }

@@ -30,6 +30,8 @@
 
 namespace bern {
 
+constexpr int kMaxTreeDims = 16;  // variables of a tree table (the input count limit)
+
 // C(n + D, n), or -1 above `cap`.
 int64_t ssize(int n, int D, int64_t cap = (int64_t)1 << 40);
 
@@ -50,17 +52,17 @@ struct ProdTable {
   int64_t npairs = 0;
 };
 
-// Stored coefficients of degree D grouped by their trailing n-m exponents.
-// The ncell groups are the cells of the (D+1)^(n-m) tensor of the trailing
-// axes that hold any: group g has dense index cell[g] there, and entries
-// off[g] .. off[g+1] give each coefficient's rank and its m leading
-// exponents packed four bits each, axis i at bits 4i. For D <= 15, m <= 16.
-struct SliceTable {
-  int ncell = 0;
-  int *cell = nullptr;
-  int *off = nullptr;
-  int *rank = nullptr;
-  unsigned long long *dig = nullptr;
+// Child tables of the tree read-off (fixing the leading variable at a
+// Bernstein index, one variable at a time). For every d = 2 .. n: the
+// (d-1)-variable layout of degree D is the child of the d-variable one (the
+// leading variable dropped); for each child coefficient r and j = 0 .. D-|r|
+// the table lists the parent rank of (j, r). One int buffer; dimension d
+// starts at base[d]: off[S(d-1) + 1] (absolute starts in the buffer), then
+// the parent ranks, S(d) of them (each parent coefficient exactly once).
+struct TreeTable {
+  int base[kMaxTreeDims + 2] = {};
+  int len = 0;
+  int *buf = nullptr;
 };
 
 struct SimplexTables {
@@ -68,7 +70,7 @@ struct SimplexTables {
   std::mutex mu;
   std::map<int, int *> dense;                      // D -> [S(n,D)] index in the (D+1)^n tensor
   std::map<std::tuple<int, int, int>, ProdTable> prod;  // (da, db, sym)
-  std::map<std::pair<int, int>, SliceTable> slices;     // (D, m leading axes)
+  std::map<int, TreeTable> trees;  // D
   std::map<std::pair<int, int>, std::pair<int *, int>> prefixes;  // (D, na) -> (table, ints)
   ~SimplexTables();
 };
@@ -80,7 +82,7 @@ constexpr int64_t kMaxPairs = (int64_t)1 << 25;
 // table would exceed its limit, or the allocation / copy error.
 hipError_t dense_index_table(SimplexTables &t, int D, const int **out);
 hipError_t product_table(SimplexTables &t, int da, int db, bool sym, const ProdTable **out);
-hipError_t slice_table(SimplexTables &t, int D, int m, const SliceTable **out);
+hipError_t tree_table(SimplexTables &t, int D, const TreeTable **out);
 
 // Valid fibre prefixes of the per-axis basis change of a tensor whose
 // nonzero coefficients all have exponent sum <= D: converting axis a (axes
