@@ -177,9 +177,10 @@ bern_status bern_bounds(const bern_net *net, const bern_opts *opts, int64_t n_bo
  * tuning parameters, parameter q having bern_tune_variants(q) variants
  * (0 = the built-in choice): 0 rows per block and inputs per step of the
  * affine kernel for layers wider than 8 neurons, 1 the same for layers of at
- * most 4 neurons, 2 threads of the block-per-neuron conversion, 3 whether
- * tensors of at most 1024 coefficients are converted one wave or one block
- * per neuron. The choice is stored in the network handle and used by every
+ * most 4 neurons, 2 threads of the dense block-per-neuron read-off, 3 the
+ * per-neuron read-off: the tree of folds (0), the dense tensor with one wave
+ * per neuron up to 1024 coefficients (1), or one block per neuron (2). The
+ * choice is stored in the network handle and used by every
  * later call on it; every variant computes the same bounds up to the order
  * of floating-point sums.
  *   bern_tune_get / bern_tune_set -- read / write `choice` (host,

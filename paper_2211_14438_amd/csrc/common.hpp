@@ -129,10 +129,11 @@ struct Tune {
   int gemm_wide = 0;    // layers wider than 8: 0 16 rows x 2 inputs/step, 1 16x4, 2 8x2, 3 8x4
   int gemm_narrow = 0;  // layers of <= 4 neurons: 0 4 rows x 8 inputs/step, 1 4x4, 2 4x16
   int conv_block = 0;   // threads of the block-per-neuron conversion: 0 by LDS use, 1 256, 2 512, 3 1024
-  int conv_wave = 0;    // tensors <= 1024 coefficients: 0 one wave per neuron, 1 one block per neuron
+  int conv_wave = 0;    // per-neuron read-off: 0 tree, 1 dense (one wave per neuron up to 1024
+                        // coefficients, else one block), 2 dense, one block per neuron
 };
 constexpr int kTuneParams = 4;
-constexpr int kTuneVariants[kTuneParams] = {4, 3, 4, 2};
+constexpr int kTuneVariants[kTuneParams] = {4, 3, 4, 3};
 
 // ----------------------------------------------------------- kernel launchers
 // Defined in the .hip files; every launcher enqueues on `stream` and returns a

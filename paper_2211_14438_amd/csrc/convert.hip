@@ -1149,10 +1149,234 @@ static hipError_t launch_tree(const ConvertArgs &a, const TreePlan &tp, size_t l
   }
 }
 
+// The tree read-off for one neuron's pair of tensors (all tensors within
+// one block's reach): a block per neuron holds both trees, upper and lower,
+// and lanes 0 .. lanes-1 take the upper tensor's tiles, the next lanes the
+// lower's. The first pass gives the extrema; a neuron that takes a fitted
+// rule gets its affine fits (closed form, wave_fit) and a second pass for
+// the remainder ranges b_K - l(K/D).
+constexpr int ntree_tile_axes(int D) { return D == 1 ? 1 : D == 2 ? 3 : D <= 4 ? 2 : 1; }
+
+struct NTreePlan {
+  int e = 0, q = 0;  // variables expanded per round, folded per round (chain)
+  int lanes = 0, threads = 0, rounds = 0;
+  int area = 0;      // doubles of one tensor's tree: stored coefficients, chain, expansions
+  int S[kMaxInputs + 1] = {};
+};
+
+// The lane's tile of one pass: pass 1 (kFit false) folds the extrema of the
+// Bernstein coefficients into mn / mx, pass 2 those of the remainders
+// x - l, with l = c + sum over the tile's variables a of g[a][digit].
+template <int D, int M, bool kFit>
+__device__ __forceinline__ void ntree_lane(const double *par, const double (&rk)[D + 1], double c,
+                                           const double (&g)[M][D + 1], double &mn, double &mx) {
+  using LT = LaneTabs<D, M>;
+  constexpr int N = cpow(D + 1, M);
+  double x[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) x[q] = 0.0;
+  Unroll<0, LaneTab<D, M>::NC>::run([&](auto C) {
+    constexpr int cc = C.value;
+    double s = 0.0;
+    Unroll<0, LT::t.deg[cc] + 1>::run([&](auto J) { s = fma(rk[J.value], par[LT::t.pr[cc][J.value]], s); });
+    x[LT::t.dl[cc]] = s;
+  });
+  block_to_bern<D, M>(x);
+  Unroll<0, N>::run([&](auto Q) {
+    double v = x[Q.value];
+    if constexpr (kFit) {
+      double l = c;
+      Unroll<0, M>::run([&](auto A) { l += g[A.value][(Q.value / cpow(D + 1, M - 1 - A.value)) % (D + 1)]; });
+      v -= l;
+    }
+    mn = fmin(mn, v);
+    mx = fmax(mx, v);
+  });
+}
+
+// One pass over both trees (areas t0 and t0 + area). bl: the two fits (pass 2).
+template <int D, int M, bool kFit>
+__device__ void ntree_pass(const ConvertArgs &a, const NTreePlan &tp, const int *tb, const double *tab, double *t0,
+                           const double *bl, double &mn, double &mx) {
+  constexpr int D1 = D + 1;
+  const int tid = threadIdx.x, nt = blockDim.x, n = a.n;
+  const int side = tid / tp.lanes, tl = tid - side * tp.lanes;  // side 0: upper, 1: lower
+  const bool lane = side < 2;
+  const int lane_k = tl % D1, pv = tl / D1;
+  double rk[D1];
+#pragma unroll
+  for (int j = 0; j < D1; ++j) rk[j] = lane ? tab[lane_k * D1 + j] : 0.0;
+  // the fit's tile part and the lane's own digits' part
+  double g[M][D1];
+  double cl = 0.0;
+  const double *beta = bl + (lane ? side : 0) * (kMaxInputs + 1);
+  if (kFit) {
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+      for (int t = 0; t < D1; ++t) g[m][t] = beta[1 + n - M + m] * ((double)t / D - 0.5);
+    cl = beta[0];
+    int rem = tl;
+    for (int i = tp.e - 1; i >= 0; --i) {  // variable q + i has digit rem % D1
+      cl = fma(beta[1 + tp.q + i], (double)(rem % D1) / D - 0.5, cl);
+      rem /= D1;
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+      for (int t = 0; t < D1; ++t) g[m][t] = 0.0;
+  }
+  // chain levels of a tree: level i (1 .. q) after the stored coefficients
+  auto level = [&](double *root, int i) -> double * {
+    double *q = root;
+    for (int l = 0; l < i; ++l) q += tp.S[n - l];
+    return q;
+  };
+  int chain_size = 0;
+  for (int i = 0; i <= tp.q; ++i) chain_size += tp.S[n - i];
+  for (int rho = 0; rho < tp.rounds; ++rho) {
+    int first = 0;
+    if (rho > 0) {
+      int a0 = rho, a1 = rho - 1;
+      for (int i = tp.q - 1; i >= 0; --i) {
+        if (a0 % D1 != a1 % D1) first = i;
+        a0 /= D1;
+        a1 /= D1;
+      }
+    }
+    double cr = cl;  // the round's chain digits' part of the fit
+    if (kFit) {
+      int rem = rho;
+      for (int i = tp.q - 1; i >= 0; --i) {
+        cr = fma(beta[1 + i], (double)(rem % D1) / D - 0.5, cr);
+        rem /= D1;
+      }
+    }
+    for (int i = first; i < tp.q; ++i) {
+      int k = rho;
+      for (int s2 = tp.q - 1; s2 > i; --s2) k /= D1;
+      k %= D1;
+      for (int sd = 0; sd < 2; ++sd) {
+        double *root = t0 + sd * tp.area;
+        tree_fold(level(root, i), level(root, i + 1), tb, tb + a.tree_base[n - i], tp.S[n - i - 1], tab + k * D1, k,
+                  tid, nt);
+      }
+      __syncthreads();
+    }
+    const int cdim = n - tp.q;
+    // expansions: step i reads the chain's last level (i = 1) or the
+    // previous step's output
+    {
+      int Vx = 1;
+      int64_t in_off = -1, out_off = chain_size;
+      for (int i = 1; i < tp.e; ++i) {
+        const int d = cdim - i + 1;
+        for (int sd = 0; sd < 2; ++sd) {
+          double *root = t0 + sd * tp.area;
+          const double *in = in_off < 0 ? level(root, tp.q) : root + in_off;
+          tree_expand<D>(in, root + out_off, tb, tb + a.tree_base[d], tp.S[d], tp.S[d - 1], Vx, tid, nt);
+        }
+        __syncthreads();
+        in_off = out_off;
+        out_off += (int64_t)Vx * D1 * tp.S[d - 1];
+        Vx *= D1;
+      }
+      if (lane) {
+        double *root = t0 + side * tp.area;
+        const double *par = (in_off < 0 ? level(root, tp.q) : root + in_off) + (int64_t)pv * tp.S[M + 1];
+        ntree_lane<D, M, kFit>(par, rk, cr, g, mn, mx);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int D, int M, typename T>
+__global__ void __launch_bounds__(1024) convert_ntree_t(ConvertArgs a, NTreePlan tp) {
+  extern __shared__ double lds[];
+  __shared__ double red[16];
+  constexpr int D1 = D + 1;
+  constexpr Ratio<D> R{};
+  const int tid = threadIdx.x, nt = blockDim.x, n = a.n, S = (int)a.S;
+  const BlockTeam bt{tid, nt, red};
+  int *tb = reinterpret_cast<int *>(lds);
+  for (int i = tid; i < a.tree_len; i += nt) tb[i] = a.tree[i];
+  double *tab = lds + (a.tree_len + 1) / 2;
+  double *bl = tab + D1 * D1;  // fits: upper, then lower (kMaxInputs + 1 each)
+  double *t0 = bl + 2 * (kMaxInputs + 1);
+  if (tid == 0) {
+#pragma unroll
+    for (int i = 0; i < D1 * D1; ++i) tab[i] = R.v[i / D1][i % D1];
+  }
+  const int64_t item = blockIdx.x;
+  const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
+  const int j = (int)(item % a.h);
+  const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + (int64_t)j * 2 * a.S;
+  double epsU = 0.0, epsL = 0.0;
+  if (!a.fp64) pre_radii(a, box, j, a.pre, tid, nt, [&](double v) { return bt.sum(v); }, epsU, epsL);
+  double su = 0.0, sl = 0.0;
+  for (int i = tid; i < S; i += nt) {
+    const double u = (double)p[i], w = (double)p[S + i];
+    t0[i] = u;
+    t0[tp.area + i] = w;
+    su += fabs(u);
+    sl += fabs(w);
+  }
+  const double l1U = bt.sum(su), l1L = bt.sum(sl);  // (the reductions' barriers publish the roots)
+  __syncthreads();
+  const int side = tid / tp.lanes;
+  double mn = INFINITY, mx = -INFINITY;
+  ntree_pass<D, M, false>(a, tp, tb, tab, t0, bl, mn, mx);
+  const double mxU = bt.max(side == 0 ? mx : -INFINITY), mnL = bt.min(side == 1 ? mn : INFINITY);
+  const double lo = side_lo(a, mnL, l1L, epsL), hi = side_hi(a, mxU, l1U, epsU);
+  const bool want = wants_fit(a, box, j);
+  const bool fitted = want && (a.fits || (lo < 0.0 && hi > 0.0));
+  double fx[4] = {0.0, 0.0, 0.0, 0.0};  // rmaxU, rminU, rmaxL, rminL
+  if (fitted) {
+    if (tid < 64) {
+      wave_fit(p, a.didx, S, n, D, tid, bl);
+      wave_fit(p + S, a.didx, S, n, D, tid, bl + kMaxInputs + 1);
+    }
+    __syncthreads();
+    double rmn = INFINITY, rmx = -INFINITY;
+    ntree_pass<D, M, true>(a, tp, tb, tab, t0, bl, rmn, rmx);
+    fx[0] = bt.max(side == 0 ? rmx : -INFINITY);
+    fx[1] = bt.min(side == 0 ? rmn : INFINITY);
+    fx[2] = bt.max(side == 1 ? rmx : -INFINITY);
+    fx[3] = bt.min(side == 1 ? rmn : INFINITY);
+    if (tid == 0) {
+      NeuronRec &rec = a.recs[box * a.h + j];
+      for (int q = 0; q <= n; ++q) {
+        rec.fitU[q] = bl[q];
+        rec.fitL[q] = bl[kMaxInputs + 1 + q];
+      }
+    }
+  }
+  if (tid == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted);
+}
+
+static NTreePlan ntree_plan(int n, int D);
+static size_t ntree_lds(const NTreePlan &tp, int n, int D);
+
 template <typename T, int D>
 static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
+  if (a.tune.conv_wave == 0 && a.tree) {
+    const NTreePlan tp = ntree_plan(a.n, D);
+    if (tp.e >= 1) {
+      constexpr int M = ntree_tile_axes(D);
+      const size_t lds = ntree_lds(tp, a.n, D);
+      RET_IF(hipFuncSetAttribute((const void *)convert_ntree_t<D, M, T>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4),
+                   (double)a.nboxes * a.h * 2 * a.n * a.C * (a.D + 2));
+      hipLaunchKernelGGL((convert_ntree_t<D, M, T>), dim3((unsigned)(a.nboxes * a.h)), dim3((unsigned)tp.threads),
+                         lds, s, a, tp);
+      return hipGetLastError();
+    }
+  }
   const size_t plb = (size_t)((a.plist_len + 1) / 2) * sizeof(double);
-  if (a.C <= kWaveC && a.tune.conv_wave == 0) {
+  if (a.C <= kWaveC && a.tune.conv_wave <= 1) {
     const size_t lds = (size_t)(kBlock / 64) * (a.C + kMaxInputs + 1) * sizeof(double) + plb;
     RET_IF(hipFuncSetAttribute((const void *)convert_wave_t<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
@@ -1406,6 +1630,42 @@ static TreePlan tree_plan(int n, int D, int64_t tensors) {
     }
   }
   return best;
+}
+
+// Plan of the neuron tree: e the most variables with 2 (D+1)^e lanes in one
+// block, the rest folded per round; e shrinks until both trees fit LDS.
+static NTreePlan ntree_plan(int n, int D) {
+  NTreePlan none;
+  if (D < 1 || D > 8 || n > kMaxInputs) return none;
+  const int M = ntree_tile_axes(D), D1 = D + 1, lead = n - M;
+  if (lead < 1) return none;
+  NTreePlan tp;
+  for (int d = 0; d <= n; ++d) tp.S[d] = (int)ssize(d, D);
+  int e = 0;
+  while (e < lead && 2 * ipow(D1, e + 1) <= 1024) ++e;
+  for (; e >= 1; --e) {
+    tp.e = e;
+    tp.q = lead - e;
+    tp.lanes = (int)ipow(D1, e);
+    tp.threads = std::max(64, (2 * tp.lanes + 63) / 64 * 64);
+    tp.rounds = (int)ipow(D1, tp.q);
+    int64_t area = 0;
+    for (int i = 0; i <= tp.q; ++i) area += tp.S[n - i];
+    int64_t V = 1;
+    for (int i = 1; i < e; ++i) {
+      V *= D1;
+      area += V * tp.S[n - tp.q - i];
+    }
+    tp.area = (int)area;
+    const size_t lds = (size_t)((tree_ints(n, D) + 1) / 2 + D1 * D1 + 2 * (kMaxInputs + 1) + 2 * area) * sizeof(double);
+    if (lds <= device_lds_limit()) return tp;
+  }
+  return none;
+}
+
+static size_t ntree_lds(const NTreePlan &tp, int n, int D) {
+  return (size_t)((tree_ints(n, D) + 1) / 2 + (D + 1) * (D + 1) + 2 * (kMaxInputs + 1) + 2 * (int64_t)tp.area) *
+         sizeof(double);
 }
 
 bool convert_tree(int n, int D) {
