@@ -427,9 +427,10 @@ __global__ void __launch_bounds__(kBlock) compose_sq2_kernel(ComposeArgs a) {
   const NeuronRec &r = a.recs[box * a.h + j];
   if (r.kind != 2) return;
   load_nu(a, in_tensor<T>(a, box, j, s), nu_of(a, &r, s), nu);
-  const int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // block x owns outputs [x kBlock, (x + 1) kBlock), whatever its threads
+  const int64_t K0 = (int64_t)blockIdx.x * kBlock, K1 = min(K0 + kBlock, a.Cout);
   double rsum = 0.0, l1sum = 0.0;
-  if (K < a.Cout) {
+  for (int64_t K = K0 + threadIdx.x; K < K1; K += blockDim.x) {
     double v = 0.0;
     if (K < a.Sm[2]) {
       double acc = 0.0;
@@ -473,9 +474,9 @@ __global__ void __launch_bounds__(kBlock) compose_hz_kernel(ComposeArgs a, int m
   const int64_t Ct = last ? a.Cout : Sq;
   const int *off = a.hz_off[m];
   const int2 *pairs = a.hz_pairs[m];
-  const int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t K0 = (int64_t)blockIdx.x * kBlock, K1 = min(K0 + kBlock, Ct);
   double rsum = 0.0, l1sum = 0.0;
-  if (K < Ct) {
+  for (int64_t K = K0 + threadIdx.x; K < K1; K += blockDim.x) {
     double v = 0.0;
     if (K < Sq) {
       const int e = off[K + 1];
@@ -612,6 +613,10 @@ static bool sq_handles(int n, int Din, int Dout) {
 
 int64_t compose_nbx(int64_t Cout) { return std::max<int64_t>(1, (Cout + kBlock - 1) / kBlock); }
 
+// Threads of the per-item composition blocks: one wave (most items return
+// at once by kind; the few that work loop over their kBlock outputs).
+constexpr unsigned kComposeThreads = 64;
+
 template <typename T, int D, int NI>
 static hipError_t launch_sq(const ComposeArgs &a, hipStream_t s) {
   const size_t lds = sq_lds(a.n, D);
@@ -658,7 +663,7 @@ static hipError_t compose_all(const ComposeArgs &a, hipStream_t s) {
   {
     dim3 grid(1, (unsigned)(a.h * a.nbounds), (unsigned)a.nboxes);
     ProfScope ps(kProfComposeSimple, s, 0.0);
-    hipLaunchKernelGGL(compose_scatter_kernel<T>, grid, dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(compose_scatter_kernel<T>, grid, dim3(kComposeThreads), 0, s, a);
     RET_IF(hipGetLastError());
   }
   const size_t lds = (size_t)a.Cin * sizeof(double);
@@ -668,7 +673,7 @@ static hipError_t compose_all(const ComposeArgs &a, hipStream_t s) {
                                (int)lds));
     dim3 grid(gx, (unsigned)(a.h * a.nbounds), (unsigned)a.nboxes);
     ProfScope ps(kProfComposeSquare, s, 0.0);
-    hipLaunchKernelGGL(compose_sq2_kernel<T>, grid, dim3(kBlock), lds, s, a);
+    hipLaunchKernelGGL(compose_sq2_kernel<T>, grid, dim3(kComposeThreads), lds, s, a);
     RET_IF(hipGetLastError());
   }
   if (a.Lmax >= 3) {
@@ -678,7 +683,7 @@ static hipError_t compose_all(const ComposeArgs &a, hipStream_t s) {
       if (!a.hz_off[m]) return hipErrorInvalidValue;
       dim3 grid(gx, (unsigned)(a.h * a.nbounds), (unsigned)a.nboxes);
       ProfScope ps(kProfComposeHorner, s, 0.0);
-      hipLaunchKernelGGL(compose_hz_kernel<T>, grid, dim3(kBlock), lds, s, a, m);
+      hipLaunchKernelGGL(compose_hz_kernel<T>, grid, dim3(kComposeThreads), lds, s, a, m);
       RET_IF(hipGetLastError());
     }
   }

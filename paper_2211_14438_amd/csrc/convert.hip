@@ -191,6 +191,38 @@ __device__ void pre_radii(const ConvertArgs &a, int64_t box, int j, const void *
   epsL = (sL + gg + rL) * kPadSafety;
 }
 
+// The same radii with the five sums reduced at once by a team.
+template <class Team>
+__device__ void pre_radii_team(const ConvertArgs &a, int64_t box, int j, const Team &tm, double &epsU,
+                               double &epsL) {
+  if (a.layer == 0) {
+    pre_radii(a, box, j, a.pre, tm.tid, tm.nt, [](double v) { return v; }, epsU, epsL);
+    return;
+  }
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // sU, sL, g, rU, rL
+  for (int k = tm.tid; k < a.hin; k += tm.nt) {
+    const double wk = a.W[(int64_t)j * a.hin + k];
+    const NeuronRec &P = a.prev[box * a.hin + k];
+    if (wk >= 0.0) {
+      v[0] += wk * P.padU;
+      v[1] += wk * P.padL;
+    } else {
+      v[0] -= wk * P.padL;
+      v[1] -= wk * P.padU;
+    }
+    v[2] += fabs(wk) * (P.pl1U + P.pl1L);
+  }
+  const double *rp = a.rpart + box * a.rpart_slot + (int64_t)j * 2 * a.cblocks;
+  for (int64_t cb = tm.tid; cb < a.cblocks; cb += tm.nt) {
+    v[3] += rp[cb];
+    v[4] += rp[a.cblocks + cb];
+  }
+  tm.reduce(v, OpAdd());
+  const double gg = gamma64(2.0 * a.hin + 6) * (v[2] + fabs(a.b[j]));
+  epsU = (v[0] + gg + v[3]) * kPadSafety;
+  epsL = (v[1] + gg + v[4]) * kPadSafety;
+}
+
 // Bounds from the Bernstein extrema: in FP32 mode widened by the FP64
 // basis-change rounding (gamma * sum|a|, the table entries lie in [0,1]) and
 // the radii, then rounded outward. Called by all `nt` cooperating threads.
@@ -471,22 +503,87 @@ __device__ __forceinline__ void to_bern(double (&x)[D + 1]) {
   }
 }
 
+// Reduction of R <= kRows rows of 64 lane values in a wave's LDS scratch
+// (row r at scr[64 r + lane]), in a fixed order: eight partials per row,
+// then the row. Row r's result lands at scr[kRows * 72 + r].
+constexpr int kRows = 8;
+constexpr int kRowScratch = kRows * 73;  // doubles of a wave's scratch
+
+template <class Op>
+__device__ __forceinline__ void wave_rows(double *scr, int R, int lane, Op op) {
+  wave_sync();
+  double *part = scr + kRows * 64;
+  if (lane < R * 8) {
+    const double *src = scr + (lane >> 3) * 64 + (lane & 7) * 8;
+    double s = src[0];
+#pragma unroll
+    for (int i = 1; i < 8; ++i) s = op(s, src[i]);
+    part[lane] = s;
+  }
+  wave_sync();
+  if (lane < R) {
+    const double *src = part + lane * 8;
+    double s = src[0];
+#pragma unroll
+    for (int i = 1; i < 8; ++i) s = op(s, src[i]);
+    scr[kRows * 72 + lane] = s;
+  }
+  wave_sync();
+}
+
 struct WaveTeam {
   int tid;
+  double *scr = nullptr;  // kRowScratch doubles of LDS for reduce(); null: shuffles
   static constexpr int nt = 64;
   __device__ void sync() const { wave_sync(); }
   __device__ double sum(double v) const { return wave_reduce(v, OpAdd()); }
   __device__ double min(double v) const { return wave_reduce(v, OpMin()); }
   __device__ double max(double v) const { return wave_reduce(v, OpMax()); }
+  // K values at once, each over the wave
+  template <int K, class Op>
+  __device__ void reduce(double (&v)[K], Op op) const {
+    static_assert(K <= kRows, "rows");
+    if (!scr) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) v[k] = wave_reduce(v[k], op);
+      return;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) scr[k * 64 + tid] = v[k];
+    wave_rows(scr, K, tid, op);
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = scr[kRows * 72 + k];
+    wave_sync();
+  }
 };
 
 struct BlockTeam {
   int tid, nt;
-  double *red;
+  double *red;  // 16 doubles; reduce() needs 17 K
   __device__ void sync() const { __syncthreads(); }
   __device__ double sum(double v) const { return block_reduce(v, OpAdd(), red); }
   __device__ double min(double v) const { return block_reduce(v, OpMin(), red); }
   __device__ double max(double v) const { return block_reduce(v, OpMax(), red); }
+  template <int K, class Op>
+  __device__ void reduce(double (&v)[K], Op op) const {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = wave_reduce(v[k], op);
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+      for (int k = 0; k < K; ++k) red[k * 16 + wid] = v[k];
+    __syncthreads();
+    if (threadIdx.x < K) {
+      double r = red[threadIdx.x * 16];
+      for (int w = 1; w < nw; ++w) r = op(r, red[threadIdx.x * 16 + w]);
+      red[16 * K + threadIdx.x] = r;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = red[16 * K + k];
+    __syncthreads();
+  }
 };
 
 // One axis pass: every fibre of D+1 coefficients at stride `st` converted in
@@ -661,8 +758,36 @@ __device__ void team_convert(double *t, const T *p, const int *didx, int C, int 
 // independent of D. One wave computes it (didx gives each J's digits, axis
 // n-1 fastest) into bl[0 .. n] in LDS; the caller's barrier publishes it.
 template <typename T>
-__device__ void wave_fit(const T *p, const int *didx, int S, int n, int D, int lane, double *bl) {
+__device__ void wave_fit(const T *p, const int *didx, int S, int n, int D, int lane, double *bl,
+                         double *scr = nullptr) {
   const unsigned D1 = (unsigned)D + 1u;
+  if (scr) {  // the n + 1 sums as rows of the wave's scratch, kRows at a time
+    for (int r0 = 0; r0 <= n; r0 += kRows) {
+      const int R = min(kRows, n + 1 - r0);
+      for (int r = 0; r < R; ++r) scr[r * 64 + lane] = 0.0;
+      for (int i = lane; i < S; i += 64) {
+        unsigned d = (unsigned)didx[i];
+        double den = 1.0;
+        for (int ax = 0; ax < n; ++ax) {
+          den *= (double)(d % D1 + 1u);
+          d /= D1;
+        }
+        const double w = (double)p[i] / den;
+        d = (unsigned)didx[i];
+        for (int ax = n - 1; ax >= 0; --ax) {  // row 1 + ax - r0
+          const double k = (double)(d % D1);
+          d /= D1;
+          const int r = 1 + ax - r0;
+          if (r >= 0 && r < R) scr[r * 64 + lane] += 6.0 * w * k / (k + 2.0);
+        }
+        if (r0 == 0) scr[lane] += w;
+      }
+      wave_rows(scr, R, lane, OpAdd());
+      if (lane < R) bl[r0 + lane] = scr[kRows * 72 + lane];
+      wave_sync();
+    }
+    return;
+  }
   for (int base = 0; base < S; base += 64) {
     const int i = base + lane;
     double w = 0.0;
@@ -1195,11 +1320,11 @@ __device__ __forceinline__ void ntree_lane(const double *par, const double (&rk)
 }
 
 // One pass over both trees (areas t0 and t0 + area). bl: the two fits (pass 2).
-template <int D, int M, bool kFit>
-__device__ void ntree_pass(const ConvertArgs &a, const NTreePlan &tp, const int *tb, const double *tab, double *t0,
-                           const double *bl, double &mn, double &mx) {
+template <int D, int M, bool kFit, class Team>
+__device__ void ntree_pass(const ConvertArgs &a, const NTreePlan &tp, const Team &tm, const int *tb,
+                           const double *tab, double *t0, const double *bl, double &mn, double &mx) {
   constexpr int D1 = D + 1;
-  const int tid = threadIdx.x, nt = blockDim.x, n = a.n;
+  const int tid = tm.tid, nt = tm.nt, n = a.n;
   const int side = tid / tp.lanes, tl = tid - side * tp.lanes;  // side 0: upper, 1: lower
   const bool lane = side < 2;
   const int lane_k = tl % D1, pv = tl / D1;
@@ -1262,7 +1387,7 @@ __device__ void ntree_pass(const ConvertArgs &a, const NTreePlan &tp, const int 
         tree_fold(level(root, i), level(root, i + 1), tb, tb + a.tree_base[n - i], tp.S[n - i - 1], tab + k * D1, k,
                   tid, nt);
       }
-      __syncthreads();
+      tm.sync();
     }
     const int cdim = n - tp.q;
     // expansions: step i reads the chain's last level (i = 1) or the
@@ -1277,7 +1402,7 @@ __device__ void ntree_pass(const ConvertArgs &a, const NTreePlan &tp, const int 
           const double *in = in_off < 0 ? level(root, tp.q) : root + in_off;
           tree_expand<D>(in, root + out_off, tb, tb + a.tree_base[d], tp.S[d], tp.S[d - 1], Vx, tid, nt);
         }
-        __syncthreads();
+        tm.sync();
         in_off = out_off;
         out_off += (int64_t)Vx * D1 * tp.S[d - 1];
         Vx *= D1;
@@ -1288,63 +1413,73 @@ __device__ void ntree_pass(const ConvertArgs &a, const NTreePlan &tp, const int 
         ntree_lane<D, M, kFit>(par, rk, cr, g, mn, mx);
       }
     }
-    __syncthreads();
+    tm.sync();
   }
 }
 
-template <int D, int M, typename T>
-__global__ void __launch_bounds__(1024) convert_ntree_t(ConvertArgs a, NTreePlan tp) {
-  extern __shared__ double lds[];
-  __shared__ double red[16];
-  constexpr int D1 = D + 1;
-  constexpr Ratio<D> R{};
-  const int tid = threadIdx.x, nt = blockDim.x, n = a.n, S = (int)a.S;
-  const BlockTeam bt{tid, nt, red};
-  int *tb = reinterpret_cast<int *>(lds);
-  for (int i = tid; i < a.tree_len; i += nt) tb[i] = a.tree[i];
-  double *tab = lds + (a.tree_len + 1) / 2;
-  double *bl = tab + D1 * D1;  // fits: upper, then lower (kMaxInputs + 1 each)
+__device__ inline double *tm_scratch(const WaveTeam &tm) { return tm.scr; }
+__device__ inline double *tm_scratch(const BlockTeam &) { return nullptr; }
+
+// One neuron's read-off by a team: a block (kWave false) or one wave of a
+// block of four, each wave with its own neuron and LDS slice (kWave true).
+template <int D, int M, typename T, bool kWave, class Team>
+__device__ void ntree_neuron(const ConvertArgs &a, const NTreePlan &tp, const Team &tm, const int *tb,
+                             const double *tab, double *bl, int64_t item) {
+  const int tid = tm.tid, nt = tm.nt, n = a.n, S = (int)a.S;
   double *t0 = bl + 2 * (kMaxInputs + 1);
-  if (tid == 0) {
-#pragma unroll
-    for (int i = 0; i < D1 * D1; ++i) tab[i] = R.v[i / D1][i % D1];
-  }
-  const int64_t item = blockIdx.x;
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
   const int j = (int)(item % a.h);
   const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + (int64_t)j * 2 * a.S;
-  double epsU = 0.0, epsL = 0.0;
-  if (!a.fp64) pre_radii(a, box, j, a.pre, tid, nt, [&](double v) { return bt.sum(v); }, epsU, epsL);
-  double su = 0.0, sl = 0.0;
-  for (int i = tid; i < S; i += nt) {
-    const double u = (double)p[i], w = (double)p[S + i];
-    t0[i] = u;
-    t0[tp.area + i] = w;
-    su += fabs(u);
-    sl += fabs(w);
+  // the stored coefficients' loads first, the radii's behind them
+  double u[2] = {0.0, 0.0}, w[2] = {0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int i = tid + q * nt;
+    if (i < S) {
+      u[q] = (double)p[i];
+      w[q] = (double)p[S + i];
+    }
   }
-  const double l1U = bt.sum(su), l1L = bt.sum(sl);  // (the reductions' barriers publish the roots)
-  __syncthreads();
+  double epsU = 0.0, epsL = 0.0;
+  if (!a.fp64) pre_radii_team(a, box, j, tm, epsU, epsL);
+  double l1[2] = {0.0, 0.0};
+  for (int i = tid; i < S; i += nt) {
+    const int q = (i - tid) / nt;
+    const double uu = q < 2 ? u[q] : (double)p[i], ww = q < 2 ? w[q] : (double)p[S + i];
+    t0[i] = uu;
+    t0[tp.area + i] = ww;
+    l1[0] += fabs(uu);
+    l1[1] += fabs(ww);
+  }
+  tm.reduce(l1, OpAdd());
+  const double l1U = l1[0], l1L = l1[1];
+  tm.sync();
   const int side = tid / tp.lanes;
   double mn = INFINITY, mx = -INFINITY;
-  ntree_pass<D, M, false>(a, tp, tb, tab, t0, bl, mn, mx);
-  const double mxU = bt.max(side == 0 ? mx : -INFINITY), mnL = bt.min(side == 1 ? mn : INFINITY);
+  ntree_pass<D, M, false>(a, tp, tm, tb, tab, t0, bl, mn, mx);
+  double ex[2] = {side == 0 ? mx : -INFINITY, side == 1 ? -mn : -INFINITY};  // maxima of max U, -min L
+  tm.reduce(ex, OpMax());
+  const double mxU = ex[0], mnL = -ex[1];
   const double lo = side_lo(a, mnL, l1L, epsL), hi = side_hi(a, mxU, l1U, epsU);
   const bool want = wants_fit(a, box, j);
   const bool fitted = want && (a.fits || (lo < 0.0 && hi > 0.0));
   double fx[4] = {0.0, 0.0, 0.0, 0.0};  // rmaxU, rminU, rmaxL, rminL
   if (fitted) {
-    if (tid < 64) {
-      wave_fit(p, a.didx, S, n, D, tid, bl);
-      wave_fit(p + S, a.didx, S, n, D, tid, bl + kMaxInputs + 1);
+    if (kWave || threadIdx.x < 64) {
+      double *scr = kWave ? tm_scratch(tm) : nullptr;
+      wave_fit(p, a.didx, S, n, D, (int)(threadIdx.x & 63), bl, scr);
+      wave_fit(p + S, a.didx, S, n, D, (int)(threadIdx.x & 63), bl + kMaxInputs + 1, scr);
     }
-    __syncthreads();
+    tm.sync();
     double rmn = INFINITY, rmx = -INFINITY;
-    ntree_pass<D, M, true>(a, tp, tb, tab, t0, bl, rmn, rmx);
-    fx[0] = bt.max(side == 0 ? rmx : -INFINITY);
-    fx[1] = bt.min(side == 0 ? rmn : INFINITY);
-    fx[2] = bt.max(side == 1 ? rmx : -INFINITY);
-    fx[3] = bt.min(side == 1 ? rmn : INFINITY);
+    ntree_pass<D, M, true>(a, tp, tm, tb, tab, t0, bl, rmn, rmx);
+    double r4[4] = {side == 0 ? rmx : -INFINITY, side == 0 ? -rmn : -INFINITY, side == 1 ? rmx : -INFINITY,
+                    side == 1 ? -rmn : -INFINITY};
+    tm.reduce(r4, OpMax());
+    fx[0] = r4[0];
+    fx[1] = -r4[1];
+    fx[2] = r4[2];
+    fx[3] = -r4[3];
     if (tid == 0) {
       NeuronRec &rec = a.recs[box * a.h + j];
       for (int q = 0; q <= n; ++q) {
@@ -1356,22 +1491,63 @@ __global__ void __launch_bounds__(1024) convert_ntree_t(ConvertArgs a, NTreePlan
   if (tid == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted);
 }
 
+template <int D, int M, typename T, bool kWave>
+__global__ void __launch_bounds__(kWave ? 256 : 1024) convert_ntree_t(ConvertArgs a, NTreePlan tp) {
+  extern __shared__ double lds[];
+  __shared__ double red[17 * 4];
+  constexpr int D1 = D + 1;
+  constexpr Ratio<D> R{};
+  int *tb = reinterpret_cast<int *>(lds);
+  for (int i = threadIdx.x; i < a.tree_len; i += blockDim.x) tb[i] = a.tree[i];
+  double *tab = lds + (a.tree_len + 1) / 2;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < D1 * D1; ++i) tab[i] = R.v[i / D1][i % D1];
+  }
+  __syncthreads();
+  double *slices = tab + D1 * D1;  // per team: fits (upper, lower), then the two trees
+  if (kWave) {
+    const int wv = threadIdx.x >> 6;
+    const int64_t item = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
+    if (item >= a.nboxes * a.h) return;
+    double *slice = slices + (int64_t)wv * (kRowScratch + 2 * (kMaxInputs + 1) + 2 * tp.area);
+    const WaveTeam tm{(int)(threadIdx.x & 63), slice};
+    ntree_neuron<D, M, T, true>(a, tp, tm, tb, tab, slice + kRowScratch, item);
+  } else {
+    const BlockTeam tm{(int)threadIdx.x, (int)blockDim.x, red};
+    ntree_neuron<D, M, T, false>(a, tp, tm, tb, tab, slices, blockIdx.x);
+  }
+}
+
 static NTreePlan ntree_plan(int n, int D);
-static size_t ntree_lds(const NTreePlan &tp, int n, int D);
+static size_t ntree_lds(const NTreePlan &tp, int n, int D, int teams);
 
 template <typename T, int D>
 static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
-  if (a.tune.conv_wave == 0 && a.tree) {
+  // degree 1 tensors are read off densely (a wave per neuron does it in a
+  // few steps); the tree needs D >= 2 to pay for its levels
+  if (a.tune.conv_wave == 0 && a.tree && D >= 2) {
     const NTreePlan tp = ntree_plan(a.n, D);
     if (tp.e >= 1) {
       constexpr int M = ntree_tile_axes(D);
-      const size_t lds = ntree_lds(tp, a.n, D);
-      RET_IF(hipFuncSetAttribute((const void *)convert_ntree_t<D, M, T>,
+      const int64_t items = a.nboxes * a.h;
+      ProfScope ps(kProfConvertSmall, s, (double)items * 2 * a.S * (a.fp64 ? 8 : 4),
+                   (double)items * 2 * a.n * a.C * (a.D + 2));
+      if (tp.threads == 64) {  // a wave per neuron, four per block
+        const size_t lds = ntree_lds(tp, a.n, D, 4);
+        if (lds <= device_lds_limit()) {
+          RET_IF(hipFuncSetAttribute((const void *)convert_ntree_t<D, M, T, true>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+          hipLaunchKernelGGL((convert_ntree_t<D, M, T, true>), dim3((unsigned)((items + 3) / 4)), dim3(256), lds, s,
+                             a, tp);
+          return hipGetLastError();
+        }
+      }
+      const size_t lds = ntree_lds(tp, a.n, D, 1);
+      RET_IF(hipFuncSetAttribute((const void *)convert_ntree_t<D, M, T, false>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-      ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4),
-                   (double)a.nboxes * a.h * 2 * a.n * a.C * (a.D + 2));
-      hipLaunchKernelGGL((convert_ntree_t<D, M, T>), dim3((unsigned)(a.nboxes * a.h)), dim3((unsigned)tp.threads),
-                         lds, s, a, tp);
+      hipLaunchKernelGGL((convert_ntree_t<D, M, T, false>), dim3((unsigned)items), dim3((unsigned)tp.threads), lds, s,
+                         a, tp);
       return hipGetLastError();
     }
   }
@@ -1663,8 +1839,10 @@ static NTreePlan ntree_plan(int n, int D) {
   return none;
 }
 
-static size_t ntree_lds(const NTreePlan &tp, int n, int D) {
-  return (size_t)((tree_ints(n, D) + 1) / 2 + (D + 1) * (D + 1) + 2 * (kMaxInputs + 1) + 2 * (int64_t)tp.area) *
+static size_t ntree_lds(const NTreePlan &tp, int n, int D, int teams) {
+  // wave teams (teams > 1) also hold their reduction scratch
+  return (size_t)((tree_ints(n, D) + 1) / 2 + (D + 1) * (D + 1) +
+                  (int64_t)teams * ((teams > 1 ? kRowScratch : 0) + 2 * (kMaxInputs + 1) + 2 * (int64_t)tp.area)) *
          sizeof(double);
 }
 
