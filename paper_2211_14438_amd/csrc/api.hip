@@ -424,13 +424,16 @@ __global__ void poison_kernel(int64_t nb, const int *flag, int nh, int o, double
   }
 }
 
-// Largest per-neuron post degree of every box of the wave.
+// Largest per-neuron post degree of every box of the wave: one wave per box,
+// its lanes over the neurons.
 __global__ void box_degree_kernel(int64_t nb, int h, const NeuronRec *recs, int *deg) {
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t b = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (b >= nb) return;
+  const int lane = threadIdx.x & 63;
   int d = 0;
-  for (int j = 0; j < h; ++j) d = max(d, recs[b * h + j].deg);
-  deg[b] = d;
+  for (int j = lane; j < h; j += 64) d = max(d, recs[b * h + j].deg);
+  for (int off = 32; off > 0; off >>= 1) d = max(d, __shfl_xor(d, off, 64));
+  if (lane == 0) deg[b] = d;
 }
 
 // Index tables of one layer's degree class: the dense positions for the
@@ -648,7 +651,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
     } else {
       {
         ProfScope ps(kProfMisc, s, 0.0);
-        hipLaunchKernelGGL(box_degree_kernel, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, B, h,
+        hipLaunchKernelGGL(box_degree_kernel, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, s, B, h,
                            (const NeuronRec *)recs, degs);
       }
       BERN_HIP_TRY(hipGetLastError());

@@ -557,9 +557,12 @@ struct WaveTeam {
   }
 };
 
+// Shared doubles a BlockTeam's `red` needs for reduce<K> with K <= kRows.
+constexpr int kRedDoubles = 17 * kRows;
+
 struct BlockTeam {
   int tid, nt;
-  double *red;  // 16 doubles; reduce() needs 17 K
+  double *red;  // 16 doubles; reduce<K>() needs 17 K (kRedDoubles)
   __device__ void sync() const { __syncthreads(); }
   __device__ double sum(double v) const { return block_reduce(v, OpAdd(), red); }
   __device__ double min(double v) const { return block_reduce(v, OpMin(), red); }
@@ -585,6 +588,9 @@ struct BlockTeam {
     __syncthreads();
   }
 };
+
+__device__ inline double *tm_scratch(const WaveTeam &tm) { return tm.scr; }
+__device__ inline double *tm_scratch(const BlockTeam &) { return nullptr; }
 
 // One axis pass: every fibre of D+1 coefficients at stride `st` converted in
 // registers. Fibre f has base (f / st) st (D+1) + f % st = f + (f / st) st D;
@@ -716,32 +722,6 @@ __device__ inline const int *stage_prefixes(const ConvertArgs &a, int *dst) {
   return dst;
 }
 
-// Stored power coefficients p[0, S) -> dense Bernstein tensor t[0, C)
-// (C = (D+1)^n; didx gives each stored coefficient's dense position, the
-// others are zero). Returns the team-wide sum of |p| and the extrema.
-// With a fit `bl` (LDS) also the remainder range of the fit, ext[0] = max and
-// ext[1] = min, and axis 0 is then left unconverted in t.
-template <int D, typename T, class Team>
-__device__ void team_convert(double *t, const T *p, const int *didx, int C, int S, int n, const Team &tm,
-                             double &l1, double &vmin, double &vmax, const int *pl, const double *bl = nullptr,
-                             double *ext = nullptr) {
-  for (int i = tm.tid; i < C; i += tm.nt) t[i] = 0.0;
-  tm.sync();
-  double s = 0.0, mn = INFINITY, mx = -INFINITY, rmn = INFINITY, rmx = -INFINITY;
-  for (int i = tm.tid; i < S; i += tm.nt) {
-    const double x = (double)p[i];
-    t[didx[i]] = x;
-    s += fabs(x);
-  }
-  team_axes<D>(t, C, 1, n, tm, true, mn, mx, pl, bl, &rmn, &rmx);
-  l1 = tm.sum(s);
-  vmin = tm.min(mn);
-  vmax = tm.max(mx);
-  if (bl) {
-    ext[0] = tm.max(rmx);
-    ext[1] = tm.min(rmn);
-  }
-}
 
 // Least-squares affine fit l(x) = beta_0 + sum_a beta_a (x_a - 1/2) of the
 // control net {(K/D, b_K)} (same quantities as lds_affine_fit), from the
@@ -813,6 +793,18 @@ __device__ void wave_fit(const T *p, const int *didx, int S, int n, int D, int l
   }
 }
 
+// team_convert without its reductions: the lane's own extrema (and, with a
+// fit, remainder extrema) are folded into mn, mx (rmn, rmx).
+template <int D, typename T, class Team>
+__device__ void team_convert_lanes(double *t, const T *p, const int *didx, int C, int S, int n, const Team &tm,
+                                   const int *pl, const double *bl, double &mn, double &mx, double &rmn,
+                                   double &rmx) {
+  for (int i = tm.tid; i < C; i += tm.nt) t[i] = 0.0;
+  tm.sync();
+  for (int i = tm.tid; i < S; i += tm.nt) t[didx[i]] = (double)p[i];
+  team_axes<D>(t, C, 1, n, tm, true, mn, mx, pl, bl, &rmn, &rmx);
+}
+
 // Remainder range of the fit bl over the converted tensor in LDS (rmax =
 // max_K b_K - l(K/D), rmin = min): one pass over the fibres along axis 0.
 template <int D, class Team>
@@ -836,8 +828,10 @@ __device__ void team_remainder(const double *t, int C, int n, const Team &tm, co
       lo = fmin(lo, r);
     }
   }
-  rmax = tm.max(hi);
-  rmin = tm.min(lo);
+  double e[2] = {hi, -lo};
+  tm.reduce(e, OpMax());
+  rmax = e[0];
+  rmin = -e[1];
 }
 
 // Bound of one side from its Bernstein extremum (FP32 mode: widened by the
@@ -880,50 +874,79 @@ __device__ void readoff_pair(const ConvertArgs &a, const Team &tm, bool fitter, 
                              const int *pl, int64_t box, int j) {
   const int C = (int)a.C, S = (int)a.S;
   const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + (int64_t)j * 2 * a.S;
+  double *scr = tm_scratch(tm);
   double epsU = 0.0, epsL = 0.0;
-  if (!a.fp64) pre_radii(a, box, j, a.pre, tm.tid, tm.nt, [&](double v) { return tm.sum(v); }, epsU, epsL);
+  if (!a.fp64) pre_radii_team(a, box, j, tm, epsU, epsL);
   const bool want = wants_fit(a, box, j);
   NeuronRec *rec = want ? &a.recs[box * a.h + j] : nullptr;
   double fx[4] = {0.0, 0.0, 0.0, 0.0};  // rmaxU, rminU, rmaxL, rminL
-  double l1L, l1U, mn, mx, dummy;
-  double hib = INFINITY;
-  if (want && !a.fits) {
-    double hub = 0.0, l1u = 0.0;
-    for (int i = tm.tid; i < S; i += tm.nt) {
-      const double v = (double)p[i];
-      l1u += fabs(v);
-      hub += i == 0 ? v : fmax(v, 0.0);
-    }
-    hub = tm.sum(hub);
-    l1u = tm.sum(l1u);
-    hib = side_hi(a, hub + 1e-12 * l1u, l1u, epsU);
+  // l1 norms of both tensors, and an upper bound of the upper tensor's
+  // largest Bernstein coefficient: its constant plus its positive
+  // coefficients (the ratio table lies in [0,1])
+  double v3[3] = {0.0, 0.0, 0.0};
+  for (int i = tm.tid; i < S; i += tm.nt) {
+    const double u = (double)p[i], w = (double)p[S + i];
+    v3[0] += i == 0 ? u : fmax(u, 0.0);
+    v3[1] += fabs(u);
+    v3[2] += fabs(w);
   }
-  team_convert<D>(t, p + S, a.didx, C, S, a.n, tm, l1L, mn, dummy, pl);
+  tm.reduce(v3, OpAdd());
+  const double l1U = v3[1], l1L = v3[2];
+  const double hib = want && !a.fits ? side_hi(a, v3[0] + 1e-12 * l1U, l1U, epsU) : INFINITY;
+  // lower tensor first; fitted while resident if the neuron can still take
+  // a fitted rule (lower bound negative, hib positive)
+  double mn = INFINITY, mx = -INFINITY, rmn = INFINITY, rmx = -INFINITY;
+  team_convert_lanes<D>(t, p + S, a.didx, C, S, a.n, tm, pl, nullptr, mn, mx, rmn, rmx);
+  {
+    double e[1] = {-mn};
+    tm.reduce(e, OpMax());
+    mn = -e[0];
+  }
   const double lo = side_lo(a, mn, l1L, epsL);
   const bool lower_fitted = want && (a.fits || (lo < 0.0 && hib > 0.0));
   if (lower_fitted) {
-    if (fitter) wave_fit(p + S, a.didx, S, a.n, D, lane, bl);
+    if (fitter) wave_fit(p + S, a.didx, S, a.n, D, lane, bl, scr);
     tm.sync();
     team_remainder<D>(t, C, a.n, tm, bl, fx[2], fx[3]);
     if (tm.tid == 0)
       for (int q = 0; q <= a.n; ++q) rec->fitL[q] = bl[q];
     tm.sync();
-    if (fitter) wave_fit(p, a.didx, S, a.n, D, lane, bl);
+    if (fitter) wave_fit(p, a.didx, S, a.n, D, lane, bl, scr);
   }
   tm.sync();
-  team_convert<D>(t, p, a.didx, C, S, a.n, tm, l1U, dummy, mx, pl, lower_fitted ? bl : nullptr, fx);
+  // upper tensor, with the remainder range of its fit in the last pass
+  mn = INFINITY;
+  mx = -INFINITY;
+  rmn = INFINITY;
+  rmx = -INFINITY;
+  team_convert_lanes<D>(t, p, a.didx, C, S, a.n, tm, pl, lower_fitted ? bl : nullptr, mn, mx, rmn, rmx);
+  {
+    double e[3] = {mx, rmx, -rmn};
+    tm.reduce(e, OpMax());
+    mx = e[0];
+    if (lower_fitted) {
+      fx[0] = e[1];
+      fx[1] = -e[2];
+    }
+  }
   const double hi = side_hi(a, mx, l1U, epsU);
   const bool fitted = want && (a.fits || (lo < 0.0 && hi > 0.0));
-  if (fitted && !lower_fitted) {  // not expected: the filter above is an upper bound of hi
-    double u1, u2, u3;
-    if (fitter) wave_fit(p, a.didx, S, a.n, D, lane, bl);
+  if (fitted && !lower_fitted) {  // not expected: hib bounds hi from above
+    if (fitter) wave_fit(p, a.didx, S, a.n, D, lane, bl, scr);
     tm.sync();
-    team_convert<D>(t, p, a.didx, C, S, a.n, tm, u1, u2, u3, pl, bl, fx);
+    double m1 = INFINITY, m2 = -INFINITY, r1 = INFINITY, r2 = -INFINITY;
+    team_convert_lanes<D>(t, p, a.didx, C, S, a.n, tm, pl, bl, m1, m2, r1, r2);
+    double e[2] = {r2, -r1};
+    tm.reduce(e, OpMax());
+    fx[0] = e[0];
+    fx[1] = -e[1];
     if (tm.tid == 0)
       for (int q = 0; q <= a.n; ++q) rec->fitU[q] = bl[q];
     tm.sync();
-    team_convert<D>(t, p + S, a.didx, C, S, a.n, tm, u1, u2, u3, pl);
-    if (fitter) wave_fit(p + S, a.didx, S, a.n, D, lane, bl);
+    m1 = INFINITY;
+    m2 = -INFINITY;
+    team_convert_lanes<D>(t, p + S, a.didx, C, S, a.n, tm, pl, nullptr, m1, m2, r1, r2);
+    if (fitter) wave_fit(p + S, a.didx, S, a.n, D, lane, bl, scr);
     tm.sync();
     team_remainder<D>(t, C, a.n, tm, bl, fx[2], fx[3]);
     if (tm.tid == 0)
@@ -943,11 +966,12 @@ __global__ void __launch_bounds__(kBlock, 6) convert_wave_t(ConvertArgs a) {
   const int wv = threadIdx.x >> 6;
   const int C = (int)a.C;
   const int *pl = stage_prefixes(a, reinterpret_cast<int *>(lds));
-  double *tw = lds + (a.plist_len + 1) / 2 + (int64_t)wv * (C + kMaxInputs + 1);
+  double *tw = lds + (a.plist_len + 1) / 2 + (int64_t)wv * (kRowScratch + C + kMaxInputs + 1);
   const int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + wv;
   if (item >= a.nboxes * a.h) return;
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
-  readoff_pair<D, T>(a, tm, true, tm.tid, tw, tw + C, pl, box, (int)(item % a.h));
+  const WaveTeam tmw{tm.tid, tw};
+  readoff_pair<D, T>(a, tmw, true, tm.tid, tw + kRowScratch, tw + kRowScratch + C, pl, box, (int)(item % a.h));
 }
 
 // One block per (box, neuron) for tensors up to kSmallLds coefficients, one
@@ -955,7 +979,7 @@ __global__ void __launch_bounds__(kBlock, 6) convert_wave_t(ConvertArgs a) {
 template <int D, typename T>
 __global__ void __launch_bounds__(1024) convert_block_t(ConvertArgs a) {
   extern __shared__ double lds[];
-  __shared__ double red[16];
+  __shared__ double red[kRedDoubles];
   const BlockTeam tm{(int)threadIdx.x, (int)blockDim.x, red};
   const int *pl = stage_prefixes(a, reinterpret_cast<int *>(lds));
   double *t = lds + (a.plist_len + 1) / 2;
@@ -1417,9 +1441,6 @@ __device__ void ntree_pass(const ConvertArgs &a, const NTreePlan &tp, const Team
   }
 }
 
-__device__ inline double *tm_scratch(const WaveTeam &tm) { return tm.scr; }
-__device__ inline double *tm_scratch(const BlockTeam &) { return nullptr; }
-
 // One neuron's read-off by a team: a block (kWave false) or one wave of a
 // block of four, each wave with its own neuron and LDS slice (kWave true).
 template <int D, int M, typename T, bool kWave, class Team>
@@ -1494,7 +1515,7 @@ __device__ void ntree_neuron(const ConvertArgs &a, const NTreePlan &tp, const Te
 template <int D, int M, typename T, bool kWave>
 __global__ void __launch_bounds__(kWave ? 256 : 1024) convert_ntree_t(ConvertArgs a, NTreePlan tp) {
   extern __shared__ double lds[];
-  __shared__ double red[17 * 4];
+  __shared__ double red[kRedDoubles];
   constexpr int D1 = D + 1;
   constexpr Ratio<D> R{};
   int *tb = reinterpret_cast<int *>(lds);
@@ -1553,7 +1574,7 @@ static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
   }
   const size_t plb = (size_t)((a.plist_len + 1) / 2) * sizeof(double);
   if (a.C <= kWaveC && a.tune.conv_wave <= 1) {
-    const size_t lds = (size_t)(kBlock / 64) * (a.C + kMaxInputs + 1) * sizeof(double) + plb;
+    const size_t lds = (size_t)(kBlock / 64) * (kRowScratch + a.C + kMaxInputs + 1) * sizeof(double) + plb;
     RET_IF(hipFuncSetAttribute((const void *)convert_wave_t<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
     ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4),
