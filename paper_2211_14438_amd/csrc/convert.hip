@@ -875,14 +875,10 @@ __device__ void readoff_pair(const ConvertArgs &a, const Team &tm, bool fitter, 
   const int C = (int)a.C, S = (int)a.S;
   const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + (int64_t)j * 2 * a.S;
   double *scr = tm_scratch(tm);
-  double epsU = 0.0, epsL = 0.0;
-  if (!a.fp64) pre_radii_team(a, box, j, tm, epsU, epsL);
-  const bool want = wants_fit(a, box, j);
-  NeuronRec *rec = want ? &a.recs[box * a.h + j] : nullptr;
-  double fx[4] = {0.0, 0.0, 0.0, 0.0};  // rmaxU, rminU, rmaxL, rminL
   // l1 norms of both tensors, and an upper bound of the upper tensor's
   // largest Bernstein coefficient: its constant plus its positive
-  // coefficients (the ratio table lies in [0,1])
+  // coefficients (the ratio table lies in [0,1]); their loads go out before
+  // the radii's
   double v3[3] = {0.0, 0.0, 0.0};
   for (int i = tm.tid; i < S; i += tm.nt) {
     const double u = (double)p[i], w = (double)p[S + i];
@@ -890,6 +886,11 @@ __device__ void readoff_pair(const ConvertArgs &a, const Team &tm, bool fitter, 
     v3[1] += fabs(u);
     v3[2] += fabs(w);
   }
+  double epsU = 0.0, epsL = 0.0;
+  if (!a.fp64) pre_radii_team(a, box, j, tm, epsU, epsL);
+  const bool want = wants_fit(a, box, j);
+  NeuronRec *rec = want ? &a.recs[box * a.h + j] : nullptr;
+  double fx[4] = {0.0, 0.0, 0.0, 0.0};  // rmaxU, rminU, rmaxL, rminL
   tm.reduce(v3, OpAdd());
   const double l1U = v3[1], l1L = v3[2];
   const double hib = want && !a.fits ? side_hi(a, v3[0] + 1e-12 * l1U, l1U, epsU) : INFINITY;
