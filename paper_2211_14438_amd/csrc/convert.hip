@@ -243,7 +243,8 @@ __device__ void padded_bounds(const ConvertArgs &a, int64_t box, int j, double m
 // rule unless a predictor chooses it later. Fitted neurons' affine fits are
 // already in the record; the others get zeros.
 __device__ void record_neuron(const ConvertArgs &a, int64_t box, int j, double lo, double hi, double epsU,
-                              double epsL, double l1U, double l1L, const double *ext, bool fitted) {
+                              double epsL, double l1U, double l1L, const double *ext, bool fitted,
+                              bool fits_written = false) {
   NeuronRec &r = a.recs[box * a.h + j];
   r.lo = lo;
   r.hi = hi;
@@ -252,7 +253,7 @@ __device__ void record_neuron(const ConvertArgs &a, int64_t box, int j, double l
   r.l1U = l1U;
   r.l1L = l1L;
   r.fitted = fitted ? 1 : 0;
-  if (!fitted) {
+  if (!fitted && !fits_written) {
     for (int q = 0; q <= kMaxInputs; ++q) r.fitU[q] = r.fitL[q] = 0.0;
   }
   r.rmaxU = fitted ? ext[0] : 0.0;
@@ -850,15 +851,27 @@ __device__ inline bool wants_fit(const ConvertArgs &a, int64_t box, int j) {
 }
 
 __device__ inline void write_neuron(const ConvertArgs &a, int64_t box, int j, double lo, double hi, double epsU,
-                                    double epsL, double l1U, double l1L, const double *ext, bool fitted) {
+                                    double epsL, double l1U, double l1L, const double *ext, bool fitted,
+                                    bool fits_written = false) {
   if (a.mode == 1) {
     a.out_lo[box * a.ld_out + a.col0 + j] = lo;
     a.out_hi[box * a.ld_out + a.col0 + j] = hi;
   } else {
     if (a.out_lo) a.out_lo[box * a.ld_out + a.col0 + j] = lo;
     if (a.out_hi) a.out_hi[box * a.ld_out + a.col0 + j] = hi;
-    record_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, ext, fitted);
+    record_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, ext, fitted, fits_written);
   }
+}
+
+// A neuron's fit coefficients (or zeros, fit null) written by the team's
+// lanes, one coefficient each, then made visible to the team (the rule
+// chosen by thread 0 may read them).
+template <class Team>
+__device__ inline void team_write_fit(const ConvertArgs &a, const Team &tm, double *dst, const double *fit) {
+  for (int q = tm.tid; q <= kMaxInputs; q += tm.nt) dst[q] = fit && q <= a.n ? fit[q] : 0.0;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  tm.sync();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 // Both bound tensors of neuron (box, j) by one team with `t` (C doubles) and
@@ -909,9 +922,7 @@ __device__ void readoff_pair(const ConvertArgs &a, const Team &tm, bool fitter, 
     if (fitter) wave_fit(p + S, a.didx, S, a.n, D, lane, bl, scr);
     tm.sync();
     team_remainder<D>(t, C, a.n, tm, bl, fx[2], fx[3]);
-    if (tm.tid == 0)
-      for (int q = 0; q <= a.n; ++q) rec->fitL[q] = bl[q];
-    tm.sync();
+    team_write_fit(a, tm, rec->fitL, bl);
     if (fitter) wave_fit(p, a.didx, S, a.n, D, lane, bl, scr);
   }
   tm.sync();
@@ -941,21 +952,22 @@ __device__ void readoff_pair(const ConvertArgs &a, const Team &tm, bool fitter, 
     tm.reduce(e, OpMax());
     fx[0] = e[0];
     fx[1] = -e[1];
-    if (tm.tid == 0)
-      for (int q = 0; q <= a.n; ++q) rec->fitU[q] = bl[q];
-    tm.sync();
+    team_write_fit(a, tm, rec->fitU, bl);
     m1 = INFINITY;
     m2 = -INFINITY;
     team_convert_lanes<D>(t, p + S, a.didx, C, S, a.n, tm, pl, nullptr, m1, m2, r1, r2);
     if (fitter) wave_fit(p + S, a.didx, S, a.n, D, lane, bl, scr);
     tm.sync();
     team_remainder<D>(t, C, a.n, tm, bl, fx[2], fx[3]);
-    if (tm.tid == 0)
-      for (int q = 0; q <= a.n; ++q) rec->fitL[q] = bl[q];
-  } else if (fitted && tm.tid == 0) {
-    for (int q = 0; q <= a.n; ++q) rec->fitU[q] = bl[q];
+    team_write_fit(a, tm, rec->fitL, bl);
+  } else if (fitted) {
+    team_write_fit(a, tm, rec->fitU, bl);
+  } else if (a.mode == 0) {  // records of neurons without a fit carry zeros
+    NeuronRec &r = a.recs[box * a.h + j];
+    team_write_fit(a, tm, r.fitU, nullptr);
+    team_write_fit(a, tm, r.fitL, nullptr);
   }
-  if (tm.tid == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted);
+  if (tm.tid == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted, true);
 }
 
 // One wave per (box, neuron), one bound tensor at a time in the wave's LDS
@@ -1502,15 +1514,13 @@ __device__ void ntree_neuron(const ConvertArgs &a, const NTreePlan &tp, const Te
     fx[1] = -r4[1];
     fx[2] = r4[2];
     fx[3] = -r4[3];
-    if (tid == 0) {
-      NeuronRec &rec = a.recs[box * a.h + j];
-      for (int q = 0; q <= n; ++q) {
-        rec.fitU[q] = bl[q];
-        rec.fitL[q] = bl[kMaxInputs + 1 + q];
-      }
-    }
   }
-  if (tid == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted);
+  if (a.mode == 0) {  // the fits, or zeros
+    NeuronRec &rec = a.recs[box * a.h + j];
+    team_write_fit(a, tm, rec.fitU, fitted ? bl : nullptr);
+    team_write_fit(a, tm, rec.fitL, fitted ? bl + kMaxInputs + 1 : nullptr);
+  }
+  if (tid == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted, true);
 }
 
 template <int D, int M, typename T, bool kWave>
