@@ -505,29 +505,32 @@ __device__ __forceinline__ void to_bern(double (&x)[D + 1]) {
 }
 
 // Reduction of R <= kRows rows of 64 lane values in a wave's LDS scratch
-// (row r at scr[64 r + lane]), in a fixed order: eight partials per row,
-// then the row. Row r's result lands at scr[kRows * 72 + r].
+// (row r at scr[kRowStride r + lane]; the stride spreads the rows over the
+// banks), in a fixed order: eight partials per row (lane k 8 + q sums the
+// row's elements q, q + 8, ...), then the row. Row r's result lands at
+// scr[kRowResult + r].
 constexpr int kRows = 8;
-constexpr int kRowScratch = kRows * 73;  // doubles of a wave's scratch
+constexpr int kRowStride = 72;
+constexpr int kRowPart = kRows * kRowStride, kRowResult = kRowPart + kRows * 8;
+constexpr int kRowScratch = kRowResult + kRows;  // doubles of a wave's scratch
 
 template <class Op>
 __device__ __forceinline__ void wave_rows(double *scr, int R, int lane, Op op) {
   wave_sync();
-  double *part = scr + kRows * 64;
   if (lane < R * 8) {
-    const double *src = scr + (lane >> 3) * 64 + (lane & 7) * 8;
+    const double *src = scr + (lane >> 3) * kRowStride + (lane & 7);
     double s = src[0];
 #pragma unroll
-    for (int i = 1; i < 8; ++i) s = op(s, src[i]);
-    part[lane] = s;
+    for (int i = 1; i < 8; ++i) s = op(s, src[8 * i]);
+    scr[kRowPart + lane] = s;
   }
   wave_sync();
   if (lane < R) {
-    const double *src = part + lane * 8;
+    const double *src = scr + kRowPart + lane * 8;
     double s = src[0];
 #pragma unroll
     for (int i = 1; i < 8; ++i) s = op(s, src[i]);
-    scr[kRows * 72 + lane] = s;
+    scr[kRowResult + lane] = s;
   }
   wave_sync();
 }
@@ -550,10 +553,10 @@ struct WaveTeam {
       return;
     }
 #pragma unroll
-    for (int k = 0; k < K; ++k) scr[k * 64 + tid] = v[k];
+    for (int k = 0; k < K; ++k) scr[k * kRowStride + tid] = v[k];
     wave_rows(scr, K, tid, op);
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = scr[kRows * 72 + k];
+    for (int k = 0; k < K; ++k) v[k] = scr[kRowResult + k];
     wave_sync();
   }
 };
@@ -738,33 +741,47 @@ __device__ inline const int *stage_prefixes(const ConvertArgs &a, int *dst) {
 //   w_J = a_J / prod_i (j_i + 1),
 // independent of D. One wave computes it (didx gives each J's digits, axis
 // n-1 fastest) into bl[0 .. n] in LDS; the caller's barrier publishes it.
-template <typename T>
-__device__ void wave_fit(const T *p, const int *didx, int S, int n, int D, int lane, double *bl,
-                         double *scr = nullptr) {
-  const unsigned D1 = (unsigned)D + 1u;
+// 1/(j+1) and 6 j/(j+2) for a digit j <= D (selects over constants).
+template <int D>
+__device__ __forceinline__ double fit_inv(unsigned j) {
+  double v = 1.0;
+#pragma unroll
+  for (int q = 1; q <= D; ++q) v = j == (unsigned)q ? 1.0 / (q + 1) : v;
+  return v;
+}
+template <int D>
+__device__ __forceinline__ double fit_slope(unsigned j) {
+  double v = 0.0;
+#pragma unroll
+  for (int q = 1; q <= D; ++q) v = j == (unsigned)q ? 6.0 * q / (q + 2) : v;
+  return v;
+}
+
+template <int D, typename T>
+__device__ void wave_fit(const T *p, const int *didx, int S, int n, int lane, double *bl, double *scr = nullptr) {
+  constexpr unsigned D1 = D + 1;
   if (scr) {  // the n + 1 sums as rows of the wave's scratch, kRows at a time
     for (int r0 = 0; r0 <= n; r0 += kRows) {
       const int R = min(kRows, n + 1 - r0);
-      for (int r = 0; r < R; ++r) scr[r * 64 + lane] = 0.0;
+      for (int r = 0; r < R; ++r) scr[r * kRowStride + lane] = 0.0;
       for (int i = lane; i < S; i += 64) {
         unsigned d = (unsigned)didx[i];
-        double den = 1.0;
+        double w = (double)p[i];
         for (int ax = 0; ax < n; ++ax) {
-          den *= (double)(d % D1 + 1u);
+          w *= fit_inv<D>(d % D1);
           d /= D1;
         }
-        const double w = (double)p[i] / den;
         d = (unsigned)didx[i];
         for (int ax = n - 1; ax >= 0; --ax) {  // row 1 + ax - r0
-          const double k = (double)(d % D1);
+          const unsigned k = d % D1;
           d /= D1;
           const int r = 1 + ax - r0;
-          if (r >= 0 && r < R) scr[r * 64 + lane] += 6.0 * w * k / (k + 2.0);
+          if (r >= 0 && r < R) scr[r * kRowStride + lane] += w * fit_slope<D>(k);
         }
         if (r0 == 0) scr[lane] += w;
       }
       wave_rows(scr, R, lane, OpAdd());
-      if (lane < R) bl[r0 + lane] = scr[kRows * 72 + lane];
+      if (lane < R) bl[r0 + lane] = scr[kRowResult + lane];
       wave_sync();
     }
     return;
@@ -775,19 +792,18 @@ __device__ void wave_fit(const T *p, const int *didx, int S, int n, int D, int l
     unsigned dig = 0u;
     if (i < S) {
       dig = (unsigned)didx[i];
-      double den = 1.0;
+      w = (double)p[i];
       unsigned d = dig;
       for (int ax = 0; ax < n; ++ax) {
-        den *= (double)(d % D1 + 1u);
+        w *= fit_inv<D>(d % D1);
         d /= D1;
       }
-      w = (double)p[i] / den;
     }
     const double b0 = wave_reduce(w, OpAdd());
     for (int ax = n - 1; ax >= 0; --ax) {
-      const double k = (double)(dig % D1);
+      const unsigned k = dig % D1;
       dig /= D1;
-      const double ba = wave_reduce(6.0 * w * k / (k + 2.0), OpAdd());
+      const double ba = wave_reduce(w * fit_slope<D>(k), OpAdd());
       if (lane == 0) bl[1 + ax] = base == 0 ? ba : bl[1 + ax] + ba;
     }
     if (lane == 0) bl[0] = base == 0 ? b0 : bl[0] + b0;
@@ -919,11 +935,11 @@ __device__ void readoff_pair(const ConvertArgs &a, const Team &tm, bool fitter, 
   const double lo = side_lo(a, mn, l1L, epsL);
   const bool lower_fitted = want && (a.fits || (lo < 0.0 && hib > 0.0));
   if (lower_fitted) {
-    if (fitter) wave_fit(p + S, a.didx, S, a.n, D, lane, bl, scr);
+    if (fitter) wave_fit<D>(p + S, a.didx, S, a.n, lane, bl, scr);
     tm.sync();
     team_remainder<D>(t, C, a.n, tm, bl, fx[2], fx[3]);
     team_write_fit(a, tm, rec->fitL, bl);
-    if (fitter) wave_fit(p, a.didx, S, a.n, D, lane, bl, scr);
+    if (fitter) wave_fit<D>(p, a.didx, S, a.n, lane, bl, scr);
   }
   tm.sync();
   // upper tensor, with the remainder range of its fit in the last pass
@@ -944,7 +960,7 @@ __device__ void readoff_pair(const ConvertArgs &a, const Team &tm, bool fitter, 
   const double hi = side_hi(a, mx, l1U, epsU);
   const bool fitted = want && (a.fits || (lo < 0.0 && hi > 0.0));
   if (fitted && !lower_fitted) {  // not expected: hib bounds hi from above
-    if (fitter) wave_fit(p, a.didx, S, a.n, D, lane, bl, scr);
+    if (fitter) wave_fit<D>(p, a.didx, S, a.n, lane, bl, scr);
     tm.sync();
     double m1 = INFINITY, m2 = -INFINITY, r1 = INFINITY, r2 = -INFINITY;
     team_convert_lanes<D>(t, p, a.didx, C, S, a.n, tm, pl, bl, m1, m2, r1, r2);
@@ -956,7 +972,7 @@ __device__ void readoff_pair(const ConvertArgs &a, const Team &tm, bool fitter, 
     m1 = INFINITY;
     m2 = -INFINITY;
     team_convert_lanes<D>(t, p + S, a.didx, C, S, a.n, tm, pl, nullptr, m1, m2, r1, r2);
-    if (fitter) wave_fit(p + S, a.didx, S, a.n, D, lane, bl, scr);
+    if (fitter) wave_fit<D>(p + S, a.didx, S, a.n, lane, bl, scr);
     tm.sync();
     team_remainder<D>(t, C, a.n, tm, bl, fx[2], fx[3]);
     team_write_fit(a, tm, rec->fitL, bl);
@@ -1465,26 +1481,16 @@ __device__ void ntree_neuron(const ConvertArgs &a, const NTreePlan &tp, const Te
   const int j = (int)(item % a.h);
   const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + (int64_t)j * 2 * a.S;
   // the stored coefficients' loads first, the radii's behind them
-  double u[2] = {0.0, 0.0}, w[2] = {0.0, 0.0};
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int i = tid + q * nt;
-    if (i < S) {
-      u[q] = (double)p[i];
-      w[q] = (double)p[S + i];
-    }
-  }
-  double epsU = 0.0, epsL = 0.0;
-  if (!a.fp64) pre_radii_team(a, box, j, tm, epsU, epsL);
   double l1[2] = {0.0, 0.0};
   for (int i = tid; i < S; i += nt) {
-    const int q = (i - tid) / nt;
-    const double uu = q < 2 ? u[q] : (double)p[i], ww = q < 2 ? w[q] : (double)p[S + i];
+    const double uu = (double)p[i], ww = (double)p[S + i];
     t0[i] = uu;
     t0[tp.area + i] = ww;
     l1[0] += fabs(uu);
     l1[1] += fabs(ww);
   }
+  double epsU = 0.0, epsL = 0.0;
+  if (!a.fp64) pre_radii_team(a, box, j, tm, epsU, epsL);
   tm.reduce(l1, OpAdd());
   const double l1U = l1[0], l1L = l1[1];
   tm.sync();
@@ -1501,8 +1507,8 @@ __device__ void ntree_neuron(const ConvertArgs &a, const NTreePlan &tp, const Te
   if (fitted) {
     if (kWave || threadIdx.x < 64) {
       double *scr = kWave ? tm_scratch(tm) : nullptr;
-      wave_fit(p, a.didx, S, n, D, (int)(threadIdx.x & 63), bl, scr);
-      wave_fit(p + S, a.didx, S, n, D, (int)(threadIdx.x & 63), bl + kMaxInputs + 1, scr);
+      wave_fit<D>(p, a.didx, S, n, (int)(threadIdx.x & 63), bl, scr);
+      wave_fit<D>(p + S, a.didx, S, n, (int)(threadIdx.x & 63), bl + kMaxInputs + 1, scr);
     }
     tm.sync();
     double rmn = INFINITY, rmx = -INFINITY;
