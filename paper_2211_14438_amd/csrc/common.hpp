@@ -222,6 +222,8 @@ struct ConvertArgs {
   int tree_len;
   int tree_base[17];
   int gextra;                     // rounding steps beyond the per-axis basis change (set by the launcher)
+  double gconv;                   // gamma(n (D+2) + 4 + gextra): read-off rounding factor (set by the launcher)
+  double gpre;                    // gamma(2 hin + 6): affine-map rounding factor of the radii (set by the launcher)
   // simplex.hpp prefix_table for (D, n), or (D, m) of the split
   // convert_nest(n, D) for tensors beyond LDS; null for degrees without a
   // compile-time kernel

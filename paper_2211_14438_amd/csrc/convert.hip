@@ -186,7 +186,7 @@ __device__ void pre_radii(const ConvertArgs &a, int64_t box, int j, const void *
   g = reduce(g) + fabs(a.b[j]);
   rU = reduce(rU);
   rL = reduce(rL);
-  const double gg = gamma64(2.0 * a.hin + 6) * g;
+  const double gg = a.gpre * g;
   epsU = (sU + gg + rU) * kPadSafety;
   epsL = (sL + gg + rL) * kPadSafety;
 }
@@ -218,7 +218,7 @@ __device__ void pre_radii_team(const ConvertArgs &a, int64_t box, int j, const T
     v[4] += rp[a.cblocks + cb];
   }
   tm.reduce(v, OpAdd());
-  const double gg = gamma64(2.0 * a.hin + 6) * (v[2] + fabs(a.b[j]));
+  const double gg = a.gpre * (v[2] + fabs(a.b[j]));
   epsU = (v[0] + gg + v[3]) * kPadSafety;
   epsL = (v[1] + gg + v[4]) * kPadSafety;
 }
@@ -234,7 +234,7 @@ __device__ void padded_bounds(const ConvertArgs &a, int64_t box, int j, double m
   epsU = epsL = 0.0;
   if (a.fp64) return;
   pre_radii(a, box, j, a.pre, tid, nt, reduce, epsU, epsL);
-  const double g = gamma64((double)a.n * (a.D + 2) + 4 + a.gextra);
+  const double g = a.gconv;
   lo = round_down(mn - g * l1L - epsL);
   hi = round_up(mx + g * l1U + epsU);
 }
@@ -535,6 +535,16 @@ __device__ __forceinline__ void wave_rows(double *scr, int R, int lane, Op op) {
   wave_sync();
 }
 
+// k/D - 1/2 for a digit k <= D: selects over the compile-time quotients,
+// the same values as the division.
+template <int D>
+__device__ __forceinline__ double grid_c(unsigned k) {
+  double v = -0.5;
+#pragma unroll
+  for (int q = 1; q <= D; ++q) v = k == (unsigned)q ? (double)q / D - 0.5 : v;
+  return v;
+}
+
 struct WaveTeam {
   int tid;
   double *scr = nullptr;  // kRowScratch doubles of LDS for reduce(); null: shuffles
@@ -666,7 +676,7 @@ __device__ __forceinline__ void last_pass_fit(const double *t, int st, int n, co
     double c = bl[0];
     unsigned q = (unsigned)f;
     for (int ax = n - 1; ax >= 1; --ax) {
-      c = fma(bl[1 + ax], (double)(q % D1) / D - 0.5, c);
+      c = fma(bl[1 + ax], grid_c<D>(q % D1), c);
       q /= D1;
     }
 #pragma unroll
@@ -835,7 +845,7 @@ __device__ void team_remainder(const double *t, int C, int n, const Team &tm, co
     double c = bl[0];
     unsigned q = (unsigned)f;
     for (int ax = n - 1; ax >= 1; --ax) {
-      c = fma(bl[1 + ax], (double)(q % D1) / D - 0.5, c);
+      c = fma(bl[1 + ax], grid_c<D>(q % D1), c);
       q /= D1;
     }
 #pragma unroll
@@ -855,11 +865,11 @@ __device__ void team_remainder(const double *t, int C, int n, const Team &tm, co
 // basis-change rounding and the pre-activation radius, rounded outward).
 __device__ inline double side_lo(const ConvertArgs &a, double mn, double l1, double eps) {
   if (a.fp64) return mn;
-  return round_down(mn - gamma64((double)a.n * (a.D + 2) + 4 + a.gextra) * l1 - eps);
+  return round_down(mn - a.gconv * l1 - eps);
 }
 __device__ inline double side_hi(const ConvertArgs &a, double mx, double l1, double eps) {
   if (a.fp64) return mx;
-  return round_up(mx + gamma64((double)a.n * (a.D + 2) + 4 + a.gextra) * l1 + eps);
+  return round_up(mx + a.gconv * l1 + eps);
 }
 
 __device__ inline bool wants_fit(const ConvertArgs &a, int64_t box, int j) {
@@ -1396,7 +1406,7 @@ __device__ void ntree_pass(const ConvertArgs &a, const NTreePlan &tp, const Team
     cl = beta[0];
     int rem = tl;
     for (int i = tp.e - 1; i >= 0; --i) {  // variable q + i has digit rem % D1
-      cl = fma(beta[1 + tp.q + i], (double)(rem % D1) / D - 0.5, cl);
+      cl = fma(beta[1 + tp.q + i], grid_c<D>(rem % D1), cl);
       rem /= D1;
     }
   } else {
@@ -1427,7 +1437,7 @@ __device__ void ntree_pass(const ConvertArgs &a, const NTreePlan &tp, const Team
     if (kFit) {
       int rem = rho;
       for (int i = tp.q - 1; i >= 0; --i) {
-        cr = fma(beta[1 + i], (double)(rem % D1) / D - 0.5, cr);
+        cr = fma(beta[1 + i], grid_c<D>(rem % D1), cr);
         rem /= D1;
       }
     }
@@ -1902,7 +1912,11 @@ size_t convert_scratch_bytes(int n, int D, int h, int64_t nboxes) {
          align256((size_t)nboxes * h * 2 * sp.Co * sizeof(double));
 }
 
-hipError_t launch_convert(const ConvertArgs &a, hipStream_t s) {
+hipError_t launch_convert(const ConvertArgs &a_in, hipStream_t s) {
+  // the rounding factors the kernels apply, once per launch
+  ConvertArgs a = a_in;
+  a.gconv = gamma64((double)a.n * (a.D + 2) + 4 + a.gextra);
+  a.gpre = gamma64(2.0 * a.hin + 6);
   const int D1 = a.D + 1;
   if (a.D >= 1 && a.D <= 8 && ((a.C <= kWaveC && a.tune.conv_wave == 0) || use_small(a.C)))
     return a.fp64 ? launch_convert_fixed<double>(a, s) : launch_convert_fixed<float>(a, s);
@@ -1933,6 +1947,7 @@ hipError_t launch_convert(const ConvertArgs &a, hipStream_t s) {
     const size_t lds = tree_lds(tp, a.n, a.D);
     ConvertArgs b = a;
     b.gextra = 0;  // one ratio per variable and step: within the per-axis count
+    b.gconv = gamma64((double)b.n * (b.D + 2) + 4);
     double *partial = a.scratch;
     double *l1part = reinterpret_cast<double *>(
         reinterpret_cast<char *>(partial) +
