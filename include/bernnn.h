@@ -179,7 +179,8 @@ bern_status bern_bounds(const bern_net *net, const bern_opts *opts, int64_t n_bo
  * affine kernel for layers wider than 8 neurons, 1 the same for layers of at
  * most 4 neurons, 2 threads of the dense block-per-neuron read-off, 3 the
  * per-neuron read-off: the tree of folds (0), the dense tensor with one wave
- * per neuron up to 1024 coefficients (1), or one block per neuron (2). The
+ * per neuron up to 1024 coefficients (1), or one block per neuron (2), the
+ * tree with one wave per neuron and more variables folded per round (3). The
  * choice is stored in the network handle and used by every
  * later call on it; every variant computes the same bounds up to the order
  * of floating-point sums.

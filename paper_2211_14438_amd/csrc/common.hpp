@@ -130,10 +130,11 @@ struct Tune {
   int gemm_narrow = 0;  // layers of <= 4 neurons: 0 4 rows x 8 inputs/step, 1 4x4, 2 4x16
   int conv_block = 0;   // threads of the block-per-neuron conversion: 0 by LDS use, 1 256, 2 512, 3 1024
   int conv_wave = 0;    // per-neuron read-off: 0 tree, 1 dense (one wave per neuron up to 1024
-                        // coefficients, else one block), 2 dense, one block per neuron
+                        // coefficients, else one block), 2 dense, one block per neuron,
+                        // 3 tree with one wave per neuron (more variables folded per round)
 };
 constexpr int kTuneParams = 4;
-constexpr int kTuneVariants[kTuneParams] = {4, 3, 4, 3};
+constexpr int kTuneVariants[kTuneParams] = {4, 3, 4, 4};
 
 // ----------------------------------------------------------- kernel launchers
 // Defined in the .hip files; every launcher enqueues on `stream` and returns a

@@ -1567,15 +1567,15 @@ __global__ void __launch_bounds__(kWave ? 256 : 1024) convert_ntree_t(ConvertArg
   }
 }
 
-static NTreePlan ntree_plan(int n, int D);
+static NTreePlan ntree_plan(int n, int D, bool wave_team);
 static size_t ntree_lds(const NTreePlan &tp, int n, int D, int teams);
 
 template <typename T, int D>
 static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
   // degree 1 tensors are read off densely (a wave per neuron does it in a
   // few steps); the tree needs D >= 2 to pay for its levels
-  if (a.tune.conv_wave == 0 && a.tree && D >= 2) {
-    const NTreePlan tp = ntree_plan(a.n, D);
+  if ((a.tune.conv_wave == 0 || a.tune.conv_wave == 3) && a.tree && D >= 2) {
+    const NTreePlan tp = ntree_plan(a.n, D, a.tune.conv_wave == 3);
     if (tp.e >= 1) {
       constexpr int M = ntree_tile_axes(D);
       const int64_t items = a.nboxes * a.h;
@@ -1857,16 +1857,18 @@ static TreePlan tree_plan(int n, int D, int64_t tensors) {
 }
 
 // Plan of the neuron tree: e the most variables with 2 (D+1)^e lanes in one
-// block, the rest folded per round; e shrinks until both trees fit LDS.
-static NTreePlan ntree_plan(int n, int D) {
+// block (one wave with wave_team), the rest folded per round; e shrinks
+// until both trees fit LDS.
+static NTreePlan ntree_plan(int n, int D, bool wave_team) {
   NTreePlan none;
   if (D < 1 || D > 8 || n > kMaxInputs) return none;
   const int M = ntree_tile_axes(D), D1 = D + 1, lead = n - M;
   if (lead < 1) return none;
   NTreePlan tp;
   for (int d = 0; d <= n; ++d) tp.S[d] = (int)ssize(d, D);
+  const int64_t max_lanes = wave_team ? 64 : 1024;
   int e = 0;
-  while (e < lead && 2 * ipow(D1, e + 1) <= 1024) ++e;
+  while (e < lead && 2 * ipow(D1, e + 1) <= max_lanes) ++e;
   for (; e >= 1; --e) {
     tp.e = e;
     tp.q = lead - e;
