@@ -80,6 +80,37 @@ __device__ inline void block_partials(const ComposeArgs &a, int64_t it, double r
   block_partials_slot(a, it, blockIdx.x, r, l1);
 }
 
+// One wave's item: its (rounding, l1) sums in slot 0, zeros in the others.
+__device__ void wave_partials(const ComposeArgs &a, int64_t it, double r, double l1) {
+  for (int off = 32; off > 0; off >>= 1) {
+    r += __shfl_xor(r, off, 64);
+    l1 += __shfl_xor(l1, off, 64);
+  }
+  const int lane = threadIdx.x & 63;
+  for (int64_t b = lane; b < a.nbx; b += 64) {
+    a.part[(it * a.nbx + b) * 2 + 0] = b == 0 ? r : 0.0;
+    a.part[(it * a.nbx + b) * 2 + 1] = b == 0 ? l1 : 0.0;
+  }
+}
+
+// The item of the calling wave: four waves per block, items in order of
+// (launch box, neuron, bound), `chunks` consecutive waves per item (chunk
+// index in `c`); false past the end.
+__device__ inline bool wave_item(const ComposeArgs &a, int64_t &g, int &j, int &s, int chunks = 1, int *c = nullptr) {
+  int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (c) {
+    *c = (int)(w % chunks);
+    w /= chunks;
+  }
+  const int64_t per = (int64_t)a.h * a.nbounds;
+  if (w >= a.nboxes * per) return false;
+  g = w / per;
+  const int rest = (int)(w - g * per);
+  j = rest / a.nbounds;
+  s = rest - j * a.nbounds;
+  return true;
+}
+
 // Store one coefficient; track its rounding and magnitude.
 template <typename T>
 __device__ __forceinline__ void store(T *dst, double q, double &r, double &l1) {
@@ -362,8 +393,11 @@ __global__ void __launch_bounds__(kBlock) live_kernel(ComposeArgs a) {
 // slot 0 and zeros to the item's other slots.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) compose_scatter_kernel(ComposeArgs a) {
-  const int j = blockIdx.y / a.nbounds, s = blockIdx.y % a.nbounds;
-  const int64_t g = blockIdx.z, box = wave_box(a, g);
+  int64_t g;
+  int j, s;
+  if (!wave_item(a, g, j, s)) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t box = wave_box(a, g);
   const NeuronRec &r = a.recs[box * a.h + j];
   const int kind = r.kind;
   if (kind >= 2 || kind == kActive || kind == kInactive) return;  // partials of these are not read
@@ -377,7 +411,7 @@ __global__ void __launch_bounds__(kBlock) compose_scatter_kernel(ComposeArgs a) 
   const int64_t Cs = a.Cs;
   double rsum = 0.0, l1sum = 0.0;
   if (kind == 1 && Ds == a.Din) {  // these neurons take degree Din <= Dout
-    for (int64_t I = threadIdx.x; I < a.Cin; I += blockDim.x) {
+    for (int64_t I = lane; I < a.Cin; I += 64) {
       double v = (double)p[I];
       if (I == 0) v += ns.shift - ns.lo;
       v = r.c[1] * (v / ns.w);
@@ -385,21 +419,16 @@ __global__ void __launch_bounds__(kBlock) compose_scatter_kernel(ComposeArgs a) 
       store(out + I, v, rsum, l1sum);
     }
   } else if (kind == kFallback) {
+    // rank 0: constant; rank 1 + axis: t_axis; the rest zero
     const double *fb = (s == 0) ? r.fbU : r.fbL;
-    for (int64_t I = threadIdx.x; I < Cs; I += blockDim.x) out[I] = (T)0;
-    __syncthreads();
-    if (threadIdx.x <= (unsigned)a.n && (threadIdx.x == 0 || Ds >= 1)) {
-      const int q = (int)threadIdx.x;  // rank 0: constant; rank 1 + axis: t_axis
-      store(out + q, fb[q], rsum, l1sum);
+    for (int64_t I = lane; I < Cs; I += 64) {
+      if (I <= a.n && (I == 0 || Ds >= 1))
+        store(out + I, fb[I], rsum, l1sum);
+      else
+        out[I] = (T)0;
     }
   }
-  if (a.part) {
-    block_partials_slot(a, it, 0, rsum, l1sum);
-    for (int64_t b = 1 + threadIdx.x; b < a.nbx; b += blockDim.x) {
-      a.part[(it * a.nbx + b) * 2 + 0] = 0.0;
-      a.part[(it * a.nbx + b) * 2 + 1] = 0.0;
-    }
-  }
+  if (a.part) wave_partials(a, it, rsum, l1sum);
 }
 
 // ---------------------------------------------- total-degree products
@@ -421,16 +450,31 @@ __device__ inline void load_nu(const ComposeArgs &a, const T *p, const NuSource 
 // degree 2 Din (a layer stored at a higher degree) are zero.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) compose_sq2_kernel(ComposeArgs a) {
-  extern __shared__ double nu[];
-  const int j = blockIdx.y / a.nbounds, s = blockIdx.y % a.nbounds;
-  const int64_t g = blockIdx.z, box = wave_box(a, g);
+  extern __shared__ double lds_nu[];
+  int64_t g;
+  int j, s, bx;
+  if (!wave_item(a, g, j, s, (int)a.nbx, &bx)) return;  // wave bx: outputs [bx kBlock, (bx + 1) kBlock)
+  const int lane = threadIdx.x & 63;
+  double *nu = lds_nu + (threadIdx.x >> 6) * a.Cin;  // the wave's nu
+  const int64_t box = wave_box(a, g);
   const NeuronRec &r = a.recs[box * a.h + j];
   if (r.kind != 2) return;
-  load_nu(a, in_tensor<T>(a, box, j, s), nu_of(a, &r, s), nu);
-  // block x owns outputs [x kBlock, (x + 1) kBlock), whatever its threads
-  const int64_t K0 = (int64_t)blockIdx.x * kBlock, K1 = min(K0 + kBlock, a.Cout);
+  {
+    const T *p = in_tensor<T>(a, box, j, s);
+    const NuSource ns = nu_of(a, &r, s);
+    for (int64_t i = lane; i < a.Cin; i += 64) {
+      double v = (double)p[i];
+      if (i == 0) v += ns.shift - ns.lo;
+      nu[i] = v / ns.w;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  T *out = out_tensor<T>(a, box, j, s);
   double rsum = 0.0, l1sum = 0.0;
-  for (int64_t K = K0 + threadIdx.x; K < K1; K += blockDim.x) {
+  const int64_t K1 = min((int64_t)(bx + 1) * kBlock, a.Cout);
+  for (int64_t K = (int64_t)bx * kBlock + lane; K < K1; K += 64) {
     double v = 0.0;
     if (K < a.Sm[2]) {
       double acc = 0.0;
@@ -446,9 +490,19 @@ __global__ void __launch_bounds__(kBlock) compose_sq2_kernel(ComposeArgs a) {
       if (K < a.Cin) v = fma(r.c[1], nu[K], v);
       if (K == 0) v += r.c[0] - (s == 1 ? r.e : 0.0);
     }
-    store(out_tensor<T>(a, box, j, s) + K, v, rsum, l1sum);
+    store(out + K, v, rsum, l1sum);
   }
-  if (a.part) block_partials(a, item_of(a, g, j, s), rsum, l1sum);
+  if (a.part) {  // the chunk's own slot
+    for (int off = 32; off > 0; off >>= 1) {
+      rsum += __shfl_xor(rsum, off, 64);
+      l1sum += __shfl_xor(l1sum, off, 64);
+    }
+    if (lane == 0) {
+      const int64_t it = item_of(a, g, j, s);
+      a.part[(it * a.nbx + bx) * 2 + 0] = rsum;
+      a.part[(it * a.nbx + bx) * 2 + 1] = l1sum;
+    }
+  }
 }
 
 // Orders L >= 3: Horner steps Q^(m) = nu Q^(m-1) + c_{L-1-m}, m = 1 .. L-1,
@@ -661,19 +715,19 @@ static hipError_t compose_all(const ComposeArgs &a, hipStream_t s) {
     RET_IF(hipGetLastError());
   }
   {
-    dim3 grid(1, (unsigned)(a.h * a.nbounds), (unsigned)a.nboxes);
+    const int64_t items = a.nboxes * a.h * a.nbounds;
     ProfScope ps(kProfComposeSimple, s, 0.0);
-    hipLaunchKernelGGL(compose_scatter_kernel<T>, grid, dim3(kComposeThreads), 0, s, a);
+    hipLaunchKernelGGL(compose_scatter_kernel<T>, dim3((unsigned)((items + 3) / 4)), dim3(256), 0, s, a);
     RET_IF(hipGetLastError());
   }
   const size_t lds = (size_t)a.Cin * sizeof(double);
   if (a.Lmax >= 2) {
-    if (!a.sq_off || lds > device_lds_limit() || (int64_t)gx * kBlock < a.Cout) return hipErrorInvalidValue;
+    if (!a.sq_off || 4 * lds > device_lds_limit() || (int64_t)gx * kBlock < a.Cout) return hipErrorInvalidValue;
     RET_IF(hipFuncSetAttribute((const void *)compose_sq2_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds));
-    dim3 grid(gx, (unsigned)(a.h * a.nbounds), (unsigned)a.nboxes);
+                               (int)(4 * lds)));
+    const int64_t waves = a.nboxes * a.h * a.nbounds * a.nbx;
     ProfScope ps(kProfComposeSquare, s, 0.0);
-    hipLaunchKernelGGL(compose_sq2_kernel<T>, grid, dim3(kComposeThreads), lds, s, a);
+    hipLaunchKernelGGL(compose_sq2_kernel<T>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 4 * lds, s, a);
     RET_IF(hipGetLastError());
   }
   if (a.Lmax >= 3) {
