@@ -170,16 +170,17 @@ __global__ void argmax_kernel(int64_t N, const float *logits, int8_t *cls) {
 __device__ void neuron_features(const LearnArgs &a, const NeuronRec &r, int j, float *f) {
   double w = r.hi - r.lo;
   if (!(w > 1e-300)) w = 1e-300;
+  const double iw = 1.0 / w;
   double slope = 0.0;
   for (int ax = 0; ax < a.n; ++ax) slope += fabs(r.fitU[1 + ax]);
-  f[0] = (float)(-r.lo / w);
+  f[0] = (float)(-r.lo * iw);
   f[1] = (float)log(w);
   f[2] = a.H > 1 ? (float)a.layer / (float)(a.H - 1) : 0.f;
-  f[3] = (float)log((double)a.D + 1.0);
-  f[4] = r.fitted ? (float)((r.fitU[0] - r.fitL[0]) / w) : 0.f;
+  f[3] = logf((float)a.D + 1.f);
+  f[4] = r.fitted ? (float)((r.fitU[0] - r.fitL[0]) * iw) : 0.f;
   f[5] = (float)log(fmax(a.sens[j] * w, 1e-30));
-  f[6] = r.fitted ? (float)(((r.rmaxU - r.rminU) + (r.rmaxL - r.rminL)) / w) : 0.f;
-  f[7] = r.fitted ? (float)(slope / w) : 0.f;
+  f[6] = r.fitted ? (float)(((r.rmaxU - r.rminU) + (r.rmaxL - r.rminL)) * iw) : 0.f;
+  f[7] = r.fitted ? (float)(slope * iw) : 0.f;
   for (int q = 0; q < kF; ++q)
     if (!isfinite(f[q])) f[q] = 0.f;
 }
@@ -194,39 +195,64 @@ __global__ void __launch_bounds__(256) features_kernel(LearnArgs a) {
   for (int q = 0; q < kF; ++q) a.feat[(box * a.nh + a.noff + j) * kF + q] = f[q];
 }
 
-// Features -> BF16 MLP -> class, one thread per (box, neuron). Stable neurons
-// get class -1 (their rule does not depend on the predictor).
-__global__ void __launch_bounds__(256) learned_classes_kernel(LearnArgs a) {
+// Features -> BF16 MLP -> class, four threads per (box, neuron): the first
+// reads the features, each computes the first layer and a quarter of the
+// second layer's units with their share of the output layer, and the four
+// shares are added in a fixed order. Stable neurons get class -1 (their rule
+// does not depend on the predictor).
+__global__ void __launch_bounds__(1024) learned_classes_kernel(LearnArgs a) {
   __shared__ float w[kParams];
+  __shared__ float fs[256][kF];
   for (int i = threadIdx.x; i < kParams; i += blockDim.x)
     w[i] = i >= kOffW1 ? bf16_round(a.params[i]) : a.params[i];
-  __syncthreads();
-  const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (it >= a.nboxes * a.h) return;
-  const int64_t box = a.bids ? a.bids[it / a.h] : it / a.h;
-  const int j = (int)(it % a.h);
-  const NeuronRec &r = a.recs[box * a.h + j];
-  float f[kF], x[kF], h1[kH], z[kC];
-  neuron_features(a, r, j, f);
-  if (a.feat)
-    for (int q = 0; q < kF; ++q) a.feat[(box * a.nh + a.noff + j) * kF + q] = f[q];
-  if (!(r.lo < 0.0 && r.hi > 0.0)) {
-    a.codes[box * a.nh + a.noff + j] = -1;
-    return;
+  const int64_t it = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 2;
+  const int k = threadIdx.x & 3, slot = threadIdx.x >> 2;
+  const bool valid = it < a.nboxes * a.h;
+  const int64_t box = valid ? (a.bids ? a.bids[it / a.h] : it / a.h) : 0;
+  const int j = valid ? (int)(it % a.h) : 0;
+  bool unstable = false;
+  if (valid) {
+    const NeuronRec &r = a.recs[box * a.h + j];
+    unstable = r.lo < 0.0 && r.hi > 0.0;
+    if (k == 0) {
+      float f[kF];
+      neuron_features(a, r, j, f);
+      for (int q = 0; q < kF; ++q) fs[slot][q] = f[q];
+      if (a.feat)
+        for (int q = 0; q < kF; ++q) a.feat[(box * a.nh + a.noff + j) * kF + q] = f[q];
+      if (!unstable) a.codes[box * a.nh + a.noff + j] = -1;
+    }
   }
-  for (int q = 0; q < kF; ++q) x[q] = bf16_round((f[q] - w[kOffMean + q]) / w[kOffStd + q]);
+  __syncthreads();
+  if (!valid || !unstable) return;
+  float x[kF], h1[kH], z[kC];
+  for (int q = 0; q < kF; ++q) x[q] = bf16_round((fs[slot][q] - w[kOffMean + q]) / w[kOffStd + q]);
   for (int o = 0; o < kH; ++o) {
     float s = w[kOffB1 + o];
     for (int q = 0; q < kF; ++q) s = fmaf(w[kOffW1 + o * kF + q], x[q], s);
     h1[o] = bf16_round(fmaxf(s, 0.f));
   }
-  for (int c = 0; c < kC; ++c) z[c] = w[kOffB3 + c];
-  for (int o = 0; o < kH; ++o) {
-    float s = w[kOffB2 + o];
-    for (int i = 0; i < kH; ++i) s = fmaf(w[kOffW2 + o * kH + i], h1[i], s);
-    s = bf16_round(fmaxf(s, 0.f));
-    for (int c = 0; c < kC; ++c) z[c] = fmaf(w[kOffW3 + c * kH + o], s, z[c]);
+  for (int c = 0; c < kC; ++c) z[c] = k == 0 ? w[kOffB3 + c] : 0.f;
+  // this thread's quarter of the hidden units, four at a time
+  for (int o0 = k * (kH / 4); o0 < (k + 1) * (kH / 4); o0 += 4) {
+    float s[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s[u] = w[kOffB2 + o0 + u];
+    for (int i = 0; i < kH; ++i)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s[u] = fmaf(w[kOffW2 + (o0 + u) * kH + i], h1[i], s[u]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const float hu = bf16_round(fmaxf(s[u], 0.f));
+      for (int c = 0; c < kC; ++c) z[c] = fmaf(w[kOffW3 + c * kH + o0 + u], hu, z[c]);
+    }
   }
+  // (z0 + z1) + (z2 + z3) over the neuron's four threads
+  for (int c = 0; c < kC; ++c) {
+    z[c] += __shfl_xor(z[c], 1, 64);
+    z[c] += __shfl_xor(z[c], 2, 64);
+  }
+  if (k != 0) return;
   int best = 0;
   for (int c = 1; c < kC; ++c)
     if (z[c] > z[best]) best = c;
@@ -264,7 +290,7 @@ __global__ void __launch_bounds__(256) learned_rules_kernel(LearnArgs a) {
 hipError_t launch_learned_rules(const LearnArgs &a, hipStream_t s) {
   {
     ProfScope ps(kProfPredictor, s, 0.0);
-    hipLaunchKernelGGL(learned_classes_kernel, dim3((unsigned)((a.nboxes * a.h + 255) / 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(learned_classes_kernel, dim3((unsigned)((a.nboxes * a.h + 255) / 256)), dim3(1024), 0, s, a);
     RET_IF(hipGetLastError());
   }
   ProfScope ps(kProfPredictor, s, 0.0);
