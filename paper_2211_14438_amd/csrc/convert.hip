@@ -1340,9 +1340,9 @@ static hipError_t launch_tree(const ConvertArgs &a, const TreePlan &tp, size_t l
 // The tree read-off for one neuron's pair of tensors (all tensors within
 // one block's reach): a block per neuron holds both trees, upper and lower,
 // and lanes 0 .. lanes-1 take the upper tensor's tiles, the next lanes the
-// lower's. The first pass gives the extrema; a neuron that takes a fitted
-// rule gets its affine fits (closed form, wave_fit) and a second pass for
-// the remainder ranges b_K - l(K/D).
+// lower's. A neuron that may take a fitted rule gets its affine fits
+// (closed form, wave_fit) before the pass, which then tracks the remainders
+// b_K - l(K/D) beside the extrema.
 constexpr int ntree_tile_axes(int D) { return D == 1 ? 1 : D == 2 ? 3 : D <= 4 ? 2 : 1; }
 
 struct NTreePlan {
@@ -1352,12 +1352,13 @@ struct NTreePlan {
   int S[kMaxInputs + 1] = {};
 };
 
-// The lane's tile of one pass: pass 1 (kFit false) folds the extrema of the
-// Bernstein coefficients into mn / mx, pass 2 those of the remainders
-// x - l, with l = c + sum over the tile's variables a of g[a][digit].
+// The lane's tile: folds the extrema of its Bernstein coefficients x into
+// mn / mx and, with kFit, those of the remainders x - l into rmn / rmx, with
+// l = c + sum over the tile's variables a of g[a][digit].
 template <int D, int M, bool kFit>
 __device__ __forceinline__ void ntree_lane(const double *par, const double (&rk)[D + 1], double c,
-                                           const double (&g)[M][D + 1], double &mn, double &mx) {
+                                           const double (&g)[M][D + 1], double &mn, double &mx, double &rmn,
+                                           double &rmx) {
   using LT = LaneTabs<D, M>;
   constexpr int N = cpow(D + 1, M);
   double x[N];
@@ -1371,21 +1372,24 @@ __device__ __forceinline__ void ntree_lane(const double *par, const double (&rk)
   });
   block_to_bern<D, M>(x);
   Unroll<0, N>::run([&](auto Q) {
-    double v = x[Q.value];
+    const double v = x[Q.value];
+    mn = fmin(mn, v);
+    mx = fmax(mx, v);
     if constexpr (kFit) {
       double l = c;
       Unroll<0, M>::run([&](auto A) { l += g[A.value][(Q.value / cpow(D + 1, M - 1 - A.value)) % (D + 1)]; });
-      v -= l;
+      rmn = fmin(rmn, v - l);
+      rmx = fmax(rmx, v - l);
     }
-    mn = fmin(mn, v);
-    mx = fmax(mx, v);
   });
 }
 
-// One pass over both trees (areas t0 and t0 + area). bl: the two fits (pass 2).
+// One pass over both trees (areas t0 and t0 + area); with kFit also the
+// remainder extrema of the fits bl (upper, then lower).
 template <int D, int M, bool kFit, class Team>
 __device__ void ntree_pass(const ConvertArgs &a, const NTreePlan &tp, const Team &tm, const int *tb,
-                           const double *tab, double *t0, const double *bl, double &mn, double &mx) {
+                           const double *tab, double *t0, const double *bl, double &mn, double &mx, double &rmn,
+                           double &rmx) {
   constexpr int D1 = D + 1;
   const int tid = tm.tid, nt = tm.nt, n = a.n;
   const int side = tid / tp.lanes, tl = tid - side * tp.lanes;  // side 0: upper, 1: lower
@@ -1473,7 +1477,7 @@ __device__ void ntree_pass(const ConvertArgs &a, const NTreePlan &tp, const Team
       if (lane) {
         double *root = t0 + side * tp.area;
         const double *par = (in_off < 0 ? level(root, tp.q) : root + in_off) + (int64_t)pv * tp.S[M + 1];
-        ntree_lane<D, M, kFit>(par, rk, cr, g, mn, mx);
+        ntree_lane<D, M, kFit>(par, rk, cr, g, mn, mx, rmn, rmx);
       }
     }
     tm.sync();
@@ -1505,31 +1509,36 @@ __device__ void ntree_neuron(const ConvertArgs &a, const NTreePlan &tp, const Te
   const double l1U = l1[0], l1L = l1[1];
   tm.sync();
   const int side = tid / tp.lanes;
-  double mn = INFINITY, mx = -INFINITY;
-  ntree_pass<D, M, false>(a, tp, tm, tb, tab, t0, bl, mn, mx);
-  double ex[2] = {side == 0 ? mx : -INFINITY, side == 1 ? -mn : -INFINITY};  // maxima of max U, -min L
-  tm.reduce(ex, OpMax());
-  const double mxU = ex[0], mnL = -ex[1];
-  const double lo = side_lo(a, mnL, l1L, epsL), hi = side_hi(a, mxU, l1U, epsU);
+  // Neurons that may take a fitted rule get their affine fits (closed form
+  // from the stored coefficients) first and the remainder ranges in the
+  // same pass as the extrema.
   const bool want = wants_fit(a, box, j);
-  const bool fitted = want && (a.fits || (lo < 0.0 && hi > 0.0));
-  double fx[4] = {0.0, 0.0, 0.0, 0.0};  // rmaxU, rminU, rmaxL, rminL
-  if (fitted) {
+  if (want) {
     if (kWave || threadIdx.x < 64) {
       double *scr = kWave ? tm_scratch(tm) : nullptr;
       wave_fit<D>(p, a.didx, S, n, (int)(threadIdx.x & 63), bl, scr);
       wave_fit<D>(p + S, a.didx, S, n, (int)(threadIdx.x & 63), bl + kMaxInputs + 1, scr);
     }
     tm.sync();
-    double rmn = INFINITY, rmx = -INFINITY;
-    ntree_pass<D, M, true>(a, tp, tm, tb, tab, t0, bl, rmn, rmx);
-    double r4[4] = {side == 0 ? rmx : -INFINITY, side == 0 ? -rmn : -INFINITY, side == 1 ? rmx : -INFINITY,
-                    side == 1 ? -rmn : -INFINITY};
-    tm.reduce(r4, OpMax());
-    fx[0] = r4[0];
-    fx[1] = -r4[1];
-    fx[2] = r4[2];
-    fx[3] = -r4[3];
+  }
+  double mn = INFINITY, mx = -INFINITY, rmn = INFINITY, rmx = -INFINITY;
+  if (want)
+    ntree_pass<D, M, true>(a, tp, tm, tb, tab, t0, bl, mn, mx, rmn, rmx);
+  else
+    ntree_pass<D, M, false>(a, tp, tm, tb, tab, t0, bl, mn, mx, rmn, rmx);
+  // maxima of: max U, -min L, and the remainders' max U, -min U, max L, -min L
+  double ex[6] = {side == 0 ? mx : -INFINITY, side == 1 ? -mn : -INFINITY, side == 0 ? rmx : -INFINITY,
+                  side == 0 ? -rmn : -INFINITY, side == 1 ? rmx : -INFINITY, side == 1 ? -rmn : -INFINITY};
+  tm.reduce(ex, OpMax());
+  const double mxU = ex[0], mnL = -ex[1];
+  const double lo = side_lo(a, mnL, l1L, epsL), hi = side_hi(a, mxU, l1U, epsU);
+  const bool fitted = want && (a.fits || (lo < 0.0 && hi > 0.0));
+  double fx[4] = {0.0, 0.0, 0.0, 0.0};  // rmaxU, rminU, rmaxL, rminL
+  if (fitted) {
+    fx[0] = ex[2];
+    fx[1] = -ex[3];
+    fx[2] = ex[4];
+    fx[3] = -ex[5];
   }
   if (a.mode == 0) {  // the fits, or zeros
     NeuronRec &rec = a.recs[box * a.h + j];
