@@ -832,34 +832,6 @@ __device__ void team_convert_lanes(double *t, const T *p, const int *didx, int C
   team_axes<D>(t, C, 1, n, tm, true, mn, mx, pl, bl, &rmn, &rmx);
 }
 
-// Remainder range of the fit bl over the converted tensor in LDS (rmax =
-// max_K b_K - l(K/D), rmin = min): one pass over the fibres along axis 0.
-template <int D, class Team>
-__device__ void team_remainder(const double *t, int C, int n, const Team &tm, const double *bl, double &rmax,
-                               double &rmin) {
-  constexpr int D1 = D + 1;
-  const int st = C / D1;
-  const double b1 = bl[1];
-  double hi = -INFINITY, lo = INFINITY;
-  for (int f = tm.tid; f < st; f += tm.nt) {
-    double c = bl[0];
-    unsigned q = (unsigned)f;
-    for (int ax = n - 1; ax >= 1; --ax) {
-      c = fma(bl[1 + ax], grid_c<D>(q % D1), c);
-      q /= D1;
-    }
-#pragma unroll
-    for (int j = 0; j < D1; ++j) {
-      const double r = t[f + j * st] - fma(b1, (double)j / D - 0.5, c);
-      hi = fmax(hi, r);
-      lo = fmin(lo, r);
-    }
-  }
-  double e[2] = {hi, -lo};
-  tm.reduce(e, OpMax());
-  rmax = e[0];
-  rmin = -e[1];
-}
 
 // Bound of one side from its Bernstein extremum (FP32 mode: widened by the
 // basis-change rounding and the pre-activation radius, rounded outward).
@@ -901,97 +873,56 @@ __device__ inline void team_write_fit(const ConvertArgs &a, const Team &tm, doub
 }
 
 // Both bound tensors of neuron (box, j) by one team with `t` (C doubles) and
-// `bl` (n+1 doubles) in LDS; `fitter` marks the team's first wave, which
-// computes the fits. Lower tensor first: it is fitted while resident if the
-// neuron can still take a fitted rule, i.e. its lower bound is negative and
-// an upper bound of the upper tensor's largest Bernstein coefficient (its
-// constant plus its positive coefficients, the ratio table lying in [0,1])
-// is positive. The upper tensor's fit is then computed before its read-off,
-// whose last pass also gives the remainder range.
+// `bl` (the two fits, 2 (kMaxInputs + 1) doubles) in LDS; `fitter` marks the
+// team's first wave, which computes the fits.
 template <int D, typename T, class Team>
 __device__ void readoff_pair(const ConvertArgs &a, const Team &tm, bool fitter, int lane, double *t, double *bl,
                              const int *pl, int64_t box, int j) {
   const int C = (int)a.C, S = (int)a.S;
   const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + (int64_t)j * 2 * a.S;
   double *scr = tm_scratch(tm);
-  // l1 norms of both tensors, and an upper bound of the upper tensor's
-  // largest Bernstein coefficient: its constant plus its positive
-  // coefficients (the ratio table lies in [0,1]); their loads go out before
-  // the radii's
-  double v3[3] = {0.0, 0.0, 0.0};
+  double *blU = bl, *blL = bl + kMaxInputs + 1;
+  // l1 norms of both tensors; their loads go out before the radii's
+  double l1[2] = {0.0, 0.0};
   for (int i = tm.tid; i < S; i += tm.nt) {
-    const double u = (double)p[i], w = (double)p[S + i];
-    v3[0] += i == 0 ? u : fmax(u, 0.0);
-    v3[1] += fabs(u);
-    v3[2] += fabs(w);
+    l1[0] += fabs((double)p[i]);
+    l1[1] += fabs((double)p[S + i]);
   }
   double epsU = 0.0, epsL = 0.0;
   if (!a.fp64) pre_radii_team(a, box, j, tm, epsU, epsL);
+  tm.reduce(l1, OpAdd());
+  const double l1U = l1[0], l1L = l1[1];
+  // Neurons that may take a fitted rule get their affine fits (closed form
+  // from the stored coefficients) first and the remainder ranges in the last
+  // pass of each read-off.
   const bool want = wants_fit(a, box, j);
-  NeuronRec *rec = want ? &a.recs[box * a.h + j] : nullptr;
-  double fx[4] = {0.0, 0.0, 0.0, 0.0};  // rmaxU, rminU, rmaxL, rminL
-  tm.reduce(v3, OpAdd());
-  const double l1U = v3[1], l1L = v3[2];
-  const double hib = want && !a.fits ? side_hi(a, v3[0] + 1e-12 * l1U, l1U, epsU) : INFINITY;
-  // lower tensor first; fitted while resident if the neuron can still take
-  // a fitted rule (lower bound negative, hib positive)
-  double mn = INFINITY, mx = -INFINITY, rmn = INFINITY, rmx = -INFINITY;
-  team_convert_lanes<D>(t, p + S, a.didx, C, S, a.n, tm, pl, nullptr, mn, mx, rmn, rmx);
-  {
-    double e[1] = {-mn};
-    tm.reduce(e, OpMax());
-    mn = -e[0];
-  }
-  const double lo = side_lo(a, mn, l1L, epsL);
-  const bool lower_fitted = want && (a.fits || (lo < 0.0 && hib > 0.0));
-  if (lower_fitted) {
-    if (fitter) wave_fit<D>(p + S, a.didx, S, a.n, lane, bl, scr);
-    tm.sync();
-    team_remainder<D>(t, C, a.n, tm, bl, fx[2], fx[3]);
-    team_write_fit(a, tm, rec->fitL, bl);
-    if (fitter) wave_fit<D>(p, a.didx, S, a.n, lane, bl, scr);
-  }
-  tm.sync();
-  // upper tensor, with the remainder range of its fit in the last pass
-  mn = INFINITY;
-  mx = -INFINITY;
-  rmn = INFINITY;
-  rmx = -INFINITY;
-  team_convert_lanes<D>(t, p, a.didx, C, S, a.n, tm, pl, lower_fitted ? bl : nullptr, mn, mx, rmn, rmx);
-  {
-    double e[3] = {mx, rmx, -rmn};
-    tm.reduce(e, OpMax());
-    mx = e[0];
-    if (lower_fitted) {
-      fx[0] = e[1];
-      fx[1] = -e[2];
+  if (want) {
+    if (fitter) {
+      wave_fit<D>(p, a.didx, S, a.n, lane, blU, scr);
+      wave_fit<D>(p + S, a.didx, S, a.n, lane, blL, scr);
     }
+    tm.sync();
   }
-  const double hi = side_hi(a, mx, l1U, epsU);
+  double mnL = INFINITY, mxL = -INFINITY, rmnL = INFINITY, rmxL = -INFINITY;
+  team_convert_lanes<D>(t, p + S, a.didx, C, S, a.n, tm, pl, want ? blL : nullptr, mnL, mxL, rmnL, rmxL);
+  double mnU = INFINITY, mxU = -INFINITY, rmnU = INFINITY, rmxU = -INFINITY;
+  team_convert_lanes<D>(t, p, a.didx, C, S, a.n, tm, pl, want ? blU : nullptr, mnU, mxU, rmnU, rmxU);
+  // maxima of: max U, -min L, and the remainders' max U, -min U, max L, -min L
+  double ex[6] = {mxU, -mnL, rmxU, -rmnU, rmxL, -rmnL};
+  tm.reduce(ex, OpMax());
+  const double lo = side_lo(a, -ex[1], l1L, epsL), hi = side_hi(a, ex[0], l1U, epsU);
   const bool fitted = want && (a.fits || (lo < 0.0 && hi > 0.0));
-  if (fitted && !lower_fitted) {  // not expected: hib bounds hi from above
-    if (fitter) wave_fit<D>(p, a.didx, S, a.n, lane, bl, scr);
-    tm.sync();
-    double m1 = INFINITY, m2 = -INFINITY, r1 = INFINITY, r2 = -INFINITY;
-    team_convert_lanes<D>(t, p, a.didx, C, S, a.n, tm, pl, bl, m1, m2, r1, r2);
-    double e[2] = {r2, -r1};
-    tm.reduce(e, OpMax());
-    fx[0] = e[0];
-    fx[1] = -e[1];
-    team_write_fit(a, tm, rec->fitU, bl);
-    m1 = INFINITY;
-    m2 = -INFINITY;
-    team_convert_lanes<D>(t, p + S, a.didx, C, S, a.n, tm, pl, nullptr, m1, m2, r1, r2);
-    if (fitter) wave_fit<D>(p + S, a.didx, S, a.n, lane, bl, scr);
-    tm.sync();
-    team_remainder<D>(t, C, a.n, tm, bl, fx[2], fx[3]);
-    team_write_fit(a, tm, rec->fitL, bl);
-  } else if (fitted) {
-    team_write_fit(a, tm, rec->fitU, bl);
-  } else if (a.mode == 0) {  // records of neurons without a fit carry zeros
-    NeuronRec &r = a.recs[box * a.h + j];
-    team_write_fit(a, tm, r.fitU, nullptr);
-    team_write_fit(a, tm, r.fitL, nullptr);
+  double fx[4] = {0.0, 0.0, 0.0, 0.0};  // rmaxU, rminU, rmaxL, rminL
+  if (fitted) {
+    fx[0] = ex[2];
+    fx[1] = -ex[3];
+    fx[2] = ex[4];
+    fx[3] = -ex[5];
+  }
+  if (a.mode == 0) {  // the fits, or zeros
+    NeuronRec &rec = a.recs[box * a.h + j];
+    team_write_fit(a, tm, rec.fitU, fitted ? blU : nullptr);
+    team_write_fit(a, tm, rec.fitL, fitted ? blL : nullptr);
   }
   if (tm.tid == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted, true);
 }
@@ -1005,7 +936,7 @@ __global__ void __launch_bounds__(kBlock, 6) convert_wave_t(ConvertArgs a) {
   const int wv = threadIdx.x >> 6;
   const int C = (int)a.C;
   const int *pl = stage_prefixes(a, reinterpret_cast<int *>(lds));
-  double *tw = lds + (a.plist_len + 1) / 2 + (int64_t)wv * (kRowScratch + C + kMaxInputs + 1);
+  double *tw = lds + (a.plist_len + 1) / 2 + (int64_t)wv * (kRowScratch + C + 2 * (kMaxInputs + 1));
   const int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + wv;
   if (item >= a.nboxes * a.h) return;
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
@@ -1610,7 +1541,7 @@ static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
   }
   const size_t plb = (size_t)((a.plist_len + 1) / 2) * sizeof(double);
   if (a.C <= kWaveC && a.tune.conv_wave <= 1) {
-    const size_t lds = (size_t)(kBlock / 64) * (kRowScratch + a.C + kMaxInputs + 1) * sizeof(double) + plb;
+    const size_t lds = (size_t)(kBlock / 64) * (kRowScratch + a.C + 2 * (kMaxInputs + 1)) * sizeof(double) + plb;
     RET_IF(hipFuncSetAttribute((const void *)convert_wave_t<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
     ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4),
@@ -1620,7 +1551,7 @@ static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
                        dim3(kBlock), lds, s, a);
     return hipGetLastError();
   }
-  const size_t lds = (size_t)(a.C + kMaxInputs + 1) * sizeof(double) + plb;
+  const size_t lds = (size_t)(a.C + 2 * (kMaxInputs + 1)) * sizeof(double) + plb;
   if (lds + 256 > device_lds_limit()) return hipErrorInvalidValue;
   RET_IF(hipFuncSetAttribute((const void *)convert_block_t<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)lds));
