@@ -1507,37 +1507,47 @@ __global__ void __launch_bounds__(kWave ? 256 : 1024) convert_ntree_t(ConvertArg
   }
 }
 
-static NTreePlan ntree_plan(int n, int D, bool wave_team);
+static NTreePlan ntree_plan(int n, int D, int M, bool wave_team);
 static size_t ntree_lds(const NTreePlan &tp, int n, int D, int teams);
+
+template <typename T, int D, int M>
+static bool launch_ntree(const ConvertArgs &a, hipStream_t s, bool wave_team, hipError_t &err) {
+  const NTreePlan tp = ntree_plan(a.n, D, M, wave_team);
+  if (tp.e < 1) return false;
+  const int64_t items = a.nboxes * a.h;
+  ProfScope ps(kProfConvertSmall, s, (double)items * 2 * a.S * (a.fp64 ? 8 : 4),
+               (double)items * 2 * a.n * a.C * (a.D + 2));
+  err = hipSuccess;
+  if (tp.threads == 64) {  // a wave per neuron, four per block
+    const size_t lds = ntree_lds(tp, a.n, D, 4);
+    if (lds <= device_lds_limit()) {
+      err = hipFuncSetAttribute((const void *)convert_ntree_t<D, M, T, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (err != hipSuccess) return true;
+      hipLaunchKernelGGL((convert_ntree_t<D, M, T, true>), dim3((unsigned)((items + 3) / 4)), dim3(256), lds, s, a,
+                         tp);
+      err = hipGetLastError();
+      return true;
+    }
+  }
+  const size_t lds = ntree_lds(tp, a.n, D, 1);
+  err = hipFuncSetAttribute((const void *)convert_ntree_t<D, M, T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+  if (err != hipSuccess) return true;
+  hipLaunchKernelGGL((convert_ntree_t<D, M, T, false>), dim3((unsigned)items), dim3((unsigned)tp.threads), lds, s, a,
+                     tp);
+  err = hipGetLastError();
+  return true;
+}
 
 template <typename T, int D>
 static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
   // degree 1 tensors are read off densely (a wave per neuron does it in a
   // few steps); the tree needs D >= 2 to pay for its levels
-  if ((a.tune.conv_wave == 0 || a.tune.conv_wave == 3) && a.tree && D >= 2) {
-    const NTreePlan tp = ntree_plan(a.n, D, a.tune.conv_wave == 3);
-    if (tp.e >= 1) {
-      constexpr int M = ntree_tile_axes(D);
-      const int64_t items = a.nboxes * a.h;
-      ProfScope ps(kProfConvertSmall, s, (double)items * 2 * a.S * (a.fp64 ? 8 : 4),
-                   (double)items * 2 * a.n * a.C * (a.D + 2));
-      if (tp.threads == 64) {  // a wave per neuron, four per block
-        const size_t lds = ntree_lds(tp, a.n, D, 4);
-        if (lds <= device_lds_limit()) {
-          RET_IF(hipFuncSetAttribute((const void *)convert_ntree_t<D, M, T, true>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-          hipLaunchKernelGGL((convert_ntree_t<D, M, T, true>), dim3((unsigned)((items + 3) / 4)), dim3(256), lds, s,
-                             a, tp);
-          return hipGetLastError();
-        }
-      }
-      const size_t lds = ntree_lds(tp, a.n, D, 1);
-      RET_IF(hipFuncSetAttribute((const void *)convert_ntree_t<D, M, T, false>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-      hipLaunchKernelGGL((convert_ntree_t<D, M, T, false>), dim3((unsigned)items), dim3((unsigned)tp.threads), lds, s,
-                         a, tp);
-      return hipGetLastError();
-    }
+  if (a.tree && D >= 2) {
+    hipError_t err = hipSuccess;
+    if (a.tune.conv_wave == 0 && launch_ntree<T, D, ntree_tile_axes(D)>(a, s, false, err)) return err;
+    if (a.tune.conv_wave == 3 && launch_ntree<T, D, ntree_tile_axes(D)>(a, s, true, err)) return err;
   }
   const size_t plb = (size_t)((a.plist_len + 1) / 2) * sizeof(double);
   if (a.C <= kWaveC && a.tune.conv_wave <= 1) {
@@ -1799,10 +1809,10 @@ static TreePlan tree_plan(int n, int D, int64_t tensors) {
 // Plan of the neuron tree: e the most variables with 2 (D+1)^e lanes in one
 // block (one wave with wave_team), the rest folded per round; e shrinks
 // until both trees fit LDS.
-static NTreePlan ntree_plan(int n, int D, bool wave_team) {
+static NTreePlan ntree_plan(int n, int D, int M, bool wave_team) {
   NTreePlan none;
   if (D < 1 || D > 8 || n > kMaxInputs) return none;
-  const int M = ntree_tile_axes(D), D1 = D + 1, lead = n - M;
+  const int D1 = D + 1, lead = n - M;
   if (lead < 1) return none;
   NTreePlan tp;
   for (int d = 0; d <= n; ++d) tp.S[d] = (int)ssize(d, D);
