@@ -1285,10 +1285,10 @@ struct NTreePlan {
 
 // The lane's tile: folds the extrema of its Bernstein coefficients x into
 // mn / mx and, with kFit, those of the remainders x - l into rmn / rmx, with
-// l = c + sum over the tile's variables a of g[a][digit].
+// l = c + sum over the tile's variables a of g[a] (digit/D - 1/2).
 template <int D, int M, bool kFit>
 __device__ __forceinline__ void ntree_lane(const double *par, const double (&rk)[D + 1], double c,
-                                           const double (&g)[M][D + 1], double &mn, double &mx, double &rmn,
+                                           const double (&g)[M], double &mn, double &mx, double &rmn,
                                            double &rmx) {
   using LT = LaneTabs<D, M>;
   constexpr int N = cpow(D + 1, M);
@@ -1308,7 +1308,10 @@ __device__ __forceinline__ void ntree_lane(const double *par, const double (&rk)
     mx = fmax(mx, v);
     if constexpr (kFit) {
       double l = c;
-      Unroll<0, M>::run([&](auto A) { l += g[A.value][(Q.value / cpow(D + 1, M - 1 - A.value)) % (D + 1)]; });
+      Unroll<0, M>::run([&](auto A) {
+        constexpr int t = (Q.value / cpow(D + 1, M - 1 - A.value)) % (D + 1);
+        l = fma(g[A.value], (double)t / D - 0.5, l);
+      });
       rmn = fmin(rmn, v - l);
       rmx = fmax(rmx, v - l);
     }
@@ -1330,14 +1333,12 @@ __device__ void ntree_pass(const ConvertArgs &a, const NTreePlan &tp, const Team
 #pragma unroll
   for (int j = 0; j < D1; ++j) rk[j] = lane ? tab[lane_k * D1 + j] : 0.0;
   // the fit's tile part and the lane's own digits' part
-  double g[M][D1];
+  double g[M];  // the fit's slopes along the tile's variables
   double cl = 0.0;
   const double *beta = bl + (lane ? side : 0) * (kMaxInputs + 1);
   if (kFit) {
 #pragma unroll
-    for (int m = 0; m < M; ++m)
-#pragma unroll
-      for (int t = 0; t < D1; ++t) g[m][t] = beta[1 + n - M + m] * ((double)t / D - 0.5);
+    for (int m = 0; m < M; ++m) g[m] = beta[1 + n - M + m];
     cl = beta[0];
     int rem = tl;
     for (int i = tp.e - 1; i >= 0; --i) {  // variable q + i has digit rem % D1
@@ -1346,9 +1347,7 @@ __device__ void ntree_pass(const ConvertArgs &a, const NTreePlan &tp, const Team
     }
   } else {
 #pragma unroll
-    for (int m = 0; m < M; ++m)
-#pragma unroll
-      for (int t = 0; t < D1; ++t) g[m][t] = 0.0;
+    for (int m = 0; m < M; ++m) g[m] = 0.0;
   }
   // chain levels of a tree: level i (1 .. q) after the stored coefficients
   auto level = [&](double *root, int i) -> double * {
