@@ -122,3 +122,18 @@ def test_degenerate_boxes(precision):
     # a point box: the bounds enclose the network's value there
     v = H.forward(case.Ws, case.bs, lo[0][None, :])[-1][0]
     assert np.all(g["out_lo"][0] <= v + 1e-9) and np.all(g["out_hi"][0] >= v - 1e-9)
+
+
+def test_tree_readoff_without_block_fixed_indices():
+    """Output tensors beyond one block's LDS (n = 7, degree 4: 78,125 Bernstein
+    coefficients) for 8,800 tensors: the tree read-off then fixes no index per
+    block (every block folds from the stored coefficients and refolds them
+    round by round). Sampled boxes against the oracle, every box for
+    soundness."""
+    case = wl.random_net_case([7, 5, 5, 4], seed=93, n_boxes=1100)
+    print(f"case {case.name}", flush=True)
+    g = _run(case)
+    _check_sound_all(case, g, m=40)
+    for i in (0, 549, 1099):
+        o = orc.network(case.Ws, case.bs, case.box_lo[i], case.box_hi[i], L=case.L)
+        _check_box_fp32(g, i, o, case.n_hidden)
