@@ -820,6 +820,33 @@ __device__ void wave_fit(const T *p, const int *didx, int S, int n, int lane, do
   }
 }
 
+// Degree 1 (an affine polynomial a_0 + sum_a a_{1+a} t_a): the Bernstein
+// coefficients at per-variable degree 1 are its values at the 2^n box
+// corners, evaluated directly (corner K: axis a's bit at n-1-a), with the
+// lane's extrema and, with a fit bl, remainder extrema; no dense tensor.
+template <typename T, class Team>
+__device__ void team_corners_lanes(double *t, const T *p, int n, const Team &tm, const double *bl, double &mn,
+                                   double &mx, double &rmn, double &rmx) {
+  for (int i = tm.tid; i <= n; i += tm.nt) t[i] = (double)p[i];
+  tm.sync();
+  const int C = 1 << n;
+  for (int K = tm.tid; K < C; K += tm.nt) {
+    double v = t[0], l = bl ? bl[0] : 0.0;
+    for (int ax = 0; ax < n; ++ax) {
+      const bool one = (K >> (n - 1 - ax)) & 1;
+      if (one) v += t[1 + ax];
+      if (bl) l = fma(bl[1 + ax], one ? 0.5 : -0.5, l);
+    }
+    mn = fmin(mn, v);
+    mx = fmax(mx, v);
+    if (bl) {
+      rmn = fmin(rmn, v - l);
+      rmx = fmax(rmx, v - l);
+    }
+  }
+  tm.sync();
+}
+
 // team_convert without its reductions: the lane's own extrema (and, with a
 // fit, remainder extrema) are folded into mn, mx (rmn, rmx).
 template <int D, typename T, class Team>
@@ -904,9 +931,14 @@ __device__ void readoff_pair(const ConvertArgs &a, const Team &tm, bool fitter, 
     tm.sync();
   }
   double mnL = INFINITY, mxL = -INFINITY, rmnL = INFINITY, rmxL = -INFINITY;
-  team_convert_lanes<D>(t, p + S, a.didx, C, S, a.n, tm, pl, want ? blL : nullptr, mnL, mxL, rmnL, rmxL);
   double mnU = INFINITY, mxU = -INFINITY, rmnU = INFINITY, rmxU = -INFINITY;
-  team_convert_lanes<D>(t, p, a.didx, C, S, a.n, tm, pl, want ? blU : nullptr, mnU, mxU, rmnU, rmxU);
+  if constexpr (D == 1) {
+    team_corners_lanes(t, p + S, a.n, tm, want ? blL : nullptr, mnL, mxL, rmnL, rmxL);
+    team_corners_lanes(t, p, a.n, tm, want ? blU : nullptr, mnU, mxU, rmnU, rmxU);
+  } else {
+    team_convert_lanes<D>(t, p + S, a.didx, C, S, a.n, tm, pl, want ? blL : nullptr, mnL, mxL, rmnL, rmxL);
+    team_convert_lanes<D>(t, p, a.didx, C, S, a.n, tm, pl, want ? blU : nullptr, mnU, mxU, rmnU, rmxU);
+  }
   // maxima of: max U, -min L, and the remainders' max U, -min U, max L, -min L
   double ex[6] = {mxU, -mnL, rmxU, -rmnU, rmxL, -rmnL};
   tm.reduce(ex, OpMax());
@@ -927,6 +959,17 @@ __device__ void readoff_pair(const ConvertArgs &a, const Team &tm, bool fitter, 
   if (tm.tid == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted, true);
 }
 
+// Doubles of one wave's LDS slice: reduction rows, the tensor (degree 1:
+// its n + 1 coefficients only) and the two fits.
+template <int D>
+__host__ __device__ constexpr int wave_tensor_doubles(int C) {
+  return D == 1 ? kMaxInputs + 1 : C;
+}
+template <int D>
+__host__ __device__ constexpr int wave_slice_doubles(int C) {
+  return kRowScratch + wave_tensor_doubles<D>(C) + 2 * (kMaxInputs + 1);
+}
+
 // One wave per (box, neuron), one bound tensor at a time in the wave's LDS
 // slice.
 template <int D, typename T>
@@ -936,12 +979,13 @@ __global__ void __launch_bounds__(kBlock, 6) convert_wave_t(ConvertArgs a) {
   const int wv = threadIdx.x >> 6;
   const int C = (int)a.C;
   const int *pl = stage_prefixes(a, reinterpret_cast<int *>(lds));
-  double *tw = lds + (a.plist_len + 1) / 2 + (int64_t)wv * (kRowScratch + C + 2 * (kMaxInputs + 1));
+  double *tw = lds + (a.plist_len + 1) / 2 + (int64_t)wv * wave_slice_doubles<D>(C);
   const int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + wv;
   if (item >= a.nboxes * a.h) return;
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
   const WaveTeam tmw{tm.tid, tw};
-  readoff_pair<D, T>(a, tmw, true, tm.tid, tw + kRowScratch, tw + kRowScratch + C, pl, box, (int)(item % a.h));
+  readoff_pair<D, T>(a, tmw, true, tm.tid, tw + kRowScratch, tw + kRowScratch + wave_tensor_doubles<D>(C), pl, box,
+                     (int)(item % a.h));
 }
 
 // One block per (box, neuron) for tensors up to kSmallLds coefficients, one
@@ -1541,16 +1585,16 @@ static bool launch_ntree(const ConvertArgs &a, hipStream_t s, bool wave_team, hi
 
 template <typename T, int D>
 static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
-  // degree 1 tensors are read off densely (a wave per neuron does it in a
-  // few steps); the tree needs D >= 2 to pay for its levels
-  if (a.tree && D >= 2) {
+  // degree 1 tensors are read off at the box corners, a wave per neuron,
+  // whatever n; the tree needs D >= 2 to pay for its levels
+  if (D >= 2 && a.tree) {
     hipError_t err = hipSuccess;
     if (a.tune.conv_wave == 0 && launch_ntree<T, D, ntree_tile_axes(D)>(a, s, false, err)) return err;
     if (a.tune.conv_wave == 3 && launch_ntree<T, D, ntree_tile_axes(D)>(a, s, true, err)) return err;
   }
   const size_t plb = (size_t)((a.plist_len + 1) / 2) * sizeof(double);
-  if (a.C <= kWaveC && a.tune.conv_wave <= 1) {
-    const size_t lds = (size_t)(kBlock / 64) * (kRowScratch + a.C + 2 * (kMaxInputs + 1)) * sizeof(double) + plb;
+  if (D == 1 || (a.C <= kWaveC && a.tune.conv_wave <= 1)) {
+    const size_t lds = (size_t)(kBlock / 64) * wave_slice_doubles<D>((int)a.C) * sizeof(double) + plb;
     RET_IF(hipFuncSetAttribute((const void *)convert_wave_t<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
     ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4),
@@ -1846,6 +1890,7 @@ static size_t ntree_lds(const NTreePlan &tp, int n, int D, int teams) {
 }
 
 bool convert_tree(int n, int D) {
+  if (D == 1) return false;  // read off at the corners
   const int64_t C = tsize(n, D);
   if (C < 0 || use_small(C)) return false;
   return tree_plan(n, D, 1).lo >= 0;
@@ -1853,7 +1898,7 @@ bool convert_tree(int n, int D) {
 
 size_t convert_scratch_bytes(int n, int D, int h, int64_t nboxes) {
   const int64_t C = ipow(D + 1, n);
-  if (use_small(C)) return 0;
+  if (D == 1 || use_small(C)) return 0;
   if (tree_plan(n, D, nboxes * h * 2).lo >= 0)
     return align256(((size_t)nboxes * h * 2 + kTreeBlocks * (D + 1)) * sizeof(double)) +
            align256((size_t)nboxes * h * 2 * sizeof(double));
@@ -1869,7 +1914,7 @@ hipError_t launch_convert(const ConvertArgs &a_in, hipStream_t s) {
   a.gconv = gamma64((double)a.n * (a.D + 2) + 4 + a.gextra);
   a.gpre = gamma64(2.0 * a.hin + 6);
   const int D1 = a.D + 1;
-  if (a.D >= 1 && a.D <= 8 && ((a.C <= kWaveC && a.tune.conv_wave == 0) || use_small(a.C)))
+  if (a.D == 1 || (a.D >= 2 && a.D <= 8 && ((a.C <= kWaveC && a.tune.conv_wave == 0) || use_small(a.C))))
     return a.fp64 ? launch_convert_fixed<double>(a, s) : launch_convert_fixed<float>(a, s);
   if (a.C <= kWaveC) {
     const size_t lds = (D1 * D1 + (kBlock / 64) * 2 * a.C) * sizeof(double);

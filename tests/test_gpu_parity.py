@@ -248,6 +248,31 @@ def test_large_output_two_pass_fp32_and_fp64():
     _assert_fp32(g32, o, case.n_hidden)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_degree_one_tensors_at_many_inputs(precision):
+    """Degree-1 tensors are read off at the 2^n box corners whatever n:
+    n = 12 under the plain rule (its second layer at degree 2 in 12
+    variables), and n = 16, the most inputs, with plans of codes 0 and 1 that
+    keep every tensor at degree 1."""
+    case = wl.random_net_case([12, 6, 3], seed=81, n_boxes=2, half_width=0.5)
+    g = _bounds_gpu(case, precision=precision, sched="batched")
+    o = _oracle(case)
+    if precision == "fp64":
+        _assert_parity(g, o, 1e-9, case.n_hidden)
+    else:
+        _assert_fp32(g, o, case.n_hidden)
+    case = wl.random_net_case([16, 5, 4, 2], seed=82, n_boxes=3, half_width=0.5)
+    plan = np.random.default_rng(3).integers(0, 2, size=(case.n_boxes, case.n_hidden)).astype(np.int8)
+    g = _bounds_gpu(case, L=1, precision=precision, sched="batched", plan=plan)
+    o = _oracle(case, plan=plan)
+    assert np.array_equal(g["used_plan"], o["used_plan"])
+    assert (o["used_plan"] >= 0).any()
+    if precision == "fp64":
+        _assert_parity(g, o, 1e-9, case.n_hidden)
+    else:
+        _assert_fp32(g, o, case.n_hidden)
+
+
 # ------------------------------------------------- per-neuron degree plans
 # Codes stay <= L so the library's clamp to the plain degrees never acts and
 # the oracle sees the same plan.
