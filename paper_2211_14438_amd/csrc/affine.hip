@@ -202,15 +202,206 @@ __global__ void __launch_bounds__(kBlock) gemm_kernel(GemmArgs a) {
   }
 }
 
+// Tensors of at most 64 coefficients: one output coefficient per lane as
+// above, but G = 64 / C boxes share a wave (lanes g C .. g C + C - 1 hold box
+// g of the block's G), and the block's four waves take one quarter of the
+// inputs each, their sums added in wave order at the end. The inputs run
+// densely over k with a kind per (box, input) staged in LDS from the live
+// lists (0 none, 1 full, 2 degree-preserving prefix, 3 active in place), so
+// k and the weights stay uniform across the wave; an input a lane's box does
+// not use reads an in-bounds element and contributes an exact zero. The
+// per-lane order of the sums depends neither on MB nor on the box's place in
+// the block; the FP32 rounding sums are added over the box's coefficients in
+// index order.
+constexpr int kPackMaxC = 64;
+constexpr int kPackWaves = 4;
+constexpr int kPackKU = 4;
+
+__host__ __device__ inline int pack_groups(int64_t C) { return (int)(64 / C); }
+
+// Dynamic LDS: the block's weights W^T[k][m0 .. m0 + MB) (hin MB doubles),
+// the wave partials ((kPackWaves - 1) x 2 MB x 64 doubles, reused for the
+// rounding sums), then the kind table (G hin bytes).
+inline size_t pack_lds(int G, int hin, int MB) {
+  return ((size_t)hin * MB + (size_t)(kPackWaves - 1) * 2 * MB * 64) * sizeof(double) + (size_t)G * hin;
+}
+
+template <typename T, int MB>
+__global__ void __launch_bounds__(kPackWaves * 64) gemm_pack_kernel(GemmArgs a) {
+  extern __shared__ double pk_lds[];
+  const int C = (int)a.C, G = pack_groups(a.C), hin = a.hin;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane / C, c = lane - g * C;
+  // logical block: row chunk fastest, the row chunks of one box group on one XCD
+  const int nx = (a.h + MB - 1) / MB;
+  const int64_t lb = xcd_block(blockIdx.x, (int64_t)gridDim.x);
+  const int m0 = (int)(lb % nx) * MB;
+  const int64_t slot0 = lb / nx * G;
+  const int64_t bslot = slot0 + g;
+  const bool valid = g < G && bslot < a.nboxes;
+  double *wl = pk_lds;
+  double *part = wl + (size_t)hin * MB;
+  unsigned char *kind = reinterpret_cast<unsigned char *>(part + (size_t)(kPackWaves - 1) * 2 * MB * 64);
+  for (int i = threadIdx.x; i < G * hin; i += blockDim.x) kind[i] = 0;
+  // weights through LDS: one uniform read per row instead of scalar loads
+  // whose latency each step would wait for
+  for (int i = threadIdx.x; i < hin * MB; i += blockDim.x) wl[i] = a.WT[(int64_t)(i / MB) * a.hp + m0 + i % MB];
+  __syncthreads();
+  for (int gg = 0; gg < G && slot0 + gg < a.nboxes; ++gg) {
+    const int64_t bx = a.bids ? a.bids[slot0 + gg] : slot0 + gg;
+    const int *lv = a.live + bx * a.live_ld;
+    for (int t = 0; t < 3; ++t) {
+      const int cnt = lv[t];
+      for (int i = threadIdx.x; i < cnt; i += blockDim.x) kind[gg * hin + lv[3 + t * hin + i]] = (unsigned char)(t + 1);
+    }
+  }
+  __syncthreads();
+  const int64_t box = a.bids ? a.bids[valid ? bslot : slot0] : (valid ? bslot : slot0);
+  const T *X = reinterpret_cast<const T *>(a.post) + box * a.slot_in;
+  const T *Xa = reinterpret_cast<const T *>(a.act) + box * a.act_slot;
+  const unsigned char *kd = kind + (valid ? g : 0) * hin;
+  const int Cs = (int)a.Cs, Ca = (int)a.Cact;
+  const int kq = (hin + kPackWaves - 1) / kPackWaves;
+  const int k0 = min(hin, w * kq), k1 = min(hin, k0 + kq);
+  double accM[MB], accR[MB];
+#pragma unroll
+  for (int mm = 0; mm < MB; ++mm) accM[mm] = accR[mm] = 0.0;
+  // loads of kPackKU inputs from kb on; inputs the lane's box does not use,
+  // and those past k1, read an in-bounds element marked out
+  auto load = [&](int kb, T (&u)[kPackKU], T (&l)[kPackKU], bool (&in)[kPackKU]) {
+#pragma unroll
+    for (int q = 0; q < kPackKU; ++q) {
+      const int k = kb + q;
+      const bool live = k < k1;
+      const int kk = live && valid ? kd[k] : 0;
+      const int lim = kk == 1 ? C : kk == 2 ? Cs : kk == 3 ? Ca : 0;
+      in[q] = c < lim;
+      const bool ac = kk == 3;
+      const int kc = live ? k : k0;
+      const T *base = ac ? Xa + (int64_t)kc * 2 * Ca : X + (int64_t)kc * 2 * C;
+      const int off = in[q] ? c : 0;
+      u[q] = base[off];
+      l[q] = base[off + (ac ? Ca : C)];
+    }
+  };
+  T u[kPackKU], l[kPackKU];
+  bool in[kPackKU];
+  if (k0 < k1) load(k0, u, l, in);
+  for (int kb = k0; kb < k1; kb += kPackKU) {
+    T un[kPackKU], ln[kPackKU];
+    bool inn[kPackKU];
+    const bool more = kb + kPackKU < k1;
+    if (more) load(kb + kPackKU, un, ln, inn);
+#pragma unroll
+    for (int q = 0; q < kPackKU; ++q) {
+      if (kb + q < k1) {
+        const double uu = in[q] ? (double)u[q] : 0.0, ll = in[q] ? (double)l[q] : 0.0;
+        const double M = (uu + ll) * 0.5;
+        const double R = (uu - ll) * 0.5;
+        const double *wk = wl + (kb + q) * MB;
+#pragma unroll
+        for (int mm = 0; mm < MB; ++mm) {
+          accM[mm] = fma(wk[mm], M, accM[mm]);
+          accR[mm] = fma(fabs(wk[mm]), R, accR[mm]);
+        }
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int q = 0; q < kPackKU; ++q) {
+        u[q] = un[q];
+        l[q] = ln[q];
+        in[q] = inn[q];
+      }
+    }
+  }
+  // the quarters' sums, added in wave order by wave 0
+  if (w > 0) {
+    double *pw = part + (int64_t)(w - 1) * 2 * MB * 64;
+#pragma unroll
+    for (int mm = 0; mm < MB; ++mm) {
+      pw[(2 * mm) * 64 + lane] = accM[mm];
+      pw[(2 * mm + 1) * 64 + lane] = accR[mm];
+    }
+  }
+  __syncthreads();
+  if (w == 0) {
+    for (int v = 0; v < kPackWaves - 1; ++v) {
+      const double *pw = part + (int64_t)v * 2 * MB * 64;
+#pragma unroll
+      for (int mm = 0; mm < MB; ++mm) {
+        accM[mm] += pw[(2 * mm) * 64 + lane];
+        accR[mm] += pw[(2 * mm + 1) * 64 + lane];
+      }
+    }
+  }
+  __syncthreads();
+  const bool track = a.rpart != nullptr;
+  if (w == 0) {
+    T *Y = reinterpret_cast<T *>(a.pre) + box * a.slot_out;
+#pragma unroll
+    for (int mm = 0; mm < MB; ++mm) {
+      const int m = m0 + mm;
+      double ru = 0.0, rl = 0.0;
+      if (valid && m < a.h) {
+        const double bias = c == 0 ? a.b[m] : 0.0;
+        const double yu = accM[mm] + accR[mm] + bias;
+        const double yl = accM[mm] - accR[mm] + bias;
+        const T su = (T)yu, sl = (T)yl;
+        Y[(int64_t)m * 2 * C + c] = su;
+        Y[(int64_t)m * 2 * C + C + c] = sl;
+        ru = fabs((double)su - yu);
+        rl = fabs((double)sl - yl);
+      }
+      if (track) {
+        part[(2 * mm) * 64 + lane] = ru;
+        part[(2 * mm + 1) * 64 + lane] = rl;
+      }
+    }
+  }
+  if (!track) return;
+  __syncthreads();
+  // per (box, row, bound): its coefficients' rounding in index order
+  for (int t = threadIdx.x; t < G * MB * 2; t += blockDim.x) {
+    const int gg = t / (2 * MB), r = t - gg * 2 * MB, mm = r >> 1, sd = r & 1;
+    if (slot0 + gg >= a.nboxes || m0 + mm >= a.h) continue;
+    double v = 0.0;
+    for (int q = 0; q < C; ++q) v += part[r * 64 + gg * C + q];
+    const int64_t bx = a.bids ? a.bids[slot0 + gg] : slot0 + gg;
+    a.rpart[bx * a.rpart_slot + ((int64_t)(m0 + mm) * 2 + sd) * a.cblocks] = v;
+  }
+}
+
 int64_t gemm_cblocks(int64_t C) { return (C + kBlock - 1) / kBlock; }
+
+template <int MB>
+static hipError_t launch_gemm_pack(const GemmArgs &a, hipStream_t s) {
+  const int G = pack_groups(a.C);
+  const size_t lds = pack_lds(G, a.hin, MB);
+  const int64_t blocks = (int64_t)((a.h + MB - 1) / MB) * ((a.nboxes + G - 1) / G);
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  dim3 grid((unsigned)blocks);
+  if (a.fp64) {
+    RET_IF(hipFuncSetAttribute((const void *)gemm_pack_kernel<double, MB>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((gemm_pack_kernel<double, MB>), grid, dim3(kPackWaves * 64), lds, s, a);
+  } else {
+    RET_IF(hipFuncSetAttribute((const void *)gemm_pack_kernel<float, MB>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((gemm_pack_kernel<float, MB>), grid, dim3(kPackWaves * 64), lds, s, a);
+  }
+  return hipGetLastError();
+}
 
 template <int MB, int KU>
 static hipError_t launch_gemm_mb(const GemmArgs &a, hipStream_t s) {
   dim3 grid((a.h + MB - 1) / MB, (unsigned)a.cblocks, (unsigned)a.nboxes);
+  // one coefficient block: only the waves that hold coefficients
+  const unsigned threads = a.C < kBlock ? (unsigned)((a.C + 63) / 64 * 64) : kBlock;
   if (a.fp64)
-    hipLaunchKernelGGL((gemm_kernel<double, MB, KU>), grid, dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((gemm_kernel<double, MB, KU>), grid, dim3(threads), 0, s, a);
   else
-    hipLaunchKernelGGL((gemm_kernel<float, MB, KU>), grid, dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((gemm_kernel<float, MB, KU>), grid, dim3(threads), 0, s, a);
   return hipGetLastError();
 }
 
@@ -222,6 +413,11 @@ hipError_t launch_gemm(const GemmArgs &a0, hipStream_t s) {
   if (a.hp % 16 != 0 || a.hp < a.h || !a.live || a.Cs > a.C || !a.act) return hipErrorInvalidValue;
   ProfScope ps(kProfGemm, s, (double)a.nboxes * (2.0 * a.hin + 2.0 * a.h) * a.C * (a.fp64 ? 8 : 4),
                4.0 * a.nboxes * a.h * a.hin * a.C);
+  if (a.C <= kPackMaxC && pack_lds(pack_groups(a.C), a.hin, 16) <= device_lds_limit()) {
+    if (a.h <= 4) return launch_gemm_pack<4>(a, s);
+    if (a.h <= 8 || a.tune.gemm_wide != 1) return launch_gemm_pack<8>(a, s);
+    return launch_gemm_pack<16>(a, s);
+  }
   if (a.h <= 4) {
     switch (a.tune.gemm_narrow) {
       case 1: return launch_gemm_mb<4, 4>(a, s);

@@ -15,6 +15,17 @@ constexpr int kMaxInputs = 16;   // n
 constexpr int kMaxOrder = 8;     // ReLU approximation order L
 constexpr int kBlock = 256;      // threads per block of the streaming kernels
 
+// Blocks go to the chip's 8 XCDs round-robin (hardware block b to XCD b % 8),
+// each XCD with its own L2. xcd_block maps a hardware block index to a
+// logical one under which consecutive logical blocks (those sharing inputs)
+// run on one XCD: the first 8 floor(n / 8) of n blocks are regrouped, the
+// tail keeps its index (a bijection of [0, n)).
+__device__ inline int64_t xcd_block(int64_t b, int64_t n) {
+  const int64_t full = n / 8 * 8;
+  if (b >= full) return b;
+  return (b % 8) * (full / 8) + b / 8;
+}
+
 void set_error(const char *fmt, ...);
 
 #define BERN_HIP_TRY(expr)                                                        \
@@ -127,6 +138,7 @@ struct ProfScope {
 // Kernel variants an autotuner may pick; 0 everywhere is the built-in choice.
 struct Tune {
   int gemm_wide = 0;    // layers wider than 8: 0 16 rows x 2 inputs/step, 1 16x4, 2 8x2, 3 8x4
+                        // (tensors of <= 64 coefficients, packed: 1 16 rows, else 8)
   int gemm_narrow = 0;  // layers of <= 4 neurons: 0 4 rows x 8 inputs/step, 1 4x4, 2 4x16
   int conv_block = 0;   // threads of the block-per-neuron conversion: 0 by LDS use, 1 256, 2 512, 3 1024
   int conv_wave = 0;    // per-neuron read-off: 0 tree, 1 dense (one wave per neuron up to 1024
