@@ -115,8 +115,10 @@ struct Plan {
   size_t elem;
   std::vector<int64_t> nbx;         // compose blocks per item, hidden layers
   // per-box bytes of each region
-  size_t recs, arenaA, arenaB, conv, horner, flags, gpart, cpart, live;
-  size_t per_box() const { return 2 * recs + 2 * arenaA + arenaB + conv + horner + flags + gpart + cpart + live; }
+  size_t recs, rad, arenaA, arenaB, conv, horner, flags, gpart, cpart, live;
+  size_t per_box() const {
+    return 2 * recs + 2 * rad + 2 * arenaA + arenaB + conv + horner + flags + gpart + cpart + live;
+  }
 };
 
 }  // namespace bern
@@ -218,6 +220,7 @@ static bern_status plan_net(const bern_net *net, const bern_opts *o, Plan &p) {
   // the predicted code of every hidden neuron
   p.flags = align256(sizeof(int) * (2 + 2 * (size_t)p.H) + (size_t)net->nh);
   p.live = align256(sizeof(int) * (3 + 3 * (size_t)net->hmax));
+  p.rad = align256(sizeof(double) * 4 * (size_t)net->hmax);
   return BERN_OK;
 }
 
@@ -486,6 +489,10 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
   NeuronRec *recbuf[2];
   recbuf[0] = reinterpret_cast<NeuronRec *>(cur); cur += p.recs * B;
   recbuf[1] = reinterpret_cast<NeuronRec *>(cur); cur += p.recs * B;
+  // dense copies of the records' post radii, alternating like the records
+  double *radbuf[2];
+  radbuf[0] = reinterpret_cast<double *>(cur); cur += p.rad * B;
+  radbuf[1] = reinterpret_cast<double *>(cur); cur += p.rad * B;
   double *gpart = reinterpret_cast<double *>(cur); cur += p.gpart * B;
   double *cpart = reinterpret_cast<double *>(cur); cur += p.cpart * B;
   // pre-activation arenas alternate between layers: the affine map of layer
@@ -590,6 +597,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       c.layer = i;
       c.hin = hin;
       c.prev = prev;
+      c.prad = radbuf[(i + 1) & 1];
       c.W = net->W64 + net->woff[i];
       c.b = net->b64 + net->boff[i];
       c.box_lo = box_lo;
@@ -706,6 +714,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       m.pre = Aa[i & 1];
       m.post = Bp;
       m.recs = recs;
+      m.rad = p.fp64 ? nullptr : radbuf[i & 1];
       m.fp64 = p.fp64 ? 1 : 0;
       m.scratch = horner;
       m.scratch_bytes = p.horner * B;

@@ -213,6 +213,7 @@ struct ConvertArgs {
   int layer;                      // 0 = first layer (closed form), else GEMM output
   int hin;
   const NeuronRec *prev;          // [B][hin] records of the previous layer (layer > 0)
+  const double *prad;             // [B][hin][4] their padU, padL, pl1U, pl1L (FP32 mode, layer > 0)
   const double *W, *b;            // this layer's W [h][hin] and b [h] (FP64)
   const double *box_lo, *box_hi;  // [B][n] (layer 0)
   const double *rpart;            // GEMM rounding partials, per wave box (stride rpart_slot):
@@ -273,6 +274,8 @@ struct ComposeArgs {
   void *scratch;                  // Horner intermediates for orders >= 3
   size_t scratch_bytes;
   int *live;                      // per box input lists for the next affine map (GemmArgs::live)
+  double *rad;                    // FP32 mode: [B][h][4] copies of the records' padU, padL, pl1U,
+                                  // pl1L, read densely by the next layer's radii
   int64_t live_ld;
 };
 hipError_t launch_compose(const ComposeArgs &a, hipStream_t s);

@@ -604,6 +604,13 @@ __global__ void post_radii_kernel(ComposeArgs a, NeuronRec *recs) {
       r.pl1L = l1;
     }
   }
+  if (a.rad) {
+    double *q = a.rad + (wave_box(a, item / a.h) * a.h + item % a.h) * 4;
+    q[0] = r.padU;
+    q[1] = r.padL;
+    q[2] = r.pl1U;
+    q[3] = r.pl1L;
+  }
 }
 
 // ------------------------------------------------ plain product kernel

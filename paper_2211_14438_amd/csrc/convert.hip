@@ -165,15 +165,15 @@ __device__ void pre_radii(const ConvertArgs &a, int64_t box, int j, const void *
   double sU = 0.0, sL = 0.0, g = 0.0;
   for (int k = tid; k < a.hin; k += nt) {
     const double wk = a.W[(int64_t)j * a.hin + k];
-    const NeuronRec &P = a.prev[box * a.hin + k];
+    const double *P = a.prad + (box * a.hin + k) * 4;  // padU, padL, pl1U, pl1L
     if (wk >= 0.0) {
-      sU += wk * P.padU;
-      sL += wk * P.padL;
+      sU += wk * P[0];
+      sL += wk * P[1];
     } else {
-      sU -= wk * P.padL;
-      sL -= wk * P.padU;
+      sU -= wk * P[1];
+      sL -= wk * P[0];
     }
-    g += fabs(wk) * (P.pl1U + P.pl1L);
+    g += fabs(wk) * (P[2] + P[3]);
   }
   double rU = 0.0, rL = 0.0;
   const double *rp = a.rpart + box * a.rpart_slot + (int64_t)j * 2 * a.cblocks;
@@ -202,15 +202,16 @@ __device__ void pre_radii_team(const ConvertArgs &a, int64_t box, int j, const T
   double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // sU, sL, g, rU, rL
   for (int k = tm.tid; k < a.hin; k += tm.nt) {
     const double wk = a.W[(int64_t)j * a.hin + k];
-    const NeuronRec &P = a.prev[box * a.hin + k];
+    // the previous layer's radii from their dense copy: 32 bytes per input
+    const double4 P = *reinterpret_cast<const double4 *>(a.prad + (box * a.hin + k) * 4);
     if (wk >= 0.0) {
-      v[0] += wk * P.padU;
-      v[1] += wk * P.padL;
+      v[0] += wk * P.x;
+      v[1] += wk * P.y;
     } else {
-      v[0] -= wk * P.padL;
-      v[1] -= wk * P.padU;
+      v[0] -= wk * P.y;
+      v[1] -= wk * P.x;
     }
-    v[2] += fabs(wk) * (P.pl1U + P.pl1L);
+    v[2] += fabs(wk) * (P.z + P.w);
   }
   const double *rp = a.rpart + box * a.rpart_slot + (int64_t)j * 2 * a.cblocks;
   for (int64_t cb = tm.tid; cb < a.cblocks; cb += tm.nt) {
