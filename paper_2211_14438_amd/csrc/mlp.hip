@@ -195,68 +195,86 @@ __global__ void __launch_bounds__(256) features_kernel(LearnArgs a) {
   for (int q = 0; q < kF; ++q) a.feat[(box * a.nh + a.noff + j) * kF + q] = f[q];
 }
 
-// Features -> BF16 MLP -> class, four threads per (box, neuron): the first
-// reads the features, each computes the first layer and a quarter of the
-// second layer's units with their share of the output layer, and the four
-// shares are added in a fixed order. Stable neurons get class -1 (their rule
-// does not depend on the predictor).
-__global__ void __launch_bounds__(1024) learned_classes_kernel(LearnArgs a) {
+// Features -> BF16 MLP -> class. A block takes 64 (box, neuron) items: one
+// thread each reads the features, and the unstable items (the only ones
+// whose rule depends on the predictor; the others get class -1) are listed
+// and taken four threads each: every thread computes the first layer and a
+// quarter of the second layer's units with their share of the output layer,
+// and the four shares are added in a fixed order.
+constexpr int kClassItems = 64;  // items per block of learned_classes_kernel (4 threads each)
+
+__global__ void __launch_bounds__(4 * kClassItems) learned_classes_kernel(LearnArgs a) {
   __shared__ float w[kParams];
-  __shared__ float fs[256][kF];
+  __shared__ float fs[kClassItems][kF];
+  __shared__ int ulist[kClassItems];  // the block's unstable items (slots), in no fixed order
+  __shared__ int ucount;
+  if (threadIdx.x == 0) ucount = 0;
   for (int i = threadIdx.x; i < kParams; i += blockDim.x)
     w[i] = i >= kOffW1 ? bf16_round(a.params[i]) : a.params[i];
-  const int64_t it = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 2;
-  const int k = threadIdx.x & 3, slot = threadIdx.x >> 2;
-  const bool valid = it < a.nboxes * a.h;
-  const int64_t box = valid ? (a.bids ? a.bids[it / a.h] : it / a.h) : 0;
-  const int j = valid ? (int)(it % a.h) : 0;
-  bool unstable = false;
-  if (valid) {
-    const NeuronRec &r = a.recs[box * a.h + j];
-    unstable = r.lo < 0.0 && r.hi > 0.0;
-    if (k == 0) {
+  __syncthreads();
+  // features of the block's items, one thread each; only unstable neurons
+  // (lo < 0 < hi) go through the network
+  if (threadIdx.x < kClassItems) {
+    const int slot = threadIdx.x;
+    const int64_t it = (int64_t)blockIdx.x * kClassItems + slot;
+    if (it < a.nboxes * a.h) {
+      const int64_t box = a.bids ? a.bids[it / a.h] : it / a.h;
+      const int j = (int)(it % a.h);
+      const NeuronRec &r = a.recs[box * a.h + j];
       float f[kF];
       neuron_features(a, r, j, f);
       for (int q = 0; q < kF; ++q) fs[slot][q] = f[q];
       if (a.feat)
         for (int q = 0; q < kF; ++q) a.feat[(box * a.nh + a.noff + j) * kF + q] = f[q];
-      if (!unstable) a.codes[box * a.nh + a.noff + j] = -1;
+      if (r.lo < 0.0 && r.hi > 0.0)
+        ulist[atomicAdd(&ucount, 1)] = slot;
+      else
+        a.codes[box * a.nh + a.noff + j] = -1;
     }
   }
   __syncthreads();
-  if (!valid || !unstable) return;
-  float x[kF], h1[kH], z[kC];
-  for (int q = 0; q < kF; ++q) x[q] = bf16_round((fs[slot][q] - w[kOffMean + q]) / w[kOffStd + q]);
-  for (int o = 0; o < kH; ++o) {
-    float s = w[kOffB1 + o];
-    for (int q = 0; q < kF; ++q) s = fmaf(w[kOffW1 + o * kF + q], x[q], s);
-    h1[o] = bf16_round(fmaxf(s, 0.f));
-  }
-  for (int c = 0; c < kC; ++c) z[c] = k == 0 ? w[kOffB3 + c] : 0.f;
-  // this thread's quarter of the hidden units, four at a time
-  for (int o0 = k * (kH / 4); o0 < (k + 1) * (kH / 4); o0 += 4) {
-    float s[4];
+  // four threads per unstable neuron; each neuron's sums do not depend on
+  // where it sits in the list
+  const int k = threadIdx.x & 3, u = threadIdx.x >> 2;
+  if (u < ucount) {
+    const int slot = ulist[u];
+    const int64_t it = (int64_t)blockIdx.x * kClassItems + slot;
+    const int64_t box = a.bids ? a.bids[it / a.h] : it / a.h;
+    const int j = (int)(it % a.h);
+    float x[kF], h1[kH], z[kC];
+    for (int q = 0; q < kF; ++q) x[q] = bf16_round((fs[slot][q] - w[kOffMean + q]) / w[kOffStd + q]);
+    for (int o = 0; o < kH; ++o) {
+      float s = w[kOffB1 + o];
+      for (int q = 0; q < kF; ++q) s = fmaf(w[kOffW1 + o * kF + q], x[q], s);
+      h1[o] = bf16_round(fmaxf(s, 0.f));
+    }
+    for (int c = 0; c < kC; ++c) z[c] = k == 0 ? w[kOffB3 + c] : 0.f;
+    // this thread's quarter of the hidden units, four at a time
+    for (int o0 = k * (kH / 4); o0 < (k + 1) * (kH / 4); o0 += 4) {
+      float s[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) s[u] = w[kOffB2 + o0 + u];
-    for (int i = 0; i < kH; ++i)
+      for (int v = 0; v < 4; ++v) s[v] = w[kOffB2 + o0 + v];
+      for (int i = 0; i < kH; ++i)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) s[u] = fmaf(w[kOffW2 + (o0 + u) * kH + i], h1[i], s[u]);
+        for (int v = 0; v < 4; ++v) s[v] = fmaf(w[kOffW2 + (o0 + v) * kH + i], h1[i], s[v]);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const float hu = bf16_round(fmaxf(s[u], 0.f));
-      for (int c = 0; c < kC; ++c) z[c] = fmaf(w[kOffW3 + c * kH + o0 + u], hu, z[c]);
+      for (int v = 0; v < 4; ++v) {
+        const float hu = bf16_round(fmaxf(s[v], 0.f));
+        for (int c = 0; c < kC; ++c) z[c] = fmaf(w[kOffW3 + c * kH + o0 + v], hu, z[c]);
+      }
+    }
+    // (z0 + z1) + (z2 + z3) over the neuron's four threads
+    for (int c = 0; c < kC; ++c) {
+      z[c] += __shfl_xor(z[c], 1, 64);
+      z[c] += __shfl_xor(z[c], 2, 64);
+    }
+    if (k == 0) {
+      int best = 0;
+      for (int c = 1; c < kC; ++c)
+        if (z[c] > z[best]) best = c;
+      a.codes[box * a.nh + a.noff + j] = (int8_t)best;
     }
   }
-  // (z0 + z1) + (z2 + z3) over the neuron's four threads
-  for (int c = 0; c < kC; ++c) {
-    z[c] += __shfl_xor(z[c], 1, 64);
-    z[c] += __shfl_xor(z[c], 2, 64);
-  }
-  if (k != 0) return;
-  int best = 0;
-  for (int c = 1; c < kC; ++c)
-    if (z[c] > z[best]) best = c;
-  a.codes[box * a.nh + a.noff + j] = (int8_t)best;
 }
 
 // Per box and layer: the layer is stored at the largest degree any of its
@@ -290,7 +308,8 @@ __global__ void __launch_bounds__(256) learned_rules_kernel(LearnArgs a) {
 hipError_t launch_learned_rules(const LearnArgs &a, hipStream_t s) {
   {
     ProfScope ps(kProfPredictor, s, 0.0);
-    hipLaunchKernelGGL(learned_classes_kernel, dim3((unsigned)((a.nboxes * a.h + 255) / 256)), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(learned_classes_kernel, dim3((unsigned)((a.nboxes * a.h + kClassItems - 1) / kClassItems)),
+                       dim3(4 * kClassItems), 0, s, a);
     RET_IF(hipGetLastError());
   }
   ProfScope ps(kProfPredictor, s, 0.0);
