@@ -821,33 +821,6 @@ __device__ void wave_fit(const T *p, const int *didx, int S, int n, int lane, do
   }
 }
 
-// Degree 1 (an affine polynomial a_0 + sum_a a_{1+a} t_a): the Bernstein
-// coefficients at per-variable degree 1 are its values at the 2^n box
-// corners, evaluated directly (corner K: axis a's bit at n-1-a), with the
-// lane's extrema and, with a fit bl, remainder extrema; no dense tensor.
-template <typename T, class Team>
-__device__ void team_corners_lanes(double *t, const T *p, int n, const Team &tm, const double *bl, double &mn,
-                                   double &mx, double &rmn, double &rmx) {
-  for (int i = tm.tid; i <= n; i += tm.nt) t[i] = (double)p[i];
-  tm.sync();
-  const int C = 1 << n;
-  for (int K = tm.tid; K < C; K += tm.nt) {
-    double v = t[0], l = bl ? bl[0] : 0.0;
-    for (int ax = 0; ax < n; ++ax) {
-      const bool one = (K >> (n - 1 - ax)) & 1;
-      if (one) v += t[1 + ax];
-      if (bl) l = fma(bl[1 + ax], one ? 0.5 : -0.5, l);
-    }
-    mn = fmin(mn, v);
-    mx = fmax(mx, v);
-    if (bl) {
-      rmn = fmin(rmn, v - l);
-      rmx = fmax(rmx, v - l);
-    }
-  }
-  tm.sync();
-}
-
 // team_convert without its reductions: the lane's own extrema (and, with a
 // fit, remainder extrema) are folded into mn, mx (rmn, rmx).
 template <int D, typename T, class Team>
@@ -932,14 +905,9 @@ __device__ void readoff_pair(const ConvertArgs &a, const Team &tm, bool fitter, 
     tm.sync();
   }
   double mnL = INFINITY, mxL = -INFINITY, rmnL = INFINITY, rmxL = -INFINITY;
+  team_convert_lanes<D>(t, p + S, a.didx, C, S, a.n, tm, pl, want ? blL : nullptr, mnL, mxL, rmnL, rmxL);
   double mnU = INFINITY, mxU = -INFINITY, rmnU = INFINITY, rmxU = -INFINITY;
-  if constexpr (D == 1) {
-    team_corners_lanes(t, p + S, a.n, tm, want ? blL : nullptr, mnL, mxL, rmnL, rmxL);
-    team_corners_lanes(t, p, a.n, tm, want ? blU : nullptr, mnU, mxU, rmnU, rmxU);
-  } else {
-    team_convert_lanes<D>(t, p + S, a.didx, C, S, a.n, tm, pl, want ? blL : nullptr, mnL, mxL, rmnL, rmxL);
-    team_convert_lanes<D>(t, p, a.didx, C, S, a.n, tm, pl, want ? blU : nullptr, mnU, mxU, rmnU, rmxU);
-  }
+  team_convert_lanes<D>(t, p, a.didx, C, S, a.n, tm, pl, want ? blU : nullptr, mnU, mxU, rmnU, rmxU);
   // maxima of: max U, -min L, and the remainders' max U, -min U, max L, -min L
   double ex[6] = {mxU, -mnL, rmxU, -rmnU, rmxL, -rmnL};
   tm.reduce(ex, OpMax());
@@ -960,16 +928,9 @@ __device__ void readoff_pair(const ConvertArgs &a, const Team &tm, bool fitter, 
   if (tm.tid == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted, true);
 }
 
-// Doubles of one wave's LDS slice: reduction rows, the tensor (degree 1:
-// its n + 1 coefficients only) and the two fits.
-template <int D>
-__host__ __device__ constexpr int wave_tensor_doubles(int C) {
-  return D == 1 ? kMaxInputs + 1 : C;
-}
-template <int D>
-__host__ __device__ constexpr int wave_slice_doubles(int C) {
-  return kRowScratch + wave_tensor_doubles<D>(C) + 2 * (kMaxInputs + 1);
-}
+// Doubles of one wave's LDS slice: reduction rows, the tensor and the two
+// fits.
+__host__ __device__ constexpr int wave_slice_doubles(int C) { return kRowScratch + C + 2 * (kMaxInputs + 1); }
 
 // One wave per (box, neuron), one bound tensor at a time in the wave's LDS
 // slice.
@@ -980,13 +941,12 @@ __global__ void __launch_bounds__(kBlock, 6) convert_wave_t(ConvertArgs a) {
   const int wv = threadIdx.x >> 6;
   const int C = (int)a.C;
   const int *pl = stage_prefixes(a, reinterpret_cast<int *>(lds));
-  double *tw = lds + (a.plist_len + 1) / 2 + (int64_t)wv * wave_slice_doubles<D>(C);
+  double *tw = lds + (a.plist_len + 1) / 2 + (int64_t)wv * wave_slice_doubles(C);
   const int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + wv;
   if (item >= a.nboxes * a.h) return;
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
   const WaveTeam tmw{tm.tid, tw};
-  readoff_pair<D, T>(a, tmw, true, tm.tid, tw + kRowScratch, tw + kRowScratch + wave_tensor_doubles<D>(C), pl, box,
-                     (int)(item % a.h));
+  readoff_pair<D, T>(a, tmw, true, tm.tid, tw + kRowScratch, tw + kRowScratch + C, pl, box, (int)(item % a.h));
 }
 
 // One block per (box, neuron) for tensors up to kSmallLds coefficients, one
@@ -1001,6 +961,132 @@ __global__ void __launch_bounds__(1024) convert_block_t(ConvertArgs a) {
   const int64_t item = blockIdx.x;
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
   readoff_pair<D, T>(a, tm, threadIdx.x < 64, (int)(threadIdx.x & 63), t, t + a.C, pl, box, (int)(item % a.h));
+}
+
+// Degree 1 (every first hidden layer, and neurons whose plan keeps degree
+// 1): an affine polynomial a_0 + sum_a a_{1+a} t_a, whose per-variable
+// degree-1 Bernstein coefficients are its values at the 2^n box corners. All
+// the read-off needs is then in closed form over the n + 1 stored
+// coefficients: the extrema a_0 + sum_a min(a_{1+a}, 0) and
+// a_0 + sum_a max(a_{1+a}, 0); the least-squares fit of the corner values,
+// beta_a = a_{1+a} and beta_0 = a_0 + sum_a a_{1+a} / 2 (the closed form of
+// the fit below at degree 1); and its remainders, the same constant
+// a_0 - beta_0 + sum_a beta_a / 2 at every corner (zero up to rounding). A
+// team of kAffLanes lanes per neuron, several neurons per wave.
+constexpr int kAffLanes = 16;
+
+__device__ __forceinline__ double aff_sum(double v) {
+#pragma unroll
+  for (int m = kAffLanes / 2; m > 0; m >>= 1) v += __shfl_xor(v, m, kAffLanes);
+  return v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) convert_affine_kernel(ConvertArgs a) {
+  const int l = threadIdx.x % kAffLanes;
+  const int64_t item = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kAffLanes;
+  if (item >= a.nboxes * a.h) return;  // whole teams leave together
+  const int S = (int)a.S;
+  const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
+  const int j = (int)(item % a.h);
+  const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + (int64_t)j * 2 * a.S;
+  // the lane's coefficients: indices l and l + kAffLanes (n + 1 <= 17)
+  double u[2] = {0.0, 0.0}, w[2] = {0.0, 0.0};
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int i = l + r * kAffLanes;
+    if (i < S) {
+      u[r] = (double)p[i];
+      w[r] = (double)p[S + i];
+    }
+  }
+  double epsU = 0.0, epsL = 0.0;
+  if (!a.fp64) {
+    if (a.layer == 0) {
+      pre_radii(a, box, j, a.pre, 0, 1, [](double v) { return v; }, epsU, epsL);
+    } else {
+      double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // sU, sL, g, rU, rL
+      for (int k = l; k < a.hin; k += kAffLanes) {
+        const double wk = a.W[(int64_t)j * a.hin + k];
+        const double4 P = *reinterpret_cast<const double4 *>(a.prad + (box * a.hin + k) * 4);
+        if (wk >= 0.0) {
+          v[0] += wk * P.x;
+          v[1] += wk * P.y;
+        } else {
+          v[0] -= wk * P.y;
+          v[1] -= wk * P.x;
+        }
+        v[2] += fabs(wk) * (P.z + P.w);
+      }
+      const double *rp = a.rpart + box * a.rpart_slot + (int64_t)j * 2 * a.cblocks;
+      for (int64_t cb = l; cb < a.cblocks; cb += kAffLanes) {
+        v[3] += rp[cb];
+        v[4] += rp[a.cblocks + cb];
+      }
+#pragma unroll
+      for (int q = 0; q < 5; ++q) v[q] = aff_sum(v[q]);
+      const double gg = a.gpre * (v[2] + fabs(a.b[j]));
+      epsU = (v[0] + gg + v[3]) * kPadSafety;
+      epsL = (v[1] + gg + v[4]) * kPadSafety;
+    }
+  }
+  // l1 norms, extrema, fit constants: lane l's share of each sum
+  double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // l1U, l1L, max U, min L, beta0 U, beta0 L
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int i = l + r * kAffLanes;
+    s[0] += fabs(u[r]);
+    s[1] += fabs(w[r]);
+    const bool c0 = i == 0;
+    s[2] += c0 ? u[r] : fmax(u[r], 0.0);
+    s[3] += c0 ? w[r] : fmin(w[r], 0.0);
+    s[4] += c0 ? u[r] : 0.5 * u[r];
+    s[5] += c0 ? w[r] : 0.5 * w[r];
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) s[q] = aff_sum(s[q]);
+  const double l1U = s[0], l1L = s[1];
+  const double lo = side_lo(a, s[3], l1L, epsL), hi = side_hi(a, s[2], l1U, epsU);
+  const bool want = wants_fit(a, box, j);
+  const bool fitted = want && (a.fits || (lo < 0.0 && hi > 0.0));
+  double fx[4] = {0.0, 0.0, 0.0, 0.0};  // rmaxU, rminU, rmaxL, rminL
+  if (fitted) {
+    // the remainder constant: a_0 - beta_0 + sum_a beta_a / 2
+    double c[2] = {0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const bool c0 = l + r * kAffLanes == 0;
+      c[0] += c0 ? u[r] - s[4] : 0.5 * u[r];
+      c[1] += c0 ? w[r] - s[5] : 0.5 * w[r];
+    }
+    c[0] = aff_sum(c[0]);
+    c[1] = aff_sum(c[1]);
+    fx[0] = fx[1] = c[0];
+    fx[2] = fx[3] = c[1];
+  }
+  if (a.mode == 0) {  // the fits (beta_0, then beta_a = a_{1+a}), or zeros
+    NeuronRec &rec = a.recs[box * a.h + j];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int q = l + r * kAffLanes;
+      if (q <= kMaxInputs) {
+        const bool on = fitted && q < S;
+        rec.fitU[q] = on ? (q == 0 ? s[4] : u[r]) : 0.0;
+        rec.fitL[q] = on ? (q == 0 ? s[5] : w[r]) : 0.0;
+      }
+    }
+  }
+  if (l == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted, true);
+}
+
+template <typename T>
+static hipError_t launch_affine(const ConvertArgs &a, hipStream_t s) {
+  ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4),
+               (double)a.nboxes * a.h * 2 * a.n * a.C * (a.D + 2));
+  const int64_t teams = a.nboxes * a.h;
+  const int64_t blocks = (teams * kAffLanes + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(convert_affine_kernel<T>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
 }
 
 // Tensors beyond one block's LDS: the tree read-off. The basis change is a
@@ -1301,7 +1387,6 @@ template <typename T>
 static hipError_t launch_tree(const ConvertArgs &a, const TreePlan &tp, size_t lds, double *partial, double *l1part,
                               hipStream_t s) {
   switch (a.D) {
-    case 1: return launch_tree_t<T, 1>(a, tp, lds, partial, l1part, s);
     case 2: return launch_tree_t<T, 2>(a, tp, lds, partial, l1part, s);
     case 3: return launch_tree_t<T, 3>(a, tp, lds, partial, l1part, s);
     case 4: return launch_tree_t<T, 4>(a, tp, lds, partial, l1part, s);
@@ -1586,37 +1671,41 @@ static bool launch_ntree(const ConvertArgs &a, hipStream_t s, bool wave_team, hi
 
 template <typename T, int D>
 static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
-  // degree 1 tensors are read off at the box corners, a wave per neuron,
-  // whatever n; the tree needs D >= 2 to pay for its levels
-  if (D >= 2 && a.tree) {
-    hipError_t err = hipSuccess;
-    if (a.tune.conv_wave == 0 && launch_ntree<T, D, ntree_tile_axes(D)>(a, s, false, err)) return err;
-    if (a.tune.conv_wave == 3 && launch_ntree<T, D, ntree_tile_axes(D)>(a, s, true, err)) return err;
-  }
-  const size_t plb = (size_t)((a.plist_len + 1) / 2) * sizeof(double);
-  if (D == 1 || (a.C <= kWaveC && a.tune.conv_wave <= 1)) {
-    const size_t lds = (size_t)(kBlock / 64) * wave_slice_doubles<D>((int)a.C) * sizeof(double) + plb;
-    RET_IF(hipFuncSetAttribute((const void *)convert_wave_t<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  // degree 1 tensors are read off in closed form, whatever n; the tree needs
+  // D >= 2 to pay for its levels
+  if constexpr (D == 1) {
+    return launch_affine<T>(a, s);
+  } else {
+    if (a.tree) {
+      hipError_t err = hipSuccess;
+      if (a.tune.conv_wave == 0 && launch_ntree<T, D, ntree_tile_axes(D)>(a, s, false, err)) return err;
+      if (a.tune.conv_wave == 3 && launch_ntree<T, D, ntree_tile_axes(D)>(a, s, true, err)) return err;
+    }
+    const size_t plb = (size_t)((a.plist_len + 1) / 2) * sizeof(double);
+    if (a.C <= kWaveC && a.tune.conv_wave <= 1) {
+      const size_t lds = (size_t)(kBlock / 64) * wave_slice_doubles((int)a.C) * sizeof(double) + plb;
+      RET_IF(hipFuncSetAttribute((const void *)convert_wave_t<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds));
+      ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4),
+                   (double)a.nboxes * a.h * 2 * a.n * a.C * (a.D + 2));
+      const int64_t items = a.nboxes * a.h;
+      hipLaunchKernelGGL((convert_wave_t<D, T>), dim3((unsigned)((items + kBlock / 64 - 1) / (kBlock / 64))),
+                         dim3(kBlock), lds, s, a);
+      return hipGetLastError();
+    }
+    const size_t lds = (size_t)(a.C + 2 * (kMaxInputs + 1)) * sizeof(double) + plb;
+    if (lds + 256 > device_lds_limit()) return hipErrorInvalidValue;
+    RET_IF(hipFuncSetAttribute((const void *)convert_block_t<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
+    // a block per neuron; when few blocks share a CU's LDS, more waves each
+    static const unsigned kThreads[4] = {0, 256, 512, 1024};
+    const unsigned threads = a.tune.conv_block > 0 && a.tune.conv_block < 4 ? kThreads[a.tune.conv_block]
+                                                                            : (lds > 40 * 1024 ? 1024 : 256);
     ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4),
                  (double)a.nboxes * a.h * 2 * a.n * a.C * (a.D + 2));
-    const int64_t items = a.nboxes * a.h;
-    hipLaunchKernelGGL((convert_wave_t<D, T>), dim3((unsigned)((items + kBlock / 64 - 1) / (kBlock / 64))),
-                       dim3(kBlock), lds, s, a);
+    hipLaunchKernelGGL((convert_block_t<D, T>), dim3((unsigned)(a.nboxes * a.h)), dim3(threads), lds, s, a);
     return hipGetLastError();
   }
-  const size_t lds = (size_t)(a.C + 2 * (kMaxInputs + 1)) * sizeof(double) + plb;
-  if (lds + 256 > device_lds_limit()) return hipErrorInvalidValue;
-  RET_IF(hipFuncSetAttribute((const void *)convert_block_t<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)lds));
-  // a block per neuron; when few blocks share a CU's LDS, more waves each
-  static const unsigned kThreads[4] = {0, 256, 512, 1024};
-  const unsigned threads = a.tune.conv_block > 0 && a.tune.conv_block < 4 ? kThreads[a.tune.conv_block]
-                                                                          : (lds > 40 * 1024 ? 1024 : 256);
-  ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4),
-                 (double)a.nboxes * a.h * 2 * a.n * a.C * (a.D + 2));
-  hipLaunchKernelGGL((convert_block_t<D, T>), dim3((unsigned)(a.nboxes * a.h)), dim3(threads), lds, s, a);
-  return hipGetLastError();
 }
 
 template <typename T>
