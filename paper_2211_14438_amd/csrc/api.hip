@@ -593,7 +593,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       c.scratch_bytes = p.conv * B;
       c.plan = (plain || learned) ? nullptr : plan;
       c.learned = learned && !last;
-      c.fits = (learned || o->features) && !last;
+      c.fits = o->features && !last;  // export: every neuron fitted
       c.layer = i;
       c.hin = hin;
       c.prev = prev;

@@ -893,26 +893,41 @@ __device__ void readoff_pair(const ConvertArgs &a, const Team &tm, bool fitter, 
   if (!a.fp64) pre_radii_team(a, box, j, tm, epsU, epsL);
   tm.reduce(l1, OpAdd());
   const double l1U = l1[0], l1L = l1[1];
-  // Neurons that may take a fitted rule get their affine fits (closed form
-  // from the stored coefficients) first and the remainder ranges in the last
-  // pass of each read-off.
+  // Affine fits (closed form from the stored coefficients) go to the
+  // neurons that may take a fitted rule and turn out unstable, or to every
+  // such neuron when all are fitted (a.fits): then first, with the remainder
+  // ranges in the read-off's last pass; else after the extrema, with a
+  // second read-off for the remainders.
   const bool want = wants_fit(a, box, j);
-  if (want) {
+  const bool early = want && a.fits;
+  auto fits = [&]() {
     if (fitter) {
       wave_fit<D>(p, a.didx, S, a.n, lane, blU, scr);
       wave_fit<D>(p + S, a.didx, S, a.n, lane, blL, scr);
     }
     tm.sync();
-  }
+  };
+  if (early) fits();
   double mnL = INFINITY, mxL = -INFINITY, rmnL = INFINITY, rmxL = -INFINITY;
-  team_convert_lanes<D>(t, p + S, a.didx, C, S, a.n, tm, pl, want ? blL : nullptr, mnL, mxL, rmnL, rmxL);
+  team_convert_lanes<D>(t, p + S, a.didx, C, S, a.n, tm, pl, early ? blL : nullptr, mnL, mxL, rmnL, rmxL);
   double mnU = INFINITY, mxU = -INFINITY, rmnU = INFINITY, rmxU = -INFINITY;
-  team_convert_lanes<D>(t, p, a.didx, C, S, a.n, tm, pl, want ? blU : nullptr, mnU, mxU, rmnU, rmxU);
+  team_convert_lanes<D>(t, p, a.didx, C, S, a.n, tm, pl, early ? blU : nullptr, mnU, mxU, rmnU, rmxU);
   // maxima of: max U, -min L, and the remainders' max U, -min U, max L, -min L
   double ex[6] = {mxU, -mnL, rmxU, -rmnU, rmxL, -rmnL};
   tm.reduce(ex, OpMax());
   const double lo = side_lo(a, -ex[1], l1L, epsL), hi = side_hi(a, ex[0], l1U, epsU);
   const bool fitted = want && (a.fits || (lo < 0.0 && hi > 0.0));
+  if (fitted && !early) {
+    fits();
+    double m0 = INFINITY, m1 = -INFINITY;
+    rmnL = rmnU = INFINITY;
+    rmxL = rmxU = -INFINITY;
+    team_convert_lanes<D>(t, p + S, a.didx, C, S, a.n, tm, pl, blL, m0, m1, rmnL, rmxL);
+    team_convert_lanes<D>(t, p, a.didx, C, S, a.n, tm, pl, blU, m0, m1, rmnU, rmxU);
+    double rx[4] = {rmxU, -rmnU, rmxL, -rmnL};
+    tm.reduce(rx, OpMax());
+    for (int q = 0; q < 4; ++q) ex[2 + q] = rx[q];
+  }
   double fx[4] = {0.0, 0.0, 0.0, 0.0};  // rmaxU, rminU, rmaxL, rminL
   if (fitted) {
     fx[0] = ex[2];
@@ -1569,20 +1584,24 @@ __device__ void ntree_neuron(const ConvertArgs &a, const NTreePlan &tp, const Te
   const double l1U = l1[0], l1L = l1[1];
   tm.sync();
   const int side = tid / tp.lanes;
-  // Neurons that may take a fitted rule get their affine fits (closed form
-  // from the stored coefficients) first and the remainder ranges in the
-  // same pass as the extrema.
+  // Affine fits (closed form from the stored coefficients) go to the
+  // neurons that may take a fitted rule and turn out unstable, or to every
+  // such neuron when all are fitted (a.fits): then first, with the remainder
+  // ranges in the extrema's pass; else after the extrema, with a second pass
+  // over the trees (their stored coefficients are kept) for the remainders.
   const bool want = wants_fit(a, box, j);
-  if (want) {
+  const bool early = want && a.fits;
+  auto fits = [&]() {
     if (kWave || threadIdx.x < 64) {
       double *scr = kWave ? tm_scratch(tm) : nullptr;
       wave_fit<D>(p, a.didx, S, n, (int)(threadIdx.x & 63), bl, scr);
       wave_fit<D>(p + S, a.didx, S, n, (int)(threadIdx.x & 63), bl + kMaxInputs + 1, scr);
     }
     tm.sync();
-  }
+  };
+  if (early) fits();
   double mn = INFINITY, mx = -INFINITY, rmn = INFINITY, rmx = -INFINITY;
-  if (want)
+  if (early)
     ntree_pass<D, M, true>(a, tp, tm, tb, tab, t0, bl, mn, mx, rmn, rmx);
   else
     ntree_pass<D, M, false>(a, tp, tm, tb, tab, t0, bl, mn, mx, rmn, rmx);
@@ -1593,6 +1612,17 @@ __device__ void ntree_neuron(const ConvertArgs &a, const NTreePlan &tp, const Te
   const double mxU = ex[0], mnL = -ex[1];
   const double lo = side_lo(a, mnL, l1L, epsL), hi = side_hi(a, mxU, l1U, epsU);
   const bool fitted = want && (a.fits || (lo < 0.0 && hi > 0.0));
+  if (fitted && !early) {
+    fits();
+    double m0 = INFINITY, m1 = -INFINITY;
+    rmn = INFINITY;
+    rmx = -INFINITY;
+    ntree_pass<D, M, true>(a, tp, tm, tb, tab, t0, bl, m0, m1, rmn, rmx);
+    double rx[4] = {side == 0 ? rmx : -INFINITY, side == 0 ? -rmn : -INFINITY, side == 1 ? rmx : -INFINITY,
+                    side == 1 ? -rmn : -INFINITY};
+    tm.reduce(rx, OpMax());
+    for (int q = 0; q < 4; ++q) ex[2 + q] = rx[q];
+  }
   double fx[4] = {0.0, 0.0, 0.0, 0.0};  // rmaxU, rminU, rmaxL, rminL
   if (fitted) {
     fx[0] = ex[2];
