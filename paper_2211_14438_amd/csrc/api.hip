@@ -143,6 +143,10 @@ struct bern_net {
   std::vector<GraphEntry> graphs;
   hipStream_t capture = nullptr;  // stream the sequences are captured on
   bern::SimplexTables *tab = nullptr;  // index tables of the total-degree layout (built on demand)
+  // pinned host staging of the per-layer box classes (box degrees in, box id
+  // lists out), so those copies run asynchronously
+  mutable int *host_ids = nullptr;
+  mutable size_t host_n = 0;
 };
 
 struct bern_pred {
@@ -359,6 +363,7 @@ void bern_net_destroy(bern_net *net) {
     if (g.graph) (void)hipGraphDestroy(g.graph);
   }
   if (net->capture) (void)hipStreamDestroy(net->capture);
+  if (net->host_ids) (void)hipHostFree(net->host_ids);
   delete net->tab;
   delete net;
 }
@@ -526,13 +531,29 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
   classes[0].Din = 1;
   classes[0].Dout = 0;
   std::vector<int> dcur(B, 1);
+  // pinned staging: B box degrees, then one id list per (layer, phase); a
+  // list is written once per wave, and every wave's first copy follows a
+  // stream synchronisation, so no staged list is rewritten in flight
+  const size_t need = (size_t)B * (1 + 2 * (size_t)p.H);
+  if (!plain && net->host_n < need) {
+    BERN_HIP_TRY(hipStreamSynchronize(s));
+    if (net->host_ids) (void)hipHostFree(net->host_ids);
+    net->host_ids = nullptr;
+    net->host_n = 0;
+    BERN_HIP_TRY(hipHostMalloc((void **)&net->host_ids, need * sizeof(int), hipHostMallocDefault));
+    net->host_n = need;
+  }
   auto upload = [&](std::vector<BoxClass> &cl, int layer, int phase, std::vector<const int *> &dev) -> bern_status {
     dev.assign(cl.size(), nullptr);
     if (cl.size() == 1 && (int64_t)cl[0].ids.size() == B) return BERN_OK;  // identity
-    std::vector<int> all;
-    for (auto &c : cl) all.insert(all.end(), c.ids.begin(), c.ids.end());
+    int *all = net->host_ids + B + ((int64_t)layer * 2 + phase) * B;
+    size_t cnt = 0;
+    for (auto &c : cl) {
+      std::copy(c.ids.begin(), c.ids.end(), all + cnt);
+      cnt += c.ids.size();
+    }
     int *dst = idlists + ((int64_t)layer * 2 + phase) * B;
-    BERN_HIP_TRY(hipMemcpyAsync(dst, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    BERN_HIP_TRY(hipMemcpyAsync(dst, all, cnt * sizeof(int), hipMemcpyHostToDevice, s));
     int64_t off = 0;
     for (size_t k = 0; k < cl.size(); ++k) {
       dev[k] = dst + off;
@@ -664,8 +685,8 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
                            (const NeuronRec *)recs, degs);
       }
       BERN_HIP_TRY(hipGetLastError());
-      std::vector<int> hd(B);
-      BERN_HIP_TRY(hipMemcpyAsync(hd.data(), degs, B * sizeof(int), hipMemcpyDeviceToHost, s));
+      int *hd = net->host_ids;
+      BERN_HIP_TRY(hipMemcpyAsync(hd, degs, B * sizeof(int), hipMemcpyDeviceToHost, s));
       BERN_HIP_TRY(hipStreamSynchronize(s));
       for (int64_t b = 0; b < B; ++b) {
         const int din = dcur[b], dout = std::max(hd[b], 0);
