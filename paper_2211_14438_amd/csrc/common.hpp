@@ -257,6 +257,7 @@ struct ComposeArgs {
   double *part;                   // FP32 mode: [B*h*nbounds][nbx][2] (rounding sum, l1 sum) per block
   int64_t nbx;                    // blocks per item of every compose launch of the layer
   int nbounds;                    // 2 (upper, lower) for the network, 1 for plain products
+  int group;                      // set by the launcher: waves take 64 items each (for_wave_items)
   int Lmax;                       // largest ReLU order any neuron of the launch may use
   int64_t Cin, Cout, nboxes;      // stored coefficients at degrees Din and Dout
   int64_t Cs;                     // stored coefficients of degree-preserving posts (degree min(Din, Dout))

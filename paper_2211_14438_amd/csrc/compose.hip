@@ -111,6 +111,45 @@ __device__ inline bool wave_item(const ComposeArgs &a, int64_t &g, int &j, int &
   return true;
 }
 
+// Many items, few of which need a kernel's work: a wave then takes kGroup
+// consecutive items (`chunks` waves per group, chunk index c), reads their
+// kinds at once and runs f(g, j, s, c) for those that pass `need`, in order.
+// Without grouping (a.group == 0) every wave has its own item, as in
+// wave_item. Either way an item's work is the same.
+constexpr int kGroup = 64;
+
+template <class Need, class F>
+__device__ inline void for_wave_items(const ComposeArgs &a, int chunks, Need need, F f) {
+  if (!a.group) {
+    int64_t g;
+    int j, s, c = 0;
+    if (!wave_item(a, g, j, s, chunks, &c)) return;
+    if (need(a.recs[wave_box(a, g) * a.h + j].kind)) f(g, j, s, c);
+    return;
+  }
+  int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int c = (int)(w % chunks);
+  w /= chunks;
+  const int64_t per = (int64_t)a.h * a.nbounds, total = a.nboxes * per;
+  const int64_t i0 = w * kGroup;
+  if (i0 >= total) return;
+  const int lane = threadIdx.x & 63;
+  bool mine = false;
+  if (i0 + lane < total) {
+    const int64_t it = i0 + lane, g = it / per;
+    const int j = (int)((it - g * per) / a.nbounds);
+    mine = need(a.recs[wave_box(a, g) * a.h + j].kind);
+  }
+  unsigned long long todo = __ballot(mine);
+  while (todo) {
+    const int b = __ffsll((long long)todo) - 1;
+    todo &= todo - 1;
+    const int64_t it = i0 + b, g = it / per;
+    const int rest = (int)(it - g * per);
+    f(g, rest / a.nbounds, rest % a.nbounds, c);
+  }
+}
+
 // Store one coefficient; track its rounding and magnitude.
 template <typename T>
 __device__ __forceinline__ void store(T *dst, double q, double &r, double &l1) {
@@ -392,15 +431,11 @@ __global__ void __launch_bounds__(kBlock) live_kernel(ComposeArgs a) {
 // ones store nothing. Writes the block's rounding and l1 sums to partial
 // slot 0 and zeros to the item's other slots.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) compose_scatter_kernel(ComposeArgs a) {
-  int64_t g;
-  int j, s;
-  if (!wave_item(a, g, j, s)) return;
+__device__ void scatter_item(const ComposeArgs &a, int64_t g, int j, int s) {
   const int lane = threadIdx.x & 63;
   const int64_t box = wave_box(a, g);
   const NeuronRec &r = a.recs[box * a.h + j];
   const int kind = r.kind;
-  if (kind >= 2 || kind == kActive || kind == kInactive) return;  // partials of these are not read
   const NuSource ns = nu_of(a, &r, s);
   const int64_t it = item_of(a, g, j, s);
   const T *p = in_tensor<T>(a, box, j, s);
@@ -429,6 +464,13 @@ __global__ void __launch_bounds__(kBlock) compose_scatter_kernel(ComposeArgs a) 
     }
   }
   if (a.part) wave_partials(a, it, rsum, l1sum);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) compose_scatter_kernel(ComposeArgs a) {
+  // order-1 and fallback neurons (the partials of the others are not read)
+  for_wave_items(a, 1, [](int kind) { return kind == 1 || kind == kFallback; },
+                 [&](int64_t g, int j, int s, int) { scatter_item<T>(a, g, j, s); });
 }
 
 // ---------------------------------------------- total-degree products
@@ -713,8 +755,14 @@ static int sq_dispatch(const ComposeArgs &a, hipStream_t s, hipError_t &err) {
 }
 
 template <typename T>
-static hipError_t compose_all(const ComposeArgs &a, hipStream_t s) {
+static hipError_t compose_all(const ComposeArgs &a_in, hipStream_t s) {
+  ComposeArgs a = a_in;
   const unsigned gx = (unsigned)a.nbx;
+  // many items: the scatter takes kGroup items per wave, which reads their
+  // kinds at once (its items are few and light); the square keeps a wave
+  // per item and output chunk
+  const int64_t items_all = a.nboxes * a.h * a.nbounds;
+  const bool group = items_all >= 1024 * kGroup;
   if (a.live) {
     ProfScope ps(kProfMisc, s, 0.0);
     hipLaunchKernelGGL(live_kernel, dim3((unsigned)((a.nboxes + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), 0,
@@ -722,9 +770,11 @@ static hipError_t compose_all(const ComposeArgs &a, hipStream_t s) {
     RET_IF(hipGetLastError());
   }
   {
-    const int64_t items = a.nboxes * a.h * a.nbounds;
     ProfScope ps(kProfComposeSimple, s, 0.0);
-    hipLaunchKernelGGL(compose_scatter_kernel<T>, dim3((unsigned)((items + 3) / 4)), dim3(256), 0, s, a);
+    ComposeArgs ag = a;
+    ag.group = group ? 1 : 0;
+    const int64_t waves = group ? (items_all + kGroup - 1) / kGroup : items_all;
+    hipLaunchKernelGGL(compose_scatter_kernel<T>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, ag);
     RET_IF(hipGetLastError());
   }
   const size_t lds = (size_t)a.Cin * sizeof(double);
@@ -732,7 +782,7 @@ static hipError_t compose_all(const ComposeArgs &a, hipStream_t s) {
     if (!a.sq_off || 4 * lds > device_lds_limit() || (int64_t)gx * kBlock < a.Cout) return hipErrorInvalidValue;
     RET_IF(hipFuncSetAttribute((const void *)compose_sq2_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)(4 * lds)));
-    const int64_t waves = a.nboxes * a.h * a.nbounds * a.nbx;
+    const int64_t waves = items_all * a.nbx;
     ProfScope ps(kProfComposeSquare, s, 0.0);
     hipLaunchKernelGGL(compose_sq2_kernel<T>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 4 * lds, s, a);
     RET_IF(hipGetLastError());
