@@ -242,7 +242,8 @@ __device__ void padded_bounds(const ConvertArgs &a, int64_t box, int j, double m
 
 // Record of one hidden neuron after its read-off (thread 0 only), then its
 // rule unless a predictor chooses it later. Fitted neurons' affine fits are
-// already in the record; the others get zeros.
+// already in the record; the others get zeros unless the caller skips them
+// (fits_written: an unfitted neuron's fit fields are never read).
 __device__ void record_neuron(const ConvertArgs &a, int64_t box, int j, double lo, double hi, double epsU,
                               double epsL, double l1U, double l1L, const double *ext, bool fitted,
                               bool fits_written = false) {
@@ -935,10 +936,10 @@ __device__ void readoff_pair(const ConvertArgs &a, const Team &tm, bool fitter, 
     fx[2] = ex[4];
     fx[3] = -ex[5];
   }
-  if (a.mode == 0) {  // the fits, or zeros
+  if (a.mode == 0 && fitted) {  // the fits (an unfitted neuron's are never read)
     NeuronRec &rec = a.recs[box * a.h + j];
-    team_write_fit(a, tm, rec.fitU, fitted ? blU : nullptr);
-    team_write_fit(a, tm, rec.fitL, fitted ? blL : nullptr);
+    team_write_fit(a, tm, rec.fitU, blU);
+    team_write_fit(a, tm, rec.fitL, blL);
   }
   if (tm.tid == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted, true);
 }
@@ -1079,18 +1080,23 @@ __global__ void __launch_bounds__(kBlock) convert_affine_kernel(ConvertArgs a) {
     fx[0] = fx[1] = c[0];
     fx[2] = fx[3] = c[1];
   }
-  if (a.mode == 0) {  // the fits (beta_0, then beta_a = a_{1+a}), or zeros
+  if (a.mode == 0 && fitted) {  // the fits: beta_0, then beta_a = a_{1+a}
     NeuronRec &rec = a.recs[box * a.h + j];
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
       const int q = l + r * kAffLanes;
       if (q <= kMaxInputs) {
-        const bool on = fitted && q < S;
+        const bool on = q < S;
         rec.fitU[q] = on ? (q == 0 ? s[4] : u[r]) : 0.0;
         rec.fitL[q] = on ? (q == 0 ? s[5] : w[r]) : 0.0;
       }
     }
+    // visible to lane 0, whose rule may read them
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   }
+  // an unfitted neuron's fit fields are never read (fitted == 0)
   if (l == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted, true);
 }
 
@@ -1630,10 +1636,10 @@ __device__ void ntree_neuron(const ConvertArgs &a, const NTreePlan &tp, const Te
     fx[2] = ex[4];
     fx[3] = -ex[5];
   }
-  if (a.mode == 0) {  // the fits, or zeros
+  if (a.mode == 0 && fitted) {  // the fits (an unfitted neuron's are never read)
     NeuronRec &rec = a.recs[box * a.h + j];
-    team_write_fit(a, tm, rec.fitU, fitted ? bl : nullptr);
-    team_write_fit(a, tm, rec.fitL, fitted ? bl + kMaxInputs + 1 : nullptr);
+    team_write_fit(a, tm, rec.fitU, bl);
+    team_write_fit(a, tm, rec.fitL, bl + kMaxInputs + 1);
   }
   if (tid == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted, true);
 }
