@@ -172,6 +172,21 @@ bern_status bern_bounds(const bern_net *net, const bern_opts *opts, int64_t n_bo
                         int8_t *used_plan, void *workspace, size_t ws_bytes, void *stream,
                         bern_stats *stats);
 
+/* bern_bounds on host memory, synchronous (the same computation, Problem 1):
+ * box_lo, box_hi, plan and every output are host arrays with bern_bounds'
+ * shapes (plan, neuron_lo/hi and used_plan nullable as there). The library
+ * allocates device copies and a workspace for all boxes in one wave (the
+ * one-box size, and waves, if that allocation fails), copies the inputs in,
+ * runs on the null stream, copies the outputs back and frees everything
+ * before returning; the PCIe copies are part of the call. For callers
+ * without device buffers of their own.
+ * Errors: those of bern_bounds, and BERN_E_DEVICE for a failed allocation
+ * or copy (nothing is left allocated). */
+bern_status bern_bounds_host(const bern_net *net, const bern_opts *opts, int64_t n_boxes,
+                             const double *box_lo, const double *box_hi, const int8_t *plan,
+                             double *neuron_lo, double *neuron_hi, double *out_lo, double *out_hi,
+                             int8_t *used_plan, bern_stats *stats);
+
 /* Kernel variants and their autotuner (the box-batch scheduler's tile
  * choices; not in the paper). The library has kTune = bern_tune_params()
  * tuning parameters, parameter q having bern_tune_variants(q) variants
@@ -180,8 +195,9 @@ bern_status bern_bounds(const bern_net *net, const bern_opts *opts, int64_t n_bo
  * most 4 neurons, 2 threads of the dense block-per-neuron read-off, 3 the
  * per-neuron read-off: the tree of folds (0), the dense tensor with one wave
  * per neuron up to 1024 coefficients (1), or one block per neuron (2), the
- * tree with one wave per neuron and more variables folded per round (3). The
- * choice is stored in the network handle and used by every
+ * tree with one wave per neuron and more variables folded per round (3);
+ * degree-1 tensors always take the closed form. The choice is stored in the
+ * network handle and used by every
  * later call on it; every variant computes the same bounds up to the order
  * of floating-point sums.
  *   bern_tune_get / bern_tune_set -- read / write `choice` (host,

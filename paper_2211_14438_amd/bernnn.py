@@ -76,6 +76,9 @@ def lib():
     L.bern_bounds.restype = i32
     L.bern_bounds.argtypes = [_vp, ctypes.POINTER(bern_opts), i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, sz,
                               _vp, ctypes.POINTER(bern_stats)]
+    L.bern_bounds_host.restype = i32
+    L.bern_bounds_host.argtypes = [_vp, ctypes.POINTER(bern_opts), i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                   ctypes.POINTER(bern_stats)]
     L.bern_basis_minmax_scratch.restype = sz
     L.bern_basis_minmax_scratch.argtypes = [i32, i32, i64]
     L.bern_basis_minmax.restype = i32
@@ -318,6 +321,30 @@ def bounds(net, box_lo, box_hi, L=2, precision="fp64", plan="plain", sched="per_
     res["stats"] = dict(n_waves=st.n_waves, boxes_per_wave=st.boxes_per_wave, out_degree=st.out_degree,
                         workspace_used=st.workspace_used)
     res["workspace"] = workspace
+    return res
+
+
+def bounds_host(net, box_lo, box_hi, L=2, precision="fp64", plan="plain", sched="batched", degree_plan=None,
+                max_wave=0, pred=None):
+    """``bounds`` on host arrays (numpy float64 [n_boxes, n]), synchronous:
+    the library allocates and frees the device buffers itself. Returns a dict
+    of numpy arrays (neuron_lo/hi, out_lo/hi, used_plan) and the run
+    statistics."""
+    box_lo = np.ascontiguousarray(box_lo, dtype=np.float64)
+    box_hi = np.ascontiguousarray(box_hi, dtype=np.float64)
+    nb = box_lo.shape[0]
+    nh = max(net.n_hidden, 1)
+    o = make_opts(L=L, precision=precision, plan=plan, sched=sched, max_wave=max_wave, pred=pred)
+    res = dict(neuron_lo=np.empty((nb, nh)), neuron_hi=np.empty((nb, nh)), out_lo=np.empty((nb, net.n_out)),
+               out_hi=np.empty((nb, net.n_out)), used_plan=np.empty((nb, nh), dtype=np.int8))
+    dp = None if degree_plan is None else np.ascontiguousarray(degree_plan, dtype=np.int8)
+    vp = lambda a: None if a is None else ctypes.c_void_p(a.ctypes.data)  # noqa: E731
+    st = bern_stats()
+    _check(lib().bern_bounds_host(net.handle, ctypes.byref(o), nb, vp(box_lo), vp(box_hi), vp(dp),
+                                  vp(res["neuron_lo"]), vp(res["neuron_hi"]), vp(res["out_lo"]), vp(res["out_hi"]),
+                                  vp(res["used_plan"]), ctypes.byref(st)))
+    res["stats"] = dict(n_waves=st.n_waves, boxes_per_wave=st.boxes_per_wave, out_degree=st.out_degree,
+                        workspace_used=st.workspace_used)
     return res
 
 

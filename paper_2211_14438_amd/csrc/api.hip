@@ -916,6 +916,70 @@ extern "C" bern_status bern_bounds(const bern_net *net, const bern_opts *opts, i
   return BERN_OK;
 }
 
+// ------------------------------------------------- host-memory convenience
+namespace {
+// Device buffers of one bern_bounds_host call, released on every return.
+struct DeviceBufs {
+  std::vector<void *> ptrs;
+  ~DeviceBufs() {
+    for (void *q : ptrs) (void)hipFree(q);
+  }
+  hipError_t alloc(void **out, size_t bytes) {
+    *out = nullptr;
+    if (bytes == 0) return hipSuccess;
+    hipError_t e = hipMalloc(out, bytes);
+    if (e == hipSuccess) ptrs.push_back(*out);
+    return e;
+  }
+};
+}  // namespace
+
+extern "C" bern_status bern_bounds_host(const bern_net *net, const bern_opts *opts, int64_t n_boxes,
+                                        const double *box_lo, const double *box_hi, const int8_t *plan,
+                                        double *neuron_lo, double *neuron_hi, double *out_lo, double *out_hi,
+                                        int8_t *used_plan, bern_stats *stats) {
+  bern_status st = check_opts(net, opts);
+  if (st != BERN_OK) return st;
+  if (n_boxes < 1 || !box_lo || !box_hi || !out_lo || !out_hi) {
+    set_error("bad arguments (n_boxes = %lld)", (long long)n_boxes);
+    return BERN_E_ARG;
+  }
+  size_t ws_all = 0, ws_one = 0;
+  if ((st = bern_workspace_size(net, opts, n_boxes, &ws_all, &ws_one)) != BERN_OK) return st;
+  const size_t nb = (size_t)n_boxes, nbox = nb * (size_t)net->n * sizeof(double);
+  const size_t nhid = nb * (size_t)net->nh, nout = nb * (size_t)net->o * sizeof(double);
+  DeviceBufs d;
+  void *dlo, *dhi, *dplan = nullptr, *dnlo = nullptr, *dnhi = nullptr, *dolo, *dohi, *dused = nullptr, *ws = nullptr;
+  BERN_HIP_TRY(d.alloc(&dlo, nbox));
+  BERN_HIP_TRY(d.alloc(&dhi, nbox));
+  if (plan) BERN_HIP_TRY(d.alloc(&dplan, nhid));
+  if (neuron_lo) BERN_HIP_TRY(d.alloc(&dnlo, nhid * sizeof(double)));
+  if (neuron_hi) BERN_HIP_TRY(d.alloc(&dnhi, nhid * sizeof(double)));
+  BERN_HIP_TRY(d.alloc(&dolo, nout));
+  BERN_HIP_TRY(d.alloc(&dohi, nout));
+  if (used_plan) BERN_HIP_TRY(d.alloc(&dused, nhid));
+  // the whole batch in one wave if it fits, else the smallest usable workspace
+  if (d.alloc(&ws, ws_all) != hipSuccess) {
+    (void)hipGetLastError();
+    BERN_HIP_TRY(d.alloc(&ws, ws_one));
+    ws_all = ws_one;
+  }
+  BERN_HIP_TRY(hipMemcpy(dlo, box_lo, nbox, hipMemcpyHostToDevice));
+  BERN_HIP_TRY(hipMemcpy(dhi, box_hi, nbox, hipMemcpyHostToDevice));
+  if (plan) BERN_HIP_TRY(hipMemcpy(dplan, plan, nhid, hipMemcpyHostToDevice));
+  st = bern_bounds(net, opts, n_boxes, (const double *)dlo, (const double *)dhi, (const int8_t *)dplan,
+                   (double *)dnlo, (double *)dnhi, (double *)dolo, (double *)dohi, (int8_t *)dused, ws, ws_all,
+                   nullptr, stats);
+  if (st != BERN_OK) return st;
+  BERN_HIP_TRY(hipStreamSynchronize(nullptr));
+  BERN_HIP_TRY(hipMemcpy(out_lo, dolo, nout, hipMemcpyDeviceToHost));
+  BERN_HIP_TRY(hipMemcpy(out_hi, dohi, nout, hipMemcpyDeviceToHost));
+  if (neuron_lo) BERN_HIP_TRY(hipMemcpy(neuron_lo, dnlo, nhid * sizeof(double), hipMemcpyDeviceToHost));
+  if (neuron_hi) BERN_HIP_TRY(hipMemcpy(neuron_hi, dnhi, nhid * sizeof(double), hipMemcpyDeviceToHost));
+  if (used_plan) BERN_HIP_TRY(hipMemcpy(used_plan, dused, nhid, hipMemcpyDeviceToHost));
+  return BERN_OK;
+}
+
 // --------------------------------------------------------------- autotuner
 static void tune_to(const Tune &t, int32_t *v) {
   v[0] = t.gemm_wide;

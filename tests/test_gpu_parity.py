@@ -249,6 +249,26 @@ def test_large_output_two_pass_fp32_and_fp64():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_bounds_host_equals_device_run(precision):
+    """The host-memory entry point gives the device entry point's bits (same
+    kernels, one wave), and so the oracle's bounds."""
+    case = wl.random_net_case([4, 10, 10, 3], seed=77, n_boxes=7)
+    plan = np.random.default_rng(5).integers(0, 3, size=(case.n_boxes, case.n_hidden)).astype(np.int8)
+    g = _bounds_gpu(case, L=2, precision=precision, sched="batched", plan=plan)
+    net = B.Net(case.Ws, case.bs)
+    h = B.bounds_host(net, case.box_lo, case.box_hi, L=2, precision=precision, plan="given", degree_plan=plan)
+    net.close()
+    for k in ("neuron_lo", "neuron_hi", "out_lo", "out_hi", "used_plan"):
+        assert np.array_equal(h[k], g[k]), k
+    assert h["stats"]["n_waves"] == 1
+    o = _oracle(case, plan=plan)
+    if precision == "fp64":
+        _assert_parity(h, o, 1e-9, case.n_hidden)
+    else:
+        _assert_fp32(h, o, case.n_hidden)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_degree_one_tensors_at_many_inputs(precision):
     """Degree-1 tensors are read off at the 2^n box corners whatever n:
     n = 12 under the plain rule (its second layer at degree 2 in 12
