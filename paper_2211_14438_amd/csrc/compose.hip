@@ -111,16 +111,15 @@ __device__ inline bool wave_item(const ComposeArgs &a, int64_t &g, int &j, int &
   return true;
 }
 
-// Many items, few of which need a kernel's work: a wave then takes kGroup
-// consecutive items (`chunks` waves per group, chunk index c), reads their
-// kinds at once and runs f(g, j, s, c) for those that pass `need`, in order.
-// Without grouping (a.group == 0) every wave has its own item, as in
+// Many items, few of which need a kernel's work: a wave then takes a.group
+// (<= 64) consecutive items (`chunks` waves per group, chunk index c), reads
+// their kinds at once and runs f(g, j, s, c) for those that pass `need`, in
+// order. Without grouping (a.group <= 1) every wave has its own item, as in
 // wave_item. Either way an item's work is the same.
-constexpr int kGroup = 64;
 
 template <class Need, class F>
 __device__ inline void for_wave_items(const ComposeArgs &a, int chunks, Need need, F f) {
-  if (!a.group) {
+  if (a.group <= 1) {
     int64_t g;
     int j, s, c = 0;
     if (!wave_item(a, g, j, s, chunks, &c)) return;
@@ -131,11 +130,11 @@ __device__ inline void for_wave_items(const ComposeArgs &a, int chunks, Need nee
   const int c = (int)(w % chunks);
   w /= chunks;
   const int64_t per = (int64_t)a.h * a.nbounds, total = a.nboxes * per;
-  const int64_t i0 = w * kGroup;
+  const int64_t i0 = w * a.group;
   if (i0 >= total) return;
   const int lane = threadIdx.x & 63;
   bool mine = false;
-  if (i0 + lane < total) {
+  if (lane < a.group && i0 + lane < total) {
     const int64_t it = i0 + lane, g = it / per;
     const int j = (int)((it - g * per) / a.nbounds);
     mine = need(a.recs[wave_box(a, g) * a.h + j].kind);
@@ -491,16 +490,13 @@ __device__ inline void load_nu(const ComposeArgs &a, const T *p, const NuSource 
 // I < J listed once and doubled, plus the diagonal term. Coefficients past
 // degree 2 Din (a layer stored at a higher degree) are zero.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) compose_sq2_kernel(ComposeArgs a) {
-  extern __shared__ double lds_nu[];
-  int64_t g;
-  int j, s, bx;
-  if (!wave_item(a, g, j, s, (int)a.nbx, &bx)) return;  // wave bx: outputs [bx kBlock, (bx + 1) kBlock)
+__device__ void sq2_item(const ComposeArgs &a, int64_t g, int j, int s, int bx, double *nu) {
+  // chunk bx: outputs [bx kBlock, (bx + 1) kBlock)
   const int lane = threadIdx.x & 63;
-  double *nu = lds_nu + (threadIdx.x >> 6) * a.Cin;  // the wave's nu
   const int64_t box = wave_box(a, g);
   const NeuronRec &r = a.recs[box * a.h + j];
-  if (r.kind != 2) return;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");  // the previous item's reads of nu are done
+  __builtin_amdgcn_wave_barrier();
   {
     const T *p = in_tensor<T>(a, box, j, s);
     const NuSource ns = nu_of(a, &r, s);
@@ -545,6 +541,14 @@ __global__ void __launch_bounds__(kBlock) compose_sq2_kernel(ComposeArgs a) {
       a.part[(it * a.nbx + bx) * 2 + 1] = l1sum;
     }
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) compose_sq2_kernel(ComposeArgs a) {
+  extern __shared__ double lds_nu[];
+  double *nu = lds_nu + (threadIdx.x >> 6) * a.Cin;  // the wave's nu
+  for_wave_items(a, (int)a.nbx, [](int kind) { return kind == 2; },
+                 [&](int64_t g, int j, int s, int bx) { sq2_item<T>(a, g, j, s, bx, nu); });
 }
 
 // Orders L >= 3: Horner steps Q^(m) = nu Q^(m-1) + c_{L-1-m}, m = 1 .. L-1,
@@ -758,11 +762,11 @@ template <typename T>
 static hipError_t compose_all(const ComposeArgs &a_in, hipStream_t s) {
   ComposeArgs a = a_in;
   const unsigned gx = (unsigned)a.nbx;
-  // many items: the scatter takes kGroup items per wave, which reads their
-  // kinds at once (its items are few and light); the square keeps a wave
-  // per item and output chunk
+  // many items: a wave takes a group of items and reads their kinds at
+  // once; 64 for the scatter (its items are few and light), 8 for the
+  // square (heavier items, which the group's wave takes one after another)
   const int64_t items_all = a.nboxes * a.h * a.nbounds;
-  const bool group = items_all >= 1024 * kGroup;
+  const bool group = items_all >= 65536;
   if (a.live) {
     ProfScope ps(kProfMisc, s, 0.0);
     hipLaunchKernelGGL(live_kernel, dim3((unsigned)((a.nboxes + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), 0,
@@ -772,8 +776,8 @@ static hipError_t compose_all(const ComposeArgs &a_in, hipStream_t s) {
   {
     ProfScope ps(kProfComposeSimple, s, 0.0);
     ComposeArgs ag = a;
-    ag.group = group ? 1 : 0;
-    const int64_t waves = group ? (items_all + kGroup - 1) / kGroup : items_all;
+    ag.group = group ? 64 : 1;
+    const int64_t waves = (items_all + ag.group - 1) / ag.group;
     hipLaunchKernelGGL(compose_scatter_kernel<T>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, ag);
     RET_IF(hipGetLastError());
   }
@@ -782,9 +786,11 @@ static hipError_t compose_all(const ComposeArgs &a_in, hipStream_t s) {
     if (!a.sq_off || 4 * lds > device_lds_limit() || (int64_t)gx * kBlock < a.Cout) return hipErrorInvalidValue;
     RET_IF(hipFuncSetAttribute((const void *)compose_sq2_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)(4 * lds)));
-    const int64_t waves = items_all * a.nbx;
+    ComposeArgs ag = a;
+    ag.group = group ? 8 : 1;
+    const int64_t waves = (items_all + ag.group - 1) / ag.group * a.nbx;
     ProfScope ps(kProfComposeSquare, s, 0.0);
-    hipLaunchKernelGGL(compose_sq2_kernel<T>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 4 * lds, s, a);
+    hipLaunchKernelGGL(compose_sq2_kernel<T>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 4 * lds, s, ag);
     RET_IF(hipGetLastError());
   }
   if (a.Lmax >= 3) {
