@@ -662,6 +662,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
         la.params = learned ? o->pred->params : nullptr;
         la.codes = codes;
         la.used = used;
+        la.degs = learned ? degs : nullptr;  // the rules kernel also gives each box's post degree
         la.cap = cap;
         la.fp64 = p.fp64 ? 1 : 0;
         la.L = p.L;
@@ -679,7 +680,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       next = classes;
       for (auto &c : next) c.Dout = p.L * c.Din;
     } else {
-      {
+      if (!learned) {  // (the learned rules kernel wrote them)
         ProfScope ps(kProfMisc, s, 0.0);
         hipLaunchKernelGGL(box_degree_kernel, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, s, B, h,
                            (const NeuronRec *)recs, degs);

@@ -298,6 +298,7 @@ struct LearnArgs {
   const float *params;            // predictor parameters (FP32 master copy)
   int8_t *codes;                  // [B][nh] predicted codes (column block noff)
   int8_t *used;                   // [B][nh] or null
+  int *degs;                      // [B] or null: each box's largest post degree (the rules kernel)
   int cap, fp64, L;
 };
 // features -> (optional) BF16 MLP -> codes -> rules, for one class of boxes.

@@ -292,6 +292,7 @@ __global__ void __launch_bounds__(256) learned_rules_kernel(LearnArgs a) {
   int top = -1;  // class as the degree it gives: fallback (0) lowest
   for (int j = lane; j < a.h; j += 64) top = max(top, (int)cl[j]);
   for (int off = 32; off > 0; off >>= 1) top = max(top, __shfl_xor(top, off, 64));
+  int deg = 0;
   for (int j = lane; j < a.h; j += 64) {
     NeuronRec &r = a.recs[box * a.h + j];
     int c = cl[j];
@@ -302,6 +303,11 @@ __global__ void __launch_bounds__(256) learned_rules_kernel(LearnArgs a) {
     }
     decide_neuron(r, c < 0 ? 1 : c, false, a.L, a.n, a.D, a.cap, a.fp64);
     if (a.used) a.used[box * a.nh + a.noff + j] = (int8_t)r.kind;
+    deg = max(deg, r.deg);
+  }
+  if (a.degs) {  // the box's largest post degree, for the next layer's classes
+    for (int off = 32; off > 0; off >>= 1) deg = max(deg, __shfl_xor(deg, off, 64));
+    if (lane == 0) a.degs[box] = deg;
   }
 }
 
