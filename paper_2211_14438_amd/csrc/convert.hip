@@ -191,18 +191,20 @@ __device__ void pre_radii(const ConvertArgs &a, int64_t box, int j, const void *
   epsL = (sL + gg + rL) * kPadSafety;
 }
 
-// The same radii with the five sums reduced at once by a team.
+// The radii and the two tensors' l1 norms (l1: the lane's shares in, the
+// team's totals out), their sums reduced together.
 template <class Team>
-__device__ void pre_radii_team(const ConvertArgs &a, int64_t box, int j, const Team &tm, double &epsU,
-                               double &epsL) {
-  if (a.layer == 0) {
-    pre_radii(a, box, j, a.pre, tm.tid, tm.nt, [](double v) { return v; }, epsU, epsL);
+__device__ void radii_and_l1(const ConvertArgs &a, int64_t box, int j, const Team &tm, double (&l1)[2],
+                             double &epsU, double &epsL) {
+  epsU = epsL = 0.0;
+  if (a.fp64 || a.layer == 0) {
+    if (!a.fp64) pre_radii(a, box, j, a.pre, tm.tid, tm.nt, [](double v) { return v; }, epsU, epsL);
+    tm.reduce(l1, OpAdd());
     return;
   }
-  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // sU, sL, g, rU, rL
+  double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, l1[0], l1[1]};  // sU, sL, g, rU, rL, l1U, l1L
   for (int k = tm.tid; k < a.hin; k += tm.nt) {
     const double wk = a.W[(int64_t)j * a.hin + k];
-    // the previous layer's radii from their dense copy: 32 bytes per input
     const double4 P = *reinterpret_cast<const double4 *>(a.prad + (box * a.hin + k) * 4);
     if (wk >= 0.0) {
       v[0] += wk * P.x;
@@ -219,6 +221,8 @@ __device__ void pre_radii_team(const ConvertArgs &a, int64_t box, int j, const T
     v[4] += rp[a.cblocks + cb];
   }
   tm.reduce(v, OpAdd());
+  l1[0] = v[5];
+  l1[1] = v[6];
   const double gg = a.gpre * (v[2] + fabs(a.b[j]));
   epsU = (v[0] + gg + v[3]) * kPadSafety;
   epsL = (v[1] + gg + v[4]) * kPadSafety;
@@ -890,9 +894,8 @@ __device__ void readoff_pair(const ConvertArgs &a, const Team &tm, bool fitter, 
     l1[0] += fabs((double)p[i]);
     l1[1] += fabs((double)p[S + i]);
   }
-  double epsU = 0.0, epsL = 0.0;
-  if (!a.fp64) pre_radii_team(a, box, j, tm, epsU, epsL);
-  tm.reduce(l1, OpAdd());
+  double epsU, epsL;
+  radii_and_l1(a, box, j, tm, l1, epsU, epsL);
   const double l1U = l1[0], l1L = l1[1];
   // Affine fits (closed form from the stored coefficients) go to the
   // neurons that may take a fitted rule and turn out unstable, or to every
@@ -1584,9 +1587,8 @@ __device__ void ntree_neuron(const ConvertArgs &a, const NTreePlan &tp, const Te
     l1[0] += fabs(uu);
     l1[1] += fabs(ww);
   }
-  double epsU = 0.0, epsL = 0.0;
-  if (!a.fp64) pre_radii_team(a, box, j, tm, epsU, epsL);
-  tm.reduce(l1, OpAdd());
+  double epsU, epsL;
+  radii_and_l1(a, box, j, tm, l1, epsU, epsL);
   const double l1U = l1[0], l1L = l1[1];
   tm.sync();
   const int side = tid / tp.lanes;
