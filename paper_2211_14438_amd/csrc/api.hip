@@ -645,32 +645,33 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
         c.used = used;
       }
       BERN_HIP_TRY(launch_convert(c, s));
-      if (!last && (learned || o->features)) {
-        LearnArgs la{};
-        la.n = n;
-        la.D = cl.Din;
-        la.h = h;
-        la.H = p.H;
-        la.layer = i;
-        la.nboxes = c.nboxes;
-        la.bids = cid[k];
-        la.recs = recs;
-        la.sens = net->sens + net->noff[i];
-        la.feat = o->features ? o->features + (size_t)b0 * net->nh * 8 : nullptr;
-        la.nh = net->nh;
-        la.noff = net->noff[i];
-        la.params = learned ? o->pred->params : nullptr;
-        la.codes = codes;
-        la.used = used;
-        la.degs = learned ? degs : nullptr;  // the rules kernel also gives each box's post degree
-        la.cap = cap;
-        la.fp64 = p.fp64 ? 1 : 0;
-        la.L = p.L;
-        if (learned)
-          BERN_HIP_TRY(launch_learned_rules(la, s));
-        else
-          BERN_HIP_TRY(launch_features(la, s));
-      }
+    }
+    // predictor and rules (learned plans), or the exported features: one
+    // launch over the wave's boxes, every record holding its own degree
+    if (!last && (learned || o->features)) {
+      LearnArgs la{};
+      la.n = n;
+      la.h = h;
+      la.H = p.H;
+      la.layer = i;
+      la.nboxes = B;
+      la.bids = nullptr;
+      la.recs = recs;
+      la.sens = net->sens + net->noff[i];
+      la.feat = o->features ? o->features + (size_t)b0 * net->nh * 8 : nullptr;
+      la.nh = net->nh;
+      la.noff = net->noff[i];
+      la.params = learned ? o->pred->params : nullptr;
+      la.codes = codes;
+      la.used = used;
+      la.degs = learned ? degs : nullptr;  // the rules kernel also gives each box's post degree
+      la.cap = cap;
+      la.fp64 = p.fp64 ? 1 : 0;
+      la.L = p.L;
+      if (learned)
+        BERN_HIP_TRY(launch_learned_rules(la, s));
+      else
+        BERN_HIP_TRY(launch_features(la, s));
     }
     if (last) break;
 

@@ -88,7 +88,7 @@ struct alignas(64) NeuronRec {
   double fitU[kMaxInputs + 1], fitL[kMaxInputs + 1];
   double rmaxU, rminU, rmaxL, rminL;
   int32_t fitted;
-  int32_t pad_;
+  int32_t dpre;            // per-variable degree of the stored pre-activation polynomials
 };
 
 // Rounding-error helpers (FP32 mode). gamma(m) = m u / (1 - m u) for FP64.
@@ -288,7 +288,7 @@ size_t compose_scratch_bytes(int64_t Cq, int Lmax, int h, int64_t nboxes);
 size_t device_lds_limit();
 
 struct LearnArgs {
-  int n, D, h, H, layer;
+  int n, h, H, layer;
   int64_t nboxes;
   const int *bids;
   NeuronRec *recs;                // [B][h]

@@ -259,6 +259,7 @@ __device__ void record_neuron(const ConvertArgs &a, int64_t box, int j, double l
   r.l1U = l1U;
   r.l1L = l1L;
   r.fitted = fitted ? 1 : 0;
+  r.dpre = a.D;
   if (!fitted && !fits_written) {
     for (int q = 0; q <= kMaxInputs; ++q) r.fitU[q] = r.fitL[q] = 0.0;
   }

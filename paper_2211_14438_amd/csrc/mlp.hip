@@ -176,7 +176,7 @@ __device__ void neuron_features(const LearnArgs &a, const NeuronRec &r, int j, f
   f[0] = (float)(-r.lo * iw);
   f[1] = (float)log(w);
   f[2] = a.H > 1 ? (float)a.layer / (float)(a.H - 1) : 0.f;
-  f[3] = logf((float)a.D + 1.f);
+  f[3] = logf((float)r.dpre + 1.f);
   f[4] = r.fitted ? (float)((r.fitU[0] - r.fitL[0]) * iw) : 0.f;
   f[5] = (float)log(fmax(a.sens[j] * w, 1e-30));
   f[6] = r.fitted ? (float)(((r.rmaxU - r.rminU) + (r.rmaxL - r.rminL)) * iw) : 0.f;
@@ -301,7 +301,7 @@ __global__ void __launch_bounds__(256) learned_rules_kernel(LearnArgs a) {
       else if (top == 1 && c == 0) c = 1;
       cl[j] = (int8_t)c;
     }
-    decide_neuron(r, c < 0 ? 1 : c, false, a.L, a.n, a.D, a.cap, a.fp64);
+    decide_neuron(r, c < 0 ? 1 : c, false, a.L, a.n, r.dpre, a.cap, a.fp64);
     if (a.used) a.used[box * a.nh + a.noff + j] = (int8_t)r.kind;
     deg = max(deg, r.deg);
   }
