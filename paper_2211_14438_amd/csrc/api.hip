@@ -702,6 +702,17 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
     std::vector<const int *> pid;
     st = upload(next, i, 1, pid);
     if (st != BERN_OK) return st;
+    // several classes: the next affine map's input lists of every box at once
+    const bool lists_once = next.size() > 1;
+    if (lists_once) {
+      ComposeArgs ml{};
+      ml.h = h;
+      ml.nboxes = B;
+      ml.recs = recs;
+      ml.live = live;
+      ml.live_ld = live_ld;
+      BERN_HIP_TRY(launch_live(ml, s));
+    }
     for (size_t k = 0; k < next.size(); ++k) {
       const BoxClass &cl = next[k];
       // composition -> post tensors in arena B
@@ -745,6 +756,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       m.part = p.fp64 ? nullptr : cpart;
       m.live = live;
       m.live_ld = live_ld;
+      m.lists_ready = lists_once ? 1 : 0;
       BERN_HIP_TRY(launch_compose(m, s));
       // affine map of the next layer -> pre-activation tensors in arena A
       GemmArgs a{};

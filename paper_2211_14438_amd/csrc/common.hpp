@@ -257,7 +257,8 @@ struct ComposeArgs {
   double *part;                   // FP32 mode: [B*h*nbounds][nbx][2] (rounding sum, l1 sum) per block
   int64_t nbx;                    // blocks per item of every compose launch of the layer
   int nbounds;                    // 2 (upper, lower) for the network, 1 for plain products
-  int group;                      // set by the launcher: waves take 64 items each (for_wave_items)
+  int group;                      // set by the launcher: items per wave (for_wave_items)
+  int lists_ready;                // the live lists were built for every box (launch_live)
   int Lmax;                       // largest ReLU order any neuron of the launch may use
   int64_t Cin, Cout, nboxes;      // stored coefficients at degrees Din and Dout
   int64_t Cs;                     // stored coefficients of degree-preserving posts (degree min(Din, Dout))
@@ -280,6 +281,10 @@ struct ComposeArgs {
   int64_t live_ld;
 };
 hipError_t launch_compose(const ComposeArgs &a, hipStream_t s);
+// The input lists (ComposeArgs::live) of a.nboxes boxes (bids, h, recs,
+// live, live_ld used) in one launch; launch_compose then skips them when
+// a.lists_ready is set.
+hipError_t launch_live(const ComposeArgs &a, hipStream_t s);
 // Blocks per item the compose launches of a layer use (partials stride).
 int64_t compose_nbx(int64_t Cout);
 size_t compose_scratch_bytes(int64_t Cq, int Lmax, int h, int64_t nboxes);

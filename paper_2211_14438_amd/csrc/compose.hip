@@ -767,7 +767,7 @@ static hipError_t compose_all(const ComposeArgs &a_in, hipStream_t s) {
   // square (heavier items, which the group's wave takes one after another)
   const int64_t items_all = a.nboxes * a.h * a.nbounds;
   const bool group = items_all >= 65536;
-  if (a.live) {
+  if (a.live && !a.lists_ready) {
     ProfScope ps(kProfMisc, s, 0.0);
     hipLaunchKernelGGL(live_kernel, dim3((unsigned)((a.nboxes + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), 0,
                        s, a);
@@ -811,6 +811,14 @@ static hipError_t compose_all(const ComposeArgs &a_in, hipStream_t s) {
     RET_IF(hipGetLastError());
   }
   return hipSuccess;
+}
+
+hipError_t launch_live(const ComposeArgs &a, hipStream_t s) {
+  if (!a.live || a.nboxes < 1) return hipErrorInvalidValue;
+  ProfScope ps(kProfMisc, s, 0.0);
+  hipLaunchKernelGGL(live_kernel, dim3((unsigned)((a.nboxes + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), 0, s,
+                     a);
+  return hipGetLastError();
 }
 
 hipError_t launch_compose(const ComposeArgs &a, hipStream_t s) {
