@@ -172,6 +172,29 @@ bern_status bern_bounds(const bern_net *net, const bern_opts *opts, int64_t n_bo
                         int8_t *used_plan, void *workspace, size_t ws_bytes, void *stream,
                         bern_stats *stats);
 
+/* The output polynomials themselves (Problem 1 asks for polynomial bounds;
+ * the output intervals follow from them): for every box and output neuron,
+ * the upper and lower polynomials U(t) >= f(x(t)) >= L(t) on t in [0,1]^n,
+ * x_a = d_lo_a + (d_hi_a - d_lo_a) t_a, as dense power tensors at
+ * per-variable degree `degree`:
+ *   poly_U, poly_L   device, [n_boxes][h_H][(degree+1)^n] FP64, coefficient
+ *                    of t^e at sum_a e_a (degree+1)^(n-1-a); zero where a
+ *                    box's own degree is lower. In FP32 mode the stored
+ *                    coefficients' radii are folded into the constant
+ *                    coefficient (rounded outward), so both stay bounds.
+ *   degree           at least every box's output degree (the plain rule:
+ *                    L^(H-1); bern_stats.out_degree of a bern_bounds run
+ *                    with the same options)
+ * The other arguments are bern_bounds' (out_lo/out_hi as there); the hidden
+ * layers' outputs are not written. Asynchronous on `stream`; never replayed
+ * from a graph.
+ * Errors: those of bern_bounds; BERN_E_DEGREE when a box's output degree
+ * exceeds `degree`; BERN_E_TOO_LARGE when (degree+1)^n exceeds 2^31. */
+bern_status bern_output_polys(const bern_net *net, const bern_opts *opts, int64_t n_boxes,
+                              const double *box_lo, const double *box_hi, const int8_t *plan, int32_t degree,
+                              double *poly_U, double *poly_L, double *out_lo, double *out_hi, void *workspace,
+                              size_t ws_bytes, void *stream);
+
 /* bern_bounds on host memory, synchronous (the same computation, Problem 1):
  * box_lo, box_hi, plan and every output are host arrays with bern_bounds'
  * shapes (plan, neuron_lo/hi and used_plan nullable as there). The library

@@ -76,6 +76,9 @@ def lib():
     L.bern_bounds.restype = i32
     L.bern_bounds.argtypes = [_vp, ctypes.POINTER(bern_opts), i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, sz,
                               _vp, ctypes.POINTER(bern_stats)]
+    L.bern_output_polys.restype = i32
+    L.bern_output_polys.argtypes = [_vp, ctypes.POINTER(bern_opts), i64, _vp, _vp, _vp, i32, _vp, _vp, _vp, _vp, _vp,
+                                    sz, _vp]
     L.bern_bounds_host.restype = i32
     L.bern_bounds_host.argtypes = [_vp, ctypes.POINTER(bern_opts), i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                    ctypes.POINTER(bern_stats)]
@@ -322,6 +325,25 @@ def bounds(net, box_lo, box_hi, L=2, precision="fp64", plan="plain", sched="per_
                         workspace_used=st.workspace_used)
     res["workspace"] = workspace
     return res
+
+
+def output_polys(net, box_lo, box_hi, degree, L=2, precision="fp64", plan="plain", sched="batched",
+                 degree_plan=None, max_wave=0, pred=None, stream=None):
+    """The output polynomials of every box as dense power tensors in t at
+    per-variable ``degree``: a dict with ``U`` and ``L`` (float64 CUDA
+    tensors [n_boxes, n_out, (degree+1)^n]) and the output bounds
+    ``out_lo``/``out_hi``. Asynchronous on ``stream``."""
+    import torch
+    args, res, workspace, keep = _prepare(net, box_lo, box_hi, L, precision, plan, sched, degree_plan, max_wave,
+                                          None, None, pred, None, False)
+    nb, dev = box_lo.shape[0], box_lo.device
+    C = (int(degree) + 1) ** net.n
+    U = torch.empty((nb, net.n_out, C), dtype=torch.float64, device=dev)
+    Lw = torch.empty((nb, net.n_out, C), dtype=torch.float64, device=dev)
+    # args: handle, opts, nb, lo, hi, plan, neuron_lo, neuron_hi, out_lo, out_hi, used, ws, ws_bytes
+    _check(lib().bern_output_polys(args[0], args[1], args[2], args[3], args[4], args[5], int(degree), _ptr(U),
+                                   _ptr(Lw), args[8], args[9], args[11], args[12], _stream(stream)))
+    return dict(U=U, L=Lw, out_lo=res["out_lo"], out_hi=res["out_hi"], workspace=workspace)
 
 
 def bounds_host(net, box_lo, box_hi, L=2, precision="fp64", plan="plain", sched="batched", degree_plan=None,

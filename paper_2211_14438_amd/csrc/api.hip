@@ -115,9 +115,9 @@ struct Plan {
   size_t elem;
   std::vector<int64_t> nbx;         // compose blocks per item, hidden layers
   // per-box bytes of each region
-  size_t recs, rad, arenaA, arenaB, conv, horner, flags, gpart, cpart, live;
+  size_t recs, rad, arenaA, arenaB, conv, horner, flags, gpart, cpart, live, oeps;
   size_t per_box() const {
-    return 2 * recs + 2 * rad + 2 * arenaA + arenaB + conv + horner + flags + gpart + cpart + live;
+    return 2 * recs + 2 * rad + 2 * arenaA + arenaB + conv + horner + flags + gpart + cpart + live + oeps;
   }
 };
 
@@ -225,6 +225,7 @@ static bern_status plan_net(const bern_net *net, const bern_opts *o, Plan &p) {
   p.flags = align256(sizeof(int) * (2 + 2 * (size_t)p.H) + (size_t)net->nh);
   p.live = align256(sizeof(int) * (3 + 3 * (size_t)net->hmax));
   p.rad = align256(sizeof(double) * 4 * (size_t)net->hmax);
+  p.oeps = align256(sizeof(double) * 2 * (size_t)net->o);
   return BERN_OK;
 }
 
@@ -487,9 +488,19 @@ struct BoxClass {
 // per-neuron degrees read each box's post degree back once per hidden layer
 // and launch each degree class of boxes on its own (a box's tensors stay
 // dense at the box's own degree inside its fixed slot).
+// Output polynomials requested by bern_output_polys: dense power tensors at
+// per-variable degree D (C = (D+1)^n coefficients each), [n_boxes][o][C].
+struct OutPolys {
+  double *U, *L;
+  int D;
+  int64_t C;
+  const int *didx;  // rank -> dense index at degree D
+};
+
 static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts *o, int64_t b0, int64_t B,
                             const double *box_lo, const double *box_hi, const int8_t *plan, double *nlo, double *nhi,
-                            double *olo, double *ohi, int8_t *used, char *ws, hipStream_t s) {
+                            double *olo, double *ohi, int8_t *used, char *ws, hipStream_t s,
+                            const OutPolys *op = nullptr) {
   char *cur = ws;
   NeuronRec *recbuf[2];
   recbuf[0] = reinterpret_cast<NeuronRec *>(cur); cur += p.recs * B;
@@ -509,6 +520,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
   double *conv = reinterpret_cast<double *>(cur); cur += p.conv * B;
   void *horner = cur; cur += p.horner * B;
   int *live = reinterpret_cast<int *>(cur); cur += p.live * B;
+  double *oeps = reinterpret_cast<double *>(cur); cur += p.oeps * B;
   const int64_t live_ld = (int64_t)(p.live / sizeof(int));
   int *flags = reinterpret_cast<int *>(cur);
   int *degs = flags + B;
@@ -636,6 +648,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
         c.ld_out = net->o;
         c.col0 = 0;
         c.used = nullptr;
+        c.out_eps = (op && !p.fp64) ? oeps : nullptr;
       } else {
         c.mode = 0;
         c.out_lo = nlo;
@@ -673,7 +686,32 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       else
         BERN_HIP_TRY(launch_features(la, s));
     }
-    if (last) break;
+    if (last) {
+      if (op) {  // the output layer's stored tensors, per class, into the caller's dense tensors
+        for (size_t k = 0; k < classes.size(); ++k) {
+          const BoxClass &cl = classes[k];
+          if (cl.Din > op->D) {
+            set_error("output degree %d of some box exceeds the requested %d", cl.Din, op->D);
+            return BERN_E_DEGREE;
+          }
+          OutPolyArgs a{};
+          a.pre = Aa[i & 1];
+          a.slot = slotA;
+          a.S = ssize(n, cl.Din);
+          a.C = op->C;
+          a.didx = op->didx;
+          a.bids = cid[k];
+          a.nboxes = (int64_t)cl.ids.size();
+          a.h = h;
+          a.eps = p.fp64 ? nullptr : oeps;
+          a.fp64 = p.fp64 ? 1 : 0;
+          a.U = op->U + (size_t)b0 * h * op->C;
+          a.L = op->L + (size_t)b0 * h * op->C;
+          BERN_HIP_TRY(launch_out_polys(a, s));
+        }
+      }
+      break;
+    }
 
     // post degree of every box -> classes (Din, Dout)
     std::vector<BoxClass> next;
@@ -856,10 +894,10 @@ static bern_status run_graph(bern_net *net, const bern_opts *o, int64_t n_boxes,
   return BERN_OK;
 }
 
-extern "C" bern_status bern_bounds(const bern_net *net, const bern_opts *opts, int64_t n_boxes, const double *box_lo,
-                                   const double *box_hi, const int8_t *plan, double *neuron_lo, double *neuron_hi,
-                                   double *out_lo, double *out_hi, int8_t *used_plan, void *workspace,
-                                   size_t ws_bytes, void *stream, bern_stats *stats) {
+static bern_status bounds_impl(const bern_net *net, const bern_opts *opts, int64_t n_boxes, const double *box_lo,
+                               const double *box_hi, const int8_t *plan, double *neuron_lo, double *neuron_hi,
+                               double *out_lo, double *out_hi, int8_t *used_plan, void *workspace, size_t ws_bytes,
+                               void *stream, bern_stats *stats, const OutPolys *op) {
   bern_status st = check_opts(net, opts);
   if (st != BERN_OK) return st;
   if (n_boxes < 1 || !box_lo || !box_hi || !out_lo || !out_hi) {
@@ -895,7 +933,7 @@ extern "C" bern_status bern_bounds(const bern_net *net, const bern_opts *opts, i
                                plan ? plan + b0 * net->nh : nullptr, neuron_lo ? neuron_lo + b0 * net->nh : nullptr,
                                neuron_hi ? neuron_hi + b0 * net->nh : nullptr, out_lo + b0 * net->o,
                                out_hi + b0 * net->o, used_plan ? used_plan + b0 * net->nh : nullptr,
-                               reinterpret_cast<char *>(workspace), rs);
+                               reinterpret_cast<char *>(workspace), rs, op);
       if (r != BERN_OK) return r;
     }
     return BERN_OK;
@@ -903,7 +941,7 @@ extern "C" bern_status bern_bounds(const bern_net *net, const bern_opts *opts, i
   // Runs with no host round trip (the plain rule) can be captured once and
   // replayed as one graph launch; plans with per-neuron degrees read every
   // box's degree back once per hidden layer and always run eagerly.
-  if (opts->graph && p.mode == BERN_PLAN_PLAIN) {
+  if (opts->graph && p.mode == BERN_PLAN_PLAIN && !op) {
     // index tables are built (device allocations) before any capture
     for (int i = 0; i < p.H; ++i) {
       LayerTables lt;
@@ -928,6 +966,40 @@ extern "C" bern_status bern_bounds(const bern_net *net, const bern_opts *opts, i
     stats->workspace_used = per_box * (size_t)wave;
   }
   return BERN_OK;
+}
+
+extern "C" bern_status bern_bounds(const bern_net *net, const bern_opts *opts, int64_t n_boxes, const double *box_lo,
+                                   const double *box_hi, const int8_t *plan, double *neuron_lo, double *neuron_hi,
+                                   double *out_lo, double *out_hi, int8_t *used_plan, void *workspace,
+                                   size_t ws_bytes, void *stream, bern_stats *stats) {
+  return bounds_impl(net, opts, n_boxes, box_lo, box_hi, plan, neuron_lo, neuron_hi, out_lo, out_hi, used_plan,
+                     workspace, ws_bytes, stream, stats, nullptr);
+}
+
+extern "C" bern_status bern_output_polys(const bern_net *net, const bern_opts *opts, int64_t n_boxes,
+                                         const double *box_lo, const double *box_hi, const int8_t *plan,
+                                         int32_t degree, double *poly_U, double *poly_L, double *out_lo,
+                                         double *out_hi, void *workspace, size_t ws_bytes, void *stream) {
+  bern_status st = check_opts(net, opts);
+  if (st != BERN_OK) return st;
+  if (!poly_U || !poly_L || degree < 1) {
+    set_error("bern_output_polys needs both polynomial arrays and a degree >= 1 (got %d)", degree);
+    return BERN_E_ARG;
+  }
+  const int64_t C = tsize(net->n, degree);
+  if (C < 0 || C > ((int64_t)1 << 31)) {
+    set_error("(%d+1)^%d dense coefficients overflow", degree, net->n);
+    return BERN_E_TOO_LARGE;
+  }
+  OutPolys op{poly_U, poly_L, degree, C, nullptr};
+  hipError_t e = dense_index_table(*net->tab, degree, &op.didx);
+  if (e == hipErrorInvalidValue) {
+    set_error("index table for degree %d in %d variables exceeds its limits", degree, net->n);
+    return BERN_E_TOO_LARGE;
+  }
+  BERN_HIP_TRY(e);
+  return bounds_impl(net, opts, n_boxes, box_lo, box_hi, plan, nullptr, nullptr, out_lo, out_hi, nullptr, workspace,
+                     ws_bytes, stream, nullptr, &op);
 }
 
 // ------------------------------------------------- host-memory convenience

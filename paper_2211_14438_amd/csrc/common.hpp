@@ -220,6 +220,7 @@ struct ConvertArgs {
   int64_t rpart_slot;             //   [h][2][cblocks] (layer > 0)
   int64_t cblocks;
   double *out_lo, *out_hi;        // [B][ld_out] bounds written at column col0 + j
+  double *out_eps;                // mode 1, optional: [B][h][2] radii (epsU, epsL) of the output tensors
   int64_t ld_out, col0;
   int8_t *used;                   // [B][ld_out] or null (hidden layers)
   const int8_t *plan;             // [B][plan_ld] degree codes or null (plain rule)
@@ -245,6 +246,22 @@ struct ConvertArgs {
   int plist_len;
 };
 hipError_t launch_convert(const ConvertArgs &a, hipStream_t s);
+
+// The output layer's stored tensors of one class as dense power tensors at a
+// caller's degree: [box][j][C] in U (upper) and L (lower), zero beyond the
+// stored degree, the radii (FP32 mode) folded into the constant term.
+struct OutPolyArgs {
+  const void *pre;    // the output layer's pre-activation arena, [B][h][2][S] per box slot
+  int64_t slot, S, C;
+  const int *didx;    // rank -> dense index at the caller's degree
+  const int *bids;
+  int64_t nboxes;
+  int h;
+  const double *eps;  // [B][h][2] or null (FP64)
+  int fp64;
+  double *U, *L;      // [B][h][C], wave boxes
+};
+hipError_t launch_out_polys(const OutPolyArgs &a, hipStream_t s);
 size_t convert_scratch_bytes(int n, int D, int h, int64_t nboxes);
 // Whether tensors of n variables and degree D take the tree read-off (they
 // then need the TreeTable of degree D).

@@ -244,6 +244,18 @@ __device__ void padded_bounds(const ConvertArgs &a, int64_t box, int j, double m
   hi = round_up(mx + g * l1U + epsU);
 }
 
+// An output neuron's bounds (thread 0 only) and, when the caller takes the
+// output polynomials, the radii of its two stored tensors.
+__device__ inline void write_output(const ConvertArgs &a, int64_t box, int j, double lo, double hi, double epsU,
+                                    double epsL) {
+  a.out_lo[box * a.ld_out + a.col0 + j] = lo;
+  a.out_hi[box * a.ld_out + a.col0 + j] = hi;
+  if (a.out_eps) {
+    a.out_eps[(box * a.h + j) * 2 + 0] = epsU;
+    a.out_eps[(box * a.h + j) * 2 + 1] = epsL;
+  }
+}
+
 // Record of one hidden neuron after its read-off (thread 0 only), then its
 // rule unless a predictor chooses it later. Fitted neurons' affine fits are
 // already in the record; the others get zeros unless the caller skips them
@@ -338,8 +350,7 @@ __global__ void __launch_bounds__(kBlock) convert_small_kernel(ConvertArgs a) {
                 [&](double v) { return block_reduce(v, OpAdd(), red); }, lo, hi, epsU, epsL);
   if (threadIdx.x == 0) {
     if (a.mode == 1) {
-      a.out_lo[box * a.ld_out + a.col0 + j] = lo;
-      a.out_hi[box * a.ld_out + a.col0 + j] = hi;
+      write_output(a, box, j, lo, hi, epsU, epsL);
     } else {
       if (a.out_lo) a.out_lo[box * a.ld_out + a.col0 + j] = lo;
       if (a.out_hi) a.out_hi[box * a.ld_out + a.col0 + j] = hi;
@@ -466,8 +477,7 @@ __global__ void __launch_bounds__(kBlock) convert_wave_kernel(ConvertArgs a) {
   }
   if (lane == 0) {
     if (a.mode == 1) {
-      a.out_lo[box * a.ld_out + a.col0 + j] = lo;
-      a.out_hi[box * a.ld_out + a.col0 + j] = hi;
+      write_output(a, box, j, lo, hi, epsU, epsL);
     } else {
       if (a.out_lo) a.out_lo[box * a.ld_out + a.col0 + j] = lo;
       if (a.out_hi) a.out_hi[box * a.ld_out + a.col0 + j] = hi;
@@ -859,8 +869,7 @@ __device__ inline void write_neuron(const ConvertArgs &a, int64_t box, int j, do
                                     double epsL, double l1U, double l1L, const double *ext, bool fitted,
                                     bool fits_written = false) {
   if (a.mode == 1) {
-    a.out_lo[box * a.ld_out + a.col0 + j] = lo;
-    a.out_hi[box * a.ld_out + a.col0 + j] = hi;
+    write_output(a, box, j, lo, hi, epsU, epsL);
   } else {
     if (a.out_lo) a.out_lo[box * a.ld_out + a.col0 + j] = lo;
     if (a.out_hi) a.out_hi[box * a.ld_out + a.col0 + j] = hi;
@@ -1897,8 +1906,7 @@ __global__ void __launch_bounds__(kBlock) convert_final_kernel(ConvertArgs a, Sp
                 epsU, epsL);
   if (lane != 0) return;
   if (a.mode == 1) {
-    a.out_lo[box * a.ld_out + a.col0 + j] = lo;
-    a.out_hi[box * a.ld_out + a.col0 + j] = hi;
+    write_output(a, box, j, lo, hi, epsU, epsL);
   } else {
     if (a.out_lo) a.out_lo[box * a.ld_out + a.col0 + j] = lo;
     if (a.out_hi) a.out_hi[box * a.ld_out + a.col0 + j] = hi;
@@ -2035,6 +2043,42 @@ size_t convert_scratch_bytes(int n, int D, int h, int64_t nboxes) {
   return align256((size_t)nboxes * h * 2 * C * sizeof(double)) +
          align256((size_t)nboxes * h * 2 * sp.nchunk * sizeof(double)) +
          align256((size_t)nboxes * h * 2 * sp.Co * sizeof(double));
+}
+
+// One block per (box, output neuron, bound): zero the dense tensor, then
+// place the stored coefficients at their dense positions (rank 0, the
+// constant, widened by the tensor's radius in FP32 mode and rounded
+// outward, so the polynomial stays a bound).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) out_polys_kernel(OutPolyArgs a) {
+  const int64_t item = blockIdx.x;
+  const int side = (int)(item & 1);
+  const int64_t gj = item >> 1, g = gj / a.h;
+  const int j = (int)(gj - g * a.h);
+  const int64_t box = a.bids ? a.bids[g] : g;
+  double *dst = (side == 0 ? a.U : a.L) + (box * a.h + j) * a.C;
+  for (int64_t i = threadIdx.x; i < a.C; i += blockDim.x) dst[i] = 0.0;
+  __syncthreads();
+  const T *src = reinterpret_cast<const T *>(a.pre) + box * a.slot + ((int64_t)j * 2 + side) * a.S;
+  for (int64_t r = threadIdx.x; r < a.S; r += blockDim.x) {
+    double v = (double)src[r];
+    if (r == 0 && a.eps) {
+      const double e = a.eps[(box * a.h + j) * 2 + side];
+      v = side == 0 ? round_up(v + e) : round_down(v - e);
+    }
+    dst[a.didx[r]] = v;
+  }
+}
+
+hipError_t launch_out_polys(const OutPolyArgs &a, hipStream_t s) {
+  if (a.nboxes < 1) return hipSuccess;
+  if (a.S > a.C || !a.didx || !a.U || !a.L) return hipErrorInvalidValue;
+  const int64_t blocks = a.nboxes * a.h * 2;
+  if (a.fp64)
+    hipLaunchKernelGGL(out_polys_kernel<double>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(out_polys_kernel<float>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_convert(const ConvertArgs &a_in, hipStream_t s) {

@@ -248,6 +248,61 @@ def test_large_output_two_pass_fp32_and_fp64():
     _assert_fp32(g32, o, case.n_hidden)
 
 
+def _power_basis(n, d, t):
+    """[m, (d+1)^n] monomials t^e, e at sum_a e_a (d+1)^(n-1-a)."""
+    idx = np.arange((d + 1) ** n)
+    out = np.ones((t.shape[0], idx.size))
+    for a in range(n):
+        e = (idx // (d + 1) ** (n - 1 - a)) % (d + 1)
+        out *= t[:, a:a + 1] ** e[None, :]
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_output_polys_match_oracle_and_enclose_the_network(precision):
+    """The output polynomials (Problem 1): in Bernstein form they are the
+    oracle's output tensors (FP64 1e-9, FP32 1e-4 of the tensor's size), they
+    enclose the network at sampled points, their Bernstein extrema are the
+    reported output bounds, and a higher requested degree only zero-pads."""
+    case = wl.random_net_case([3, 6, 5, 2], seed=88, n_boxes=3)
+    net = B.Net(case.Ws, case.bs)
+    lo = torch.tensor(case.box_lo, dtype=torch.float64, device=DEV)
+    hi = torch.tensor(case.box_hi, dtype=torch.float64, device=DEV)
+    d, n = 4, case.n  # L^(H-1) for L = 2, H = 3
+    r = B.output_polys(net, lo, hi, d, L=2, precision=precision)
+    r5 = B.output_polys(net, lo, hi, d + 1, L=2, precision=precision)
+    torch.cuda.synchronize()
+    U, Lp = r["U"].cpu().numpy(), r["L"].cpu().numpy()
+    U5 = r5["U"].cpu().numpy()
+    olo, ohi = r["out_lo"].cpu().numpy(), r["out_hi"].cpu().numpy()
+    with pytest.raises(B.BernError):
+        B.output_polys(net, lo, hi, d - 1, L=2, precision=precision)
+    net.close()
+    tol = 1e-9 if precision == "fp64" else 1e-4
+    rng = np.random.default_rng(1)
+    for i in range(case.n_boxes):
+        o = orc.network(case.Ws, case.bs, case.box_lo[i], case.box_hi[i], L=2, want_polys=True)
+        assert o["out_deg"] == d
+        for j in range(U.shape[1]):
+            bu, bl = orc.power_to_bern(n, d, U[i, j]), orc.power_to_bern(n, d, Lp[i, j])
+            scale = max(np.abs(o["out_U"][j]).max(), np.abs(o["out_L"][j]).max(), 1e-300)
+            assert np.max(np.abs(bu - o["out_U"][j])) <= tol * scale
+            assert np.max(np.abs(bl - o["out_L"][j])) <= tol * scale
+            # the read-off of these tensors gives the bounds (FP32: within the read-off pad)
+            assert abs(bu.max() - ohi[i, j]) <= tol * scale and abs(bl.min() - olo[i, j]) <= tol * scale
+            # degree d + 1: the same polynomial, zero-padded
+            e = np.arange((d + 2) ** n)
+            digits = [(e // (d + 2) ** (n - 1 - a)) % (d + 2) for a in range(n)]
+            low = np.all([dg <= d for dg in digits], axis=0)
+            dense_d = sum(dg * (d + 1) ** (n - 1 - a) for a, dg in enumerate(digits))
+            assert np.array_equal(U5[i, j][~low], np.zeros((~low).sum()))
+            assert np.array_equal(U5[i, j][low], U[i, j][dense_d[low]])
+        t, x = H.box_points(case.box_lo[i], case.box_hi[i], 2000, rng)
+        f = H.forward(case.Ws, case.bs, x)[-1]
+        P = _power_basis(n, d, t)
+        assert np.all(P @ Lp[i].T <= f + 1e-9) and np.all(f <= P @ U[i].T + 1e-9)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_bounds_host_equals_device_run(precision):
     """The host-memory entry point gives the device entry point's bits (same
