@@ -201,7 +201,7 @@ __global__ void __launch_bounds__(256) features_kernel(LearnArgs a) {
 // and taken four threads each: every thread computes the first layer and a
 // quarter of the second layer's units with their share of the output layer,
 // and the four shares are added in a fixed order.
-constexpr int kClassItems = 64;  // items per block of learned_classes_kernel (4 threads each)
+constexpr int kClassItems = 256;  // items per block of learned_classes_kernel (4 threads each)
 
 __global__ void __launch_bounds__(4 * kClassItems) learned_classes_kernel(LearnArgs a) {
   __shared__ float w[kParams];
