@@ -539,6 +539,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
   BERN_HIP_TRY(hipGetLastError());
 
   // degree classes of the current layer's pre-activations
+  std::vector<const int *> carried;  // device id lists the next layer's read-off can reuse
   std::vector<BoxClass> classes(1);
   classes[0].Din = 1;
   classes[0].Dout = 0;
@@ -593,8 +594,14 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
     for (int q = 0; q <= i; ++q) cap *= p.L;
     // bounds read-off (+ rules and approximants for hidden layers), per class
     std::vector<const int *> cid;
-    bern_status st = upload(classes, i, 0, cid);
-    if (st != BERN_OK) return st;
+    bern_status st = BERN_OK;
+    if (carried.size() == classes.size()) {
+      cid = carried;  // the previous layer's composition lists, same classes in the same order
+    } else {
+      st = upload(classes, i, 0, cid);
+      if (st != BERN_OK) return st;
+    }
+    carried.clear();
     for (size_t k = 0; k < classes.size(); ++k) {
       const BoxClass &cl = classes[k];
       ConvertArgs c{};
@@ -832,6 +839,8 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       nc[k].ids.insert(nc[k].ids.end(), cl.ids.begin(), cl.ids.end());
       for (int b : cl.ids) dcur[b] = cl.Dout;
     }
+    // no classes merged: the lists just uploaded serve the next read-off
+    if (nc.size() == next.size()) carried = pid;
     classes.swap(nc);
   }
   {
