@@ -798,10 +798,12 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       m.scratch = horner;
       m.scratch_bytes = p.horner * B;
       m.nbx = compose_nbx(m.Cout);
+      m.pstride = p.nbx[i];  // the layer's partial layout, the same for every class
       m.part = p.fp64 ? nullptr : cpart;
       m.live = live;
       m.live_ld = live_ld;
       m.lists_ready = lists_once ? 1 : 0;
+      m.radii_later = lists_once ? 1 : 0;
       BERN_HIP_TRY(launch_compose(m, s));
       // affine map of the next layer -> pre-activation tensors in arena A
       GemmArgs a{};
@@ -828,6 +830,21 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       a.rpart = p.fp64 ? nullptr : gpart;
       a.rpart_slot = (int64_t)(p.gpart / sizeof(double));
       BERN_HIP_TRY(launch_gemm(a, s));
+    }
+    // several classes: the post radii of every box at once
+    if (lists_once && !p.fp64) {
+      ComposeArgs mr{};
+      mr.n = n;
+      mr.h = h;
+      mr.nboxes = B;
+      mr.nbounds = 2;
+      mr.recs = recs;
+      mr.part = cpart;
+      mr.nbx = p.nbx[i];
+      mr.pstride = p.nbx[i];
+      mr.rad = radbuf[i & 1];
+      mr.fp64 = 0;
+      BERN_HIP_TRY(launch_post_radii(mr, s));
     }
     // next layer's classes: by the new pre degree
     std::vector<BoxClass> nc;

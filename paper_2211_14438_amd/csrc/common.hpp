@@ -276,6 +276,8 @@ struct ComposeArgs {
   int nbounds;                    // 2 (upper, lower) for the network, 1 for plain products
   int group;                      // set by the launcher: items per wave (for_wave_items)
   int lists_ready;                // the live lists were built for every box (launch_live)
+  int64_t pstride;                // partial slots per item (>= nbx; 0: nbx); the slots past nbx hold zeros
+  int radii_later;                // launch_post_radii runs once for all the layer's classes
   int Lmax;                       // largest ReLU order any neuron of the launch may use
   int64_t Cin, Cout, nboxes;      // stored coefficients at degrees Din and Dout
   int64_t Cs;                     // stored coefficients of degree-preserving posts (degree min(Din, Dout))
@@ -302,6 +304,9 @@ hipError_t launch_compose(const ComposeArgs &a, hipStream_t s);
 // live, live_ld used) in one launch; launch_compose then skips them when
 // a.lists_ready is set.
 hipError_t launch_live(const ComposeArgs &a, hipStream_t s);
+// The post radii (FP32 mode) of a.nboxes boxes in one launch (n, h, bids,
+// recs, part, pstride or nbx, rad used), after every class's composition.
+hipError_t launch_post_radii(const ComposeArgs &a, hipStream_t s);
 // Blocks per item the compose launches of a layer use (partials stride).
 int64_t compose_nbx(int64_t Cout);
 size_t compose_scratch_bytes(int64_t Cq, int Lmax, int h, int64_t nboxes);

@@ -35,12 +35,15 @@ namespace bern {
 
 __host__ __device__ constexpr int cpow(int b, int e) { return e == 0 ? 1 : b * cpow(b, e - 1); }
 
-// launch-local item index of (launch box g, neuron j, bound s)
+__device__ inline int64_t wave_box(const ComposeArgs &a, int64_t g) { return a.bids ? a.bids[g] : g; }
+
+// item index of (launch box g, neuron j, bound s) among the wave's boxes
 __device__ inline int64_t item_of(const ComposeArgs &a, int64_t g, int j, int s) {
-  return (g * a.h + j) * a.nbounds + s;
+  return (wave_box(a, g) * a.h + j) * a.nbounds + s;
 }
 
-__device__ inline int64_t wave_box(const ComposeArgs &a, int64_t g) { return a.bids ? a.bids[g] : g; }
+// partial slots per item: every class of a layer uses the layer's stride
+__device__ inline int64_t pslots(const ComposeArgs &a) { return a.pstride > 0 ? a.pstride : a.nbx; }
 
 template <typename T>
 __device__ inline const T *in_tensor(const ComposeArgs &a, int64_t box, int j, int s) {
@@ -71,8 +74,11 @@ __device__ void block_partials_slot(const ComposeArgs &a, int64_t it, int64_t sl
       sr += red[w][0];
       sl += red[w][1];
     }
-    a.part[(it * a.nbx + slot) * 2 + 0] = sr;
-    a.part[(it * a.nbx + slot) * 2 + 1] = sl;
+    a.part[(it * pslots(a) + slot) * 2 + 0] = sr;
+    a.part[(it * pslots(a) + slot) * 2 + 1] = sl;
+    if (slot == 0)  // the slots past this class's blocks
+      for (int64_t b = a.nbx; b < pslots(a); ++b) a.part[(it * pslots(a) + b) * 2 + 0] =
+                                                     a.part[(it * pslots(a) + b) * 2 + 1] = 0.0;
   }
 }
 
@@ -87,9 +93,9 @@ __device__ void wave_partials(const ComposeArgs &a, int64_t it, double r, double
     l1 += __shfl_xor(l1, off, 64);
   }
   const int lane = threadIdx.x & 63;
-  for (int64_t b = lane; b < a.nbx; b += 64) {
-    a.part[(it * a.nbx + b) * 2 + 0] = b == 0 ? r : 0.0;
-    a.part[(it * a.nbx + b) * 2 + 1] = b == 0 ? l1 : 0.0;
+  for (int64_t b = lane; b < pslots(a); b += 64) {
+    a.part[(it * pslots(a) + b) * 2 + 0] = b == 0 ? r : 0.0;
+    a.part[(it * pslots(a) + b) * 2 + 1] = b == 0 ? l1 : 0.0;
   }
 }
 
@@ -535,11 +541,14 @@ __device__ void sq2_item(const ComposeArgs &a, int64_t g, int j, int s, int bx, 
       rsum += __shfl_xor(rsum, off, 64);
       l1sum += __shfl_xor(l1sum, off, 64);
     }
+    const int64_t it = item_of(a, g, j, s);
     if (lane == 0) {
-      const int64_t it = item_of(a, g, j, s);
-      a.part[(it * a.nbx + bx) * 2 + 0] = rsum;
-      a.part[(it * a.nbx + bx) * 2 + 1] = l1sum;
+      a.part[(it * pslots(a) + bx) * 2 + 0] = rsum;
+      a.part[(it * pslots(a) + bx) * 2 + 1] = l1sum;
     }
+    if (bx == 0)  // the slots past this class's chunks
+      for (int64_t b = a.nbx + lane; b < pslots(a); b += 64)
+        a.part[(it * pslots(a) + b) * 2 + 0] = a.part[(it * pslots(a) + b) * 2 + 1] = 0.0;
   }
 }
 
@@ -607,15 +616,20 @@ __global__ void __launch_bounds__(kBlock) compose_hz_kernel(ComposeArgs a, int m
 __global__ void post_radii_kernel(ComposeArgs a, NeuronRec *recs) {
   const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (item >= a.nboxes * a.h) return;
-  NeuronRec &r = recs[wave_box(a, item / a.h) * a.h + item % a.h];
+  const int64_t box = wave_box(a, item / a.h);
+  const int j = (int)(item % a.h);
+  NeuronRec &r = recs[box * a.h + j];
   const int kind = r.kind;
+  // coefficients of the stored pre-activation tensors (degree r.dpre)
+  double cin = 1.0;
+  for (int q = 1; q <= a.n; ++q) cin = cin * (r.dpre + q) / q;
   for (int s = 0; s < 2; ++s) {
-    const int64_t it = item * 2 + s;
+    const int64_t it = (box * a.h + j) * 2 + s;
     double rs = 0.0, l1 = 0.0;
     if (kind != kActive && kind != kInactive) {  // stored by one of the kernels above
-      for (int64_t b = 0; b < a.nbx; ++b) {
-        rs += a.part[(it * a.nbx + b) * 2 + 0];
-        l1 += a.part[(it * a.nbx + b) * 2 + 1];
+      for (int64_t b = 0; b < pslots(a); ++b) {
+        rs += a.part[(it * pslots(a) + b) * 2 + 0];
+        l1 += a.part[(it * pslots(a) + b) * 2 + 1];
       }
     }
     const double eps_pre = s == 0 ? r.epsU : r.epsL;
@@ -639,7 +653,7 @@ __global__ void post_radii_kernel(ComposeArgs a, NeuronRec *recs) {
         t3 += fabs(r.c[jj]) * pw;
         pw *= N;
       }
-      pad = rs + t1 + r.dB + gamma64((double)kind * ((double)a.Cin + 4.0)) * t3;
+      pad = rs + t1 + r.dB + gamma64((double)kind * (cin + 4.0)) * t3;
     }
     pad *= kPadSafety;
     if (s == 0) {
@@ -651,7 +665,7 @@ __global__ void post_radii_kernel(ComposeArgs a, NeuronRec *recs) {
     }
   }
   if (a.rad) {
-    double *q = a.rad + (wave_box(a, item / a.h) * a.h + item % a.h) * 4;
+    double *q = a.rad + (box * a.h + j) * 4;
     q[0] = r.padU;
     q[1] = r.padL;
     q[2] = r.pl1U;
@@ -804,13 +818,16 @@ static hipError_t compose_all(const ComposeArgs &a_in, hipStream_t s) {
       RET_IF(hipGetLastError());
     }
   }
-  if (a.part) {
-    ProfScope ps(kProfMisc, s, 0.0);
-    hipLaunchKernelGGL(post_radii_kernel, dim3((unsigned)((a.nboxes * a.h + 63) / 64)), dim3(64), 0, s, a,
-                       const_cast<NeuronRec *>(a.recs));
-    RET_IF(hipGetLastError());
-  }
+  if (a.part && !a.radii_later) RET_IF(launch_post_radii(a, s));
   return hipSuccess;
+}
+
+hipError_t launch_post_radii(const ComposeArgs &a, hipStream_t s) {
+  if (!a.part || !a.recs) return hipErrorInvalidValue;
+  ProfScope ps(kProfMisc, s, 0.0);
+  hipLaunchKernelGGL(post_radii_kernel, dim3((unsigned)((a.nboxes * a.h + 63) / 64)), dim3(64), 0, s, a,
+                     const_cast<NeuronRec *>(a.recs));
+  return hipGetLastError();
 }
 
 hipError_t launch_live(const ComposeArgs &a, hipStream_t s) {
