@@ -119,8 +119,8 @@ __device__ inline bool wave_item(const ComposeArgs &a, int64_t &g, int &j, int &
 
 // Many items, few of which need a kernel's work: a wave then takes a.group
 // (<= 64) consecutive items (`chunks` waves per group, chunk index c), reads
-// their kinds at once and runs f(g, j, s, c) for those that pass `need`, in
-// order. Without grouping (a.group <= 1) every wave has its own item, as in
+// their kinds at once and runs f(g, j, s, c) for those that pass
+// need(kind, s), in order. Without grouping (a.group <= 1) every wave has its own item, as in
 // wave_item. Either way an item's work is the same.
 
 template <class Need, class F>
@@ -129,7 +129,7 @@ __device__ inline void for_wave_items(const ComposeArgs &a, int chunks, Need nee
     int64_t g;
     int j, s, c = 0;
     if (!wave_item(a, g, j, s, chunks, &c)) return;
-    if (need(a.recs[wave_box(a, g) * a.h + j].kind)) f(g, j, s, c);
+    if (need(a.recs[wave_box(a, g) * a.h + j].kind, s)) f(g, j, s, c);
     return;
   }
   int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -142,8 +142,8 @@ __device__ inline void for_wave_items(const ComposeArgs &a, int chunks, Need nee
   bool mine = false;
   if (lane < a.group && i0 + lane < total) {
     const int64_t it = i0 + lane, g = it / per;
-    const int j = (int)((it - g * per) / a.nbounds);
-    mine = need(a.recs[wave_box(a, g) * a.h + j].kind);
+    const int rest = (int)(it - g * per);
+    mine = need(a.recs[wave_box(a, g) * a.h + rest / a.nbounds].kind, rest % a.nbounds);
   }
   unsigned long long todo = __ballot(mine);
   while (todo) {
@@ -474,7 +474,7 @@ __device__ void scatter_item(const ComposeArgs &a, int64_t g, int j, int s) {
 template <typename T>
 __global__ void __launch_bounds__(kBlock) compose_scatter_kernel(ComposeArgs a) {
   // order-1 and fallback neurons (the partials of the others are not read)
-  for_wave_items(a, 1, [](int kind) { return kind == 1 || kind == kFallback; },
+  for_wave_items(a, 1, [](int kind, int) { return kind == 1 || kind == kFallback; },
                  [&](int64_t g, int j, int s, int) { scatter_item<T>(a, g, j, s); });
 }
 
@@ -552,12 +552,97 @@ __device__ void sq2_item(const ComposeArgs &a, int64_t g, int j, int s, int bx, 
   }
 }
 
+// Both bounds of a neuron in one wave (nu of each in the wave's LDS): every
+// pair of the table is read once for the two sums; each bound's sums are
+// those of sq2_item, in the same order.
 template <typename T>
+__device__ void sq2_pair(const ComposeArgs &a, int64_t g, int j, int bx, double *nu) {
+  const int lane = threadIdx.x & 63;
+  const int64_t box = wave_box(a, g);
+  const NeuronRec &r = a.recs[box * a.h + j];
+  double *nu0 = nu, *nu1 = nu + a.Cin;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");  // the previous item's reads of nu are done
+  __builtin_amdgcn_wave_barrier();
+  for (int s = 0; s < 2; ++s) {
+    const T *p = in_tensor<T>(a, box, j, s);
+    const NuSource ns = nu_of(a, &r, s);
+    double *q = s == 0 ? nu0 : nu1;
+    for (int64_t i = lane; i < a.Cin; i += 64) {
+      double v = (double)p[i];
+      if (i == 0) v += ns.shift - ns.lo;
+      q[i] = v / ns.w;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  T *out0 = out_tensor<T>(a, box, j, 0), *out1 = out_tensor<T>(a, box, j, 1);
+  double rsum0 = 0.0, l1sum0 = 0.0, rsum1 = 0.0, l1sum1 = 0.0;
+  const int64_t K1 = min((int64_t)(bx + 1) * kBlock, a.Cout);
+  for (int64_t K = (int64_t)bx * kBlock + lane; K < K1; K += 64) {
+    double v0 = 0.0, v1 = 0.0;
+    if (K < a.Sm[2]) {
+      double acc0 = 0.0, acc1 = 0.0;
+      const int e = a.sq_off[K + 1];
+      for (int q = a.sq_off[K]; q < e; ++q) {
+        const int2 pr = a.sq_pairs[q];
+        acc0 = fma(nu0[pr.x], nu0[pr.y], acc0);
+        acc1 = fma(nu1[pr.x], nu1[pr.y], acc1);
+      }
+      acc0 = acc0 + acc0;
+      acc1 = acc1 + acc1;
+      const int d = a.sq_diag[K];
+      if (d >= 0) {
+        acc0 = fma(nu0[d], nu0[d], acc0);
+        acc1 = fma(nu1[d], nu1[d], acc1);
+      }
+      v0 = r.c[2] * acc0;
+      v1 = r.c[2] * acc1;
+      if (K < a.Cin) {
+        v0 = fma(r.c[1], nu0[K], v0);
+        v1 = fma(r.c[1], nu1[K], v1);
+      }
+      if (K == 0) {
+        v0 += r.c[0] - 0.0;
+        v1 += r.c[0] - r.e;
+      }
+    }
+    store(out0 + K, v0, rsum0, l1sum0);
+    store(out1 + K, v1, rsum1, l1sum1);
+  }
+  if (a.part) {  // each bound's own slot for the chunk
+    for (int off = 32; off > 0; off >>= 1) {
+      rsum0 += __shfl_xor(rsum0, off, 64);
+      l1sum0 += __shfl_xor(l1sum0, off, 64);
+      rsum1 += __shfl_xor(rsum1, off, 64);
+      l1sum1 += __shfl_xor(l1sum1, off, 64);
+    }
+    for (int s = 0; s < 2; ++s) {
+      const int64_t it = item_of(a, g, j, s);
+      if (lane == 0) {
+        a.part[(it * pslots(a) + bx) * 2 + 0] = s == 0 ? rsum0 : rsum1;
+        a.part[(it * pslots(a) + bx) * 2 + 1] = s == 0 ? l1sum0 : l1sum1;
+      }
+      if (bx == 0)  // the slots past this class's chunks
+        for (int64_t b = a.nbx + lane; b < pslots(a); b += 64)
+          a.part[(it * pslots(a) + b) * 2 + 0] = a.part[(it * pslots(a) + b) * 2 + 1] = 0.0;
+    }
+  }
+}
+
+// kPair: both bounds per wave (the items of bound 1 are then skipped).
+template <typename T, bool kPair>
 __global__ void __launch_bounds__(kBlock) compose_sq2_kernel(ComposeArgs a) {
   extern __shared__ double lds_nu[];
-  double *nu = lds_nu + (threadIdx.x >> 6) * a.Cin;  // the wave's nu
-  for_wave_items(a, (int)a.nbx, [](int kind) { return kind == 2; },
-                 [&](int64_t g, int j, int s, int bx) { sq2_item<T>(a, g, j, s, bx, nu); });
+  double *nu = lds_nu + (threadIdx.x >> 6) * (kPair ? 2 : 1) * a.Cin;  // the wave's nu
+  if constexpr (kPair) {
+    for_wave_items(a, (int)a.nbx, [](int kind, int s) { return kind == 2 && s == 0; },
+                   [&](int64_t g, int j, int, int bx) { sq2_pair<T>(a, g, j, bx, nu); });
+  } else {
+    for_wave_items(a, (int)a.nbx, [](int kind, int) { return kind == 2; },
+                   [&](int64_t g, int j, int s, int bx) { sq2_item<T>(a, g, j, s, bx, nu); });
+  }
+
 }
 
 // Orders L >= 3: Horner steps Q^(m) = nu Q^(m-1) + c_{L-1-m}, m = 1 .. L-1,
@@ -798,13 +883,19 @@ static hipError_t compose_all(const ComposeArgs &a_in, hipStream_t s) {
   const size_t lds = (size_t)a.Cin * sizeof(double);
   if (a.Lmax >= 2) {
     if (!a.sq_off || 4 * lds > device_lds_limit() || (int64_t)gx * kBlock < a.Cout) return hipErrorInvalidValue;
-    RET_IF(hipFuncSetAttribute((const void *)compose_sq2_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)(4 * lds)));
+    // both bounds of a neuron per wave when their two nu fit
+    const bool pair = a.nbounds == 2 && 8 * lds <= device_lds_limit();
+    const void *k = pair ? (const void *)compose_sq2_kernel<T, true> : (const void *)compose_sq2_kernel<T, false>;
+    const size_t klds = (pair ? 8 : 4) * lds;
+    RET_IF(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)klds));
     ComposeArgs ag = a;
     ag.group = group ? 8 : 1;
     const int64_t waves = (items_all + ag.group - 1) / ag.group * a.nbx;
     ProfScope ps(kProfComposeSquare, s, 0.0);
-    hipLaunchKernelGGL(compose_sq2_kernel<T>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 4 * lds, s, ag);
+    if (pair)
+      hipLaunchKernelGGL((compose_sq2_kernel<T, true>), dim3((unsigned)((waves + 3) / 4)), dim3(256), klds, s, ag);
+    else
+      hipLaunchKernelGGL((compose_sq2_kernel<T, false>), dim3((unsigned)((waves + 3) / 4)), dim3(256), klds, s, ag);
     RET_IF(hipGetLastError());
   }
   if (a.Lmax >= 3) {
