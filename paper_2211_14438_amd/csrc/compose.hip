@@ -875,7 +875,7 @@ static hipError_t compose_all(const ComposeArgs &a_in, hipStream_t s) {
   {
     ProfScope ps(kProfComposeSimple, s, 0.0);
     ComposeArgs ag = a;
-    ag.group = group ? 64 : 1;
+    ag.group = group ? 16 : 1;
     const int64_t waves = (items_all + ag.group - 1) / ag.group;
     hipLaunchKernelGGL(compose_scatter_kernel<T>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, ag);
     RET_IF(hipGetLastError());
