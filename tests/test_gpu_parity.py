@@ -271,7 +271,10 @@ def test_output_polys_match_oracle_and_enclose_the_network(precision):
     d, n = 4, case.n  # L^(H-1) for L = 2, H = 3
     r = B.output_polys(net, lo, hi, d, L=2, precision=precision)
     r5 = B.output_polys(net, lo, hi, d + 1, L=2, precision=precision)
+    r2 = B.output_polys(net, lo, hi, d, L=2, precision=precision, sched="per_box")  # one box per wave
     torch.cuda.synchronize()
+    for k in ("U", "L", "out_lo", "out_hi"):
+        assert torch.equal(r2[k], r[k]), k
     U, Lp = r["U"].cpu().numpy(), r["L"].cpu().numpy()
     U5 = r5["U"].cpu().numpy()
     olo, ohi = r["out_lo"].cpu().numpy(), r["out_hi"].cpu().numpy()
