@@ -195,6 +195,32 @@ bern_status bern_output_polys(const bern_net *net, const bern_opts *opts, int64_
                               double *poly_U, double *poly_L, double *out_lo, double *out_hi, void *workspace,
                               size_t ws_bytes, void *stream);
 
+/* Branch and bound over input boxes (the batched path's producer of many
+ * sub-boxes; not in the paper) for the property "output out_index <= threshold
+ * on the box". Each round bounds every pending box with bern_bounds (one
+ * batch); a box whose out_hi <= threshold is verified, one whose
+ * out_lo > threshold violates the property everywhere, and every other box is
+ * bisected along its widest input dimension for the next round, while the
+ * pending boxes stay within max_boxes and the rounds within max_rounds
+ * (after that they count as undecided). box_lo/box_hi are host arrays
+ * [n_boxes][n] with d_lo < d_hi in every dimension; the call is synchronous
+ * and allocates and frees its own device buffers.
+ *   res  host: the verified, violated and undecided fractions of the boxes'
+ *        total volume (summing to 1 up to rounding), the rounds run, the
+ *        number of box bounds computed, and the boxes left undecided.
+ * Errors: those of bern_bounds; BERN_E_ARG for a bad out_index, limits or
+ * result pointer; BERN_E_BOX for a box with d_lo >= d_hi. */
+typedef struct {
+  double verified, violated, undecided;  /* fractions of the total input volume */
+  int32_t rounds;
+  int32_t reserved0;
+  int64_t boxes_bounded;
+  int64_t undecided_boxes;
+} bern_verify_result;
+bern_status bern_verify(const bern_net *net, const bern_opts *opts, int64_t n_boxes, const double *box_lo,
+                        const double *box_hi, int32_t out_index, double threshold, int32_t max_rounds,
+                        int64_t max_boxes, bern_verify_result *res);
+
 /* bern_bounds on host memory, synchronous (the same computation, Problem 1):
  * box_lo, box_hi, plan and every output are host arrays with bern_bounds'
  * shapes (plan, neuron_lo/hi and used_plan nullable as there). The library

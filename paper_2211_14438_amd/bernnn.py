@@ -38,6 +38,12 @@ class bern_stats(ctypes.Structure):
                 ("reserved", ctypes.c_uint64 * 6)]
 
 
+class bern_verify_result(ctypes.Structure):
+    _fields_ = [("verified", ctypes.c_double), ("violated", ctypes.c_double), ("undecided", ctypes.c_double),
+                ("rounds", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("boxes_bounded", ctypes.c_int64),
+                ("undecided_boxes", ctypes.c_int64)]
+
+
 class BernError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{status_str(status)}: {msg}")
@@ -79,6 +85,9 @@ def lib():
     L.bern_output_polys.restype = i32
     L.bern_output_polys.argtypes = [_vp, ctypes.POINTER(bern_opts), i64, _vp, _vp, _vp, i32, _vp, _vp, _vp, _vp, _vp,
                                     sz, _vp]
+    L.bern_verify.restype = i32
+    L.bern_verify.argtypes = [_vp, ctypes.POINTER(bern_opts), i64, _vp, _vp, i32, ctypes.c_double, i32, i64,
+                              ctypes.POINTER(bern_verify_result)]
     L.bern_bounds_host.restype = i32
     L.bern_bounds_host.argtypes = [_vp, ctypes.POINTER(bern_opts), i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                    ctypes.POINTER(bern_stats)]
@@ -344,6 +353,22 @@ def output_polys(net, box_lo, box_hi, degree, L=2, precision="fp64", plan="plain
     _check(lib().bern_output_polys(args[0], args[1], args[2], args[3], args[4], args[5], int(degree), _ptr(U),
                                    _ptr(Lw), args[8], args[9], args[11], args[12], _stream(stream)))
     return dict(U=U, L=Lw, out_lo=res["out_lo"], out_hi=res["out_hi"], workspace=workspace)
+
+
+def verify(net, box_lo, box_hi, out_index, threshold, max_rounds=8, max_boxes=1 << 16, L=2, precision="fp64",
+           plan="plain", sched="batched", pred=None):
+    """Branch and bound for "output ``out_index`` <= ``threshold``" over host
+    boxes (numpy [n_boxes, n]); returns the verified / violated / undecided
+    volume fractions, the rounds run and the box counts."""
+    box_lo = np.ascontiguousarray(box_lo, dtype=np.float64)
+    box_hi = np.ascontiguousarray(box_hi, dtype=np.float64)
+    o = make_opts(L=L, precision=precision, plan=plan, sched=sched, pred=pred)
+    r = bern_verify_result()
+    _check(lib().bern_verify(net.handle, ctypes.byref(o), box_lo.shape[0], ctypes.c_void_p(box_lo.ctypes.data),
+                             ctypes.c_void_p(box_hi.ctypes.data), int(out_index), float(threshold), int(max_rounds),
+                             int(max_boxes), ctypes.byref(r)))
+    return dict(verified=r.verified, violated=r.violated, undecided=r.undecided, rounds=r.rounds,
+                boxes_bounded=r.boxes_bounded, undecided_boxes=r.undecided_boxes)
 
 
 def bounds_host(net, box_lo, box_hi, L=2, precision="fp64", plan="plain", sched="batched", degree_plan=None,

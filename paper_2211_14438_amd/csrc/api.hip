@@ -1092,6 +1092,87 @@ extern "C" bern_status bern_bounds_host(const bern_net *net, const bern_opts *op
   return BERN_OK;
 }
 
+// ------------------------------------------------------- branch and bound
+extern "C" bern_status bern_verify(const bern_net *net, const bern_opts *opts, int64_t n_boxes,
+                                   const double *box_lo, const double *box_hi, int32_t out_index, double threshold,
+                                   int32_t max_rounds, int64_t max_boxes, bern_verify_result *res) {
+  bern_status st = check_opts(net, opts);
+  if (st != BERN_OK) return st;
+  if (n_boxes < 1 || !box_lo || !box_hi || !res || out_index < 0 || out_index >= net->o || max_rounds < 1 ||
+      max_boxes < n_boxes) {
+    set_error("bad arguments (n_boxes %lld, out_index %d, max_rounds %d, max_boxes %lld)", (long long)n_boxes,
+              out_index, max_rounds, (long long)max_boxes);
+    return BERN_E_ARG;
+  }
+  const int n = net->n, o = net->o;
+  std::vector<double> lo(box_lo, box_lo + n_boxes * n), hi(box_hi, box_hi + n_boxes * n);
+  double total = 0.0;
+  auto volume = [&](const double *l, const double *h) {
+    double v = 1.0;
+    for (int a = 0; a < n; ++a) v *= h[a] - l[a];
+    return v;
+  };
+  for (int64_t b = 0; b < n_boxes; ++b) {
+    for (int a = 0; a < n; ++a)
+      if (!(lo[b * n + a] < hi[b * n + a])) {
+        set_error("box %lld: d_lo >= d_hi in dimension %d", (long long)b, a);
+        return BERN_E_BOX;
+      }
+    total += volume(&lo[b * n], &hi[b * n]);
+  }
+  memset(res, 0, sizeof(*res));
+  std::vector<double> olo, ohi;
+  for (int round = 0; round < max_rounds && !lo.empty(); ++round) {
+    const int64_t nb = (int64_t)(lo.size() / n);
+    olo.resize((size_t)nb * o);
+    ohi.resize((size_t)nb * o);
+    if ((st = bern_bounds_host(net, opts, nb, lo.data(), hi.data(), nullptr, nullptr, nullptr, olo.data(),
+                               ohi.data(), nullptr, nullptr)) != BERN_OK)
+      return st;
+    res->rounds = round + 1;
+    res->boxes_bounded += nb;
+    // classify; bisect the undecided boxes while they fit
+    std::vector<double> nlo, nhi;
+    std::vector<int64_t> open;
+    for (int64_t b = 0; b < nb; ++b) {
+      const double v = volume(&lo[b * n], &hi[b * n]) / total;
+      if (ohi[b * o + out_index] <= threshold)
+        res->verified += v;
+      else if (olo[b * o + out_index] > threshold)
+        res->violated += v;
+      else
+        open.push_back(b);
+    }
+    const bool split = round + 1 < max_rounds && (int64_t)open.size() * 2 <= max_boxes;
+    for (int64_t b : open) {
+      const double *l = &lo[b * n], *h = &hi[b * n];
+      if (!split) {
+        res->undecided += volume(l, h) / total;
+        res->undecided_boxes += 1;
+        continue;
+      }
+      int wide = 0;
+      for (int a = 1; a < n; ++a)
+        if (h[a] - l[a] > h[wide] - l[wide]) wide = a;
+      const double mid = 0.5 * (l[wide] + h[wide]);
+      for (int half = 0; half < 2; ++half) {
+        for (int a = 0; a < n; ++a) {
+          nlo.push_back(a == wide && half == 1 ? mid : l[a]);
+          nhi.push_back(a == wide && half == 0 ? mid : h[a]);
+        }
+      }
+    }
+    lo.swap(nlo);
+    hi.swap(nhi);
+  }
+  // boxes still pending after the last round that was allowed to split
+  for (size_t b = 0; b < lo.size() / n; ++b) {
+    res->undecided += volume(&lo[b * n], &hi[b * n]) / total;
+    res->undecided_boxes += 1;
+  }
+  return BERN_OK;
+}
+
 // --------------------------------------------------------------- autotuner
 static void tune_to(const Tune &t, int32_t *v) {
   v[0] = t.gemm_wide;

@@ -473,3 +473,43 @@ def test_learned_plan_is_sound_and_matches_oracle_on_its_plan():
             _assert_fp32(g, o, case.n_hidden)
     net.close()
     pred.close()
+
+
+# ------------------------------------------------------ branch and bound
+
+def test_verify_branch_and_bound_is_sound_and_converges():
+    """bern_verify on a 2-input network: the volume fractions sum to one,
+    a threshold above the network's maximum is verified on (nearly) the whole
+    box and never violated, one below its minimum is never verified, and for
+    a threshold in between the verified (violated) fraction stays below the
+    sampled fraction of points that satisfy (violate) it, shrinking the
+    undecided part as rounds are added."""
+    case = wl.random_net_case([2, 8, 8, 1], seed=91, n_boxes=1, half_width=0.5)
+    net = B.Net(case.Ws, case.bs)
+    g = np.linspace(0.0, 1.0, 201)
+    t = np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2)
+    x = case.box_lo[0] + t * (case.box_hi[0] - case.box_lo[0])
+    f = H.forward(case.Ws, case.bs, x)[-1][:, 0]
+    span = f.max() - f.min()
+    for precision in ("fp64", "fp32"):
+        hi_t = B.verify(net, case.box_lo, case.box_hi, 0, f.max() + 0.05 * span, max_rounds=14, max_boxes=8192,
+                        precision=precision)
+        assert abs(hi_t["verified"] + hi_t["violated"] + hi_t["undecided"] - 1.0) < 1e-12
+        assert hi_t["violated"] == 0.0 and hi_t["verified"] > 0.99, hi_t
+        lo_t = B.verify(net, case.box_lo, case.box_hi, 0, f.min() - 0.05 * span, max_rounds=14, max_boxes=8192,
+                        precision=precision)
+        assert lo_t["verified"] == 0.0 and lo_t["violated"] > 0.99, lo_t
+        mid = float(np.median(f))
+        frac_ok = float(np.mean(f <= mid))
+        prev = 2.0
+        for rounds in (2, 6, 10):
+            r = B.verify(net, case.box_lo, case.box_hi, 0, mid, max_rounds=rounds, max_boxes=8192,
+                         precision=precision)
+            assert abs(r["verified"] + r["violated"] + r["undecided"] - 1.0) < 1e-12
+            assert r["verified"] <= frac_ok + 0.02 and r["violated"] <= 1.0 - frac_ok + 0.02, (rounds, r)
+            assert r["undecided"] <= prev + 1e-12
+            prev = r["undecided"]
+        assert prev < 0.5
+    with pytest.raises(B.BernError):
+        B.verify(net, case.box_lo, case.box_hi, 1, 0.0)  # no output 1
+    net.close()
