@@ -1001,17 +1001,20 @@ __global__ void __launch_bounds__(1024) convert_block_t(ConvertArgs a) {
 // beta_a = a_{1+a} and beta_0 = a_0 + sum_a a_{1+a} / 2 (the closed form of
 // the fit below at degree 1); and its remainders, the same constant
 // a_0 - beta_0 + sum_a beta_a / 2 at every corner (zero up to rounding). A
-// team of kAffLanes lanes per neuron, several neurons per wave.
-constexpr int kAffLanes = 16;
-
+// team of lanes per neuron, several neurons per wave.
+// kL lanes per neuron (8 when the n + 1 coefficients fit, else 16), each
+// holding coefficients l, l + kL, ...
+template <int kL>
 __device__ __forceinline__ double aff_sum(double v) {
 #pragma unroll
-  for (int m = kAffLanes / 2; m > 0; m >>= 1) v += __shfl_xor(v, m, kAffLanes);
+  for (int m = kL / 2; m > 0; m >>= 1) v += __shfl_xor(v, m, kL);
   return v;
 }
 
-template <typename T>
+template <typename T, int kL>
 __global__ void __launch_bounds__(kBlock) convert_affine_kernel(ConvertArgs a) {
+  constexpr int kAffLanes = kL;
+  constexpr int kR = (kMaxInputs + 1 + kL - 1) / kL;  // coefficient slots per lane
   const int l = threadIdx.x % kAffLanes;
   const int64_t item = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kAffLanes;
   if (item >= a.nboxes * a.h) return;  // whole teams leave together
@@ -1019,10 +1022,11 @@ __global__ void __launch_bounds__(kBlock) convert_affine_kernel(ConvertArgs a) {
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
   const int j = (int)(item % a.h);
   const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + (int64_t)j * 2 * a.S;
-  // the lane's coefficients: indices l and l + kAffLanes (n + 1 <= 17)
-  double u[2] = {0.0, 0.0}, w[2] = {0.0, 0.0};
+  // the lane's coefficients: indices l + r kL (n + 1 <= 17)
+  double u[kR], w[kR];
 #pragma unroll
-  for (int r = 0; r < 2; ++r) {
+  for (int r = 0; r < kR; ++r) {
+    u[r] = w[r] = 0.0;
     const int i = l + r * kAffLanes;
     if (i < S) {
       u[r] = (double)p[i];
@@ -1053,7 +1057,7 @@ __global__ void __launch_bounds__(kBlock) convert_affine_kernel(ConvertArgs a) {
         v[4] += rp[a.cblocks + cb];
       }
 #pragma unroll
-      for (int q = 0; q < 5; ++q) v[q] = aff_sum(v[q]);
+      for (int q = 0; q < 5; ++q) v[q] = aff_sum<kL>(v[q]);
       const double gg = a.gpre * (v[2] + fabs(a.b[j]));
       epsU = (v[0] + gg + v[3]) * kPadSafety;
       epsL = (v[1] + gg + v[4]) * kPadSafety;
@@ -1062,7 +1066,7 @@ __global__ void __launch_bounds__(kBlock) convert_affine_kernel(ConvertArgs a) {
   // l1 norms, extrema, fit constants: lane l's share of each sum
   double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // l1U, l1L, max U, min L, beta0 U, beta0 L
 #pragma unroll
-  for (int r = 0; r < 2; ++r) {
+  for (int r = 0; r < kR; ++r) {
     const int i = l + r * kAffLanes;
     s[0] += fabs(u[r]);
     s[1] += fabs(w[r]);
@@ -1073,7 +1077,7 @@ __global__ void __launch_bounds__(kBlock) convert_affine_kernel(ConvertArgs a) {
     s[5] += c0 ? w[r] : 0.5 * w[r];
   }
 #pragma unroll
-  for (int q = 0; q < 6; ++q) s[q] = aff_sum(s[q]);
+  for (int q = 0; q < 6; ++q) s[q] = aff_sum<kL>(s[q]);
   const double l1U = s[0], l1L = s[1];
   const double lo = side_lo(a, s[3], l1L, epsL), hi = side_hi(a, s[2], l1U, epsU);
   const bool want = wants_fit(a, box, j);
@@ -1083,20 +1087,20 @@ __global__ void __launch_bounds__(kBlock) convert_affine_kernel(ConvertArgs a) {
     // the remainder constant: a_0 - beta_0 + sum_a beta_a / 2
     double c[2] = {0.0, 0.0};
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
+    for (int r = 0; r < kR; ++r) {
       const bool c0 = l + r * kAffLanes == 0;
       c[0] += c0 ? u[r] - s[4] : 0.5 * u[r];
       c[1] += c0 ? w[r] - s[5] : 0.5 * w[r];
     }
-    c[0] = aff_sum(c[0]);
-    c[1] = aff_sum(c[1]);
+    c[0] = aff_sum<kL>(c[0]);
+    c[1] = aff_sum<kL>(c[1]);
     fx[0] = fx[1] = c[0];
     fx[2] = fx[3] = c[1];
   }
   if (a.mode == 0 && fitted) {  // the fits: beta_0, then beta_a = a_{1+a}
     NeuronRec &rec = a.recs[box * a.h + j];
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
+    for (int r = 0; r < kR; ++r) {
       const int q = l + r * kAffLanes;
       if (q <= kMaxInputs) {
         const bool on = q < S;
@@ -1118,8 +1122,13 @@ static hipError_t launch_affine(const ConvertArgs &a, hipStream_t s) {
   ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4),
                (double)a.nboxes * a.h * 2 * a.n * a.C * (a.D + 2));
   const int64_t teams = a.nboxes * a.h;
-  const int64_t blocks = (teams * kAffLanes + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(convert_affine_kernel<T>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+  if (a.S <= 8) {
+    hipLaunchKernelGGL((convert_affine_kernel<T, 8>), dim3((unsigned)((teams * 8 + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((convert_affine_kernel<T, 16>), dim3((unsigned)((teams * 16 + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, s, a);
+  }
   return hipGetLastError();
 }
 
