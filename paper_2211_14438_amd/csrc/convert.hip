@@ -1665,8 +1665,11 @@ __device__ void ntree_neuron(const ConvertArgs &a, const NTreePlan &tp, const Te
   if (tid == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted, true);
 }
 
+// Wave teams per block of the one-wave-per-neuron form.
+constexpr int kNTeams = 2;
+
 template <int D, int M, typename T, bool kWave>
-__global__ void __launch_bounds__(kWave ? 256 : 1024) convert_ntree_t(ConvertArgs a, NTreePlan tp) {
+__global__ void __launch_bounds__(kWave ? 64 * kNTeams : 1024) convert_ntree_t(ConvertArgs a, NTreePlan tp) {
   extern __shared__ double lds[];
   __shared__ double red[kRedDoubles];
   constexpr int D1 = D + 1;
@@ -1704,14 +1707,14 @@ static bool launch_ntree(const ConvertArgs &a, hipStream_t s, bool wave_team, hi
   ProfScope ps(kProfConvertSmall, s, (double)items * 2 * a.S * (a.fp64 ? 8 : 4),
                (double)items * 2 * a.n * a.C * (a.D + 2));
   err = hipSuccess;
-  if (tp.threads == 64) {  // a wave per neuron, four per block
-    const size_t lds = ntree_lds(tp, a.n, D, 4);
+  if (tp.threads == 64) {  // a wave per neuron, kNTeams per block
+    const size_t lds = ntree_lds(tp, a.n, D, kNTeams);
     if (lds <= device_lds_limit()) {
       err = hipFuncSetAttribute((const void *)convert_ntree_t<D, M, T, true>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (err != hipSuccess) return true;
-      hipLaunchKernelGGL((convert_ntree_t<D, M, T, true>), dim3((unsigned)((items + 3) / 4)), dim3(256), lds, s, a,
-                         tp);
+      hipLaunchKernelGGL((convert_ntree_t<D, M, T, true>), dim3((unsigned)((items + kNTeams - 1) / kNTeams)),
+                         dim3(64 * kNTeams), lds, s, a, tp);
       err = hipGetLastError();
       return true;
     }
