@@ -1665,8 +1665,9 @@ __device__ void ntree_neuron(const ConvertArgs &a, const NTreePlan &tp, const Te
   if (tid == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted, true);
 }
 
-// Wave teams per block of the one-wave-per-neuron form.
-constexpr int kNTeams = 2;
+// Wave teams per block of the one-wave-per-neuron form: one, so a neuron's
+// wave is scheduled (and its LDS slice freed) on its own.
+constexpr int kNTeams = 1;
 
 template <int D, int M, typename T, bool kWave>
 __global__ void __launch_bounds__(kWave ? 64 * kNTeams : 1024) convert_ntree_t(ConvertArgs a, NTreePlan tp) {
@@ -1697,7 +1698,7 @@ __global__ void __launch_bounds__(kWave ? 64 * kNTeams : 1024) convert_ntree_t(C
 }
 
 static NTreePlan ntree_plan(int n, int D, int M, bool wave_team);
-static size_t ntree_lds(const NTreePlan &tp, int n, int D, int teams);
+static size_t ntree_lds(const NTreePlan &tp, int n, int D, int teams, bool wave);
 
 template <typename T, int D, int M>
 static bool launch_ntree(const ConvertArgs &a, hipStream_t s, bool wave_team, hipError_t &err) {
@@ -1708,7 +1709,7 @@ static bool launch_ntree(const ConvertArgs &a, hipStream_t s, bool wave_team, hi
                (double)items * 2 * a.n * a.C * (a.D + 2));
   err = hipSuccess;
   if (tp.threads == 64) {  // a wave per neuron, kNTeams per block
-    const size_t lds = ntree_lds(tp, a.n, D, kNTeams);
+    const size_t lds = ntree_lds(tp, a.n, D, kNTeams, true);
     if (lds <= device_lds_limit()) {
       err = hipFuncSetAttribute((const void *)convert_ntree_t<D, M, T, true>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1719,7 +1720,7 @@ static bool launch_ntree(const ConvertArgs &a, hipStream_t s, bool wave_team, hi
       return true;
     }
   }
-  const size_t lds = ntree_lds(tp, a.n, D, 1);
+  const size_t lds = ntree_lds(tp, a.n, D, 1, false);
   err = hipFuncSetAttribute((const void *)convert_ntree_t<D, M, T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
   if (err != hipSuccess) return true;
@@ -2031,10 +2032,10 @@ static NTreePlan ntree_plan(int n, int D, int M, bool wave_team) {
   return none;
 }
 
-static size_t ntree_lds(const NTreePlan &tp, int n, int D, int teams) {
-  // wave teams (teams > 1) also hold their reduction scratch
+static size_t ntree_lds(const NTreePlan &tp, int n, int D, int teams, bool wave) {
+  // wave teams also hold their reduction scratch
   return (size_t)((tree_ints(n, D) + 1) / 2 + (D + 1) * (D + 1) +
-                  (int64_t)teams * ((teams > 1 ? kRowScratch : 0) + 2 * (kMaxInputs + 1) + 2 * (int64_t)tp.area)) *
+                  (int64_t)teams * ((wave ? kRowScratch : 0) + 2 * (kMaxInputs + 1) + 2 * (int64_t)tp.area)) *
          sizeof(double);
 }
 
