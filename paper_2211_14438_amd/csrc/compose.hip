@@ -857,6 +857,9 @@ static int sq_dispatch(const ComposeArgs &a, hipStream_t s, hipError_t &err) {
   return err == hipSuccess ? D : -1;
 }
 
+// Waves per block of the one-wave-per-item kernels (scatter, square).
+constexpr int kComposeWaves = 1;
+
 template <typename T>
 static hipError_t compose_all(const ComposeArgs &a_in, hipStream_t s) {
   ComposeArgs a = a_in;
@@ -877,25 +880,29 @@ static hipError_t compose_all(const ComposeArgs &a_in, hipStream_t s) {
     ComposeArgs ag = a;
     ag.group = group ? 16 : 1;
     const int64_t waves = (items_all + ag.group - 1) / ag.group;
-    hipLaunchKernelGGL(compose_scatter_kernel<T>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, ag);
+    hipLaunchKernelGGL(compose_scatter_kernel<T>, dim3((unsigned)((waves + kComposeWaves - 1) / kComposeWaves)),
+                       dim3(64 * kComposeWaves), 0, s, ag);
     RET_IF(hipGetLastError());
   }
   const size_t lds = (size_t)a.Cin * sizeof(double);
   if (a.Lmax >= 2) {
-    if (!a.sq_off || 4 * lds > device_lds_limit() || (int64_t)gx * kBlock < a.Cout) return hipErrorInvalidValue;
+    if (!a.sq_off || kComposeWaves * lds > device_lds_limit() || (int64_t)gx * kBlock < a.Cout)
+      return hipErrorInvalidValue;
     // both bounds of a neuron per wave when their two nu fit
-    const bool pair = a.nbounds == 2 && 8 * lds <= device_lds_limit();
+    const bool pair = a.nbounds == 2 && 2 * kComposeWaves * lds <= device_lds_limit();
     const void *k = pair ? (const void *)compose_sq2_kernel<T, true> : (const void *)compose_sq2_kernel<T, false>;
-    const size_t klds = (pair ? 8 : 4) * lds;
+    const size_t klds = (pair ? 2 : 1) * kComposeWaves * lds;
     RET_IF(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)klds));
     ComposeArgs ag = a;
     ag.group = group ? 8 : 1;
     const int64_t waves = (items_all + ag.group - 1) / ag.group * a.nbx;
     ProfScope ps(kProfComposeSquare, s, 0.0);
     if (pair)
-      hipLaunchKernelGGL((compose_sq2_kernel<T, true>), dim3((unsigned)((waves + 3) / 4)), dim3(256), klds, s, ag);
+      hipLaunchKernelGGL((compose_sq2_kernel<T, true>), dim3((unsigned)((waves + kComposeWaves - 1) / kComposeWaves)),
+                         dim3(64 * kComposeWaves), klds, s, ag);
     else
-      hipLaunchKernelGGL((compose_sq2_kernel<T, false>), dim3((unsigned)((waves + 3) / 4)), dim3(256), klds, s, ag);
+      hipLaunchKernelGGL((compose_sq2_kernel<T, false>), dim3((unsigned)((waves + kComposeWaves - 1) / kComposeWaves)),
+                         dim3(64 * kComposeWaves), klds, s, ag);
     RET_IF(hipGetLastError());
   }
   if (a.Lmax >= 3) {
