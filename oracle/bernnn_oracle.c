@@ -18,7 +18,7 @@
  *   Prop. 4, eqs. (L_sum)-(tensor_sum)       Sum_Bern: elevate with a ones tensor, add
  *   Section 5.1, Steps 1-3                   one neuron
  *   Section 5.2, eqs. (upper_bounds_layer), (lower_bounds_layer)   one layer
- *   Section 5.3                              input initialisation and driver
+ *   Section 5.3                              input initialisation and the layer loop
  *
  * Readings of points the paper leaves open (each one is listed with its reason
  * in the design notes of the repository):

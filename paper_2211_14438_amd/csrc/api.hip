@@ -1,5 +1,5 @@
 // C ABI of the bound-propagation library: validation, planning of degrees and
-// workspace, waves of boxes, and the per-layer launch sequence (the driver of
+// workspace, waves of boxes, and the per-layer launch sequence (the top-level loop of
 // Section 5.3: input initialisation, then for each layer the affine map of
 // Section 5.2, the bounds of Step 1, the approximant of Step 2 and the
 // composition of Step 3, and finally the output bounds).
