@@ -195,6 +195,22 @@ bern_status bern_output_polys(const bern_net *net, const bern_opts *opts, int64_
                               double *poly_U, double *poly_L, double *out_lo, double *out_hi, void *workspace,
                               size_t ws_bytes, void *stream);
 
+/* Relative volume of the output set (Section 6, evaluation metrics): for
+ * every box and output neuron j, the integral over the input box of
+ * U_j(x) - L_j(x) divided by the box's volume, i.e. the mean of U_j - L_j
+ * over t in [0,1]^n (each power coefficient of t^e weighted by
+ * prod_a 1/(e_a+1)).
+ *   rel_vol          device, [n_boxes][h_H] FP64, written. In FP32 mode the
+ *                    stored coefficients' radii are added: the volume of the
+ *                    padded pair, which encloses the network.
+ * The other arguments are bern_bounds' (out_lo/out_hi as there); the hidden
+ * layers' outputs are not written. Asynchronous on `stream`; never replayed
+ * from a graph.
+ * Errors: those of bern_bounds; BERN_E_ARG when rel_vol is NULL. */
+bern_status bern_rel_volume(const bern_net *net, const bern_opts *opts, int64_t n_boxes, const double *box_lo,
+                            const double *box_hi, const int8_t *plan, double *rel_vol, double *out_lo,
+                            double *out_hi, void *workspace, size_t ws_bytes, void *stream);
+
 /* Branch and bound over input boxes (the batched path's producer of many
  * sub-boxes; not in the paper) for the property "output out_index <= threshold
  * on the box". Each round bounds every pending box with bern_bounds (one

@@ -85,6 +85,8 @@ def lib():
     L.bern_output_polys.restype = i32
     L.bern_output_polys.argtypes = [_vp, ctypes.POINTER(bern_opts), i64, _vp, _vp, _vp, i32, _vp, _vp, _vp, _vp, _vp,
                                     sz, _vp]
+    L.bern_rel_volume.restype = i32
+    L.bern_rel_volume.argtypes = [_vp, ctypes.POINTER(bern_opts), i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, sz, _vp]
     L.bern_verify.restype = i32
     L.bern_verify.argtypes = [_vp, ctypes.POINTER(bern_opts), i64, _vp, _vp, i32, ctypes.c_double, i32, i64,
                               ctypes.POINTER(bern_verify_result)]
@@ -353,6 +355,21 @@ def output_polys(net, box_lo, box_hi, degree, L=2, precision="fp64", plan="plain
     _check(lib().bern_output_polys(args[0], args[1], args[2], args[3], args[4], args[5], int(degree), _ptr(U),
                                    _ptr(Lw), args[8], args[9], args[11], args[12], _stream(stream)))
     return dict(U=U, L=Lw, out_lo=res["out_lo"], out_hi=res["out_hi"], workspace=workspace)
+
+
+def rel_volume(net, box_lo, box_hi, L=2, precision="fp64", plan="plain", sched="batched", degree_plan=None,
+               max_wave=0, pred=None, stream=None):
+    """Relative volume of the output set of every box (Section 6): a dict with
+    ``rel_vol`` (float64 CUDA tensor [n_boxes, n_out]) and the output bounds
+    ``out_lo``/``out_hi``. Asynchronous on ``stream``."""
+    import torch
+    args, res, workspace, keep = _prepare(net, box_lo, box_hi, L, precision, plan, sched, degree_plan, max_wave,
+                                          None, None, pred, None, False)
+    vol = torch.empty((box_lo.shape[0], net.n_out), dtype=torch.float64, device=box_lo.device)
+    # args: handle, opts, nb, lo, hi, plan, neuron_lo, neuron_hi, out_lo, out_hi, used, ws, ws_bytes
+    _check(lib().bern_rel_volume(args[0], args[1], args[2], args[3], args[4], args[5], _ptr(vol), args[8], args[9],
+                                 args[11], args[12], _stream(stream)))
+    return dict(rel_vol=vol, out_lo=res["out_lo"], out_hi=res["out_hi"], workspace=workspace)
 
 
 def verify(net, box_lo, box_hi, out_index, threshold, max_rounds=8, max_boxes=1 << 16, L=2, precision="fp64",

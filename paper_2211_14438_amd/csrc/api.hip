@@ -13,6 +13,7 @@
 
 #include "common.hpp"
 #include "simplex.hpp"
+#include "volume.hpp"
 
 namespace bern {
 
@@ -489,12 +490,14 @@ struct BoxClass {
 // and launch each degree class of boxes on its own (a box's tensors stay
 // dense at the box's own degree inside its fixed slot).
 // Output polynomials requested by bern_output_polys: dense power tensors at
-// per-variable degree D (C = (D+1)^n coefficients each), [n_boxes][o][C].
+// per-variable degree D (C = (D+1)^n coefficients each), [n_boxes][o][C];
+// or, by bern_rel_volume, only their relative volumes vol [n_boxes][o].
 struct OutPolys {
   double *U, *L;
   int D;
   int64_t C;
   const int *didx;  // rank -> dense index at degree D
+  double *vol = nullptr;
 };
 
 static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts *o, int64_t b0, int64_t B,
@@ -697,6 +700,20 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       if (op) {  // the output layer's stored tensors, per class, into the caller's dense tensors
         for (size_t k = 0; k < classes.size(); ++k) {
           const BoxClass &cl = classes[k];
+          if (op->vol) {  // relative volume at the class's own degree
+            OutPolyArgs a{};
+            a.pre = Aa[i & 1];
+            a.slot = slotA;
+            a.S = ssize(n, cl.Din);
+            BERN_HIP_TRY(dense_index_table(*net->tab, cl.Din, &a.didx));  // built for this layer's read-off
+            a.bids = cid[k];
+            a.nboxes = (int64_t)cl.ids.size();
+            a.h = h;
+            a.eps = p.fp64 ? nullptr : oeps;
+            a.fp64 = p.fp64 ? 1 : 0;
+            BERN_HIP_TRY(launch_rel_volume(a, n, cl.Din, op->vol + (size_t)b0 * h, s));
+            continue;
+          }
           if (cl.Din > op->D) {
             set_error("output degree %d of some box exceeds the requested %d", cl.Din, op->D);
             return BERN_E_DEGREE;
@@ -1024,6 +1041,21 @@ extern "C" bern_status bern_output_polys(const bern_net *net, const bern_opts *o
     return BERN_E_TOO_LARGE;
   }
   BERN_HIP_TRY(e);
+  return bounds_impl(net, opts, n_boxes, box_lo, box_hi, plan, nullptr, nullptr, out_lo, out_hi, nullptr, workspace,
+                     ws_bytes, stream, nullptr, &op);
+}
+
+extern "C" bern_status bern_rel_volume(const bern_net *net, const bern_opts *opts, int64_t n_boxes,
+                                       const double *box_lo, const double *box_hi, const int8_t *plan,
+                                       double *rel_vol, double *out_lo, double *out_hi, void *workspace,
+                                       size_t ws_bytes, void *stream) {
+  bern_status st = check_opts(net, opts);
+  if (st != BERN_OK) return st;
+  if (!rel_vol) {
+    set_error("bern_rel_volume needs an output array");
+    return BERN_E_ARG;
+  }
+  OutPolys op{nullptr, nullptr, 0, 0, nullptr, rel_vol};
   return bounds_impl(net, opts, n_boxes, box_lo, box_hi, plan, nullptr, nullptr, out_lo, out_hi, nullptr, workspace,
                      ws_bytes, stream, nullptr, &op);
 }
