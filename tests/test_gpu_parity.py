@@ -548,3 +548,31 @@ def test_verify_branch_and_bound_is_sound_and_converges():
     with pytest.raises(B.BernError):
         B.verify(net, case.box_lo, case.box_hi, 1, 0.0)  # no output 1
     net.close()
+
+
+def test_relative_volume_fig4_setting():
+    """Fig. 4's setting (50 random [2,20,20,1] nets, U[-5,5] weights, box
+    [-1,1]^2, L = 2, 3, 4): the kernel's relative volumes are the oracle's
+    (FP64 1e-9, FP32 1e-3 of the output width), and their median falls as L
+    grows, the trade-off the figure shows."""
+    lo = torch.tensor([[-1.0, -1.0]], dtype=torch.float64, device=DEV)
+    hi = torch.tensor([[1.0, 1.0]], dtype=torch.float64, device=DEV)
+    med = {}
+    for L in (2, 3, 4):
+        v = []
+        for s in range(50):
+            Ws, bs = wl.make_net([2, 20, 20, 1], 1000 + s, law="uniform5")
+            net = B.Net(Ws, bs)
+            r64 = B.rel_volume(net, lo, hi, L=L, precision="fp64")
+            r32 = B.rel_volume(net, lo, hi, L=L, precision="fp32")
+            torch.cuda.synchronize()
+            net.close()
+            o = orc.network(Ws, bs, np.array([-1.0, -1.0]), np.array([1.0, 1.0]), L=L)
+            g64, g32 = float(r64["rel_vol"][0, 0]), float(r32["rel_vol"][0, 0])
+            width = o["out_hi"][0] - o["out_lo"][0]
+            scale = max(abs(o["rel_vol"][0]), width, 1e-300)
+            assert abs(g64 - o["rel_vol"][0]) <= 1e-9 * scale, (L, s, g64, o["rel_vol"][0])
+            assert abs(g32 - o["rel_vol"][0]) <= 1e-3 * scale, (L, s, g32, o["rel_vol"][0])
+            v.append(g64)
+        med[L] = float(np.median(v))
+    assert med[2] > med[3] > med[4]
