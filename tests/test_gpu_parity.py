@@ -576,3 +576,26 @@ def test_relative_volume_fig4_setting():
             v.append(g64)
         med[L] = float(np.median(v))
     assert med[2] > med[3] > med[4]
+
+
+@pytest.mark.parametrize("plan", ["plain", "given"])
+def test_relative_volume_of_constant_outputs(plan):
+    """Degenerate case: every hidden neuron inactive, so each output is its
+    bias, U = L, and the relative volume is exactly zero (FP64), or the
+    tensors' radii alone (FP32: nonnegative and tiny). Under a given plan the
+    output layer's tensors have degree 0."""
+    rng = np.random.default_rng(12)
+    Ws = [rng.uniform(-0.1, 0.1, (5, 3)), rng.uniform(-1, 1, (4, 5)), rng.uniform(-1, 1, (2, 4))]
+    bs = [np.full(5, -100.0), np.full(4, -50.0), np.array([0.5, -0.25])]
+    lo = torch.tensor([[-1.0, -1.0, -1.0], [0.0, 0.2, 0.4]], dtype=torch.float64, device=DEV)
+    hi = torch.tensor([[1.0, 1.0, 1.0], [0.1, 0.3, 0.5]], dtype=torch.float64, device=DEV)
+    codes = torch.full((2, 9), 2, dtype=torch.int8, device=DEV) if plan == "given" else None
+    net = B.Net(Ws, bs)
+    r64 = B.rel_volume(net, lo, hi, L=2, precision="fp64", plan=plan, degree_plan=codes)
+    r32 = B.rel_volume(net, lo, hi, L=2, precision="fp32", plan=plan, degree_plan=codes)
+    torch.cuda.synchronize()
+    net.close()
+    assert torch.all(r64["rel_vol"] == 0.0)
+    assert torch.all(r64["out_lo"] == torch.tensor([[0.5, -0.25]] * 2, dtype=torch.float64, device=DEV))
+    assert torch.all(r64["out_hi"] == r64["out_lo"])
+    assert torch.all(r32["rel_vol"] >= 0.0) and torch.all(r32["rel_vol"] <= 1e-5)
