@@ -1452,6 +1452,7 @@ constexpr int ntree_tile_axes(int D) { return D == 1 ? 1 : D == 2 ? 3 : D <= 4 ?
 struct NTreePlan {
   int e = 0, q = 0;  // variables expanded per round, folded per round (chain)
   int lanes = 0, threads = 0, rounds = 0;
+  int sides = 2;     // trees per team: both bounds, or one (output layers: a block per bound)
   int area = 0;      // doubles of one tensor's tree: stored coefficients, chain, expansions
   int S[kMaxInputs + 1] = {};
 };
@@ -1500,7 +1501,7 @@ __device__ void ntree_pass(const ConvertArgs &a, const NTreePlan &tp, const Team
   constexpr int D1 = D + 1;
   const int tid = tm.tid, nt = tm.nt, n = a.n;
   const int side = tid / tp.lanes, tl = tid - side * tp.lanes;  // side 0: upper, 1: lower
-  const bool lane = side < 2;
+  const bool lane = side < tp.sides;
   const int lane_k = tl % D1, pv = tl / D1;
   double rk[D1];
 #pragma unroll
@@ -1552,7 +1553,7 @@ __device__ void ntree_pass(const ConvertArgs &a, const NTreePlan &tp, const Team
       int k = rho;
       for (int s2 = tp.q - 1; s2 > i; --s2) k /= D1;
       k %= D1;
-      for (int sd = 0; sd < 2; ++sd) {
+      for (int sd = 0; sd < tp.sides; ++sd) {
         double *root = t0 + sd * tp.area;
         tree_fold(level(root, i), level(root, i + 1), tb, tb + a.tree_base[n - i], tp.S[n - i - 1], tab + k * D1, k,
                   tid, nt);
@@ -1567,7 +1568,7 @@ __device__ void ntree_pass(const ConvertArgs &a, const NTreePlan &tp, const Team
       int64_t in_off = -1, out_off = chain_size;
       for (int i = 1; i < tp.e; ++i) {
         const int d = cdim - i + 1;
-        for (int sd = 0; sd < 2; ++sd) {
+        for (int sd = 0; sd < tp.sides; ++sd) {
           double *root = t0 + sd * tp.area;
           const double *in = in_off < 0 ? level(root, tp.q) : root + in_off;
           tree_expand<D>(in, root + out_off, tb, tb + a.tree_base[d], tp.S[d], tp.S[d - 1], Vx, tid, nt);
@@ -1589,6 +1590,40 @@ __device__ void ntree_pass(const ConvertArgs &a, const NTreePlan &tp, const Team
 
 // One neuron's read-off by a team: a block (kWave false) or one wave of a
 // block of four, each wave with its own neuron and LDS slice (kWave true).
+// An output neuron's one bound (bside 0 upper, 1 lower) by a block with
+// one tree (tp.sides == 1): its extremum, radius and output bound only.
+template <int D, int M, typename T, class Team>
+__device__ void ntree_output_side(const ConvertArgs &a, const NTreePlan &tp, const Team &tm, const int *tb,
+                                  const double *tab, double *bl, int64_t item, int bside) {
+  const int tid = tm.tid, nt = tm.nt, S = (int)a.S;
+  double *t0 = bl + 2 * (kMaxInputs + 1);
+  const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
+  const int j = (int)(item % a.h);
+  const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + ((int64_t)j * 2 + bside) * a.S;
+  double l1[2] = {0.0, 0.0};
+  for (int i = tid; i < S; i += nt) {
+    const double v = (double)p[i];
+    t0[i] = v;
+    l1[bside] += fabs(v);
+  }
+  double epsU, epsL;
+  radii_and_l1(a, box, j, tm, l1, epsU, epsL);
+  tm.sync();
+  double mn = INFINITY, mx = -INFINITY, rmn = INFINITY, rmx = -INFINITY;
+  ntree_pass<D, M, false>(a, tp, tm, tb, tab, t0, bl, mn, mx, rmn, rmx);
+  double ex[2] = {mx, -mn};
+  tm.reduce(ex, OpMax());
+  if (tid != 0) return;
+  const int64_t o = box * a.ld_out + a.col0 + j;
+  if (bside == 0) {
+    a.out_hi[o] = side_hi(a, ex[0], l1[0], epsU);
+    if (a.out_eps) a.out_eps[(box * a.h + j) * 2 + 0] = epsU;
+  } else {
+    a.out_lo[o] = side_lo(a, -ex[1], l1[1], epsL);
+    if (a.out_eps) a.out_eps[(box * a.h + j) * 2 + 1] = epsL;
+  }
+}
+
 template <int D, int M, typename T, bool kWave, class Team>
 __device__ void ntree_neuron(const ConvertArgs &a, const NTreePlan &tp, const Team &tm, const int *tb,
                              const double *tab, double *bl, int64_t item) {
@@ -1669,7 +1704,7 @@ __device__ void ntree_neuron(const ConvertArgs &a, const NTreePlan &tp, const Te
 // wave is scheduled (and its LDS slice freed) on its own.
 constexpr int kNTeams = 1;
 
-template <int D, int M, typename T, bool kWave>
+template <int D, int M, typename T, bool kWave, bool kSide = false>
 __global__ void __launch_bounds__(kWave ? 64 * kNTeams : 1024) convert_ntree_t(ConvertArgs a, NTreePlan tp) {
   extern __shared__ double lds[];
   __shared__ double red[kRedDoubles];
@@ -1693,11 +1728,14 @@ __global__ void __launch_bounds__(kWave ? 64 * kNTeams : 1024) convert_ntree_t(C
     ntree_neuron<D, M, T, true>(a, tp, tm, tb, tab, slice + kRowScratch, item);
   } else {
     const BlockTeam tm{(int)threadIdx.x, (int)blockDim.x, red};
-    ntree_neuron<D, M, T, false>(a, tp, tm, tb, tab, slices, blockIdx.x);
+    if constexpr (kSide)
+      ntree_output_side<D, M, T>(a, tp, tm, tb, tab, slices, blockIdx.x >> 1, (int)(blockIdx.x & 1));
+    else
+      ntree_neuron<D, M, T, false>(a, tp, tm, tb, tab, slices, blockIdx.x);
   }
 }
 
-static NTreePlan ntree_plan(int n, int D, int M, bool wave_team);
+static NTreePlan ntree_plan(int n, int D, int M, bool wave_team, int sides = 2);
 static size_t ntree_lds(const NTreePlan &tp, int n, int D, int teams, bool wave);
 
 template <typename T, int D, int M>
@@ -1716,6 +1754,19 @@ static bool launch_ntree(const ConvertArgs &a, hipStream_t s, bool wave_team, hi
       if (err != hipSuccess) return true;
       hipLaunchKernelGGL((convert_ntree_t<D, M, T, true>), dim3((unsigned)((items + kNTeams - 1) / kNTeams)),
                          dim3(64 * kNTeams), lds, s, a, tp);
+      err = hipGetLastError();
+      return true;
+    }
+  }
+  if (a.mode == 1) {  // output neurons: a block per bound, one tree each
+    const NTreePlan t1 = ntree_plan(a.n, D, M, false, 1);
+    if (t1.e >= 1) {
+      const size_t l1 = ntree_lds(t1, a.n, D, 1, false);
+      err = hipFuncSetAttribute((const void *)convert_ntree_t<D, M, T, false, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)l1);
+      if (err != hipSuccess) return true;
+      hipLaunchKernelGGL((convert_ntree_t<D, M, T, false, true>), dim3((unsigned)(items * 2)), dim3((unsigned)t1.threads),
+                         l1, s, a, t1);
       err = hipGetLastError();
       return true;
     }
@@ -2002,21 +2053,23 @@ static TreePlan tree_plan(int n, int D, int64_t tensors) {
 // Plan of the neuron tree: e the most variables with 2 (D+1)^e lanes in one
 // block (one wave with wave_team), the rest folded per round; e shrinks
 // until both trees fit LDS.
-static NTreePlan ntree_plan(int n, int D, int M, bool wave_team) {
+static NTreePlan ntree_plan(int n, int D, int M, bool wave_team, int sides) {
   NTreePlan none;
   if (D < 1 || D > 8 || n > kMaxInputs) return none;
   const int D1 = D + 1, lead = n - M;
   if (lead < 1) return none;
   NTreePlan tp;
+  tp.sides = sides;
   for (int d = 0; d <= n; ++d) tp.S[d] = (int)ssize(d, D);
-  const int64_t max_lanes = wave_team ? 64 : 1024;
+  // one tree per block: the same expansion as with two, half the block
+  const int64_t max_lanes = wave_team ? 64 : (sides == 1 ? 512 : 1024);
   int e = 0;
-  while (e < lead && 2 * ipow(D1, e + 1) <= max_lanes) ++e;
+  while (e < lead && sides * ipow(D1, e + 1) <= max_lanes) ++e;
   for (; e >= 1; --e) {
     tp.e = e;
     tp.q = lead - e;
     tp.lanes = (int)ipow(D1, e);
-    tp.threads = std::max(64, (2 * tp.lanes + 63) / 64 * 64);
+    tp.threads = std::max(64, (sides * tp.lanes + 63) / 64 * 64);
     tp.rounds = (int)ipow(D1, tp.q);
     int64_t area = 0;
     for (int i = 0; i <= tp.q; ++i) area += tp.S[n - i];
@@ -2026,7 +2079,8 @@ static NTreePlan ntree_plan(int n, int D, int M, bool wave_team) {
       area += V * tp.S[n - tp.q - i];
     }
     tp.area = (int)area;
-    const size_t lds = (size_t)((tree_ints(n, D) + 1) / 2 + D1 * D1 + 2 * (kMaxInputs + 1) + 2 * area) * sizeof(double);
+    const size_t lds =
+        (size_t)((tree_ints(n, D) + 1) / 2 + D1 * D1 + 2 * (kMaxInputs + 1) + sides * area) * sizeof(double);
     if (lds <= device_lds_limit()) return tp;
   }
   return none;
@@ -2035,7 +2089,7 @@ static NTreePlan ntree_plan(int n, int D, int M, bool wave_team) {
 static size_t ntree_lds(const NTreePlan &tp, int n, int D, int teams, bool wave) {
   // wave teams also hold their reduction scratch
   return (size_t)((tree_ints(n, D) + 1) / 2 + (D + 1) * (D + 1) +
-                  (int64_t)teams * ((wave ? kRowScratch : 0) + 2 * (kMaxInputs + 1) + 2 * (int64_t)tp.area)) *
+                  (int64_t)teams * ((wave ? kRowScratch : 0) + 2 * (kMaxInputs + 1) + (int64_t)tp.sides * tp.area)) *
          sizeof(double);
 }
 
