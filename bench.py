@@ -37,28 +37,56 @@ WORKLOADS = {
 }
 
 
-def cpu_baseline(case, budget_s=10.0):
-    """The oracle, as it stands, on the host cores: repeated passes over boxes
-    of the workload until about `budget_s` seconds of CPU work."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(case, budget_s=20.0):
+    """The oracle, as it stands (FP64, Bernstein-literal), built -O3
+    -march=native on this host and timed on its cores: a seeded sample of the
+    workload's boxes (boxes are independent), first with every OpenMP thread,
+    then single-threaded, each leg within its share of `budget_s` seconds
+    (at least one box). Per-box times give the median and spread; `value`
+    scales the all-core median to the metric's unit."""
     from oracle import oracle as orc
-    t0 = time.perf_counter()
-    boxes = 0
-    reps = 0
-    while True:
-        for i in range(case.n_boxes):
+    orc.use_native()
+    all_threads = orc.get_threads()
+    order = np.random.default_rng(1234).permutation(case.n_boxes)
+
+    def leg(threads, budget, cap):
+        orc.set_threads(threads)
+        times = []
+        t_all = time.perf_counter()
+        for i in order[:cap]:
+            t0 = time.perf_counter()
             orc.network(case.Ws, case.bs, case.box_lo[i], case.box_hi[i], L=case.L,
                         plan=None if case.plan is None else case.plan[i])
-            boxes += 1
-            if time.perf_counter() - t0 >= budget_s:
+            times.append(time.perf_counter() - t0)
+            if time.perf_counter() - t_all >= budget:
                 break
-        reps += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return dict(value=boxes * case.bounded_neurons_per_box / dt, unit="neurons/s", cores=orc.get_threads(),
-                kind="oracle",
-                sample=f"{boxes} box evaluations of the workload ({reps} pass(es) over its {case.n_boxes} box(es)) "
-                       f"in {dt:.1f} s, FP64 Bernstein-literal oracle")
+        return np.array(times)
+
+    multi = leg(all_threads, 0.6 * budget_s, 32)
+    single = leg(1, 0.4 * budget_s, 32)
+    orc.set_threads(all_threads)
+    per_box = case.bounded_neurons_per_box
+
+    def summary(t, threads):
+        return dict(value=per_box / float(np.median(t)), threads=threads, boxes=int(t.size),
+                    median_box_s=float(np.median(t)), min_box_s=float(t.min()), max_box_s=float(t.max()))
+
+    m, s1 = summary(multi, all_threads), summary(single, 1)
+    return dict(value=m["value"], unit="neurons/s", cores=all_threads, kind="oracle",
+                sample=(f"{m['boxes']} seeded boxes of the workload's {case.n_boxes} with {all_threads} threads "
+                        f"(median {m['median_box_s']:.3f} s per box), {s1['boxes']} single-threaded (median "
+                        f"{s1['median_box_s']:.3f} s); FP64 Bernstein-literal oracle, gcc -O3 -march=native"),
+                single_thread=s1, all_core=m, nproc=os.cpu_count(), cpu_model=_cpu_model())
 
 
 def measured_traffic(workload, cls):
@@ -110,7 +138,7 @@ def main():
     ap.add_argument("--workload", default="cfg5", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-plain", action="store_true", help="do not time the plain form (profiling runs)")
-    ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-autotune", action="store_true", help="keep the built-in kernel variants")
     ap.add_argument("--graph", action="store_true",
                     help="replay the plain rule's launch sequence as one captured graph")

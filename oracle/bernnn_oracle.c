@@ -43,7 +43,15 @@
  *   R9  linear fallback: the degree-1 approximant's post polynomials, replaced
  *       by their least-squares affine fit to the Bernstein control net plus the
  *       largest (upper) or smallest (lower) remainder coefficient; sound by
- *       Def. 2 for any affine function.
+ *       Def. 2 for any affine function;
+ *   R13 periodic linearisation Lin (Section 5.4: the post polynomials are
+ *       dropped to degree (1,...,1) every Lin hidden layers; the cited
+ *       linearisation is not given): after every hidden layer whose index
+ *       (1-based) is a multiple of Lin, each neuron's stored post polynomials
+ *       (at the layer's degree, after the elevation of R7/R8) are replaced by
+ *       the R9 construction -- least-squares affine fit of the Bernstein
+ *       control net plus the extreme remainder -- so the next layer starts
+ *       at degree 1. Lin = 0 switches it off (the paper's experiments).
  */
 #include <math.h>
 #include <stdint.h>
@@ -368,6 +376,9 @@ static void ls_affine(int n, int d, const double *B, double *beta) {
   for (int a = 0; a < n; ++a) beta[1 + a] = (d == 0) ? 0.0 : beta[1 + a] / ss[a];
 }
 
+/* Exported for the tests (pins of reading R9). */
+void orc_ls_affine(int n, int d, const double *B, double *beta) { ls_affine(n, d, B, beta); }
+
 /* Affine function l given by beta, evaluated at t. */
 static double ls_eval(int n, const double *beta, const double *t) {
   double v = beta[0];
@@ -398,6 +409,8 @@ static void linearize(int n, int d, const double *P, int sign, double *out) {
     out[i] = ls_eval(n, beta, t) + ext; /* linear precision: Bernstein coef = value at corner */
   }
 }
+
+void orc_linearize(int n, int d, const double *P, int sign, double *out) { linearize(n, d, P, sign, out); }
 
 static double tmin(const double *x, long long c) {
   double m = x[0];
@@ -435,13 +448,15 @@ int orc_get_threads(void) {
  *   out_U/out_L  (nullable) output Bernstein tensors, capacity out_cap doubles each
  *   used_plan    (nullable) per hidden neuron: the ReLU degree actually used
  *                (0 inactive/zero, -1 active/identity, -2 linear fallback, >=1 degree)
+ *   lin          periodic linearisation (reading R13): 0 off, k >= 1 after
+ *                every k-th hidden layer
  */
 int orc_network(int H, const int *widths, const double *W, const double *bias,
                 const double *box_lo, const double *box_hi, int L, const int8_t *plan,
                 double *neuron_lo, double *neuron_hi, double *out_lo, double *out_hi,
                 double *rel_vol, int *out_deg, double *out_U, double *out_L,
-                long long out_cap, int8_t *used_plan) {
-  if (H < 1 || !widths || !W || !bias || !box_lo || !box_hi) return ORC_E_ARG;
+                long long out_cap, int8_t *used_plan, int lin) {
+  if (H < 1 || !widths || !W || !bias || !box_lo || !box_hi || lin < 0) return ORC_E_ARG;
   int n = widths[0];
   if (n < 1 || n > 16) return ORC_E_ARG;
   for (int i = 0; i <= H; ++i) if (widths[i] < 1) return ORC_E_ARG;
@@ -594,6 +609,27 @@ int orc_network(int H, const int *widths, const double *W, const double *bias,
       if (s < stl) stl = s;
     }
     st = stl;
+    /* R13: every lin-th hidden layer, every neuron's stored post polynomials
+     * (degree dpost) become their linearisation at degree 1 */
+    if (st == ORC_OK && lin > 0 && layer % lin == 0) {
+      long long c1n = orc_tsize(n, 1);
+      double *lu = (double *)malloc(sizeof(double) * (size_t)(h * c1n));
+      double *ll = (double *)malloc(sizeof(double) * (size_t)(h * c1n));
+      if (!lu || !ll) {
+        free(lu); free(ll);
+        st = ORC_E_OOM;
+      } else {
+        for (int j = 0; j < h; ++j) {
+          linearize(n, dpost, prev.U + j * cp, +1, lu + j * c1n);
+          linearize(n, dpost, prev.Lw + j * cp, -1, ll + j * c1n);
+        }
+        free(prev.U);
+        free(prev.Lw);
+        prev.U = lu;
+        prev.Lw = ll;
+        prev.d = 1;
+      }
+    }
     free(lo); free(hi); free(deg); free(kind);
     free(Uh); free(Lh);
     woff += (long long)h * hin;
@@ -617,7 +653,7 @@ int orc_network_boxes(int H, const int *widths, const double *W, const double *b
   for (long long bx = 0; bx < n_boxes; ++bx) {
     int st = orc_network(H, widths, W, bias, box_lo + bx * n, box_hi + bx * n, L,
                          plan ? plan + bx * nh : NULL, neuron_lo + bx * nh, neuron_hi + bx * nh,
-                         out_lo + bx * o, out_hi + bx * o, NULL, NULL, NULL, NULL, 0, NULL);
+                         out_lo + bx * o, out_hi + bx * o, NULL, NULL, NULL, NULL, 0, NULL, 0);
     if (st != ORC_OK) return st;
   }
   return ORC_OK;

@@ -20,17 +20,34 @@ _pi8 = ctypes.POINTER(ctypes.c_int8)
 _ll = ctypes.c_longlong
 
 
-def lib():
+def _builder():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("_oracle_build", os.path.join(HERE, "build.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def use_native():
+    """Switch to a copy of the oracle compiled with -O3 -march=native on this
+    host (built now; the same source). Must be called before the first use."""
+    global _LIB
+    if _LIB is not None and getattr(_LIB, "_native", False):
+        return
+    if _LIB is not None:
+        raise RuntimeError("the oracle library is already loaded")
+    _builder().build_native()
+    lib(native=True)
+
+
+def lib(native=False):
     global _LIB
     if _LIB is None:
-        path = os.path.join(HERE, "liboracle.so")
+        path = os.path.join(HERE, "liboracle_native.so" if native else "liboracle.so")
         if not os.path.exists(path):
-            import importlib.util
-            spec = importlib.util.spec_from_file_location("_oracle_build", os.path.join(HERE, "build.py"))
-            mod = importlib.util.module_from_spec(spec)
-            spec.loader.exec_module(mod)
-            mod.build()
+            _builder().build()
         L = ctypes.CDLL(path)
+        L._native = native
         L.orc_binom.restype = _d
         L.orc_binom.argtypes = [ctypes.c_int, ctypes.c_int]
         L.orc_tsize.restype = _ll
@@ -60,7 +77,11 @@ def lib():
         L.orc_get_threads.restype = ctypes.c_int
         L.orc_network.restype = ctypes.c_int
         L.orc_network.argtypes = [ctypes.c_int, _pi, _pd, _pd, _pd, _pd, ctypes.c_int, _pi8,
-                                  _pd, _pd, _pd, _pd, _pd, _pi, _pd, _pd, _ll, _pi8]
+                                  _pd, _pd, _pd, _pd, _pd, _pi, _pd, _pd, _ll, _pi8, ctypes.c_int]
+        L.orc_ls_affine.restype = None
+        L.orc_ls_affine.argtypes = [ctypes.c_int, ctypes.c_int, _pd, _pd]
+        L.orc_linearize.restype = None
+        L.orc_linearize.argtypes = [ctypes.c_int, ctypes.c_int, _pd, ctypes.c_int, _pd]
         _LIB = L
     return _LIB
 
@@ -170,12 +191,31 @@ def get_threads():
     return lib().orc_get_threads()
 
 
-def network(Ws, bs, box_lo, box_hi, L=2, plan=None, want_polys=False):
+def ls_affine(n, d, B):
+    """Least-squares affine fit of the Bernstein control net of B (degree d):
+    beta[0] + sum_a beta[1+a] (t_a - 1/2)."""
+    B = _c(B)
+    beta = np.zeros(n + 1)
+    lib().orc_ls_affine(n, d, _p(B), _p(beta))
+    return beta
+
+
+def linearize(n, d, P, sign):
+    """Degree-1 Bernstein tensor of the linear fallback of P (sign +1: upper,
+    -1: lower)."""
+    P = _c(P)
+    out = np.zeros(tsize(n, 1))
+    lib().orc_linearize(n, d, _p(P), int(sign), _p(out))
+    return out
+
+
+def network(Ws, bs, box_lo, box_hi, L=2, plan=None, want_polys=False, lin=0):
     """Bounds of one box (Problem 1). ``Ws``/``bs`` are lists of per-layer
     arrays (W^(i) of shape h_i x h_{i-1}). Returns a dict with the hidden
     pre-activation bounds, output bounds, relative volume, output degree, the
     per-neuron degree actually used and (optionally) the output Bernstein
-    tensors."""
+    tensors. ``lin`` > 0 linearises every lin-th hidden layer's post
+    polynomials."""
     H = len(Ws)
     widths = np.array([Ws[0].shape[1]] + [w.shape[0] for w in Ws], dtype=np.int32)
     n = int(widths[0])
@@ -197,13 +237,13 @@ def network(Ws, bs, box_lo, box_hi, L=2, plan=None, want_polys=False):
     if want_polys:
         # capacity for the largest degree this call can reach
         Lmax = L if plan is None else max(1, int(plan.max()))
-        dmax = Lmax ** (H - 1)
+        dmax = Lmax ** (H - 1) if lin == 0 else Lmax ** max(1, min(H - 1, lin))
         cap = o * tsize(n, dmax)
         oU, oL = np.zeros(cap), np.zeros(cap)
     st = lib().orc_network(H, widths.ctypes.data_as(_pi), _p(W), _p(b), _p(lo_), _p(hi_), int(L), planp,
                            _p(nlo), _p(nhi), _p(olo), _p(ohi), _p(rv), deg.ctypes.data_as(_pi),
                            _p(oU) if oU is not None else None, _p(oL) if oL is not None else None,
-                           cap, used.ctypes.data_as(_pi8))
+                           cap, used.ctypes.data_as(_pi8), int(lin))
     _check(st)
     res = dict(neuron_lo=nlo[:nh], neuron_hi=nhi[:nh], out_lo=olo, out_hi=ohi, rel_vol=rv,
                out_deg=int(deg[0]), used_plan=used[:nh])
