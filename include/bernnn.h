@@ -106,16 +106,47 @@ typedef struct {
   int32_t graph;      /* nonzero: runs with no host round trip (BERN_PLAN_PLAIN) are
                          captured once per distinct argument set into a HIP graph
                          and replayed as one graph launch; other plans run eagerly */
-  int32_t reserved[6];
+  int32_t lin;        /* periodic linearisation (the Lin parameter of Section 5.4):
+                         0 = off (the paper's experiments); k >= 1 = after every k-th
+                         hidden layer, each neuron's post polynomials are replaced by
+                         affine upper / lower bounds -- the least-squares affine fit of
+                         their Bernstein control net at the layer's stored degree plus
+                         the largest (upper) or smallest (lower) remainder -- so the
+                         next layer starts again at degree 1. The post degrees of
+                         the linearised layers must be read off by one block each
+                         (BERN_E_TOO_LARGE otherwise)                              */
+  int32_t reserved0;
+  uint64_t mem_budget_bytes; /* 0 = no limit; else bern_workspace_size, bern_bounds and
+                         the calls built on it refuse (BERN_E_TOO_LARGE, the size
+                         needed in the message) options whose one-box workspace
+                         exceeds this many bytes                                   */
+  int64_t *counters;  /* optional device output, BERN_NCOUNTERS int64 values written
+                         by the call (see bern_counter), or NULL                   */
 } bern_opts;
+
+/* Entries of bern_opts.counters (device, int64), summed over the call's boxes. */
+typedef enum {
+  BERN_CNT_HIDDEN = 0,   /* hidden neurons bounded                                  */
+  BERN_CNT_INACTIVE = 1, /* stable neurons with hi <= 0 (zero polynomial)           */
+  BERN_CNT_ACTIVE = 2,   /* stable neurons with lo >= 0 (identity)                  */
+  BERN_CNT_FALLBACK = 3, /* unstable neurons on the linear fallback                 */
+  BERN_CNT_ORDER1 = 4,   /* unstable neurons with a ReLU approximant of order 1     */
+  BERN_CNT_ORDER2 = 5,   /* ... of order 2                                          */
+  BERN_CNT_ORDER3UP = 6, /* ... of order 3 or more                                  */
+  BERN_CNT_MAXPAD = 7,   /* FP32 mode: the largest rounding radius of an output
+                            polynomial (the bits of a non-negative double), 0 in FP64 */
+  BERN_NCOUNTERS = 8
+} bern_counter;
 
 typedef struct {
   int32_t n_waves;      /* waves the boxes were split into                          */
   int32_t boxes_per_wave;
   int32_t out_degree;   /* largest per-variable degree of an output polynomial      */
-  int32_t reserved0;
+  int32_t lin_layers;   /* hidden layers linearised (bern_opts.lin)                 */
   uint64_t workspace_used; /* bytes of the workspace actually used                  */
-  uint64_t reserved[6];
+  double enqueue_ms;    /* host time spent inside the call (the device work it
+                           enqueued may still be running when it returns)          */
+  uint64_t reserved[5];
 } bern_stats;
 
 /* Fill *opts with defaults: L = 2, FP64, plain plan, per-box schedule. */

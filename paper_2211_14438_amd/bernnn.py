@@ -29,13 +29,22 @@ _vp = ctypes.c_void_p
 class bern_opts(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("precision", ctypes.c_int32), ("plan", ctypes.c_int32),
                 ("sched", ctypes.c_int32), ("pred", ctypes.c_void_p), ("features", ctypes.c_void_p),
-                ("max_wave", ctypes.c_int32), ("graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("max_wave", ctypes.c_int32), ("graph", ctypes.c_int32), ("lin", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("mem_budget_bytes", ctypes.c_uint64), ("counters", ctypes.c_void_p)]
+
+
+COUNTERS = ("hidden", "inactive", "active", "fallback", "order1", "order2", "order3up", "max_pad")
 
 
 class bern_stats(ctypes.Structure):
     _fields_ = [("n_waves", ctypes.c_int32), ("boxes_per_wave", ctypes.c_int32), ("out_degree", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("workspace_used", ctypes.c_uint64),
-                ("reserved", ctypes.c_uint64 * 6)]
+                ("lin_layers", ctypes.c_int32), ("workspace_used", ctypes.c_uint64),
+                ("enqueue_ms", ctypes.c_double), ("reserved", ctypes.c_uint64 * 5)]
+
+
+def _stats(st):
+    return dict(n_waves=st.n_waves, boxes_per_wave=st.boxes_per_wave, out_degree=st.out_degree,
+                lin_layers=st.lin_layers, workspace_used=st.workspace_used, enqueue_ms=st.enqueue_ms)
 
 
 class bern_verify_result(ctypes.Structure):
@@ -175,7 +184,7 @@ def _stream(stream):
 
 
 def make_opts(L=2, precision="fp64", plan="plain", sched="per_box", max_wave=0, pred=None, features=None,
-              graph=False):
+              graph=False, lin=0, mem_budget=0, counters=None):
     o = bern_opts()
     lib().bern_opts_default(ctypes.byref(o))
     o.L = int(L)
@@ -186,7 +195,19 @@ def make_opts(L=2, precision="fp64", plan="plain", sched="per_box", max_wave=0, 
     o.pred = None if pred is None else (pred.handle if isinstance(pred, Predictor) else pred)
     o.features = None if features is None else features.data_ptr()
     o.graph = 1 if graph else 0
+    o.lin = int(lin)
+    o.mem_budget_bytes = int(mem_budget)
+    o.counters = None if counters is None else counters.data_ptr()
     return o
+
+
+def read_counters(counters):
+    """The bern_opts.counters entries of a finished call as a dict (the
+    largest output pad decoded from its double bits)."""
+    v = counters.cpu().numpy().astype(np.int64)
+    d = {k: int(x) for k, x in zip(COUNTERS, v)}
+    d["max_pad"] = float(np.array([v[7]], dtype=np.int64).view(np.float64)[0])
+    return d
 
 
 N_PARAMS = 5012
@@ -287,7 +308,7 @@ class Net:
 
 
 def _prepare(net, box_lo, box_hi, L, precision, plan, sched, degree_plan, max_wave, workspace, outputs, pred,
-             features, graph):
+             features, graph, lin=0, mem_budget=0, counters=None):
     import torch
     dev = box_lo.device
     assert box_lo.dtype == torch.float64 and box_hi.dtype == torch.float64
@@ -295,7 +316,7 @@ def _prepare(net, box_lo, box_hi, L, precision, plan, sched, degree_plan, max_wa
     box_hi = box_hi.contiguous()
     nb = box_lo.shape[0]
     o = make_opts(L=L, precision=precision, plan=plan, sched=sched, max_wave=max_wave, pred=pred, features=features,
-                  graph=graph)
+                  graph=graph, lin=lin, mem_budget=mem_budget, counters=counters)
     if outputs is None:
         nh = max(net.n_hidden, 1)
         outputs = dict(
@@ -307,7 +328,7 @@ def _prepare(net, box_lo, box_hi, L, precision, plan, sched, degree_plan, max_wa
         )
     if workspace is None:
         total, one = net.workspace_size(nb, L=L, precision=precision, plan=plan, sched=sched, max_wave=max_wave,
-                                        pred=pred)
+                                        pred=pred, lin=lin, mem_budget=mem_budget)
         workspace = torch.empty(total + 256, dtype=torch.uint8, device=dev)
     ws_ptr = workspace.data_ptr()
     pad = (-ws_ptr) % 256
@@ -322,31 +343,31 @@ def _prepare(net, box_lo, box_hi, L, precision, plan, sched, degree_plan, max_wa
 
 
 def bounds(net, box_lo, box_hi, L=2, precision="fp64", plan="plain", sched="per_box", degree_plan=None,
-           max_wave=0, workspace=None, stream=None, outputs=None, pred=None, features=None, graph=False):
+           max_wave=0, workspace=None, stream=None, outputs=None, pred=None, features=None, graph=False, lin=0,
+           mem_budget=0, counters=None):
     """Bounds of every box. ``box_lo``/``box_hi``: float64 CUDA tensors
     [n_boxes, n]. Returns a dict of CUDA tensors (neuron_lo/hi, out_lo/hi,
     used_plan) plus the run statistics. Asynchronous on ``stream``. With
     ``graph`` the plain rule's launch sequence is captured once and replayed
     as one graph launch."""
     args, res, workspace, keep = _prepare(net, box_lo, box_hi, L, precision, plan, sched, degree_plan, max_wave,
-                                          workspace, outputs, pred, features, graph)
+                                          workspace, outputs, pred, features, graph, lin, mem_budget, counters)
     st = bern_stats()
     _check(lib().bern_bounds(*args, _stream(stream), ctypes.byref(st)))
-    res["stats"] = dict(n_waves=st.n_waves, boxes_per_wave=st.boxes_per_wave, out_degree=st.out_degree,
-                        workspace_used=st.workspace_used)
+    res["stats"] = _stats(st)
     res["workspace"] = workspace
     return res
 
 
 def output_polys(net, box_lo, box_hi, degree, L=2, precision="fp64", plan="plain", sched="batched",
-                 degree_plan=None, max_wave=0, pred=None, stream=None):
+                 degree_plan=None, max_wave=0, pred=None, stream=None, lin=0):
     """The output polynomials of every box as dense power tensors in t at
     per-variable ``degree``: a dict with ``U`` and ``L`` (float64 CUDA
     tensors [n_boxes, n_out, (degree+1)^n]) and the output bounds
     ``out_lo``/``out_hi``. Asynchronous on ``stream``."""
     import torch
     args, res, workspace, keep = _prepare(net, box_lo, box_hi, L, precision, plan, sched, degree_plan, max_wave,
-                                          None, None, pred, None, False)
+                                          None, None, pred, None, False, lin)
     nb, dev = box_lo.shape[0], box_lo.device
     C = (int(degree) + 1) ** net.n
     U = torch.empty((nb, net.n_out, C), dtype=torch.float64, device=dev)
@@ -358,13 +379,13 @@ def output_polys(net, box_lo, box_hi, degree, L=2, precision="fp64", plan="plain
 
 
 def rel_volume(net, box_lo, box_hi, L=2, precision="fp64", plan="plain", sched="batched", degree_plan=None,
-               max_wave=0, pred=None, stream=None):
+               max_wave=0, pred=None, stream=None, lin=0):
     """Relative volume of the output set of every box (Section 6): a dict with
     ``rel_vol`` (float64 CUDA tensor [n_boxes, n_out]) and the output bounds
     ``out_lo``/``out_hi``. Asynchronous on ``stream``."""
     import torch
     args, res, workspace, keep = _prepare(net, box_lo, box_hi, L, precision, plan, sched, degree_plan, max_wave,
-                                          None, None, pred, None, False)
+                                          None, None, pred, None, False, lin)
     vol = torch.empty((box_lo.shape[0], net.n_out), dtype=torch.float64, device=box_lo.device)
     # args: handle, opts, nb, lo, hi, plan, neuron_lo, neuron_hi, out_lo, out_hi, used, ws, ws_bytes
     _check(lib().bern_rel_volume(args[0], args[1], args[2], args[3], args[4], args[5], _ptr(vol), args[8], args[9],
@@ -373,13 +394,13 @@ def rel_volume(net, box_lo, box_hi, L=2, precision="fp64", plan="plain", sched="
 
 
 def verify(net, box_lo, box_hi, out_index, threshold, max_rounds=8, max_boxes=1 << 16, L=2, precision="fp64",
-           plan="plain", sched="batched", pred=None):
+           plan="plain", sched="batched", pred=None, lin=0):
     """Branch and bound for "output ``out_index`` <= ``threshold``" over host
     boxes (numpy [n_boxes, n]); returns the verified / violated / undecided
     volume fractions, the rounds run and the box counts."""
     box_lo = np.ascontiguousarray(box_lo, dtype=np.float64)
     box_hi = np.ascontiguousarray(box_hi, dtype=np.float64)
-    o = make_opts(L=L, precision=precision, plan=plan, sched=sched, pred=pred)
+    o = make_opts(L=L, precision=precision, plan=plan, sched=sched, pred=pred, lin=lin)
     r = bern_verify_result()
     _check(lib().bern_verify(net.handle, ctypes.byref(o), box_lo.shape[0], ctypes.c_void_p(box_lo.ctypes.data),
                              ctypes.c_void_p(box_hi.ctypes.data), int(out_index), float(threshold), int(max_rounds),
@@ -389,7 +410,7 @@ def verify(net, box_lo, box_hi, out_index, threshold, max_rounds=8, max_boxes=1 
 
 
 def bounds_host(net, box_lo, box_hi, L=2, precision="fp64", plan="plain", sched="batched", degree_plan=None,
-                max_wave=0, pred=None):
+                max_wave=0, pred=None, lin=0, mem_budget=0):
     """``bounds`` on host arrays (numpy float64 [n_boxes, n]), synchronous:
     the library allocates and frees the device buffers itself. Returns a dict
     of numpy arrays (neuron_lo/hi, out_lo/hi, used_plan) and the run
@@ -398,7 +419,8 @@ def bounds_host(net, box_lo, box_hi, L=2, precision="fp64", plan="plain", sched=
     box_hi = np.ascontiguousarray(box_hi, dtype=np.float64)
     nb = box_lo.shape[0]
     nh = max(net.n_hidden, 1)
-    o = make_opts(L=L, precision=precision, plan=plan, sched=sched, max_wave=max_wave, pred=pred)
+    o = make_opts(L=L, precision=precision, plan=plan, sched=sched, max_wave=max_wave, pred=pred, lin=lin,
+                  mem_budget=mem_budget)
     res = dict(neuron_lo=np.empty((nb, nh)), neuron_hi=np.empty((nb, nh)), out_lo=np.empty((nb, net.n_out)),
                out_hi=np.empty((nb, net.n_out)), used_plan=np.empty((nb, nh), dtype=np.int8))
     dp = None if degree_plan is None else np.ascontiguousarray(degree_plan, dtype=np.int8)
@@ -407,17 +429,16 @@ def bounds_host(net, box_lo, box_hi, L=2, precision="fp64", plan="plain", sched=
     _check(lib().bern_bounds_host(net.handle, ctypes.byref(o), nb, vp(box_lo), vp(box_hi), vp(dp),
                                   vp(res["neuron_lo"]), vp(res["neuron_hi"]), vp(res["out_lo"]), vp(res["out_hi"]),
                                   vp(res["used_plan"]), ctypes.byref(st)))
-    res["stats"] = dict(n_waves=st.n_waves, boxes_per_wave=st.boxes_per_wave, out_degree=st.out_degree,
-                        workspace_used=st.workspace_used)
+    res["stats"] = _stats(st)
     return res
 
 
 def autotune(net, box_lo, box_hi, reps=3, L=2, precision="fp64", plan="plain", sched="batched", degree_plan=None,
-             max_wave=0, workspace=None, stream=None, outputs=None, pred=None):
+             max_wave=0, workspace=None, stream=None, outputs=None, pred=None, lin=0):
     """Pick the fastest kernel variants for this network and workload (stored
     in the network handle). Returns (choice list, mean ms per run)."""
     args, res, workspace, keep = _prepare(net, box_lo, box_hi, L, precision, plan, sched, degree_plan, max_wave,
-                                          workspace, outputs, pred, None, False)
+                                          workspace, outputs, pred, None, False, lin)
     L_ = lib()
     k = L_.bern_tune_params()
     choice = (ctypes.c_int32 * k)()

@@ -4,6 +4,7 @@
 // Section 5.2, the bounds of Step 1, the approximant of Step 2 and the
 // composition of Step 3, and finally the output bounds).
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
@@ -87,7 +88,7 @@ ProfScope::~ProfScope() {
 static const char *kProfNames[kProfCount] = {
     "layer1",          "gemm",         "convert_small",  "convert_passA",  "convert_passB", "convert_final",
     "convert_chunk",   "compose_scatter", "compose_fill", "compose_square", "compose_horner", "poly_mul",
-    "predictor",       "misc"};
+    "predictor",       "misc",         "lin"};
 
 size_t device_lds_limit() {
   static std::mutex mu;
@@ -110,6 +111,8 @@ size_t device_lds_limit() {
 // layer's pre-activation and post tensors and the per-box workspace layout.
 struct Plan {
   int H, n, L, Lmax, mode;
+  int lin;                          // periodic linearisation: every lin-th hidden layer (0 off)
+  int lin_layers;                   // hidden layers linearised
   bool fp64;
   std::vector<int> Dpre, Dpost;     // per layer i = 1..H (index i-1); Dpost for hidden layers
   std::vector<int64_t> Cpre, Cpost;
@@ -163,6 +166,8 @@ static bern_status plan_net(const bern_net *net, const bern_opts *o, Plan &p) {
   p.elem = p.fp64 ? 8 : 4;
   p.L = o->L;
   p.mode = o->plan;
+  p.lin = o->lin;
+  p.lin_layers = 0;
   if (o->L < 1 || o->L > kMaxOrder) {
     set_error("L = %d outside 1..%d", o->L, kMaxOrder);
     return BERN_E_DEGREE;
@@ -219,6 +224,17 @@ static bern_status plan_net(const bern_net *net, const bern_opts *o, Plan &p) {
         p.horner = std::max(p.horner, compose_scratch_bytes(Cq, p.Lmax, h, 1));
       }
       D = Dn;
+      if (p.lin > 0 && (i + 1) % p.lin == 0) {
+        // the post tensors are read off whole (fits and remainders) by one
+        // block each, then the next layer starts at degree 1
+        if (!convert_one_block(p.n, Dn)) {
+          set_error("Lin at hidden layer %d: post degree %d in %d variables exceeds one block's read-off", i + 1,
+                    Dn, p.n);
+          return BERN_E_TOO_LARGE;
+        }
+        ++p.lin_layers;
+        D = 1;
+      }
     }
   }
   // per box: validity flag, post degree, one id per (layer, phase) list, and
@@ -227,6 +243,11 @@ static bern_status plan_net(const bern_net *net, const bern_opts *o, Plan &p) {
   p.live = align256(sizeof(int) * (3 + 3 * (size_t)net->hmax));
   p.rad = align256(sizeof(double) * 4 * (size_t)net->hmax);
   p.oeps = align256(sizeof(double) * 2 * (size_t)net->o);
+  if (o->mem_budget_bytes > 0 && p.per_box() > o->mem_budget_bytes) {
+    set_error("one box needs %zu bytes of workspace, over the budget of %llu", p.per_box(),
+              (unsigned long long)o->mem_budget_bytes);
+    return BERN_E_TOO_LARGE;
+  }
   return BERN_OK;
 }
 
@@ -388,6 +409,10 @@ static bern_status check_opts(const bern_net *net, const bern_opts *o) {
     set_error("unknown plan %d", o->plan);
     return BERN_E_ARG;
   }
+  if (o->lin < 0 || o->lin > 64) {
+    set_error("lin = %d outside 0..64", o->lin);
+    return BERN_E_ARG;
+  }
   return BERN_OK;
 }
 
@@ -446,6 +471,44 @@ __global__ void box_degree_kernel(int64_t nb, int h, const NeuronRec *recs, int 
   if (lane == 0) deg[b] = d;
 }
 
+// Counters (bern_opts.counters): cleared by one block, then per hidden layer
+// one wave per box counts its neurons' rules, and after the output layer one
+// thread per box folds the output radii into the largest pad.
+__global__ void counters_clear_kernel(long long *cnt) {
+  if (threadIdx.x < BERN_NCOUNTERS) cnt[threadIdx.x] = 0;
+}
+
+__global__ void counters_rules_kernel(int64_t nb, int h, const NeuronRec *recs, long long *cnt) {
+  const int64_t b = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (b >= nb) return;
+  const int lane = threadIdx.x & 63;
+  long long c[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int j = lane; j < h; j += 64) {
+    const int k = recs[b * h + j].kind;
+    c[0] += 1;
+    c[1] += k == kInactive;
+    c[2] += k == kActive;
+    c[3] += k == kFallback;
+    c[4] += k == 1;
+    c[5] += k == 2;
+    c[6] += k >= 3;
+  }
+  for (int q = 0; q < 7; ++q) {
+    long long v = c[q];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0 && v) atomicAdd(reinterpret_cast<unsigned long long *>(cnt + q), (unsigned long long)v);
+  }
+}
+
+__global__ void counters_pad_kernel(int64_t nb, int o, const double *eps, long long *cnt) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  double m = 0.0;
+  for (int q = 0; q < 2 * o; ++q) m = fmax(m, eps[b * 2 * o + q]);
+  // non-negative doubles order like their bit patterns
+  atomicMax(reinterpret_cast<unsigned long long *>(cnt + BERN_CNT_MAXPAD), (unsigned long long)__double_as_longlong(m));
+}
+
 // Index tables of one layer's degree class: the dense positions for the
 // read-off at Din and, for compositions, the square table (Din, Din) and the
 // Horner tables (Din, m Din), m = 1 .. Lmax - 1. Built once per network.
@@ -499,6 +562,182 @@ struct OutPolys {
   const int *didx;  // rank -> dense index at degree D
   double *vol = nullptr;
 };
+
+// Compose arguments of hidden layer i for the boxes of class cl (bids).
+static bern_status compose_args(const bern_net *net, const Plan &p, int i, const BoxClass &cl, const int *bids,
+                                void *pre, void *post, int64_t slotA, int64_t slotB, NeuronRec *recs, double *rad,
+                                double *cpart, void *horner, size_t horner_bytes, int *live, int64_t live_ld,
+                                ComposeArgs &m) {
+  const int n = net->n;
+  m = ComposeArgs{};
+  m.n = n;
+  m.Din = cl.Din;
+  m.Dout = cl.Dout;
+  m.h = net->widths[i + 1];
+  m.bids = bids;
+  m.slot_in = slotA;
+  m.slot_out = slotB;
+  m.nbounds = 2;
+  m.Lmax = p.Lmax;
+  LayerTables lt;
+  bern_status st = layer_tables(net, cl.Din, p.Lmax, true, lt);
+  if (st != BERN_OK) return st;
+  m.Cin = ssize(n, cl.Din);
+  m.Cout = ssize(n, cl.Dout);
+  m.Cs = ssize(n, std::min(cl.Din, cl.Dout));
+  for (int q = 0; q <= kMaxOrder; ++q) m.Sm[q] = q <= p.Lmax ? ssize(n, q * cl.Din) : 0;
+  m.Cq = p.Lmax >= 3 ? ssize(n, (p.Lmax - 1) * cl.Din) : 0;
+  if (lt.sq) {
+    m.sq_off = lt.sq->off;
+    m.sq_pairs = lt.sq->pairs;
+    m.sq_diag = lt.sq->diag;
+  }
+  for (int q = 1; q < kMaxOrder; ++q)
+    if (lt.hz[q]) {
+      m.hz_off[q] = lt.hz[q]->off;
+      m.hz_pairs[q] = lt.hz[q]->pairs;
+    }
+  m.nboxes = (int64_t)cl.ids.size();
+  m.pre = pre;
+  m.post = post;
+  m.recs = recs;
+  m.rad = p.fp64 ? nullptr : rad;
+  m.fp64 = p.fp64 ? 1 : 0;
+  m.scratch = horner;
+  m.scratch_bytes = horner_bytes;
+  m.nbx = compose_nbx(m.Cout);
+  m.pstride = p.nbx[i];
+  m.part = p.fp64 ? nullptr : cpart;
+  m.live = live;
+  m.live_ld = live_ld;
+  return BERN_OK;
+}
+
+// Hidden layer i under periodic linearisation (opts.lin): every class's
+// compositions at its post degree, the post radii of the layer (FP32 mode),
+// then per class every neuron's post polynomials staged whole at that degree
+// and read off with fits and remainders (mode 2); the affine posts stored at
+// degree 1 for all boxes, and the next layer's affine map over every box at
+// degree 1 (Section 5.4, the Lin parameter).
+static bern_status lin_layer_run(const bern_net *net, const Plan &p, int i, const std::vector<BoxClass> &next,
+                                 const std::vector<const int *> &pid, int64_t B, void *const *Aa, void *Bp,
+                                 int64_t slotA, int64_t slotB, NeuronRec *recs, double *rad, double *cpart,
+                                 void *horner, int *live, int64_t live_ld, double *gpart, double *conv,
+                                 hipStream_t s) {
+  const int n = net->n, h = net->widths[i + 1];
+  for (size_t k = 0; k < next.size(); ++k) {
+    ComposeArgs m;
+    bern_status st = compose_args(net, p, i, next[k], pid[k], Aa[i & 1], Bp, slotA, slotB, recs, rad, cpart, horner,
+                                  p.horner * B, live, live_ld, m);
+    if (st != BERN_OK) return st;
+    m.lists_ready = 1;  // the lists below, once the layer is linearised
+    m.radii_later = 1;
+    BERN_HIP_TRY(launch_compose(m, s));
+  }
+  if (!p.fp64) {
+    ComposeArgs mr{};
+    mr.n = n;
+    mr.h = h;
+    mr.nboxes = B;
+    mr.nbounds = 2;
+    mr.recs = recs;
+    mr.part = cpart;
+    mr.nbx = p.nbx[i];
+    mr.pstride = p.nbx[i];
+    mr.rad = rad;
+    mr.fp64 = 0;
+    BERN_HIP_TRY(launch_post_radii(mr, s));
+  }
+  for (size_t k = 0; k < next.size(); ++k) {
+    const BoxClass &cl = next[k];
+    if (cl.Dout < 1) continue;  // every neuron inactive: nothing to linearise
+    ComposeArgs m;
+    bern_status st = compose_args(net, p, i, cl, pid[k], Aa[i & 1], Bp, slotA, slotB, recs, rad, cpart, horner,
+                                  p.horner * B, live, live_ld, m);
+    if (st != BERN_OK) return st;
+    BERN_HIP_TRY(launch_lin_stage(m, s));
+    LayerTables lt;
+    st = layer_tables(net, cl.Dout, p.Lmax, false, lt);
+    if (st != BERN_OK) return st;
+    ConvertArgs c{};
+    c.n = n;
+    c.D = cl.Dout;
+    c.h = h;
+    c.L = p.L;
+    c.C = ipow(cl.Dout + 1, n);
+    c.S = ssize(n, cl.Dout);
+    c.didx = lt.didx;
+    c.plist = lt.plist;
+    c.plist_len = lt.plist_len;
+    if (lt.tree) {
+      c.tree = lt.tree->buf;
+      c.tree_len = lt.tree->len;
+      for (int d = 0; d <= n && d < 17; ++d) c.tree_base[d] = lt.tree->base[d];
+    }
+    c.nboxes = (int64_t)cl.ids.size();
+    c.bids = pid[k];
+    c.slot = slotB;
+    c.cap = cl.Dout;
+    c.pre = Bp;
+    c.fp64 = p.fp64 ? 1 : 0;
+    c.recs = recs;
+    c.scratch = conv;
+    c.scratch_bytes = p.conv * B;
+    c.layer = i;
+    c.hin = net->widths[i];
+    c.W = net->W64 + net->woff[i];
+    c.b = net->b64 + net->boff[i];
+    c.mode = 2;
+    c.tune = net->tune;
+    const hipError_t e = launch_convert(c, s);
+    if (e == hipErrorInvalidValue) {
+      set_error("Lin read-off at degree %d in %d variables is not available", cl.Dout, n);
+      return BERN_E_TOO_LARGE;
+    }
+    BERN_HIP_TRY(e);
+  }
+  // the affine posts of every box at degree 1, then their input lists
+  ComposeArgs ml{};
+  ml.n = n;
+  ml.h = h;
+  ml.nboxes = B;
+  ml.nbounds = 2;
+  ml.recs = recs;
+  ml.post = Bp;
+  ml.slot_out = slotB;
+  ml.rad = p.fp64 ? nullptr : rad;
+  ml.fp64 = p.fp64 ? 1 : 0;
+  ml.live = live;
+  ml.live_ld = live_ld;
+  ml.lin = 1;
+  BERN_HIP_TRY(launch_lin_scatter(ml, s));
+  BERN_HIP_TRY(launch_live(ml, s));
+  GemmArgs a{};
+  a.hin = h;
+  a.h = net->widths[i + 2];
+  a.C = n + 1;
+  a.nboxes = B;
+  a.bids = nullptr;
+  a.slot_in = slotB;
+  a.slot_out = slotA;
+  a.post = Bp;
+  a.pre = Aa[(i + 1) & 1];
+  a.act = Aa[i & 1];
+  a.act_slot = slotA;
+  a.Cact = n + 1;
+  a.live = live;
+  a.live_ld = live_ld;
+  a.Cs = n + 1;
+  a.tune = net->tune;
+  a.WT = net->WT + net->wtoff[i + 1];
+  a.hp = net->hpad[i + 1];
+  a.b = net->b64 + net->boff[i + 1];
+  a.fp64 = p.fp64 ? 1 : 0;
+  a.rpart = p.fp64 ? nullptr : gpart;
+  a.rpart_slot = (int64_t)(p.gpart / sizeof(double));
+  BERN_HIP_TRY(launch_gemm(a, s));
+  return BERN_OK;
+}
 
 static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts *o, int64_t b0, int64_t B,
                             const double *box_lo, const double *box_hi, const int8_t *plan, double *nlo, double *nhi,
@@ -593,8 +832,9 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
     const bool last = (i == p.H - 1);
     NeuronRec *recs = recbuf[i & 1];
     const NeuronRec *prev = recbuf[(i + 1) & 1];
-    int cap = 1;
-    for (int q = 0; q <= i; ++q) cap *= p.L;
+    // plan codes are clamped to the plain rule's post degree of the layer
+    const int cap = last ? 1 : p.Dpost[i];
+    const bool lin_layer = !last && p.lin > 0 && (i + 1) % p.lin == 0;
     // bounds read-off (+ rules and approximants for hidden layers), per class
     std::vector<const int *> cid;
     bern_status st = BERN_OK;
@@ -658,7 +898,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
         c.ld_out = net->o;
         c.col0 = 0;
         c.used = nullptr;
-        c.out_eps = (op && !p.fp64) ? oeps : nullptr;
+        c.out_eps = ((op || o->counters) && !p.fp64) ? oeps : nullptr;
       } else {
         c.mode = 0;
         c.out_lo = nlo;
@@ -695,6 +935,18 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
         BERN_HIP_TRY(launch_learned_rules(la, s));
       else
         BERN_HIP_TRY(launch_features(la, s));
+    }
+    if (!last && o->counters) {
+      ProfScope ps(kProfMisc, s, 0.0);
+      hipLaunchKernelGGL(counters_rules_kernel, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, s, B, h,
+                         (const NeuronRec *)recs, (long long *)o->counters);
+      BERN_HIP_TRY(hipGetLastError());
+    }
+    if (last && o->counters && !p.fp64) {
+      ProfScope ps(kProfMisc, s, 0.0);
+      hipLaunchKernelGGL(counters_pad_kernel, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, B, net->o,
+                         (const double *)oeps, (long long *)o->counters);
+      BERN_HIP_TRY(hipGetLastError());
     }
     if (last) {
       if (op) {  // the output layer's stored tensors, per class, into the caller's dense tensors
@@ -764,6 +1016,19 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
     std::vector<const int *> pid;
     st = upload(next, i, 1, pid);
     if (st != BERN_OK) return st;
+    if (lin_layer) {
+      st = lin_layer_run(net, p, i, next, pid, B, Aa, Bp, slotA, slotB, recs, radbuf[i & 1], cpart, horner, live,
+                         live_ld, gpart, conv, s);
+      if (st != BERN_OK) return st;
+      classes.assign(1, BoxClass{1, 0, {}});
+      classes[0].ids.resize(B);
+      for (int64_t b = 0; b < B; ++b) {
+        classes[0].ids[b] = (int)b;
+        dcur[b] = 1;
+      }
+      carried.clear();
+      continue;
+    }
     // several classes: the next affine map's input lists of every box at once
     const bool lists_once = next.size() > 1;
     if (lists_once) {
@@ -897,6 +1162,8 @@ static bern_status run_graph(bern_net *net, const bern_opts *o, int64_t n_boxes,
   key.push_back((uint64_t)o->sched);
   key.push_back((uint64_t)o->max_wave);
   key.push_back((uint64_t)(uintptr_t)o->features);
+  key.push_back((uint64_t)o->lin);
+  key.push_back((uint64_t)(uintptr_t)o->counters);
   key.push_back((uint64_t)net->tune.gemm_wide | (uint64_t)net->tune.gemm_narrow << 8 |
                 (uint64_t)net->tune.conv_block << 16 | (uint64_t)net->tune.conv_wave << 24);
   int dev = 0;
@@ -941,6 +1208,7 @@ static bern_status bounds_impl(const bern_net *net, const bern_opts *opts, int64
                                const double *box_hi, const int8_t *plan, double *neuron_lo, double *neuron_hi,
                                double *out_lo, double *out_hi, int8_t *used_plan, void *workspace, size_t ws_bytes,
                                void *stream, bern_stats *stats, const OutPolys *op) {
+  const auto t_enter = std::chrono::steady_clock::now();
   bern_status st = check_opts(net, opts);
   if (st != BERN_OK) return st;
   if (n_boxes < 1 || !box_lo || !box_hi || !out_lo || !out_hi) {
@@ -970,6 +1238,11 @@ static bern_status bounds_impl(const bern_net *net, const bern_opts *opts, int64
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int nwaves = (int)((n_boxes + wave - 1) / wave);
   auto run_all = [&](hipStream_t rs) -> bern_status {
+    if (opts->counters) {
+      ProfScope ps(kProfMisc, rs, 0.0);
+      hipLaunchKernelGGL(counters_clear_kernel, dim3(1), dim3(64), 0, rs, (long long *)opts->counters);
+      BERN_HIP_TRY(hipGetLastError());
+    }
     for (int64_t b0 = 0; b0 < n_boxes; b0 += wave) {
       const int64_t B = std::min<int64_t>(wave, n_boxes - b0);
       bern_status r = run_wave(net, p, opts, b0, B, box_lo + b0 * net->n, box_hi + b0 * net->n,
@@ -990,6 +1263,10 @@ static bern_status bounds_impl(const bern_net *net, const bern_opts *opts, int64
       LayerTables lt;
       st = layer_tables(net, p.Dpre[i], p.Lmax, i < p.H - 1, lt);
       if (st != BERN_OK) return st;
+      if (i < p.H - 1 && p.lin > 0 && (i + 1) % p.lin == 0) {  // the Lin read-off at the post degree
+        st = layer_tables(net, p.Dpost[i], p.Lmax, false, lt);
+        if (st != BERN_OK) return st;
+      }
     }
     st = run_graph(const_cast<bern_net *>(net), opts, n_boxes,
                    {(uint64_t)(uintptr_t)box_lo, (uint64_t)(uintptr_t)box_hi, (uint64_t)(uintptr_t)neuron_lo,
@@ -1006,7 +1283,10 @@ static bern_status bounds_impl(const bern_net *net, const bern_opts *opts, int64
     stats->n_waves = nwaves;
     stats->boxes_per_wave = (int32_t)wave;
     stats->out_degree = p.Dpre[p.H - 1];
+    stats->lin_layers = p.lin_layers;
     stats->workspace_used = per_box * (size_t)wave;
+    stats->enqueue_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_enter).count();
   }
   return BERN_OK;
 }

@@ -124,6 +124,7 @@ enum ProfClass : int {
   kProfPolyMul,
   kProfPredictor,
   kProfMisc,
+  kProfLin,
   kProfCount
 };
 struct ProfScope {
@@ -227,7 +228,12 @@ struct ConvertArgs {
   int64_t plan_ld, plan_col0;
   int learned;                    // rules are chosen later by the predictor (fits always needed)
   int fits;                       // compute the affine fits of every hidden neuron (features)
-  int mode;                       // 0 hidden layer, 1 output layer
+  int mode;                       // 0 hidden layer, 1 output layer, 2 periodic linearisation
+                                  // (Lin): `pre` holds the hidden layer's post tensors at degree
+                                  // D, every neuron is fitted, and the affine post (fit plus the
+                                  // extreme remainder) goes to the record's fbU / fbL with its
+                                  // radius in fbpadU / fbpadL (the stored posts' radii padU /
+                                  // padL take the place of the pre-activation radii)
   double *scratch;                // staging and partial extrema for tensors too large for LDS
   size_t scratch_bytes;
   Tune tune;
@@ -263,6 +269,9 @@ struct OutPolyArgs {
 };
 hipError_t launch_out_polys(const OutPolyArgs &a, hipStream_t s);
 size_t convert_scratch_bytes(int n, int D, int h, int64_t nboxes);
+// Whether tensors of n variables and degree D are read off by one block each
+// (no staging): the read-offs that can fit every neuron (mode 2 needs it).
+bool convert_one_block(int n, int D);
 // Whether tensors of n variables and degree D take the tree read-off (they
 // then need the TreeTable of degree D).
 bool convert_tree(int n, int D);
@@ -298,6 +307,8 @@ struct ComposeArgs {
   double *rad;                    // FP32 mode: [B][h][4] copies of the records' padU, padL, pl1U,
                                   // pl1L, read densely by the next layer's radii
   int64_t live_ld;
+  int lin;                        // the layer was linearised: every neuron that is not inactive
+                                  // holds a full degree-1 post tensor (live lists, Lin launchers)
 };
 hipError_t launch_compose(const ComposeArgs &a, hipStream_t s);
 // The input lists (ComposeArgs::live) of a.nboxes boxes (bids, h, recs,
@@ -307,6 +318,19 @@ hipError_t launch_live(const ComposeArgs &a, hipStream_t s);
 // The post radii (FP32 mode) of a.nboxes boxes in one launch (n, h, bids,
 // recs, part, pstride or nbx, rad used), after every class's composition.
 hipError_t launch_post_radii(const ComposeArgs &a, hipStream_t s);
+// Periodic linearisation (Lin) of a hidden layer, around a mode-2 read-off:
+// launch_lin_stage writes every neuron's post polynomials of a.nboxes boxes
+// (bids) as full tensors of a.Cout coefficients (degree Dout) in the post
+// arena: composed ones are already there, order-1 and fallback ones are
+// zero-padded past their a.Cs stored coefficients, active ones copied from
+// their pre-activations (a.Cin coefficients) and zero-padded, inactive ones
+// zeroed. launch_lin_scatter then stores the records' affine posts (fbU /
+// fbL) of a.nboxes boxes at degree 1 (n + 1 coefficients per tensor, the
+// post arena's layout for Dout = 1), sets each record's degree to 1, and in
+// FP32 mode its radii (fbpad plus the stores' rounding) and l1 norms, also
+// into a.rad.
+hipError_t launch_lin_stage(const ComposeArgs &a, hipStream_t s);
+hipError_t launch_lin_scatter(const ComposeArgs &a, hipStream_t s);
 // Blocks per item the compose launches of a layer use (partials stride).
 int64_t compose_nbx(int64_t Cout);
 size_t compose_scratch_bytes(int64_t Cq, int Lmax, int h, int64_t nboxes);

@@ -411,9 +411,11 @@ __global__ void __launch_bounds__(kBlock) live_kernel(ComposeArgs a) {
   for (int j0 = 0; j0 < a.h; j0 += 64) {
     const int j = j0 + lane;
     const int kind = j < a.h ? a.recs[box * a.h + j].kind : (int)kInactive;
-    const bool full = kind >= 2;
-    const bool small = kind == 1 || kind == kFallback;
-    const bool act = kind == kActive;
+    // after a linearisation every neuron that is not inactive holds a full
+    // degree-1 post tensor
+    const bool full = a.lin ? (j < a.h && kind != kInactive) : kind >= 2;
+    const bool small = !a.lin && (kind == 1 || kind == kFallback);
+    const bool act = !a.lin && kind == kActive;
     const unsigned long long bf = __ballot(full), bs = __ballot(small), ba = __ballot(act);
     if (full) lv[3 + nf + __popcll(bf & below)] = j;
     if (small) lv[3 + a.h + ns + __popcll(bs & below)] = j;
@@ -756,6 +758,99 @@ __global__ void post_radii_kernel(ComposeArgs a, NeuronRec *recs) {
     q[2] = r.pl1U;
     q[3] = r.pl1L;
   }
+}
+
+// ------------------------------------- periodic linearisation (Lin)
+// One wave per (box, neuron, bound): the neuron's post polynomial as a full
+// tensor of Cout coefficients (degree Dout) in the post arena, for the
+// mode-2 read-off. Composed neurons (order >= 2) already hold it; order-1
+// and fallback ones hold their first Cs coefficients; active ones take their
+// pre-activation (Cin coefficients, Din <= Dout); the rest is zero, which in
+// the total-degree layout is the elevation to Dout (Prop. 4).
+template <typename T>
+__global__ void __launch_bounds__(64) lin_stage_kernel(ComposeArgs a) {
+  int64_t g;
+  int j, s;
+  if (!wave_item(a, g, j, s)) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t box = wave_box(a, g);
+  const int kind = a.recs[box * a.h + j].kind;
+  if (kind >= 2) return;
+  T *out = out_tensor<T>(a, box, j, s);
+  int64_t from = 0;
+  if (kind == kActive) {
+    const T *p = in_tensor<T>(a, box, j, s);
+    for (int64_t I = lane; I < a.Cin; I += 64) out[I] = p[I];
+    from = a.Cin;
+  } else if (kind == 1 || kind == kFallback) {
+    from = a.Cs;
+  }
+  for (int64_t I = from + lane; I < a.Cout; I += 64) out[I] = (T)0;
+}
+
+// One thread per (box, neuron): the linearised posts (fbU, fbL) stored at
+// degree 1, n + 1 coefficients per tensor, and the record updated: degree 1,
+// FP32 radii = the linearisation's radius plus the exact rounding of the
+// stores, l1 norms of the stored coefficients. Inactive neurons store
+// nothing (they stay out of the next affine map's lists).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) lin_scatter_kernel(ComposeArgs a, NeuronRec *recs) {
+  const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= a.nboxes * a.h) return;
+  const int64_t box = wave_box(a, item / a.h);
+  const int j = (int)(item % a.h);
+  NeuronRec &r = recs[box * a.h + j];
+  const int64_t C1 = a.n + 1;
+  double pad[2] = {0.0, 0.0}, l1[2] = {0.0, 0.0};
+  if (r.kind != kInactive) {
+    for (int s = 0; s < 2; ++s) {
+      const double *fb = s == 0 ? r.fbU : r.fbL;
+      T *out = reinterpret_cast<T *>(a.post) + box * a.slot_out + ((int64_t)j * 2 + s) * C1;
+      double rs = 0.0;
+      for (int q = 0; q <= a.n; ++q) store(out + q, fb[q], rs, l1[s]);
+      if (!a.fp64) pad[s] = ((s == 0 ? r.fbpadU : r.fbpadL) + rs) * kPadSafety;
+    }
+  }
+  r.deg = r.kind == kInactive ? 0 : 1;
+  r.padU = pad[0];
+  r.padL = pad[1];
+  r.pl1U = l1[0];
+  r.pl1L = l1[1];
+  if (a.rad) {
+    double *q = a.rad + (box * a.h + j) * 4;
+    q[0] = pad[0];
+    q[1] = pad[1];
+    q[2] = l1[0];
+    q[3] = l1[1];
+  }
+}
+
+hipError_t launch_lin_stage(const ComposeArgs &a_in, hipStream_t s) {
+  if (a_in.nboxes < 1) return hipSuccess;
+  if (a_in.Cin > a_in.Cout || a_in.Cs > a_in.Cout || a_in.nbounds != 2) return hipErrorInvalidValue;
+  ComposeArgs a = a_in;
+  a.group = 1;
+  const int64_t items = a.nboxes * a.h * a.nbounds;
+  ProfScope ps(kProfLin, s, 0.0);
+  if (a.fp64)
+    hipLaunchKernelGGL(lin_stage_kernel<double>, dim3((unsigned)items), dim3(64), 0, s, a);
+  else
+    hipLaunchKernelGGL(lin_stage_kernel<float>, dim3((unsigned)items), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_lin_scatter(const ComposeArgs &a, hipStream_t s) {
+  if (a.nboxes < 1) return hipSuccess;
+  if (!a.recs || !a.post) return hipErrorInvalidValue;
+  const unsigned blocks = (unsigned)((a.nboxes * a.h + kBlock - 1) / kBlock);
+  ProfScope ps(kProfLin, s, 0.0);
+  if (a.fp64)
+    hipLaunchKernelGGL(lin_scatter_kernel<double>, dim3(blocks), dim3(kBlock), 0, s, a,
+                       const_cast<NeuronRec *>(a.recs));
+  else
+    hipLaunchKernelGGL(lin_scatter_kernel<float>, dim3(blocks), dim3(kBlock), 0, s, a,
+                       const_cast<NeuronRec *>(a.recs));
+  return hipGetLastError();
 }
 
 // ------------------------------------------------ plain product kernel

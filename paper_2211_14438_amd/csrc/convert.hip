@@ -197,6 +197,15 @@ template <class Team>
 __device__ void radii_and_l1(const ConvertArgs &a, int64_t box, int j, const Team &tm, double (&l1)[2],
                              double &epsU, double &epsL) {
   epsU = epsL = 0.0;
+  if (a.mode == 2) {  // linearisation: the radii of the stored post polynomials
+    if (!a.fp64) {
+      const NeuronRec &r = a.recs[box * a.h + j];
+      epsU = r.padU;
+      epsL = r.padL;
+    }
+    tm.reduce(l1, OpAdd());
+    return;
+  }
   if (a.fp64 || a.layer == 0) {
     if (!a.fp64) pre_radii(a, box, j, a.pre, tm.tid, tm.nt, [](double v) { return v; }, epsU, epsL);
     tm.reduce(l1, OpAdd());
@@ -862,7 +871,40 @@ __device__ inline double side_hi(const ConvertArgs &a, double mx, double l1, dou
 }
 
 __device__ inline bool wants_fit(const ConvertArgs &a, int64_t box, int j) {
+  if (a.mode == 2) return true;
   return a.mode == 0 && a.D > 0 && (a.learned || a.fits || (a.plan && a.plan[box * a.plan_ld + a.plan_col0 + j] <= 0));
+}
+
+// Periodic linearisation (mode 2, thread 0): the affine post polynomials
+// l + max remainder (upper) and l + min remainder (lower) of one neuron in
+// the power basis, from the fits bU, bL (l(t) = b[0] + sum_a b[1+a] (t_a -
+// 1/2)) and the remainder extrema fx = (rmaxU, rminU, rmaxL, rminL). FP32
+// mode: the radius of each is the stored post's radius, the read-off's
+// rounding of the Bernstein coefficients (gconv times the l1 norm) and the
+// FP64 rounding of the fit's evaluation at the grid and of the conversion to
+// the power basis (gamma(n + 8) times the fit's and remainder's magnitudes).
+__device__ inline void write_lin(const ConvertArgs &a, int64_t box, int j, const double *bU, const double *bL,
+                                 const double *fx, double epsU, double epsL, double l1U, double l1L) {
+  NeuronRec &r = a.recs[box * a.h + j];
+  double sU = 0.0, sL = 0.0, aU = fabs(bU[0]), aL = fabs(bL[0]);
+  for (int ax = 0; ax < a.n; ++ax) {
+    sU += bU[1 + ax];
+    sL += bL[1 + ax];
+    aU += fabs(bU[1 + ax]);
+    aL += fabs(bL[1 + ax]);
+  }
+  r.fbU[0] = bU[0] - 0.5 * sU + fx[0];
+  r.fbL[0] = bL[0] - 0.5 * sL + fx[3];
+  for (int q = 1; q <= kMaxInputs; ++q) {
+    r.fbU[q] = q <= a.n ? bU[q] : 0.0;
+    r.fbL[q] = q <= a.n ? bL[q] : 0.0;
+  }
+  r.fbpadU = r.fbpadL = 0.0;
+  if (!a.fp64) {
+    const double ge = gamma64(a.n + 8);
+    r.fbpadU = epsU + a.gconv * l1U + ge * (aU + fabs(fx[0]));
+    r.fbpadL = epsL + a.gconv * l1L + ge * (aL + fabs(fx[3]));
+  }
 }
 
 __device__ inline void write_neuron(const ConvertArgs &a, int64_t box, int j, double lo, double hi, double epsU,
@@ -949,6 +991,10 @@ __device__ void readoff_pair(const ConvertArgs &a, const Team &tm, bool fitter, 
     fx[2] = ex[4];
     fx[3] = -ex[5];
   }
+  if (a.mode == 2) {
+    if (tm.tid == 0) write_lin(a, box, j, blU, blL, fx, epsU, epsL, l1U, l1L);
+    return;
+  }
   if (a.mode == 0 && fitted) {  // the fits (an unfitted neuron's are never read)
     NeuronRec &rec = a.recs[box * a.h + j];
     team_write_fit(a, tm, rec.fitU, blU);
@@ -1032,6 +1078,24 @@ __global__ void __launch_bounds__(kBlock) convert_affine_kernel(ConvertArgs a) {
       u[r] = (double)p[i];
       w[r] = (double)p[S + i];
     }
+  }
+  if (a.mode == 2) {
+    // an affine post is its own linearisation (zero remainders): its
+    // coefficients, and in FP32 mode its radius, carry over unchanged
+    NeuronRec &rec = a.recs[box * a.h + j];
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+      const int q = l + r * kAffLanes;
+      if (q <= kMaxInputs) {
+        rec.fbU[q] = q < S ? u[r] : 0.0;
+        rec.fbL[q] = q < S ? w[r] : 0.0;
+      }
+    }
+    if (l == 0) {
+      rec.fbpadU = a.fp64 ? 0.0 : rec.padU;
+      rec.fbpadL = a.fp64 ? 0.0 : rec.padL;
+    }
+    return;
   }
   double epsU = 0.0, epsL = 0.0;
   if (!a.fp64) {
@@ -1692,6 +1756,10 @@ __device__ void ntree_neuron(const ConvertArgs &a, const NTreePlan &tp, const Te
     fx[2] = ex[4];
     fx[3] = -ex[5];
   }
+  if (a.mode == 2) {
+    if (tid == 0) write_lin(a, box, j, bl, bl + kMaxInputs + 1, fx, epsU, epsL, l1U, l1L);
+    return;
+  }
   if (a.mode == 0 && fitted) {  // the fits (an unfitted neuron's are never read)
     NeuronRec &rec = a.recs[box * a.h + j];
     team_write_fit(a, tm, rec.fitU, bl);
@@ -2148,12 +2216,31 @@ hipError_t launch_out_polys(const OutPolyArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
+bool convert_one_block(int n, int D) {
+  if (D == 1) return true;
+  const int64_t C = tsize(n, D);
+  return D >= 2 && D <= 8 && C >= 0 && (C <= kWaveC || use_small(C));
+}
+
 hipError_t launch_convert(const ConvertArgs &a_in, hipStream_t s) {
   // the rounding factors the kernels apply, once per launch
   ConvertArgs a = a_in;
   a.gconv = gamma64((double)a.n * (a.D + 2) + 4 + a.gextra);
   a.gpre = gamma64(2.0 * a.hin + 6);
   const int D1 = a.D + 1;
+  if (a.mode == 2) {  // linearisation: the kernels that fit every neuron
+    if (!convert_one_block(a.n, a.D) || (a.D >= 2 && !a.didx)) return hipErrorInvalidValue;
+    a.fits = 1;
+    a.used = nullptr;
+    a.out_lo = a.out_hi = nullptr;
+    if (a.tune.conv_wave == 1 || a.tune.conv_wave == 2) {
+      // the dense variants need the wave kernel's reach or a block's LDS
+      if (a.tune.conv_wave == 1 && a.C > kWaveC) a.tune.conv_wave = 2;
+    } else if (!a.tree && a.D >= 2) {
+      a.tune.conv_wave = a.C <= kWaveC ? 1 : 2;
+    }
+    return a.fp64 ? launch_convert_fixed<double>(a, s) : launch_convert_fixed<float>(a, s);
+  }
   if (a.D == 1 || (a.D >= 2 && a.D <= 8 && ((a.C <= kWaveC && a.tune.conv_wave == 0) || use_small(a.C))))
     return a.fp64 ? launch_convert_fixed<double>(a, s) : launch_convert_fixed<float>(a, s);
   if (a.C <= kWaveC) {

@@ -1,0 +1,123 @@
+"""Failure handling of the boundary, forced from the host (no kernel is made
+to fail): each call is refused with its documented status and a message
+before any work is enqueued, and the run statistics and counters report what
+the header promises."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2211_14438_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2211_14438_amd import bernnn as B  # noqa: E402
+
+DEV = "cuda:0"
+E_ARG, E_DEGREE, E_TOO_LARGE, E_WORKSPACE = -1, -4, -5, -7
+
+
+def _net_and_boxes(widths, seed=1, n_boxes=2):
+    case = wl.random_net_case(widths, seed=seed, n_boxes=n_boxes)
+    net = B.Net(case.Ws, case.bs)
+    lo = torch.tensor(case.box_lo, dtype=torch.float64, device=DEV)
+    hi = torch.tensor(case.box_hi, dtype=torch.float64, device=DEV)
+    return case, net, lo, hi
+
+
+def _status(fn):
+    with pytest.raises(B.BernError) as ei:
+        fn()
+    return ei.value.status, str(ei.value)
+
+
+@pytest.mark.parametrize("L", [0, 9, -1])
+def test_order_outside_range(L):
+    _, net, lo, hi = _net_and_boxes([3, 4, 2])
+    st, msg = _status(lambda: net.workspace_size(2, L=L))
+    assert st == E_DEGREE and "L =" in msg
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device=DEV)
+    st, _ = _status(lambda: B.bounds(net, lo, hi, L=L, workspace=ws))
+    assert st == E_DEGREE
+    net.close()
+
+
+def test_workspace_too_small_or_misaligned():
+    _, net, lo, hi = _net_and_boxes([3, 6, 5, 2])
+    total, one = net.workspace_size(2, L=2, sched="batched")
+    small = torch.empty(one - 512, dtype=torch.uint8, device=DEV)
+    ptr = small.data_ptr()
+    # an aligned view that is one 256-byte block short of one box
+    L_ = B.lib()
+    o = B.make_opts(L=2, sched="batched")
+    out = torch.empty((2, 2), dtype=torch.float64, device=DEV)
+    base = ptr + ((-ptr) % 256)
+    st = L_.bern_bounds(net.handle, ctypes.byref(o), 2, B._ptr(lo), B._ptr(hi), None, None, None, B._ptr(out),
+                        B._ptr(out), None, ctypes.c_void_p(base), one - 768, None, None)
+    assert st == E_WORKSPACE and b"smaller than one box" in L_.bern_last_error()
+    big = torch.empty(total + 512, dtype=torch.uint8, device=DEV)
+    mis = big.data_ptr() + ((-big.data_ptr()) % 256) + 8
+    st = L_.bern_bounds(net.handle, ctypes.byref(o), 2, B._ptr(lo), B._ptr(hi), None, None, None, B._ptr(out),
+                        B._ptr(out), None, ctypes.c_void_p(mis), total, None, None)
+    assert st == E_WORKSPACE
+    net.close()
+
+
+def test_tensor_size_overflow():
+    """(D+1)^n past the index range: 16 inputs, order 8, five hidden layers
+    reach per-variable degree 8^5."""
+    _, net, _, _ = _net_and_boxes([16, 3, 3, 3, 3, 3, 1])
+    st, msg = _status(lambda: net.workspace_size(1, L=8))
+    assert st == E_TOO_LARGE and "overflow" in msg
+    net.close()
+
+
+def test_memory_budget_refusal():
+    _, net, lo, hi = _net_and_boxes([3, 6, 5, 2])
+    _, one = net.workspace_size(1, L=2)
+    st, msg = _status(lambda: net.workspace_size(1, L=2, mem_budget=one - 1))
+    assert st == E_TOO_LARGE and str(one) in msg
+    assert net.workspace_size(1, L=2, mem_budget=one)[1] == one
+    st, _ = _status(lambda: B.bounds(net, lo, hi, L=2, mem_budget=one // 2))
+    assert st == E_TOO_LARGE
+    net.close()
+
+
+def test_bad_lin_and_plan_arguments():
+    _, net, lo, hi = _net_and_boxes([3, 6, 5, 2])
+    assert _status(lambda: net.workspace_size(1, L=2, lin=-1))[0] == E_ARG
+    assert _status(lambda: B.bounds(net, lo, hi, L=2, plan="given"))[0] == E_ARG  # no plan array
+    assert _status(lambda: B.bounds(net, lo, hi, L=2, plan="learned"))[0] == E_ARG  # no predictor
+    net.close()
+    # Lin needs the post tensors read off by one block: 8 inputs at degree 8 are not
+    _, net, _, _ = _net_and_boxes([8, 3, 3, 1])
+    st, msg = _status(lambda: net.workspace_size(1, L=8, lin=1))
+    assert st == E_TOO_LARGE and "Lin" in msg
+    net.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_counters_and_stats(precision):
+    case, net, lo, hi = _net_and_boxes([4, 9, 8, 3], seed=7, n_boxes=6)
+    plan = np.random.default_rng(2).integers(0, 4, size=(6, case.n_hidden)).astype(np.int8)
+    cnt = torch.full((8,), -5, dtype=torch.int64, device=DEV)
+    r = B.bounds(net, lo, hi, L=3, precision=precision, sched="batched", plan="given",
+                 degree_plan=torch.tensor(plan, device=DEV), counters=cnt)
+    torch.cuda.synchronize()
+    c = B.read_counters(cnt)
+    used = r["used_plan"].cpu().numpy()[:, :case.n_hidden]
+    assert c["hidden"] == used.size
+    assert c["inactive"] == int((used == 0).sum()) and c["active"] == int((used == -1).sum())
+    assert c["fallback"] == int((used == -2).sum()) and c["order1"] == int((used == 1).sum())
+    assert c["order2"] == int((used == 2).sum()) and c["order3up"] == int((used >= 3).sum())
+    if precision == "fp64":
+        assert c["max_pad"] == 0.0
+    else:
+        assert 0.0 < c["max_pad"] < 1e-4
+    s = r["stats"]
+    assert s["n_waves"] == 1 and s["boxes_per_wave"] == 6 and s["lin_layers"] == 0 and s["enqueue_ms"] > 0.0
+    net.close()
