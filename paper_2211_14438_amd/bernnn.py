@@ -99,6 +99,9 @@ def lib():
     L.bern_verify.restype = i32
     L.bern_verify.argtypes = [_vp, ctypes.POINTER(bern_opts), i64, _vp, _vp, i32, ctypes.c_double, i32, i64,
                               ctypes.POINTER(bern_verify_result)]
+    L.bern_bounds_noalloc.restype = i32
+    L.bern_bounds_noalloc.argtypes = [_vp, ctypes.POINTER(bern_opts), i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                      ctypes.POINTER(bern_stats)]
     L.bern_bounds_host.restype = i32
     L.bern_bounds_host.argtypes = [_vp, ctypes.POINTER(bern_opts), i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                    ctypes.POINTER(bern_stats)]
@@ -160,7 +163,9 @@ EXPORTED = ("bern_opts_default", "bern_net_create", "bern_net_destroy", "bern_ne
             "bern_prof_enable", "bern_prof_reset", "bern_prof_classes", "bern_prof_name", "bern_prof_read",
             "bern_pred_params", "bern_pred_create", "bern_pred_destroy", "bern_mlp_backward_scratch",
             "bern_mlp_forward", "bern_mlp_backward", "bern_mlp_adam", "bern_mlp_classify", "bern_tune_params",
-            "bern_tune_variants", "bern_tune_get", "bern_tune_set", "bern_autotune")
+            "bern_tune_variants", "bern_tune_get", "bern_tune_set", "bern_autotune", "bern_bounds_noalloc")
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # BERN_NOALLOC_SCRATCH_BYTES
 
 
 def status_str(s):
@@ -356,6 +361,32 @@ def bounds(net, box_lo, box_hi, L=2, precision="fp64", plan="plain", sched="per_
     _check(lib().bern_bounds(*args, _stream(stream), ctypes.byref(st)))
     res["stats"] = _stats(st)
     res["workspace"] = workspace
+    return res
+
+
+def bounds_noalloc(net, box_lo, box_hi, L=2, precision="fp64", lin=0, outputs=None, stream=None):
+    """``bounds`` of the plain rule without a workspace (bern_bounds_noalloc):
+    the library's own per-GPU scratch array, no allocation by the library.
+    Output tensors are allocated here unless ``outputs`` is given."""
+    import torch
+    dev = box_lo.device
+    box_lo, box_hi = box_lo.contiguous(), box_hi.contiguous()
+    nb = box_lo.shape[0]
+    if outputs is None:
+        nh = max(net.n_hidden, 1)
+        outputs = dict(neuron_lo=torch.empty((nb, nh), dtype=torch.float64, device=dev),
+                       neuron_hi=torch.empty((nb, nh), dtype=torch.float64, device=dev),
+                       out_lo=torch.empty((nb, net.n_out), dtype=torch.float64, device=dev),
+                       out_hi=torch.empty((nb, net.n_out), dtype=torch.float64, device=dev),
+                       used_plan=torch.empty((nb, nh), dtype=torch.int8, device=dev))
+    o = make_opts(L=L, precision=precision, plan="plain", sched="batched", lin=lin)
+    st = bern_stats()
+    _check(lib().bern_bounds_noalloc(net.handle, ctypes.byref(o), nb, _ptr(box_lo), _ptr(box_hi),
+                                     _ptr(outputs["neuron_lo"]), _ptr(outputs["neuron_hi"]), _ptr(outputs["out_lo"]),
+                                     _ptr(outputs["out_hi"]), _ptr(outputs.get("used_plan")), _stream(stream),
+                                     ctypes.byref(st)))
+    res = dict(outputs)
+    res["stats"] = _stats(st)
     return res
 
 

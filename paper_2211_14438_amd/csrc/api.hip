@@ -19,6 +19,9 @@
 namespace bern {
 
 static thread_local char g_err[1024] = "";
+static thread_local bool g_no_alloc = false;
+
+bool no_alloc_active() { return g_no_alloc; }
 
 void set_error(const char *fmt, ...) {
   va_list ap;
@@ -46,6 +49,7 @@ static hipEvent_t pool_get() {
     return e;
   }
   hipEvent_t e = nullptr;
+  if (g_no_alloc) return nullptr;  // no new events: the launch goes untimed
   if (hipEventCreate(&e) != hipSuccess) return nullptr;
   return e;
 }
@@ -1298,6 +1302,51 @@ extern "C" bern_status bern_bounds(const bern_net *net, const bern_opts *opts, i
   return bounds_impl(net, opts, n_boxes, box_lo, box_hi, plan, neuron_lo, neuron_hi, out_lo, out_hi, used_plan,
                      workspace, ws_bytes, stream, stats, nullptr);
 }
+
+namespace bern {
+// bern_bounds on a library-owned scratch buffer (bern_bounds_noalloc): the
+// plain rule only (no host staging of per-box degrees), run eagerly (no
+// graph objects), and only once every index table the options need exists
+// (checked before anything is enqueued); while it runs, table builders and
+// the profiler's event pool allocate nothing.
+bern_status bounds_on_scratch(const bern_net *net, const bern_opts *opts, int64_t n_boxes, const double *box_lo,
+                              const double *box_hi, double *neuron_lo, double *neuron_hi, double *out_lo,
+                              double *out_hi, int8_t *used_plan, void *scratch, size_t scratch_bytes, void *stream,
+                              bern_stats *stats) {
+  bern_status st = check_opts(net, opts);
+  if (st != BERN_OK) return st;
+  if (opts->plan != BERN_PLAN_PLAIN) {
+    set_error("bern_bounds_noalloc takes the plain rule only (per-neuron plans stage box degrees in host memory)");
+    return BERN_E_ARG;
+  }
+  Plan p;
+  if ((st = plan_net(net, opts, p)) != BERN_OK) return st;
+  if (p.per_box() > scratch_bytes) {
+    set_error("one box needs %zu bytes of scratch, over the %zu bytes bern_bounds_noalloc holds", p.per_box(),
+              scratch_bytes);
+    return BERN_E_TOO_LARGE;
+  }
+  struct Guard {
+    Guard() { g_no_alloc = true; }
+    ~Guard() { g_no_alloc = false; }
+  } guard;
+  for (int i = 0; i < p.H; ++i) {
+    LayerTables lt;
+    bool ok = layer_tables(net, p.Dpre[i], p.Lmax, i < p.H - 1, lt) == BERN_OK;
+    if (ok && i < p.H - 1 && p.lin > 0 && (i + 1) % p.lin == 0)
+      ok = layer_tables(net, p.Dpost[i], p.Lmax, false, lt) == BERN_OK;
+    if (!ok) {
+      set_error("the network's index tables for these options are not built yet (a bern_bounds call with the "
+                "same options builds them)");
+      return BERN_E_ARG;
+    }
+  }
+  bern_opts o = *opts;
+  o.graph = 0;
+  return bounds_impl(net, &o, n_boxes, box_lo, box_hi, nullptr, neuron_lo, neuron_hi, out_lo, out_hi, used_plan,
+                     scratch, scratch_bytes, stream, stats, nullptr);
+}
+}  // namespace bern
 
 extern "C" bern_status bern_output_polys(const bern_net *net, const bern_opts *opts, int64_t n_boxes,
                                          const double *box_lo, const double *box_hi, const int8_t *plan,

@@ -335,6 +335,13 @@ hipError_t launch_lin_scatter(const ComposeArgs &a, hipStream_t s);
 int64_t compose_nbx(int64_t Cout);
 size_t compose_scratch_bytes(int64_t Cq, int Lmax, int h, int64_t nboxes);
 
+// bern_bounds of the plain rule on a caller-independent scratch buffer,
+// allocating nothing (api.hip; used by bern_bounds_noalloc).
+bern_status bounds_on_scratch(const bern_net *net, const bern_opts *opts, int64_t n_boxes, const double *box_lo,
+                              const double *box_hi, double *neuron_lo, double *neuron_hi, double *out_lo,
+                              double *out_hi, int8_t *used_plan, void *scratch, size_t scratch_bytes, void *stream,
+                              bern_stats *stats);
+
 // Largest dynamic LDS allocation one block may use on the current device.
 size_t device_lds_limit();
 

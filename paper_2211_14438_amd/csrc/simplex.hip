@@ -77,6 +77,7 @@ hipError_t tree_table(SimplexTables &t, int D, const TreeTable **out) {
     *out = &it->second;
     return hipSuccess;
   }
+  if (no_alloc_active()) return hipErrorNotReady;
   const int n = t.n;
   if (D < 1 || D > 15 || n < 2 || n > kMaxTreeDims) return hipErrorInvalidValue;
   if (ssize(n, D, (int64_t)1 << 24) < 0) return hipErrorInvalidValue;
@@ -122,6 +123,7 @@ hipError_t dense_index_table(SimplexTables &t, int D, const int **out) {
     *out = it->second;
     return hipSuccess;
   }
+  if (no_alloc_active()) return hipErrorNotReady;
   const int n = t.n;
   const int64_t S = ssize(n, D, (int64_t)1 << 31);
   if (S < 0) return hipErrorInvalidValue;
@@ -155,6 +157,7 @@ hipError_t product_table(SimplexTables &t, int da, int db, bool sym, const ProdT
     *out = &it->second;
     return hipSuccess;
   }
+  if (no_alloc_active()) return hipErrorNotReady;
   if (sym && da != db) return hipErrorInvalidValue;
   const int n = t.n;
   const int64_t Sa = ssize(n, da, (int64_t)1 << 31), Sb = ssize(n, db, (int64_t)1 << 31);
@@ -216,6 +219,7 @@ hipError_t prefix_table(SimplexTables &t, int D, int na, const int **out, int *l
     *len = it->second.second;
     return hipSuccess;
   }
+  if (no_alloc_active()) return hipErrorNotReady;
   if (na < 1 || D < 0) return hipErrorInvalidValue;
   std::vector<int> off(na + 1), vals;
   for (int a = 0; a < na; ++a) {

@@ -75,6 +75,11 @@ struct SimplexTables {
   ~SimplexTables();
 };
 
+// True while the calling thread runs an entry point that must not allocate
+// (bern_bounds_noalloc): a table that is not built yet is then not built,
+// and its builder returns hipErrorNotReady.
+bool no_alloc_active();
+
 // Largest number of index pairs a product table may hold.
 constexpr int64_t kMaxPairs = (int64_t)1 << 25;
 
