@@ -89,6 +89,68 @@ def cpu_baseline(case, budget_s=20.0):
                 single_thread=s1, all_core=m, nproc=os.cpu_count(), cpu_model=_cpu_model())
 
 
+def _ssize(n, D):
+    from math import comb
+    return comb(n + D, n) if D >= 0 else 0
+
+
+def executed_work(case, used, L, plain, elem):
+    """Executed work of one pass in the composition and affine-map classes,
+    from the rule each hidden neuron took (used_plan) and the degrees that
+    follow from them: per box, a hidden layer's post degree is the largest of
+    its neurons' (inactive 0, active D, fallback 1, order k: k D; the plain
+    rule stores every neuron at L D). Square compositions (order 2) sum every
+    index pair of the stored coefficients once (S (S + 1) / 2 FMAs per bound,
+    S = C(n + D, n)); orders k >= 3 take k - 1 Horner products of the
+    (D, m D) tables; the affine map multiplies each live input coefficient by
+    every output row twice (midpoint and radius). Bytes: tensors read and
+    written. Returns {class: (flops, bytes)}."""
+    n, widths = case.n, case.widths
+    nb = used.shape[0]
+    D = np.ones(nb, dtype=np.int64)
+    sq_f = sq_b = hz_f = gm_f = gm_b = 0.0
+    col = 0
+    for i in range(1, len(widths) - 1):
+        h, hn = widths[i], widths[i + 1]
+        k = used[:, col:col + h].astype(np.int64)
+        deg = np.where(k == 0, 0, np.where(k == -1, D[:, None], np.where(k == -2, 1, k * D[:, None])))
+        Dout = np.full(nb, L, np.int64) * D if plain else deg.max(axis=1)
+        for d in np.unique(D):
+            rows = D == d
+            S = _ssize(n, int(d))
+            n2 = int((k[rows] == 2).sum())
+            sq_f += 2.0 * 2 * n2 * S * (S + 1) / 2
+            sq_b += 2 * n2 * elem * (S + _ssize(n, 2 * int(d)))
+            for order in range(3, 9):
+                no = int((k[rows] == order).sum())
+                if no:
+                    hz_f += 2.0 * 2 * no * sum(S * _ssize(n, m * int(d)) for m in range(1, order))
+        for b in range(nb):
+            so = _ssize(n, int(Dout[b]))
+            si = _ssize(n, int(D[b]))
+            sm = _ssize(n, int(min(D[b], Dout[b])))
+            kb = k[b]
+            live = so * int((kb >= 2).sum()) + sm * int(((kb == 1) | (kb == -2)).sum()) + si * int((kb == -1).sum())
+            gm_f += 2.0 * 2 * hn * live
+            gm_b += elem * (2 * live + 2 * hn * so)
+        D = Dout
+        col += h
+    return {"compose_square": (sq_f, sq_b), "compose_horner": (hz_f, 0.0), "gemm": (gm_f, gm_b)}
+
+
+def roof(flops, bytes_, ms, peak_flops):
+    """Roofline of a class by the intensity of its executed work: the FP64
+    vector roof above the ridge point, the HBM roof below it."""
+    ridge = peak_flops * 1e12 / (PEAK_HBM_GBS * 1e9)
+    if flops > 0 and (bytes_ <= 0 or flops / bytes_ > ridge):
+        a = flops / (ms * 1e-3) / 1e12
+        return dict(bound="alu", achieved=a, peak=peak_flops, unit="TFLOP/s", frac=a / peak_flops,
+                    intensity=flops / bytes_ if bytes_ > 0 else None)
+    a = bytes_ / (ms * 1e-3) / 1e9
+    return dict(bound="hbm", achieved=a, peak=PEAK_HBM_GBS, unit="GB/s", frac=a / PEAK_HBM_GBS,
+                intensity=flops / bytes_ if bytes_ > 0 else None)
+
+
 def measured_traffic(workload, cls):
     """HBM bytes per launch of kernel class `cls` on `workload`, from the
     rocprofv3 FETCH_SIZE / WRITE_SIZE summary under profiles/ (scaled by the
@@ -140,6 +202,8 @@ def main():
     ap.add_argument("--skip-plain", action="store_true", help="do not time the plain form (profiling runs)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-autotune", action="store_true", help="keep the built-in kernel variants")
+    ap.add_argument("--tune", default=None,
+                    help="comma-separated kernel variants to use instead of autotuning (profiling runs)")
     ap.add_argument("--graph", action="store_true",
                     help="replay the plain rule's launch sequence as one captured graph")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -169,8 +233,7 @@ def main():
         kw = dict(L=case.L, precision=spec["precision"], sched=sched)
         if form == "learned":
             from paper_2211_14438_amd import predictor as PR
-            params, meta = PR.load()
-            kw.update(plan="learned", pred=B.Predictor(params))
+            kw.update(plan="learned", pred=PR.load_predictor())
         elif form == "given":
             kw.update(plan="given", degree_plan=torch.tensor(case.plan, dtype=torch.int8, device=dev))
         total, one = net.workspace_size(case.n_boxes, **{k: v for k, v in kw.items() if k != "degree_plan"})
@@ -210,7 +273,11 @@ def main():
         return dt, prof
 
     kw = setup(spec["form"], spec["sched"])
-    tuned = None if args.no_autotune else autotune(kw)
+    if args.tune:
+        B.tune_set(net, [int(v) for v in args.tune.split(",")])
+        tuned = dict(choice=B.tune_get(net), seconds=0.0, ms_per_pass=None, fixed=True)
+    else:
+        tuned = None if args.no_autotune else autotune(kw)
     graph = bool(kw.get("graph"))
     # the timed region that gives `value` runs without per-launch events; the
     # kernel classes are then timed over the same number of steps with a pair
@@ -224,36 +291,48 @@ def main():
     used = outs["used_plan"].cpu().numpy()
     width = float((outs["out_hi"] - outs["out_lo"]).mean().item())
     plain_line = None
+    plain_batched = None
     if spec["form"] != "plain" and not args.skip_plain:
         del kw
         torch.cuda.empty_cache()
-        pkw = setup("plain", spec.get("plain_sched", "batched"))
         psteps = max(1, min(args.steps, 3))
-        pdt, _ = timed(pkw, psteps, False)
-        pw = float((pkw["outputs"]["out_hi"] - pkw["outputs"]["out_lo"]).mean().item())
-        plain_line = dict(form=f"plain order-{case.L} ({spec.get('plain_sched', 'batched')})",
-                          value=neurons * psteps / pdt, ms_per_step=pdt / psteps * 1e3, mean_output_width=pw)
-        del pkw
+        lines = {}
+        for psched in sorted({spec.get("plain_sched", "batched"), "batched"}):
+            pkw = setup("plain", psched)
+            pdt, _ = timed(pkw, psteps, False)
+            pw = float((pkw["outputs"]["out_hi"] - pkw["outputs"]["out_lo"]).mean().item())
+            lines[psched] = dict(form=f"plain order-{case.L} ({psched})", value=neurons * psteps / pdt,
+                                 ms_per_step=pdt / psteps * 1e3, mean_output_width=pw)
+            del pkw
+            torch.cuda.empty_cache()
+        plain_line = lines[spec.get("plain_sched", "batched")]
+        plain_batched = lines["batched"]
 
-    # roofline of the dominant kernel class (largest summed duration): the
-    # FP64 vector-ALU roof when its algorithmic flops per byte exceed the ridge
-    # point, the HBM roof otherwise
+    # roofline of the dominant kernel class (largest summed duration), from
+    # the work its kernels execute as the library counts it per launch (the
+    # tree read-off: its folds, expansions, lane tiles and extrema; bytes:
+    # stored tensors read, bounds and rules written): the FP64 vector roof
+    # when that work's flops per byte exceed the ridge point, else HBM. The
+    # read-off's arithmetic is FP64 in both precision modes.
     kernels = {}
     for name, (launches, ms, by, fl) in prof.items():
         kernels[name] = dict(launches=launches, avg_us=ms / launches * 1e3, total_ms=ms)
     dom = max(prof.items(), key=lambda kv: kv[1][1])[0]
     launches, ms, by, fl = prof[dom]
-    ridge = PEAK_VALU_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
-    if fl > 0 and (by <= 0 or fl / by > ridge):
-        achieved = fl / (ms * 1e-3) / 1e12
-        roof = dict(bound="alu", achieved=achieved, peak=PEAK_VALU_TFLOPS, unit="TFLOP/s",
-                    frac=achieved / PEAK_VALU_TFLOPS, traffic=measured_traffic(case.name, dom), kernel=dom,
-                    per_launch_flops=fl / launches, per_launch_bytes=by / launches, avg_launch_us=ms / launches * 1e3)
-    else:
-        achieved = by / (ms * 1e-3) / 1e9
-        roof = dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s", frac=achieved / PEAK_HBM_GBS,
-                    traffic=measured_traffic(case.name, dom), kernel=dom, per_launch_bytes=by / launches,
-                    avg_launch_us=ms / launches * 1e3)
+    roofline = roof(fl / launches, by / launches, ms / launches, PEAK_VALU_TFLOPS)
+    roofline.update(traffic=measured_traffic(case.name, dom), kernel=dom, per_launch_flops=fl / launches,
+                    per_launch_bytes=by / launches, avg_launch_us=ms / launches * 1e3)
+    # the composition and affine-map classes: executed work of the timed
+    # passes from the rules the neurons took, over the classes' event times
+    classes = {}
+    if used is not None:
+        elem = 8 if spec["precision"] == "fp64" else 4
+        work = executed_work(case, used[:, :case.n_hidden], case.L, spec["form"] == "plain", elem)
+        for cls, (wf, wb) in work.items():
+            if cls in prof and wf > 0:
+                n_, ms_, _, _ = prof[cls]
+                classes[cls] = roof(wf * args.steps / n_, wb * args.steps / n_, ms_ / n_, PEAK_VALU_TFLOPS)
+                classes[cls].update(avg_launch_us=ms_ / n_ * 1e3, launches=n_)
 
     line = {
         "metric": METRIC,
@@ -272,7 +351,8 @@ def main():
                    "L": case.L, "precision": spec["precision"], "form": f"{spec['form']} ({spec['sched']})"},
         "mean_output_width": width,
         "stable_neurons_skipped": int(((used == 0) | (used == -1)).sum()),
-        "roofline": roof,
+        "roofline": roofline,
+        "class_rooflines": classes,
         "kernels": kernels,
     }
     if tuned is not None:
@@ -283,6 +363,9 @@ def main():
         line["plain"] = plain_line
         line["speedup_vs_plain"] = value / plain_line["value"]
         line["width_ratio_vs_plain"] = width / plain_line["mean_output_width"]
+        line["plain_batched"] = plain_batched
+        line["speedup_vs_batched_plain"] = value / plain_batched["value"]
+        line["width_ratio_vs_batched_plain"] = width / plain_batched["mean_output_width"]
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(case, args.cpu_budget)
     print(json.dumps(line), flush=True)

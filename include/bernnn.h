@@ -115,7 +115,11 @@ typedef struct {
                          next layer starts again at degree 1. The post degrees of
                          the linearised layers must be read off by one block each
                          (BERN_E_TOO_LARGE otherwise)                              */
-  int32_t reserved0;
+  int32_t no_raise;   /* BERN_PLAN_LEARNED: 0 = per box and hidden layer, once the
+                         predictor has chosen, classes below the layer's top class
+                         are raised (to order 2 if some neuron takes order >= 2,
+                         fallback to order 1 if the top is order 1); 1 = every
+                         neuron keeps the predictor's class                        */
   uint64_t mem_budget_bytes; /* 0 = no limit; else bern_workspace_size, bern_bounds and
                          the calls built on it refuse (BERN_E_TOO_LARGE, the size
                          needed in the message) options whose one-box workspace
@@ -407,6 +411,40 @@ int32_t bern_pred_params(void);
 /* params: host, bern_pred_params() floats; copied to the current device. */
 bern_status bern_pred_create(const float *params, int64_t n_params, bern_pred **out);
 void bern_pred_destroy(bern_pred *pred);
+
+/* Predictor files and training.
+ * bern_pred_load -- a predictor from a file written by bern_pred_train
+ *   ("BERNPRED", uint32 version 1, uint32 bern_pred_params(), that many
+ *   float32 parameters, uint32 length and bytes of a metadata text; little-
+ *   endian). Errors: BERN_E_ARG (missing, foreign or truncated file), those
+ *   of bern_pred_create.
+ * bern_pred_train -- fit the MLP to N records, synchronously on the current
+ *   device with the training kernels below: X host [N][8] features (as
+ *   bern_opts.features exports them), y host [N] classes 0..3. The feature
+ *   normalisation is the records' mean and standard deviation (+1e-3); the
+ *   weights start from a seeded He initialisation (SplitMix64 stream,
+ *   Box-Muller normals); each epoch shuffles the records (seeded) and takes
+ *   N / batch minibatch Adam steps on the mean softmax cross-entropy, with the
+ *   learning rate lr (1 + cos(pi epoch / epochs)) / 2. `path` (nullable)
+ *   receives the file, with `meta` (nullable) as its metadata text; `out`
+ *   (nullable) a predictor with the trained parameters; opts->loss_out (host,
+ *   nullable, [epochs]) each epoch's mean minibatch loss. The library
+ *   allocates its device buffers and frees them before returning.
+ *   Errors: BERN_E_ARG (bad sizes, labels outside 0..3, an unwritable path),
+ *   BERN_E_NUMERIC (a non-finite feature), BERN_E_DEVICE. */
+typedef struct {
+  int32_t epochs;   /* passes over the records (default 40)                     */
+  int32_t batch;    /* records per Adam step (default 8192; at most N)          */
+  float lr;         /* peak learning rate (default 3e-3)                        */
+  float beta1, beta2, eps;  /* Adam (defaults 0.9, 0.999, 1e-8)                 */
+  uint64_t seed;    /* initialisation and shuffling stream (default 0)          */
+  float *loss_out;  /* host, optional, [epochs]                                 */
+  int32_t reserved[4];
+} bern_train_opts;
+void bern_train_opts_default(bern_train_opts *opts);
+bern_status bern_pred_load(const char *path, bern_pred **out);
+bern_status bern_pred_train(const float *X, const int8_t *y, int64_t N, const bern_train_opts *opts,
+                            const char *path, const char *meta, bern_pred **out);
 
 /* Training and evaluation kernels of the predictor (FP32, deterministic),
  * asynchronous on `stream`, all pointers device pointers:

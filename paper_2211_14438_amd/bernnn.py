@@ -30,7 +30,13 @@ class bern_opts(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("precision", ctypes.c_int32), ("plan", ctypes.c_int32),
                 ("sched", ctypes.c_int32), ("pred", ctypes.c_void_p), ("features", ctypes.c_void_p),
                 ("max_wave", ctypes.c_int32), ("graph", ctypes.c_int32), ("lin", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("mem_budget_bytes", ctypes.c_uint64), ("counters", ctypes.c_void_p)]
+                ("no_raise", ctypes.c_int32), ("mem_budget_bytes", ctypes.c_uint64), ("counters", ctypes.c_void_p)]
+
+
+class bern_train_opts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("seed", ctypes.c_uint64), ("loss_out", ctypes.c_void_p), ("reserved", ctypes.c_int32 * 4)]
 
 
 COUNTERS = ("hidden", "inactive", "active", "fallback", "order1", "order2", "order3up", "max_pad")
@@ -131,6 +137,13 @@ def lib():
     L.bern_pred_create.argtypes = [fp, i64, ctypes.POINTER(_vp)]
     L.bern_pred_destroy.restype = None
     L.bern_pred_destroy.argtypes = [_vp]
+    L.bern_pred_load.restype = i32
+    L.bern_pred_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(_vp)]
+    L.bern_train_opts_default.restype = None
+    L.bern_train_opts_default.argtypes = [ctypes.POINTER(bern_train_opts)]
+    L.bern_pred_train.restype = i32
+    L.bern_pred_train.argtypes = [_vp, _vp, i64, ctypes.POINTER(bern_train_opts), ctypes.c_char_p, ctypes.c_char_p,
+                                  ctypes.POINTER(_vp)]
     L.bern_mlp_backward_scratch.restype = sz
     L.bern_mlp_backward_scratch.argtypes = [i64]
     L.bern_mlp_forward.restype = i32
@@ -163,7 +176,8 @@ EXPORTED = ("bern_opts_default", "bern_net_create", "bern_net_destroy", "bern_ne
             "bern_prof_enable", "bern_prof_reset", "bern_prof_classes", "bern_prof_name", "bern_prof_read",
             "bern_pred_params", "bern_pred_create", "bern_pred_destroy", "bern_mlp_backward_scratch",
             "bern_mlp_forward", "bern_mlp_backward", "bern_mlp_adam", "bern_mlp_classify", "bern_tune_params",
-            "bern_tune_variants", "bern_tune_get", "bern_tune_set", "bern_autotune", "bern_bounds_noalloc")
+            "bern_tune_variants", "bern_tune_get", "bern_tune_set", "bern_autotune", "bern_bounds_noalloc",
+            "bern_pred_load", "bern_pred_train", "bern_train_opts_default")
 
 NOALLOC_SCRATCH_BYTES = 64 << 20  # BERN_NOALLOC_SCRATCH_BYTES
 
@@ -189,7 +203,7 @@ def _stream(stream):
 
 
 def make_opts(L=2, precision="fp64", plan="plain", sched="per_box", max_wave=0, pred=None, features=None,
-              graph=False, lin=0, mem_budget=0, counters=None):
+              graph=False, lin=0, mem_budget=0, counters=None, no_raise=False):
     o = bern_opts()
     lib().bern_opts_default(ctypes.byref(o))
     o.L = int(L)
@@ -201,6 +215,7 @@ def make_opts(L=2, precision="fp64", plan="plain", sched="per_box", max_wave=0, 
     o.features = None if features is None else features.data_ptr()
     o.graph = 1 if graph else 0
     o.lin = int(lin)
+    o.no_raise = 1 if no_raise else 0
     o.mem_budget_bytes = int(mem_budget)
     o.counters = None if counters is None else counters.data_ptr()
     return o
@@ -219,15 +234,26 @@ N_PARAMS = 5012
 
 
 class Predictor:
-    """Degree predictor on the current device (parameters copied at creation)."""
+    """Degree predictor on the current device (parameters copied at creation,
+    or read from a predictor file with ``Predictor.load``)."""
 
-    def __init__(self, params):
+    def __init__(self, params=None, handle=None):
+        if handle is not None:
+            self.handle = handle
+            self.params = None
+            return
         params = np.ascontiguousarray(params, dtype=np.float32)
         h = _vp()
         _check(lib().bern_pred_create(params.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), params.size,
                                       ctypes.byref(h)))
         self.handle = h
         self.params = params
+
+    @classmethod
+    def load(cls, path):
+        h = _vp()
+        _check(lib().bern_pred_load(os.fsencode(path), ctypes.byref(h)))
+        return cls(handle=h)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -239,6 +265,25 @@ class Predictor:
             self.close()
         except Exception:
             pass
+
+
+def pred_train(X, y, path=None, epochs=40, batch=8192, lr=3e-3, seed=0, meta=None, want_predictor=True):
+    """Train the degree predictor on host records (bern_pred_train): X
+    [N, 8] float32 features, y [N] int8 classes. Writes ``path`` (if given)
+    and returns (Predictor or None, per-epoch mean losses)."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.int8)
+    t = bern_train_opts()
+    lib().bern_train_opts_default(ctypes.byref(t))
+    t.epochs, t.batch, t.lr, t.seed = int(epochs), int(batch), float(lr), int(seed)
+    losses = np.zeros(int(epochs), dtype=np.float32)
+    t.loss_out = losses.ctypes.data
+    h = _vp()
+    _check(lib().bern_pred_train(ctypes.c_void_p(X.ctypes.data), ctypes.c_void_p(y.ctypes.data), X.shape[0],
+                                 ctypes.byref(t), None if path is None else os.fsencode(path),
+                                 None if meta is None else meta.encode(),
+                                 ctypes.byref(h) if want_predictor else None))
+    return (Predictor(handle=h) if want_predictor else None), losses
 
 
 def mlp_forward(P, X, bf16=False, stream=None):
@@ -313,7 +358,7 @@ class Net:
 
 
 def _prepare(net, box_lo, box_hi, L, precision, plan, sched, degree_plan, max_wave, workspace, outputs, pred,
-             features, graph, lin=0, mem_budget=0, counters=None):
+             features, graph, lin=0, mem_budget=0, counters=None, no_raise=False):
     import torch
     dev = box_lo.device
     assert box_lo.dtype == torch.float64 and box_hi.dtype == torch.float64
@@ -321,7 +366,7 @@ def _prepare(net, box_lo, box_hi, L, precision, plan, sched, degree_plan, max_wa
     box_hi = box_hi.contiguous()
     nb = box_lo.shape[0]
     o = make_opts(L=L, precision=precision, plan=plan, sched=sched, max_wave=max_wave, pred=pred, features=features,
-                  graph=graph, lin=lin, mem_budget=mem_budget, counters=counters)
+                  graph=graph, lin=lin, mem_budget=mem_budget, counters=counters, no_raise=no_raise)
     if outputs is None:
         nh = max(net.n_hidden, 1)
         outputs = dict(
@@ -349,14 +394,15 @@ def _prepare(net, box_lo, box_hi, L, precision, plan, sched, degree_plan, max_wa
 
 def bounds(net, box_lo, box_hi, L=2, precision="fp64", plan="plain", sched="per_box", degree_plan=None,
            max_wave=0, workspace=None, stream=None, outputs=None, pred=None, features=None, graph=False, lin=0,
-           mem_budget=0, counters=None):
+           mem_budget=0, counters=None, no_raise=False):
     """Bounds of every box. ``box_lo``/``box_hi``: float64 CUDA tensors
     [n_boxes, n]. Returns a dict of CUDA tensors (neuron_lo/hi, out_lo/hi,
     used_plan) plus the run statistics. Asynchronous on ``stream``. With
     ``graph`` the plain rule's launch sequence is captured once and replayed
     as one graph launch."""
     args, res, workspace, keep = _prepare(net, box_lo, box_hi, L, precision, plan, sched, degree_plan, max_wave,
-                                          workspace, outputs, pred, features, graph, lin, mem_budget, counters)
+                                          workspace, outputs, pred, features, graph, lin, mem_budget, counters,
+                                          no_raise)
     st = bern_stats()
     _check(lib().bern_bounds(*args, _stream(stream), ctypes.byref(st)))
     res["stats"] = _stats(st)

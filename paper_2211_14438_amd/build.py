@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbernnn.so")
 SOURCES = ["api.hip", "affine.hip", "convert.hip", "compose.hip", "mlp.hip", "simplex.hip", "volume.hip",
-           "noalloc.hip"]
+           "noalloc.hip", "predictor.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

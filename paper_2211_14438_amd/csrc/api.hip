@@ -202,8 +202,11 @@ static bern_status plan_net(const bern_net *net, const bern_opts *o, Plan &p) {
       return BERN_E_TOO_LARGE;
     }
     p.arenaA = std::max(p.arenaA, align256((size_t)h * 2 * p.Cpre[i] * p.elem));
-    const size_t cs = convert_scratch_bytes(p.n, D, h, 1);
-    p.conv = std::max(p.conv, cs);
+    p.conv = std::max(p.conv, convert_scratch_bytes(p.n, D, h, 1));
+    // per-neuron plans leave boxes at any degree up to the plain one, and a
+    // lower degree may take a read-off with more staging
+    if (p.mode != BERN_PLAN_PLAIN)
+      for (int d = 2; d < D; ++d) p.conv = std::max(p.conv, convert_scratch_bytes(p.n, d, h, 1));
     if (!p.fp64 && i > 0) p.gpart = std::max(p.gpart, align256((size_t)h * 2 * gemm_cblocks(p.Cpre[i]) * 8));
     if (i < p.H - 1) {
       const int Dn = p.Lmax * D;
@@ -226,6 +229,17 @@ static bern_status plan_net(const bern_net *net, const bern_opts *o, Plan &p) {
           return BERN_E_TOO_LARGE;
         }
         p.horner = std::max(p.horner, compose_scratch_bytes(Cq, p.Lmax, h, 1));
+      }
+      if (p.mode != BERN_PLAN_PLAIN && Dn >= 3) {
+        // a box at a lower degree may take orders up to Dn / Din (at most
+        // 3 for learned classes, 8 for given codes): Horner intermediates
+        // of degree up to Dn - 1
+        const int64_t Cq = ssize(p.n, Dn - 1, cap);
+        if (Cq < 0) {
+          set_error("layer %d: Horner intermediates of degree %d overflow", i + 1, Dn - 1);
+          return BERN_E_TOO_LARGE;
+        }
+        p.horner = std::max(p.horner, compose_scratch_bytes(Cq, 3, h, 1));
       }
       D = Dn;
       if (p.lin > 0 && (i + 1) % p.lin == 0) {
@@ -567,6 +581,17 @@ struct OutPolys {
   double *vol = nullptr;
 };
 
+// Largest ReLU order a neuron of a box class (Din, Dout) may hold: the plain
+// rule's L; under per-neuron plans an order-k neuron has degree k Din <=
+// Dout, so at most Dout / Din (and at most 3 for the predictor's classes,
+// kMaxOrder for given codes).
+static int class_order(const Plan &p, int Din, int Dout) {
+  if (p.mode == BERN_PLAN_PLAIN) return p.L;
+  if (Din < 1) return 1;
+  const int top = p.mode == BERN_PLAN_LEARNED ? 3 : kMaxOrder;
+  return std::max(1, std::min(top, Dout / Din));
+}
+
 // Compose arguments of hidden layer i for the boxes of class cl (bids).
 static bern_status compose_args(const bern_net *net, const Plan &p, int i, const BoxClass &cl, const int *bids,
                                 void *pre, void *post, int64_t slotA, int64_t slotB, NeuronRec *recs, double *rad,
@@ -582,15 +607,15 @@ static bern_status compose_args(const bern_net *net, const Plan &p, int i, const
   m.slot_in = slotA;
   m.slot_out = slotB;
   m.nbounds = 2;
-  m.Lmax = p.Lmax;
+  m.Lmax = class_order(p, cl.Din, cl.Dout);
   LayerTables lt;
-  bern_status st = layer_tables(net, cl.Din, p.Lmax, true, lt);
+  bern_status st = layer_tables(net, cl.Din, m.Lmax, true, lt);
   if (st != BERN_OK) return st;
   m.Cin = ssize(n, cl.Din);
   m.Cout = ssize(n, cl.Dout);
   m.Cs = ssize(n, std::min(cl.Din, cl.Dout));
-  for (int q = 0; q <= kMaxOrder; ++q) m.Sm[q] = q <= p.Lmax ? ssize(n, q * cl.Din) : 0;
-  m.Cq = p.Lmax >= 3 ? ssize(n, (p.Lmax - 1) * cl.Din) : 0;
+  for (int q = 0; q <= kMaxOrder; ++q) m.Sm[q] = q <= m.Lmax ? ssize(n, q * cl.Din) : 0;
+  m.Cq = m.Lmax >= 3 ? ssize(n, (m.Lmax - 1) * cl.Din) : 0;
   if (lt.sq) {
     m.sq_off = lt.sq->off;
     m.sq_pairs = lt.sq->pairs;
@@ -935,6 +960,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       la.cap = cap;
       la.fp64 = p.fp64 ? 1 : 0;
       la.L = p.L;
+      la.raise = o->no_raise ? 0 : 1;
       if (learned)
         BERN_HIP_TRY(launch_learned_rules(la, s));
       else
@@ -1047,47 +1073,10 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
     for (size_t k = 0; k < next.size(); ++k) {
       const BoxClass &cl = next[k];
       // composition -> post tensors in arena B
-      ComposeArgs m{};
-      m.n = n;
-      m.Din = cl.Din;
-      m.Dout = cl.Dout;
-      m.h = h;
-      m.bids = pid[k];
-      m.slot_in = slotA;
-      m.slot_out = slotB;
-      m.nbounds = 2;
-      m.Lmax = p.Lmax;
-      LayerTables lt;
-      st = layer_tables(net, cl.Din, p.Lmax, true, lt);
+      ComposeArgs m;
+      st = compose_args(net, p, i, cl, pid[k], Aa[i & 1], Bp, slotA, slotB, recs, radbuf[i & 1], cpart, horner,
+                        p.horner * B, live, live_ld, m);
       if (st != BERN_OK) return st;
-      m.Cin = ssize(n, cl.Din);
-      m.Cout = ssize(n, cl.Dout);
-      m.Cs = ssize(n, std::min(cl.Din, cl.Dout));
-      for (int q = 0; q <= kMaxOrder; ++q) m.Sm[q] = q <= p.Lmax ? ssize(n, q * cl.Din) : 0;
-      m.Cq = p.Lmax >= 3 ? ssize(n, (p.Lmax - 1) * cl.Din) : 0;
-      if (lt.sq) {
-        m.sq_off = lt.sq->off;
-        m.sq_pairs = lt.sq->pairs;
-        m.sq_diag = lt.sq->diag;
-      }
-      for (int q = 1; q < kMaxOrder; ++q)
-        if (lt.hz[q]) {
-          m.hz_off[q] = lt.hz[q]->off;
-          m.hz_pairs[q] = lt.hz[q]->pairs;
-        }
-      m.nboxes = (int64_t)cl.ids.size();
-      m.pre = Aa[i & 1];
-      m.post = Bp;
-      m.recs = recs;
-      m.rad = p.fp64 ? nullptr : radbuf[i & 1];
-      m.fp64 = p.fp64 ? 1 : 0;
-      m.scratch = horner;
-      m.scratch_bytes = p.horner * B;
-      m.nbx = compose_nbx(m.Cout);
-      m.pstride = p.nbx[i];  // the layer's partial layout, the same for every class
-      m.part = p.fp64 ? nullptr : cpart;
-      m.live = live;
-      m.live_ld = live_ld;
       m.lists_ready = lists_once ? 1 : 0;
       m.radii_later = lists_once ? 1 : 0;
       BERN_HIP_TRY(launch_compose(m, s));
@@ -1167,6 +1156,7 @@ static bern_status run_graph(bern_net *net, const bern_opts *o, int64_t n_boxes,
   key.push_back((uint64_t)o->max_wave);
   key.push_back((uint64_t)(uintptr_t)o->features);
   key.push_back((uint64_t)o->lin);
+  key.push_back((uint64_t)o->no_raise);
   key.push_back((uint64_t)(uintptr_t)o->counters);
   key.push_back((uint64_t)net->tune.gemm_wide | (uint64_t)net->tune.gemm_narrow << 8 |
                 (uint64_t)net->tune.conv_block << 16 | (uint64_t)net->tune.conv_wave << 24);

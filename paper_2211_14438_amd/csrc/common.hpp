@@ -358,6 +358,7 @@ struct LearnArgs {
   int8_t *used;                   // [B][nh] or null
   int *degs;                      // [B] or null: each box's largest post degree (the rules kernel)
   int cap, fp64, L;
+  int raise;                      // raise classes below the layer's top class (bern_opts.no_raise == 0)
 };
 // features -> (optional) BF16 MLP -> codes -> rules, for one class of boxes.
 hipError_t launch_learned_rules(const LearnArgs &a, hipStream_t s);

@@ -26,6 +26,8 @@
 #include "rules.hpp"
 #include "simplex.hpp"
 
+#include <algorithm>
+#include <cmath>
 #include <type_traits>
 
 namespace bern {
@@ -1181,10 +1183,81 @@ __global__ void __launch_bounds__(kBlock) convert_affine_kernel(ConvertArgs a) {
   if (l == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted, true);
 }
 
+// Executed-work counts of the read-off kernels, for the profiler (host).
+// Coefficients of total degree t in nv variables: C(t + nv - 1, nv - 1).
+static double count_at(int nv, int t) {
+  if (nv == 0) return t == 0 ? 1.0 : 0.0;
+  double c = 1.0;
+  for (int i = 1; i < nv; ++i) c = c * (t + i) / i;
+  return c;
+}
+
+// FP64 operations (an FMA counts 2, a min or max 1) of one tensor's tree
+// read-off: the `fix` leading variables folded once per block ((D+1)^fix
+// blocks, each with its own digits), the next q chain levels refolded as
+// their round digits change, then per round (D+1)^q of them) e - 1
+// expansions (one-variable basis change, (D+1)(D+2)/2 FMAs per output
+// polynomial coefficient) and (D+1)^e lanes, each folding its last variable
+// (every parent coefficient once) and converting its (D+1)^M tile in
+// registers, then a min and a max per Bernstein coefficient. The pass that
+// adds the remainders of fitted neurons is not counted.
+static double tree_ops(int n, int D, int M, int fix, int q, int e) {
+  const double D1 = D + 1, T = 0.5 * (D + 1) * (D + 2);
+  // level i: folding variable i of an (n - i)-variable polynomial, summed
+  // over the D + 1 digits; a child coefficient of total degree t takes
+  // min(D - t, k) + 1 parents at digit k
+  auto fold_all_digits = [&](int i) {
+    double s = 0.0;
+    for (int t = 0; t <= D; ++t) {
+      double per = 0.0;
+      for (int k = 0; k <= D; ++k) per += std::min(D - t, k) + 1;
+      s += count_at(n - i - 1, t) * per;
+    }
+    return s;
+  };
+  double mac = 0.0;
+  for (int i = 0; i < fix; ++i) mac += std::pow(D1, fix - 1) * fold_all_digits(i);
+  double block = 0.0;
+  for (int c = 0; c < q; ++c) block += std::pow(D1, c) * fold_all_digits(fix + c);
+  double round = 0.0, V = 1.0;
+  for (int st = 1; st < e; ++st) {
+    const int d = n - fix - q - st + 1;
+    round += V * (double)ssize(d - 1, D) * T;
+    V *= D1;
+  }
+  const double lane = (double)ssize(M + 1, D) + M * std::pow(D1, M - 1) * T;
+  round += std::pow(D1, e) * lane;
+  mac += std::pow(D1, fix) * (block + std::pow(D1, q) * round);
+  return 2.0 * mac + 2.0 * std::pow(D1, n);
+}
+
+// Bytes a hidden or output neuron's read-off must move: its two stored
+// tensors, in FP32 mode the GEMM's rounding partials of its row, and what it
+// writes (bounds and, for hidden neurons, the rule: kind, degree, interval,
+// approximant, shift, radii and norms); per box the previous layer's radii.
+static double readoff_neuron_bytes(const ConvertArgs &a) {
+  double b = 2.0 * a.S * (a.fp64 ? 8 : 4) + 16.0;
+  if (!a.fp64 && a.layer > 0) b += 2.0 * a.cblocks * 8;
+  if (a.mode == 0) b += (a.L + 10) * 8.0;
+  return b;
+}
+static double readoff_box_bytes(const ConvertArgs &a) { return (!a.fp64 && a.layer > 0) ? a.hin * 32.0 : 0.0; }
+
+// Closed-form degree-1 read-off, per neuron: six sums over the n + 1
+// coefficients of both tensors with their min / max / abs (about ten
+// operations per coefficient), and in FP32 mode after the first layer the
+// radii's sums over the previous layer's neurons and the GEMM partials.
+static double affine_ops(const ConvertArgs &a) {
+  double f = 10.0 * (a.n + 1);
+  if (!a.fp64 && a.layer > 0) f += 5.0 * a.hin + 2.0 * a.cblocks;
+  return f;
+}
+
 template <typename T>
 static hipError_t launch_affine(const ConvertArgs &a, hipStream_t s) {
-  ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4),
-               (double)a.nboxes * a.h * 2 * a.n * a.C * (a.D + 2));
+  ProfScope ps(a.mode == 2 ? kProfLin : kProfConvertSmall, s,
+               a.nboxes * a.h * readoff_neuron_bytes(a) + a.nboxes * readoff_box_bytes(a),
+               (double)a.nboxes * a.h * affine_ops(a));
   const int64_t teams = a.nboxes * a.h;
   if (a.S <= 8) {
     hipLaunchKernelGGL((convert_affine_kernel<T, 8>), dim3((unsigned)((teams * 8 + kBlock - 1) / kBlock)),
@@ -1806,13 +1879,16 @@ __global__ void __launch_bounds__(kWave ? 64 * kNTeams : 1024) convert_ntree_t(C
 static NTreePlan ntree_plan(int n, int D, int M, bool wave_team, int sides = 2);
 static size_t ntree_lds(const NTreePlan &tp, int n, int D, int teams, bool wave);
 
+
+
 template <typename T, int D, int M>
 static bool launch_ntree(const ConvertArgs &a, hipStream_t s, bool wave_team, hipError_t &err) {
   const NTreePlan tp = ntree_plan(a.n, D, M, wave_team);
   if (tp.e < 1) return false;
   const int64_t items = a.nboxes * a.h;
-  ProfScope ps(kProfConvertSmall, s, (double)items * 2 * a.S * (a.fp64 ? 8 : 4),
-               (double)items * 2 * a.n * a.C * (a.D + 2));
+  ProfScope ps(a.mode == 2 ? kProfLin : kProfConvertSmall, s,
+               items * readoff_neuron_bytes(a) + a.nboxes * readoff_box_bytes(a),
+               (double)items * 2 * tree_ops(a.n, D, M, 0, tp.q, tp.e));
   err = hipSuccess;
   if (tp.threads == 64) {  // a wave per neuron, kNTeams per block
     const size_t lds = ntree_lds(tp, a.n, D, kNTeams, true);
@@ -2276,8 +2352,9 @@ hipError_t launch_convert(const ConvertArgs &a_in, hipStream_t s) {
         reinterpret_cast<char *>(partial) +
         align256(((size_t)a.nboxes * a.h * 2 + kTreeBlocks * (a.D + 1)) * sizeof(double)));
     {
-      ProfScope ps(kProfConvertChunk, s, (double)tensors * a.S * (a.fp64 ? 8 : 4),
-                   (double)tensors * a.n * a.C * (a.D + 2));
+      ProfScope ps(kProfConvertChunk, s,
+                   (double)(a.nboxes * a.h) * readoff_neuron_bytes(a) + a.nboxes * readoff_box_bytes(a),
+                   (double)tensors * tree_ops(a.n, a.D, tree_tile_axes(a.D), tp.lo, tp.q, tp.e));
       RET_IF(a.fp64 ? launch_tree<double>(b, tp, lds, partial, l1part, s)
                     : launch_tree<float>(b, tp, lds, partial, l1part, s));
     }

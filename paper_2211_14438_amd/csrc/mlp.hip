@@ -278,11 +278,11 @@ __global__ void __launch_bounds__(4 * kClassItems) learned_classes_kernel(LearnA
 }
 
 // Per box and layer: the layer is stored at the largest degree any of its
-// neurons takes, so classes below that degree only cost tightness. Raise
-// them at no cost in tensor size: if some unstable neuron takes order >= 2,
-// the others take at least order 2; otherwise, if some takes order 1, the
-// fallback neurons take order 1. Then apply the rules: one wave per box, its
-// lanes over the neurons.
+// neurons takes, so classes below that degree cost tightness while saving
+// only composition and affine-map work. With a.raise they are raised: if
+// some unstable neuron takes order >= 2, the others take at least order 2;
+// otherwise, if some takes order 1, the fallback neurons take order 1. Then
+// apply the rules: one wave per box, its lanes over the neurons.
 __global__ void __launch_bounds__(256) learned_rules_kernel(LearnArgs a) {
   const int lane = threadIdx.x & 63;
   const int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -296,7 +296,7 @@ __global__ void __launch_bounds__(256) learned_rules_kernel(LearnArgs a) {
   for (int j = lane; j < a.h; j += 64) {
     NeuronRec &r = a.recs[box * a.h + j];
     int c = cl[j];
-    if (c >= 0) {
+    if (c >= 0 && a.raise) {
       if (top >= 2 && c < 2) c = 2;
       else if (top == 1 && c == 0) c = 1;
       cl[j] = (int8_t)c;

@@ -3,24 +3,34 @@
 The predictor (an MLP 8 -> 64 -> 64 -> 4, see include/bernnn.h) chooses, per
 unstable neuron, the order of its Bernstein ReLU approximant (1, 2, 3) or the
 linear fallback (class 0). Every choice yields sound bounds; the choice only
-trades output-bound width for tensor size.
+trades output-bound width for work.
 
 Training data come from the method's own GPU runs on training networks (the
 architecture of the learned workload, other seeds, boxes of the same law).
-A box's tensors are stored at the largest degree of each layer's neurons, so
-the decisions that pay are per box and layer. The teacher measures them: it
-runs every combination of one class per hidden layer (order 2, order 1,
-linear fallback for all unstable neurons of that layer) as a given plan, and
-picks for each box the cheapest combination (by measured run time) whose
-output-bound width for that box stays within (1 + budget) times the plain
-width. Every unstable neuron is labelled with its layer's class in the chosen
-combination; its features are recorded from a run under the chosen plans, so
-that they match what the predictor sees when it drives the plan itself. The
-MLP is trained to reproduce these labels with the library's own FP32 HIP
-forward/backward/Adam kernels; inference inside the bounds pipeline is BF16.
-A simpler per-neuron teacher (band height of each class, Prop. 2, times the
-neuron's downstream sensitivity, against tensor growth) is kept as a
-reference.
+A box's tensors are stored at the largest degree of each layer's neurons,
+while the composition and the next affine map work per neuron (composed
+neurons carry full tensors, order-1, fallback and active ones only their own
+prefix). The teacher therefore decides in two measured levels:
+  1. per box and hidden layer, the layer's top class, over every
+     combination of one class per layer from {order 3, order 2, order 1,
+     fallback} (orders are lowered on the device where the plain degree cap
+     does not allow them);
+  2. within each such layer, a fraction of its unstable neurons -- those
+     with the least downstream effect (sensitivity times interval width
+     times the ReLU band gap of Prop. 2 between the top class and the one
+     below) -- drop one class below the top; the fraction comes from measured
+     plans as well.
+Each box then takes, from every measured plan of both levels, the cheapest
+(run time shared over the boxes) subject to the mean output width staying
+within the budget, by a Lagrange multiplier on the width. Every unstable
+neuron is labelled with its own class in the chosen plan; its features are
+recorded from a run under that plan, so that they match what the predictor
+sees when it drives the plan itself. The MLP is trained on these labels by bern_pred_train (the library's
+FP32 HIP forward/backward/Adam kernels); inference inside the bounds
+pipeline is BF16. The library then raises, per box and layer, the classes
+below the layer's top class (bern_opts.no_raise = 0); measured on the
+held-out network this is tighter than keeping every predicted class, at
+about the same run time (the evaluation reports both).
 """
 import json
 import math
@@ -33,7 +43,7 @@ from . import bernnn as B
 from . import workloads as wl
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-DEFAULT_PARAMS = os.path.join(HERE, "predictor_params.npz")
+DEFAULT_PARAMS = os.path.join(HERE, "predictor_params.bin")
 
 
 # --------------------------------------------------------------- teacher
@@ -127,53 +137,20 @@ def post_cap(case):
 
 # --------------------------------------------------------------- training
 
-def train(X, y, mean, std, epochs=30, batch=8192, lr=3e-3, seed=0, log=print):
-    """Train the MLP on the GPU with the library's kernels. X [N, 8] float32,
-    y [N] int8 classes. Returns the parameter vector (numpy float32)."""
-    import torch
-    rng = np.random.default_rng(seed)
-    P = np.zeros(B.N_PARAMS, dtype=np.float32)
-    F, H, C = 8, 64, 4
-    o = 0
-    P[o:o + F] = mean; o += F
-    P[o:o + F] = std; o += F
-    P[o:o + H * F] = rng.standard_normal(H * F) * np.sqrt(2.0 / F); o += H * F + H
-    P[o:o + H * H] = rng.standard_normal(H * H) * np.sqrt(2.0 / H); o += H * H + H
-    P[o:o + C * H] = rng.standard_normal(C * H) * np.sqrt(1.0 / H)
-    dev = "cuda"
-    Pd = torch.tensor(P, device=dev)
-    m = torch.zeros_like(Pd)
-    v = torch.zeros_like(Pd)
-    Xd = torch.tensor(X, dtype=torch.float32, device=dev)
-    yd = torch.tensor(y, dtype=torch.int8, device=dev)
-    N = X.shape[0]
-    scratch = torch.empty(B.lib().bern_mlp_backward_scratch(batch), dtype=torch.uint8, device=dev)
-    step = 0
-    for ep in range(epochs):
-        perm = torch.tensor(rng.permutation(N), device=dev)
-        tot = 0.0
-        nb = 0
-        for s0 in range(0, N - batch + 1, batch):
-            idx = perm[s0:s0 + batch]
-            G, loss = B.mlp_backward(Pd, Xd[idx], yd[idx], scratch=scratch)
-            step += 1
-            B.mlp_adam(Pd, G, m, v, step, lr * (0.5 * (1 + math.cos(math.pi * ep / epochs))))
-            tot += float(loss.item())
-            nb += 1
-        if log and (ep % 5 == 0 or ep == epochs - 1):
-            cls, _ = B.mlp_classify(Pd, Xd, bf16=True)
-            acc = float((cls == yd).float().mean().item())
-            log(f"epoch {ep}: loss {tot / max(nb, 1):.4f}  bf16 accuracy {acc:.4f}")
-    return Pd.cpu().numpy()
+def train(X, y, path=DEFAULT_PARAMS, epochs=40, batch=8192, lr=3e-3, seed=0, meta=None, log=print):
+    """Train the MLP on the GPU (bern_pred_train) and write the predictor
+    file. Returns (Predictor, per-epoch mean losses)."""
+    pred, losses = B.pred_train(X, y, path=path, epochs=epochs, batch=batch, lr=lr, seed=seed,
+                                meta=None if meta is None else json.dumps(meta))
+    if log:
+        log("epoch losses: " + " ".join(f"{v:.4f}" for v in losses[:: max(1, len(losses) // 8)]) +
+            f" ... {losses[-1]:.4f}")
+    return pred, losses
 
 
-def save(path, P, meta):
-    np.savez(path, params=np.asarray(P, np.float32), meta=json.dumps(meta))
-
-
-def load(path=DEFAULT_PARAMS):
-    with np.load(path, allow_pickle=False) as z:
-        return z["params"].astype(np.float32), json.loads(str(z["meta"]))
+def load_predictor(path=DEFAULT_PARAMS):
+    """The trained predictor on the current device (bern_pred_load)."""
+    return B.Predictor.load(path)
 
 
 # --------------------------------------------------------------- pipeline
@@ -209,7 +186,7 @@ def run_given(case, codes, precision="fp32"):
     return w, dt
 
 
-def layer_combos(n_layers, classes=(2, 1, 0)):
+def layer_combos(n_layers, classes=(3, 2, 1, 0)):
     import itertools
     return list(itertools.product(classes, repeat=n_layers))
 
@@ -249,21 +226,11 @@ def run_plan(case, codes, precision="fp32", features=False, reps=1):
     return out
 
 
-def measured_teacher(case, budget, log=print):
-    """Per box, one combination of per-layer classes, chosen from measured
-    runs: minimise total run time subject to the mean output width staying
-    within (1 + budget) of the plain rule's. Solved by a Lagrange multiplier
-    on the width: box b takes argmin_k t_k / B + lam * (w_bk - w_b0) / mean(w_0),
-    with lam bisected to meet the budget. Returns (choice per box, combos,
-    per-combo results)."""
-    nl = len(case.widths) - 2
-    combos = layer_combos(nl)
-    res = [run_plan(case, combo_codes(case, cb)) for cb in combos]
-    k0 = combos.index((2,) * nl)
-    base = res[k0]
-    nb = case.n_boxes
-    t = np.array([r["time"] for r in res]) / nb                      # [K] time share per box
-    dw = np.stack([r["width"] - base["width"] for r in res], 1) / base["width"].mean()  # [B, K]
+def _lagrange_pick(t, dw, budget):
+    """Per box, argmin_k t[k] + lam * dw[b, k] with the smallest lam whose
+    mean width increase stays within `budget` (t [K] time shares, dw [B, K]
+    width increases relative to the plain mean width)."""
+    nb = dw.shape[0]
 
     def pick(lam):
         return np.argmin(t[None, :] + lam * dw, axis=1)
@@ -277,40 +244,116 @@ def measured_teacher(case, budget, log=print):
             lo_l = mid
         else:
             hi_l = mid
-    choice = pick(hi_l)
+    return pick(hi_l)
+
+
+def measured_teacher(case, budget, log=print):
+    """Level 1: per box, one top class per hidden layer, chosen from measured
+    runs of every combination (a plan with that class for all of a layer's
+    neurons): minimise run time subject to the mean output width staying
+    within (1 + budget) of the plain rule's. Returns (choice per box,
+    combos, per-combo results, the plain run)."""
+    nl = len(case.widths) - 2
+    combos = layer_combos(nl)
+    res = [run_plan(case, combo_codes(case, cb)) for cb in combos]
+    base = run_plan(case, np.full((case.n_boxes, case.n_hidden), case.L, np.int8))
+    nb = case.n_boxes
+    t = np.array([r["time"] for r in res]) / nb
+    dw = np.stack([r["width"] - base["width"] for r in res], 1) / base["width"].mean()
+    choice = _lagrange_pick(t, dw, budget)
     for k, cb in enumerate(combos):
-        log(f"  combo {cb}: time {res[k]['time'] * 1e3:.1f} ms  width x{res[k]['width'].mean() / base['width'].mean():.4f}"
-            f"  chosen by {(choice == k).sum()} boxes")
-    return choice, combos, res
+        if (choice == k).sum():
+            log(f"  combo {cb}: time {res[k]['time'] * 1e3:.1f} ms  width x{res[k]['width'].mean() / base['width'].mean():.4f}"
+                f"  chosen by {(choice == k).sum()} boxes")
+    return choice, combos, res, base
 
 
-def evaluate(P, case=None, precision="fp32", log=print):
-    """Learned plan against the plain rule (both batched) on the held-out
-    evaluation network: output-width ratio and speedup."""
+def demote(case, codes, feat, used, q):
+    """Level 2 candidate: in every box and hidden layer whose top class is k
+    >= 1, the fraction q of its unstable neurons with the smallest downstream
+    effect drop to class k - 1 (order 1 drops to the fallback). Effect =
+    downstream sensitivity x interval width x the band gap (Prop. 2 heights)
+    between the lower class and k."""
+    out = codes.copy()
+    u0 = np.clip(feat[..., 0], 0.0, 1.0)
+    sw = np.exp(feat[..., 5])
+    spread = np.maximum(feat[..., 6], 0.0)
+    band = {c: _relu_band(u0, c) for c in (1, 2, 3)}
+    band[0] = band[1] + (1.0 - u0) * spread
+    col = 0
+    for h in case.widths[1:-1]:
+        blk = out[:, col:col + h]
+        uns = (used[:, col:col + h] >= 1) | (used[:, col:col + h] == -2)
+        top = blk[:, 0].astype(int)  # level-1 plans hold one class per layer
+        for b in np.nonzero((top >= 1) & uns.any(axis=1))[0]:
+            k = int(top[b])
+            idx = np.nonzero(uns[b])[0]
+            m = int(np.floor(q * idx.size))
+            if m == 0:
+                continue
+            gap = band[k - 1][b, col + idx] - band[k][b, col + idx]
+            eff = sw[b, col + idx] * gap
+            drop = idx[np.argsort(eff, kind="stable")[:m]]
+            blk[b, drop] = k - 1
+        col += h
+    return out
+
+
+def refine(case, variants, fractions, res1, base, budget, log=print):
+    """Level 2: the demotion variants of each box's level-1 plan, measured,
+    and one final pick per box over every measured plan -- the level-1
+    combinations (res1) and these variants -- within the full width budget.
+    Returns the per-box index into combinations + variants."""
+    res2 = [run_plan(case, v) for v in variants]
+    res = list(res1) + res2
+    t = np.array([r["time"] for r in res]) / case.n_boxes
+    dw = np.stack([r["width"] - base["width"] for r in res], 1) / base["width"].mean()
+    choice = _lagrange_pick(t, dw, budget)
+    k1 = len(res1)
+    for k, q in enumerate(fractions):
+        log(f"  demote {q:.2f}: time {res2[k]['time'] * 1e3:.1f} ms  width x{res2[k]['width'].mean() / base['width'].mean():.4f}"
+            f"  chosen by {(choice == k1 + k).sum()} boxes")
+    return choice
+
+
+def evaluate(pred, case=None, precision="fp32", log=print):
+    """The learned plan (with the per-layer raise, and without it) against
+    the batched plain rule, a fixed order 1 and the linear fallback for every
+    unstable neuron, all batched, on the held-out evaluation network."""
     import torch
     case = case or wl.cfg5()
-    pred = B.Predictor(P)
     net = B.Net(case.Ws, case.bs)
     lo = torch.tensor(case.box_lo, dtype=torch.float64, device="cuda")
     hi = torch.tensor(case.box_hi, dtype=torch.float64, device="cuda")
+    shape = (case.n_boxes, case.n_hidden)
+    forms = (("plain", dict(plan="plain")),
+             ("learned", dict(plan="learned", pred=pred)),
+             ("learned_no_raise", dict(plan="learned", pred=pred, no_raise=True)),
+             ("fixed1", dict(plan="given", degree_plan=torch.full(shape, 1, dtype=torch.int8, device="cuda"))),
+             ("fallback", dict(plan="given", degree_plan=torch.full(shape, 0, dtype=torch.int8, device="cuda"))))
     out = {}
-    for name, kw in (("plain", dict(plan="plain")), ("learned", dict(plan="learned", pred=pred))):
-        ws = _workspace(net, case.n_boxes, L=case.L, precision=precision, **kw)
-        for _ in range(2):
+    for name, kw in forms:
+        ws = _workspace(net, case.n_boxes, L=case.L, precision=precision,
+                        **{k: v for k, v in kw.items() if k not in ("degree_plan", "no_raise")})
+        for _ in range(3):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             r = B.bounds(net, lo, hi, L=case.L, precision=precision, sched="batched", workspace=ws, **kw)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
+        used = r["used_plan"].cpu().numpy().ravel()
         out[name] = dict(time=dt, width=float((r["out_hi"] - r["out_lo"]).mean().item()),
-                         used=np.bincount(r["used_plan"].cpu().numpy().ravel() + 2, minlength=12).tolist())
+                         rules={k: int((used == v).sum()) for k, v in (("inactive", 0), ("active", -1),
+                                                                        ("fallback", -2), ("order1", 1),
+                                                                        ("order2", 2), ("order3", 3))})
         del ws
-    res = dict(width_ratio=out["learned"]["width"] / out["plain"]["width"],
-               speedup=out["plain"]["time"] / out["learned"]["time"], detail=out)
-    log(f"eval net: learned width x{res['width_ratio']:.4f}, speedup x{res['speedup']:.2f} (batched plain "
-        f"{out['plain']['time'] * 1e3:.1f} ms, learned {out['learned']['time'] * 1e3:.1f} ms)")
+    res = dict(detail=out)
+    for name in ("learned", "learned_no_raise", "fixed1", "fallback"):
+        res[name] = dict(width_ratio=out[name]["width"] / out["plain"]["width"],
+                         speedup=out["plain"]["time"] / out[name]["time"])
+        log(f"eval net: {name} width x{res[name]['width_ratio']:.4f}, speedup over batched plain "
+            f"x{res[name]['speedup']:.2f}")
     net.close()
-    pred.close()
     return res
 
 
@@ -319,7 +362,7 @@ def main(argv=None):
     import torch
     ap = argparse.ArgumentParser(description="collect records, label them by measured plans, train the predictor")
     ap.add_argument("--out", default=DEFAULT_PARAMS)
-    ap.add_argument("--nets", type=int, default=2)
+    ap.add_argument("--nets", type=int, default=8)
     ap.add_argument("--boxes", type=int, default=1024)
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--budget", type=float, default=0.08, help="mean output-width increase the teacher may spend")
@@ -330,15 +373,21 @@ def main(argv=None):
     Xs, ys = [], []
     for ci, c in enumerate(training_cases(args.nets, args.boxes)):
         t0 = time.perf_counter()
-        choice, combos, res = measured_teacher(c, args.budget, log=log)
-        nl = len(c.widths) - 2
-        codes = np.stack([combo_codes(c, combos[k])[b] for b, k in enumerate(choice)])
+        choice, combos, res, base = measured_teacher(c, args.budget, log=log)
+        combo_plans = [combo_codes(c, cb) for cb in combos]
+        codes1 = np.stack([combo_plans[k][b] for b, k in enumerate(choice)])
+        run1 = run_plan(c, codes1, features=True)
+        fracs = (0.25, 0.5, 0.75)
+        variants = [demote(c, codes1, run1["features"], run1["used"], q) for q in fracs]
+        pick = refine(c, variants, fracs, res, base, args.budget, log=log)
+        plans = combo_plans + variants
+        codes = np.stack([plans[k][b] for b, k in enumerate(pick)])
         run = run_plan(c, codes, features=True)
-        base = res[combos.index((2,) * nl)]
         used, feat = run["used"], run["features"]
         mask = (used >= 1) | (used == -2)  # unstable neurons (any order or the fallback)
         X = feat[mask]
-        y = codes[mask]
+        # label: the class the library applied (orders lowered under the degree cap)
+        y = np.where(used[mask] == -2, 0, used[mask]).astype(np.int8)
         Xs.append(X)
         ys.append(y)
         entry = dict(net=ci, records=int(X.shape[0]), width_ratio=float(run["width"].mean() / base["width"].mean()),
@@ -350,17 +399,35 @@ def main(argv=None):
     X = np.concatenate(Xs).astype(np.float32)
     y = np.concatenate(ys).astype(np.int8)
     report["records"] = int(X.shape[0])
-    mean = X.mean(0)
-    std = X.std(0) + 1e-3
-    P = train(X, y, mean, std, epochs=args.epochs, log=log)
-    cls, _ = B.mlp_classify(torch.tensor(P, device="cuda"), torch.tensor(X, device="cuda"), bf16=True)
-    report["train_accuracy_bf16"] = float((cls.cpu().numpy() == y).mean())
-    save(args.out, P, dict(records=int(X.shape[0]), accuracy=report["train_accuracy_bf16"], budget=args.budget))
-    log(f"saved {args.out}")
-    report["eval"] = evaluate(P, log=log)
+    report["label_counts"] = np.bincount(y, minlength=4).tolist()
+    pred, losses = train(X, y, path=args.out, epochs=args.epochs,
+                         meta=dict(records=int(X.shape[0]), budget=args.budget, classes=report["label_counts"]),
+                         log=log)
+    report["losses"] = [float(v) for v in losses]
+    # accuracy per class of the BF16 inference arithmetic, on the training records
+    P = torch.tensor(read_params(args.out), device="cuda")
+    cls, _ = B.mlp_classify(P, torch.tensor(X, device="cuda"), bf16=True)
+    cls = cls.cpu().numpy()
+    report["train_accuracy_bf16"] = float((cls == y).mean())
+    report["per_class_accuracy_bf16"] = [float((cls[y == c] == c).mean()) if (y == c).any() else None
+                                         for c in range(4)]
+    log(f"saved {args.out}: accuracy {report['train_accuracy_bf16']:.4f}, per class "
+        f"{report['per_class_accuracy_bf16']}")
+    report["eval"] = evaluate(pred, log=log)
+    pred.close()
     if args.report:
         with open(args.report, "w") as fh:
             json.dump(report, fh, indent=1)
+
+
+def read_params(path=DEFAULT_PARAMS):
+    """The parameter vector of a predictor file (format of bern_pred_load),
+    for tests and reports."""
+    with open(path, "rb") as fh:
+        head = fh.read(16)
+        assert head[:8] == b"BERNPRED"
+        n = int(np.frombuffer(head[12:16], dtype="<u4")[0])
+        return np.frombuffer(fh.read(4 * n), dtype="<f4").astype(np.float32)
 
 
 if __name__ == "__main__":

@@ -52,3 +52,11 @@ def box_points(lo, hi, m, rng, grid=None):
         pts.append(np.stack(np.meshgrid(*[g] * n, indexing="ij"), -1).reshape(-1, n))
     t = np.concatenate(pts)
     return t, lo + t * (hi - lo)
+
+
+def poisoned_workspace(torch, net, n_boxes, **opts):
+    """A device workspace for bern_bounds filled with 0xFF bytes (NaN in FP32
+    and FP64): a kernel that reads scratch it did not write first turns the
+    bounds into NaN instead of silently reusing a previous run's values."""
+    total, _ = net.workspace_size(n_boxes, **opts)
+    return torch.full((total + 256,), 255, dtype=torch.uint8, device="cuda:0")

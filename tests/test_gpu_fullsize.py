@@ -30,7 +30,9 @@ def _run(case, **kw):
     net = B.Net(case.Ws, case.bs)
     lo = torch.tensor(case.box_lo, dtype=torch.float64, device=DEV)
     hi = torch.tensor(case.box_hi, dtype=torch.float64, device=DEV)
-    r = B.bounds(net, lo, hi, L=case.L, precision="fp32", sched="batched", **kw)
+    ws = H.poisoned_workspace(torch, net, case.n_boxes, L=case.L, precision="fp32", sched="batched",
+                              **{k: v for k, v in kw.items() if k in ("plan", "pred")})
+    r = B.bounds(net, lo, hi, L=case.L, precision="fp32", sched="batched", workspace=ws, **kw)
     torch.cuda.synchronize()
     out = {k: r[k].cpu().numpy() for k in KEYS}
     net.close()
@@ -70,7 +72,7 @@ def _sample(case, k=16, seed=0):
 def test_learned_workload_full_size():
     case = wl.cfg5()  # 1024 boxes, [6,64,64,64,4], L = 2
     print(f"case {case.name}", flush=True)
-    pred = B.Predictor(PR.load()[0])
+    pred = PR.load_predictor()
     g = _run(case, plan="learned", pred=pred)
     pred.close()
     _check_sound_all(case, g, m=200)

@@ -29,7 +29,8 @@ def _gpu(case, **kw):
     hi = torch.tensor(case.box_hi, dtype=torch.float64, device=DEV)
     if "degree_plan" in kw and kw["degree_plan"] is not None:
         kw["degree_plan"] = torch.tensor(kw["degree_plan"], dtype=torch.int8, device=DEV)
-    r = B.bounds(net, lo, hi, **kw)
+    ws = H.poisoned_workspace(torch, net, case.n_boxes, **{k: v for k, v in kw.items() if k != "degree_plan"})
+    r = B.bounds(net, lo, hi, workspace=ws, **kw)
     torch.cuda.synchronize()
     out = {k: r[k].cpu().numpy() for k in KEYS}
     out["stats"] = r["stats"]

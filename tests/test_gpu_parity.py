@@ -35,8 +35,11 @@ def _bounds_gpu(case, L=2, precision="fp64", sched="per_box", plan=None, max_wav
     lo = torch.tensor(case.box_lo, dtype=torch.float64, device=DEV)
     hi = torch.tensor(case.box_hi, dtype=torch.float64, device=DEV)
     pl = None if plan is None else torch.tensor(plan, dtype=torch.int8, device=DEV)
-    r = B.bounds(net, lo, hi, L=L, precision=precision, sched=sched, max_wave=max_wave,
-                 plan="plain" if plan is None else "given", degree_plan=pl)
+    kind = "plain" if plan is None else "given"
+    ws = H.poisoned_workspace(torch, net, case.n_boxes, L=L, precision=precision, sched=sched, max_wave=max_wave,
+                              plan=kind)
+    r = B.bounds(net, lo, hi, L=L, precision=precision, sched=sched, max_wave=max_wave, plan=kind, degree_plan=pl,
+                 workspace=ws)
     torch.cuda.synchronize()
     out = {k: r[k].cpu().numpy() for k in ("neuron_lo", "neuron_hi", "out_lo", "out_hi", "used_plan")}
     out["stats"] = r["stats"]
@@ -450,6 +453,29 @@ def test_given_plans_match_oracle(precision, seed):
     g = _bounds_gpu(case, L=3, precision=precision, sched="batched", plan=plan)
     o = _oracle(case, plan=plan)
     assert np.array_equal(g["used_plan"], o["used_plan"])
+    if precision == "fp64":
+        _assert_parity(g, o, 1e-9, case.n_hidden)
+    else:
+        _assert_fp32(g, o, case.n_hidden)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_given_orders_above_L(precision):
+    """Codes above L where the layer's cap allows them: at L = 2 a box whose
+    first hidden layer stays at degree 1 may take orders 3 and 4 in the second
+    (cap L^2 = 4) and 2 or 3 after a degree-3 layer in the third (cap 8), so
+    Horner compositions of orders the plain rule never uses; on a workspace
+    filled with NaN bytes, against the oracle."""
+    case = wl.random_net_case([3, 6, 5, 4, 2], seed=404, n_boxes=6)
+    plan = np.ones((case.n_boxes, case.n_hidden), dtype=np.int8)
+    plan[:, 6:11] = np.array([3, 4, 3, 4, 3], dtype=np.int8)
+    plan[:, 11:] = 2
+    plan[1::2, 11:] = 3
+    g = _bounds_gpu(case, L=2, precision=precision, sched="batched", plan=plan)
+    used = g["used_plan"][:, :case.n_hidden]
+    assert (used >= 3).any(), "no order above L was taken"
+    o = _oracle(case, L=2, plan=np.where(used >= 1, used, np.where(used == -2, 0, 1)).astype(np.int8))
+    assert np.array_equal(used, o["used_plan"])
     if precision == "fp64":
         _assert_parity(g, o, 1e-9, case.n_hidden)
     else:

@@ -1,10 +1,10 @@
 """What the trained degree predictor gains, on the held-out network of the
 predictor workload ([6,64,64,64,4], half-width 0.05, L = 2), on 256 of its
-boxes: batched runs under the learned plan, under a fixed order 1 for every
-unstable neuron and under a fixed order 2 (the stable-neuron rule of the
-plain method). The learned plan must sit on the good side of both: within
-10 % of the fixed-order-2 mean output width at a fraction of its time, and
-tighter than fixed order 1."""
+boxes: batched runs under the learned plan, under a fixed order 1 and under the linear fallback for
+every unstable neuron, and under a fixed order 2 (the stable-neuron rule of
+the plain method). The learned plan must sit on the good side of all three:
+within 10 % of the fixed-order-2 mean output width at a fraction of its time,
+and tighter than fixed order 1 and the fallback everywhere."""
 import time
 
 import numpy as np
@@ -44,17 +44,17 @@ def test_learned_plan_beats_fixed_orders():
     net = B.Net(case.Ws, case.bs)
     lo = torch.tensor(case.box_lo, dtype=torch.float64, device=DEV)
     hi = torch.tensor(case.box_hi, dtype=torch.float64, device=DEV)
-    pred = B.Predictor(PR.load()[0])
+    pred = PR.load_predictor()
     shape = (case.n_boxes, sum(case.widths[1:-1]))
     res = {}
     res["learned"] = _run(net, lo, hi, 5, plan="learned", pred=pred)
-    for k in (1, 2):
+    for k in (0, 1, 2):
         plan = torch.full(shape, k, dtype=torch.int8, device=DEV)
         res[f"fixed{k}"] = _run(net, lo, hi, 2 if k == 2 else 5, plan="given", degree_plan=plan)
     print({k: (round(v[0], 2), round(v[1], 5)) for k, v in res.items()}, flush=True)
-    (t_l, w_l), (t_1, w_1), (t_2, w_2) = res["learned"], res["fixed1"], res["fixed2"]
+    (t_l, w_l), (t_0, w_0), (t_1, w_1), (t_2, w_2) = res["learned"], res["fixed0"], res["fixed1"], res["fixed2"]
     assert w_l <= 1.10 * w_2
-    assert t_l < 0.5 * t_2
-    assert w_l < w_1
+    assert t_l < 0.2 * t_2
+    assert w_l < w_1 and w_l < w_0
     pred.close()
     net.close()
