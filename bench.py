@@ -138,6 +138,94 @@ def executed_work(case, used, L, plain, elem):
     return {"compose_square": (sq_f, sq_b), "compose_horner": (hz_f, 0.0), "gemm": (gm_f, gm_b)}
 
 
+def verify_demo(torch):
+    """Branch and bound (bern_verify) of the property "output <= its sampled
+    median" on a network of Fig. 4's shape ([2,20,20,1], weights and biases
+    U[-5,5]) over [-1,1]^2, FP32 padded, L = 2: the input-volume fractions
+    verified, violated and left undecided after 12 rounds, and the fraction
+    decided per second of the call (host time, bounds of every round
+    included)."""
+    from paper_2211_14438_amd import bernnn as B
+    from paper_2211_14438_amd import workloads as wl
+    Ws, bs = wl.make_net([2, 20, 20, 1], 1000, law="uniform5")
+    net = B.Net(Ws, bs)
+    g = np.linspace(-1.0, 1.0, 201)
+    x = np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2)
+    z = x
+    for i, (W, b) in enumerate(zip(Ws, bs)):
+        z = z @ W.T + b
+        if i < len(Ws) - 1:
+            z = np.maximum(z, 0.0)
+    tau = float(np.median(z[:, 0]))
+    lo, hi = np.array([[-1.0, -1.0]]), np.array([[1.0, 1.0]])
+    B.verify(net, lo, hi, 0, tau, max_rounds=2, precision="fp32")  # warm-up: tables, first allocations
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = B.verify(net, lo, hi, 0, tau, max_rounds=12, max_boxes=1 << 16, precision="fp32")
+    dt = time.perf_counter() - t0
+    net.close()
+    decided = r["verified"] + r["violated"]
+    return dict(net="2-20-20-1 U[-5,5]", property="output <= sampled median", rounds=r["rounds"],
+                verified=r["verified"], violated=r["violated"], undecided=r["undecided"],
+                boxes_bounded=r["boxes_bounded"], seconds=dt, decided_fraction_per_s=decided / dt,
+                verified_fraction_per_s=r["verified"] / dt)
+
+
+# The paper's Section 6.1 medians (50 random networks, weights and biases
+# U[-5,5], box [-1,1]^n, L = 2 unless stated; one NVIDIA RTX 2080 Ti and
+# PyTorch): seconds per network, and relative volumes where printed.
+PAPER_SWEEPS = {
+    "fig4_L": {"shape": [2, 20, 20, 1], "values": {2: (1.29, 1823.96), 3: (1.70, 1524.99), 4: (2.44, 1348.26),
+                                                   5: (3.47, 1248.37), 6: (5.11, 1173.46)}},
+    "fig5_n": {"values": {2: 1.17, 3: 1.34, 4: 1.54, 5: 1.759, 6: 2.79, 7: 3.36, 8: 6.56}},
+    "fig6_Ne": {"values": {10: 0.45, 20: 1.22, 40: 3.87, 60: 8.48, 80: 14.64, 100: 18.25}},
+    "fig7_depth": {"values": {1: 0.28, 2: 1.27, 3: 2.291, 4: 3.23, 5: 4.25}},
+}
+
+
+def sweeps(torch, nets=50):
+    """The shapes of Figs. 4-7 on this GPU: per shape, `nets` seeded random
+    networks (U[-5,5] weights and biases), one box [-1,1]^n, the plain rule
+    in FP64 one box per launch sequence (the paper's setting): median time of
+    one bound computation (HIP-synchronised wall time after a warm-up run)
+    and median relative volume, printed one JSON line per figure beside the
+    paper's medians."""
+    from paper_2211_14438_amd import bernnn as B
+    from paper_2211_14438_amd import workloads as wl
+    figs = {
+        "fig4_L": [([2, 20, 20, 1], L) for L in (2, 3, 4, 5, 6)],
+        "fig5_n": [([n, 20, 20, 1], 2) for n in range(2, 9)],
+        "fig6_Ne": [([2, Ne, Ne, 1], 2) for Ne in (10, 20, 40, 60, 80, 100)],
+        "fig7_depth": [([2] + [20] * d + [1], 2) for d in range(1, 6)],
+    }
+    for fig, cases in figs.items():
+        rows = []
+        for widths, L in cases:
+            n = widths[0]
+            lo = torch.full((1, n), -1.0, dtype=torch.float64, device="cuda:0")
+            hi = torch.full((1, n), 1.0, dtype=torch.float64, device="cuda:0")
+            ts, vs = [], []
+            for s in range(nets):
+                Ws, bs = wl.make_net(widths, 1000 + s, law="uniform5")
+                net = B.Net(Ws, bs)
+                B.rel_volume(net, lo, hi, L=L, precision="fp64", sched="per_box")  # tables, buffers
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = B.rel_volume(net, lo, hi, L=L, precision="fp64", sched="per_box")
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+                vs.append(float(r["rel_vol"][0, 0]))
+                net.close()
+            key = {"fig4_L": L, "fig5_n": n, "fig6_Ne": widths[1], "fig7_depth": len(widths) - 2}[fig]
+            paper = PAPER_SWEEPS[fig]["values"].get(key)
+            rows.append(dict(shape=widths, L=L, median_s=float(np.median(ts)),
+                             neurons_per_s=sum(widths[1:]) / float(np.median(ts)),
+                             median_rel_volume=float(np.median(vs)),
+                             paper_median_s=paper[0] if isinstance(paper, tuple) else paper,
+                             paper_median_rel_volume=paper[1] if isinstance(paper, tuple) else None))
+        print(json.dumps({"sweep": fig, "nets": nets, "precision": "fp64", "rows": rows}), flush=True)
+
+
 def roof(flops, bytes_, ms, peak_flops):
     """Roofline of a class by the intensity of its executed work: the FP64
     vector roof above the ridge point, the HBM roof below it."""
@@ -206,6 +294,8 @@ def main():
                     help="comma-separated kernel variants to use instead of autotuning (profiling runs)")
     ap.add_argument("--graph", action="store_true",
                     help="replay the plain rule's launch sequence as one captured graph")
+    ap.add_argument("--sweep", action="store_true",
+                    help="only time the network shapes of the paper's Figs. 4-7 (one JSON line per figure)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only time a plain device copy of 1 GiB (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -217,6 +307,9 @@ def main():
     import torch
     if args.copy_calibration:
         copy_calibration(torch)
+        return
+    if args.sweep:
+        sweeps(torch)
         return
     from paper_2211_14438_amd import bernnn as B
     from paper_2211_14438_amd import workloads as wl
@@ -366,6 +459,8 @@ def main():
         line["plain_batched"] = plain_batched
         line["speedup_vs_batched_plain"] = value / plain_batched["value"]
         line["width_ratio_vs_batched_plain"] = width / plain_batched["mean_output_width"]
+    if not args.skip_plain:
+        line["verify"] = verify_demo(torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(case, args.cpu_budget)
     print(json.dumps(line), flush=True)

@@ -289,6 +289,15 @@ typedef struct {
   int32_t reserved0;
   int64_t boxes_bounded;
   int64_t undecided_boxes;
+  /* optional decision log (host arrays of the caller, NULL to skip): every
+   * decided box in decision order -- verified (+1), violated (-1), and the
+   * boxes left undecided at the end (0) -- with its corners and its output
+   * bounds, up to log_cap entries; log_count receives the number written */
+  int64_t log_cap;
+  int64_t log_count;
+  double *log_lo, *log_hi;      /* [log_cap][n] */
+  double *log_out_lo, *log_out_hi; /* [log_cap]: bounds of output out_index */
+  int8_t *log_status;           /* [log_cap] */
 } bern_verify_result;
 bern_status bern_verify(const bern_net *net, const bern_opts *opts, int64_t n_boxes, const double *box_lo,
                         const double *box_hi, int32_t out_index, double threshold, int32_t max_rounds,

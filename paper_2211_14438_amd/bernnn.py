@@ -56,7 +56,9 @@ def _stats(st):
 class bern_verify_result(ctypes.Structure):
     _fields_ = [("verified", ctypes.c_double), ("violated", ctypes.c_double), ("undecided", ctypes.c_double),
                 ("rounds", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("boxes_bounded", ctypes.c_int64),
-                ("undecided_boxes", ctypes.c_int64)]
+                ("undecided_boxes", ctypes.c_int64), ("log_cap", ctypes.c_int64), ("log_count", ctypes.c_int64),
+                ("log_lo", ctypes.c_void_p), ("log_hi", ctypes.c_void_p), ("log_out_lo", ctypes.c_void_p),
+                ("log_out_hi", ctypes.c_void_p), ("log_status", ctypes.c_void_p)]
 
 
 class BernError(RuntimeError):
@@ -471,19 +473,33 @@ def rel_volume(net, box_lo, box_hi, L=2, precision="fp64", plan="plain", sched="
 
 
 def verify(net, box_lo, box_hi, out_index, threshold, max_rounds=8, max_boxes=1 << 16, L=2, precision="fp64",
-           plan="plain", sched="batched", pred=None, lin=0):
+           plan="plain", sched="batched", pred=None, lin=0, log_cap=0):
     """Branch and bound for "output ``out_index`` <= ``threshold``" over host
     boxes (numpy [n_boxes, n]); returns the verified / violated / undecided
-    volume fractions, the rounds run and the box counts."""
+    volume fractions, the rounds run and the box counts, and with
+    ``log_cap`` > 0 the decision log (boxes, output bounds, status)."""
     box_lo = np.ascontiguousarray(box_lo, dtype=np.float64)
     box_hi = np.ascontiguousarray(box_hi, dtype=np.float64)
+    n = box_lo.shape[1]
     o = make_opts(L=L, precision=precision, plan=plan, sched=sched, pred=pred, lin=lin)
     r = bern_verify_result()
+    logs = None
+    if log_cap > 0:
+        logs = dict(lo=np.zeros((log_cap, n)), hi=np.zeros((log_cap, n)), out_lo=np.zeros(log_cap),
+                    out_hi=np.zeros(log_cap), status=np.zeros(log_cap, dtype=np.int8))
+        r.log_cap = int(log_cap)
+        r.log_lo, r.log_hi = logs["lo"].ctypes.data, logs["hi"].ctypes.data
+        r.log_out_lo, r.log_out_hi = logs["out_lo"].ctypes.data, logs["out_hi"].ctypes.data
+        r.log_status = logs["status"].ctypes.data
     _check(lib().bern_verify(net.handle, ctypes.byref(o), box_lo.shape[0], ctypes.c_void_p(box_lo.ctypes.data),
                              ctypes.c_void_p(box_hi.ctypes.data), int(out_index), float(threshold), int(max_rounds),
                              int(max_boxes), ctypes.byref(r)))
-    return dict(verified=r.verified, violated=r.violated, undecided=r.undecided, rounds=r.rounds,
-                boxes_bounded=r.boxes_bounded, undecided_boxes=r.undecided_boxes)
+    out = dict(verified=r.verified, violated=r.violated, undecided=r.undecided, rounds=r.rounds,
+               boxes_bounded=r.boxes_bounded, undecided_boxes=r.undecided_boxes)
+    if logs is not None:
+        k = int(r.log_count)
+        out["log"] = {key: v[:k] for key, v in logs.items()}
+    return out
 
 
 def bounds_host(net, box_lo, box_hi, L=2, precision="fp64", plan="plain", sched="batched", degree_plan=None,

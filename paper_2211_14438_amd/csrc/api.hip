@@ -1471,7 +1471,27 @@ extern "C" bern_status bern_verify(const bern_net *net, const bern_opts *opts, i
       }
     total += volume(&lo[b * n], &hi[b * n]);
   }
+  // keep the caller's decision log settings, clear the rest
+  const int64_t log_cap = res->log_cap;
+  double *log_lo = res->log_lo, *log_hi = res->log_hi, *log_olo = res->log_out_lo, *log_ohi = res->log_out_hi;
+  int8_t *log_st = res->log_status;
+  const bool logging = log_cap > 0 && log_lo && log_hi && log_olo && log_ohi && log_st;
   memset(res, 0, sizeof(*res));
+  res->log_cap = log_cap;
+  res->log_lo = log_lo;
+  res->log_hi = log_hi;
+  res->log_out_lo = log_olo;
+  res->log_out_hi = log_ohi;
+  res->log_status = log_st;
+  auto log_box = [&](const double *l, const double *h, double olo_, double ohi_, int8_t status) {
+    if (!logging || res->log_count >= log_cap) return;
+    const int64_t k = res->log_count++;
+    std::copy(l, l + n, log_lo + k * n);
+    std::copy(h, h + n, log_hi + k * n);
+    log_olo[k] = olo_;
+    log_ohi[k] = ohi_;
+    log_st[k] = status;
+  };
   std::vector<double> olo, ohi;
   for (int round = 0; round < max_rounds && !lo.empty(); ++round) {
     const int64_t nb = (int64_t)(lo.size() / n);
@@ -1487,12 +1507,16 @@ extern "C" bern_status bern_verify(const bern_net *net, const bern_opts *opts, i
     std::vector<int64_t> open;
     for (int64_t b = 0; b < nb; ++b) {
       const double v = volume(&lo[b * n], &hi[b * n]) / total;
-      if (ohi[b * o + out_index] <= threshold)
+      const double bl = olo[b * o + out_index], bh = ohi[b * o + out_index];
+      if (bh <= threshold) {
         res->verified += v;
-      else if (olo[b * o + out_index] > threshold)
+        log_box(&lo[b * n], &hi[b * n], bl, bh, 1);
+      } else if (bl > threshold) {
         res->violated += v;
-      else
+        log_box(&lo[b * n], &hi[b * n], bl, bh, -1);
+      } else {
         open.push_back(b);
+      }
     }
     const bool split = round + 1 < max_rounds && (int64_t)open.size() * 2 <= max_boxes;
     for (int64_t b : open) {
@@ -1500,6 +1524,7 @@ extern "C" bern_status bern_verify(const bern_net *net, const bern_opts *opts, i
       if (!split) {
         res->undecided += volume(l, h) / total;
         res->undecided_boxes += 1;
+        log_box(l, h, olo[b * o + out_index], ohi[b * o + out_index], 0);
         continue;
       }
       int wide = 0;
@@ -1517,9 +1542,11 @@ extern "C" bern_status bern_verify(const bern_net *net, const bern_opts *opts, i
     hi.swap(nhi);
   }
   // boxes still pending after the last round that was allowed to split
+  // (split but never bounded: logged with NaN bounds)
   for (size_t b = 0; b < lo.size() / n; ++b) {
     res->undecided += volume(&lo[b * n], &hi[b * n]) / total;
     res->undecided_boxes += 1;
+    log_box(&lo[b * n], &hi[b * n], NAN, NAN, 0);
   }
   return BERN_OK;
 }

@@ -1196,13 +1196,14 @@ static double count_at(int nv, int t) {
 // read-off: the `fix` leading variables folded once per block ((D+1)^fix
 // blocks, each with its own digits), the next q chain levels refolded as
 // their round digits change, then per round (D+1)^q of them) e - 1
-// expansions (one-variable basis change, (D+1)(D+2)/2 FMAs per output
-// polynomial coefficient) and (D+1)^e lanes, each folding its last variable
-// (every parent coefficient once) and converting its (D+1)^M tile in
-// registers, then a min and a max per Bernstein coefficient. The pass that
-// adds the remainders of fitted neurons is not counted.
+// expansions and (D+1)^e lanes, each folding its last variable (every parent
+// coefficient once, ratios from LDS) and converting its (D+1)^M tile in
+// registers, then a min and a max per Bernstein coefficient. A one-variable
+// basis change with the compile-time ratio table costs D(D+1)/2 FMAs: its
+// column j = 0 is all ones, so those products fold into the sums. The pass
+// that adds the remainders of fitted neurons is not counted.
 static double tree_ops(int n, int D, int M, int fix, int q, int e) {
-  const double D1 = D + 1, T = 0.5 * (D + 1) * (D + 2);
+  const double D1 = D + 1, T = 0.5 * D * (D + 1);
   // level i: folding variable i of an (n - i)-variable polynomial, summed
   // over the D + 1 digits; a child coefficient of total degree t takes
   // min(D - t, k) + 1 parents at digit k
