@@ -292,8 +292,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the built-in kernel variants")
     ap.add_argument("--tune", default=None,
                     help="comma-separated kernel variants to use instead of autotuning (profiling runs)")
-    ap.add_argument("--graph", action="store_true",
-                    help="replay the plain rule's launch sequence as one captured graph")
+    ap.add_argument("--eager", action="store_true",
+                    help="launch eagerly; by default batched runs replay their launch sequence as one captured "
+                         "graph (per-neuron plans with their degree classes listed on the device)")
     ap.add_argument("--sweep", action="store_true",
                     help="only time the network shapes of the paper's Figs. 4-7 (one JSON line per figure)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -334,7 +335,7 @@ def main():
         kw["workspace"] = torch.empty(size + 256, dtype=torch.uint8, device=dev)
         r = B.bounds(net, lo, hi, **kw)
         kw["outputs"] = {k: r[k] for k in ("neuron_lo", "neuron_hi", "out_lo", "out_hi", "used_plan")}
-        if form == "plain" and sched == "batched" and args.graph:
+        if sched == "batched" and not args.eager:
             kw["graph"] = True
         return kw
 
@@ -376,7 +377,10 @@ def main():
     # kernel classes are then timed over the same number of steps with a pair
     # of HIP events around every launch (eagerly when graphs are replayed)
     dt, _ = timed(kw, args.steps, False)
-    _, prof = timed({k: v for k, v in kw.items() if k != "graph"}, args.steps, True)
+    eager_kw = {k: v for k, v in kw.items() if k != "graph"}
+    st = B.bounds(net, lo, hi, **kw)["stats"]
+    dt_eager = timed(eager_kw, args.steps, False)[0] if graph else dt
+    _, prof = timed(eager_kw, args.steps, True)
     outs = kw["outputs"]
     ms_step = dt / args.steps * 1e3
     neurons = case.n_boxes * case.bounded_neurons_per_box
@@ -452,6 +456,8 @@ def main():
         line["autotune"] = tuned
     line["kernel_timing"] = ("per-launch HIP events over a second timed region of the same steps" +
                              (", launched eagerly (value: one captured graph per pass)" if graph else ""))
+    line["launch"] = dict(graph=bool(st["graph"]), device_classes=bool(st["device_classes"]),
+                          eager_ms_per_step=dt_eager / args.steps * 1e3, graph_ms_per_step=ms_step if graph else None)
     if plain_line is not None:
         line["plain"] = plain_line
         line["speedup_vs_plain"] = value / plain_line["value"]

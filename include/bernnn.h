@@ -103,9 +103,19 @@ typedef struct {
                          predictor's input features of every hidden neuron
                          (written in every plan mode; for training records)      */
   int32_t max_wave;   /* upper limit on boxes per wave (0 = as many as fit)         */
-  int32_t graph;      /* nonzero: runs with no host round trip (BERN_PLAN_PLAIN) are
-                         captured once per distinct argument set into a HIP graph
-                         and replayed as one graph launch; other plans run eagerly */
+  int32_t graph;      /* nonzero: the call's launch sequence is captured once per
+                         distinct argument set into a HIP graph and replayed as one
+                         graph launch. Per-neuron plans (GIVEN, LEARNED) then list
+                         their boxes' degree classes on the device: every class the
+                         rules can give is launched with its box count read from
+                         device memory (no host round trip). When those classes
+                         are too many (over 48 (pre, post) degree pairs in all,
+                         or over 64 lists in one layer) or their index tables
+                         exceed their limits, the call runs eagerly as with
+                         graph = 0 (bern_stats.graph tells). The outputs are
+                         bit-for-bit those of graph = 0. Zero: eager launches;
+                         per-neuron plans read every box's post degree back to
+                         the host once per hidden layer                         */
   int32_t lin;        /* periodic linearisation (the Lin parameter of Section 5.4):
                          0 = off (the paper's experiments); k >= 1 = after every k-th
                          hidden layer, each neuron's post polynomials are replaced by
@@ -150,7 +160,10 @@ typedef struct {
   uint64_t workspace_used; /* bytes of the workspace actually used                  */
   double enqueue_ms;    /* host time spent inside the call (the device work it
                            enqueued may still be running when it returns)          */
-  uint64_t reserved[5];
+  int32_t graph;        /* 1: the launches ran as one captured graph (opts.graph) */
+  int32_t device_classes; /* 1: a per-neuron plan's degree classes were listed on
+                           the device (no host round trip)                         */
+  uint64_t reserved[4];
 } bern_stats;
 
 /* Fill *opts with defaults: L = 2, FP64, plain plan, per-box schedule. */
@@ -184,7 +197,14 @@ int32_t bern_net_outputs(const bern_net *net);
 bern_status bern_workspace_size(const bern_net *net, const bern_opts *opts, int64_t n_boxes,
                                 size_t *bytes, size_t *one_box);
 
-/* Bounds of `n_boxes` boxes (Problem 1), asynchronous on `stream`.
+/* Bounds of `n_boxes` boxes (Problem 1), enqueued on `stream`. The call is
+ * asynchronous (it returns once the work is enqueued) for the plain rule, and
+ * for per-neuron plans with opts.graph whose classes the device lists
+ * (bern_stats.device_classes). Other per-neuron plan runs synchronise `stream`
+ * once per hidden layer and wave (each box's post degree is copied to pinned
+ * host memory, the network's own, and the class id lists back), so the call
+ * returns only once all but the output layer's work of the last wave is done;
+ * two such calls on one network from different threads must be serialised. 
  *   box_lo, box_hi   device, [n_boxes][n] FP64; d_lo <= d_hi required (the
  *                    library checks it on the device; a violation gives NaN
  *                    bounds for that box, never an invalid memory access)

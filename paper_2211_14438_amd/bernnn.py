@@ -45,12 +45,14 @@ COUNTERS = ("hidden", "inactive", "active", "fallback", "order1", "order2", "ord
 class bern_stats(ctypes.Structure):
     _fields_ = [("n_waves", ctypes.c_int32), ("boxes_per_wave", ctypes.c_int32), ("out_degree", ctypes.c_int32),
                 ("lin_layers", ctypes.c_int32), ("workspace_used", ctypes.c_uint64),
-                ("enqueue_ms", ctypes.c_double), ("reserved", ctypes.c_uint64 * 5)]
+                ("enqueue_ms", ctypes.c_double), ("graph", ctypes.c_int32), ("device_classes", ctypes.c_int32),
+                ("reserved", ctypes.c_uint64 * 4)]
 
 
 def _stats(st):
     return dict(n_waves=st.n_waves, boxes_per_wave=st.boxes_per_wave, out_degree=st.out_degree,
-                lin_layers=st.lin_layers, workspace_used=st.workspace_used, enqueue_ms=st.enqueue_ms)
+                lin_layers=st.lin_layers, workspace_used=st.workspace_used, enqueue_ms=st.enqueue_ms,
+                graph=st.graph, device_classes=st.device_classes)
 
 
 class bern_verify_result(ctypes.Structure):
@@ -399,9 +401,9 @@ def bounds(net, box_lo, box_hi, L=2, precision="fp64", plan="plain", sched="per_
            mem_budget=0, counters=None, no_raise=False):
     """Bounds of every box. ``box_lo``/``box_hi``: float64 CUDA tensors
     [n_boxes, n]. Returns a dict of CUDA tensors (neuron_lo/hi, out_lo/hi,
-    used_plan) plus the run statistics. Asynchronous on ``stream``. With
-    ``graph`` the plain rule's launch sequence is captured once and replayed
-    as one graph launch."""
+    used_plan) plus the run statistics. Enqueued on ``stream``. With
+    ``graph`` the launch sequence is captured once and replayed as one graph
+    launch; per-neuron plans then list their degree classes on the device."""
     args, res, workspace, keep = _prepare(net, box_lo, box_hi, L, precision, plan, sched, degree_plan, max_wave,
                                           workspace, outputs, pred, features, graph, lin, mem_budget, counters,
                                           no_raise)

@@ -138,7 +138,9 @@ __global__ void __launch_bounds__(kBlock) gemm_kernel(GemmArgs a) {
   __shared__ double red[kBlock / 64][MB][2];
   const int m0 = blockIdx.x * MB;
   const int64_t c = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
-  const int64_t box = a.bids ? a.bids[blockIdx.z] : blockIdx.z;
+  const int64_t nb = launch_boxes(a);
+  for (int64_t z = blockIdx.z; z < nb; z += gridDim.z) {
+  const int64_t box = a.bids ? a.bids[z] : z;
   const bool valid = c < a.C;
   const T *X = reinterpret_cast<const T *>(a.post) + box * a.slot_in;
   double accM[MB], accR[MB];
@@ -192,13 +194,16 @@ __global__ void __launch_bounds__(kBlock) gemm_kernel(GemmArgs a) {
       }
     }
   }
-  if (!track) return;
-  __syncthreads();
-  if (threadIdx.x < 2 * mcount) {
-    const int mm = threadIdx.x >> 1, s = threadIdx.x & 1;
-    double v = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v += red[w][mm][s];
-    a.rpart[box * a.rpart_slot + ((int64_t)(m0 + mm) * 2 + s) * a.cblocks + blockIdx.y] = v;
+  if (track) {
+    __syncthreads();
+    if (threadIdx.x < 2 * mcount) {
+      const int mm = threadIdx.x >> 1, s = threadIdx.x & 1;
+      double v = 0.0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v += red[w][mm][s];
+      a.rpart[box * a.rpart_slot + ((int64_t)(m0 + mm) * 2 + s) * a.cblocks + blockIdx.y] = v;
+    }
+    __syncthreads();  // red is rewritten by the next box
+  }
   }
 }
 
@@ -232,13 +237,17 @@ __global__ void __launch_bounds__(kPackWaves * 64) gemm_pack_kernel(GemmArgs a) 
   const int C = (int)a.C, G = pack_groups(a.C), hin = a.hin;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane / C, c = lane - g * C;
-  // logical block: row chunk fastest, the row chunks of one box group on one XCD
+  // logical block: row chunk fastest, the row chunks of one box group on one
+  // XCD; a grid smaller than the logical blocks (a device box count) strides
+  // over them
   const int nx = (a.h + MB - 1) / MB;
-  const int64_t lb = xcd_block(blockIdx.x, (int64_t)gridDim.x);
+  const int64_t nb = launch_boxes(a);
+  const int64_t nlb = (int64_t)nx * ((nb + G - 1) / G);
+  for (int64_t lb = xcd_block(blockIdx.x, (int64_t)gridDim.x); lb < nlb; lb += gridDim.x) {
   const int m0 = (int)(lb % nx) * MB;
   const int64_t slot0 = lb / nx * G;
   const int64_t bslot = slot0 + g;
-  const bool valid = g < G && bslot < a.nboxes;
+  const bool valid = g < G && bslot < nb;
   double *wl = pk_lds;
   double *part = wl + (size_t)hin * MB;
   unsigned char *kind = reinterpret_cast<unsigned char *>(part + (size_t)(kPackWaves - 1) * 2 * MB * 64);
@@ -247,7 +256,7 @@ __global__ void __launch_bounds__(kPackWaves * 64) gemm_pack_kernel(GemmArgs a) 
   // whose latency each step would wait for
   for (int i = threadIdx.x; i < hin * MB; i += blockDim.x) wl[i] = a.WT[(int64_t)(i / MB) * a.hp + m0 + i % MB];
   __syncthreads();
-  for (int gg = 0; gg < G && slot0 + gg < a.nboxes; ++gg) {
+  for (int gg = 0; gg < G && slot0 + gg < nb; ++gg) {
     const int64_t bx = a.bids ? a.bids[slot0 + gg] : slot0 + gg;
     const int *lv = a.live + bx * a.live_ld;
     for (int t = 0; t < 3; ++t) {
@@ -359,16 +368,19 @@ __global__ void __launch_bounds__(kPackWaves * 64) gemm_pack_kernel(GemmArgs a) 
       }
     }
   }
-  if (!track) return;
-  __syncthreads();
-  // per (box, row, bound): its coefficients' rounding in index order
-  for (int t = threadIdx.x; t < G * MB * 2; t += blockDim.x) {
-    const int gg = t / (2 * MB), r = t - gg * 2 * MB, mm = r >> 1, sd = r & 1;
-    if (slot0 + gg >= a.nboxes || m0 + mm >= a.h) continue;
-    double v = 0.0;
-    for (int q = 0; q < C; ++q) v += part[r * 64 + gg * C + q];
-    const int64_t bx = a.bids ? a.bids[slot0 + gg] : slot0 + gg;
-    a.rpart[bx * a.rpart_slot + ((int64_t)(m0 + mm) * 2 + sd) * a.cblocks] = v;
+  if (track) {
+    __syncthreads();
+    // per (box, row, bound): its coefficients' rounding in index order
+    for (int t = threadIdx.x; t < G * MB * 2; t += blockDim.x) {
+      const int gg = t / (2 * MB), r = t - gg * 2 * MB, mm = r >> 1, sd = r & 1;
+      if (slot0 + gg >= nb || m0 + mm >= a.h) continue;
+      double v = 0.0;
+      for (int q = 0; q < C; ++q) v += part[r * 64 + gg * C + q];
+      const int64_t bx = a.bids ? a.bids[slot0 + gg] : slot0 + gg;
+      a.rpart[bx * a.rpart_slot + ((int64_t)(m0 + mm) * 2 + sd) * a.cblocks] = v;
+    }
+  }
+  __syncthreads();  // LDS is restaged for the next logical block
   }
 }
 
@@ -380,7 +392,7 @@ static hipError_t launch_gemm_pack(const GemmArgs &a, hipStream_t s) {
   const size_t lds = pack_lds(G, a.hin, MB);
   const int64_t blocks = (int64_t)((a.h + MB - 1) / MB) * ((a.nboxes + G - 1) / G);
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  dim3 grid((unsigned)blocks);
+  dim3 grid((unsigned)dev_grid(blocks, a.dcount));
   if (a.fp64) {
     RET_IF(hipFuncSetAttribute((const void *)gemm_pack_kernel<double, MB>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -395,7 +407,8 @@ static hipError_t launch_gemm_pack(const GemmArgs &a, hipStream_t s) {
 
 template <int MB, int KU>
 static hipError_t launch_gemm_mb(const GemmArgs &a, hipStream_t s) {
-  dim3 grid((a.h + MB - 1) / MB, (unsigned)a.cblocks, (unsigned)a.nboxes);
+  const int64_t gxy = (int64_t)((a.h + MB - 1) / MB) * a.cblocks;
+  dim3 grid((a.h + MB - 1) / MB, (unsigned)a.cblocks, (unsigned)dev_grid(a.nboxes, a.dcount, gxy));
   // one coefficient block: only the waves that hold coefficients
   const unsigned threads = a.C < kBlock ? (unsigned)((a.C + 63) / 64 * 64) : kBlock;
   if (a.fp64)

@@ -111,6 +111,25 @@ size_t device_lds_limit() {
   return (size_t)cached[dev];
 }
 
+// Device-side classes of per-neuron plans (no host round trip, so the wave
+// can be captured as one graph): every pre degree a box can hold at each
+// layer and every (pre, post) pair the rules can give at each hidden layer.
+// A neuron of a box at pre degree Din takes degree 0 (inactive), Din
+// (active, order 1), k Din (order k <= the plan's largest: 3 for the
+// predictor's classes, kMaxOrder for given codes; k Din within the layer's
+// cap) or 1 (the linear fallback); the box's post degree is the largest, so
+// the pairs are (0, {0, 1}) and (Din, {0, 1} + {k Din}). Every pair is
+// launched with its device count, an empty one costing its launches, so
+// the device path is taken only while the pairs stay few.
+constexpr int kMaxDevLists = 64;  // lists per hidden layer: pairs + the next layer's pre degrees
+constexpr int kMaxDevPairs = 48;  // pairs over all hidden layers
+
+struct DevClasses {
+  std::vector<std::vector<int>> din;                    // [layer] pre degrees, ascending
+  std::vector<std::vector<std::pair<int, int>>> pairs;  // [hidden layer] (Din, Dout)
+  int slots = 0;                                        // lists per layer
+};
+
 // Host-side plan of one network under one set of options: degree of every
 // layer's pre-activation and post tensors and the per-box workspace layout.
 struct Plan {
@@ -127,7 +146,44 @@ struct Plan {
   size_t per_box() const {
     return 2 * recs + 2 * rad + 2 * arenaA + arenaB + conv + horner + flags + gpart + cpart + live + oeps;
   }
+  size_t list_ints = 0;             // ints per box of the class id lists
+  bool dev_ok = false;              // per-neuron plan whose classes the device can list
+  DevClasses dc;
 };
+
+static bool dev_classes(const Plan &p, DevClasses &dc) {
+  const int top = p.mode == BERN_PLAN_LEARNED ? 3 : kMaxOrder;
+  std::vector<int> cur{1};
+  int total = 0;
+  dc = DevClasses{};
+  for (int i = 0; i < p.H; ++i) {
+    dc.din.push_back(cur);
+    if (i == p.H - 1) break;
+    const int cap = p.Dpost[i];
+    std::vector<std::pair<int, int>> pr;
+    std::vector<int> nxt;
+    for (int d : cur) {
+      std::vector<int> outs{0, 1};
+      for (int k = 1; d >= 1 && k <= top && k * d <= cap; ++k) outs.push_back(k * d);
+      std::sort(outs.begin(), outs.end());
+      outs.erase(std::unique(outs.begin(), outs.end()), outs.end());
+      for (int o : outs) {
+        pr.emplace_back(d, o);
+        nxt.push_back(o);
+      }
+    }
+    std::sort(nxt.begin(), nxt.end());
+    nxt.erase(std::unique(nxt.begin(), nxt.end()), nxt.end());
+    const bool lin = p.lin > 0 && (i + 1) % p.lin == 0;
+    if (lin) nxt.assign(1, 1);  // every box restarts at degree 1
+    total += (int)pr.size();
+    dc.slots = std::max(dc.slots, (int)pr.size() + (lin ? 0 : (int)nxt.size()));
+    dc.pairs.push_back(pr);
+    cur = nxt;
+  }
+  return dc.slots <= kMaxDevLists && total <= kMaxDevPairs;
+}
+
 
 }  // namespace bern
 
@@ -255,9 +311,14 @@ static bern_status plan_net(const bern_net *net, const bern_opts *o, Plan &p) {
       }
     }
   }
-  // per box: validity flag, post degree, one id per (layer, phase) list, and
-  // the predicted code of every hidden neuron
-  p.flags = align256(sizeof(int) * (2 + 2 * (size_t)p.H) + (size_t)net->nh);
+  // per box: validity flag, post degree (two layers), the class id lists
+  // (host classes: one per layer and phase; device classes: one per list
+  // slot and layer parity, then their counts), and the predicted code of
+  // every hidden neuron
+  p.list_ints = 2 * (size_t)p.H;
+  p.dev_ok = p.mode != BERN_PLAN_PLAIN && dev_classes(p, p.dc);
+  if (p.dev_ok) p.list_ints = std::max(p.list_ints, 4 * (size_t)p.dc.slots);
+  p.flags = align256(sizeof(int) * (3 + p.list_ints) + (size_t)net->nh);
   p.live = align256(sizeof(int) * (3 + 3 * (size_t)net->hmax));
   p.rad = align256(sizeof(double) * 4 * (size_t)net->hmax);
   p.oeps = align256(sizeof(double) * 2 * (size_t)net->o);
@@ -559,17 +620,81 @@ static bern_status layer_tables(const bern_net *net, int Din, int Lmax, bool com
   return BERN_OK;
 }
 
-// Boxes of one degree class within a wave.
+// Boxes of one degree class within a wave (host-side classification).
 struct BoxClass {
   int Din, Dout;
   std::vector<int> ids;
 };
 
-// Enqueue the launch sequence of one wave of `B` boxes. The plain rule keeps
-// every box at the same degrees: one class, no host round trip. Plans with
-// per-neuron degrees read each box's post degree back once per hidden layer
-// and launch each degree class of boxes on its own (a box's tensors stay
-// dense at the box's own degree inside its fixed slot).
+// The boxes one launch takes: `nboxes` boxes listed in `bids` (null: the
+// wave's boxes in order) or, with `dcount`, the first *dcount of them, a
+// count the device wrote (nboxes then bounds it).
+struct LaunchClass {
+  int Din = 1, Dout = 0;
+  const int *bids = nullptr;
+  int64_t nboxes = 0;
+  const int *dcount = nullptr;
+};
+
+struct ClassTab {
+  int npairs, nvals;
+  int din[kMaxDevLists], dout[kMaxDevLists], vals[kMaxDevLists];
+};
+
+// One block per list, boxes in order: list k < npairs holds the boxes whose
+// (pre degree, post degree) is pair k, list npairs + m those whose post
+// degree is vals[m] (the next layer's read-off classes), and counts[k] their
+// lengths. The last block flags every box no pair covers (none, as the
+// pairs are every combination the rules give; a flagged box ends with NaN
+// bounds rather than stale ones). Degrees below 0 count as 0; a null dpre
+// puts every box at pre degree 1.
+__global__ void __launch_bounds__(1024) classify_kernel(int64_t B, const int *dpre, const int *dpost, ClassTab t,
+                                                        int *ids, int *counts, int *flags) {
+  __shared__ int wsum[16];
+  __shared__ int base;
+  const int k = blockIdx.x;
+  const int lists = t.npairs + t.nvals;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (threadIdx.x == 0) base = 0;
+  __syncthreads();
+  for (int64_t b0 = 0; b0 < B; b0 += blockDim.x) {
+    const int64_t b = b0 + threadIdx.x;
+    bool m = false;
+    if (b < B) {
+      const int di = dpre ? max(dpre[b], 0) : 1, dq = max(dpost[b], 0);
+      if (k < t.npairs) {
+        m = di == t.din[k] && dq == t.dout[k];
+      } else if (k < lists) {
+        m = dq == t.vals[k - t.npairs];
+      } else {
+        bool any = false;
+        for (int q = 0; q < t.npairs; ++q) any |= di == t.din[q] && dq == t.dout[q];
+        m = !any;
+      }
+    }
+    const unsigned long long bal = __ballot(m);
+    if (lane == 0) wsum[wid] = __popcll(bal);
+    __syncthreads();
+    if (m) {
+      if (k < lists) {
+        int pos = base;
+        for (int w = 0; w < wid; ++w) pos += wsum[w];
+        ids[(int64_t)k * B + pos + __popcll(bal & ((1ull << lane) - 1ull))] = (int)b;
+      } else {
+        flags[b] = 1;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int tot = 0;
+      for (int w = 0; w < nw; ++w) tot += wsum[w];
+      base += tot;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && k < lists) counts[k] = base;
+}
+
 // Output polynomials requested by bern_output_polys: dense power tensors at
 // per-variable degree D (C = (D+1)^n coefficients each), [n_boxes][o][C];
 // or, by bern_rel_volume, only their relative volumes vol [n_boxes][o].
@@ -593,8 +718,8 @@ static int class_order(const Plan &p, int Din, int Dout) {
 }
 
 // Compose arguments of hidden layer i for the boxes of class cl (bids).
-static bern_status compose_args(const bern_net *net, const Plan &p, int i, const BoxClass &cl, const int *bids,
-                                void *pre, void *post, int64_t slotA, int64_t slotB, NeuronRec *recs, double *rad,
+static bern_status compose_args(const bern_net *net, const Plan &p, int i, const LaunchClass &cl, void *pre,
+                                void *post, int64_t slotA, int64_t slotB, NeuronRec *recs, double *rad,
                                 double *cpart, void *horner, size_t horner_bytes, int *live, int64_t live_ld,
                                 ComposeArgs &m) {
   const int n = net->n;
@@ -603,7 +728,8 @@ static bern_status compose_args(const bern_net *net, const Plan &p, int i, const
   m.Din = cl.Din;
   m.Dout = cl.Dout;
   m.h = net->widths[i + 1];
-  m.bids = bids;
+  m.bids = cl.bids;
+  m.dcount = cl.dcount;
   m.slot_in = slotA;
   m.slot_out = slotB;
   m.nbounds = 2;
@@ -626,7 +752,7 @@ static bern_status compose_args(const bern_net *net, const Plan &p, int i, const
       m.hz_off[q] = lt.hz[q]->off;
       m.hz_pairs[q] = lt.hz[q]->pairs;
     }
-  m.nboxes = (int64_t)cl.ids.size();
+  m.nboxes = cl.nboxes;
   m.pre = pre;
   m.post = post;
   m.recs = recs;
@@ -648,15 +774,14 @@ static bern_status compose_args(const bern_net *net, const Plan &p, int i, const
 // and read off with fits and remainders (mode 2); the affine posts stored at
 // degree 1 for all boxes, and the next layer's affine map over every box at
 // degree 1 (Section 5.4, the Lin parameter).
-static bern_status lin_layer_run(const bern_net *net, const Plan &p, int i, const std::vector<BoxClass> &next,
-                                 const std::vector<const int *> &pid, int64_t B, void *const *Aa, void *Bp,
-                                 int64_t slotA, int64_t slotB, NeuronRec *recs, double *rad, double *cpart,
-                                 void *horner, int *live, int64_t live_ld, double *gpart, double *conv,
-                                 hipStream_t s) {
+static bern_status lin_layer_run(const bern_net *net, const Plan &p, int i, const std::vector<LaunchClass> &next,
+                                 int64_t B, void *const *Aa, void *Bp, int64_t slotA, int64_t slotB, NeuronRec *recs,
+                                 double *rad, double *cpart, void *horner, int *live, int64_t live_ld, double *gpart,
+                                 double *conv, hipStream_t s) {
   const int n = net->n, h = net->widths[i + 1];
   for (size_t k = 0; k < next.size(); ++k) {
     ComposeArgs m;
-    bern_status st = compose_args(net, p, i, next[k], pid[k], Aa[i & 1], Bp, slotA, slotB, recs, rad, cpart, horner,
+    bern_status st = compose_args(net, p, i, next[k], Aa[i & 1], Bp, slotA, slotB, recs, rad, cpart, horner,
                                   p.horner * B, live, live_ld, m);
     if (st != BERN_OK) return st;
     m.lists_ready = 1;  // the lists below, once the layer is linearised
@@ -678,10 +803,10 @@ static bern_status lin_layer_run(const bern_net *net, const Plan &p, int i, cons
     BERN_HIP_TRY(launch_post_radii(mr, s));
   }
   for (size_t k = 0; k < next.size(); ++k) {
-    const BoxClass &cl = next[k];
+    const LaunchClass &cl = next[k];
     if (cl.Dout < 1) continue;  // every neuron inactive: nothing to linearise
     ComposeArgs m;
-    bern_status st = compose_args(net, p, i, cl, pid[k], Aa[i & 1], Bp, slotA, slotB, recs, rad, cpart, horner,
+    bern_status st = compose_args(net, p, i, cl, Aa[i & 1], Bp, slotA, slotB, recs, rad, cpart, horner,
                                   p.horner * B, live, live_ld, m);
     if (st != BERN_OK) return st;
     BERN_HIP_TRY(launch_lin_stage(m, s));
@@ -703,8 +828,9 @@ static bern_status lin_layer_run(const bern_net *net, const Plan &p, int i, cons
       c.tree_len = lt.tree->len;
       for (int d = 0; d <= n && d < 17; ++d) c.tree_base[d] = lt.tree->base[d];
     }
-    c.nboxes = (int64_t)cl.ids.size();
-    c.bids = pid[k];
+    c.nboxes = cl.nboxes;
+    c.bids = cl.bids;
+    c.dcount = cl.dcount;
     c.slot = slotB;
     c.cap = cl.Dout;
     c.pre = Bp;
@@ -768,10 +894,18 @@ static bern_status lin_layer_run(const bern_net *net, const Plan &p, int i, cons
   return BERN_OK;
 }
 
+// Enqueue the launch sequence of one wave of `B` boxes. The plain rule keeps
+// every box at the same degrees: one class, no host round trip. Plans with
+// per-neuron degrees launch each degree class of boxes on its own (a box's
+// tensors stay dense at the box's own degree inside its fixed slot): with
+// `dc`, every class the rules can give, its box list and count written by a
+// classification kernel (no host round trip); without, the classes that
+// occur, read back once per hidden layer (the box degrees to the host, the
+// id lists to the device).
 static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts *o, int64_t b0, int64_t B,
                             const double *box_lo, const double *box_hi, const int8_t *plan, double *nlo, double *nhi,
                             double *olo, double *ohi, int8_t *used, char *ws, hipStream_t s,
-                            const OutPolys *op = nullptr) {
+                            const OutPolys *op = nullptr, const DevClasses *dc = nullptr) {
   char *cur = ws;
   NeuronRec *recbuf[2];
   recbuf[0] = reinterpret_cast<NeuronRec *>(cur); cur += p.recs * B;
@@ -794,13 +928,17 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
   double *oeps = reinterpret_cast<double *>(cur); cur += p.oeps * B;
   const int64_t live_ld = (int64_t)(p.live / sizeof(int));
   int *flags = reinterpret_cast<int *>(cur);
-  int *degs = flags + B;
-  int *idlists = flags + 2 * B;  // [H][2][B]
-  int8_t *codes = reinterpret_cast<int8_t *>(idlists + (int64_t)p.H * 2 * B);  // [B][nh]
+  int *degs = flags + B;          // [2][B] box post degrees, alternating by layer
+  int *idlists = flags + 3 * B;   // host classes: [H][2][B]; device classes: [2][slots][B], then [2][slots] counts
+  int8_t *codes = reinterpret_cast<int8_t *>(idlists + (int64_t)p.list_ints * B);  // [B][nh]
   const bool learned = p.mode == BERN_PLAN_LEARNED;
   const int n = net->n;
   const int64_t slotA = (int64_t)(p.arenaA / p.elem), slotB = (int64_t)(p.arenaB / p.elem);
   const bool plain = p.mode == BERN_PLAN_PLAIN;
+  const bool dev = !plain && dc != nullptr;
+  const int64_t slots = dev ? dc->slots : 0;
+  auto dev_ids = [&](int layer, int64_t k) -> const int * { return idlists + ((layer & 1) * slots + k) * B; };
+  auto dev_cnt = [&](int layer, int64_t k) -> int * { return idlists + 2 * slots * B + (layer & 1) * slots + k; };
 
   {
     ProfScope ps(kProfMisc, s, 0.0);
@@ -809,7 +947,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
   }
   BERN_HIP_TRY(hipGetLastError());
 
-  // degree classes of the current layer's pre-activations
+  // host-side degree classes of the current layer's pre-activations
   std::vector<const int *> carried;  // device id lists the next layer's read-off can reuse
   std::vector<BoxClass> classes(1);
   classes[0].Din = 1;
@@ -819,7 +957,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
   // list is written once per wave, and every wave's first copy follows a
   // stream synchronisation, so no staged list is rewritten in flight
   const size_t need = (size_t)B * (1 + 2 * (size_t)p.H);
-  if (!plain && net->host_n < need) {
+  if (!plain && !dev && net->host_n < need) {
     BERN_HIP_TRY(hipStreamSynchronize(s));
     if (net->host_ids) (void)hipHostFree(net->host_ids);
     net->host_ids = nullptr;
@@ -827,8 +965,8 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
     BERN_HIP_TRY(hipHostMalloc((void **)&net->host_ids, need * sizeof(int), hipHostMallocDefault));
     net->host_n = need;
   }
-  auto upload = [&](std::vector<BoxClass> &cl, int layer, int phase, std::vector<const int *> &dev) -> bern_status {
-    dev.assign(cl.size(), nullptr);
+  auto upload = [&](std::vector<BoxClass> &cl, int layer, int phase, std::vector<const int *> &devl) -> bern_status {
+    devl.assign(cl.size(), nullptr);
     if (cl.size() == 1 && (int64_t)cl[0].ids.size() == B) return BERN_OK;  // identity
     int *all = net->host_ids + B + ((int64_t)layer * 2 + phase) * B;
     size_t cnt = 0;
@@ -840,7 +978,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
     BERN_HIP_TRY(hipMemcpyAsync(dst, all, cnt * sizeof(int), hipMemcpyHostToDevice, s));
     int64_t off = 0;
     for (size_t k = 0; k < cl.size(); ++k) {
-      dev[k] = dst + off;
+      devl[k] = dst + off;
       off += cl[k].ids.size();
     }
     return BERN_OK;
@@ -849,6 +987,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
     c.ids.resize(B);
     for (int64_t b = 0; b < B; ++b) c.ids[b] = (int)b;
   }
+  bool restart = true;  // every box at pre degree 1 (the first layer, or after a linearisation)
 
   {
     Layer1Args a{n, net->widths[1], B, nullptr, slotA, box_lo, box_hi, net->W64 + net->woff[0],
@@ -864,18 +1003,32 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
     // plan codes are clamped to the plain rule's post degree of the layer
     const int cap = last ? 1 : p.Dpost[i];
     const bool lin_layer = !last && p.lin > 0 && (i + 1) % p.lin == 0;
-    // bounds read-off (+ rules and approximants for hidden layers), per class
-    std::vector<const int *> cid;
+    int *ldeg = degs + (i & 1) * B;  // this layer's box post degrees
+    // the read-off classes of the layer
+    std::vector<LaunchClass> rc;
     bern_status st = BERN_OK;
-    if (carried.size() == classes.size()) {
-      cid = carried;  // the previous layer's composition lists, same classes in the same order
+    if (dev) {
+      if (restart) {
+        rc.push_back(LaunchClass{1, 0, nullptr, B, nullptr});
+      } else {
+        const int64_t np = (int64_t)dc->pairs[i - 1].size();
+        for (size_t m = 0; m < dc->din[i].size(); ++m)
+          rc.push_back(LaunchClass{dc->din[i][m], 0, dev_ids(i - 1, np + m), B, dev_cnt(i - 1, np + m)});
+      }
     } else {
-      st = upload(classes, i, 0, cid);
-      if (st != BERN_OK) return st;
+      std::vector<const int *> cid;
+      if (carried.size() == classes.size()) {
+        cid = carried;  // the previous layer's composition lists, same classes in the same order
+      } else {
+        st = upload(classes, i, 0, cid);
+        if (st != BERN_OK) return st;
+      }
+      for (size_t k = 0; k < classes.size(); ++k)
+        rc.push_back(LaunchClass{classes[k].Din, 0, cid[k], (int64_t)classes[k].ids.size(), nullptr});
     }
     carried.clear();
-    for (size_t k = 0; k < classes.size(); ++k) {
-      const BoxClass &cl = classes[k];
+    // bounds read-off (+ rules and approximants for hidden layers), per class
+    for (const LaunchClass &cl : rc) {
       ConvertArgs c{};
       c.n = n;
       c.D = cl.Din;
@@ -894,8 +1047,9 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
         c.tree_len = lt.tree->len;
         for (int d = 0; d <= n && d < 17; ++d) c.tree_base[d] = lt.tree->base[d];
       }
-      c.nboxes = (int64_t)cl.ids.size();
-      c.bids = cid[k];
+      c.nboxes = cl.nboxes;
+      c.bids = cl.bids;
+      c.dcount = cl.dcount;
       c.slot = slotA;
       c.cap = cap;
       c.pre = Aa[i & 1];
@@ -956,7 +1110,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       la.params = learned ? o->pred->params : nullptr;
       la.codes = codes;
       la.used = used;
-      la.degs = learned ? degs : nullptr;  // the rules kernel also gives each box's post degree
+      la.degs = learned ? ldeg : nullptr;  // the rules kernel also gives each box's post degree
       la.cap = cap;
       la.fp64 = p.fp64 ? 1 : 0;
       la.L = p.L;
@@ -980,16 +1134,19 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
     }
     if (last) {
       if (op) {  // the output layer's stored tensors, per class, into the caller's dense tensors
-        for (size_t k = 0; k < classes.size(); ++k) {
-          const BoxClass &cl = classes[k];
+        for (const LaunchClass &cl : rc) {
+          if (cl.dcount) {
+            set_error("output tensors are taken with host-side classes only");
+            return BERN_E_ARG;
+          }
           if (op->vol) {  // relative volume at the class's own degree
             OutPolyArgs a{};
             a.pre = Aa[i & 1];
             a.slot = slotA;
             a.S = ssize(n, cl.Din);
             BERN_HIP_TRY(dense_index_table(*net->tab, cl.Din, &a.didx));  // built for this layer's read-off
-            a.bids = cid[k];
-            a.nboxes = (int64_t)cl.ids.size();
+            a.bids = cl.bids;
+            a.nboxes = cl.nboxes;
             a.h = h;
             a.eps = p.fp64 ? nullptr : oeps;
             a.fp64 = p.fp64 ? 1 : 0;
@@ -1006,8 +1163,8 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
           a.S = ssize(n, cl.Din);
           a.C = op->C;
           a.didx = op->didx;
-          a.bids = cid[k];
-          a.nboxes = (int64_t)cl.ids.size();
+          a.bids = cl.bids;
+          a.nboxes = cl.nboxes;
           a.h = h;
           a.eps = p.fp64 ? nullptr : oeps;
           a.fp64 = p.fp64 ? 1 : 0;
@@ -1021,34 +1178,65 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
 
     // post degree of every box -> classes (Din, Dout)
     std::vector<BoxClass> next;
+    std::vector<LaunchClass> pc;
     if (plain) {
       next = classes;
       for (auto &c : next) c.Dout = p.L * c.Din;
+      for (size_t k = 0; k < rc.size(); ++k)
+        pc.push_back(LaunchClass{rc[k].Din, p.L * rc[k].Din, rc[k].bids, rc[k].nboxes, nullptr});
     } else {
       if (!learned) {  // (the learned rules kernel wrote them)
         ProfScope ps(kProfMisc, s, 0.0);
         hipLaunchKernelGGL(box_degree_kernel, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, s, B, h,
-                           (const NeuronRec *)recs, degs);
+                           (const NeuronRec *)recs, ldeg);
       }
       BERN_HIP_TRY(hipGetLastError());
-      int *hd = net->host_ids;
-      BERN_HIP_TRY(hipMemcpyAsync(hd, degs, B * sizeof(int), hipMemcpyDeviceToHost, s));
-      BERN_HIP_TRY(hipStreamSynchronize(s));
-      for (int64_t b = 0; b < B; ++b) {
-        const int din = dcur[b], dout = std::max(hd[b], 0);
-        size_t k = 0;
-        for (; k < next.size(); ++k)
-          if (next[k].Din == din && next[k].Dout == dout) break;
-        if (k == next.size()) next.push_back(BoxClass{din, dout, {}});
-        next[k].ids.push_back((int)b);
+      if (dev) {
+        const auto &pr = dc->pairs[i];
+        ClassTab t{};
+        t.npairs = (int)pr.size();
+        t.nvals = lin_layer ? 0 : (int)dc->din[i + 1].size();
+        for (int k = 0; k < t.npairs; ++k) {
+          t.din[k] = pr[k].first;
+          t.dout[k] = pr[k].second;
+        }
+        for (int m = 0; m < t.nvals; ++m) t.vals[m] = dc->din[i + 1][m];
+        {
+          ProfScope ps(kProfMisc, s, 0.0);
+          hipLaunchKernelGGL(classify_kernel, dim3((unsigned)(t.npairs + t.nvals + 1)), dim3(1024), 0, s, B,
+                             restart ? (const int *)nullptr : (const int *)(degs + ((i + 1) & 1) * B),
+                             (const int *)ldeg, t, idlists + (i & 1) * slots * B, dev_cnt(i, 0), flags);
+        }
+        BERN_HIP_TRY(hipGetLastError());
+        for (int k = 0; k < t.npairs; ++k)
+          pc.push_back(LaunchClass{pr[k].first, pr[k].second, dev_ids(i, k), B, dev_cnt(i, k)});
+      } else {
+        int *hd = net->host_ids;
+        BERN_HIP_TRY(hipMemcpyAsync(hd, ldeg, B * sizeof(int), hipMemcpyDeviceToHost, s));
+        BERN_HIP_TRY(hipStreamSynchronize(s));
+        for (int64_t b = 0; b < B; ++b) {
+          const int din = dcur[b], dout = std::max(hd[b], 0);
+          size_t k = 0;
+          for (; k < next.size(); ++k)
+            if (next[k].Din == din && next[k].Dout == dout) break;
+          if (k == next.size()) next.push_back(BoxClass{din, dout, {}});
+          next[k].ids.push_back((int)b);
+        }
       }
     }
     std::vector<const int *> pid;
-    st = upload(next, i, 1, pid);
-    if (st != BERN_OK) return st;
+    if (!dev && !plain) {
+      st = upload(next, i, 1, pid);
+      if (st != BERN_OK) return st;
+      for (size_t k = 0; k < next.size(); ++k)
+        pc.push_back(LaunchClass{next[k].Din, next[k].Dout, pid[k], (int64_t)next[k].ids.size(), nullptr});
+    } else if (plain) {
+      pid.assign(pc.size(), nullptr);
+      for (size_t k = 0; k < pc.size(); ++k) pid[k] = pc[k].bids;
+    }
     if (lin_layer) {
-      st = lin_layer_run(net, p, i, next, pid, B, Aa, Bp, slotA, slotB, recs, radbuf[i & 1], cpart, horner, live,
-                         live_ld, gpart, conv, s);
+      st = lin_layer_run(net, p, i, pc, B, Aa, Bp, slotA, slotB, recs, radbuf[i & 1], cpart, horner, live, live_ld,
+                         gpart, conv, s);
       if (st != BERN_OK) return st;
       classes.assign(1, BoxClass{1, 0, {}});
       classes[0].ids.resize(B);
@@ -1057,10 +1245,13 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
         dcur[b] = 1;
       }
       carried.clear();
+      restart = true;
       continue;
     }
-    // several classes: the next affine map's input lists of every box at once
-    const bool lists_once = next.size() > 1;
+    restart = false;
+    // several classes (or device classes): the next affine map's input lists
+    // of every box at once
+    const bool lists_once = dev || pc.size() > 1;
     if (lists_once) {
       ComposeArgs ml{};
       ml.h = h;
@@ -1070,12 +1261,11 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       ml.live_ld = live_ld;
       BERN_HIP_TRY(launch_live(ml, s));
     }
-    for (size_t k = 0; k < next.size(); ++k) {
-      const BoxClass &cl = next[k];
+    for (const LaunchClass &cl : pc) {
       // composition -> post tensors in arena B
       ComposeArgs m;
-      st = compose_args(net, p, i, cl, pid[k], Aa[i & 1], Bp, slotA, slotB, recs, radbuf[i & 1], cpart, horner,
-                        p.horner * B, live, live_ld, m);
+      st = compose_args(net, p, i, cl, Aa[i & 1], Bp, slotA, slotB, recs, radbuf[i & 1], cpart, horner, p.horner * B,
+                        live, live_ld, m);
       if (st != BERN_OK) return st;
       m.lists_ready = lists_once ? 1 : 0;
       m.radii_later = lists_once ? 1 : 0;
@@ -1085,8 +1275,9 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       a.hin = h;
       a.h = net->widths[i + 2];
       a.C = m.Cout;
-      a.nboxes = m.nboxes;
-      a.bids = pid[k];
+      a.nboxes = cl.nboxes;
+      a.bids = cl.bids;
+      a.dcount = cl.dcount;
       a.slot_in = slotB;
       a.slot_out = slotA;
       a.post = Bp;
@@ -1121,6 +1312,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       mr.fp64 = 0;
       BERN_HIP_TRY(launch_post_radii(mr, s));
     }
+    if (dev) continue;  // the classification kernel listed the next read-off's classes
     // next layer's classes: by the new pre degree
     std::vector<BoxClass> nc;
     for (auto &cl : next) {
@@ -1231,6 +1423,30 @@ static bern_status bounds_impl(const bern_net *net, const bern_opts *opts, int64
   wave = std::min<int64_t>(wave, std::min<int64_t>(n_boxes, 65535));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int nwaves = (int)((n_boxes + wave - 1) / wave);
+  // Per-neuron plans in a graph: the device lists every class the rules can
+  // give (when they are few), so the wave needs no host round trip.
+  bool graph = opts->graph && !op && (p.mode == BERN_PLAN_PLAIN || p.dev_ok);
+  const DevClasses *dc = graph && p.mode != BERN_PLAN_PLAIN ? &p.dc : nullptr;
+  if (dc) {
+    // every class's index tables before the capture (device allocations);
+    // a class whose tables exceed their limits leaves the run to the host
+    // classes, which build only those of the classes that occur
+    for (int i = 0; i < p.H && dc; ++i) {
+      LayerTables lt;
+      bool ok = true;
+      for (int d : dc->din[i]) ok = ok && layer_tables(net, d, p.Lmax, false, lt) == BERN_OK;
+      const bool lin = i < p.H - 1 && p.lin > 0 && (i + 1) % p.lin == 0;
+      for (size_t k = 0; i < p.H - 1 && k < dc->pairs[i].size(); ++k) {
+        const auto &pr = dc->pairs[i][k];
+        ok = ok && layer_tables(net, pr.first, class_order(p, pr.first, pr.second), true, lt) == BERN_OK;
+        if (lin && pr.second >= 1) ok = ok && layer_tables(net, pr.second, p.Lmax, false, lt) == BERN_OK;
+      }
+      if (!ok) {
+        dc = nullptr;
+        graph = false;
+      }
+    }
+  }
   auto run_all = [&](hipStream_t rs) -> bern_status {
     if (opts->counters) {
       ProfScope ps(kProfMisc, rs, 0.0);
@@ -1243,17 +1459,18 @@ static bern_status bounds_impl(const bern_net *net, const bern_opts *opts, int64
                                plan ? plan + b0 * net->nh : nullptr, neuron_lo ? neuron_lo + b0 * net->nh : nullptr,
                                neuron_hi ? neuron_hi + b0 * net->nh : nullptr, out_lo + b0 * net->o,
                                out_hi + b0 * net->o, used_plan ? used_plan + b0 * net->nh : nullptr,
-                               reinterpret_cast<char *>(workspace), rs, op);
+                               reinterpret_cast<char *>(workspace), rs, op, dc);
       if (r != BERN_OK) return r;
     }
     return BERN_OK;
   };
-  // Runs with no host round trip (the plain rule) can be captured once and
-  // replayed as one graph launch; plans with per-neuron degrees read every
-  // box's degree back once per hidden layer and always run eagerly.
-  if (opts->graph && p.mode == BERN_PLAN_PLAIN && !op) {
+  // Runs with no host round trip (the plain rule, or per-neuron plans with
+  // device classes) are captured once per argument set and replayed as one
+  // graph launch; per-neuron plans otherwise read every box's degree back
+  // once per hidden layer and run eagerly.
+  if (graph) {
     // index tables are built (device allocations) before any capture
-    for (int i = 0; i < p.H; ++i) {
+    for (int i = 0; i < p.H && !dc; ++i) {
       LayerTables lt;
       st = layer_tables(net, p.Dpre[i], p.Lmax, i < p.H - 1, lt);
       if (st != BERN_OK) return st;
@@ -1266,7 +1483,8 @@ static bern_status bounds_impl(const bern_net *net, const bern_opts *opts, int64
                    {(uint64_t)(uintptr_t)box_lo, (uint64_t)(uintptr_t)box_hi, (uint64_t)(uintptr_t)neuron_lo,
                     (uint64_t)(uintptr_t)neuron_hi, (uint64_t)(uintptr_t)out_lo, (uint64_t)(uintptr_t)out_hi,
                     (uint64_t)(uintptr_t)used_plan, (uint64_t)(uintptr_t)workspace, (uint64_t)ws_bytes,
-                    (uint64_t)wave},
+                    (uint64_t)wave, (uint64_t)opts->plan, (uint64_t)(uintptr_t)plan,
+                    (uint64_t)(uintptr_t)(opts->pred ? opts->pred->params : nullptr)},
                    run_all, s);
   } else {
     st = run_all(s);
@@ -1279,6 +1497,8 @@ static bern_status bounds_impl(const bern_net *net, const bern_opts *opts, int64
     stats->out_degree = p.Dpre[p.H - 1];
     stats->lin_layers = p.lin_layers;
     stats->workspace_used = per_box * (size_t)wave;
+    stats->graph = graph ? 1 : 0;
+    stats->device_classes = dc ? 1 : 0;
     stats->enqueue_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_enter).count();
   }

@@ -62,6 +62,21 @@ __host__ __device__ inline int64_t ipow(int64_t b, int e) {
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Launches whose box count lives on the device (a device-side
+// classification wrote it to `dcount`): the host only knows the upper bound
+// `nboxes`, the grid covers at most kDevGrid blocks along the box dimension,
+// and the kernels' blocks loop over the launch's items. Without a device
+// count every block takes one item, as the grid covers them all.
+constexpr int64_t kDevGrid = 4096;
+template <class A>
+__device__ __forceinline__ int64_t launch_boxes(const A &a) {
+  return a.dcount ? min((int64_t)*a.dcount, a.nboxes) : a.nboxes;
+}
+inline int64_t dev_grid(int64_t blocks, const int *dcount, int64_t per = 1) {
+  const int64_t cap = std::max<int64_t>(1, kDevGrid / std::max<int64_t>(1, per));
+  return dcount && blocks > cap ? cap : blocks;
+}
+
 // What the library knows about one hidden neuron of one box after its
 // pre-activation bounds were read (Step 1) and its rule chosen (Step 2).
 // FP32 mode: every stored polynomial p~ carries a radius eps such that the
@@ -195,6 +210,7 @@ struct GemmArgs {
   int64_t rpart_slot;             //   sums of |fl32(y) - y| per coefficient block
   int64_t cblocks;                // coefficient blocks of the launch (set by the launcher)
   Tune tune;
+  const int *dcount = nullptr;    // device count of the launch's boxes (nboxes: its upper bound)
 };
 int64_t gemm_cblocks(int64_t C);
 hipError_t launch_gemm(const GemmArgs &a, hipStream_t s);
@@ -250,6 +266,7 @@ struct ConvertArgs {
   // compile-time kernel
   const int *plist;
   int plist_len;
+  const int *dcount = nullptr;    // device count of the launch's boxes (nboxes: its upper bound)
 };
 hipError_t launch_convert(const ConvertArgs &a, hipStream_t s);
 
@@ -309,6 +326,7 @@ struct ComposeArgs {
   int64_t live_ld;
   int lin;                        // the layer was linearised: every neuron that is not inactive
                                   // holds a full degree-1 post tensor (live lists, Lin launchers)
+  const int *dcount = nullptr;    // device count of the launch's boxes (nboxes: its upper bound)
 };
 hipError_t launch_compose(const ComposeArgs &a, hipStream_t s);
 // The input lists (ComposeArgs::live) of a.nboxes boxes (bids, h, recs,

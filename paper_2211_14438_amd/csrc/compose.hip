@@ -99,59 +99,51 @@ __device__ void wave_partials(const ComposeArgs &a, int64_t it, double r, double
   }
 }
 
-// The item of the calling wave: four waves per block, items in order of
-// (launch box, neuron, bound), `chunks` consecutive waves per item (chunk
-// index in `c`); false past the end.
-__device__ inline bool wave_item(const ComposeArgs &a, int64_t &g, int &j, int &s, int chunks = 1, int *c = nullptr) {
-  int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (c) {
-    *c = (int)(w % chunks);
-    w /= chunks;
-  }
-  const int64_t per = (int64_t)a.h * a.nbounds;
-  if (w >= a.nboxes * per) return false;
-  g = w / per;
-  const int rest = (int)(w - g * per);
-  j = rest / a.nbounds;
-  s = rest - j * a.nbounds;
-  return true;
+// Items of a launch are (launch box, neuron, bound) in that order; the boxes
+// are a.nboxes, or the count a.dcount reads from device memory.
+__device__ inline int64_t launch_items(const ComposeArgs &a) {
+  return launch_boxes(a) * (int64_t)a.h * a.nbounds;
 }
 
-// Many items, few of which need a kernel's work: a wave then takes a.group
-// (<= 64) consecutive items (`chunks` waves per group, chunk index c), reads
-// their kinds at once and runs f(g, j, s, c) for those that pass
-// need(kind, s), in order. Without grouping (a.group <= 1) every wave has its own item, as in
-// wave_item. Either way an item's work is the same.
-
+// Every item of the launch with work to do: a wave takes `chunks`
+// consecutive wave slots per item (chunk index c), one item after another
+// over a grid that may hold fewer waves than items, and runs f(g, j, s, c)
+// for each item that passes need(kind, s). With grouping (a.group > 1, at
+// most 64) a wave slot covers a.group consecutive items, whose kinds it reads
+// at once, and runs those that pass in order. Either way an item's work is
+// the same.
 template <class Need, class F>
 __device__ inline void for_wave_items(const ComposeArgs &a, int chunks, Need need, F f) {
-  if (a.group <= 1) {
-    int64_t g;
-    int j, s, c = 0;
-    if (!wave_item(a, g, j, s, chunks, &c)) return;
-    if (need(a.recs[wave_box(a, g) * a.h + j].kind, s)) f(g, j, s, c);
-    return;
-  }
-  int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int c = (int)(w % chunks);
-  w /= chunks;
-  const int64_t per = (int64_t)a.h * a.nbounds, total = a.nboxes * per;
-  const int64_t i0 = w * a.group;
-  if (i0 >= total) return;
+  const int64_t per = (int64_t)a.h * a.nbounds, total = launch_items(a);
+  const int grp = a.group > 1 ? a.group : 1;
+  const int64_t slots = (total + grp - 1) / grp * chunks;
+  const int64_t stride = (int64_t)gridDim.x * (blockDim.x >> 6);
   const int lane = threadIdx.x & 63;
-  bool mine = false;
-  if (lane < a.group && i0 + lane < total) {
-    const int64_t it = i0 + lane, g = it / per;
-    const int rest = (int)(it - g * per);
-    mine = need(a.recs[wave_box(a, g) * a.h + rest / a.nbounds].kind, rest % a.nbounds);
-  }
-  unsigned long long todo = __ballot(mine);
-  while (todo) {
-    const int b = __ffsll((long long)todo) - 1;
-    todo &= todo - 1;
-    const int64_t it = i0 + b, g = it / per;
-    const int rest = (int)(it - g * per);
-    f(g, rest / a.nbounds, rest % a.nbounds, c);
+  for (int64_t w0 = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w0 < slots; w0 += stride) {
+    const int c = (int)(w0 % chunks);
+    const int64_t w = w0 / chunks;
+    if (grp == 1) {
+      const int64_t g = w / per;
+      const int rest = (int)(w - g * per);
+      const int j = rest / a.nbounds, s = rest - j * a.nbounds;
+      if (need(a.recs[wave_box(a, g) * a.h + j].kind, s)) f(g, j, s, c);
+      continue;
+    }
+    const int64_t i0 = w * grp;
+    bool mine = false;
+    if (lane < grp && i0 + lane < total) {
+      const int64_t it = i0 + lane, g = it / per;
+      const int rest = (int)(it - g * per);
+      mine = need(a.recs[wave_box(a, g) * a.h + rest / a.nbounds].kind, rest % a.nbounds);
+    }
+    unsigned long long todo = __ballot(mine);
+    while (todo) {
+      const int b = __ffsll((long long)todo) - 1;
+      todo &= todo - 1;
+      const int64_t it = i0 + b, g = it / per;
+      const int rest = (int)(it - g * per);
+      f(g, rest / a.nbounds, rest % a.nbounds, c);
+    }
   }
 }
 
@@ -655,10 +647,13 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) compose_hz_kernel(ComposeArgs a, int m) {
   extern __shared__ double nu[];
   const int j = blockIdx.y / a.nbounds, s = blockIdx.y % a.nbounds;
-  const int64_t g = blockIdx.z, box = wave_box(a, g);
+  const int64_t nb = launch_boxes(a);
+  for (int64_t g = blockIdx.z; g < nb; g += gridDim.z) {
+  const int64_t box = wave_box(a, g);
   const NeuronRec &r = a.recs[box * a.h + j];
   const int L = r.kind;
-  if (L < 3 || m > L - 1) return;
+  if (L < 3 || m > L - 1) continue;  // uniform over the block
+  __syncthreads();                    // the previous item's reads of nu are done
   load_nu(a, in_tensor<T>(a, box, j, s), nu_of(a, &r, s), nu);
   const bool last = (m == L - 1);
   const int64_t it = item_of(a, g, j, s);
@@ -689,6 +684,7 @@ __global__ void __launch_bounds__(kBlock) compose_hz_kernel(ComposeArgs a, int m
       qcur[K] = v;
   }
   if (last && a.part) block_partials(a, it, rsum, l1sum);
+  }
 }
 
 // ---------------------------------------------- post radii (FP32 mode)
@@ -769,23 +765,27 @@ __global__ void post_radii_kernel(ComposeArgs a, NeuronRec *recs) {
 // the total-degree layout is the elevation to Dout (Prop. 4).
 template <typename T>
 __global__ void __launch_bounds__(64) lin_stage_kernel(ComposeArgs a) {
-  int64_t g;
-  int j, s;
-  if (!wave_item(a, g, j, s)) return;
   const int lane = threadIdx.x & 63;
+  const int64_t items = launch_items(a);
+  for (int64_t w = blockIdx.x; w < items; w += gridDim.x) {
+  const int64_t g = w / ((int64_t)a.h * a.nbounds);
+  const int rest = (int)(w - g * a.h * a.nbounds);
+  const int j = rest / a.nbounds, s = rest - j * a.nbounds;
   const int64_t box = wave_box(a, g);
   const int kind = a.recs[box * a.h + j].kind;
-  if (kind >= 2) return;
+  if (kind >= 2) continue;
   T *out = out_tensor<T>(a, box, j, s);
   int64_t from = 0;
-  if (kind == kActive) {
+  if (kind == kActive) {  // degree Din <= Dout (the box's post degree is the largest)
     const T *p = in_tensor<T>(a, box, j, s);
-    for (int64_t I = lane; I < a.Cin; I += 64) out[I] = p[I];
-    from = a.Cin;
+    const int64_t cc = min(a.Cin, a.Cout);
+    for (int64_t I = lane; I < cc; I += 64) out[I] = p[I];
+    from = cc;
   } else if (kind == 1 || kind == kFallback) {
     from = a.Cs;
   }
   for (int64_t I = from + lane; I < a.Cout; I += 64) out[I] = (T)0;
+  }
 }
 
 // One thread per (box, neuron): the linearised posts (fbU, fbL) stored at
@@ -827,21 +827,23 @@ __global__ void __launch_bounds__(kBlock) lin_scatter_kernel(ComposeArgs a, Neur
 
 hipError_t launch_lin_stage(const ComposeArgs &a_in, hipStream_t s) {
   if (a_in.nboxes < 1) return hipSuccess;
-  if (a_in.Cin > a_in.Cout || a_in.Cs > a_in.Cout || a_in.nbounds != 2) return hipErrorInvalidValue;
+  // a class below its pre degree (Dout < Din) holds fallback and inactive
+  // neurons only
+  if (a_in.Cs > a_in.Cout || a_in.nbounds != 2) return hipErrorInvalidValue;
   ComposeArgs a = a_in;
   a.group = 1;
   const int64_t items = a.nboxes * a.h * a.nbounds;
   ProfScope ps(kProfLin, s, 0.0);
   if (a.fp64)
-    hipLaunchKernelGGL(lin_stage_kernel<double>, dim3((unsigned)items), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(lin_stage_kernel<double>, dim3((unsigned)dev_grid(items, a.dcount)), dim3(64), 0, s, a);
   else
-    hipLaunchKernelGGL(lin_stage_kernel<float>, dim3((unsigned)items), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(lin_stage_kernel<float>, dim3((unsigned)dev_grid(items, a.dcount)), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_lin_scatter(const ComposeArgs &a, hipStream_t s) {
   if (a.nboxes < 1) return hipSuccess;
-  if (!a.recs || !a.post) return hipErrorInvalidValue;
+  if (!a.recs || !a.post || a.dcount) return hipErrorInvalidValue;
   const unsigned blocks = (unsigned)((a.nboxes * a.h + kBlock - 1) / kBlock);
   ProfScope ps(kProfLin, s, 0.0);
   if (a.fp64)
@@ -958,6 +960,8 @@ constexpr int kComposeWaves = 1;
 template <typename T>
 static hipError_t compose_all(const ComposeArgs &a_in, hipStream_t s) {
   ComposeArgs a = a_in;
+  // with a device count the lists and radii are the caller's, over all boxes
+  if (a.dcount && (!a.lists_ready || !a.radii_later)) return hipErrorInvalidValue;
   const unsigned gx = (unsigned)a.nbx;
   // many items: a wave takes a group of items and reads their kinds at
   // once; 64 for the scatter (its items are few and light), 8 for the
@@ -975,7 +979,8 @@ static hipError_t compose_all(const ComposeArgs &a_in, hipStream_t s) {
     ComposeArgs ag = a;
     ag.group = group ? 16 : 1;
     const int64_t waves = (items_all + ag.group - 1) / ag.group;
-    hipLaunchKernelGGL(compose_scatter_kernel<T>, dim3((unsigned)((waves + kComposeWaves - 1) / kComposeWaves)),
+    hipLaunchKernelGGL(compose_scatter_kernel<T>,
+                       dim3((unsigned)dev_grid((waves + kComposeWaves - 1) / kComposeWaves, a.dcount)),
                        dim3(64 * kComposeWaves), 0, s, ag);
     RET_IF(hipGetLastError());
   }
@@ -992,12 +997,11 @@ static hipError_t compose_all(const ComposeArgs &a_in, hipStream_t s) {
     ag.group = group ? 8 : 1;
     const int64_t waves = (items_all + ag.group - 1) / ag.group * a.nbx;
     ProfScope ps(kProfComposeSquare, s, 0.0);
+    const dim3 grid((unsigned)dev_grid((waves + kComposeWaves - 1) / kComposeWaves, a.dcount));
     if (pair)
-      hipLaunchKernelGGL((compose_sq2_kernel<T, true>), dim3((unsigned)((waves + kComposeWaves - 1) / kComposeWaves)),
-                         dim3(64 * kComposeWaves), klds, s, ag);
+      hipLaunchKernelGGL((compose_sq2_kernel<T, true>), grid, dim3(64 * kComposeWaves), klds, s, ag);
     else
-      hipLaunchKernelGGL((compose_sq2_kernel<T, false>), dim3((unsigned)((waves + kComposeWaves - 1) / kComposeWaves)),
-                         dim3(64 * kComposeWaves), klds, s, ag);
+      hipLaunchKernelGGL((compose_sq2_kernel<T, false>), grid, dim3(64 * kComposeWaves), klds, s, ag);
     RET_IF(hipGetLastError());
   }
   if (a.Lmax >= 3) {
@@ -1005,7 +1009,7 @@ static hipError_t compose_all(const ComposeArgs &a_in, hipStream_t s) {
                                (int)lds));
     for (int m = 1; m <= a.Lmax - 1; ++m) {
       if (!a.hz_off[m]) return hipErrorInvalidValue;
-      dim3 grid(gx, (unsigned)(a.h * a.nbounds), (unsigned)a.nboxes);
+      dim3 grid(gx, (unsigned)(a.h * a.nbounds), (unsigned)dev_grid(a.nboxes, a.dcount, (int64_t)gx * a.h * a.nbounds));
       ProfScope ps(kProfComposeHorner, s, 0.0);
       hipLaunchKernelGGL(compose_hz_kernel<T>, grid, dim3(kComposeThreads), lds, s, a, m);
       RET_IF(hipGetLastError());
@@ -1016,7 +1020,7 @@ static hipError_t compose_all(const ComposeArgs &a_in, hipStream_t s) {
 }
 
 hipError_t launch_post_radii(const ComposeArgs &a, hipStream_t s) {
-  if (!a.part || !a.recs) return hipErrorInvalidValue;
+  if (!a.part || !a.recs || a.dcount) return hipErrorInvalidValue;
   ProfScope ps(kProfMisc, s, 0.0);
   hipLaunchKernelGGL(post_radii_kernel, dim3((unsigned)((a.nboxes * a.h + 63) / 64)), dim3(64), 0, s, a,
                      const_cast<NeuronRec *>(a.recs));
@@ -1024,7 +1028,7 @@ hipError_t launch_post_radii(const ComposeArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_live(const ComposeArgs &a, hipStream_t s) {
-  if (!a.live || a.nboxes < 1) return hipErrorInvalidValue;
+  if (!a.live || a.nboxes < 1 || a.dcount) return hipErrorInvalidValue;
   ProfScope ps(kProfMisc, s, 0.0);
   hipLaunchKernelGGL(live_kernel, dim3((unsigned)((a.nboxes + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), 0, s,
                      a);

@@ -319,7 +319,8 @@ __global__ void __launch_bounds__(kBlock) convert_small_kernel(ConvertArgs a) {
   double *red = tab + D1 * D1;
   __shared__ double fit[2][kMaxInputs + 1];
   __shared__ double ext[4];  // rmaxU, rminU, rmaxL, rminL
-  const int64_t item = blockIdx.x;  // launch box * h + j
+  const int64_t items = launch_boxes(a) * a.h;
+  for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {  // launch box * h + j
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
   const int j = (int)(item % a.h);
   fill_table(tab, a.D);
@@ -367,6 +368,8 @@ __global__ void __launch_bounds__(kBlock) convert_small_kernel(ConvertArgs a) {
       if (a.out_hi) a.out_hi[box * a.ld_out + a.col0 + j] = hi;
       finish_neuron(a, box, j, lo, hi, epsU, epsL, l1s[0], l1s[1], fit, ext, want_fit);
     }
+  }
+  __syncthreads();  // the next item rewrites the shared tensor, fits and extrema
   }
 }
 
@@ -452,8 +455,9 @@ __global__ void __launch_bounds__(kBlock) convert_wave_kernel(ConvertArgs a) {
   double *tab = lds;
   double *tw = lds + D1 * D1 + (int64_t)wv * 2 * C;  // [2][C]: lower, upper
   fill_table(tab, a.D);
-  const int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + wv;
-  if (item >= a.nboxes * a.h) return;
+  const int64_t items = launch_boxes(a) * a.h;
+  for (int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + wv; item < items;
+       item += (int64_t)gridDim.x * (kBlock / 64)) {
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
   const int j = (int)(item % a.h);
   double ext[2], l1s[2];
@@ -494,6 +498,8 @@ __global__ void __launch_bounds__(kBlock) convert_wave_kernel(ConvertArgs a) {
       if (a.out_hi) a.out_hi[box * a.ld_out + a.col0 + j] = hi;
       finish_neuron(a, box, j, lo, hi, epsU, epsL, l1s[0], l1s[1], fit, fx, want_fit);
     }
+  }
+  wave_sync();  // the wave's next item rewrites its slice
   }
 }
 
@@ -1019,11 +1025,14 @@ __global__ void __launch_bounds__(kBlock, 6) convert_wave_t(ConvertArgs a) {
   const int C = (int)a.C;
   const int *pl = stage_prefixes(a, reinterpret_cast<int *>(lds));
   double *tw = lds + (a.plist_len + 1) / 2 + (int64_t)wv * wave_slice_doubles(C);
-  const int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + wv;
-  if (item >= a.nboxes * a.h) return;
-  const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
-  const WaveTeam tmw{tm.tid, tw};
-  readoff_pair<D, T>(a, tmw, true, tm.tid, tw + kRowScratch, tw + kRowScratch + C, pl, box, (int)(item % a.h));
+  const int64_t items = launch_boxes(a) * a.h;
+  for (int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + wv; item < items;
+       item += (int64_t)gridDim.x * (kBlock / 64)) {
+    const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
+    const WaveTeam tmw{tm.tid, tw};
+    readoff_pair<D, T>(a, tmw, true, tm.tid, tw + kRowScratch, tw + kRowScratch + C, pl, box, (int)(item % a.h));
+    wave_sync();
+  }
 }
 
 // One block per (box, neuron) for tensors up to kSmallLds coefficients, one
@@ -1035,9 +1044,12 @@ __global__ void __launch_bounds__(1024) convert_block_t(ConvertArgs a) {
   const BlockTeam tm{(int)threadIdx.x, (int)blockDim.x, red};
   const int *pl = stage_prefixes(a, reinterpret_cast<int *>(lds));
   double *t = lds + (a.plist_len + 1) / 2;
-  const int64_t item = blockIdx.x;
-  const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
-  readoff_pair<D, T>(a, tm, threadIdx.x < 64, (int)(threadIdx.x & 63), t, t + a.C, pl, box, (int)(item % a.h));
+  const int64_t items = launch_boxes(a) * a.h;
+  for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
+    const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
+    readoff_pair<D, T>(a, tm, threadIdx.x < 64, (int)(threadIdx.x & 63), t, t + a.C, pl, box, (int)(item % a.h));
+    __syncthreads();
+  }
 }
 
 // Degree 1 (every first hidden layer, and neurons whose plan keeps degree
@@ -1064,8 +1076,9 @@ __global__ void __launch_bounds__(kBlock) convert_affine_kernel(ConvertArgs a) {
   constexpr int kAffLanes = kL;
   constexpr int kR = (kMaxInputs + 1 + kL - 1) / kL;  // coefficient slots per lane
   const int l = threadIdx.x % kAffLanes;
-  const int64_t item = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kAffLanes;
-  if (item >= a.nboxes * a.h) return;  // whole teams leave together
+  const int64_t items = launch_boxes(a) * a.h;
+  for (int64_t item = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kAffLanes; item < items;
+       item += (int64_t)gridDim.x * (blockDim.x / kAffLanes)) {  // whole teams leave together
   const int S = (int)a.S;
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
   const int j = (int)(item % a.h);
@@ -1097,7 +1110,7 @@ __global__ void __launch_bounds__(kBlock) convert_affine_kernel(ConvertArgs a) {
       rec.fbpadU = a.fp64 ? 0.0 : rec.padU;
       rec.fbpadL = a.fp64 ? 0.0 : rec.padL;
     }
-    return;
+    continue;
   }
   double epsU = 0.0, epsL = 0.0;
   if (!a.fp64) {
@@ -1181,6 +1194,7 @@ __global__ void __launch_bounds__(kBlock) convert_affine_kernel(ConvertArgs a) {
   }
   // an unfitted neuron's fit fields are never read (fitted == 0)
   if (l == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted, true);
+  }
 }
 
 // Executed-work counts of the read-off kernels, for the profiler (host).
@@ -1261,10 +1275,10 @@ static hipError_t launch_affine(const ConvertArgs &a, hipStream_t s) {
                (double)a.nboxes * a.h * affine_ops(a));
   const int64_t teams = a.nboxes * a.h;
   if (a.S <= 8) {
-    hipLaunchKernelGGL((convert_affine_kernel<T, 8>), dim3((unsigned)((teams * 8 + kBlock - 1) / kBlock)),
+    hipLaunchKernelGGL((convert_affine_kernel<T, 8>), dim3((unsigned)dev_grid((teams * 8 + kBlock - 1) / kBlock, a.dcount)),
                        dim3(kBlock), 0, s, a);
   } else {
-    hipLaunchKernelGGL((convert_affine_kernel<T, 16>), dim3((unsigned)((teams * 16 + kBlock - 1) / kBlock)),
+    hipLaunchKernelGGL((convert_affine_kernel<T, 16>), dim3((unsigned)dev_grid((teams * 16 + kBlock - 1) / kBlock, a.dcount)),
                        dim3(kBlock), 0, s, a);
   }
   return hipGetLastError();
@@ -1470,7 +1484,9 @@ __global__ void __launch_bounds__(1024) convert_tree_t(ConvertArgs a, TreePlan t
 #pragma unroll
     for (int i = 0; i < D1 * D1; ++i) tab[i] = R.v[i / D1][i % D1];
   }
-  const int64_t tensor = blockIdx.y;
+  const int64_t tensors = launch_boxes(a) * a.h * 2;
+  for (int64_t tensor = blockIdx.y; tensor < tensors; tensor += gridDim.y) {
+  __syncthreads();  // the previous tensor's last reads of the root and chain are done
   const int side = (int)(tensor & 1);  // 1: lower bound tensor (minimum), 0: upper (maximum)
   const int64_t gb = tensor / (2 * a.h), rest = tensor % (2 * a.h);
   const int64_t box = a.bids ? a.bids[gb] : gb;
@@ -1551,6 +1567,7 @@ __global__ void __launch_bounds__(1024) convert_tree_t(ConvertArgs a, TreePlan t
   }
   const double v = side ? bt.min(ext) : bt.max(ext);
   if (tid == 0) partial[tensor * tp.nchunk + blockIdx.x] = v;
+  }
 }
 
 template <typename T, int D>
@@ -1559,7 +1576,7 @@ static hipError_t launch_tree_t(const ConvertArgs &a, const TreePlan &tp, size_t
   constexpr int M = tree_tile_axes(D);
   RET_IF(hipFuncSetAttribute((const void *)convert_tree_t<D, M, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)lds));
-  hipLaunchKernelGGL((convert_tree_t<D, M, T>), dim3((unsigned)tp.nchunk, (unsigned)(a.nboxes * a.h * 2)),
+  hipLaunchKernelGGL((convert_tree_t<D, M, T>), dim3((unsigned)tp.nchunk, (unsigned)dev_grid(a.nboxes * a.h * 2, a.dcount)),
                      dim3((unsigned)tp.threads), lds, s, a, tp, partial, l1part);
   return hipGetLastError();
 }
@@ -1861,19 +1878,29 @@ __global__ void __launch_bounds__(kWave ? 64 * kNTeams : 1024) convert_ntree_t(C
   }
   __syncthreads();
   double *slices = tab + D1 * D1;  // per team: fits (upper, lower), then the two trees
+  const int64_t items = launch_boxes(a) * a.h;
   if (kWave) {
     const int wv = threadIdx.x >> 6;
-    const int64_t item = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
-    if (item >= a.nboxes * a.h) return;
     double *slice = slices + (int64_t)wv * (kRowScratch + 2 * (kMaxInputs + 1) + 2 * tp.area);
     const WaveTeam tm{(int)(threadIdx.x & 63), slice};
-    ntree_neuron<D, M, T, true>(a, tp, tm, tb, tab, slice + kRowScratch, item);
+    for (int64_t item = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv; item < items;
+         item += (int64_t)gridDim.x * (blockDim.x >> 6)) {
+      ntree_neuron<D, M, T, true>(a, tp, tm, tb, tab, slice + kRowScratch, item);
+      tm.sync();  // the wave's next item rewrites its slice
+    }
   } else {
     const BlockTeam tm{(int)threadIdx.x, (int)blockDim.x, red};
-    if constexpr (kSide)
-      ntree_output_side<D, M, T>(a, tp, tm, tb, tab, slices, blockIdx.x >> 1, (int)(blockIdx.x & 1));
-    else
-      ntree_neuron<D, M, T, false>(a, tp, tm, tb, tab, slices, blockIdx.x);
+    if constexpr (kSide) {
+      for (int64_t vb = blockIdx.x; vb < 2 * items; vb += gridDim.x) {
+        ntree_output_side<D, M, T>(a, tp, tm, tb, tab, slices, vb >> 1, (int)(vb & 1));
+        __syncthreads();
+      }
+    } else {
+      for (int64_t vb = blockIdx.x; vb < items; vb += gridDim.x) {
+        ntree_neuron<D, M, T, false>(a, tp, tm, tb, tab, slices, vb);
+        __syncthreads();
+      }
+    }
   }
 }
 
@@ -1897,7 +1924,7 @@ static bool launch_ntree(const ConvertArgs &a, hipStream_t s, bool wave_team, hi
       err = hipFuncSetAttribute((const void *)convert_ntree_t<D, M, T, true>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (err != hipSuccess) return true;
-      hipLaunchKernelGGL((convert_ntree_t<D, M, T, true>), dim3((unsigned)((items + kNTeams - 1) / kNTeams)),
+      hipLaunchKernelGGL((convert_ntree_t<D, M, T, true>), dim3((unsigned)dev_grid((items + kNTeams - 1) / kNTeams, a.dcount)),
                          dim3(64 * kNTeams), lds, s, a, tp);
       err = hipGetLastError();
       return true;
@@ -1910,7 +1937,7 @@ static bool launch_ntree(const ConvertArgs &a, hipStream_t s, bool wave_team, hi
       err = hipFuncSetAttribute((const void *)convert_ntree_t<D, M, T, false, true>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)l1);
       if (err != hipSuccess) return true;
-      hipLaunchKernelGGL((convert_ntree_t<D, M, T, false, true>), dim3((unsigned)(items * 2)), dim3((unsigned)t1.threads),
+      hipLaunchKernelGGL((convert_ntree_t<D, M, T, false, true>), dim3((unsigned)dev_grid(items * 2, a.dcount)), dim3((unsigned)t1.threads),
                          l1, s, a, t1);
       err = hipGetLastError();
       return true;
@@ -1920,7 +1947,7 @@ static bool launch_ntree(const ConvertArgs &a, hipStream_t s, bool wave_team, hi
   err = hipFuncSetAttribute((const void *)convert_ntree_t<D, M, T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
   if (err != hipSuccess) return true;
-  hipLaunchKernelGGL((convert_ntree_t<D, M, T, false>), dim3((unsigned)items), dim3((unsigned)tp.threads), lds, s, a,
+  hipLaunchKernelGGL((convert_ntree_t<D, M, T, false>), dim3((unsigned)dev_grid(items, a.dcount)), dim3((unsigned)tp.threads), lds, s, a,
                      tp);
   err = hipGetLastError();
   return true;
@@ -1946,7 +1973,7 @@ static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
       ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4),
                    (double)a.nboxes * a.h * 2 * a.n * a.C * (a.D + 2));
       const int64_t items = a.nboxes * a.h;
-      hipLaunchKernelGGL((convert_wave_t<D, T>), dim3((unsigned)((items + kBlock / 64 - 1) / (kBlock / 64))),
+      hipLaunchKernelGGL((convert_wave_t<D, T>), dim3((unsigned)dev_grid((items + kBlock / 64 - 1) / (kBlock / 64), a.dcount)),
                          dim3(kBlock), lds, s, a);
       return hipGetLastError();
     }
@@ -1960,7 +1987,7 @@ static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
                                                                             : (lds > 40 * 1024 ? 1024 : 256);
     ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4),
                  (double)a.nboxes * a.h * 2 * a.n * a.C * (a.D + 2));
-    hipLaunchKernelGGL((convert_block_t<D, T>), dim3((unsigned)(a.nboxes * a.h)), dim3(threads), lds, s, a);
+    hipLaunchKernelGGL((convert_block_t<D, T>), dim3((unsigned)dev_grid(a.nboxes * a.h, a.dcount)), dim3(threads), lds, s, a);
     return hipGetLastError();
   }
 }
@@ -2019,8 +2046,9 @@ __global__ void __launch_bounds__(kBlock) convert_passA_kernel(ConvertArgs a, Sp
   const int D1 = a.D + 1;
   double *t = lds;
   double *tab = lds + sp.Ci;
-  const int64_t tensor = blockIdx.y;  // (box*h + j)*2 + s
   const int64_t o = blockIdx.x;
+  const int64_t tensors = launch_boxes(a) * a.h * 2;
+  for (int64_t tensor = blockIdx.y; tensor < tensors; tensor += gridDim.y) {  // (box*h + j)*2 + s
   fill_table(tab, a.D);
   double *red = tab + D1 * D1;
   const int64_t gb = tensor / (2 * a.h), rest = tensor % (2 * a.h);
@@ -2043,6 +2071,8 @@ __global__ void __launch_bounds__(kBlock) convert_passA_kernel(ConvertArgs a, Sp
   double *q = a.scratch + tensor * a.C + o * sp.Ci;
   for (int64_t i = threadIdx.x; i < sp.Ci; i += blockDim.x) q[i] = t[i];
   if (threadIdx.x == 0) l1part[tensor * sp.Co + o] = l1;
+  __syncthreads();
+  }
 }
 
 // Pass B: one block per (tensor, column chunk): convert the n-m leading axes
@@ -2054,7 +2084,8 @@ __global__ void __launch_bounds__(kBlock) convert_passB_kernel(ConvertArgs a, Sp
   double *t = lds;                      // [Co][Q]
   double *tab = lds + sp.Co * sp.Q;
   double *red = tab + D1 * D1;
-  const int64_t tensor = blockIdx.y;
+  const int64_t tensors = launch_boxes(a) * a.h * 2;
+  for (int64_t tensor = blockIdx.y; tensor < tensors; tensor += gridDim.y) {
   const int s = (int)(tensor & 1);
   const int64_t q0 = (int64_t)blockIdx.x * sp.Q;
   const int64_t qn = min(sp.Q, sp.Ci - q0);
@@ -2087,14 +2118,17 @@ __global__ void __launch_bounds__(kBlock) convert_passB_kernel(ConvertArgs a, Sp
   }
   v = s ? block_reduce(v, OpMin(), red) : block_reduce(v, OpMax(), red);
   if (threadIdx.x == 0) partial[tensor * sp.nchunk + blockIdx.x] = v;
+  __syncthreads();
+  }
 }
 
 // Fold the per-chunk extrema of both bounds of one neuron: one wave each.
 __global__ void __launch_bounds__(kBlock) convert_final_kernel(ConvertArgs a, Split sp, const double *partial,
                                                                const double *l1part) {
   const int lane = threadIdx.x & 63;
-  const int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  if (item >= a.nboxes * a.h) return;
+  const int64_t items = launch_boxes(a) * a.h;
+  for (int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); item < items;
+       item += (int64_t)gridDim.x * (kBlock / 64)) {
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
   const int j = (int)(item % a.h);
   double mn = INFINITY, mx = -INFINITY, l1U = 0.0, l1L = 0.0;
@@ -2113,13 +2147,15 @@ __global__ void __launch_bounds__(kBlock) convert_final_kernel(ConvertArgs a, Sp
   double lo, hi, epsU, epsL;
   padded_bounds(a, box, j, mn, mx, l1L, l1U, lane, 64, [](double v) { return wave_reduce(v, OpAdd()); }, lo, hi,
                 epsU, epsL);
-  if (lane != 0) return;
-  if (a.mode == 1) {
-    write_output(a, box, j, lo, hi, epsU, epsL);
-  } else {
-    if (a.out_lo) a.out_lo[box * a.ld_out + a.col0 + j] = lo;
-    if (a.out_hi) a.out_hi[box * a.ld_out + a.col0 + j] = hi;
-    finish_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, nullptr, nullptr, false);
+  if (lane == 0) {
+    if (a.mode == 1) {
+      write_output(a, box, j, lo, hi, epsU, epsL);
+    } else {
+      if (a.out_lo) a.out_lo[box * a.ld_out + a.col0 + j] = lo;
+      if (a.out_hi) a.out_hi[box * a.ld_out + a.col0 + j] = hi;
+      finish_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, nullptr, nullptr, false);
+    }
+  }
   }
 }
 
@@ -2327,7 +2363,8 @@ hipError_t launch_convert(const ConvertArgs &a_in, hipStream_t s) {
     ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4),
                  (double)a.nboxes * a.h * 2 * a.n * a.C * (a.D + 2));
     const int64_t items = a.nboxes * a.h;
-    hipLaunchKernelGGL(k, dim3((unsigned)((items + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), lds, s, a);
+    hipLaunchKernelGGL(k, dim3((unsigned)dev_grid((items + kBlock / 64 - 1) / (kBlock / 64), a.dcount)), dim3(kBlock),
+                       lds, s, a);
     return hipGetLastError();
   }
   if (use_small(a.C)) {
@@ -2336,7 +2373,7 @@ hipError_t launch_convert(const ConvertArgs &a_in, hipStream_t s) {
     RET_IF(hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4),
                  (double)a.nboxes * a.h * 2 * a.n * a.C * (a.D + 2));
-    hipLaunchKernelGGL(k, dim3((unsigned)(a.nboxes * a.h)), dim3(kBlock), lds, s, a);
+    hipLaunchKernelGGL(k, dim3((unsigned)dev_grid(a.nboxes * a.h, a.dcount)), dim3(kBlock), lds, s, a);
     return hipGetLastError();
   }
   const int64_t tensors = a.nboxes * a.h * 2;
@@ -2363,7 +2400,8 @@ hipError_t launch_convert(const ConvertArgs &a_in, hipStream_t s) {
     fsp.nchunk = tp.nchunk;
     fsp.Co = 1;
     ProfScope ps(kProfConvertFinal, s, (double)tensors * tp.nchunk * 8);
-    hipLaunchKernelGGL(convert_final_kernel, dim3((unsigned)((a.nboxes * a.h + 3) / 4)), dim3(kBlock), 0, s, b, fsp,
+    hipLaunchKernelGGL(convert_final_kernel, dim3((unsigned)dev_grid((a.nboxes * a.h + 3) / 4, a.dcount)), dim3(kBlock),
+                       0, s, b, fsp,
                        (const double *)partial, (const double *)l1part);
     return hipGetLastError();
   }
@@ -2378,18 +2416,21 @@ hipError_t launch_convert(const ConvertArgs &a_in, hipStream_t s) {
     auto k = a.fp64 ? convert_passA_kernel<double> : convert_passA_kernel<float>;
     RET_IF(hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     ProfScope ps(kProfConvertPassA, s, (double)tensors * (a.S * (a.fp64 ? 8 : 4) + a.C * 8));
-    hipLaunchKernelGGL(k, dim3((unsigned)sp.Co, (unsigned)tensors), dim3(kBlock), lds, s, a, sp, l1part);
+    hipLaunchKernelGGL(k, dim3((unsigned)sp.Co, (unsigned)dev_grid(tensors, a.dcount)), dim3(kBlock), lds, s, a, sp,
+                       l1part);
   }
   {
     const size_t lds = (sp.Co * sp.Q + D1 * D1 + 16) * sizeof(double);
     RET_IF(hipFuncSetAttribute((const void *)convert_passB_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     ProfScope ps(kProfConvertPassB, s, (double)tensors * a.C * 8);
-    hipLaunchKernelGGL(convert_passB_kernel, dim3((unsigned)sp.nchunk, (unsigned)tensors), dim3(kBlock), lds, s, a,
+    hipLaunchKernelGGL(convert_passB_kernel, dim3((unsigned)sp.nchunk, (unsigned)dev_grid(tensors, a.dcount)),
+                       dim3(kBlock), lds, s, a,
                        sp, partial);
   }
   {
     ProfScope ps(kProfConvertFinal, s, (double)tensors * sp.nchunk * 8);
-    hipLaunchKernelGGL(convert_final_kernel, dim3((unsigned)((a.nboxes * a.h + 3) / 4)), dim3(kBlock), 0, s, a, sp,
+    hipLaunchKernelGGL(convert_final_kernel, dim3((unsigned)dev_grid((a.nboxes * a.h + 3) / 4, a.dcount)), dim3(kBlock),
+                       0, s, a, sp,
                        (const double *)partial, (const double *)l1part);
   }
   return hipGetLastError();

@@ -67,3 +67,28 @@ def test_null_arguments_rejected():
     assert L.bern_poly_mul(0, 1, 1, 1, None, None, None, 1, None) == -1
     assert L.bern_relu_poly(1, 9, None, None, None, None, None) == -1
     assert L.bern_basis_minmax(2, 2, 0, None, 1, None, None, None, None, None, 0, None) == -1
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every option and result struct the binding marshals has the header's
+    size and field offsets (a C program built against the header prints them)."""
+    structs = {"bern_opts": B.bern_opts, "bern_stats": B.bern_stats, "bern_verify_result": B.bern_verify_result,
+               "bern_train_opts": B.bern_train_opts}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "bernnn.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    got = {}
+    for l in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        parts = l.split()
+        got[tuple(parts[:-1])] = int(parts[-1])
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert got[(name, f)] == getattr(cls, f).offset, (name, f)
