@@ -376,10 +376,14 @@ def main():
     # the timed region that gives `value` runs without per-launch events; the
     # kernel classes are then timed over the same number of steps with a pair
     # of HIP events around every launch (eagerly when graphs are replayed)
-    dt, _ = timed(kw, args.steps, False)
+    dt_graph, _ = timed(kw, args.steps, False)
     eager_kw = {k: v for k, v in kw.items() if k != "graph"}
     st = B.bounds(net, lo, hi, **kw)["stats"]
-    dt_eager = timed(eager_kw, args.steps, False)[0] if graph else dt
+    dt_eager = timed(eager_kw, args.steps, False)[0] if graph else dt_graph
+    # `value`: the faster of the two launch forms of the same work, both
+    # reported under "launch"
+    dt = min(dt_graph, dt_eager)
+    form = "graph" if graph and dt_graph <= dt_eager else "eager"
     _, prof = timed(eager_kw, args.steps, True)
     outs = kw["outputs"]
     ms_step = dt / args.steps * 1e3
@@ -397,6 +401,8 @@ def main():
         for psched in sorted({spec.get("plain_sched", "batched"), "batched"}):
             pkw = setup("plain", psched)
             pdt, _ = timed(pkw, psteps, False)
+            if pkw.get("graph"):  # the faster launch form, as for `value`
+                pdt = min(pdt, timed({k: v for k, v in pkw.items() if k != "graph"}, psteps, False)[0])
             pw = float((pkw["outputs"]["out_hi"] - pkw["outputs"]["out_lo"]).mean().item())
             lines[psched] = dict(form=f"plain order-{case.L} ({psched})", value=neurons * psteps / pdt,
                                  ms_per_step=pdt / psteps * 1e3, mean_output_width=pw)
@@ -456,8 +462,9 @@ def main():
         line["autotune"] = tuned
     line["kernel_timing"] = ("per-launch HIP events over a second timed region of the same steps" +
                              (", launched eagerly (value: one captured graph per pass)" if graph else ""))
-    line["launch"] = dict(graph=bool(st["graph"]), device_classes=bool(st["device_classes"]),
-                          eager_ms_per_step=dt_eager / args.steps * 1e3, graph_ms_per_step=ms_step if graph else None)
+    line["launch"] = dict(value_from=form, graph=bool(st["graph"]), device_classes=bool(st["device_classes"]),
+                          eager_ms_per_step=dt_eager / args.steps * 1e3,
+                          graph_ms_per_step=dt_graph / args.steps * 1e3 if graph else None)
     if plain_line is not None:
         line["plain"] = plain_line
         line["speedup_vs_plain"] = value / plain_line["value"]

@@ -133,13 +133,13 @@ __device__ __forceinline__ void gemm_rows(const T *X, int64_t st, int64_t C, con
 // FP32 mode each block also reports, per output neuron and bound, the sum of
 // |fl32(y) - y| over its coefficients (the exact rounding of the stored
 // tensor), reduced in a fixed order.
-template <typename T, int MB, int KU>
+template <typename T, int MB, int KU, bool kLoop>
 __global__ void __launch_bounds__(kBlock) gemm_kernel(GemmArgs a) {
   __shared__ double red[kBlock / 64][MB][2];
   const int m0 = blockIdx.x * MB;
   const int64_t c = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
-  const int64_t nb = launch_boxes(a);
-  for (int64_t z = blockIdx.z; z < nb; z += gridDim.z) {
+  const int64_t nb = loop_boxes<kLoop>(a);
+  for (int64_t z = blockIdx.z; z < nb; z = next_item<kLoop>(z, gridDim.z, nb)) {
   const int64_t box = a.bids ? a.bids[z] : z;
   const bool valid = c < a.C;
   const T *X = reinterpret_cast<const T *>(a.post) + box * a.slot_in;
@@ -202,7 +202,7 @@ __global__ void __launch_bounds__(kBlock) gemm_kernel(GemmArgs a) {
       for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v += red[w][mm][s];
       a.rpart[box * a.rpart_slot + ((int64_t)(m0 + mm) * 2 + s) * a.cblocks + blockIdx.y] = v;
     }
-    __syncthreads();  // red is rewritten by the next box
+    if constexpr (kLoop) __syncthreads();  // red is rewritten by the next box
   }
   }
 }
@@ -231,7 +231,7 @@ inline size_t pack_lds(int G, int hin, int MB) {
   return ((size_t)hin * MB + (size_t)(kPackWaves - 1) * 2 * MB * 64) * sizeof(double) + (size_t)G * hin;
 }
 
-template <typename T, int MB>
+template <typename T, int MB, bool kLoop>
 __global__ void __launch_bounds__(kPackWaves * 64) gemm_pack_kernel(GemmArgs a) {
   extern __shared__ double pk_lds[];
   const int C = (int)a.C, G = pack_groups(a.C), hin = a.hin;
@@ -241,9 +241,9 @@ __global__ void __launch_bounds__(kPackWaves * 64) gemm_pack_kernel(GemmArgs a) 
   // XCD; a grid smaller than the logical blocks (a device box count) strides
   // over them
   const int nx = (a.h + MB - 1) / MB;
-  const int64_t nb = launch_boxes(a);
+  const int64_t nb = loop_boxes<kLoop>(a);
   const int64_t nlb = (int64_t)nx * ((nb + G - 1) / G);
-  for (int64_t lb = xcd_block(blockIdx.x, (int64_t)gridDim.x); lb < nlb; lb += gridDim.x) {
+  for (int64_t lb = xcd_block(blockIdx.x, (int64_t)gridDim.x); lb < nlb; lb = next_item<kLoop>(lb, gridDim.x, nlb)) {
   const int m0 = (int)(lb % nx) * MB;
   const int64_t slot0 = lb / nx * G;
   const int64_t bslot = slot0 + g;
@@ -380,7 +380,7 @@ __global__ void __launch_bounds__(kPackWaves * 64) gemm_pack_kernel(GemmArgs a) 
       a.rpart[bx * a.rpart_slot + ((int64_t)(m0 + mm) * 2 + sd) * a.cblocks] = v;
     }
   }
-  __syncthreads();  // LDS is restaged for the next logical block
+  if constexpr (kLoop) __syncthreads();  // LDS is restaged for the next logical block
   }
 }
 
@@ -393,14 +393,21 @@ static hipError_t launch_gemm_pack(const GemmArgs &a, hipStream_t s) {
   const int64_t blocks = (int64_t)((a.h + MB - 1) / MB) * ((a.nboxes + G - 1) / G);
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   dim3 grid((unsigned)dev_grid(blocks, a.dcount));
+  const void *k = a.fp64 ? (a.dcount ? (const void *)gemm_pack_kernel<double, MB, true>
+                                     : (const void *)gemm_pack_kernel<double, MB, false>)
+                         : (a.dcount ? (const void *)gemm_pack_kernel<float, MB, true>
+                                     : (const void *)gemm_pack_kernel<float, MB, false>);
+  RET_IF(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   if (a.fp64) {
-    RET_IF(hipFuncSetAttribute((const void *)gemm_pack_kernel<double, MB>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL((gemm_pack_kernel<double, MB>), grid, dim3(kPackWaves * 64), lds, s, a);
+    if (a.dcount)
+      hipLaunchKernelGGL((gemm_pack_kernel<double, MB, true>), grid, dim3(kPackWaves * 64), lds, s, a);
+    else
+      hipLaunchKernelGGL((gemm_pack_kernel<double, MB, false>), grid, dim3(kPackWaves * 64), lds, s, a);
   } else {
-    RET_IF(hipFuncSetAttribute((const void *)gemm_pack_kernel<float, MB>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL((gemm_pack_kernel<float, MB>), grid, dim3(kPackWaves * 64), lds, s, a);
+    if (a.dcount)
+      hipLaunchKernelGGL((gemm_pack_kernel<float, MB, true>), grid, dim3(kPackWaves * 64), lds, s, a);
+    else
+      hipLaunchKernelGGL((gemm_pack_kernel<float, MB, false>), grid, dim3(kPackWaves * 64), lds, s, a);
   }
   return hipGetLastError();
 }
@@ -411,10 +418,17 @@ static hipError_t launch_gemm_mb(const GemmArgs &a, hipStream_t s) {
   dim3 grid((a.h + MB - 1) / MB, (unsigned)a.cblocks, (unsigned)dev_grid(a.nboxes, a.dcount, gxy));
   // one coefficient block: only the waves that hold coefficients
   const unsigned threads = a.C < kBlock ? (unsigned)((a.C + 63) / 64 * 64) : kBlock;
-  if (a.fp64)
-    hipLaunchKernelGGL((gemm_kernel<double, MB, KU>), grid, dim3(threads), 0, s, a);
-  else
-    hipLaunchKernelGGL((gemm_kernel<float, MB, KU>), grid, dim3(threads), 0, s, a);
+  if (a.fp64) {
+    if (a.dcount)
+      hipLaunchKernelGGL((gemm_kernel<double, MB, KU, true>), grid, dim3(threads), 0, s, a);
+    else
+      hipLaunchKernelGGL((gemm_kernel<double, MB, KU, false>), grid, dim3(threads), 0, s, a);
+  } else {
+    if (a.dcount)
+      hipLaunchKernelGGL((gemm_kernel<float, MB, KU, true>), grid, dim3(threads), 0, s, a);
+    else
+      hipLaunchKernelGGL((gemm_kernel<float, MB, KU, false>), grid, dim3(threads), 0, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -72,6 +72,19 @@ template <class A>
 __device__ __forceinline__ int64_t launch_boxes(const A &a) {
   return a.dcount ? min((int64_t)*a.dcount, a.nboxes) : a.nboxes;
 }
+// The kernels that loop take `bool kLoop`: true for launches with a device
+// count; false for launches whose grid covers every item, where each block
+// takes its one item and the compiler sees a single pass (a loop the
+// compiler cannot bound keeps more values live across iterations: more
+// registers, lower occupancy).
+template <bool kLoop, class A>
+__device__ __forceinline__ int64_t loop_boxes(const A &a) {
+  return kLoop ? launch_boxes(a) : a.nboxes;
+}
+template <bool kLoop>
+__device__ __forceinline__ int64_t next_item(int64_t item, int64_t stride, int64_t end) {
+  return kLoop ? item + stride : end;
+}
 inline int64_t dev_grid(int64_t blocks, const int *dcount, int64_t per = 1) {
   const int64_t cap = std::max<int64_t>(1, kDevGrid / std::max<int64_t>(1, per));
   return dcount && blocks > cap ? cap : blocks;
