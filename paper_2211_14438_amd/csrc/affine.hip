@@ -133,14 +133,13 @@ __device__ __forceinline__ void gemm_rows(const T *X, int64_t st, int64_t C, con
 // FP32 mode each block also reports, per output neuron and bound, the sum of
 // |fl32(y) - y| over its coefficients (the exact rounding of the stored
 // tensor), reduced in a fixed order.
-template <typename T, int MB, int KU, bool kLoop>
+template <typename T, int MB, int KU>
 __global__ void __launch_bounds__(kBlock) gemm_kernel(GemmArgs a) {
   __shared__ double red[kBlock / 64][MB][2];
   const int m0 = blockIdx.x * MB;
   const int64_t c = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
-  const int64_t nb = loop_boxes<kLoop>(a);
-  for (int64_t z = blockIdx.z; z < nb; z = next_item<kLoop>(z, gridDim.z, nb)) {
-  const int64_t box = a.bids ? a.bids[z] : z;
+  if ((int64_t)blockIdx.z >= launch_boxes(a)) return;  // past a device count
+  const int64_t box = a.bids ? a.bids[blockIdx.z] : blockIdx.z;
   const bool valid = c < a.C;
   const T *X = reinterpret_cast<const T *>(a.post) + box * a.slot_in;
   double accM[MB], accR[MB];
@@ -150,20 +149,26 @@ __global__ void __launch_bounds__(kBlock) gemm_kernel(GemmArgs a) {
   const int *lv = a.live + box * a.live_ld;
   const int64_t st = 2 * a.C;
   const double *wt = a.WT + m0;
+  int64_t Cs = a.Cs, Cact = a.Cact;
+  if (a.box_din) {  // the box's own pre degree
+    const int din = box_degree(a.box_din, box);
+    Cact = a.counts.at(a.n, din);
+    Cs = a.counts.at(a.n, min(din, a.Dout));
+  }
   // lanes past the tensor read its last coefficient; their sums are dropped
   const int64_t cc = valid ? c : a.C - 1;
   gemm_rows<T, MB, KU>(X + cc, st, a.C, lv + 3, lv[0], true, wt, a.hp, accM, accR);
   if (lv[1] > 0) {
     // degree-preserving inputs hold the first Cs coefficients (graded order:
     // the monomials of their degree); beyond, their lifted tensor is zero
-    const bool inside = cc < a.Cs;
+    const bool inside = cc < Cs;
     gemm_rows<T, MB, KU>(X + (inside ? cc : 0), st, a.C, lv + 3 + a.hin, lv[1], inside, wt, a.hp, accM, accR);
   }
   if (lv[2] > 0) {
     // active neurons: post = pre, read from the previous pre-activation arena
-    const bool inside = cc < a.Cact;
+    const bool inside = cc < Cact;
     const T *Xa = reinterpret_cast<const T *>(a.act) + box * a.act_slot;
-    gemm_rows<T, MB, KU>(Xa + (inside ? cc : 0), 2 * a.Cact, a.Cact, lv + 3 + 2 * a.hin, lv[2], inside, wt, a.hp, accM,
+    gemm_rows<T, MB, KU>(Xa + (inside ? cc : 0), 2 * Cact, Cact, lv + 3 + 2 * a.hin, lv[2], inside, wt, a.hp, accM,
                          accR);
   }
   T *Y = reinterpret_cast<T *>(a.pre) + box * a.slot_out;
@@ -194,16 +199,13 @@ __global__ void __launch_bounds__(kBlock) gemm_kernel(GemmArgs a) {
       }
     }
   }
-  if (track) {
-    __syncthreads();
-    if (threadIdx.x < 2 * mcount) {
-      const int mm = threadIdx.x >> 1, s = threadIdx.x & 1;
-      double v = 0.0;
-      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v += red[w][mm][s];
-      a.rpart[box * a.rpart_slot + ((int64_t)(m0 + mm) * 2 + s) * a.cblocks + blockIdx.y] = v;
-    }
-    if constexpr (kLoop) __syncthreads();  // red is rewritten by the next box
-  }
+  if (!track) return;
+  __syncthreads();
+  if (threadIdx.x < 2 * mcount) {
+    const int mm = threadIdx.x >> 1, s = threadIdx.x & 1;
+    double v = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v += red[w][mm][s];
+    a.rpart[box * a.rpart_slot + ((int64_t)(m0 + mm) * 2 + s) * a.cblocks + blockIdx.y] = v;
   }
 }
 
@@ -231,22 +233,20 @@ inline size_t pack_lds(int G, int hin, int MB) {
   return ((size_t)hin * MB + (size_t)(kPackWaves - 1) * 2 * MB * 64) * sizeof(double) + (size_t)G * hin;
 }
 
-template <typename T, int MB, bool kLoop>
+template <typename T, int MB>
 __global__ void __launch_bounds__(kPackWaves * 64) gemm_pack_kernel(GemmArgs a) {
   extern __shared__ double pk_lds[];
   const int C = (int)a.C, G = pack_groups(a.C), hin = a.hin;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane / C, c = lane - g * C;
-  // logical block: row chunk fastest, the row chunks of one box group on one
-  // XCD; a grid smaller than the logical blocks (a device box count) strides
-  // over them
+  // logical block: row chunk fastest, the row chunks of one box group on one XCD
   const int nx = (a.h + MB - 1) / MB;
-  const int64_t nb = loop_boxes<kLoop>(a);
-  const int64_t nlb = (int64_t)nx * ((nb + G - 1) / G);
-  for (int64_t lb = xcd_block(blockIdx.x, (int64_t)gridDim.x); lb < nlb; lb = next_item<kLoop>(lb, gridDim.x, nlb)) {
+  const int64_t lb = xcd_block(blockIdx.x, (int64_t)gridDim.x);
   const int m0 = (int)(lb % nx) * MB;
   const int64_t slot0 = lb / nx * G;
   const int64_t bslot = slot0 + g;
+  const int64_t nb = launch_boxes(a);
+  if (slot0 >= nb) return;  // past a device count
   const bool valid = g < G && bslot < nb;
   double *wl = pk_lds;
   double *part = wl + (size_t)hin * MB;
@@ -269,7 +269,12 @@ __global__ void __launch_bounds__(kPackWaves * 64) gemm_pack_kernel(GemmArgs a) 
   const T *X = reinterpret_cast<const T *>(a.post) + box * a.slot_in;
   const T *Xa = reinterpret_cast<const T *>(a.act) + box * a.act_slot;
   const unsigned char *kd = kind + (valid ? g : 0) * hin;
-  const int Cs = (int)a.Cs, Ca = (int)a.Cact;
+  int Cs = (int)a.Cs, Ca = (int)a.Cact;
+  if (a.box_din) {  // the lane's box's own pre degree
+    const int din = box_degree(a.box_din, box);
+    Ca = (int)a.counts.at(a.n, din);
+    Cs = (int)a.counts.at(a.n, min(din, a.Dout));
+  }
   const int kq = (hin + kPackWaves - 1) / kPackWaves;
   const int k0 = min(hin, w * kq), k1 = min(hin, k0 + kq);
   double accM[MB], accR[MB];
@@ -368,19 +373,16 @@ __global__ void __launch_bounds__(kPackWaves * 64) gemm_pack_kernel(GemmArgs a) 
       }
     }
   }
-  if (track) {
-    __syncthreads();
-    // per (box, row, bound): its coefficients' rounding in index order
-    for (int t = threadIdx.x; t < G * MB * 2; t += blockDim.x) {
-      const int gg = t / (2 * MB), r = t - gg * 2 * MB, mm = r >> 1, sd = r & 1;
-      if (slot0 + gg >= nb || m0 + mm >= a.h) continue;
-      double v = 0.0;
-      for (int q = 0; q < C; ++q) v += part[r * 64 + gg * C + q];
-      const int64_t bx = a.bids ? a.bids[slot0 + gg] : slot0 + gg;
-      a.rpart[bx * a.rpart_slot + ((int64_t)(m0 + mm) * 2 + sd) * a.cblocks] = v;
-    }
-  }
-  if constexpr (kLoop) __syncthreads();  // LDS is restaged for the next logical block
+  if (!track) return;
+  __syncthreads();
+  // per (box, row, bound): its coefficients' rounding in index order
+  for (int t = threadIdx.x; t < G * MB * 2; t += blockDim.x) {
+    const int gg = t / (2 * MB), r = t - gg * 2 * MB, mm = r >> 1, sd = r & 1;
+    if (slot0 + gg >= nb || m0 + mm >= a.h) continue;
+    double v = 0.0;
+    for (int q = 0; q < C; ++q) v += part[r * 64 + gg * C + q];
+    const int64_t bx = a.bids ? a.bids[slot0 + gg] : slot0 + gg;
+    a.rpart[bx * a.rpart_slot + ((int64_t)(m0 + mm) * 2 + sd) * a.cblocks] = v;
   }
 }
 
@@ -392,43 +394,28 @@ static hipError_t launch_gemm_pack(const GemmArgs &a, hipStream_t s) {
   const size_t lds = pack_lds(G, a.hin, MB);
   const int64_t blocks = (int64_t)((a.h + MB - 1) / MB) * ((a.nboxes + G - 1) / G);
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  dim3 grid((unsigned)dev_grid(blocks, a.dcount));
-  const void *k = a.fp64 ? (a.dcount ? (const void *)gemm_pack_kernel<double, MB, true>
-                                     : (const void *)gemm_pack_kernel<double, MB, false>)
-                         : (a.dcount ? (const void *)gemm_pack_kernel<float, MB, true>
-                                     : (const void *)gemm_pack_kernel<float, MB, false>);
-  RET_IF(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  dim3 grid((unsigned)blocks);
   if (a.fp64) {
-    if (a.dcount)
-      hipLaunchKernelGGL((gemm_pack_kernel<double, MB, true>), grid, dim3(kPackWaves * 64), lds, s, a);
-    else
-      hipLaunchKernelGGL((gemm_pack_kernel<double, MB, false>), grid, dim3(kPackWaves * 64), lds, s, a);
+    RET_IF(hipFuncSetAttribute((const void *)gemm_pack_kernel<double, MB>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((gemm_pack_kernel<double, MB>), grid, dim3(kPackWaves * 64), lds, s, a);
   } else {
-    if (a.dcount)
-      hipLaunchKernelGGL((gemm_pack_kernel<float, MB, true>), grid, dim3(kPackWaves * 64), lds, s, a);
-    else
-      hipLaunchKernelGGL((gemm_pack_kernel<float, MB, false>), grid, dim3(kPackWaves * 64), lds, s, a);
+    RET_IF(hipFuncSetAttribute((const void *)gemm_pack_kernel<float, MB>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((gemm_pack_kernel<float, MB>), grid, dim3(kPackWaves * 64), lds, s, a);
   }
   return hipGetLastError();
 }
 
 template <int MB, int KU>
 static hipError_t launch_gemm_mb(const GemmArgs &a, hipStream_t s) {
-  const int64_t gxy = (int64_t)((a.h + MB - 1) / MB) * a.cblocks;
-  dim3 grid((a.h + MB - 1) / MB, (unsigned)a.cblocks, (unsigned)dev_grid(a.nboxes, a.dcount, gxy));
+  dim3 grid((a.h + MB - 1) / MB, (unsigned)a.cblocks, (unsigned)a.nboxes);
   // one coefficient block: only the waves that hold coefficients
   const unsigned threads = a.C < kBlock ? (unsigned)((a.C + 63) / 64 * 64) : kBlock;
-  if (a.fp64) {
-    if (a.dcount)
-      hipLaunchKernelGGL((gemm_kernel<double, MB, KU, true>), grid, dim3(threads), 0, s, a);
-    else
-      hipLaunchKernelGGL((gemm_kernel<double, MB, KU, false>), grid, dim3(threads), 0, s, a);
-  } else {
-    if (a.dcount)
-      hipLaunchKernelGGL((gemm_kernel<float, MB, KU, true>), grid, dim3(threads), 0, s, a);
-    else
-      hipLaunchKernelGGL((gemm_kernel<float, MB, KU, false>), grid, dim3(threads), 0, s, a);
-  }
+  if (a.fp64)
+    hipLaunchKernelGGL((gemm_kernel<double, MB, KU>), grid, dim3(threads), 0, s, a);
+  else
+    hipLaunchKernelGGL((gemm_kernel<float, MB, KU>), grid, dim3(threads), 0, s, a);
   return hipGetLastError();
 }
 
@@ -438,6 +425,8 @@ hipError_t launch_gemm(const GemmArgs &a0, hipStream_t s) {
   GemmArgs a = a0;
   a.cblocks = gemm_cblocks(a.C);
   if (a.hp % 16 != 0 || a.hp < a.h || !a.live || a.Cs > a.C || !a.act) return hipErrorInvalidValue;
+  if (a.box_din && (a.n < 1 || stored_count(a.n, a.Dout) != a.C)) return hipErrorInvalidValue;
+  if (a.box_din) a.counts.fill(a.n);
   ProfScope ps(kProfGemm, s, (double)a.nboxes * (2.0 * a.hin + 2.0 * a.h) * a.C * (a.fp64 ? 8 : 4),
                4.0 * a.nboxes * a.h * a.hin * a.C);
   if (a.C <= kPackMaxC && pack_lds(pack_groups(a.C), a.hin, 16) <= device_lds_limit()) {

@@ -127,7 +127,8 @@ constexpr int kMaxDevPairs = 48;  // pairs over all hidden layers
 struct DevClasses {
   std::vector<std::vector<int>> din;                    // [layer] pre degrees, ascending
   std::vector<std::vector<std::pair<int, int>>> pairs;  // [hidden layer] (Din, Dout)
-  int slots = 0;                                        // lists per layer
+  std::vector<std::vector<int>> dout;                   // [hidden layer] post degrees, ascending
+  int slots = 0;                                        // lists per layer: pairs, then post degrees
 };
 
 // Host-side plan of one network under one set of options: degree of every
@@ -175,11 +176,11 @@ static bool dev_classes(const Plan &p, DevClasses &dc) {
     std::sort(nxt.begin(), nxt.end());
     nxt.erase(std::unique(nxt.begin(), nxt.end()), nxt.end());
     const bool lin = p.lin > 0 && (i + 1) % p.lin == 0;
-    if (lin) nxt.assign(1, 1);  // every box restarts at degree 1
     total += (int)pr.size();
-    dc.slots = std::max(dc.slots, (int)pr.size() + (lin ? 0 : (int)nxt.size()));
+    dc.slots = std::max(dc.slots, (int)(pr.size() + nxt.size()));
     dc.pairs.push_back(pr);
-    cur = nxt;
+    dc.dout.push_back(nxt);
+    cur = lin ? std::vector<int>{1} : nxt;  // after a linearisation every box restarts at degree 1
   }
   return dc.slots <= kMaxDevLists && total <= kMaxDevPairs;
 }
@@ -768,25 +769,56 @@ static bern_status compose_args(const bern_net *net, const Plan &p, int i, const
   return BERN_OK;
 }
 
-// Hidden layer i under periodic linearisation (opts.lin): every class's
-// compositions at its post degree, the post radii of the layer (FP32 mode),
-// then per class every neuron's post polynomials staged whole at that degree
-// and read off with fits and remainders (mode 2); the affine posts stored at
-// degree 1 for all boxes, and the next layer's affine map over every box at
-// degree 1 (Section 5.4, the Lin parameter).
-static bern_status lin_layer_run(const bern_net *net, const Plan &p, int i, const std::vector<LaunchClass> &next,
-                                 int64_t B, void *const *Aa, void *Bp, int64_t slotA, int64_t slotB, NeuronRec *recs,
-                                 double *rad, double *cpart, void *horner, int *live, int64_t live_ld, double *gpart,
-                                 double *conv, hipStream_t s) {
+// The compositions of hidden layer i (Section 5.1 Step 3): the order-1
+// and fallback posts of every box in one launch (each box at its own
+// degrees din / dout, or at the uniform uDin / uDout where those are null),
+// the products of every (Din, Dout) class that can hold an order >= 2 (its
+// own square and Horner tables), then the post radii of every box (FP32).
+static bern_status compose_layer(const bern_net *net, const Plan &p, int i, const std::vector<LaunchClass> &pairs,
+                                 int uDin, int uDout, const int *din, const int *dout, int64_t B, void *pre,
+                                 void *post, int64_t slotA, int64_t slotB, NeuronRec *recs, double *rad,
+                                 double *cpart, void *horner, int *live, int64_t live_ld, hipStream_t s) {
   const int n = net->n, h = net->widths[i + 1];
-  for (size_t k = 0; k < next.size(); ++k) {
-    ComposeArgs m;
-    bern_status st = compose_args(net, p, i, next[k], Aa[i & 1], Bp, slotA, slotB, recs, rad, cpart, horner,
-                                  p.horner * B, live, live_ld, m);
+  ComposeArgs m{};
+  m.n = n;
+  m.Din = uDin;
+  m.Dout = uDout;
+  m.h = h;
+  m.bids = nullptr;
+  m.nboxes = B;
+  m.slot_in = slotA;
+  m.slot_out = slotB;
+  m.nbounds = 2;
+  m.Lmax = 1;
+  m.Cin = ssize(n, uDin);
+  m.Cout = ssize(n, uDout);
+  m.Cs = ssize(n, std::min(uDin, uDout));
+  m.pre = pre;
+  m.post = post;
+  m.recs = recs;
+  m.rad = p.fp64 ? nullptr : rad;
+  m.fp64 = p.fp64 ? 1 : 0;
+  m.nbx = p.nbx[i];
+  m.pstride = p.nbx[i];
+  m.part = p.fp64 ? nullptr : cpart;
+  m.live = live;
+  m.live_ld = live_ld;
+  m.box_din = din;
+  m.box_dout = dout;
+  m.stage = 1;
+  m.lists_ready = 1;
+  m.radii_later = 1;
+  BERN_HIP_TRY(launch_compose(m, s));
+  for (const LaunchClass &cl : pairs) {
+    if (class_order(p, cl.Din, cl.Dout) < 2) continue;  // no neuron of the class has a product
+    ComposeArgs mp;
+    const bern_status st = compose_args(net, p, i, cl, pre, post, slotA, slotB, recs, rad, cpart, horner,
+                                        p.horner * B, live, live_ld, mp);
     if (st != BERN_OK) return st;
-    m.lists_ready = 1;  // the lists below, once the layer is linearised
-    m.radii_later = 1;
-    BERN_HIP_TRY(launch_compose(m, s));
+    mp.stage = 2;
+    mp.lists_ready = 1;
+    mp.radii_later = 1;
+    BERN_HIP_TRY(launch_compose(mp, s));
   }
   if (!p.fp64) {
     ComposeArgs mr{};
@@ -802,16 +834,91 @@ static bern_status lin_layer_run(const bern_net *net, const Plan &p, int i, cons
     mr.fp64 = 0;
     BERN_HIP_TRY(launch_post_radii(mr, s));
   }
-  for (size_t k = 0; k < next.size(); ++k) {
-    const LaunchClass &cl = next[k];
-    if (cl.Dout < 1) continue;  // every neuron inactive: nothing to linearise
-    ComposeArgs m;
-    bern_status st = compose_args(net, p, i, cl, Aa[i & 1], Bp, slotA, slotB, recs, rad, cpart, horner,
-                                  p.horner * B, live, live_ld, m);
-    if (st != BERN_OK) return st;
+  return BERN_OK;
+}
+
+// The affine map after hidden layer i (Section 5.2), one launch per post
+// degree class: every box of the class holds its posts at that degree and
+// reads its active neurons' pre-activations at its own pre degree (din, or
+// the uniform uDin where din is null).
+static bern_status gemm_layer(const bern_net *net, const Plan &p, int i, const std::vector<LaunchClass> &gc, int uDin,
+                              const int *din, void *const *Aa, void *Bp, int64_t slotA, int64_t slotB, int *live,
+                              int64_t live_ld, double *gpart, hipStream_t s) {
+  const int n = net->n;
+  for (const LaunchClass &cl : gc) {
+    GemmArgs a{};
+    a.hin = net->widths[i + 1];
+    a.h = net->widths[i + 2];
+    a.C = ssize(n, cl.Dout);
+    a.nboxes = cl.nboxes;
+    a.bids = cl.bids;
+    a.dcount = cl.dcount;
+    a.slot_in = slotB;
+    a.slot_out = slotA;
+    a.post = Bp;
+    a.pre = Aa[(i + 1) & 1];
+    a.act = Aa[i & 1];
+    a.act_slot = slotA;
+    if (din) {
+      a.box_din = din;
+      a.n = n;
+      a.Dout = cl.Dout;
+      a.Cs = a.C;
+      a.Cact = a.C;
+    } else {
+      a.Cact = ssize(n, uDin);
+      a.Cs = ssize(n, std::min(uDin, cl.Dout));
+    }
+    a.live = live;
+    a.live_ld = live_ld;
+    a.tune = net->tune;
+    a.WT = net->WT + net->wtoff[i + 1];
+    a.hp = net->hpad[i + 1];
+    a.b = net->b64 + net->boff[i + 1];
+    a.fp64 = p.fp64 ? 1 : 0;
+    a.rpart = p.fp64 ? nullptr : gpart;
+    a.rpart_slot = (int64_t)(p.gpart / sizeof(double));
+    BERN_HIP_TRY(launch_gemm(a, s));
+  }
+  return BERN_OK;
+}
+
+// Hidden layer i under periodic linearisation (opts.lin), after its
+// compositions: every neuron's post polynomials staged whole at its box's
+// post degree, read off per post degree class with fits and remainders
+// (mode 2), the affine posts stored at degree 1 for all boxes, and the next
+// layer's affine map over every box at degree 1 (Section 5.4, the Lin
+// parameter).
+static bern_status lin_layer_run(const bern_net *net, const Plan &p, int i, const std::vector<LaunchClass> &gc,
+                                 int uDin, int uDout, const int *din, const int *dout, int64_t B, void *const *Aa,
+                                 void *Bp, int64_t slotA, int64_t slotB, NeuronRec *recs, double *rad, int *live,
+                                 int64_t live_ld, double *gpart, double *conv, hipStream_t s) {
+  const int n = net->n, h = net->widths[i + 1];
+  {
+    ComposeArgs m{};
+    m.n = n;
+    m.Din = uDin;
+    m.Dout = uDout;
+    m.h = h;
+    m.nboxes = B;
+    m.nbounds = 2;
+    m.slot_in = slotA;
+    m.slot_out = slotB;
+    m.Cin = ssize(n, uDin);
+    m.Cout = ssize(n, uDout);
+    m.Cs = ssize(n, std::min(uDin, uDout));
+    m.pre = Aa[i & 1];
+    m.post = Bp;
+    m.recs = recs;
+    m.fp64 = p.fp64 ? 1 : 0;
+    m.box_din = din;
+    m.box_dout = dout;
     BERN_HIP_TRY(launch_lin_stage(m, s));
+  }
+  for (const LaunchClass &cl : gc) {
+    if (cl.Dout < 1) continue;  // every neuron inactive: nothing to linearise
     LayerTables lt;
-    st = layer_tables(net, cl.Dout, p.Lmax, false, lt);
+    bern_status st = layer_tables(net, cl.Dout, p.Lmax, false, lt);
     if (st != BERN_OK) return st;
     ConvertArgs c{};
     c.n = n;
@@ -867,31 +974,8 @@ static bern_status lin_layer_run(const bern_net *net, const Plan &p, int i, cons
   ml.lin = 1;
   BERN_HIP_TRY(launch_lin_scatter(ml, s));
   BERN_HIP_TRY(launch_live(ml, s));
-  GemmArgs a{};
-  a.hin = h;
-  a.h = net->widths[i + 2];
-  a.C = n + 1;
-  a.nboxes = B;
-  a.bids = nullptr;
-  a.slot_in = slotB;
-  a.slot_out = slotA;
-  a.post = Bp;
-  a.pre = Aa[(i + 1) & 1];
-  a.act = Aa[i & 1];
-  a.act_slot = slotA;
-  a.Cact = n + 1;
-  a.live = live;
-  a.live_ld = live_ld;
-  a.Cs = n + 1;
-  a.tune = net->tune;
-  a.WT = net->WT + net->wtoff[i + 1];
-  a.hp = net->hpad[i + 1];
-  a.b = net->b64 + net->boff[i + 1];
-  a.fp64 = p.fp64 ? 1 : 0;
-  a.rpart = p.fp64 ? nullptr : gpart;
-  a.rpart_slot = (int64_t)(p.gpart / sizeof(double));
-  BERN_HIP_TRY(launch_gemm(a, s));
-  return BERN_OK;
+  const std::vector<LaunchClass> all{LaunchClass{1, 1, nullptr, B, nullptr}};
+  return gemm_layer(net, p, i, all, 1, nullptr, Aa, Bp, slotA, slotB, live, live_ld, gpart, s);
 }
 
 // Enqueue the launch sequence of one wave of `B` boxes. The plain rule keeps
@@ -1176,14 +1260,23 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       break;
     }
 
-    // post degree of every box -> classes (Din, Dout)
-    std::vector<BoxClass> next;
-    std::vector<LaunchClass> pc;
+    // this layer's box degrees: pre (null: every box at the uniform uDin)
+    // and post (null: uniform, the plain rule)
+    const int uDin = plain ? rc[0].Din : 1;
+    const int uDout = plain ? p.L * uDin : 0;
+    const int *din = (plain || restart) ? nullptr : degs + ((i + 1) & 1) * B;
+    const int *dout = plain ? nullptr : ldeg;
+    // (Din, Dout) classes for the products; post degree classes for the
+    // affine map and the next layer's read-off
+    std::vector<BoxClass> next, nc;  // host classes
+    std::vector<LaunchClass> pc, gc;
+    std::vector<const int *> gid;
     if (plain) {
-      next = classes;
-      for (auto &c : next) c.Dout = p.L * c.Din;
-      for (size_t k = 0; k < rc.size(); ++k)
-        pc.push_back(LaunchClass{rc[k].Din, p.L * rc[k].Din, rc[k].bids, rc[k].nboxes, nullptr});
+      pc.push_back(LaunchClass{uDin, uDout, rc[0].bids, rc[0].nboxes, nullptr});
+      gc = pc;
+      nc = classes;
+      nc[0].Din = uDout;
+      gid.assign(1, rc[0].bids);
     } else {
       if (!learned) {  // (the learned rules kernel wrote them)
         ProfScope ps(kProfMisc, s, 0.0);
@@ -1193,14 +1286,15 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       BERN_HIP_TRY(hipGetLastError());
       if (dev) {
         const auto &pr = dc->pairs[i];
+        const auto &dv = dc->dout[i];
         ClassTab t{};
         t.npairs = (int)pr.size();
-        t.nvals = lin_layer ? 0 : (int)dc->din[i + 1].size();
+        t.nvals = (int)dv.size();
         for (int k = 0; k < t.npairs; ++k) {
           t.din[k] = pr[k].first;
           t.dout[k] = pr[k].second;
         }
-        for (int m = 0; m < t.nvals; ++m) t.vals[m] = dc->din[i + 1][m];
+        for (int m = 0; m < t.nvals; ++m) t.vals[m] = dv[m];
         {
           ProfScope ps(kProfMisc, s, 0.0);
           hipLaunchKernelGGL(classify_kernel, dim3((unsigned)(t.npairs + t.nvals + 1)), dim3(1024), 0, s, B,
@@ -1210,33 +1304,56 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
         BERN_HIP_TRY(hipGetLastError());
         for (int k = 0; k < t.npairs; ++k)
           pc.push_back(LaunchClass{pr[k].first, pr[k].second, dev_ids(i, k), B, dev_cnt(i, k)});
+        for (int m = 0; m < t.nvals; ++m)
+          gc.push_back(LaunchClass{0, dv[m], dev_ids(i, t.npairs + m), B, dev_cnt(i, t.npairs + m)});
       } else {
         int *hd = net->host_ids;
         BERN_HIP_TRY(hipMemcpyAsync(hd, ldeg, B * sizeof(int), hipMemcpyDeviceToHost, s));
         BERN_HIP_TRY(hipStreamSynchronize(s));
         for (int64_t b = 0; b < B; ++b) {
-          const int din = dcur[b], dout = std::max(hd[b], 0);
+          const int din_b = dcur[b], dout_b = std::max(hd[b], 0);
           size_t k = 0;
           for (; k < next.size(); ++k)
-            if (next[k].Din == din && next[k].Dout == dout) break;
-          if (k == next.size()) next.push_back(BoxClass{din, dout, {}});
+            if (next[k].Din == din_b && next[k].Dout == dout_b) break;
+          if (k == next.size()) next.push_back(BoxClass{din_b, dout_b, {}});
           next[k].ids.push_back((int)b);
         }
+        for (auto &cl : next) {
+          size_t k = 0;
+          for (; k < nc.size(); ++k)
+            if (nc[k].Din == cl.Dout) break;
+          if (k == nc.size()) nc.push_back(BoxClass{cl.Dout, 0, {}});
+          nc[k].ids.insert(nc[k].ids.end(), cl.ids.begin(), cl.ids.end());
+        }
+        for (auto &cl : nc) std::sort(cl.ids.begin(), cl.ids.end());
+        std::vector<const int *> pid;
+        st = upload(next, i, 0, pid);
+        if (st != BERN_OK) return st;
+        st = upload(nc, i, 1, gid);
+        if (st != BERN_OK) return st;
+        for (size_t k = 0; k < next.size(); ++k)
+          pc.push_back(LaunchClass{next[k].Din, next[k].Dout, pid[k], (int64_t)next[k].ids.size(), nullptr});
+        for (size_t k = 0; k < nc.size(); ++k)
+          gc.push_back(LaunchClass{0, nc[k].Din, gid[k], (int64_t)nc[k].ids.size(), nullptr});
       }
     }
-    std::vector<const int *> pid;
-    if (!dev && !plain) {
-      st = upload(next, i, 1, pid);
-      if (st != BERN_OK) return st;
-      for (size_t k = 0; k < next.size(); ++k)
-        pc.push_back(LaunchClass{next[k].Din, next[k].Dout, pid[k], (int64_t)next[k].ids.size(), nullptr});
-    } else if (plain) {
-      pid.assign(pc.size(), nullptr);
-      for (size_t k = 0; k < pc.size(); ++k) pid[k] = pc[k].bids;
+    // the next affine map's input lists of every box (a linearised layer
+    // builds its own after the linearisation)
+    if (!lin_layer) {
+      ComposeArgs ml{};
+      ml.h = h;
+      ml.nboxes = B;
+      ml.recs = recs;
+      ml.live = live;
+      ml.live_ld = live_ld;
+      BERN_HIP_TRY(launch_live(ml, s));
     }
+    st = compose_layer(net, p, i, pc, uDin, uDout, din, dout, B, Aa[i & 1], Bp, slotA, slotB, recs, radbuf[i & 1],
+                       cpart, horner, live, live_ld, s);
+    if (st != BERN_OK) return st;
     if (lin_layer) {
-      st = lin_layer_run(net, p, i, pc, B, Aa, Bp, slotA, slotB, recs, radbuf[i & 1], cpart, horner, live, live_ld,
-                         gpart, conv, s);
+      st = lin_layer_run(net, p, i, gc, uDin, uDout, din, dout, B, Aa, Bp, slotA, slotB, recs, radbuf[i & 1], live,
+                         live_ld, gpart, conv, s);
       if (st != BERN_OK) return st;
       classes.assign(1, BoxClass{1, 0, {}});
       classes[0].ids.resize(B);
@@ -1249,82 +1366,13 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       continue;
     }
     restart = false;
-    // several classes (or device classes): the next affine map's input lists
-    // of every box at once
-    const bool lists_once = dev || pc.size() > 1;
-    if (lists_once) {
-      ComposeArgs ml{};
-      ml.h = h;
-      ml.nboxes = B;
-      ml.recs = recs;
-      ml.live = live;
-      ml.live_ld = live_ld;
-      BERN_HIP_TRY(launch_live(ml, s));
-    }
-    for (const LaunchClass &cl : pc) {
-      // composition -> post tensors in arena B
-      ComposeArgs m;
-      st = compose_args(net, p, i, cl, Aa[i & 1], Bp, slotA, slotB, recs, radbuf[i & 1], cpart, horner, p.horner * B,
-                        live, live_ld, m);
-      if (st != BERN_OK) return st;
-      m.lists_ready = lists_once ? 1 : 0;
-      m.radii_later = lists_once ? 1 : 0;
-      BERN_HIP_TRY(launch_compose(m, s));
-      // affine map of the next layer -> pre-activation tensors in arena A
-      GemmArgs a{};
-      a.hin = h;
-      a.h = net->widths[i + 2];
-      a.C = m.Cout;
-      a.nboxes = cl.nboxes;
-      a.bids = cl.bids;
-      a.dcount = cl.dcount;
-      a.slot_in = slotB;
-      a.slot_out = slotA;
-      a.post = Bp;
-      a.pre = Aa[(i + 1) & 1];
-      a.act = Aa[i & 1];
-      a.act_slot = slotA;
-      a.Cact = m.Cin;
-      a.live = live;
-      a.live_ld = live_ld;
-      a.Cs = m.Cs;
-      a.tune = net->tune;
-      a.WT = net->WT + net->wtoff[i + 1];
-      a.hp = net->hpad[i + 1];
-      a.b = net->b64 + net->boff[i + 1];
-      a.fp64 = p.fp64 ? 1 : 0;
-      a.rpart = p.fp64 ? nullptr : gpart;
-      a.rpart_slot = (int64_t)(p.gpart / sizeof(double));
-      BERN_HIP_TRY(launch_gemm(a, s));
-    }
-    // several classes: the post radii of every box at once
-    if (lists_once && !p.fp64) {
-      ComposeArgs mr{};
-      mr.n = n;
-      mr.h = h;
-      mr.nboxes = B;
-      mr.nbounds = 2;
-      mr.recs = recs;
-      mr.part = cpart;
-      mr.nbx = p.nbx[i];
-      mr.pstride = p.nbx[i];
-      mr.rad = radbuf[i & 1];
-      mr.fp64 = 0;
-      BERN_HIP_TRY(launch_post_radii(mr, s));
-    }
+    st = gemm_layer(net, p, i, gc, uDin, din, Aa, Bp, slotA, slotB, live, live_ld, gpart, s);
+    if (st != BERN_OK) return st;
     if (dev) continue;  // the classification kernel listed the next read-off's classes
-    // next layer's classes: by the new pre degree
-    std::vector<BoxClass> nc;
-    for (auto &cl : next) {
-      size_t k = 0;
-      for (; k < nc.size(); ++k)
-        if (nc[k].Din == cl.Dout) break;
-      if (k == nc.size()) nc.push_back(BoxClass{cl.Dout, 0, {}});
-      nc[k].ids.insert(nc[k].ids.end(), cl.ids.begin(), cl.ids.end());
-      for (int b : cl.ids) dcur[b] = cl.Dout;
-    }
-    // no classes merged: the lists just uploaded serve the next read-off
-    if (nc.size() == next.size()) carried = pid;
+    // next layer's classes: by the new pre degree, the lists just uploaded
+    for (auto &cl : nc)
+      for (int b : cl.ids) dcur[b] = cl.Din;
+    carried = gid;
     classes.swap(nc);
   }
   {
@@ -1438,9 +1486,11 @@ static bern_status bounds_impl(const bern_net *net, const bern_opts *opts, int64
       const bool lin = i < p.H - 1 && p.lin > 0 && (i + 1) % p.lin == 0;
       for (size_t k = 0; i < p.H - 1 && k < dc->pairs[i].size(); ++k) {
         const auto &pr = dc->pairs[i][k];
-        ok = ok && layer_tables(net, pr.first, class_order(p, pr.first, pr.second), true, lt) == BERN_OK;
-        if (lin && pr.second >= 1) ok = ok && layer_tables(net, pr.second, p.Lmax, false, lt) == BERN_OK;
+        const int order = class_order(p, pr.first, pr.second);
+        if (order >= 2) ok = ok && layer_tables(net, pr.first, order, true, lt) == BERN_OK;
       }
+      for (size_t k = 0; lin && k < dc->dout[i].size(); ++k)
+        if (dc->dout[i][k] >= 1) ok = ok && layer_tables(net, dc->dout[i][k], p.Lmax, false, lt) == BERN_OK;
       if (!ok) {
         dc = nullptr;
         graph = false;

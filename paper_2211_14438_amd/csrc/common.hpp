@@ -62,28 +62,38 @@ __host__ __device__ inline int64_t ipow(int64_t b, int e) {
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// C(n + d, n): the stored coefficients of a degree-d tensor in n variables
+// (total-degree layout), on either side; every partial product is exact.
+__host__ __device__ inline int64_t stored_count(int n, int d) {
+  int64_t r = 1;
+  for (int i = 1; i <= n; ++i) r = r * (d + i) / i;
+  return r;
+}
+// A box's degree from a per-box degree array (negative values count as 0).
+__device__ inline int box_degree(const int *deg, int64_t box) { return max(deg[box], 0); }
+
+// C(n + d, n) for d < kCountTable, carried by launches with per-box degrees
+// (a table lookup instead of the divisions of stored_count on the device).
+constexpr int kCountTable = 65;
+struct CountTable {
+  int64_t c[kCountTable];
+  __host__ void fill(int n) {
+    for (int d = 0; d < kCountTable; ++d) c[d] = stored_count(n, d);
+  }
+  __device__ int64_t at(int n, int d) const { return d < kCountTable ? c[d] : stored_count(n, d); }
+};
+
 // Launches whose box count lives on the device (a device-side
 // classification wrote it to `dcount`): the host only knows the upper bound
-// `nboxes`, the grid covers at most kDevGrid blocks along the box dimension,
-// and the kernels' blocks loop over the launch's items. Without a device
-// count every block takes one item, as the grid covers them all.
+// `nboxes`. The read-off and affine-map kernels take the grid of `nboxes`
+// boxes and their blocks past the count leave at once (a loop over items
+// would keep more values live and cost them occupancy); the composition
+// kernels take a grid of at most kDevGrid blocks over which they loop.
+// Without a device count the grid covers the items and each block takes one.
 constexpr int64_t kDevGrid = 4096;
 template <class A>
 __device__ __forceinline__ int64_t launch_boxes(const A &a) {
   return a.dcount ? min((int64_t)*a.dcount, a.nboxes) : a.nboxes;
-}
-// The kernels that loop take `bool kLoop`: true for launches with a device
-// count; false for launches whose grid covers every item, where each block
-// takes its one item and the compiler sees a single pass (a loop the
-// compiler cannot bound keeps more values live across iterations: more
-// registers, lower occupancy).
-template <bool kLoop, class A>
-__device__ __forceinline__ int64_t loop_boxes(const A &a) {
-  return kLoop ? launch_boxes(a) : a.nboxes;
-}
-template <bool kLoop>
-__device__ __forceinline__ int64_t next_item(int64_t item, int64_t stride, int64_t end) {
-  return kLoop ? item + stride : end;
 }
 inline int64_t dev_grid(int64_t blocks, const int *dcount, int64_t per = 1) {
   const int64_t cap = std::max<int64_t>(1, kDevGrid / std::max<int64_t>(1, per));
@@ -224,6 +234,12 @@ struct GemmArgs {
   int64_t cblocks;                // coefficient blocks of the launch (set by the launcher)
   Tune tune;
   const int *dcount = nullptr;    // device count of the launch's boxes (nboxes: its upper bound)
+  // Boxes of one post degree but different pre degrees (per-neuron plans):
+  // each box's pre degree Din from box_din, its Cact = C(n + Din, n) and
+  // Cs = C(n + min(Din, Dout), n); null: Cact and Cs above for every box.
+  const int *box_din = nullptr;
+  int n = 0, Dout = 0;
+  CountTable counts;              // filled by the launcher when box_din is set
 };
 int64_t gemm_cblocks(int64_t C);
 hipError_t launch_gemm(const GemmArgs &a, hipStream_t s);
@@ -340,6 +356,13 @@ struct ComposeArgs {
   int lin;                        // the layer was linearised: every neuron that is not inactive
                                   // holds a full degree-1 post tensor (live lists, Lin launchers)
   const int *dcount = nullptr;    // device count of the launch's boxes (nboxes: its upper bound)
+  // Per-box degrees (per-neuron plans, launches over boxes of several
+  // classes: the scatter of order-1 and fallback posts, the Lin staging):
+  // Din from box_din (null: Din above), Dout from box_dout (null: Dout), and
+  // Cin, Cout, Cs from them.
+  const int *box_din = nullptr, *box_dout = nullptr;
+  int stage = 0;                  // launch_compose: 0 everything, 1 the scatter only, 2 the products only
+  CountTable counts;              // filled by the launchers when per-box degrees are set
 };
 hipError_t launch_compose(const ComposeArgs &a, hipStream_t s);
 // The input lists (ComposeArgs::live) of a.nboxes boxes (bids, h, recs,

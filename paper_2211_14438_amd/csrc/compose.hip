@@ -46,12 +46,40 @@ __device__ inline int64_t item_of(const ComposeArgs &a, int64_t g, int j, int s)
 __device__ inline int64_t pslots(const ComposeArgs &a) { return a.pstride > 0 ? a.pstride : a.nbx; }
 
 template <typename T>
+__device__ inline const T *in_tensor(const ComposeArgs &a, int64_t box, int j, int s, int64_t Cin) {
+  return reinterpret_cast<const T *>(a.pre) + box * a.slot_in + ((int64_t)j * a.nbounds + s) * Cin;
+}
+template <typename T>
+__device__ inline T *out_tensor(const ComposeArgs &a, int64_t box, int j, int s, int64_t Cout) {
+  return reinterpret_cast<T *>(a.post) + box * a.slot_out + ((int64_t)j * a.nbounds + s) * Cout;
+}
+template <typename T>
 __device__ inline const T *in_tensor(const ComposeArgs &a, int64_t box, int j, int s) {
-  return reinterpret_cast<const T *>(a.pre) + box * a.slot_in + ((int64_t)j * a.nbounds + s) * a.Cin;
+  return in_tensor<T>(a, box, j, s, a.Cin);
 }
 template <typename T>
 __device__ inline T *out_tensor(const ComposeArgs &a, int64_t box, int j, int s) {
-  return reinterpret_cast<T *>(a.post) + box * a.slot_out + ((int64_t)j * a.nbounds + s) * a.Cout;
+  return out_tensor<T>(a, box, j, s, a.Cout);
+}
+
+// A box's degrees and stored-coefficient counts in a launch: the launch's
+// own, or the box's from the per-box degree arrays.
+struct BoxDeg {
+  int Din, Dout;
+  int64_t Cin, Cout, Cs;
+};
+__device__ inline BoxDeg box_deg(const ComposeArgs &a, int64_t box) {
+  BoxDeg d{a.Din, a.Dout, a.Cin, a.Cout, a.Cs};
+  if (a.box_din) {
+    d.Din = box_degree(a.box_din, box);
+    d.Cin = a.counts.at(a.n, d.Din);
+  }
+  if (a.box_dout) {
+    d.Dout = box_degree(a.box_dout, box);
+    d.Cout = a.counts.at(a.n, d.Dout);
+  }
+  if (a.box_din || a.box_dout) d.Cs = a.counts.at(a.n, min(d.Din, d.Dout));
+  return d;
 }
 
 // Block-wide sums of (rounding, l1) in a fixed order; thread 0 writes them
@@ -437,15 +465,16 @@ __device__ void scatter_item(const ComposeArgs &a, int64_t g, int j, int s) {
   const int kind = r.kind;
   const NuSource ns = nu_of(a, &r, s);
   const int64_t it = item_of(a, g, j, s);
-  const T *p = in_tensor<T>(a, box, j, s);
-  T *out = out_tensor<T>(a, box, j, s);
+  const BoxDeg bd = box_deg(a, box);
+  const T *p = in_tensor<T>(a, box, j, s, bd.Cin);
+  T *out = out_tensor<T>(a, box, j, s, bd.Cout);
   // storage degree: Din, or the layer's post degree when that is lower (only
   // fallback and inactive neurons then); a prefix of the total-degree layout
-  const int Ds = min(a.Din, a.Dout);
-  const int64_t Cs = a.Cs;
+  const int Ds = min(bd.Din, bd.Dout);
+  const int64_t Cs = bd.Cs;
   double rsum = 0.0, l1sum = 0.0;
-  if (kind == 1 && Ds == a.Din) {  // these neurons take degree Din <= Dout
-    for (int64_t I = lane; I < a.Cin; I += 64) {
+  if (kind == 1 && Ds == bd.Din) {  // these neurons take degree Din <= Dout
+    for (int64_t I = lane; I < bd.Cin; I += 64) {
       double v = (double)p[I];
       if (I == 0) v += ns.shift - ns.lo;
       v = r.c[1] * (v / ns.w);
@@ -774,17 +803,18 @@ __global__ void __launch_bounds__(64) lin_stage_kernel(ComposeArgs a) {
   const int64_t box = wave_box(a, g);
   const int kind = a.recs[box * a.h + j].kind;
   if (kind >= 2) continue;
-  T *out = out_tensor<T>(a, box, j, s);
+  const BoxDeg bd = box_deg(a, box);
+  T *out = out_tensor<T>(a, box, j, s, bd.Cout);
   int64_t from = 0;
   if (kind == kActive) {  // degree Din <= Dout (the box's post degree is the largest)
-    const T *p = in_tensor<T>(a, box, j, s);
-    const int64_t cc = min(a.Cin, a.Cout);
+    const T *p = in_tensor<T>(a, box, j, s, bd.Cin);
+    const int64_t cc = min(bd.Cin, bd.Cout);
     for (int64_t I = lane; I < cc; I += 64) out[I] = p[I];
     from = cc;
   } else if (kind == 1 || kind == kFallback) {
-    from = a.Cs;
+    from = bd.Cs;
   }
-  for (int64_t I = from + lane; I < a.Cout; I += 64) out[I] = (T)0;
+  for (int64_t I = from + lane; I < bd.Cout; I += 64) out[I] = (T)0;
   }
 }
 
@@ -828,10 +858,13 @@ __global__ void __launch_bounds__(kBlock) lin_scatter_kernel(ComposeArgs a, Neur
 hipError_t launch_lin_stage(const ComposeArgs &a_in, hipStream_t s) {
   if (a_in.nboxes < 1) return hipSuccess;
   // a class below its pre degree (Dout < Din) holds fallback and inactive
-  // neurons only
-  if (a_in.Cs > a_in.Cout || a_in.nbounds != 2) return hipErrorInvalidValue;
+  // neurons only (with per-box degrees this holds by construction: a box's
+  // post degree is the largest of its neurons')
+  const bool per_box = a_in.box_din || a_in.box_dout;
+  if ((!per_box && a_in.Cs > a_in.Cout) || a_in.nbounds != 2) return hipErrorInvalidValue;
   ComposeArgs a = a_in;
   a.group = 1;
+  if (per_box) a.counts.fill(a.n);
   const int64_t items = a.nboxes * a.h * a.nbounds;
   ProfScope ps(kProfLin, s, 0.0);
   if (a.fp64)
@@ -961,7 +994,7 @@ template <typename T>
 static hipError_t compose_all(const ComposeArgs &a_in, hipStream_t s) {
   ComposeArgs a = a_in;
   // with a device count the lists and radii are the caller's, over all boxes
-  if (a.dcount && (!a.lists_ready || !a.radii_later)) return hipErrorInvalidValue;
+  if ((a.dcount || a.stage != 0) && (!a.lists_ready || !a.radii_later)) return hipErrorInvalidValue;
   const unsigned gx = (unsigned)a.nbx;
   // many items: a wave takes a group of items and reads their kinds at
   // once; 64 for the scatter (its items are few and light), 8 for the
@@ -974,7 +1007,7 @@ static hipError_t compose_all(const ComposeArgs &a_in, hipStream_t s) {
                        s, a);
     RET_IF(hipGetLastError());
   }
-  {
+  if (a.stage != 2) {
     ProfScope ps(kProfComposeSimple, s, 0.0);
     ComposeArgs ag = a;
     ag.group = group ? 16 : 1;
@@ -985,6 +1018,8 @@ static hipError_t compose_all(const ComposeArgs &a_in, hipStream_t s) {
     RET_IF(hipGetLastError());
   }
   const size_t lds = (size_t)a.Cin * sizeof(double);
+  if (a.stage == 1) return hipSuccess;  // the products run per class
+  if (a.box_din || a.box_dout) return hipErrorInvalidValue;  // products take one (Din, Dout) class
   if (a.Lmax >= 2) {
     if (!a.sq_off || kComposeWaves * lds > device_lds_limit() || (int64_t)gx * kBlock < a.Cout)
       return hipErrorInvalidValue;
@@ -1035,7 +1070,9 @@ hipError_t launch_live(const ComposeArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_compose(const ComposeArgs &a, hipStream_t s) {
+hipError_t launch_compose(const ComposeArgs &a_in, hipStream_t s) {
+  ComposeArgs a = a_in;
+  if (a.box_din || a.box_dout) a.counts.fill(a.n);
   return a.fp64 ? compose_all<double>(a, s) : compose_all<float>(a, s);
 }
 

@@ -310,7 +310,7 @@ __device__ void finish_neuron(const ConvertArgs &a, int64_t box, int j, double l
 }
 
 // One block per (box, neuron): both bounds of the neuron, all axes in LDS.
-template <typename T, bool kLoop>
+template <typename T>
 __global__ void __launch_bounds__(kBlock) convert_small_kernel(ConvertArgs a) {
   extern __shared__ double lds[];
   const int D1 = a.D + 1;
@@ -319,8 +319,8 @@ __global__ void __launch_bounds__(kBlock) convert_small_kernel(ConvertArgs a) {
   double *red = tab + D1 * D1;
   __shared__ double fit[2][kMaxInputs + 1];
   __shared__ double ext[4];  // rmaxU, rminU, rmaxL, rminL
-  const int64_t items = loop_boxes<kLoop>(a) * a.h;
-  for (int64_t item = blockIdx.x; item < items; item = next_item<kLoop>(item, gridDim.x, items)) {  // launch box * h + j
+  const int64_t item = blockIdx.x;  // launch box * h + j
+  if (item >= launch_boxes(a) * a.h) return;
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
   const int j = (int)(item % a.h);
   fill_table(tab, a.D);
@@ -368,8 +368,6 @@ __global__ void __launch_bounds__(kBlock) convert_small_kernel(ConvertArgs a) {
       if (a.out_hi) a.out_hi[box * a.ld_out + a.col0 + j] = hi;
       finish_neuron(a, box, j, lo, hi, epsU, epsL, l1s[0], l1s[1], fit, ext, want_fit);
     }
-  }
-  if constexpr (kLoop) __syncthreads();  // the next item rewrites the shared tensor, fits and extrema
   }
 }
 
@@ -446,7 +444,7 @@ __device__ void wave_affine_fit(const double *t, int C, int n, int D, int lane, 
   rmin = wave_reduce(lo, OpMin());
 }
 
-template <typename T, bool kLoop>
+template <typename T>
 __global__ void __launch_bounds__(kBlock) convert_wave_kernel(ConvertArgs a) {
   extern __shared__ double lds[];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -455,9 +453,8 @@ __global__ void __launch_bounds__(kBlock) convert_wave_kernel(ConvertArgs a) {
   double *tab = lds;
   double *tw = lds + D1 * D1 + (int64_t)wv * 2 * C;  // [2][C]: lower, upper
   fill_table(tab, a.D);
-  const int64_t items = loop_boxes<kLoop>(a) * a.h;
-  for (int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + wv; item < items;
-       item = next_item<kLoop>(item, (int64_t)gridDim.x * (kBlock / 64), items)) {
+  const int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + wv;
+  if (item >= launch_boxes(a) * a.h) return;
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
   const int j = (int)(item % a.h);
   double ext[2], l1s[2];
@@ -498,8 +495,6 @@ __global__ void __launch_bounds__(kBlock) convert_wave_kernel(ConvertArgs a) {
       if (a.out_hi) a.out_hi[box * a.ld_out + a.col0 + j] = hi;
       finish_neuron(a, box, j, lo, hi, epsU, epsL, l1s[0], l1s[1], fit, fx, want_fit);
     }
-  }
-  if constexpr (kLoop) wave_sync();  // the wave's next item rewrites its slice
   }
 }
 
@@ -1017,7 +1012,7 @@ __host__ __device__ constexpr int wave_slice_doubles(int C) { return kRowScratch
 
 // One wave per (box, neuron), one bound tensor at a time in the wave's LDS
 // slice.
-template <int D, typename T, bool kLoop>
+template <int D, typename T>
 __global__ void __launch_bounds__(kBlock, 6) convert_wave_t(ConvertArgs a) {
   extern __shared__ double lds[];
   const WaveTeam tm{(int)(threadIdx.x & 63)};
@@ -1025,31 +1020,26 @@ __global__ void __launch_bounds__(kBlock, 6) convert_wave_t(ConvertArgs a) {
   const int C = (int)a.C;
   const int *pl = stage_prefixes(a, reinterpret_cast<int *>(lds));
   double *tw = lds + (a.plist_len + 1) / 2 + (int64_t)wv * wave_slice_doubles(C);
-  const int64_t items = loop_boxes<kLoop>(a) * a.h;
-  for (int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + wv; item < items;
-       item = next_item<kLoop>(item, (int64_t)gridDim.x * (kBlock / 64), items)) {
-    const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
-    const WaveTeam tmw{tm.tid, tw};
-    readoff_pair<D, T>(a, tmw, true, tm.tid, tw + kRowScratch, tw + kRowScratch + C, pl, box, (int)(item % a.h));
-    if constexpr (kLoop) wave_sync();
-  }
+  const int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + wv;
+  if (item >= launch_boxes(a) * a.h) return;
+  const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
+  const WaveTeam tmw{tm.tid, tw};
+  readoff_pair<D, T>(a, tmw, true, tm.tid, tw + kRowScratch, tw + kRowScratch + C, pl, box, (int)(item % a.h));
 }
 
 // One block per (box, neuron) for tensors up to kSmallLds coefficients, one
 // tensor in LDS at a time.
-template <int D, typename T, bool kLoop>
+template <int D, typename T>
 __global__ void __launch_bounds__(1024) convert_block_t(ConvertArgs a) {
   extern __shared__ double lds[];
   __shared__ double red[kRedDoubles];
   const BlockTeam tm{(int)threadIdx.x, (int)blockDim.x, red};
   const int *pl = stage_prefixes(a, reinterpret_cast<int *>(lds));
   double *t = lds + (a.plist_len + 1) / 2;
-  const int64_t items = loop_boxes<kLoop>(a) * a.h;
-  for (int64_t item = blockIdx.x; item < items; item = next_item<kLoop>(item, gridDim.x, items)) {
-    const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
-    readoff_pair<D, T>(a, tm, threadIdx.x < 64, (int)(threadIdx.x & 63), t, t + a.C, pl, box, (int)(item % a.h));
-    if constexpr (kLoop) __syncthreads();
-  }
+  const int64_t item = blockIdx.x;
+  if (item >= launch_boxes(a) * a.h) return;
+  const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
+  readoff_pair<D, T>(a, tm, threadIdx.x < 64, (int)(threadIdx.x & 63), t, t + a.C, pl, box, (int)(item % a.h));
 }
 
 // Degree 1 (every first hidden layer, and neurons whose plan keeps degree
@@ -1071,14 +1061,13 @@ __device__ __forceinline__ double aff_sum(double v) {
   return v;
 }
 
-template <typename T, int kL, bool kLoop>
+template <typename T, int kL>
 __global__ void __launch_bounds__(kBlock) convert_affine_kernel(ConvertArgs a) {
   constexpr int kAffLanes = kL;
   constexpr int kR = (kMaxInputs + 1 + kL - 1) / kL;  // coefficient slots per lane
   const int l = threadIdx.x % kAffLanes;
-  const int64_t items = loop_boxes<kLoop>(a) * a.h;
-  for (int64_t item = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kAffLanes; item < items;
-       item = next_item<kLoop>(item, (int64_t)gridDim.x * (blockDim.x / kAffLanes), items)) {  // whole teams leave together
+  const int64_t item = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kAffLanes;
+  if (item >= launch_boxes(a) * a.h) return;  // whole teams leave together
   const int S = (int)a.S;
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
   const int j = (int)(item % a.h);
@@ -1110,7 +1099,7 @@ __global__ void __launch_bounds__(kBlock) convert_affine_kernel(ConvertArgs a) {
       rec.fbpadU = a.fp64 ? 0.0 : rec.padU;
       rec.fbpadL = a.fp64 ? 0.0 : rec.padL;
     }
-    continue;
+    return;
   }
   double epsU = 0.0, epsL = 0.0;
   if (!a.fp64) {
@@ -1194,7 +1183,6 @@ __global__ void __launch_bounds__(kBlock) convert_affine_kernel(ConvertArgs a) {
   }
   // an unfitted neuron's fit fields are never read (fitted == 0)
   if (l == 0) write_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, fx, fitted, true);
-  }
 }
 
 // Executed-work counts of the read-off kernels, for the profiler (host).
@@ -1274,18 +1262,12 @@ static hipError_t launch_affine(const ConvertArgs &a, hipStream_t s) {
                a.nboxes * a.h * readoff_neuron_bytes(a) + a.nboxes * readoff_box_bytes(a),
                (double)a.nboxes * a.h * affine_ops(a));
   const int64_t teams = a.nboxes * a.h;
-  const int lanes = a.S <= 8 ? 8 : 16;
-  const dim3 grid((unsigned)dev_grid((teams * lanes + kBlock - 1) / kBlock, a.dcount));
-  if (lanes == 8) {
-    if (a.dcount)
-      hipLaunchKernelGGL((convert_affine_kernel<T, 8, true>), grid, dim3(kBlock), 0, s, a);
-    else
-      hipLaunchKernelGGL((convert_affine_kernel<T, 8, false>), grid, dim3(kBlock), 0, s, a);
+  if (a.S <= 8) {
+    hipLaunchKernelGGL((convert_affine_kernel<T, 8>), dim3((unsigned)((teams * 8 + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, s, a);
   } else {
-    if (a.dcount)
-      hipLaunchKernelGGL((convert_affine_kernel<T, 16, true>), grid, dim3(kBlock), 0, s, a);
-    else
-      hipLaunchKernelGGL((convert_affine_kernel<T, 16, false>), grid, dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((convert_affine_kernel<T, 16>), dim3((unsigned)((teams * 16 + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, s, a);
   }
   return hipGetLastError();
 }
@@ -1464,13 +1446,14 @@ struct TreePlan {
   int S[kMaxInputs + 1] = {};  // S(d, D), d = 0 .. n
 };
 
-template <int D, int M, typename T, bool kLoop>
+template <int D, int M, typename T>
 __global__ void __launch_bounds__(1024) convert_tree_t(ConvertArgs a, TreePlan tp, double *partial,
                                                        double *l1part) {
   extern __shared__ double lds[];
   __shared__ double red[16];
   constexpr int D1 = D + 1;
   constexpr Ratio<D> R{};
+  if ((int64_t)blockIdx.y >= launch_boxes(a) * a.h * 2) return;  // past a device count
   const int tid = threadIdx.x, nt = blockDim.x, n = a.n;
   const BlockTeam bt{tid, nt, red};
   // LDS: child tables (ints), ratio table, root, chain levels, expansions
@@ -1490,9 +1473,7 @@ __global__ void __launch_bounds__(1024) convert_tree_t(ConvertArgs a, TreePlan t
 #pragma unroll
     for (int i = 0; i < D1 * D1; ++i) tab[i] = R.v[i / D1][i % D1];
   }
-  const int64_t tensors = loop_boxes<kLoop>(a) * a.h * 2;
-  for (int64_t tensor = blockIdx.y; tensor < tensors; tensor = next_item<kLoop>(tensor, gridDim.y, tensors)) {
-  if constexpr (kLoop) __syncthreads();  // the previous tensor's last reads of the root and chain are done
+  const int64_t tensor = blockIdx.y;
   const int side = (int)(tensor & 1);  // 1: lower bound tensor (minimum), 0: upper (maximum)
   const int64_t gb = tensor / (2 * a.h), rest = tensor % (2 * a.h);
   const int64_t box = a.bids ? a.bids[gb] : gb;
@@ -1573,24 +1554,16 @@ __global__ void __launch_bounds__(1024) convert_tree_t(ConvertArgs a, TreePlan t
   }
   const double v = side ? bt.min(ext) : bt.max(ext);
   if (tid == 0) partial[tensor * tp.nchunk + blockIdx.x] = v;
-  }
 }
 
 template <typename T, int D>
 static hipError_t launch_tree_t(const ConvertArgs &a, const TreePlan &tp, size_t lds, double *partial,
                                 double *l1part, hipStream_t s) {
   constexpr int M = tree_tile_axes(D);
-  const dim3 grid((unsigned)tp.nchunk, (unsigned)dev_grid(a.nboxes * a.h * 2, a.dcount));
-  if (a.dcount) {
-    RET_IF(hipFuncSetAttribute((const void *)convert_tree_t<D, M, T, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds));
-    hipLaunchKernelGGL((convert_tree_t<D, M, T, true>), grid, dim3((unsigned)tp.threads), lds, s, a, tp, partial, l1part);
-  } else {
-    RET_IF(hipFuncSetAttribute((const void *)convert_tree_t<D, M, T, false>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL((convert_tree_t<D, M, T, false>), grid, dim3((unsigned)tp.threads), lds, s, a, tp, partial,
-                       l1part);
-  }
+  RET_IF(hipFuncSetAttribute((const void *)convert_tree_t<D, M, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds));
+  hipLaunchKernelGGL((convert_tree_t<D, M, T>), dim3((unsigned)tp.nchunk, (unsigned)(a.nboxes * a.h * 2)),
+                     dim3((unsigned)tp.threads), lds, s, a, tp, partial, l1part);
   return hipGetLastError();
 }
 
@@ -1876,12 +1849,17 @@ __device__ void ntree_neuron(const ConvertArgs &a, const NTreePlan &tp, const Te
 // wave is scheduled (and its LDS slice freed) on its own.
 constexpr int kNTeams = 1;
 
-template <int D, int M, typename T, bool kWave, bool kSide, bool kLoop>
+template <int D, int M, typename T, bool kWave, bool kSide = false>
 __global__ void __launch_bounds__(kWave ? 64 * kNTeams : 1024) convert_ntree_t(ConvertArgs a, NTreePlan tp) {
   extern __shared__ double lds[];
   __shared__ double red[kRedDoubles];
   constexpr int D1 = D + 1;
   constexpr Ratio<D> R{};
+  {  // blocks past a device count leave before staging anything
+    const int64_t items = launch_boxes(a) * a.h;
+    const int64_t first = kWave ? (int64_t)blockIdx.x * (blockDim.x >> 6) : (int64_t)blockIdx.x;
+    if (first >= (kSide ? 2 * items : items)) return;
+  }
   int *tb = reinterpret_cast<int *>(lds);
   for (int i = threadIdx.x; i < a.tree_len; i += blockDim.x) tb[i] = a.tree[i];
   double *tab = lds + (a.tree_len + 1) / 2;
@@ -1891,29 +1869,19 @@ __global__ void __launch_bounds__(kWave ? 64 * kNTeams : 1024) convert_ntree_t(C
   }
   __syncthreads();
   double *slices = tab + D1 * D1;  // per team: fits (upper, lower), then the two trees
-  const int64_t items = loop_boxes<kLoop>(a) * a.h;
   if (kWave) {
     const int wv = threadIdx.x >> 6;
+    const int64_t item = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
+    if (item >= launch_boxes(a) * a.h) return;
     double *slice = slices + (int64_t)wv * (kRowScratch + 2 * (kMaxInputs + 1) + 2 * tp.area);
     const WaveTeam tm{(int)(threadIdx.x & 63), slice};
-    for (int64_t item = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv; item < items;
-         item = next_item<kLoop>(item, (int64_t)gridDim.x * (blockDim.x >> 6), items)) {
-      ntree_neuron<D, M, T, true>(a, tp, tm, tb, tab, slice + kRowScratch, item);
-      if constexpr (kLoop) tm.sync();  // the wave's next item rewrites its slice
-    }
+    ntree_neuron<D, M, T, true>(a, tp, tm, tb, tab, slice + kRowScratch, item);
   } else {
     const BlockTeam tm{(int)threadIdx.x, (int)blockDim.x, red};
-    if constexpr (kSide) {
-      for (int64_t vb = blockIdx.x; vb < 2 * items; vb = next_item<kLoop>(vb, gridDim.x, 2 * items)) {
-        ntree_output_side<D, M, T>(a, tp, tm, tb, tab, slices, vb >> 1, (int)(vb & 1));
-        if constexpr (kLoop) __syncthreads();
-      }
-    } else {
-      for (int64_t vb = blockIdx.x; vb < items; vb = next_item<kLoop>(vb, gridDim.x, items)) {
-        ntree_neuron<D, M, T, false>(a, tp, tm, tb, tab, slices, vb);
-        if constexpr (kLoop) __syncthreads();
-      }
-    }
+    if constexpr (kSide)
+      ntree_output_side<D, M, T>(a, tp, tm, tb, tab, slices, blockIdx.x >> 1, (int)(blockIdx.x & 1));
+    else
+      ntree_neuron<D, M, T, false>(a, tp, tm, tb, tab, slices, blockIdx.x);
   }
 }
 
@@ -1922,7 +1890,7 @@ static size_t ntree_lds(const NTreePlan &tp, int n, int D, int teams, bool wave)
 
 
 
-template <typename T, int D, int M, bool kLoop>
+template <typename T, int D, int M>
 static bool launch_ntree(const ConvertArgs &a, hipStream_t s, bool wave_team, hipError_t &err) {
   const NTreePlan tp = ntree_plan(a.n, D, M, wave_team);
   if (tp.e < 1) return false;
@@ -1934,10 +1902,10 @@ static bool launch_ntree(const ConvertArgs &a, hipStream_t s, bool wave_team, hi
   if (tp.threads == 64) {  // a wave per neuron, kNTeams per block
     const size_t lds = ntree_lds(tp, a.n, D, kNTeams, true);
     if (lds <= device_lds_limit()) {
-      err = hipFuncSetAttribute((const void *)convert_ntree_t<D, M, T, true, false, kLoop>,
+      err = hipFuncSetAttribute((const void *)convert_ntree_t<D, M, T, true>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (err != hipSuccess) return true;
-      hipLaunchKernelGGL((convert_ntree_t<D, M, T, true, false, kLoop>), dim3((unsigned)dev_grid((items + kNTeams - 1) / kNTeams, a.dcount)),
+      hipLaunchKernelGGL((convert_ntree_t<D, M, T, true>), dim3((unsigned)((items + kNTeams - 1) / kNTeams)),
                          dim3(64 * kNTeams), lds, s, a, tp);
       err = hipGetLastError();
       return true;
@@ -1947,26 +1915,26 @@ static bool launch_ntree(const ConvertArgs &a, hipStream_t s, bool wave_team, hi
     const NTreePlan t1 = ntree_plan(a.n, D, M, false, 1);
     if (t1.e >= 1) {
       const size_t l1 = ntree_lds(t1, a.n, D, 1, false);
-      err = hipFuncSetAttribute((const void *)convert_ntree_t<D, M, T, false, true, kLoop>,
+      err = hipFuncSetAttribute((const void *)convert_ntree_t<D, M, T, false, true>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)l1);
       if (err != hipSuccess) return true;
-      hipLaunchKernelGGL((convert_ntree_t<D, M, T, false, true, kLoop>), dim3((unsigned)dev_grid(items * 2, a.dcount)), dim3((unsigned)t1.threads),
+      hipLaunchKernelGGL((convert_ntree_t<D, M, T, false, true>), dim3((unsigned)(items * 2)), dim3((unsigned)t1.threads),
                          l1, s, a, t1);
       err = hipGetLastError();
       return true;
     }
   }
   const size_t lds = ntree_lds(tp, a.n, D, 1, false);
-  err = hipFuncSetAttribute((const void *)convert_ntree_t<D, M, T, false, false, kLoop>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  err = hipFuncSetAttribute((const void *)convert_ntree_t<D, M, T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
   if (err != hipSuccess) return true;
-  hipLaunchKernelGGL((convert_ntree_t<D, M, T, false, false, kLoop>), dim3((unsigned)dev_grid(items, a.dcount)), dim3((unsigned)tp.threads), lds, s, a,
+  hipLaunchKernelGGL((convert_ntree_t<D, M, T, false>), dim3((unsigned)items), dim3((unsigned)tp.threads), lds, s, a,
                      tp);
   err = hipGetLastError();
   return true;
 }
 
-template <typename T, int D, bool kLoop>
+template <typename T, int D>
 static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
   // degree 1 tensors are read off in closed form, whatever n; the tree needs
   // D >= 2 to pay for its levels
@@ -1975,24 +1943,24 @@ static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
   } else {
     if (a.tree) {
       hipError_t err = hipSuccess;
-      if (a.tune.conv_wave == 0 && launch_ntree<T, D, ntree_tile_axes(D), kLoop>(a, s, false, err)) return err;
-      if (a.tune.conv_wave == 3 && launch_ntree<T, D, ntree_tile_axes(D), kLoop>(a, s, true, err)) return err;
+      if (a.tune.conv_wave == 0 && launch_ntree<T, D, ntree_tile_axes(D)>(a, s, false, err)) return err;
+      if (a.tune.conv_wave == 3 && launch_ntree<T, D, ntree_tile_axes(D)>(a, s, true, err)) return err;
     }
     const size_t plb = (size_t)((a.plist_len + 1) / 2) * sizeof(double);
     if (a.C <= kWaveC && a.tune.conv_wave <= 1) {
       const size_t lds = (size_t)(kBlock / 64) * wave_slice_doubles((int)a.C) * sizeof(double) + plb;
-      RET_IF(hipFuncSetAttribute((const void *)convert_wave_t<D, T, kLoop>, hipFuncAttributeMaxDynamicSharedMemorySize,
+      RET_IF(hipFuncSetAttribute((const void *)convert_wave_t<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)lds));
       ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4),
                    (double)a.nboxes * a.h * 2 * a.n * a.C * (a.D + 2));
       const int64_t items = a.nboxes * a.h;
-      hipLaunchKernelGGL((convert_wave_t<D, T, kLoop>), dim3((unsigned)dev_grid((items + kBlock / 64 - 1) / (kBlock / 64), a.dcount)),
+      hipLaunchKernelGGL((convert_wave_t<D, T>), dim3((unsigned)((items + kBlock / 64 - 1) / (kBlock / 64))),
                          dim3(kBlock), lds, s, a);
       return hipGetLastError();
     }
     const size_t lds = (size_t)(a.C + 2 * (kMaxInputs + 1)) * sizeof(double) + plb;
     if (lds + 256 > device_lds_limit()) return hipErrorInvalidValue;
-    RET_IF(hipFuncSetAttribute((const void *)convert_block_t<D, T, kLoop>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    RET_IF(hipFuncSetAttribute((const void *)convert_block_t<D, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
     // a block per neuron; when few blocks share a CU's LDS, more waves each
     static const unsigned kThreads[4] = {0, 256, 512, 1024};
@@ -2000,29 +1968,24 @@ static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
                                                                             : (lds > 40 * 1024 ? 1024 : 256);
     ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4),
                  (double)a.nboxes * a.h * 2 * a.n * a.C * (a.D + 2));
-    hipLaunchKernelGGL((convert_block_t<D, T, kLoop>), dim3((unsigned)dev_grid(a.nboxes * a.h, a.dcount)), dim3(threads), lds, s, a);
+    hipLaunchKernelGGL((convert_block_t<D, T>), dim3((unsigned)(a.nboxes * a.h)), dim3(threads), lds, s, a);
     return hipGetLastError();
-  }
-}
-
-template <typename T, bool kLoop>
-static hipError_t launch_convert_fixed_l(const ConvertArgs &a, hipStream_t s) {
-  switch (a.D) {
-    case 1: return launch_convert_t<T, 1, kLoop>(a, s);
-    case 2: return launch_convert_t<T, 2, kLoop>(a, s);
-    case 3: return launch_convert_t<T, 3, kLoop>(a, s);
-    case 4: return launch_convert_t<T, 4, kLoop>(a, s);
-    case 5: return launch_convert_t<T, 5, kLoop>(a, s);
-    case 6: return launch_convert_t<T, 6, kLoop>(a, s);
-    case 7: return launch_convert_t<T, 7, kLoop>(a, s);
-    case 8: return launch_convert_t<T, 8, kLoop>(a, s);
-    default: return hipErrorInvalidValue;
   }
 }
 
 template <typename T>
 static hipError_t launch_convert_fixed(const ConvertArgs &a, hipStream_t s) {
-  return a.dcount ? launch_convert_fixed_l<T, true>(a, s) : launch_convert_fixed_l<T, false>(a, s);
+  switch (a.D) {
+    case 1: return launch_convert_t<T, 1>(a, s);
+    case 2: return launch_convert_t<T, 2>(a, s);
+    case 3: return launch_convert_t<T, 3>(a, s);
+    case 4: return launch_convert_t<T, 4>(a, s);
+    case 5: return launch_convert_t<T, 5>(a, s);
+    case 6: return launch_convert_t<T, 6>(a, s);
+    case 7: return launch_convert_t<T, 7>(a, s);
+    case 8: return launch_convert_t<T, 8>(a, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // ---------------------------------------------------------- two-pass path
@@ -2058,15 +2021,15 @@ static Split make_split(int n, int D) {
 }
 
 // Pass A: one block per (tensor, outer slice): convert the m trailing axes.
-template <typename T, bool kLoop>
+template <typename T>
 __global__ void __launch_bounds__(kBlock) convert_passA_kernel(ConvertArgs a, Split sp, double *l1part) {
   extern __shared__ double lds[];
   const int D1 = a.D + 1;
   double *t = lds;
   double *tab = lds + sp.Ci;
+  const int64_t tensor = blockIdx.y;  // (box*h + j)*2 + s
+  if (tensor >= launch_boxes(a) * a.h * 2) return;
   const int64_t o = blockIdx.x;
-  const int64_t tensors = loop_boxes<kLoop>(a) * a.h * 2;
-  for (int64_t tensor = blockIdx.y; tensor < tensors; tensor = next_item<kLoop>(tensor, gridDim.y, tensors)) {  // (box*h + j)*2 + s
   fill_table(tab, a.D);
   double *red = tab + D1 * D1;
   const int64_t gb = tensor / (2 * a.h), rest = tensor % (2 * a.h);
@@ -2089,22 +2052,19 @@ __global__ void __launch_bounds__(kBlock) convert_passA_kernel(ConvertArgs a, Sp
   double *q = a.scratch + tensor * a.C + o * sp.Ci;
   for (int64_t i = threadIdx.x; i < sp.Ci; i += blockDim.x) q[i] = t[i];
   if (threadIdx.x == 0) l1part[tensor * sp.Co + o] = l1;
-  if constexpr (kLoop) __syncthreads();
-  }
 }
 
 // Pass B: one block per (tensor, column chunk): convert the n-m leading axes
 // of a [Co][Q] tile and reduce it to one extremum (min for lower bounds,
 // max for upper bounds) written to the partials area.
-template <bool kLoop>
 __global__ void __launch_bounds__(kBlock) convert_passB_kernel(ConvertArgs a, Split sp, double *partial) {
   extern __shared__ double lds[];
   const int D1 = a.D + 1;
   double *t = lds;                      // [Co][Q]
   double *tab = lds + sp.Co * sp.Q;
   double *red = tab + D1 * D1;
-  const int64_t tensors = loop_boxes<kLoop>(a) * a.h * 2;
-  for (int64_t tensor = blockIdx.y; tensor < tensors; tensor = next_item<kLoop>(tensor, gridDim.y, tensors)) {
+  const int64_t tensor = blockIdx.y;
+  if (tensor >= launch_boxes(a) * a.h * 2) return;
   const int s = (int)(tensor & 1);
   const int64_t q0 = (int64_t)blockIdx.x * sp.Q;
   const int64_t qn = min(sp.Q, sp.Ci - q0);
@@ -2137,18 +2097,14 @@ __global__ void __launch_bounds__(kBlock) convert_passB_kernel(ConvertArgs a, Sp
   }
   v = s ? block_reduce(v, OpMin(), red) : block_reduce(v, OpMax(), red);
   if (threadIdx.x == 0) partial[tensor * sp.nchunk + blockIdx.x] = v;
-  if constexpr (kLoop) __syncthreads();
-  }
 }
 
 // Fold the per-chunk extrema of both bounds of one neuron: one wave each.
-template <bool kLoop>
 __global__ void __launch_bounds__(kBlock) convert_final_kernel(ConvertArgs a, Split sp, const double *partial,
                                                                const double *l1part) {
   const int lane = threadIdx.x & 63;
-  const int64_t items = loop_boxes<kLoop>(a) * a.h;
-  for (int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); item < items;
-       item = next_item<kLoop>(item, (int64_t)gridDim.x * (kBlock / 64), items)) {
+  const int64_t item = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (item >= launch_boxes(a) * a.h) return;
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
   const int j = (int)(item % a.h);
   double mn = INFINITY, mx = -INFINITY, l1U = 0.0, l1L = 0.0;
@@ -2167,15 +2123,13 @@ __global__ void __launch_bounds__(kBlock) convert_final_kernel(ConvertArgs a, Sp
   double lo, hi, epsU, epsL;
   padded_bounds(a, box, j, mn, mx, l1L, l1U, lane, 64, [](double v) { return wave_reduce(v, OpAdd()); }, lo, hi,
                 epsU, epsL);
-  if (lane == 0) {
-    if (a.mode == 1) {
-      write_output(a, box, j, lo, hi, epsU, epsL);
-    } else {
-      if (a.out_lo) a.out_lo[box * a.ld_out + a.col0 + j] = lo;
-      if (a.out_hi) a.out_hi[box * a.ld_out + a.col0 + j] = hi;
-      finish_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, nullptr, nullptr, false);
-    }
-  }
+  if (lane != 0) return;
+  if (a.mode == 1) {
+    write_output(a, box, j, lo, hi, epsU, epsL);
+  } else {
+    if (a.out_lo) a.out_lo[box * a.ld_out + a.col0 + j] = lo;
+    if (a.out_hi) a.out_hi[box * a.ld_out + a.col0 + j] = hi;
+    finish_neuron(a, box, j, lo, hi, epsU, epsL, l1U, l1L, nullptr, nullptr, false);
   }
 }
 
@@ -2378,24 +2332,21 @@ hipError_t launch_convert(const ConvertArgs &a_in, hipStream_t s) {
     return a.fp64 ? launch_convert_fixed<double>(a, s) : launch_convert_fixed<float>(a, s);
   if (a.C <= kWaveC) {
     const size_t lds = (D1 * D1 + (kBlock / 64) * 2 * a.C) * sizeof(double);
-    auto k = a.fp64 ? (a.dcount ? convert_wave_kernel<double, true> : convert_wave_kernel<double, false>)
-                    : (a.dcount ? convert_wave_kernel<float, true> : convert_wave_kernel<float, false>);
+    auto k = a.fp64 ? convert_wave_kernel<double> : convert_wave_kernel<float>;
     RET_IF(hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4),
                  (double)a.nboxes * a.h * 2 * a.n * a.C * (a.D + 2));
     const int64_t items = a.nboxes * a.h;
-    hipLaunchKernelGGL(k, dim3((unsigned)dev_grid((items + kBlock / 64 - 1) / (kBlock / 64), a.dcount)), dim3(kBlock),
-                       lds, s, a);
+    hipLaunchKernelGGL(k, dim3((unsigned)((items + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), lds, s, a);
     return hipGetLastError();
   }
   if (use_small(a.C)) {
     const size_t lds = (a.C + D1 * D1 + 16) * sizeof(double);
-    auto k = a.fp64 ? (a.dcount ? convert_small_kernel<double, true> : convert_small_kernel<double, false>)
-                    : (a.dcount ? convert_small_kernel<float, true> : convert_small_kernel<float, false>);
+    auto k = a.fp64 ? convert_small_kernel<double> : convert_small_kernel<float>;
     RET_IF(hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     ProfScope ps(kProfConvertSmall, s, (double)a.nboxes * a.h * 2 * a.S * (a.fp64 ? 8 : 4),
                  (double)a.nboxes * a.h * 2 * a.n * a.C * (a.D + 2));
-    hipLaunchKernelGGL(k, dim3((unsigned)dev_grid(a.nboxes * a.h, a.dcount)), dim3(kBlock), lds, s, a);
+    hipLaunchKernelGGL(k, dim3((unsigned)(a.nboxes * a.h)), dim3(kBlock), lds, s, a);
     return hipGetLastError();
   }
   const int64_t tensors = a.nboxes * a.h * 2;
@@ -2422,8 +2373,7 @@ hipError_t launch_convert(const ConvertArgs &a_in, hipStream_t s) {
     fsp.nchunk = tp.nchunk;
     fsp.Co = 1;
     ProfScope ps(kProfConvertFinal, s, (double)tensors * tp.nchunk * 8);
-    auto fk = a.dcount ? convert_final_kernel<true> : convert_final_kernel<false>;
-    hipLaunchKernelGGL(fk, dim3((unsigned)dev_grid((a.nboxes * a.h + 3) / 4, a.dcount)), dim3(kBlock), 0, s, b, fsp,
+    hipLaunchKernelGGL(convert_final_kernel, dim3((unsigned)((a.nboxes * a.h + 3) / 4)), dim3(kBlock), 0, s, b, fsp,
                        (const double *)partial, (const double *)l1part);
     return hipGetLastError();
   }
@@ -2435,27 +2385,21 @@ hipError_t launch_convert(const ConvertArgs &a_in, hipStream_t s) {
                                               align256((size_t)a.nboxes * a.h * 2 * sp.nchunk * sizeof(double)));
   {
     const size_t lds = (sp.Ci + D1 * D1 + 16) * sizeof(double);
-    auto k = a.fp64 ? (a.dcount ? convert_passA_kernel<double, true> : convert_passA_kernel<double, false>)
-                    : (a.dcount ? convert_passA_kernel<float, true> : convert_passA_kernel<float, false>);
+    auto k = a.fp64 ? convert_passA_kernel<double> : convert_passA_kernel<float>;
     RET_IF(hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     ProfScope ps(kProfConvertPassA, s, (double)tensors * (a.S * (a.fp64 ? 8 : 4) + a.C * 8));
-    hipLaunchKernelGGL(k, dim3((unsigned)sp.Co, (unsigned)dev_grid(tensors, a.dcount)), dim3(kBlock), lds, s, a, sp,
-                       l1part);
+    hipLaunchKernelGGL(k, dim3((unsigned)sp.Co, (unsigned)tensors), dim3(kBlock), lds, s, a, sp, l1part);
   }
   {
     const size_t lds = (sp.Co * sp.Q + D1 * D1 + 16) * sizeof(double);
-    auto k = a.dcount ? convert_passB_kernel<true> : convert_passB_kernel<false>;
-    RET_IF(hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    RET_IF(hipFuncSetAttribute((const void *)convert_passB_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     ProfScope ps(kProfConvertPassB, s, (double)tensors * a.C * 8);
-    hipLaunchKernelGGL(k, dim3((unsigned)sp.nchunk, (unsigned)dev_grid(tensors, a.dcount)),
-                       dim3(kBlock), lds, s, a,
+    hipLaunchKernelGGL(convert_passB_kernel, dim3((unsigned)sp.nchunk, (unsigned)tensors), dim3(kBlock), lds, s, a,
                        sp, partial);
   }
   {
     ProfScope ps(kProfConvertFinal, s, (double)tensors * sp.nchunk * 8);
-    auto fk = a.dcount ? convert_final_kernel<true> : convert_final_kernel<false>;
-    hipLaunchKernelGGL(fk, dim3((unsigned)dev_grid((a.nboxes * a.h + 3) / 4, a.dcount)), dim3(kBlock),
-                       0, s, a, sp,
+    hipLaunchKernelGGL(convert_final_kernel, dim3((unsigned)((a.nboxes * a.h + 3) / 4)), dim3(kBlock), 0, s, a, sp,
                        (const double *)partial, (const double *)l1part);
   }
   return hipGetLastError();
