@@ -605,7 +605,7 @@ static bern_status layer_tables(const bern_net *net, int Din, int Lmax, bool com
   hipError_t e = dense_index_table(*net->tab, Din, &t.didx);
   const bool tree = convert_tree(net->n, Din);
   // degree 1 is read off at the box corners and needs neither
-  if (e == hipSuccess && Din >= 2 && Din <= 8 && net->n >= 2) e = tree_table(*net->tab, Din, &t.tree);
+  if (e == hipSuccess && Din >= 2 && Din <= 12 && net->n >= 2) e = tree_table(*net->tab, Din, &t.tree);
   if (e == hipSuccess && !tree && Din >= 2 && Din <= 8) e = prefix_table(*net->tab, Din, net->n, &t.plist, &t.plist_len);
   if (e == hipSuccess && compose && Lmax >= 2) e = product_table(*net->tab, Din, Din, true, &t.sq);
   for (int m = 1; e == hipSuccess && compose && m <= Lmax - 1 && Lmax >= 3; ++m)

@@ -1294,6 +1294,10 @@ static hipError_t launch_affine(const ConvertArgs &a, hipStream_t s) {
 // most D+1 terms, within the n(D+2) rounding steps of the per-axis change.
 constexpr int tree_tile_axes(int D) { return D == 1 ? 5 : D == 2 ? 3 : D <= 5 ? 2 : 1; }
 
+// Highest degree of the block-per-tensor tree read-off (the per-neuron
+// kernels stop at 8; above, tensors no longer fit one block's LDS anyway).
+constexpr int kTreeMaxDegree = 12;
+
 constexpr int cpow(int b, int e) {
   int r = 1;
   for (int i = 0; i < e; ++i) r *= b;
@@ -1578,6 +1582,10 @@ static hipError_t launch_tree(const ConvertArgs &a, const TreePlan &tp, size_t l
     case 6: return launch_tree_t<T, 6>(a, tp, lds, partial, l1part, s);
     case 7: return launch_tree_t<T, 7>(a, tp, lds, partial, l1part, s);
     case 8: return launch_tree_t<T, 8>(a, tp, lds, partial, l1part, s);
+    case 9: return launch_tree_t<T, 9>(a, tp, lds, partial, l1part, s);
+    case 10: return launch_tree_t<T, 10>(a, tp, lds, partial, l1part, s);
+    case 11: return launch_tree_t<T, 11>(a, tp, lds, partial, l1part, s);
+    case 12: return launch_tree_t<T, 12>(a, tp, lds, partial, l1part, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -2170,7 +2178,7 @@ constexpr int64_t kTreeBlocks = 8192;
 // until the levels fit LDS. lo < 0 when the path does not apply.
 static TreePlan tree_plan(int n, int D, int64_t tensors) {
   TreePlan none;
-  if (D < 1 || D > 8 || n < 2 || n > kMaxInputs) return none;
+  if (D < 1 || D > kTreeMaxDegree || n < 2 || n > kMaxInputs) return none;
   const int M = tree_tile_axes(D), D1 = D + 1, lead = n - M;
   if (lead < 1 || ssize(n, D, (int64_t)1 << 24) < 0) return none;
   TreePlan tp;

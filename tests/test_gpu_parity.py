@@ -302,6 +302,22 @@ def test_large_output_two_pass_fp32_and_fp64():
     _assert_fp32(g32, o, case.n_hidden)
 
 
+@pytest.mark.parametrize("widths,L,seed", [([5, 4, 4, 1], 3, 61), ([4, 3, 3, 1], 4, 62)])
+def test_large_tensor_readoffs(widths, L, seed):
+    """Output tensors beyond one block's LDS at high degree: degree 9 in five
+    variables (100,000 Bernstein coefficients, the block-per-tensor tree
+    read-off) and degree 16 in four (83,521, above the tree's degree range:
+    the dense two-pass basis change). Parity in both precisions."""
+    case = wl.random_net_case(widths, seed, n_boxes=2, half_width=0.3, L=L)
+    print(f"case {case.name} L={L}", flush=True)
+    o = _oracle(case, L=L)
+    g64 = _bounds_gpu(case, L=L, precision="fp64")
+    assert g64["stats"]["out_degree"] == L * L
+    _assert_parity(g64, o, 1e-9, case.n_hidden)
+    g32 = _bounds_gpu(case, L=L, precision="fp32")
+    _assert_fp32(g32, o, case.n_hidden)
+
+
 def _power_basis(n, d, t):
     """[m, (d+1)^n] monomials t^e, e at sum_a e_a (d+1)^(n-1-a)."""
     idx = np.arange((d + 1) ** n)
