@@ -234,15 +234,19 @@ bern_status bern_bounds(const bern_net *net, const bern_opts *opts, int64_t n_bo
  * library-owned device array of BERN_NOALLOC_SCRATCH_BYTES bytes, one per GPU,
  * held until the process ends. Arguments and outputs are bern_bounds' (no
  * degree plan, no workspace); the boxes run in waves that fit the scratch.
- * Limits: the plain rule only (BERN_PLAN_PLAIN, with or without opts.lin), run
- * eagerly (opts.graph is ignored); the network's index tables for these
- * options must already exist -- one bern_bounds call with the same options on
- * the same network builds them. Every call on a GPU shares that GPU's array,
+ * Limits: the plain rule (BERN_PLAN_PLAIN) or the learned plan
+ * (BERN_PLAN_LEARNED, its degree classes listed on the device as under
+ * opts.graph; refused when they exceed that path's limits), with or without
+ * opts.lin, run eagerly (opts.graph is ignored); the network's index tables
+ * for these options must already exist -- one bern_bounds call with the same
+ * options on the same network builds them (with opts.graph set, for the
+ * learned plan). Results are bit-for-bit those of bern_bounds. Every call on a GPU shares that GPU's array,
  * so calls that overlap in time on one GPU (other streams, other threads)
  * race and must be serialised by the caller; nothing in the array needs to
  * start at zero. Asynchronous on `stream` as bern_bounds.
- * Errors: those of bern_bounds; BERN_E_ARG for another plan or tables not
- * built yet; BERN_E_TOO_LARGE when one box needs more than the array holds. */
+ * Errors: those of bern_bounds; BERN_E_ARG for given codes, too many degree
+ * classes or tables not built yet; BERN_E_TOO_LARGE when one box needs more
+ * than the array holds. */
 #define BERN_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
 bern_status bern_bounds_noalloc(const bern_net *net, const bern_opts *opts, int64_t n_boxes,
                                 const double *box_lo, const double *box_hi, double *neuron_lo, double *neuron_hi,

@@ -414,10 +414,12 @@ def bounds(net, box_lo, box_hi, L=2, precision="fp64", plan="plain", sched="per_
     return res
 
 
-def bounds_noalloc(net, box_lo, box_hi, L=2, precision="fp64", lin=0, outputs=None, stream=None):
-    """``bounds`` of the plain rule without a workspace (bern_bounds_noalloc):
-    the library's own per-GPU scratch array, no allocation by the library.
-    Output tensors are allocated here unless ``outputs`` is given."""
+def bounds_noalloc(net, box_lo, box_hi, L=2, precision="fp64", lin=0, outputs=None, stream=None, plan="plain",
+                   pred=None):
+    """``bounds`` of the plain rule or the learned plan without a workspace
+    (bern_bounds_noalloc): the library's own per-GPU scratch array, no
+    allocation by the library. Output tensors are allocated here unless
+    ``outputs`` is given."""
     import torch
     dev = box_lo.device
     box_lo, box_hi = box_lo.contiguous(), box_hi.contiguous()
@@ -429,7 +431,7 @@ def bounds_noalloc(net, box_lo, box_hi, L=2, precision="fp64", lin=0, outputs=No
                        out_lo=torch.empty((nb, net.n_out), dtype=torch.float64, device=dev),
                        out_hi=torch.empty((nb, net.n_out), dtype=torch.float64, device=dev),
                        used_plan=torch.empty((nb, nh), dtype=torch.int8, device=dev))
-    o = make_opts(L=L, precision=precision, plan="plain", sched="batched", lin=lin)
+    o = make_opts(L=L, precision=precision, plan=plan, sched="batched", lin=lin, pred=pred)
     st = bern_stats()
     _check(lib().bern_bounds_noalloc(net.handle, ctypes.byref(o), nb, _ptr(box_lo), _ptr(box_hi),
                                      _ptr(outputs["neuron_lo"]), _ptr(outputs["neuron_hi"]), _ptr(outputs["out_lo"]),

@@ -1438,6 +1438,29 @@ static bern_status run_graph(bern_net *net, const bern_opts *o, int64_t n_boxes,
   return BERN_OK;
 }
 
+// Every index table the device classes of plan p can use (built here, once
+// per network, before any capture; without allocations only looked up):
+// the read-off at every pre degree, the products of every class that can
+// hold an order >= 2, and the Lin read-off at every post degree. False when
+// one of them exceeds its limits or, without allocations, is missing.
+static bool dev_class_tables(const bern_net *net, const Plan &p) {
+  const DevClasses &dc = p.dc;
+  for (int i = 0; i < p.H; ++i) {
+    LayerTables lt;
+    for (int d : dc.din[i])
+      if (layer_tables(net, d, p.Lmax, false, lt) != BERN_OK) return false;
+    if (i == p.H - 1) continue;
+    for (const auto &pr : dc.pairs[i]) {
+      const int order = class_order(p, pr.first, pr.second);
+      if (order >= 2 && layer_tables(net, pr.first, order, true, lt) != BERN_OK) return false;
+    }
+    const bool lin = p.lin > 0 && (i + 1) % p.lin == 0;
+    for (int d : dc.dout[i])
+      if (lin && d >= 1 && layer_tables(net, d, p.Lmax, false, lt) != BERN_OK) return false;
+  }
+  return true;
+}
+
 static bern_status bounds_impl(const bern_net *net, const bern_opts *opts, int64_t n_boxes, const double *box_lo,
                                const double *box_hi, const int8_t *plan, double *neuron_lo, double *neuron_hi,
                                double *out_lo, double *out_hi, int8_t *used_plan, void *workspace, size_t ws_bytes,
@@ -1474,28 +1497,23 @@ static bern_status bounds_impl(const bern_net *net, const bern_opts *opts, int64
   // Per-neuron plans in a graph: the device lists every class the rules can
   // give (when they are few), so the wave needs no host round trip.
   bool graph = opts->graph && !op && (p.mode == BERN_PLAN_PLAIN || p.dev_ok);
-  const DevClasses *dc = graph && p.mode != BERN_PLAN_PLAIN ? &p.dc : nullptr;
-  if (dc) {
-    // every class's index tables before the capture (device allocations);
+  // device classes: under a graph, and always without allocations (the
+  // host classes stage box degrees in pinned host memory)
+  const bool plain_rule = p.mode == BERN_PLAN_PLAIN;
+  const DevClasses *dc = !plain_rule && !op && p.dev_ok && (graph || g_no_alloc) ? &p.dc : nullptr;
+  if (dc && !dev_class_tables(net, p)) {
     // a class whose tables exceed their limits leaves the run to the host
     // classes, which build only those of the classes that occur
-    for (int i = 0; i < p.H && dc; ++i) {
-      LayerTables lt;
-      bool ok = true;
-      for (int d : dc->din[i]) ok = ok && layer_tables(net, d, p.Lmax, false, lt) == BERN_OK;
-      const bool lin = i < p.H - 1 && p.lin > 0 && (i + 1) % p.lin == 0;
-      for (size_t k = 0; i < p.H - 1 && k < dc->pairs[i].size(); ++k) {
-        const auto &pr = dc->pairs[i][k];
-        const int order = class_order(p, pr.first, pr.second);
-        if (order >= 2) ok = ok && layer_tables(net, pr.first, order, true, lt) == BERN_OK;
-      }
-      for (size_t k = 0; lin && k < dc->dout[i].size(); ++k)
-        if (dc->dout[i][k] >= 1) ok = ok && layer_tables(net, dc->dout[i][k], p.Lmax, false, lt) == BERN_OK;
-      if (!ok) {
-        dc = nullptr;
-        graph = false;
-      }
+    if (g_no_alloc) {
+      set_error("the network's index tables for these options are not built yet");
+      return BERN_E_ARG;
     }
+    dc = nullptr;
+    graph = false;
+  }
+  if (!plain_rule && !dc && g_no_alloc) {
+    set_error("the degree classes of this plan exceed what the device lists");
+    return BERN_E_ARG;
   }
   auto run_all = [&](hipStream_t rs) -> bern_status {
     if (opts->counters) {
@@ -1565,8 +1583,9 @@ extern "C" bern_status bern_bounds(const bern_net *net, const bern_opts *opts, i
 
 namespace bern {
 // bern_bounds on a library-owned scratch buffer (bern_bounds_noalloc): the
-// plain rule only (no host staging of per-box degrees), run eagerly (no
-// graph objects), and only once every index table the options need exists
+// plain rule, or the learned plan with its degree classes listed on the
+// device (no host staging of per-box degrees), run eagerly (no graph
+// objects), and only once every index table the options need exists
 // (checked before anything is enqueued); while it runs, table builders and
 // the profiler's event pool allocate nothing.
 bern_status bounds_on_scratch(const bern_net *net, const bern_opts *opts, int64_t n_boxes, const double *box_lo,
@@ -1575,12 +1594,17 @@ bern_status bounds_on_scratch(const bern_net *net, const bern_opts *opts, int64_
                               bern_stats *stats) {
   bern_status st = check_opts(net, opts);
   if (st != BERN_OK) return st;
-  if (opts->plan != BERN_PLAN_PLAIN) {
-    set_error("bern_bounds_noalloc takes the plain rule only (per-neuron plans stage box degrees in host memory)");
+  if (opts->plan == BERN_PLAN_GIVEN) {
+    set_error("bern_bounds_noalloc takes the plain rule or the learned plan (it has no codes argument)");
     return BERN_E_ARG;
   }
   Plan p;
   if ((st = plan_net(net, opts, p)) != BERN_OK) return st;
+  if (p.mode == BERN_PLAN_LEARNED && !p.dev_ok) {
+    set_error("the learned plan's degree classes exceed what the device lists (over %d (pre, post) pairs or %d "
+              "lists in a layer), which bern_bounds_noalloc needs", kMaxDevPairs, kMaxDevLists);
+    return BERN_E_ARG;
+  }
   if (p.per_box() > scratch_bytes) {
     set_error("one box needs %zu bytes of scratch, over the %zu bytes bern_bounds_noalloc holds", p.per_box(),
               scratch_bytes);
@@ -1590,16 +1614,21 @@ bern_status bounds_on_scratch(const bern_net *net, const bern_opts *opts, int64_
     Guard() { g_no_alloc = true; }
     ~Guard() { g_no_alloc = false; }
   } guard;
-  for (int i = 0; i < p.H; ++i) {
-    LayerTables lt;
-    bool ok = layer_tables(net, p.Dpre[i], p.Lmax, i < p.H - 1, lt) == BERN_OK;
-    if (ok && i < p.H - 1 && p.lin > 0 && (i + 1) % p.lin == 0)
-      ok = layer_tables(net, p.Dpost[i], p.Lmax, false, lt) == BERN_OK;
-    if (!ok) {
-      set_error("the network's index tables for these options are not built yet (a bern_bounds call with the "
-                "same options builds them)");
-      return BERN_E_ARG;
+  bool ok = true;
+  if (p.mode == BERN_PLAN_PLAIN) {
+    for (int i = 0; i < p.H && ok; ++i) {
+      LayerTables lt;
+      ok = layer_tables(net, p.Dpre[i], p.Lmax, i < p.H - 1, lt) == BERN_OK;
+      if (ok && i < p.H - 1 && p.lin > 0 && (i + 1) % p.lin == 0)
+        ok = layer_tables(net, p.Dpost[i], p.Lmax, false, lt) == BERN_OK;
     }
+  } else {
+    ok = dev_class_tables(net, p);
+  }
+  if (!ok) {
+    set_error("the network's index tables for these options are not built yet (a bern_bounds call with the "
+              "same options builds them; for the learned plan, with opts.graph set)");
+    return BERN_E_ARG;
   }
   bern_opts o = *opts;
   o.graph = 0;

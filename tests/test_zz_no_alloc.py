@@ -4,7 +4,9 @@ workspace, through the C ABI: two calls in a row on the same GPU, the second
 with fewer boxes, each bitwise equal to bern_bounds (same kernels and
 summation order) and so within the parity bar of the FP64 oracle (1e-9
 relative in FP64; FP32 padded: within 1e-4 and containing the oracle's
-interval). Also the documented refusals."""
+interval). The learned plan runs there with its degree classes listed on
+the device, bitwise equal to bern_bounds with host classes. Also the
+documented refusals."""
 import ctypes
 
 import numpy as np
@@ -59,6 +61,34 @@ def test_noalloc_matches_bounds_twice(precision, lin):
         assert r["stats"]["n_waves"] >= 1
         for i in (0, nb - 1):
             _oracle_close(case, g, i, 2, lin, precision)
+    net.close()
+
+
+@pytest.mark.parametrize("precision,lin", [("fp32", 0), ("fp64", 0), ("fp32", 1)])
+def test_noalloc_learned_plan_matches_bounds_twice(precision, lin):
+    """The learned plan on the scratch array: its degree classes listed on the
+    device (no host staging), bitwise equal to bern_bounds with host classes."""
+    from paper_2211_14438_amd import predictor as PR
+    case = wl.cfg5(n_boxes=48)
+    print(f"case {case.name} learned {precision} lin {lin}", flush=True)
+    net = B.Net(case.Ws, case.bs)
+    pred = PR.load_predictor()
+    lo = torch.tensor(case.box_lo, dtype=torch.float64, device=DEV)
+    hi = torch.tensor(case.box_hi, dtype=torch.float64, device=DEV)
+    kw = dict(L=2, precision=precision, lin=lin, plan="learned", pred=pred)
+    B.bounds(net, lo, hi, sched="batched", graph=True, **kw)  # builds every class's index tables
+    ref = B.bounds(net, lo, hi, sched="batched", **kw)  # host classes
+    torch.cuda.synchronize()
+    assert ref["stats"]["device_classes"] == 0
+    ref = {k: ref[k].cpu().numpy() for k in KEYS}
+    for nb in (48, 17):
+        r = B.bounds_noalloc(net, lo[:nb], hi[:nb], **kw)
+        torch.cuda.synchronize()
+        assert r["stats"]["device_classes"] == 1
+        g = {k: r[k].cpu().numpy() for k in KEYS}
+        for k in KEYS:
+            assert np.array_equal(g[k], ref[k][:nb]), (nb, k)
+    pred.close()
     net.close()
 
 
