@@ -219,8 +219,9 @@ bern_status bern_workspace_size(const bern_net *net, const bern_opts *opts, int6
  *                    -2 linear fallback, k >= 1 ReLU order k)
  *   workspace        device scratch of ws_bytes bytes, 256-byte aligned
  *   stats            host, optional
- * Errors: BERN_E_ARG, BERN_E_DEGREE, BERN_E_WORKSPACE (too small for one
- * box), BERN_E_DEVICE. */
+ * Errors: BERN_E_ARG (also: a per-neuron plan run with host-side classes on
+ * a stream under capture), BERN_E_DEGREE, BERN_E_WORKSPACE (too small for
+ * one box), BERN_E_TOO_LARGE, BERN_E_DEVICE. */
 bern_status bern_bounds(const bern_net *net, const bern_opts *opts, int64_t n_boxes,
                         const double *box_lo, const double *box_hi, const int8_t *plan,
                         double *neuron_lo, double *neuron_hi, double *out_lo, double *out_hi,

@@ -1515,6 +1515,17 @@ static bern_status bounds_impl(const bern_net *net, const bern_opts *opts, int64
     set_error("the degree classes of this plan exceed what the device lists");
     return BERN_E_ARG;
   }
+  if (!plain_rule && !dc) {
+    // host classes synchronise the stream once per hidden layer, which a
+    // stream under capture does not allow
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    BERN_HIP_TRY(hipStreamIsCapturing(reinterpret_cast<hipStream_t>(stream), &cs));
+    if (cs != hipStreamCaptureStatusNone) {
+      set_error("a per-neuron plan run with host-side degree classes synchronises its stream, which is being "
+                "captured (set opts.graph to list the classes on the device)");
+      return BERN_E_ARG;
+    }
+  }
   auto run_all = [&](hipStream_t rs) -> bern_status {
     if (opts->counters) {
       ProfScope ps(kProfMisc, rs, 0.0);

@@ -121,3 +121,29 @@ def test_counters_and_stats(precision):
     s = r["stats"]
     assert s["n_waves"] == 1 and s["boxes_per_wave"] == 6 and s["lin_layers"] == 0 and s["enqueue_ms"] > 0.0
     net.close()
+
+
+def test_host_classes_refused_under_stream_capture():
+    """A per-neuron plan run with host-side classes synchronises its stream;
+    on a stream under capture it is refused before anything is enqueued, and
+    the capture ends empty."""
+    case, net, lo, hi = _net_and_boxes([3, 6, 5, 2])
+    plan = torch.ones((case.n_boxes, case.n_hidden), dtype=torch.int8, device=DEV)
+    kw = dict(L=2, plan="given", degree_plan=plan, sched="batched")
+    r = B.bounds(net, lo, hi, **kw)  # buffers, outside the capture
+    outs = {k: r[k] for k in ("neuron_lo", "neuron_hi", "out_lo", "out_hi", "used_plan")}
+    torch.cuda.synchronize()
+    hip = ctypes.CDLL("libamdhip64.so")
+    s = torch.cuda.Stream()
+    sp = ctypes.c_void_p(s.cuda_stream)
+    assert hip.hipStreamBeginCapture(sp, 2) == 0  # relaxed mode
+    try:
+        st, msg = _status(lambda: B.bounds(net, lo, hi, workspace=r["workspace"], outputs=outs, stream=s, **kw))
+    finally:
+        g = ctypes.c_void_p()
+        end = hip.hipStreamEndCapture(sp, ctypes.byref(g))
+        if g.value:
+            hip.hipGraphDestroy(g)
+    assert end == 0
+    assert st == E_ARG and "captured" in msg
+    net.close()
