@@ -300,9 +300,17 @@ bern_status bern_rel_volume(const bern_net *net, const bern_opts *opts, int64_t 
  * out_lo > threshold violates the property everywhere, and every other box is
  * bisected along its widest input dimension for the next round, while the
  * pending boxes stay within max_boxes and the rounds within max_rounds
- * (after that they count as undecided). box_lo/box_hi are host arrays
- * [n_boxes][n] with d_lo < d_hi in every dimension; the call is synchronous
- * and allocates and frees its own device buffers.
+ * (after that they count as undecided). The pending boxes, their bounds,
+ * the decisions and the bisection stay in device memory across the rounds;
+ * each round reads back its open-box count and volume sums (and the round's
+ * boxes when a decision log is given). The halves of open box number q (in
+ * box order) are pending boxes 2q and 2q + 1 of the next round. Volume
+ * fractions are summed in a fixed order, so a call is reproducible
+ * bit for bit. box_lo/box_hi are host arrays [n_boxes][n] with
+ * d_lo < d_hi in every dimension; the call is synchronous on the null
+ * stream and allocates and frees its own device buffers (two box buffers
+ * of max_boxes each and a bern_bounds workspace for max_boxes boxes, or
+ * the smallest usable one when that does not fit).
  *   res  host: the verified, violated and undecided fractions of the boxes'
  *        total volume (summing to 1 up to rounding), the rounds run, the
  *        number of box bounds computed, and the boxes left undecided.
@@ -315,8 +323,9 @@ typedef struct {
   int64_t boxes_bounded;
   int64_t undecided_boxes;
   /* optional decision log (host arrays of the caller, NULL to skip): every
-   * decided box in decision order -- verified (+1), violated (-1), and the
-   * boxes left undecided at the end (0) -- with its corners and its output
+   * decided box, round by round: the round's verified (+1) and violated (-1)
+   * boxes in box order, then, in the last round, the boxes left undecided
+   * (0) -- with its corners and its output
    * bounds, up to log_cap entries; log_count receives the number written */
   int64_t log_cap;
   int64_t log_count;

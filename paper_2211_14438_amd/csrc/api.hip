@@ -1754,6 +1754,97 @@ extern "C" bern_status bern_bounds_host(const bern_net *net, const bern_opts *op
 }
 
 // ------------------------------------------------------- branch and bound
+// One branch-and-bound round (bern_verify) in one block: every pending box is
+// decided from the bounds of output k -- verified (+1) when out_hi <= thr,
+// violated (-1) when out_lo > thr, open (0) otherwise -- and, when the round
+// may split and the halves of the open boxes fit max_boxes, each open box is
+// bisected along its widest input dimension into the next buffer (box
+// order: open box number q gives boxes 2q and 2q + 1). The volume fractions
+// (box volume over `total`) are summed in a fixed order: each thread over a
+// contiguous run of boxes, then thread 0 over the threads. out: [0] open
+// boxes, [1] split (1/0), [2] verified, [3] violated, [4] open-and-unsplit
+// volume fractions.
+static __global__ void __launch_bounds__(1024) bb_round_kernel(int n, int o, int64_t nb, const double *lo, const double *hi,
+                                                        const double *olo, const double *ohi, int k, double thr,
+                                                        double total, int64_t max_boxes, int may_split, double *nlo,
+                                                        double *nhi, int8_t *status, int64_t *pos, double *out) {
+  __shared__ int wsum[16];
+  __shared__ int64_t base;
+  __shared__ int split;
+  __shared__ double part[3][1024];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
+  if (tid == 0) base = 0;
+  __syncthreads();
+  for (int64_t b0 = 0; b0 < nb; b0 += blockDim.x) {  // decisions, and the open boxes' numbers
+    const int64_t b = b0 + tid;
+    bool open = false;
+    if (b < nb) {
+      const double bl = olo[b * o + k], bh = ohi[b * o + k];
+      const int8_t st = bh <= thr ? 1 : (bl > thr ? -1 : 0);
+      status[b] = st;
+      open = st == 0;
+    }
+    const unsigned long long bal = __ballot(open);
+    if (lane == 0) wsum[wid] = __popcll(bal);
+    __syncthreads();
+    if (open) {
+      int64_t q = base;
+      for (int w = 0; w < wid; ++w) q += wsum[w];
+      pos[b] = q + __popcll(bal & ((1ull << lane) - 1ull));
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int tot = 0;
+      for (int w = 0; w < nw; ++w) tot += wsum[w];
+      base += tot;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) split = may_split && base * 2 <= max_boxes;
+  __syncthreads();
+  double v[3] = {0.0, 0.0, 0.0};
+  const int64_t run = (nb + blockDim.x - 1) / blockDim.x;
+  for (int64_t b = tid * run; b < nb && b < (tid + 1) * run; ++b) {
+    const double *l = lo + b * n, *h = hi + b * n;
+    double vol = 1.0;
+    int wide = 0;
+    for (int a = 0; a < n; ++a) {
+      vol *= h[a] - l[a];
+      if (a > 0 && h[a] - l[a] > h[wide] - l[wide]) wide = a;
+    }
+    vol /= total;
+    const int st = status[b];
+    if (st == 1) {
+      v[0] += vol;
+    } else if (st == -1) {
+      v[1] += vol;
+    } else if (!split) {
+      v[2] += vol;
+    } else {
+      const double mid = 0.5 * (l[wide] + h[wide]);
+      for (int half = 0; half < 2; ++half) {
+        double *cl = nlo + (2 * pos[b] + half) * n, *ch = nhi + (2 * pos[b] + half) * n;
+        for (int a = 0; a < n; ++a) {
+          cl[a] = a == wide && half == 1 ? mid : l[a];
+          ch[a] = a == wide && half == 0 ? mid : h[a];
+        }
+      }
+    }
+  }
+  for (int q = 0; q < 3; ++q) part[q][tid] = v[q];
+  __syncthreads();
+  if (tid == 0) {
+    double t[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < (int)blockDim.x; ++i)
+      for (int q = 0; q < 3; ++q) t[q] += part[q][i];
+    out[0] = (double)base;
+    out[1] = split ? 1.0 : 0.0;
+    out[2] = t[0];
+    out[3] = t[1];
+    out[4] = t[2];
+  }
+}
+
 extern "C" bern_status bern_verify(const bern_net *net, const bern_opts *opts, int64_t n_boxes,
                                    const double *box_lo, const double *box_hi, int32_t out_index, double threshold,
                                    int32_t max_rounds, int64_t max_boxes, bern_verify_result *res) {
@@ -1802,61 +1893,80 @@ extern "C" bern_status bern_verify(const bern_net *net, const bern_opts *opts, i
     log_ohi[k] = ohi_;
     log_st[k] = status;
   };
-  std::vector<double> olo, ohi;
-  for (int round = 0; round < max_rounds && !lo.empty(); ++round) {
-    const int64_t nb = (int64_t)(lo.size() / n);
-    olo.resize((size_t)nb * o);
-    ohi.resize((size_t)nb * o);
-    if ((st = bern_bounds_host(net, opts, nb, lo.data(), hi.data(), nullptr, nullptr, nullptr, olo.data(),
-                               ohi.data(), nullptr, nullptr)) != BERN_OK)
+  // the rounds on the device: the pending boxes (two buffers, alternating),
+  // their output bounds, decisions and halves stay in device memory; each
+  // round reads back its open count and volume sums (and, when the caller
+  // logs decisions, the round's boxes and bounds)
+  size_t ws_bytes = 0, ws_one = 0;
+  if ((st = bern_workspace_size(net, opts, max_boxes, &ws_bytes, &ws_one)) != BERN_OK) return st;
+  DeviceBufs d;
+  void *blo[2], *bhi[2], *dolo, *dohi, *dstat, *dpos, *dout, *ws;
+  const size_t boxb = (size_t)max_boxes * n * sizeof(double), outb = (size_t)max_boxes * o * sizeof(double);
+  for (int q = 0; q < 2; ++q) {
+    BERN_HIP_TRY(d.alloc(&blo[q], boxb));
+    BERN_HIP_TRY(d.alloc(&bhi[q], boxb));
+  }
+  BERN_HIP_TRY(d.alloc(&dolo, outb));
+  BERN_HIP_TRY(d.alloc(&dohi, outb));
+  BERN_HIP_TRY(d.alloc(&dstat, (size_t)max_boxes));
+  BERN_HIP_TRY(d.alloc(&dpos, (size_t)max_boxes * sizeof(int64_t)));
+  BERN_HIP_TRY(d.alloc(&dout, 8 * sizeof(double)));
+  // a round in one wave if the largest one fits, else the smallest usable workspace
+  if (d.alloc(&ws, ws_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    BERN_HIP_TRY(d.alloc(&ws, ws_one));
+    ws_bytes = ws_one;
+  }
+  BERN_HIP_TRY(hipMemcpy(blo[0], lo.data(), (size_t)n_boxes * n * sizeof(double), hipMemcpyHostToDevice));
+  BERN_HIP_TRY(hipMemcpy(bhi[0], hi.data(), (size_t)n_boxes * n * sizeof(double), hipMemcpyHostToDevice));
+  std::vector<double> hlo, hhi, holo, hohi;
+  std::vector<int8_t> hst;
+  int cur = 0;
+  int64_t nb = n_boxes;
+  for (int round = 0; round < max_rounds && nb > 0; ++round) {
+    if ((st = bern_bounds(net, opts, nb, (const double *)blo[cur], (const double *)bhi[cur], nullptr, nullptr,
+                          nullptr, (double *)dolo, (double *)dohi, nullptr, ws, ws_bytes, nullptr, nullptr)) != BERN_OK)
       return st;
     res->rounds = round + 1;
     res->boxes_bounded += nb;
-    // classify; bisect the undecided boxes while they fit
-    std::vector<double> nlo, nhi;
-    std::vector<int64_t> open;
-    for (int64_t b = 0; b < nb; ++b) {
-      const double v = volume(&lo[b * n], &hi[b * n]) / total;
-      const double bl = olo[b * o + out_index], bh = ohi[b * o + out_index];
-      if (bh <= threshold) {
-        res->verified += v;
-        log_box(&lo[b * n], &hi[b * n], bl, bh, 1);
-      } else if (bl > threshold) {
-        res->violated += v;
-        log_box(&lo[b * n], &hi[b * n], bl, bh, -1);
-      } else {
-        open.push_back(b);
-      }
+    {
+      ProfScope ps(kProfMisc, nullptr, 0.0);
+      hipLaunchKernelGGL(bb_round_kernel, dim3(1), dim3(1024), 0, nullptr, n, o, nb, (const double *)blo[cur],
+                         (const double *)bhi[cur], (const double *)dolo, (const double *)dohi, out_index, threshold,
+                         total, max_boxes, round + 1 < max_rounds ? 1 : 0, (double *)blo[cur ^ 1],
+                         (double *)bhi[cur ^ 1], (int8_t *)dstat, (int64_t *)dpos, (double *)dout);
     }
-    const bool split = round + 1 < max_rounds && (int64_t)open.size() * 2 <= max_boxes;
-    for (int64_t b : open) {
-      const double *l = &lo[b * n], *h = &hi[b * n];
-      if (!split) {
-        res->undecided += volume(l, h) / total;
-        res->undecided_boxes += 1;
-        log_box(l, h, olo[b * o + out_index], ohi[b * o + out_index], 0);
-        continue;
-      }
-      int wide = 0;
-      for (int a = 1; a < n; ++a)
-        if (h[a] - l[a] > h[wide] - l[wide]) wide = a;
-      const double mid = 0.5 * (l[wide] + h[wide]);
-      for (int half = 0; half < 2; ++half) {
-        for (int a = 0; a < n; ++a) {
-          nlo.push_back(a == wide && half == 1 ? mid : l[a]);
-          nhi.push_back(a == wide && half == 0 ? mid : h[a]);
+    BERN_HIP_TRY(hipGetLastError());
+    double hout[8];
+    BERN_HIP_TRY(hipMemcpy(hout, dout, sizeof(hout), hipMemcpyDeviceToHost));  // waits for the round
+    const int64_t open = (int64_t)hout[0];
+    const bool split = hout[1] != 0.0;
+    res->verified += hout[2];
+    res->violated += hout[3];
+    if (!split) {
+      res->undecided += hout[4];
+      res->undecided_boxes += open;
+    }
+    if (logging && res->log_count < log_cap) {
+      hlo.resize((size_t)nb * n);
+      hhi.resize((size_t)nb * n);
+      holo.resize((size_t)nb * o);
+      hohi.resize((size_t)nb * o);
+      hst.resize((size_t)nb);
+      BERN_HIP_TRY(hipMemcpy(hlo.data(), blo[cur], (size_t)nb * n * sizeof(double), hipMemcpyDeviceToHost));
+      BERN_HIP_TRY(hipMemcpy(hhi.data(), bhi[cur], (size_t)nb * n * sizeof(double), hipMemcpyDeviceToHost));
+      BERN_HIP_TRY(hipMemcpy(holo.data(), dolo, (size_t)nb * o * sizeof(double), hipMemcpyDeviceToHost));
+      BERN_HIP_TRY(hipMemcpy(hohi.data(), dohi, (size_t)nb * o * sizeof(double), hipMemcpyDeviceToHost));
+      BERN_HIP_TRY(hipMemcpy(hst.data(), dstat, (size_t)nb, hipMemcpyDeviceToHost));
+      for (int pass = 0; pass < 2; ++pass)  // the decided boxes, then the open ones left unsplit
+        for (int64_t b = 0; b < nb; ++b) {
+          const bool take = pass == 0 ? hst[b] != 0 : (hst[b] == 0 && !split);
+          if (take)
+            log_box(&hlo[b * n], &hhi[b * n], holo[b * o + out_index], hohi[b * o + out_index], hst[b]);
         }
-      }
     }
-    lo.swap(nlo);
-    hi.swap(nhi);
-  }
-  // boxes still pending after the last round that was allowed to split
-  // (split but never bounded: logged with NaN bounds)
-  for (size_t b = 0; b < lo.size() / n; ++b) {
-    res->undecided += volume(&lo[b * n], &hi[b * n]) / total;
-    res->undecided_boxes += 1;
-    log_box(&lo[b * n], &hi[b * n], NAN, NAN, 0);
+    nb = split ? 2 * open : 0;
+    cur ^= 1;
   }
   return BERN_OK;
 }

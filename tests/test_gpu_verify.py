@@ -62,3 +62,63 @@ def test_verify_decisions_match_oracle(precision):
             assert olo > tau - (1e-9 * scale if precision == "fp64" else 0.0), k
         else:
             assert olo <= tau + 1e-9 * scale and ohi > tau - 1e-9 * scale, k
+
+
+def _host_rounds(net, lo, hi, k, tau, max_rounds, max_boxes, precision):
+    """The same branch and bound with the rounds driven from the host: each
+    round bounds the pending boxes with bounds_host, decides them and
+    bisects the open ones (widest dimension, lowest index on ties) in box
+    order; returns the fractions and the decision log."""
+    total = np.prod(hi - lo, axis=1).sum()
+    frac = dict(verified=0.0, violated=0.0, undecided=0.0)
+    log = dict(lo=[], hi=[], out_lo=[], out_hi=[], status=[])
+    for rnd in range(max_rounds):
+        r = B.bounds_host(net, lo, hi, precision=precision)
+        blo, bhi = r["out_lo"][:, k], r["out_hi"][:, k]
+        st = np.where(bhi <= tau, 1, np.where(blo > tau, -1, 0)).astype(np.int8)
+        vol = np.prod(hi - lo, axis=1) / total
+        frac["verified"] += vol[st == 1].sum()
+        frac["violated"] += vol[st == -1].sum()
+        op = np.nonzero(st == 0)[0]
+        split = rnd + 1 < max_rounds and 2 * op.size <= max_boxes
+        for b in np.nonzero(st != 0)[0]:
+            for key, v in (("lo", lo[b]), ("hi", hi[b]), ("out_lo", blo[b]), ("out_hi", bhi[b]), ("status", st[b])):
+                log[key].append(v)
+        if not split:
+            frac["undecided"] += vol[op].sum()
+            for b in op:
+                for key, v in (("lo", lo[b]), ("hi", hi[b]), ("out_lo", blo[b]), ("out_hi", bhi[b]), ("status", 0)):
+                    log[key].append(v)
+            break
+        w = np.argmax(hi[op] - lo[op], axis=1)
+        mid = 0.5 * (lo[op, w] + hi[op, w])
+        nlo = np.repeat(lo[op], 2, axis=0)
+        nhi = np.repeat(hi[op], 2, axis=0)
+        nhi[0::2][np.arange(op.size), w] = mid
+        nlo[1::2][np.arange(op.size), w] = mid
+        lo, hi = nlo, nhi
+        if op.size == 0:
+            break
+    return frac, {key: np.array(v) for key, v in log.items()}
+
+
+@pytest.mark.parametrize("precision,max_boxes", [("fp64", 4096), ("fp32", 300)])
+def test_verify_device_rounds_match_host_rounds(precision, max_boxes):
+    """The device-resident rounds decide, bisect and log exactly as rounds
+    driven from the host over bounds_host do (the boxes bit for bit, the
+    fractions up to summation order), also when max_boxes stops the
+    splitting early (300)."""
+    case = wl.random_net_case([3, 10, 10, 2], seed=17, n_boxes=3, half_width=0.4)
+    net = B.Net(case.Ws, case.bs)
+    x = case.box_lo[0] + np.random.default_rng(5).random((2000, 3)) * (case.box_hi[0] - case.box_lo[0])
+    tau = float(np.median(H.forward(case.Ws, case.bs, x)[-1][:, 1]))
+    r = B.verify(net, case.box_lo, case.box_hi, 1, tau, max_rounds=7, max_boxes=max_boxes, precision=precision,
+                 log_cap=100000)
+    frac, log = _host_rounds(net, case.box_lo.copy(), case.box_hi.copy(), 1, tau, 7, max_boxes, precision)
+    net.close()
+    print({k: r[k] for k in ("verified", "violated", "undecided", "rounds", "boxes_bounded")}, flush=True)
+    for key in ("verified", "violated", "undecided"):
+        assert abs(r[key] - frac[key]) <= 1e-12, (key, r[key], frac[key])
+    assert r["log"]["status"].size == log["status"].size
+    for key in ("lo", "hi", "out_lo", "out_hi", "status"):
+        assert np.array_equal(r["log"][key], log[key]), key
