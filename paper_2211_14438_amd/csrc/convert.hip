@@ -27,6 +27,7 @@
 #include "simplex.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <type_traits>
 
@@ -1773,9 +1774,12 @@ __device__ void ntree_output_side(const ConvertArgs &a, const NTreePlan &tp, con
   }
 }
 
-template <int D, int M, typename T, bool kWave, class Team>
-__device__ void ntree_neuron(const ConvertArgs &a, const NTreePlan &tp, const Team &tm, const int *tb,
-                             const double *tab, double *bl, int64_t item) {
+// `pass(F, t0, mn, mx, rmn, rmx)` runs one pass over both tensors (the
+// upper at t0, the lower at t0 + tp.area; side = tid / tp.lanes) and, with
+// F::value, tracks the remainders of the fits in bl.
+template <int D, typename T, bool kWave, class Team, class Pass>
+__device__ void ntree_neuron(const ConvertArgs &a, const NTreePlan &tp, const Team &tm, double *bl, int64_t item,
+                             Pass pass) {
   const int tid = tm.tid, nt = tm.nt, n = a.n, S = (int)a.S;
   double *t0 = bl + 2 * (kMaxInputs + 1);
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
@@ -1813,9 +1817,9 @@ __device__ void ntree_neuron(const ConvertArgs &a, const NTreePlan &tp, const Te
   if (early) fits();
   double mn = INFINITY, mx = -INFINITY, rmn = INFINITY, rmx = -INFINITY;
   if (early)
-    ntree_pass<D, M, true>(a, tp, tm, tb, tab, t0, bl, mn, mx, rmn, rmx);
+    pass(std::true_type{}, t0, mn, mx, rmn, rmx);
   else
-    ntree_pass<D, M, false>(a, tp, tm, tb, tab, t0, bl, mn, mx, rmn, rmx);
+    pass(std::false_type{}, t0, mn, mx, rmn, rmx);
   // maxima of: max U, -min L, and the remainders' max U, -min U, max L, -min L
   double ex[6] = {side == 0 ? mx : -INFINITY, side == 1 ? -mn : -INFINITY, side == 0 ? rmx : -INFINITY,
                   side == 0 ? -rmn : -INFINITY, side == 1 ? rmx : -INFINITY, side == 1 ? -rmn : -INFINITY};
@@ -1828,7 +1832,7 @@ __device__ void ntree_neuron(const ConvertArgs &a, const NTreePlan &tp, const Te
     double m0 = INFINITY, m1 = -INFINITY;
     rmn = INFINITY;
     rmx = -INFINITY;
-    ntree_pass<D, M, true>(a, tp, tm, tb, tab, t0, bl, m0, m1, rmn, rmx);
+    pass(std::true_type{}, t0, m0, m1, rmn, rmx);
     double rx[4] = {side == 0 ? rmx : -INFINITY, side == 0 ? -rmn : -INFINITY, side == 1 ? rmx : -INFINITY,
                     side == 1 ? -rmn : -INFINITY};
     tm.reduce(rx, OpMax());
@@ -1883,14 +1887,257 @@ __global__ void __launch_bounds__(kWave ? 64 * kNTeams : 1024) convert_ntree_t(C
     if (item >= launch_boxes(a) * a.h) return;
     double *slice = slices + (int64_t)wv * (kRowScratch + 2 * (kMaxInputs + 1) + 2 * tp.area);
     const WaveTeam tm{(int)(threadIdx.x & 63), slice};
-    ntree_neuron<D, M, T, true>(a, tp, tm, tb, tab, slice + kRowScratch, item);
+    double *bl = slice + kRowScratch;
+    ntree_neuron<D, T, true>(a, tp, tm, bl, item,
+                             [&](auto F, double *t0, double &mn, double &mx, double &rmn, double &rmx) {
+                               ntree_pass<D, M, decltype(F)::value>(a, tp, tm, tb, tab, t0, bl, mn, mx, rmn, rmx);
+                             });
   } else {
     const BlockTeam tm{(int)threadIdx.x, (int)blockDim.x, red};
     if constexpr (kSide)
       ntree_output_side<D, M, T>(a, tp, tm, tb, tab, slices, blockIdx.x >> 1, (int)(blockIdx.x & 1));
     else
-      ntree_neuron<D, M, T, false>(a, tp, tm, tb, tab, slices, blockIdx.x);
+      ntree_neuron<D, T, false>(a, tp, tm, slices, blockIdx.x,
+                                [&](auto F, double *t0, double &mn, double &mx, double &rmn, double &rmx) {
+                                  ntree_pass<D, M, decltype(F)::value>(a, tp, tm, tb, tab, t0, slices, mn, mx, rmn,
+                                                                       rmx);
+                                });
   }
+}
+
+// ------------------------------------------- quadratic tensors, one wave
+// At per-variable degree 2 every stored monomial is 1, t_a, t_a^2 or
+// t_a t_b, and the Bernstein coefficient at index K (Def. 2 at degree 2) is
+//   b_K = sum_J a_J prod_a r(K_a, J_a),  r(k, 0) = 1, r(k, 1) = k/2,
+//   r(k, 2) = [k = 2]
+// (the ratios C(k,j)/C(2,j), exact in binary). A wave takes one neuron:
+// lanes 0..31 the upper tensor, 32..63 the lower. Each lane fixes the
+// digits of the first P variables (3^P <= 32 lanes per tensor), folds them
+// out of the stored coefficients (each coefficient once, weighted by its
+// prefix monomial's value at the lane's digits), then for each of the 3^R
+// digit tuples of the next R variables folds those, and converts the
+// remaining M-variable tile in registers. The stored coefficients are read
+// as LDS broadcasts; the pass has no barrier. Rounding: a Bernstein
+// coefficient is a sum of at most S(P,2) + S(R,2) + 2M rounded terms of
+// the |a_J| weighted by products of ratios in [0, 1], within the read-off's
+// gamma(n (D + 2) + 4) l1 bound for every n here.
+constexpr int qsize(int n) { return (n + 1) * (n + 2) / 2; }  // S(n, 2)
+
+// Layout rank (simplex.hpp order) of the monomial t_u t_v (u <= v; -1 for
+// an absent factor) among n variables: the constant, the n linear
+// monomials, then t_u t_v in row order of the upper triangle.
+constexpr int qrank(int n, int u, int v) {
+  return u < 0 ? 0 : v < 0 ? 1 + u : 1 + n + u * n - u * (u - 1) / 2 + (v - u);
+}
+
+// The factors (u, v) of every rank of the n-variable degree-2 layout.
+template <int N>
+struct QuadMono {
+  int u[qsize(N)], v[qsize(N)];
+  constexpr QuadMono() : u(), v() {
+    u[0] = v[0] = -1;
+    for (int a = 0; a < N; ++a) {
+      u[1 + a] = a;
+      v[1 + a] = -1;
+    }
+    int r = 1 + N;
+    for (int a = 0; a < N; ++a)
+      for (int b = a; b < N; ++b) {
+        u[r] = a;
+        v[r] = b;
+        ++r;
+      }
+  }
+};
+
+template <int N>
+struct QuadMonos {
+  static constexpr QuadMono<N> t{};
+};
+
+// Split of every rank of the N-variable layout into its monomial over the
+// first P variables (rank in the P-variable layout) and over the other
+// N - P (rank in that layout, variables renumbered from 0).
+template <int N, int P>
+struct QuadSplit {
+  int pre[qsize(N)], rest[qsize(N)];
+  constexpr QuadSplit() : pre(), rest() {
+    const QuadMono<N> m{};
+    for (int r = 0; r < qsize(N); ++r) {
+      int f[2] = {m.u[r], m.v[r]}, pf[2] = {-1, -1}, rf[2] = {-1, -1}, np = 0, nr = 0;
+      for (int i = 0; i < 2; ++i) {
+        if (f[i] < 0) continue;
+        if (f[i] < P)
+          pf[np++] = f[i];
+        else
+          rf[nr++] = f[i] - P;
+      }
+      pre[r] = qrank(P, pf[0], pf[1]);
+      rest[r] = qrank(N - P, rf[0], rf[1]);
+    }
+  }
+};
+template <int N, int P>
+struct QuadSplits {
+  static constexpr QuadSplit<N, P> t{};
+};
+
+// Dense tile position (digits, first variable slowest) of every rank of
+// the M-variable layout.
+template <int M>
+struct QuadDense {
+  int at[qsize(M)];
+  constexpr QuadDense() : at() {
+    const QuadMono<M> m{};
+    for (int r = 0; r < qsize(M); ++r) {
+      int d = 0;
+      if (m.u[r] >= 0) d += cpow(3, M - 1 - m.u[r]);
+      if (m.v[r] >= 0) d += cpow(3, M - 1 - m.v[r]);
+      at[r] = d;
+    }
+  }
+};
+template <int M>
+struct QuadDenses {
+  static constexpr QuadDense<M> t{};
+};
+
+// Values of the K-variable layout's monomials at Bernstein digits k.
+template <int K>
+__device__ __forceinline__ void quad_weights(const int (&k)[K > 0 ? K : 1], double (&w)[qsize(K)]) {
+  using QM = QuadMonos<K>;
+  Unroll<0, qsize(K)>::run([&](auto R) {
+    constexpr int r = R.value, u = QM::t.u[r], v = QM::t.v[r];
+    if constexpr (u < 0) {
+      w[r] = 1.0;
+    } else if constexpr (v < 0) {
+      w[r] = 0.5 * k[u];
+    } else if constexpr (u == v) {
+      w[r] = k[u] == 2 ? 1.0 : 0.0;
+    } else {
+      w[r] = (0.5 * k[u]) * (0.5 * k[v]);
+    }
+  });
+}
+
+template <int N>
+struct QuadShape {
+  static constexpr int P = N - 1 < 3 ? N - 1 : 3;          // lane variables
+  static constexpr int M = N - P < 3 ? N - P : 3;          // tile variables
+  static constexpr int R = N - P - M;                      // round variables
+  static constexpr int lanes = cpow(3, P), rounds = cpow(3, R), tile = cpow(3, M);
+};
+
+// One pass over the lane's share of its tensor (`c`, the S(N,2) stored
+// coefficients in LDS; fit `beta` when kFit): extrema of the Bernstein
+// coefficients into mn / mx and of the remainders b_K - l(K/2) into
+// rmn / rmx, l(x) = beta_0 + sum_a beta_a (x_a - 1/2).
+template <int N, bool kFit>
+__device__ __forceinline__ void quad_pass(const double *c, const double *beta, int tl, double &mn, double &mx,
+                                          double &rmn, double &rmx) {
+  using Q = QuadShape<N>;
+  constexpr int P = Q::P, M = Q::M, R = Q::R, NT = Q::tile;
+  constexpr int SRM = qsize(R + M), SM = qsize(M);
+  using S1 = QuadSplits<N, P>;
+  using S2 = QuadSplits<R + M, R>;
+  using QD = QuadDenses<M>;
+  if (tl >= Q::lanes) return;
+  int kp[P];
+  {
+    int rem = tl;
+#pragma unroll
+    for (int v = P - 1; v >= 0; --v) {
+      kp[v] = rem % 3;
+      rem /= 3;
+    }
+  }
+  double wp[qsize(P)];
+  quad_weights<P>(kp, wp);
+  // fold the lane's variables: p1 over the other R + M variables
+  double p1[SRM];
+#pragma unroll
+  for (int q = 0; q < SRM; ++q) p1[q] = 0.0;
+  Unroll<0, qsize(N)>::run([&](auto Rk) {
+    constexpr int r = Rk.value, q = S1::t.rest[r], w = S1::t.pre[r];
+    p1[q] = fma(c[r], wp[w], p1[q]);
+  });
+  double cl = 0.0, g[M];
+  if constexpr (kFit) {
+    cl = beta[0];
+#pragma unroll
+    for (int v = 0; v < P; ++v) cl = fma(beta[1 + v], 0.5 * kp[v] - 0.5, cl);
+#pragma unroll
+    for (int m = 0; m < M; ++m) g[m] = beta[1 + P + R + m];
+  }
+#pragma unroll 1
+  for (int rho = 0; rho < Q::rounds; ++rho) {
+    double p2[SM];
+    double cr = cl;
+    if constexpr (R == 0) {
+#pragma unroll
+      for (int q = 0; q < SM; ++q) p2[q] = p1[q];
+    } else {
+      int kr[R];
+      int rem = rho;
+#pragma unroll
+      for (int v = R - 1; v >= 0; --v) {
+        kr[v] = rem % 3;
+        rem /= 3;
+      }
+      double wr[qsize(R)];
+      quad_weights<R>(kr, wr);
+#pragma unroll
+      for (int q = 0; q < SM; ++q) p2[q] = 0.0;
+      Unroll<0, SRM>::run([&](auto Rk) {
+        constexpr int r = Rk.value, q = S2::t.rest[r], w = S2::t.pre[r];
+        p2[q] = fma(p1[r], wr[w], p2[q]);
+      });
+      if constexpr (kFit) {
+#pragma unroll
+        for (int v = 0; v < R; ++v) cr = fma(beta[1 + P + v], 0.5 * kr[v] - 0.5, cr);
+      }
+    }
+    double x[NT];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) x[q] = 0.0;
+    Unroll<0, SM>::run([&](auto Rk) { x[QD::t.at[Rk.value]] = p2[Rk.value]; });
+    block_to_bern<2, M>(x);
+    Unroll<0, NT>::run([&](auto Qv) {
+      const double v = x[Qv.value];
+      mn = fmin(mn, v);
+      mx = fmax(mx, v);
+      if constexpr (kFit) {
+        double l = cr;
+        Unroll<0, M>::run([&](auto A) {
+          constexpr int t = (Qv.value / cpow(3, M - 1 - A.value)) % 3;
+          l = fma(g[A.value], 0.5 * t - 0.5, l);
+        });
+        rmn = fmin(rmn, v - l);
+        rmx = fmax(rmx, v - l);
+      }
+    });
+  }
+}
+
+// LDS of the quadratic read-off: the wave's reduction scratch, the two
+// fits, the two stored tensors.
+constexpr size_t quad_lds(int n) { return (size_t)(kRowScratch + 2 * (kMaxInputs + 1) + 2 * qsize(n)) * sizeof(double); }
+
+template <int N, typename T>
+__global__ void __launch_bounds__(64) convert_quad_t(ConvertArgs a) {
+  extern __shared__ double lds[];
+  if ((int64_t)blockIdx.x >= launch_boxes(a) * a.h) return;  // past a device count
+  const WaveTeam tm{(int)threadIdx.x, lds};
+  double *bl = lds + kRowScratch;
+  NTreePlan tp;  // what ntree_neuron reads of it: 32 lanes per tensor, the lower tensor's offset
+  tp.lanes = 32;
+  tp.area = qsize(N);
+  const int tl = (int)(threadIdx.x & 31), side = (int)(threadIdx.x >> 5);
+  ntree_neuron<2, T, true>(a, tp, tm, bl, blockIdx.x,
+                           [&](auto F, double *t0, double &mn, double &mx, double &rmn, double &rmx) {
+                             quad_pass<N, decltype(F)::value>(t0 + side * qsize(N), bl + side * (kMaxInputs + 1),
+                                                              tl, mn, mx, rmn, rmx);
+                           });
 }
 
 static NTreePlan ntree_plan(int n, int D, int M, bool wave_team, int sides = 2);
@@ -1942,6 +2189,59 @@ static bool launch_ntree(const ConvertArgs &a, hipStream_t s, bool wave_team, hi
   return true;
 }
 
+// The quadratic read-off's rank formula against the layout's own ranks,
+// checked once per n (no allocation).
+static bool quad_layout_ok(int n) {
+  static std::atomic<int> known[kMaxInputs + 1];  // 0 unknown, 1 matches, -1 not
+  if (n < 1 || n > kMaxInputs) return false;
+  const int k = known[n].load(std::memory_order_relaxed);
+  if (k != 0) return k > 0;
+  bool good = true;
+  for (int u = -1; u < n; ++u)
+    for (int v = -1; v < n; ++v) {
+      if ((u < 0 && v >= 0) || (v >= 0 && v < u)) continue;
+      uint16_t e[kMaxInputs] = {};
+      if (u >= 0) ++e[u];
+      if (v >= 0) ++e[v];
+      good = good && simplex_rank(n, e) == qrank(n, u, v);
+    }
+  known[n].store(good ? 1 : -1, std::memory_order_relaxed);
+  return good;
+}
+
+// Executed FP64 operations of one neuron's quadratic read-off (both
+// tensors): the lane fold (an FMA per stored coefficient), per round the
+// round fold, the tile's basis change (6 FMAs per fibre and axis) and its
+// extrema.
+static double quad_ops(int n) {
+  const int P = std::min(n - 1, 3), M = std::min(n - P, 3), R = n - P - M;
+  double tile = 1, lanes = 1, rounds = 1;
+  for (int i = 0; i < M; ++i) tile *= 3;
+  for (int i = 0; i < P; ++i) lanes *= 3;
+  for (int i = 0; i < R; ++i) rounds *= 3;
+  const double round = (R > 0 ? 2.0 * qsize(R + M) : 0.0) + 12.0 * M * tile / 3 + 2.0 * tile;
+  return 2.0 * lanes * (2.0 * qsize(n) + rounds * round);
+}
+
+template <typename T>
+static bool launch_quad(const ConvertArgs &a, hipStream_t s, hipError_t &err) {
+  if (a.n < 4 || a.n > 8 || a.S != qsize(a.n) || !quad_layout_ok(a.n)) return false;
+  const int64_t items = a.nboxes * a.h;
+  ProfScope ps(a.mode == 2 ? kProfLin : kProfConvertSmall, s,
+               items * readoff_neuron_bytes(a) + a.nboxes * readoff_box_bytes(a), (double)items * quad_ops(a.n));
+  const dim3 grid((unsigned)items), block(64);
+  const size_t lds = quad_lds(a.n);
+  switch (a.n) {
+    case 4: hipLaunchKernelGGL((convert_quad_t<4, T>), grid, block, lds, s, a); break;
+    case 5: hipLaunchKernelGGL((convert_quad_t<5, T>), grid, block, lds, s, a); break;
+    case 6: hipLaunchKernelGGL((convert_quad_t<6, T>), grid, block, lds, s, a); break;
+    case 7: hipLaunchKernelGGL((convert_quad_t<7, T>), grid, block, lds, s, a); break;
+    default: hipLaunchKernelGGL((convert_quad_t<8, T>), grid, block, lds, s, a); break;
+  }
+  err = hipGetLastError();
+  return true;
+}
+
 template <typename T, int D>
 static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
   // degree 1 tensors are read off in closed form, whatever n; the tree needs
@@ -1949,6 +2249,10 @@ static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
   if constexpr (D == 1) {
     return launch_affine<T>(a, s);
   } else {
+    if constexpr (D == 2) {  // quadratic tensors: the direct one-wave form unless tuned away
+      hipError_t err = hipSuccess;
+      if (a.tune.conv_wave == 0 && launch_quad<T>(a, s, err)) return err;
+    }
     if (a.tree) {
       hipError_t err = hipSuccess;
       if (a.tune.conv_wave == 0 && launch_ntree<T, D, ntree_tile_axes(D)>(a, s, false, err)) return err;
