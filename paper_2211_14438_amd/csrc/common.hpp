@@ -26,6 +26,17 @@ __device__ inline int64_t xcd_block(int64_t b, int64_t n) {
   return (b % 8) * (full / 8) + b / 8;
 }
 
+// Box-major order with the boxes dealt to the XCDs in turn: hardware block b
+// takes item (box, j) of an h-item-per-box launch with box = 8 (b / 8 / h) +
+// b % 8 and j = (b / 8) % h, so one box's items share an XCD and its L2, and
+// the live boxes under a device count stay spread over all XCDs. The grid
+// holds 8 ceil(nboxes / 8) h blocks; blocks past nboxes get -1.
+__device__ inline int64_t xcd_item(int64_t b, int h, int64_t nboxes) {
+  const int64_t idx = b >> 3, box = (idx / h) * 8 + (b & 7);
+  return box < nboxes ? box * h + idx % h : -1;
+}
+__host__ __device__ inline int64_t xcd_item_blocks(int64_t nboxes, int h) { return (nboxes + 7) / 8 * 8 * h; }
+
 void set_error(const char *fmt, ...);
 
 #define BERN_HIP_TRY(expr)                                                        \

@@ -194,11 +194,33 @@ __device__ void pre_radii(const ConvertArgs &a, int64_t box, int j, const void *
   epsL = (sL + gg + rL) * kPadSafety;
 }
 
+// The first share of a later FP32 layer's radius inputs (k = tid: the
+// weight, the previous layer's radii and l1 norms; cb = tid: the GEMM's
+// rounding partials), loaded by a caller before its coefficients so that
+// both loads are in flight together.
+struct RadiiIn {
+  double w = 0.0, r0 = 0.0, r1 = 0.0;
+  double4 P = {0.0, 0.0, 0.0, 0.0};
+};
+__device__ inline void radii_prefetch(const ConvertArgs &a, int64_t box, int j, int tid, RadiiIn &ri) {
+  if (a.mode == 2 || a.fp64 || a.layer == 0) return;
+  if (tid < a.hin) {
+    ri.w = a.W[(int64_t)j * a.hin + tid];
+    ri.P = *reinterpret_cast<const double4 *>(a.prad + (box * a.hin + tid) * 4);
+  }
+  if (tid < a.cblocks) {
+    const double *rp = a.rpart + box * a.rpart_slot + (int64_t)j * 2 * a.cblocks;
+    ri.r0 = rp[tid];
+    ri.r1 = rp[a.cblocks + tid];
+  }
+}
+
 // The radii and the two tensors' l1 norms (l1: the lane's shares in, the
-// team's totals out), their sums reduced together.
+// team's totals out), their sums reduced together. `ri`: the first share,
+// already loaded (radii_prefetch).
 template <class Team>
 __device__ void radii_and_l1(const ConvertArgs &a, int64_t box, int j, const Team &tm, double (&l1)[2],
-                             double &epsU, double &epsL) {
+                             double &epsU, double &epsL, const RadiiIn *ri = nullptr) {
   epsU = epsL = 0.0;
   if (a.mode == 2) {  // linearisation: the radii of the stored post polynomials
     if (!a.fp64) {
@@ -216,8 +238,9 @@ __device__ void radii_and_l1(const ConvertArgs &a, int64_t box, int j, const Tea
   }
   double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, l1[0], l1[1]};  // sU, sL, g, rU, rL, l1U, l1L
   for (int k = tm.tid; k < a.hin; k += tm.nt) {
-    const double wk = a.W[(int64_t)j * a.hin + k];
-    const double4 P = *reinterpret_cast<const double4 *>(a.prad + (box * a.hin + k) * 4);
+    const bool pre = ri && k == tm.tid;
+    const double wk = pre ? ri->w : a.W[(int64_t)j * a.hin + k];
+    const double4 P = pre ? ri->P : *reinterpret_cast<const double4 *>(a.prad + (box * a.hin + k) * 4);
     if (wk >= 0.0) {
       v[0] += wk * P.x;
       v[1] += wk * P.y;
@@ -229,8 +252,9 @@ __device__ void radii_and_l1(const ConvertArgs &a, int64_t box, int j, const Tea
   }
   const double *rp = a.rpart + box * a.rpart_slot + (int64_t)j * 2 * a.cblocks;
   for (int64_t cb = tm.tid; cb < a.cblocks; cb += tm.nt) {
-    v[3] += rp[cb];
-    v[4] += rp[a.cblocks + cb];
+    const bool pre = ri && cb == tm.tid;
+    v[3] += pre ? ri->r0 : rp[cb];
+    v[4] += pre ? ri->r1 : rp[a.cblocks + cb];
   }
   tm.reduce(v, OpAdd());
   l1[0] = v[5];
@@ -1785,7 +1809,9 @@ __device__ void ntree_neuron(const ConvertArgs &a, const NTreePlan &tp, const Te
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
   const int j = (int)(item % a.h);
   const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + (int64_t)j * 2 * a.S;
-  // the stored coefficients' loads first, the radii's behind them
+  // the radii's first inputs and the stored coefficients in flight together
+  RadiiIn ri;
+  radii_prefetch(a, box, j, tid, ri);
   double l1[2] = {0.0, 0.0};
   for (int i = tid; i < S; i += nt) {
     const double uu = (double)p[i], ww = (double)p[S + i];
@@ -1795,7 +1821,7 @@ __device__ void ntree_neuron(const ConvertArgs &a, const NTreePlan &tp, const Te
     l1[1] += fabs(ww);
   }
   double epsU, epsL;
-  radii_and_l1(a, box, j, tm, l1, epsU, epsL);
+  radii_and_l1(a, box, j, tm, l1, epsU, epsL, &ri);
   const double l1U = l1[0], l1L = l1[1];
   tm.sync();
   const int side = tid / tp.lanes;
@@ -1916,8 +1942,10 @@ __global__ void __launch_bounds__(kWave ? 64 * kNTeams : 1024) convert_ntree_t(C
 // out of the stored coefficients (each coefficient once, weighted by its
 // prefix monomial's value at the lane's digits), then for each of the 3^R
 // digit tuples of the next R variables folds those, and converts the
-// remaining M-variable tile in registers. The stored coefficients are read
-// as LDS broadcasts; the pass has no barrier. Rounding: a Bernstein
+// remaining M-variable tile (M <= 2, which keeps the wave's registers, and
+// so the waves per SIMD, in check) in registers. The stored coefficients are
+// read as LDS broadcasts; the pass has no barrier. A box's neurons run on
+// one XCD (xcd_item), sharing its radius inputs in one L2. Rounding: a Bernstein
 // coefficient is a sum of at most S(P,2) + S(R,2) + 2M rounded terms of
 // the |a_J| weighted by products of ratios in [0, 1], within the read-off's
 // gamma(n (D + 2) + 4) l1 bound for every n here.
@@ -2023,23 +2051,108 @@ __device__ __forceinline__ void quad_weights(const int (&k)[K > 0 ? K : 1], doub
 template <int N>
 struct QuadShape {
   static constexpr int P = N - 1 < 3 ? N - 1 : 3;          // lane variables
-  static constexpr int M = N - P < 3 ? N - P : 3;          // tile variables
+  static constexpr int M = N - P < 2 ? N - P : 2;          // tile variables
   static constexpr int R = N - P - M;                      // round variables
   static constexpr int lanes = cpow(3, P), rounds = cpow(3, R), tile = cpow(3, M);
 };
 
+// The degree-2 basis change of one fibre (y0, y1, y2) in place:
+// b_0 = y0, b_1 = y0 + y1/2, b_2 = (y0 + y1) + y2, leaving out the entries
+// that are structurally zero (kNz1, kNz2 false).
+template <bool kNz1, bool kNz2>
+__device__ __forceinline__ void to_bern2(double &y0, double &y1, double &y2) {
+  double b1 = y0, b2 = y0;
+  if constexpr (kNz1) {
+    b1 = fma(0.5, y1, y0);
+    b2 = y0 + y1;
+  }
+  if constexpr (kNz2) b2 = b2 + y2;
+  y1 = b1;
+  y2 = b2;
+}
+
+// Sum of the digits after axis a of dense tile position `pos` (M digits,
+// the first slowest).
+constexpr int tile_digits_after(int pos, int a, int M) {
+  int s = 0;
+  for (int b = a + 1; b < M; ++b) s += (pos / cpow(3, M - 1 - b)) % 3;
+  return s;
+}
+
+// Basis change of a dense M-variable degree-2 tile whose entries of total
+// degree above 2 are zero: axis by axis, an entry with digit t on the axis
+// being converted can be nonzero only if t plus the digits of the axes not
+// yet converted is at most 2, and such zeros are skipped.
+template <int M>
+__device__ __forceinline__ void tile_to_bern2(double (&x)[cpow(3, M)]) {
+  Unroll<0, M>::run([&](auto A) {
+    constexpr int s = cpow(3, M - 1 - A.value);
+    Unroll<0, cpow(3, M) / 3>::run([&](auto L) {
+      constexpr int line = (L.value / s) * s * 3 + L.value % s;
+      constexpr int rest = tile_digits_after(line, A.value, M);
+      to_bern2<1 + rest <= 2, 2 + rest <= 2>(x[line], x[line + s], x[line + 2 * s]);
+    });
+  });
+}
+
+// Value of monomial t_u t_v (layout factors; -1 absent) at Bernstein
+// digits k of degree 2: 1, k_u/2, [k_u = 2] or k_u k_v / 4.
+constexpr double quad_weight(int u, int v, const int *k) {
+  return u < 0 ? 1.0 : v < 0 ? 0.5 * k[u] : u == v ? (k[u] == 2 ? 1.0 : 0.0) : 0.25 * k[u] * k[v];
+}
+
+// Fold of the R round variables at the digits of round `Rho` (first
+// variable slowest) out of a polynomial over R + M variables: for each
+// tile monomial t, the terms q (ascending) with a nonzero weight.
+template <int R, int M, int Rho>
+struct QuadRoundFold {
+  int nt[qsize(M)], q[qsize(M)][qsize(R)];
+  double w[qsize(M)][qsize(R)];
+  int k[R > 0 ? R : 1];
+  constexpr QuadRoundFold() : nt(), q(), w(), k() {
+    int rem = Rho;
+    for (int v = R - 1; v >= 0; --v) {
+      k[v] = rem % 3;
+      rem /= 3;
+    }
+    const QuadMono<R + M> m{};
+    for (int r = 0; r < qsize(R + M); ++r) {
+      int f[2] = {m.u[r], m.v[r]}, rf[2] = {-1, -1}, tf[2] = {-1, -1}, nr = 0, nm = 0;
+      for (int i = 0; i < 2; ++i) {
+        if (f[i] < 0) continue;
+        if (f[i] < R)
+          rf[nr++] = f[i];
+        else
+          tf[nm++] = f[i] - R;
+      }
+      const double wt = quad_weight(rf[0], rf[1], k);
+      if (wt == 0.0) continue;
+      const int t = qrank(M, tf[0], tf[1]);
+      q[t][nt[t]] = r;
+      w[t][nt[t]] = wt;
+      ++nt[t];
+    }
+  }
+};
+template <int R, int M, int Rho>
+struct QuadRoundFolds {
+  static constexpr QuadRoundFold<R, M, Rho> t{};
+};
+
 // One pass over the lane's share of its tensor (`c`, the S(N,2) stored
-// coefficients in LDS; fit `beta` when kFit): extrema of the Bernstein
-// coefficients into mn / mx and of the remainders b_K - l(K/2) into
-// rmn / rmx, l(x) = beta_0 + sum_a beta_a (x_a - 1/2).
+// coefficients in LDS). Without kFit only the extremum the bound needs is
+// kept: the maximum of the upper tensor (side 0) into mx, the minimum of
+// the lower (side 1) into mn, both as a maximum over the lane's
+// coefficients times +1 or -1 (the sign folded into the lane's weights,
+// exact). With kFit, both extrema and those of the remainders
+// b_K - l(K/2), l(x) = beta_0 + sum_a beta_a (x_a - 1/2), into rmn / rmx.
 template <int N, bool kFit>
-__device__ __forceinline__ void quad_pass(const double *c, const double *beta, int tl, double &mn, double &mx,
-                                          double &rmn, double &rmx) {
+__device__ __forceinline__ void quad_pass(const double *c, const double *beta, int tl, int side, double &mn,
+                                          double &mx, double &rmn, double &rmx) {
   using Q = QuadShape<N>;
   constexpr int P = Q::P, M = Q::M, R = Q::R, NT = Q::tile;
   constexpr int SRM = qsize(R + M), SM = qsize(M);
   using S1 = QuadSplits<N, P>;
-  using S2 = QuadSplits<R + M, R>;
   using QD = QuadDenses<M>;
   if (tl >= Q::lanes) return;
   int kp[P];
@@ -2053,6 +2166,11 @@ __device__ __forceinline__ void quad_pass(const double *c, const double *beta, i
   }
   double wp[qsize(P)];
   quad_weights<P>(kp, wp);
+  if constexpr (!kFit) {
+    const double sgn = side ? -1.0 : 1.0;
+#pragma unroll
+    for (int q = 0; q < qsize(P); ++q) wp[q] *= sgn;
+  }
   // fold the lane's variables: p1 over the other R + M variables
   double p1[SRM];
 #pragma unroll
@@ -2069,44 +2187,43 @@ __device__ __forceinline__ void quad_pass(const double *c, const double *beta, i
 #pragma unroll
     for (int m = 0; m < M; ++m) g[m] = beta[1 + P + R + m];
   }
-#pragma unroll 1
-  for (int rho = 0; rho < Q::rounds; ++rho) {
-    double p2[SM];
-    double cr = cl;
-    if constexpr (R == 0) {
-#pragma unroll
-      for (int q = 0; q < SM; ++q) p2[q] = p1[q];
-    } else {
-      int kr[R];
-      int rem = rho;
-#pragma unroll
-      for (int v = R - 1; v >= 0; --v) {
-        kr[v] = rem % 3;
-        rem /= 3;
-      }
-      double wr[qsize(R)];
-      quad_weights<R>(kr, wr);
-#pragma unroll
-      for (int q = 0; q < SM; ++q) p2[q] = 0.0;
-      Unroll<0, SRM>::run([&](auto Rk) {
-        constexpr int r = Rk.value, q = S2::t.rest[r], w = S2::t.pre[r];
-        p2[q] = fma(p1[r], wr[w], p2[q]);
-      });
-      if constexpr (kFit) {
-#pragma unroll
-        for (int v = 0; v < R; ++v) cr = fma(beta[1 + P + v], 0.5 * kr[v] - 0.5, cr);
-      }
-    }
+  double best = -INFINITY;
+  Unroll<0, Q::rounds>::run([&](auto Rho) {
+    using F = QuadRoundFolds<R, M, Rho.value>;
     double x[NT];
 #pragma unroll
-    for (int q = 0; q < NT; ++q) x[q] = 0.0;
-    Unroll<0, SM>::run([&](auto Rk) { x[QD::t.at[Rk.value]] = p2[Rk.value]; });
-    block_to_bern<2, M>(x);
-    Unroll<0, NT>::run([&](auto Qv) {
-      const double v = x[Qv.value];
-      mn = fmin(mn, v);
-      mx = fmax(mx, v);
-      if constexpr (kFit) {
+    for (int i = 0; i < NT; ++i) x[i] = 0.0;
+    Unroll<0, SM>::run([&](auto T) {
+      constexpr int t = T.value;
+      if constexpr (R == 0) {
+        x[QD::t.at[t]] = p1[t];
+      } else {
+        constexpr int n0 = F::t.nt[t];
+        static_assert(n0 >= 1, "every tile monomial keeps its round-constant term");
+        constexpr double w0 = F::t.w[t][0];
+        double acc = w0 == 1.0 ? p1[F::t.q[t][0]] : w0 * p1[F::t.q[t][0]];  // exact: w0 is a power of 2
+        Unroll<1, n0>::run([&](auto I) {
+          constexpr double wi = F::t.w[t][I.value];
+          constexpr int qi = F::t.q[t][I.value];
+          acc = wi == 1.0 ? acc + p1[qi] : fma(wi, p1[qi], acc);
+        });
+        x[QD::t.at[t]] = acc;
+      }
+    });
+    tile_to_bern2<M>(x);
+    if constexpr (!kFit) {
+#pragma unroll
+      for (int i = 0; i < NT; ++i) best = fmax(best, x[i]);
+    } else {
+      double cr = cl;
+      Unroll<0, R>::run([&](auto V) {
+        constexpr double gv = 0.5 * F::t.k[V.value] - 0.5;
+        cr = fma(beta[1 + P + V.value], gv, cr);
+      });
+      Unroll<0, NT>::run([&](auto Qv) {
+        const double v = x[Qv.value];
+        mn = fmin(mn, v);
+        mx = fmax(mx, v);
         double l = cr;
         Unroll<0, M>::run([&](auto A) {
           constexpr int t = (Qv.value / cpow(3, M - 1 - A.value)) % 3;
@@ -2114,8 +2231,14 @@ __device__ __forceinline__ void quad_pass(const double *c, const double *beta, i
         });
         rmn = fmin(rmn, v - l);
         rmx = fmax(rmx, v - l);
-      }
-    });
+      });
+    }
+  });
+  if constexpr (!kFit) {
+    if (side == 0)
+      mx = fmax(mx, best);
+    else
+      mn = fmin(mn, -best);
   }
 }
 
@@ -2126,17 +2249,18 @@ constexpr size_t quad_lds(int n) { return (size_t)(kRowScratch + 2 * (kMaxInputs
 template <int N, typename T>
 __global__ void __launch_bounds__(64) convert_quad_t(ConvertArgs a) {
   extern __shared__ double lds[];
-  if ((int64_t)blockIdx.x >= launch_boxes(a) * a.h) return;  // past a device count
+  const int64_t item = xcd_item(blockIdx.x, a.h, launch_boxes(a));  // a box's neurons on one XCD
+  if (item < 0) return;                                             // past the boxes (or a device count)
   const WaveTeam tm{(int)threadIdx.x, lds};
   double *bl = lds + kRowScratch;
   NTreePlan tp;  // what ntree_neuron reads of it: 32 lanes per tensor, the lower tensor's offset
   tp.lanes = 32;
   tp.area = qsize(N);
   const int tl = (int)(threadIdx.x & 31), side = (int)(threadIdx.x >> 5);
-  ntree_neuron<2, T, true>(a, tp, tm, bl, blockIdx.x,
+  ntree_neuron<2, T, true>(a, tp, tm, bl, item,
                            [&](auto F, double *t0, double &mn, double &mx, double &rmn, double &rmx) {
                              quad_pass<N, decltype(F)::value>(t0 + side * qsize(N), bl + side * (kMaxInputs + 1),
-                                                              tl, mn, mx, rmn, rmx);
+                                                              tl, side, mn, mx, rmn, rmx);
                            });
 }
 
@@ -2214,7 +2338,7 @@ static bool quad_layout_ok(int n) {
 // round fold, the tile's basis change (6 FMAs per fibre and axis) and its
 // extrema.
 static double quad_ops(int n) {
-  const int P = std::min(n - 1, 3), M = std::min(n - P, 3), R = n - P - M;
+  const int P = std::min(n - 1, 3), M = std::min(n - P, 2), R = n - P - M;
   double tile = 1, lanes = 1, rounds = 1;
   for (int i = 0; i < M; ++i) tile *= 3;
   for (int i = 0; i < P; ++i) lanes *= 3;
@@ -2229,7 +2353,7 @@ static bool launch_quad(const ConvertArgs &a, hipStream_t s, hipError_t &err) {
   const int64_t items = a.nboxes * a.h;
   ProfScope ps(a.mode == 2 ? kProfLin : kProfConvertSmall, s,
                items * readoff_neuron_bytes(a) + a.nboxes * readoff_box_bytes(a), (double)items * quad_ops(a.n));
-  const dim3 grid((unsigned)items), block(64);
+  const dim3 grid((unsigned)xcd_item_blocks(a.nboxes, a.h)), block(64);
   const size_t lds = quad_lds(a.n);
   switch (a.n) {
     case 4: hipLaunchKernelGGL((convert_quad_t<4, T>), grid, block, lds, s, a); break;
