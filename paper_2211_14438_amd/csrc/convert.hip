@@ -1766,9 +1766,11 @@ __device__ void ntree_pass(const ConvertArgs &a, const NTreePlan &tp, const Team
 // block of four, each wave with its own neuron and LDS slice (kWave true).
 // An output neuron's one bound (bside 0 upper, 1 lower) by a block with
 // one tree (tp.sides == 1): its extremum, radius and output bound only.
-template <int D, int M, typename T, class Team>
-__device__ void ntree_output_side(const ConvertArgs &a, const NTreePlan &tp, const Team &tm, const int *tb,
-                                  const double *tab, double *bl, int64_t item, int bside) {
+// `pass(t0, mn, mx)` runs one pass over the tensor at t0 (the bound's
+// extremum: mx for the upper tensor, mn for the lower).
+template <typename T, class Team, class Pass>
+__device__ void ntree_output_side(const ConvertArgs &a, const Team &tm, double *bl, int64_t item, int bside,
+                                  Pass pass) {
   const int tid = tm.tid, nt = tm.nt, S = (int)a.S;
   double *t0 = bl + 2 * (kMaxInputs + 1);
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
@@ -1783,8 +1785,8 @@ __device__ void ntree_output_side(const ConvertArgs &a, const NTreePlan &tp, con
   double epsU, epsL;
   radii_and_l1(a, box, j, tm, l1, epsU, epsL);
   tm.sync();
-  double mn = INFINITY, mx = -INFINITY, rmn = INFINITY, rmx = -INFINITY;
-  ntree_pass<D, M, false>(a, tp, tm, tb, tab, t0, bl, mn, mx, rmn, rmx);
+  double mn = INFINITY, mx = -INFINITY;
+  pass(t0, mn, mx);
   double ex[2] = {mx, -mn};
   tm.reduce(ex, OpMax());
   if (tid != 0) return;
@@ -1921,7 +1923,11 @@ __global__ void __launch_bounds__(kWave ? 64 * kNTeams : 1024) convert_ntree_t(C
   } else {
     const BlockTeam tm{(int)threadIdx.x, (int)blockDim.x, red};
     if constexpr (kSide)
-      ntree_output_side<D, M, T>(a, tp, tm, tb, tab, slices, blockIdx.x >> 1, (int)(blockIdx.x & 1));
+      ntree_output_side<T>(a, tm, slices, blockIdx.x >> 1, (int)(blockIdx.x & 1),
+                           [&](double *t0, double &mn, double &mx) {
+                             double rmn = INFINITY, rmx = -INFINITY;
+                             ntree_pass<D, M, false>(a, tp, tm, tb, tab, t0, slices, mn, mx, rmn, rmx);
+                           });
     else
       ntree_neuron<D, T, false>(a, tp, tm, slices, blockIdx.x,
                                 [&](auto F, double *t0, double &mn, double &mx, double &rmn, double &rmx) {
@@ -2264,6 +2270,294 @@ __global__ void __launch_bounds__(64) convert_quad_t(ConvertArgs a) {
                            });
 }
 
+// --------------------------------- output tensors of degree 3 or 4, direct
+// The same direct fold as the degree-2 read-off for an output neuron's
+// bound tensor at degree D = 3 or 4 (one block per bound, as the tree's
+// output form): each lane fixes the Bernstein digits of the first P
+// variables ((D+1)^P <= 128 lanes), folds them out of the stored
+// coefficients with the ratios C(k,j)/C(D,j) of its digits (prefix
+// monomial by prefix monomial, each stored coefficient once), folds the next
+// R variables per round at compile-time digits, and converts its M <= 2
+// variable tile in registers, keeping only the bound's extremum.
+
+// Exponents of the N-variable degree-D layout in rank order (simplex.hpp
+// order: graded by total degree, descending lexicographic within one).
+template <int D, int N>
+struct DLayout {
+  static constexpr int count = (int)binom_u(N + D, D);
+  int e[count][N > 0 ? N : 1];
+  constexpr DLayout() : e() {
+    int r = 0;
+    for (int t = 0; t <= D && N > 0; ++t) {
+      int x[N > 0 ? N : 1] = {};
+      x[0] = t;
+      for (;;) {
+        for (int a = 0; a < N; ++a) e[r][a] = x[a];
+        ++r;
+        int i = N - 2;  // the next tuple of the same degree, descending
+        while (i >= 0 && x[i] == 0) --i;
+        if (i < 0) break;
+        int tail = 0;
+        for (int b = i + 1; b < N; ++b) {
+          tail += x[b];
+          x[b] = 0;
+        }
+        --x[i];
+        x[i + 1] = tail + 1;
+      }
+    }
+  }
+};
+template <int D, int N>
+struct DLayouts {
+  static constexpr DLayout<D, N> t{};
+};
+
+// Layout rank of the exponents e[0..n) (any total degree).
+constexpr int drank(int n, const int *e) {
+  int d = 0;
+  for (int i = 0; i < n; ++i) d += e[i];
+  int r = d > 0 ? (int)binom_u(n + d - 1, n) : 0;  // every monomial of lower degree
+  int rem = d;
+  for (int i = 0; i + 1 < n; ++i) {
+    const int m = n - 2 - i;
+    for (int v = e[i] + 1; v <= rem; ++v) r += (int)binom_u(rem - v + m, m);
+    rem -= e[i];
+  }
+  return r;
+}
+
+template <int D, int N>
+struct DirectShape {
+  static constexpr int D1 = D + 1;
+  static constexpr int P = [] {
+    int p = 1;
+    while (p + 1 <= N - 1 && cpow(D + 1, p + 1) <= 128) ++p;
+    return p;
+  }();
+  static constexpr int M = N - P < 2 ? N - P : 2;
+  static constexpr int R = N - P - M;
+  static constexpr int lanes = cpow(D1, P), rounds = cpow(D1, R), tile = cpow(D1, M);
+  static constexpr int threads = (lanes + 63) / 64 * 64;
+};
+
+// Rank in the N-variable layout of (prefix monomial m of P variables, rest
+// monomial q of N - P), -1 when the total degree exceeds D.
+template <int D, int N, int P>
+struct DJoin {
+  static constexpr int SP = (int)binom_u(P + D, D), SQ = (int)binom_u(N - P + D, D);
+  int r[SP][SQ];
+  constexpr DJoin() : r() {
+    const DLayout<D, P> lp{};
+    const DLayout<D, N - P> lq{};
+    for (int m = 0; m < SP; ++m)
+      for (int q = 0; q < SQ; ++q) {
+        int e[N] = {}, d = 0;
+        for (int a = 0; a < P; ++a) d += e[a] = lp.e[m][a];
+        for (int a = 0; a < N - P; ++a) d += e[P + a] = lq.e[q][a];
+        r[m][q] = d <= D ? drank(N, e) : -1;
+      }
+  }
+};
+template <int D, int N, int P>
+struct DJoins {
+  static constexpr DJoin<D, N, P> t{};
+};
+
+// The round fold at compile-time digits: for each tile monomial t of M
+// variables, the terms q of the (R+M)-variable polynomial with a nonzero
+// weight prod_a C(k_a, e_a)/C(D, e_a) over the round variables, ascending q.
+template <int D, int R, int M, int Rho>
+struct DRoundFold {
+  static constexpr int SRM = (int)binom_u(R + M + D, D), SM = (int)binom_u(M + D, D);
+  int nt[SM], q[SM][SRM];
+  double w[SM][SRM];
+  int k[R > 0 ? R : 1];
+  constexpr DRoundFold() : nt(), q(), w(), k() {
+    const Ratio<D> rt{};
+    int rem = Rho;
+    for (int v = R - 1; v >= 0; --v) {
+      k[v] = rem % (D + 1);
+      rem /= (D + 1);
+    }
+    const DLayout<D, R + M> l{};
+    for (int r = 0; r < SRM; ++r) {
+      double wt = 1.0;
+      for (int a = 0; a < R; ++a)
+        if (l.e[r][a] > 0) wt = wt * rt.v[k[a]][l.e[r][a]];
+      if (wt == 0.0) continue;
+      int et[M > 0 ? M : 1] = {};
+      for (int a = 0; a < M; ++a) et[a] = l.e[r][R + a];
+      const int t = drank(M, et);
+      q[t][nt[t]] = r;
+      w[t][nt[t]] = wt;
+      ++nt[t];
+    }
+  }
+};
+template <int D, int R, int M, int Rho>
+struct DRoundFolds {
+  static constexpr DRoundFold<D, R, M, Rho> t{};
+};
+
+// Dense tile position (digits, first variable slowest) of the rank-t
+// monomial of the M-variable layout.
+template <int D, int M>
+struct DTilePos {
+  static constexpr int SM = (int)binom_u(M + D, D);
+  int at[SM];
+  constexpr DTilePos() : at() {
+    const DLayout<D, M> l{};
+    for (int t = 0; t < SM; ++t) {
+      int v = 0;
+      for (int a = 0; a < M; ++a) v = v * (D + 1) + l.e[t][a];
+      at[t] = v;
+    }
+  }
+};
+template <int D, int M>
+struct DTilePoss {
+  static constexpr DTilePos<D, M> t{};
+};
+
+// Sum of the digits (base b) after axis a of dense position `pos` (M digits,
+// the first slowest).
+constexpr int tile_digits_after_d(int pos, int a, int M, int b) {
+  int s = 0;
+  for (int c = a + 1; c < M; ++c) s += (pos / cpow(b, M - 1 - c)) % b;
+  return s;
+}
+
+// Basis change of a dense M-variable degree-D tile whose entries of total
+// degree above D are zero; along each axis the entries that can be nonzero
+// (digit plus the digits of the axes not yet converted at most D) only.
+template <int D, int M>
+__device__ __forceinline__ void tile_to_bern(double (&x)[cpow(D + 1, M)]) {
+  constexpr int D1 = D + 1;
+  constexpr Ratio<D> rt{};
+  Unroll<0, M>::run([&](auto A) {
+    constexpr int st = cpow(D1, M - 1 - A.value);
+    Unroll<0, cpow(D1, M) / D1>::run([&](auto L) {
+      constexpr int line = (L.value / st) * st * D1 + L.value % st;
+      constexpr int jmax = D - tile_digits_after_d(line, decltype(A)::value, M, D1);  // entries j > jmax are zero
+      if constexpr (jmax >= 0) {
+        double y[D1];
+#pragma unroll
+        for (int j = 0; j < D1; ++j) y[j] = x[line + j * st];
+        Unroll<0, D1>::run([&](auto K) {
+          constexpr int kk = D - K.value;  // descending k keeps y_j (j < k)
+          double sacc = y[0];
+          Unroll<1, (kk < jmax ? kk : jmax) + 1>::run([&](auto J) {
+            constexpr double r = rt.v[kk][J.value];
+            sacc = r == 1.0 ? sacc + y[J.value] : fma(r, y[J.value], sacc);
+          });
+          x[line + kk * st] = sacc;
+        });
+      }
+    });
+  });
+}
+
+// One bound's pass over its stored coefficients c (LDS), lanes < lanes
+// active, the ratio table in LDS: the maximum of the upper tensor
+// (bside 0) into mx, the minimum of the lower into mn.
+template <int D, int N>
+__device__ __forceinline__ void direct_side_pass(const double *c, const double *tab, int tid, int bside, double &mn,
+                                                 double &mx) {
+  using Q = DirectShape<D, N>;
+  constexpr int D1 = D + 1, P = Q::P, M = Q::M, R = Q::R, NT = Q::tile;
+  constexpr int SP = (int)binom_u(P + D, D), SRM = (int)binom_u(R + M + D, D), SM = (int)binom_u(M + D, D);
+  using LP = DLayouts<D, P>;
+  using LQ = DLayouts<D, R + M>;
+  using J = DJoins<D, N, P>;
+  using TP = DTilePoss<D, M>;
+  if (tid >= Q::lanes) return;
+  double rho[P][D1];  // the ratios of the lane's digits
+  {
+    int rem = tid;
+#pragma unroll
+    for (int v = P - 1; v >= 0; --v) {
+      const int k = rem % D1;
+      rem /= D1;
+#pragma unroll
+      for (int j = 0; j < D1; ++j) rho[v][j] = tab[k * D1 + j];
+    }
+  }
+  const double sgn = bside ? -1.0 : 1.0;
+  double p1[SRM];
+#pragma unroll
+  for (int q = 0; q < SRM; ++q) p1[q] = 0.0;
+  Unroll<0, SP>::run([&](auto Mm) {
+    constexpr int m = Mm.value;
+    double w = sgn;
+    Unroll<0, P>::run([&](auto A) {
+      constexpr int e = LP::t.e[m][A.value];
+      if constexpr (e > 0) w *= rho[A.value][e];
+    });
+    Unroll<0, SRM>::run([&](auto Qq) {
+      constexpr int r = J::t.r[m][Qq.value];
+      if constexpr (r >= 0) p1[Qq.value] = fma(c[r], w, p1[Qq.value]);
+    });
+  });
+  double best = -INFINITY;
+  Unroll<0, Q::rounds>::run([&](auto Rho) {
+    using F = DRoundFolds<D, R, M, Rho.value>;
+    double x[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) x[i] = 0.0;
+    Unroll<0, SM>::run([&](auto T) {
+      constexpr int t = T.value;
+      if constexpr (R == 0) {
+        x[TP::t.at[t]] = p1[t];
+      } else {
+        constexpr int n0 = F::t.nt[t];
+        static_assert(n0 >= 1, "every tile monomial keeps its round-constant term");
+        constexpr double w0 = F::t.w[t][0];
+        double acc = w0 == 1.0 ? p1[F::t.q[t][0]] : w0 * p1[F::t.q[t][0]];
+        Unroll<1, n0>::run([&](auto I) {
+          constexpr double wi = F::t.w[t][I.value];
+          constexpr int qi = F::t.q[t][I.value];
+          acc = wi == 1.0 ? acc + p1[qi] : fma(wi, p1[qi], acc);
+        });
+        x[TP::t.at[t]] = acc;
+      }
+    });
+    tile_to_bern<D, M>(x);
+#pragma unroll
+    for (int i = 0; i < NT; ++i) best = fmax(best, x[i]);
+  });
+  if (bside == 0)
+    mx = fmax(mx, best);
+  else
+    mn = fmin(mn, -best);
+}
+
+// Rounding steps of the direct read-off beyond its terms' count: a prefix
+// weight is a product of P rounded ratios (2P - 1 roundings), a round's
+// weight one of R, and each tile axis adds one rounded ratio per term.
+constexpr int direct_depth(int D, int N, int P, int R, int M) {
+  return (int)binom_u(P + D, D) + 2 * P - 1 + (R > 0 ? (int)binom_u(R + D, D) + 2 * R - 1 : 0) + M * (D + 2);
+}
+
+template <int D, int N, typename T>
+__global__ void __launch_bounds__(128) convert_direct_side_t(ConvertArgs a) {  // DirectShape::threads <= 128
+  extern __shared__ double lds[];
+  __shared__ double red[kRedDoubles];
+  constexpr int D1 = D + 1;
+  constexpr Ratio<D> Rt{};
+  const int64_t item = blockIdx.x >> 1;
+  if (item >= launch_boxes(a) * a.h) return;  // past a device count
+  double *tab = lds;
+  if (threadIdx.x < D1 * D1) tab[threadIdx.x] = Rt.v[threadIdx.x / D1][threadIdx.x % D1];
+  __syncthreads();
+  double *bl = tab + D1 * D1;  // the fits' space (unused here), then the tensor
+  const BlockTeam tm{(int)threadIdx.x, (int)blockDim.x, red};
+  const int bside = (int)(blockIdx.x & 1);
+  ntree_output_side<T>(a, tm, bl, item, bside, [&](double *t0, double &mn, double &mx) {
+    direct_side_pass<D, N>(t0, tab, (int)threadIdx.x, bside, mn, mx);
+  });
+}
+
 static NTreePlan ntree_plan(int n, int D, int M, bool wave_team, int sides = 2);
 static size_t ntree_lds(const NTreePlan &tp, int n, int D, int teams, bool wave);
 
@@ -2366,6 +2660,45 @@ static bool launch_quad(const ConvertArgs &a, hipStream_t s, hipError_t &err) {
   return true;
 }
 
+// Executed FP64 operations of one bound's direct read-off at degree D.
+static double direct_side_ops(int D, int n, int P, int R, int M) {
+  double lanes = 1, rounds = 1, tile = 1;
+  for (int i = 0; i < P; ++i) lanes *= D + 1;
+  for (int i = 0; i < R; ++i) rounds *= D + 1;
+  for (int i = 0; i < M; ++i) tile *= D + 1;
+  const double per_round = 2.0 * (double)ssize(R + M, D) + M * tile * (D + 2) + tile;
+  return lanes * (2.0 * (double)ssize(n, D) + 2.0 * (double)ssize(P, D) + rounds * per_round);
+}
+
+template <typename T, int D, int N>
+static void launch_direct_side_n(const ConvertArgs &a, hipStream_t s) {
+  using Q = DirectShape<D, N>;
+  const size_t lds = ((D + 1) * (D + 1) + 2 * (kMaxInputs + 1) + ssize(N, D)) * sizeof(double);
+  hipLaunchKernelGGL((convert_direct_side_t<D, N, T>), dim3((unsigned)(a.nboxes * a.h * 2)), dim3(Q::threads), lds, s,
+                     a);
+}
+
+// Output layers at degree 3 or 4 with 5 or 6 inputs: a block per bound.
+template <typename T, int D>
+static bool launch_direct_side(const ConvertArgs &a_in, hipStream_t s, hipError_t &err) {
+  if (a_in.mode != 1 || a_in.n < 5 || a_in.n > 6 || a_in.S != ssize(a_in.n, D)) return false;
+  ConvertArgs a = a_in;
+  int P = 1;
+  while (P + 1 <= a.n - 1 && ipow(D + 1, P + 1) <= 128) ++P;
+  const int M = std::min(a.n - P, 2), R = a.n - P - M;
+  // the read-off pad covers this kernel's rounding steps
+  a.gconv = gamma64(std::max((double)a.n * (D + 2) + 4, (double)direct_depth(D, a.n, P, R, M)) + a.gextra);
+  const int64_t items = a.nboxes * a.h;
+  ProfScope ps(kProfConvertSmall, s, items * readoff_neuron_bytes(a) + a.nboxes * readoff_box_bytes(a),
+               (double)items * direct_side_ops(D, a.n, P, R, M));
+  if (a.n == 5)
+    launch_direct_side_n<T, D, 5>(a, s);
+  else
+    launch_direct_side_n<T, D, 6>(a, s);
+  err = hipGetLastError();
+  return true;
+}
+
 template <typename T, int D>
 static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
   // degree 1 tensors are read off in closed form, whatever n; the tree needs
@@ -2376,6 +2709,10 @@ static hipError_t launch_convert_t(const ConvertArgs &a, hipStream_t s) {
     if constexpr (D == 2) {  // quadratic tensors: the direct one-wave form unless tuned away
       hipError_t err = hipSuccess;
       if (a.tune.conv_wave == 0 && launch_quad<T>(a, s, err)) return err;
+    }
+    if constexpr (D == 3 || D == 4) {  // output bounds: the direct form unless tuned away
+      hipError_t err = hipSuccess;
+      if (a.tune.conv_wave == 0 && launch_direct_side<T, D>(a, s, err)) return err;
     }
     if (a.tree) {
       hipError_t err = hipSuccess;
