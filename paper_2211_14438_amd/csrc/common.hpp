@@ -26,6 +26,14 @@ __device__ inline int64_t xcd_block(int64_t b, int64_t n) {
   return (b % 8) * (full / 8) + b / 8;
 }
 
+// Orders a wave's LDS accesses (and the compiler's) around a point where the
+// wave's lanes read what other lanes wrote.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Box-major order with the boxes dealt to the XCDs in turn: hardware block b
 // takes item (box, j) of an h-item-per-box launch with box = 8 (b / 8 / h) +
 // b % 8 and j = (b / 8) % h, so one box's items share an XCD and its L2, and

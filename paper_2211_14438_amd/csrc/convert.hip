@@ -404,12 +404,6 @@ __global__ void __launch_bounds__(kBlock) convert_small_kernel(ConvertArgs a) {
 // export needs them (unstable neurons, or every neuron when exporting).
 constexpr int kWaveC = 1024;
 
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 template <typename Op>
 __device__ inline double wave_reduce(double v, Op op) {
   for (int off = 32; off > 0; off >>= 1) v = op(v, __shfl_xor(v, off, 64));
