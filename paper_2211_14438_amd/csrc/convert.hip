@@ -1776,11 +1776,14 @@ __device__ void ntree_output_side(const ConvertArgs &a, const Team &tm, double *
     t0[i] = v;
     l1[bside] += fabs(v);
   }
-  double epsU, epsL;
-  radii_and_l1(a, box, j, tm, l1, epsU, epsL);
   tm.sync();
+  // the radii's first inputs past the barrier: they arrive while the pass runs
+  RadiiIn ri;
+  radii_prefetch(a, box, j, tid, ri);
   double mn = INFINITY, mx = -INFINITY;
   pass(t0, mn, mx);
+  double epsU, epsL;
+  radii_and_l1(a, box, j, tm, l1, epsU, epsL, &ri);
   double ex[2] = {mx, -mn};
   tm.reduce(ex, OpMax());
   if (tid != 0) return;
@@ -1805,9 +1808,6 @@ __device__ void ntree_neuron(const ConvertArgs &a, const NTreePlan &tp, const Te
   const int64_t box = a.bids ? a.bids[item / a.h] : item / a.h;
   const int j = (int)(item % a.h);
   const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + (int64_t)j * 2 * a.S;
-  // the radii's first inputs and the stored coefficients in flight together
-  RadiiIn ri;
-  radii_prefetch(a, box, j, tid, ri);
   double l1[2] = {0.0, 0.0};
   for (int i = tid; i < S; i += nt) {
     const double uu = (double)p[i], ww = (double)p[S + i];
@@ -1816,10 +1816,11 @@ __device__ void ntree_neuron(const ConvertArgs &a, const NTreePlan &tp, const Te
     l1[0] += fabs(uu);
     l1[1] += fabs(ww);
   }
-  double epsU, epsL;
-  radii_and_l1(a, box, j, tm, l1, epsU, epsL, &ri);
-  const double l1U = l1[0], l1L = l1[1];
   tm.sync();
+  // the radii's first inputs, loaded past the barrier (which waits for every
+  // outstanding load) so that they arrive while the pass runs
+  RadiiIn ri;
+  radii_prefetch(a, box, j, tid, ri);
   const int side = tid / tp.lanes;
   // Affine fits (closed form from the stored coefficients) go to the
   // neurons that may take a fitted rule and turn out unstable, or to every
@@ -1842,6 +1843,10 @@ __device__ void ntree_neuron(const ConvertArgs &a, const NTreePlan &tp, const Te
     pass(std::true_type{}, t0, mn, mx, rmn, rmx);
   else
     pass(std::false_type{}, t0, mn, mx, rmn, rmx);
+  // the radii after the pass: their loads arrive while it runs
+  double epsU, epsL;
+  radii_and_l1(a, box, j, tm, l1, epsU, epsL, &ri);
+  const double l1U = l1[0], l1L = l1[1];
   // maxima of: max U, -min L, and the remainders' max U, -min U, max L, -min L
   double ex[6] = {side == 0 ? mx : -INFINITY, side == 1 ? -mn : -INFINITY, side == 0 ? rmx : -INFINITY,
                   side == 0 ? -rmn : -INFINITY, side == 1 ? rmx : -INFINITY, side == 1 ? -rmn : -INFINITY};
