@@ -195,22 +195,30 @@ __global__ void __launch_bounds__(256) features_kernel(LearnArgs a) {
   for (int q = 0; q < kF; ++q) a.feat[(box * a.nh + a.noff + j) * kF + q] = f[q];
 }
 
-// Features -> BF16 MLP -> class. A block takes 64 (box, neuron) items: one
-// thread each reads the features, and the unstable items (the only ones
-// whose rule depends on the predictor; the others get class -1) are listed
-// and taken four threads each: every thread computes the first layer and a
-// quarter of the second layer's units with their share of the output layer,
-// and the four shares are added in a fixed order.
-constexpr int kClassItems = 256;  // items per block of learned_classes_kernel (4 threads each)
+// Features -> BF16 MLP -> class. A block takes kClassItems (box, neuron)
+// items: one thread each reads the features, and the unstable items (the
+// only ones whose rule depends on the predictor; the others get class -1)
+// are listed. The block's waves then take the listed items in turn: lane o
+// holds hidden unit o's weights of both hidden layers in registers (loaded
+// once per wave), computes unit o of each layer, and passes the layer to
+// the other lanes through the wave's LDS row. The output layer is summed
+// as four quarters of 16 hidden units each, each quarter in ascending unit
+// order (lanes 4c .. 4c + 3 for class c), added as (q0 + q1) + (q2 + q3):
+// every sum in the same order as a neuron taken by four threads, so the
+// class does not depend on the form or on where the item sits in the list.
+constexpr int kClassItems = 256;  // items per block of learned_classes_kernel
+constexpr int kClassWaves = 16;   // waves per block
 
-__global__ void __launch_bounds__(4 * kClassItems) learned_classes_kernel(LearnArgs a) {
-  __shared__ float w[kParams];
+__device__ inline float mlp_param(const float *P, int i) { return i >= kOffW1 ? bf16_round(P[i]) : P[i]; }
+
+__global__ void __launch_bounds__(64 * kClassWaves) learned_classes_kernel(LearnArgs a) {
   __shared__ float fs[kClassItems][kF];
   __shared__ int ulist[kClassItems];  // the block's unstable items (slots), in no fixed order
   __shared__ int ucount;
+  __shared__ float hrow[kClassWaves][kH];  // per wave: the hidden layer passed between lanes
+  __shared__ float w3s[kC * kH];           // the output layer's weights
   if (threadIdx.x == 0) ucount = 0;
-  for (int i = threadIdx.x; i < kParams; i += blockDim.x)
-    w[i] = i >= kOffW1 ? bf16_round(a.params[i]) : a.params[i];
+  for (int i = threadIdx.x; i < kC * kH; i += blockDim.x) w3s[i] = mlp_param(a.params, kOffW3 + i);
   __syncthreads();
   // features of the block's items, one thread each; only unstable neurons
   // (lo < 0 < hi) go through the network
@@ -223,7 +231,8 @@ __global__ void __launch_bounds__(4 * kClassItems) learned_classes_kernel(LearnA
       const NeuronRec &r = a.recs[box * a.h + j];
       float f[kF];
       neuron_features(a, r, j, f);
-      for (int q = 0; q < kF; ++q) fs[slot][q] = f[q];
+      // the network's input: the features normalised and rounded to BF16
+      for (int q = 0; q < kF; ++q) fs[slot][q] = bf16_round((f[q] - a.params[kOffMean + q]) / a.params[kOffStd + q]);
       if (a.feat)
         for (int q = 0; q < kF; ++q) a.feat[(box * a.nh + a.noff + j) * kF + q] = f[q];
       if (r.lo < 0.0 && r.hi > 0.0)
@@ -233,46 +242,48 @@ __global__ void __launch_bounds__(4 * kClassItems) learned_classes_kernel(LearnA
     }
   }
   __syncthreads();
-  // four threads per unstable neuron; each neuron's sums do not depend on
-  // where it sits in the list
-  const int k = threadIdx.x & 3, u = threadIdx.x >> 2;
-  if (u < ucount) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nu = ucount;
+  if (wv >= nu) return;  // a wave without items (no block barrier below)
+  const float *P = a.params;
+  // lane o: unit o's weights; lanes 4c + k (16 lanes): class c over the
+  // quarter k of the second hidden layer
+  float w1[kF], w2[kH];
+  const int o = lane;
+  for (int q = 0; q < kF; ++q) w1[q] = mlp_param(P, kOffW1 + o * kF + q);
+  for (int i = 0; i < kH; ++i) w2[i] = mlp_param(P, kOffW2 + o * kH + i);
+  const float b1 = mlp_param(P, kOffB1 + o), b2 = mlp_param(P, kOffB2 + o);
+  const int oc = (lane >> 2) & (kC - 1), ok = lane & 3;
+  const float *w3 = w3s + oc * kH + ok * (kH / 4);
+  const float b3 = mlp_param(P, kOffB3 + oc);
+  float *hr = hrow[wv];
+  for (int u = wv; u < nu; u += kClassWaves) {
     const int slot = ulist[u];
-    const int64_t it = (int64_t)blockIdx.x * kClassItems + slot;
-    const int64_t box = a.bids ? a.bids[it / a.h] : it / a.h;
-    const int j = (int)(it % a.h);
-    float x[kF], h1[kH], z[kC];
-    for (int q = 0; q < kF; ++q) x[q] = bf16_round((fs[slot][q] - w[kOffMean + q]) / w[kOffStd + q]);
-    for (int o = 0; o < kH; ++o) {
-      float s = w[kOffB1 + o];
-      for (int q = 0; q < kF; ++q) s = fmaf(w[kOffW1 + o * kF + q], x[q], s);
-      h1[o] = bf16_round(fmaxf(s, 0.f));
-    }
-    for (int c = 0; c < kC; ++c) z[c] = k == 0 ? w[kOffB3 + c] : 0.f;
-    // this thread's quarter of the hidden units, four at a time
-    for (int o0 = k * (kH / 4); o0 < (k + 1) * (kH / 4); o0 += 4) {
-      float s[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) s[v] = w[kOffB2 + o0 + v];
-      for (int i = 0; i < kH; ++i)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) s[v] = fmaf(w[kOffW2 + (o0 + v) * kH + i], h1[i], s[v]);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const float hu = bf16_round(fmaxf(s[v], 0.f));
-        for (int c = 0; c < kC; ++c) z[c] = fmaf(w[kOffW3 + c * kH + o0 + v], hu, z[c]);
-      }
-    }
-    // (z0 + z1) + (z2 + z3) over the neuron's four threads
-    for (int c = 0; c < kC; ++c) {
-      z[c] += __shfl_xor(z[c], 1, 64);
-      z[c] += __shfl_xor(z[c], 2, 64);
-    }
-    if (k == 0) {
+    float s1 = b1;
+    for (int q = 0; q < kF; ++q) s1 = fmaf(w1[q], fs[slot][q], s1);
+    const float h1 = bf16_round(fmaxf(s1, 0.f));
+    wave_sync();  // the row's previous readers are done
+    hr[o] = h1;
+    wave_sync();
+    float s2 = b2;
+    for (int i = 0; i < kH; ++i) s2 = fmaf(w2[i], hr[i], s2);
+    const float h2 = bf16_round(fmaxf(s2, 0.f));
+    wave_sync();
+    hr[o] = h2;
+    wave_sync();
+    float z = ok == 0 ? b3 : 0.f;
+    for (int v = 0; v < kH / 4; ++v) z = fmaf(w3[v], hr[ok * (kH / 4) + v], z);
+    z += __shfl_xor(z, 1, 64);  // (q0 + q1) + (q2 + q3) over lanes 4c .. 4c + 3
+    z += __shfl_xor(z, 2, 64);
+    float zc[kC];
+    for (int c = 0; c < kC; ++c) zc[c] = __shfl(z, 4 * c, 64);
+    if (lane == 0) {
       int best = 0;
       for (int c = 1; c < kC; ++c)
-        if (z[c] > z[best]) best = c;
-      a.codes[box * a.nh + a.noff + j] = (int8_t)best;
+        if (zc[c] > zc[best]) best = c;
+      const int64_t it = (int64_t)blockIdx.x * kClassItems + slot;
+      const int64_t box = a.bids ? a.bids[it / a.h] : it / a.h;
+      a.codes[box * a.nh + a.noff + (int)(it % a.h)] = (int8_t)best;
     }
   }
 }
@@ -315,7 +326,7 @@ hipError_t launch_learned_rules(const LearnArgs &a, hipStream_t s) {
   {
     ProfScope ps(kProfPredictor, s, 0.0);
     hipLaunchKernelGGL(learned_classes_kernel, dim3((unsigned)((a.nboxes * a.h + kClassItems - 1) / kClassItems)),
-                       dim3(4 * kClassItems), 0, s, a);
+                       dim3(64 * kClassWaves), 0, s, a);
     RET_IF(hipGetLastError());
   }
   ProfScope ps(kProfPredictor, s, 0.0);
