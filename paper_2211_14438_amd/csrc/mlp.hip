@@ -195,6 +195,43 @@ __global__ void __launch_bounds__(256) features_kernel(LearnArgs a) {
   for (int q = 0; q < kF; ++q) a.feat[(box * a.nh + a.noff + j) * kF + q] = f[q];
 }
 
+// Per box and layer: the layer is stored at the largest degree any of its
+// neurons takes, so classes below that degree cost tightness while saving
+// only composition and affine-map work. With a.raise they are raised: if
+// some unstable neuron takes order >= 2, the others take at least order 2;
+// otherwise, if some takes order 1, the fallback neurons take order 1. Then
+// apply the rules: one wave per box (list position g), its lanes over the
+// neurons.
+__device__ void box_rules(const LearnArgs &a, int64_t g, int lane) {
+  const int64_t box = a.bids ? a.bids[g] : g;
+  int8_t *cl = a.codes + box * a.nh + a.noff;
+  int top = -1;  // class as the degree it gives: fallback (0) lowest
+  for (int j = lane; j < a.h; j += 64) top = max(top, (int)cl[j]);
+  for (int off = 32; off > 0; off >>= 1) top = max(top, __shfl_xor(top, off, 64));
+  int deg = 0;
+  for (int j = lane; j < a.h; j += 64) {
+    NeuronRec &r = a.recs[box * a.h + j];
+    int c = cl[j];
+    if (c >= 0 && a.raise) {
+      if (top >= 2 && c < 2) c = 2;
+      else if (top == 1 && c == 0) c = 1;
+      cl[j] = (int8_t)c;
+    }
+    decide_neuron(r, c < 0 ? 1 : c, false, a.L, a.n, r.dpre, a.cap, a.fp64);
+    if (a.used) a.used[box * a.nh + a.noff + j] = (int8_t)r.kind;
+    deg = max(deg, r.deg);
+  }
+  if (a.degs) {  // the box's largest post degree, for the next layer's classes
+    for (int off = 32; off > 0; off >>= 1) deg = max(deg, __shfl_xor(deg, off, 64));
+    if (lane == 0) a.degs[box] = deg;
+  }
+}
+
+__global__ void __launch_bounds__(256) learned_rules_kernel(LearnArgs a) {
+  const int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (g < a.nboxes) box_rules(a, g, (int)(threadIdx.x & 63));
+}
+
 // Features -> BF16 MLP -> class. A block takes kClassItems (box, neuron)
 // items: one thread each reads the features, and the unstable items (the
 // only ones whose rule depends on the predictor; the others get class -1)
@@ -211,6 +248,56 @@ constexpr int kClassWaves = 16;   // waves per block
 
 __device__ inline float mlp_param(const float *P, int i) { return i >= kOffW1 ? bf16_round(P[i]) : P[i]; }
 
+// The MLP of the listed unstable items u = wv, wv + kClassWaves, ... by one
+// wave (see learned_classes_kernel).
+__device__ void classes_of_wave(const LearnArgs &a, int wv, int nu, int lane, const float *fs, const int *ulist,
+                                float *hr, const float *w3s) {
+  const float *P = a.params;
+  // lane o: unit o's weights; lanes 4c + k (16 lanes): class c over the
+  // quarter k of the second hidden layer
+  float w1[kF], w2[kH];
+  const int o = lane;
+  for (int q = 0; q < kF; ++q) w1[q] = mlp_param(P, kOffW1 + o * kF + q);
+  for (int i = 0; i < kH; ++i) w2[i] = mlp_param(P, kOffW2 + o * kH + i);
+  const float b1 = mlp_param(P, kOffB1 + o), b2 = mlp_param(P, kOffB2 + o);
+  const int oc = (lane >> 2) & (kC - 1), ok = lane & 3;
+  const float *w3 = w3s + oc * kH + ok * (kH / 4);
+  const float b3 = mlp_param(P, kOffB3 + oc);
+  for (int u = wv; u < nu; u += kClassWaves) {
+    const int slot = ulist[u];
+    float s1 = b1;
+    for (int q = 0; q < kF; ++q) s1 = fmaf(w1[q], fs[slot * kF + q], s1);
+    const float h1 = bf16_round(fmaxf(s1, 0.f));
+    wave_sync();  // the row's previous readers are done
+    hr[o] = h1;
+    wave_sync();
+    float s2 = b2;
+    for (int i = 0; i < kH; ++i) s2 = fmaf(w2[i], hr[i], s2);
+    const float h2 = bf16_round(fmaxf(s2, 0.f));
+    wave_sync();
+    hr[o] = h2;
+    wave_sync();
+    float z = ok == 0 ? b3 : 0.f;
+    for (int v = 0; v < kH / 4; ++v) z = fmaf(w3[v], hr[ok * (kH / 4) + v], z);
+    z += __shfl_xor(z, 1, 64);  // (q0 + q1) + (q2 + q3) over lanes 4c .. 4c + 3
+    z += __shfl_xor(z, 2, 64);
+    float zc[kC];
+    for (int c = 0; c < kC; ++c) zc[c] = __shfl(z, 4 * c, 64);
+    if (lane == 0) {
+      int best = 0;
+      for (int c = 1; c < kC; ++c)
+        if (zc[c] > zc[best]) best = c;
+      const int64_t it = (int64_t)blockIdx.x * kClassItems + slot;
+      const int64_t box = a.bids ? a.bids[it / a.h] : it / a.h;
+      a.codes[box * a.nh + a.noff + (int)(it % a.h)] = (int8_t)best;
+    }
+  }
+}
+
+// kRules: the block's items are whole boxes (h divides kClassItems), and
+// once every class is written the block applies their rules (box_rules),
+// one wave per box, in place of learned_rules_kernel.
+template <bool kRules>
 __global__ void __launch_bounds__(64 * kClassWaves) learned_classes_kernel(LearnArgs a) {
   __shared__ float fs[kClassItems][kF];
   __shared__ int ulist[kClassItems];  // the block's unstable items (slots), in no fixed order
@@ -244,89 +331,24 @@ __global__ void __launch_bounds__(64 * kClassWaves) learned_classes_kernel(Learn
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int nu = ucount;
-  if (wv >= nu) return;  // a wave without items (no block barrier below)
-  const float *P = a.params;
-  // lane o: unit o's weights; lanes 4c + k (16 lanes): class c over the
-  // quarter k of the second hidden layer
-  float w1[kF], w2[kH];
-  const int o = lane;
-  for (int q = 0; q < kF; ++q) w1[q] = mlp_param(P, kOffW1 + o * kF + q);
-  for (int i = 0; i < kH; ++i) w2[i] = mlp_param(P, kOffW2 + o * kH + i);
-  const float b1 = mlp_param(P, kOffB1 + o), b2 = mlp_param(P, kOffB2 + o);
-  const int oc = (lane >> 2) & (kC - 1), ok = lane & 3;
-  const float *w3 = w3s + oc * kH + ok * (kH / 4);
-  const float b3 = mlp_param(P, kOffB3 + oc);
-  float *hr = hrow[wv];
-  for (int u = wv; u < nu; u += kClassWaves) {
-    const int slot = ulist[u];
-    float s1 = b1;
-    for (int q = 0; q < kF; ++q) s1 = fmaf(w1[q], fs[slot][q], s1);
-    const float h1 = bf16_round(fmaxf(s1, 0.f));
-    wave_sync();  // the row's previous readers are done
-    hr[o] = h1;
-    wave_sync();
-    float s2 = b2;
-    for (int i = 0; i < kH; ++i) s2 = fmaf(w2[i], hr[i], s2);
-    const float h2 = bf16_round(fmaxf(s2, 0.f));
-    wave_sync();
-    hr[o] = h2;
-    wave_sync();
-    float z = ok == 0 ? b3 : 0.f;
-    for (int v = 0; v < kH / 4; ++v) z = fmaf(w3[v], hr[ok * (kH / 4) + v], z);
-    z += __shfl_xor(z, 1, 64);  // (q0 + q1) + (q2 + q3) over lanes 4c .. 4c + 3
-    z += __shfl_xor(z, 2, 64);
-    float zc[kC];
-    for (int c = 0; c < kC; ++c) zc[c] = __shfl(z, 4 * c, 64);
-    if (lane == 0) {
-      int best = 0;
-      for (int c = 1; c < kC; ++c)
-        if (zc[c] > zc[best]) best = c;
-      const int64_t it = (int64_t)blockIdx.x * kClassItems + slot;
-      const int64_t box = a.bids ? a.bids[it / a.h] : it / a.h;
-      a.codes[box * a.nh + a.noff + (int)(it % a.h)] = (int8_t)best;
-    }
-  }
-}
-
-// Per box and layer: the layer is stored at the largest degree any of its
-// neurons takes, so classes below that degree cost tightness while saving
-// only composition and affine-map work. With a.raise they are raised: if
-// some unstable neuron takes order >= 2, the others take at least order 2;
-// otherwise, if some takes order 1, the fallback neurons take order 1. Then
-// apply the rules: one wave per box, its lanes over the neurons.
-__global__ void __launch_bounds__(256) learned_rules_kernel(LearnArgs a) {
-  const int lane = threadIdx.x & 63;
-  const int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (g >= a.nboxes) return;
-  const int64_t box = a.bids ? a.bids[g] : g;
-  int8_t *cl = a.codes + box * a.nh + a.noff;
-  int top = -1;  // class as the degree it gives: fallback (0) lowest
-  for (int j = lane; j < a.h; j += 64) top = max(top, (int)cl[j]);
-  for (int off = 32; off > 0; off >>= 1) top = max(top, __shfl_xor(top, off, 64));
-  int deg = 0;
-  for (int j = lane; j < a.h; j += 64) {
-    NeuronRec &r = a.recs[box * a.h + j];
-    int c = cl[j];
-    if (c >= 0 && a.raise) {
-      if (top >= 2 && c < 2) c = 2;
-      else if (top == 1 && c == 0) c = 1;
-      cl[j] = (int8_t)c;
-    }
-    decide_neuron(r, c < 0 ? 1 : c, false, a.L, a.n, r.dpre, a.cap, a.fp64);
-    if (a.used) a.used[box * a.nh + a.noff + j] = (int8_t)r.kind;
-    deg = max(deg, r.deg);
-  }
-  if (a.degs) {  // the box's largest post degree, for the next layer's classes
-    for (int off = 32; off > 0; off >>= 1) deg = max(deg, __shfl_xor(deg, off, 64));
-    if (lane == 0) a.degs[box] = deg;
+  if (wv < nu) classes_of_wave(a, wv, nu, lane, &fs[0][0], ulist, hrow[wv], w3s);
+  if constexpr (kRules) {
+    __syncthreads();  // every class of the block's boxes written
+    const int per = kClassItems / a.h;
+    const int64_t g = (int64_t)blockIdx.x * per + wv;
+    if (wv < per && g < a.nboxes) box_rules(a, g, lane);
   }
 }
 
 hipError_t launch_learned_rules(const LearnArgs &a, hipStream_t s) {
   {
     ProfScope ps(kProfPredictor, s, 0.0);
-    hipLaunchKernelGGL(learned_classes_kernel, dim3((unsigned)((a.nboxes * a.h + kClassItems - 1) / kClassItems)),
-                       dim3(64 * kClassWaves), 0, s, a);
+    const dim3 grid((unsigned)((a.nboxes * a.h + kClassItems - 1) / kClassItems)), block(64 * kClassWaves);
+    if (kClassItems % a.h == 0 && kClassItems / a.h <= kClassWaves) {  // whole boxes per block: rules fused
+      hipLaunchKernelGGL(learned_classes_kernel<true>, grid, block, 0, s, a);
+      return hipGetLastError();
+    }
+    hipLaunchKernelGGL(learned_classes_kernel<false>, grid, block, 0, s, a);
     RET_IF(hipGetLastError());
   }
   ProfScope ps(kProfPredictor, s, 0.0);
