@@ -1199,6 +1199,10 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       la.fp64 = p.fp64 ? 1 : 0;
       la.L = p.L;
       la.raise = o->no_raise ? 0 : 1;
+      if (learned && !lin_layer) {  // the rules also write the next affine map's input lists
+        la.live = live;
+        la.live_ld = live_ld;
+      }
       if (learned)
         BERN_HIP_TRY(launch_learned_rules(la, s));
       else
@@ -1338,8 +1342,9 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       }
     }
     // the next affine map's input lists of every box (a linearised layer
-    // builds its own after the linearisation)
-    if (!lin_layer) {
+    // builds its own after the linearisation; a learned plan's rules kernel
+    // has written them)
+    if (!lin_layer && !learned) {
       ComposeArgs ml{};
       ml.h = h;
       ml.nboxes = B;

@@ -432,6 +432,8 @@ struct LearnArgs {
   int *degs;                      // [B] or null: each box's largest post degree (the rules kernel)
   int cap, fp64, L;
   int raise;                      // raise classes below the layer's top class (bern_opts.no_raise == 0)
+  int *live = nullptr;            // or null: the next affine map's input lists, written with the rules
+  int64_t live_ld = 0;            //   (live_kernel's layout, per box stride live_ld)
 };
 // features -> (optional) BF16 MLP -> codes -> rules, for one class of boxes.
 hipError_t launch_learned_rules(const LearnArgs &a, hipStream_t s);

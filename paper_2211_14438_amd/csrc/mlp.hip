@@ -225,6 +225,28 @@ __device__ void box_rules(const LearnArgs &a, int64_t g, int lane) {
     for (int off = 32; off > 0; off >>= 1) deg = max(deg, __shfl_xor(deg, off, 64));
     if (lane == 0) a.degs[box] = deg;
   }
+  if (a.live) {  // the next affine map's input lists (as live_kernel, from the kinds just decided)
+    int *lv = a.live + box * a.live_ld;
+    const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    int nf = 0, ns = 0, na = 0;
+    for (int j0 = 0; j0 < a.h; j0 += 64) {
+      const int j = j0 + lane;
+      const int kind = j < a.h ? a.recs[box * a.h + j].kind : (int)kInactive;
+      const bool full = kind >= 2, small = kind == 1 || kind == kFallback, act = kind == kActive;
+      const unsigned long long bf = __ballot(full), bs = __ballot(small), ba = __ballot(act);
+      if (full) lv[3 + nf + __popcll(bf & below)] = j;
+      if (small) lv[3 + a.h + ns + __popcll(bs & below)] = j;
+      if (act) lv[3 + 2 * a.h + na + __popcll(ba & below)] = j;
+      nf += __popcll(bf);
+      ns += __popcll(bs);
+      na += __popcll(ba);
+    }
+    if (lane == 0) {
+      lv[0] = nf;
+      lv[1] = ns;
+      lv[2] = na;
+    }
+  }
 }
 
 __global__ void __launch_bounds__(256) learned_rules_kernel(LearnArgs a) {
