@@ -1049,9 +1049,11 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
     BERN_HIP_TRY(hipHostMalloc((void **)&net->host_ids, need * sizeof(int), hipHostMallocDefault));
     net->host_n = need;
   }
-  auto upload = [&](std::vector<BoxClass> &cl, int layer, int phase, std::vector<const int *> &devl) -> bern_status {
+  // a phase's lists into the pinned staging, their device addresses into
+  // devl; the ints to copy (0: one class of every box, the identity)
+  auto stage = [&](std::vector<BoxClass> &cl, int layer, int phase, std::vector<const int *> &devl) -> size_t {
     devl.assign(cl.size(), nullptr);
-    if (cl.size() == 1 && (int64_t)cl[0].ids.size() == B) return BERN_OK;  // identity
+    if (cl.size() == 1 && (int64_t)cl[0].ids.size() == B) return 0;  // identity
     int *all = net->host_ids + B + ((int64_t)layer * 2 + phase) * B;
     size_t cnt = 0;
     for (auto &c : cl) {
@@ -1059,12 +1061,20 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       cnt += c.ids.size();
     }
     int *dst = idlists + ((int64_t)layer * 2 + phase) * B;
-    BERN_HIP_TRY(hipMemcpyAsync(dst, all, cnt * sizeof(int), hipMemcpyHostToDevice, s));
     int64_t off = 0;
     for (size_t k = 0; k < cl.size(); ++k) {
       devl[k] = dst + off;
       off += cl[k].ids.size();
     }
+    return cnt;
+  };
+  // both phases of a layer (adjacent slots of B ints) in one copy
+  auto upload2 = [&](size_t c0, size_t c1, int layer) -> bern_status {
+    const int64_t base = ((int64_t)layer * 2) * B;
+    if (c0 == 0 && c1 == 0) return BERN_OK;
+    const int64_t from = c0 > 0 ? base : base + B, count = c1 > 0 ? base + B + (int64_t)c1 - from : (int64_t)c0;
+    BERN_HIP_TRY(hipMemcpyAsync(idlists + from, net->host_ids + B + from, (size_t)count * sizeof(int),
+                                hipMemcpyHostToDevice, s));
     return BERN_OK;
   };
   for (auto &c : classes) {
@@ -1104,7 +1114,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       if (carried.size() == classes.size()) {
         cid = carried;  // the previous layer's composition lists, same classes in the same order
       } else {
-        st = upload(classes, i, 0, cid);
+        st = upload2(stage(classes, i, 0, cid), 0, i);
         if (st != BERN_OK) return st;
       }
       for (size_t k = 0; k < classes.size(); ++k)
@@ -1331,9 +1341,8 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
         }
         for (auto &cl : nc) std::sort(cl.ids.begin(), cl.ids.end());
         std::vector<const int *> pid;
-        st = upload(next, i, 0, pid);
-        if (st != BERN_OK) return st;
-        st = upload(nc, i, 1, gid);
+        const size_t c0 = stage(next, i, 0, pid), c1 = stage(nc, i, 1, gid);
+        st = upload2(c0, c1, i);
         if (st != BERN_OK) return st;
         for (size_t k = 0; k < next.size(); ++k)
           pc.push_back(LaunchClass{next[k].Din, next[k].Dout, pid[k], (int64_t)next[k].ids.size(), nullptr});

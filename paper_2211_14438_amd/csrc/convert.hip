@@ -2467,7 +2467,6 @@ __device__ __forceinline__ void direct_side_pass(const double *c, const double *
   constexpr int D1 = D + 1, P = Q::P, M = Q::M, R = Q::R, NT = Q::tile;
   constexpr int SP = (int)binom_u(P + D, D), SRM = (int)binom_u(R + M + D, D), SM = (int)binom_u(M + D, D);
   using LP = DLayouts<D, P>;
-  using LQ = DLayouts<D, R + M>;
   using J = DJoins<D, N, P>;
   using TP = DTilePoss<D, M>;
   if (tid >= Q::lanes) return;
