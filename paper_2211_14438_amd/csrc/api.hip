@@ -986,6 +986,23 @@ static bern_status lin_layer_run(const bern_net *net, const Plan &p, int i, cons
 // classification kernel (no host round trip); without, the classes that
 // occur, read back once per hidden layer (the box degrees to the host, the
 // id lists to the device).
+// Waits for the work enqueued on s so far by polling an event (one per host
+// thread and device) instead of a blocking stream synchronisation: the host
+// resumes within microseconds of the copy it waits for, which the per-layer
+// degree read-back of host classes pays once per hidden layer.
+static hipError_t spin_wait(hipStream_t s) {
+  static thread_local hipEvent_t ev[64] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipStreamSynchronize(s);
+  if (!ev[dev] && (e = hipEventCreateWithFlags(&ev[dev], hipEventDisableTiming)) != hipSuccess) return e;
+  if ((e = hipEventRecord(ev[dev], s)) != hipSuccess) return e;
+  while ((e = hipEventQuery(ev[dev])) == hipErrorNotReady) {
+  }
+  return e;
+}
+
 static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts *o, int64_t b0, int64_t B,
                             const double *box_lo, const double *box_hi, const int8_t *plan, double *nlo, double *nhi,
                             double *olo, double *ohi, int8_t *used, char *ws, hipStream_t s,
@@ -1323,7 +1340,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       } else {
         int *hd = net->host_ids;
         BERN_HIP_TRY(hipMemcpyAsync(hd, ldeg, B * sizeof(int), hipMemcpyDeviceToHost, s));
-        BERN_HIP_TRY(hipStreamSynchronize(s));
+        BERN_HIP_TRY(spin_wait(s));
         for (int64_t b = 0; b < B; ++b) {
           const int din_b = dcur[b], dout_b = std::max(hd[b], 0);
           size_t k = 0;
