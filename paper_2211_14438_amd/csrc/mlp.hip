@@ -273,14 +273,14 @@ __device__ inline float mlp_param(const float *P, int i) { return i >= kOffW1 ? 
 // The MLP of the listed unstable items u = wv, wv + kClassWaves, ... by one
 // wave (see learned_classes_kernel).
 __device__ void classes_of_wave(const LearnArgs &a, int wv, int nu, int lane, const float *fs, const int *ulist,
-                                float *hr, const float *w3s) {
+                                float *hr, const float *w3s, const float *w1s, const float *w2s) {
   const float *P = a.params;
-  // lane o: unit o's weights; lanes 4c + k (16 lanes): class c over the
-  // quarter k of the second hidden layer
+  // lane o: unit o's weights (from the block's padded rows in LDS); lanes
+  // 4c + k (16 lanes): class c over the quarter k of the second hidden layer
   float w1[kF], w2[kH];
   const int o = lane;
-  for (int q = 0; q < kF; ++q) w1[q] = mlp_param(P, kOffW1 + o * kF + q);
-  for (int i = 0; i < kH; ++i) w2[i] = mlp_param(P, kOffW2 + o * kH + i);
+  for (int q = 0; q < kF; ++q) w1[q] = w1s[o * (kF + 1) + q];
+  for (int i = 0; i < kH; ++i) w2[i] = w2s[o * (kH + 1) + i];
   const float b1 = mlp_param(P, kOffB1 + o), b2 = mlp_param(P, kOffB2 + o);
   const int oc = (lane >> 2) & (kC - 1), ok = lane & 3;
   const float *w3 = w3s + oc * kH + ok * (kH / 4);
@@ -326,8 +326,12 @@ __global__ void __launch_bounds__(64 * kClassWaves) learned_classes_kernel(Learn
   __shared__ int ucount;
   __shared__ float hrow[kClassWaves][kH];  // per wave: the hidden layer passed between lanes
   __shared__ float w3s[kC * kH];           // the output layer's weights
+  __shared__ float w1s[kH * (kF + 1)];     // the hidden layers' weights, rows padded by one
+  __shared__ float w2s[kH * (kH + 1)];     //   (a lane reading its row hits its own bank)
   if (threadIdx.x == 0) ucount = 0;
   for (int i = threadIdx.x; i < kC * kH; i += blockDim.x) w3s[i] = mlp_param(a.params, kOffW3 + i);
+  for (int i = threadIdx.x; i < kH * kF; i += blockDim.x) w1s[(i / kF) * (kF + 1) + i % kF] = mlp_param(a.params, kOffW1 + i);
+  for (int i = threadIdx.x; i < kH * kH; i += blockDim.x) w2s[(i / kH) * (kH + 1) + i % kH] = mlp_param(a.params, kOffW2 + i);
   __syncthreads();
   // features of the block's items, one thread each; only unstable neurons
   // (lo < 0 < hi) go through the network
@@ -338,13 +342,18 @@ __global__ void __launch_bounds__(64 * kClassWaves) learned_classes_kernel(Learn
       const int64_t box = a.bids ? a.bids[it / a.h] : it / a.h;
       const int j = (int)(it % a.h);
       const NeuronRec &r = a.recs[box * a.h + j];
-      float f[kF];
-      neuron_features(a, r, j, f);
-      // the network's input: the features normalised and rounded to BF16
-      for (int q = 0; q < kF; ++q) fs[slot][q] = bf16_round((f[q] - a.params[kOffMean + q]) / a.params[kOffStd + q]);
-      if (a.feat)
-        for (int q = 0; q < kF; ++q) a.feat[(box * a.nh + a.noff + j) * kF + q] = f[q];
-      if (r.lo < 0.0 && r.hi > 0.0)
+      // a stable neuron's record is read no further than its interval (the
+      // first cache line) unless the features are exported
+      const bool unstable = r.lo < 0.0 && r.hi > 0.0;
+      if (unstable || a.feat) {
+        float f[kF];
+        neuron_features(a, r, j, f);
+        // the network's input: the features normalised and rounded to BF16
+        for (int q = 0; q < kF; ++q) fs[slot][q] = bf16_round((f[q] - a.params[kOffMean + q]) / a.params[kOffStd + q]);
+        if (a.feat)
+          for (int q = 0; q < kF; ++q) a.feat[(box * a.nh + a.noff + j) * kF + q] = f[q];
+      }
+      if (unstable)
         ulist[atomicAdd(&ucount, 1)] = slot;
       else
         a.codes[box * a.nh + a.noff + j] = -1;
@@ -353,7 +362,7 @@ __global__ void __launch_bounds__(64 * kClassWaves) learned_classes_kernel(Learn
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int nu = ucount;
-  if (wv < nu) classes_of_wave(a, wv, nu, lane, &fs[0][0], ulist, hrow[wv], w3s);
+  if (wv < nu) classes_of_wave(a, wv, nu, lane, &fs[0][0], ulist, hrow[wv], w3s, w1s, w2s);
   if constexpr (kRules) {
     __syncthreads();  // every class of the block's boxes written
     const int per = kClassItems / a.h;
