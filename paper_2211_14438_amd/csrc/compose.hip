@@ -759,8 +759,13 @@ __global__ void post_radii_kernel(ComposeArgs a, NeuronRec *recs) {
       const double src = l1_pre + eps_pre + fabs(r.lo);
       const double dnu = gamma64(6) * src / w;
       const double N = src / w * (1.0 + gamma64(6)) + 1.0;
-      double t1 = 0.0, t3 = 0.0, pw = 1.0;
-      for (int jj = 1; jj <= kind; ++jj) t1 += fabs(r.c[jj]) * jj * dnu * pow(1.0 + dnu, jj - 1);
+      // (1 + dnu)^(j-1) by repeated products: exact for j <= 2, within an
+      // ulp per further factor after (covered by kPadSafety)
+      double t1 = 0.0, t3 = 0.0, pw = 1.0, gr = 1.0;
+      for (int jj = 1; jj <= kind; ++jj) {
+        t1 += fabs(r.c[jj]) * jj * dnu * gr;
+        gr *= 1.0 + dnu;
+      }
       for (int jj = 0; jj <= kind; ++jj) {
         t3 += fabs(r.c[jj]) * pw;
         pw *= N;
