@@ -451,52 +451,181 @@ __global__ void __launch_bounds__(kBlock) live_kernel(ComposeArgs a) {
   }
 }
 
-// One block per (box, neuron, bound) of order 1 (c1 nu + c0, minus e for the
+// One item (box, neuron, bound) of order 1 (c1 nu + c0, minus e for the
 // lower bound) or the linear fallback (n+1 affine coefficients), each stored
 // at degree Ds = min(Din, Dout) at the start of its post tensor. Active
 // neurons (post = pre, read in place by the next affine map) and inactive
-// ones store nothing. Writes the block's rounding and l1 sums to partial
+// ones store nothing. Writes the wave's rounding and l1 sums to partial
 // slot 0 and zeros to the item's other slots.
 template <typename T>
-__device__ void scatter_item(const ComposeArgs &a, int64_t g, int j, int s) {
-  const int lane = threadIdx.x & 63;
+struct ScatterJob {
+  const T *p;        // pre tensor (order 1)
+  T *out;            // post tensor
+  const double *fb;  // fallback coefficients
+  double a0, w, c1, b0;  // order 1: q_I = c1 (p_I + a0 [I=0]) / w + b0 [I=0]
+  int64_t it;        // item index, for the partials
+  int mode;          // 1 order 1, 2 fallback, 0 nothing
+  int n;             // coefficients stored
+  int lim;           // fallback: last nonzero coefficient
+};
+
+template <typename T>
+__device__ inline ScatterJob<T> scatter_job(const ComposeArgs &a, int64_t g, int j, int s) {
+  ScatterJob<T> J{};
   const int64_t box = wave_box(a, g);
   const NeuronRec &r = a.recs[box * a.h + j];
   const int kind = r.kind;
-  const NuSource ns = nu_of(a, &r, s);
-  const int64_t it = item_of(a, g, j, s);
   const BoxDeg bd = box_deg(a, box);
-  const T *p = in_tensor<T>(a, box, j, s, bd.Cin);
-  T *out = out_tensor<T>(a, box, j, s, bd.Cout);
   // storage degree: Din, or the layer's post degree when that is lower (only
   // fallback and inactive neurons then); a prefix of the total-degree layout
   const int Ds = min(bd.Din, bd.Dout);
-  const int64_t Cs = bd.Cs;
-  double rsum = 0.0, l1sum = 0.0;
-  if (kind == 1 && Ds == bd.Din) {  // these neurons take degree Din <= Dout
-    for (int64_t I = lane; I < bd.Cin; I += 64) {
-      double v = (double)p[I];
-      if (I == 0) v += ns.shift - ns.lo;
-      v = r.c[1] * (v / ns.w);
-      if (I == 0) v += r.c[0] - (s == 1 ? r.e : 0.0);
-      store(out + I, v, rsum, l1sum);
-    }
+  J.it = (box * a.h + j) * a.nbounds + s;
+  J.p = in_tensor<T>(a, box, j, s, bd.Cin);
+  J.out = out_tensor<T>(a, box, j, s, bd.Cout);
+  if (kind == 1) {  // these neurons take degree Din <= Dout
+    const NuSource ns = nu_of(a, &r, s);
+    J.mode = 1;
+    J.n = Ds == bd.Din ? (int)bd.Cin : 0;
+    J.a0 = ns.shift - ns.lo;
+    J.w = ns.w;
+    J.c1 = r.c[1];
+    J.b0 = r.c[0] - (s == 1 ? r.e : 0.0);
   } else if (kind == kFallback) {
     // rank 0: constant; rank 1 + axis: t_axis; the rest zero
-    const double *fb = (s == 0) ? r.fbU : r.fbL;
-    for (int64_t I = lane; I < Cs; I += 64) {
-      if (I <= a.n && (I == 0 || Ds >= 1))
-        store(out + I, fb[I], rsum, l1sum);
+    J.mode = 2;
+    J.n = (int)bd.Cs;
+    J.lim = Ds >= 1 ? a.n : 0;
+    J.fb = (s == 0) ? r.fbU : r.fbL;
+  }
+  return J;
+}
+
+__device__ inline int lane_int(int v, int b) { return __builtin_amdgcn_readlane(v, b); }
+__device__ inline int64_t lane_i64(int64_t v, int b) {
+  const uint32_t lo = (uint32_t)lane_int((int)(uint32_t)v, b);
+  const uint32_t hi = (uint32_t)lane_int((int)(uint32_t)((uint64_t)v >> 32), b);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ inline double lane_f64(double v, int b) { return __longlong_as_double(lane_i64(__double_as_longlong(v), b)); }
+template <class P>
+__device__ inline P *lane_ptr(P *v, int b) { return reinterpret_cast<P *>(lane_i64(reinterpret_cast<int64_t>(v), b)); }
+
+// Lane b's job, read by the whole wave.
+template <typename T>
+__device__ inline ScatterJob<T> job_of_lane(const ScatterJob<T> &J, int b) {
+  ScatterJob<T> K;
+  K.p = lane_ptr(J.p, b);
+  K.out = lane_ptr(J.out, b);
+  K.fb = lane_ptr(J.fb, b);
+  K.a0 = lane_f64(J.a0, b);
+  K.w = lane_f64(J.w, b);
+  K.c1 = lane_f64(J.c1, b);
+  K.b0 = lane_f64(J.b0, b);
+  K.it = lane_i64(J.it, b);
+  K.mode = lane_int(J.mode, b);
+  K.n = lane_int(J.n, b);
+  K.lim = lane_int(J.lim, b);
+  return K;
+}
+
+// The first two pre coefficients of each lane (order 1 with at most 128
+// coefficients), loaded ahead of the job's stores.
+template <typename T>
+__device__ inline void scatter_prefetch(const ScatterJob<T> &J, T &x0, T &x1) {
+  const int lane = threadIdx.x & 63;
+  x0 = x1 = (T)0;
+  if (J.mode != 1 || J.n > 128) return;
+  if (lane < J.n) x0 = J.p[lane];
+  if (lane + 64 < J.n) x1 = J.p[lane + 64];
+}
+
+template <typename T>
+__device__ inline void scatter_run(const ComposeArgs &a, const ScatterJob<T> &J, T x0, T x1) {
+  const int lane = threadIdx.x & 63;
+  double rsum = 0.0, l1sum = 0.0;
+  auto one = [&](int64_t I, T x) {
+    double v = (double)x;
+    if (I == 0) v += J.a0;
+    v = J.c1 * (v / J.w);
+    if (I == 0) v += J.b0;
+    store(J.out + I, v, rsum, l1sum);
+  };
+  if (J.mode == 1 && J.n <= 128) {
+    if (lane < J.n) one(lane, x0);
+    if (lane + 64 < J.n) one(lane + 64, x1);
+  } else if (J.mode == 1) {
+    for (int64_t I = lane; I < J.n; I += 64) one(I, J.p[I]);
+  } else if (J.mode == 2) {
+    for (int64_t I = lane; I < J.n; I += 64) {
+      if (I <= J.lim)
+        store(J.out + I, J.fb[I], rsum, l1sum);
       else
-        out[I] = (T)0;
+        J.out[I] = (T)0;
     }
   }
-  if (a.part) wave_partials(a, it, rsum, l1sum);
+  if (a.part) wave_partials(a, J.it, rsum, l1sum);
+}
+
+template <typename T>
+__device__ void scatter_item(const ComposeArgs &a, int64_t g, int j, int s) {
+  const ScatterJob<T> J = scatter_job<T>(a, g, j, s);
+  T x0, x1;
+  scatter_prefetch(J, x0, x1);
+  scatter_run(a, J, x0, x1);
+}
+
+// Grouped items (a.group > 1, at most 64): lane b builds the job of the
+// slot's item b, all at once; the wave then runs the jobs in item order,
+// loading each job's coefficients before the previous job's stores. The
+// work and sums of every item are those of scatter_item.
+template <typename T>
+__device__ void scatter_grouped(const ComposeArgs &a) {
+  const int64_t per = (int64_t)a.h * a.nbounds, total = launch_items(a);
+  const int grp = a.group;
+  const int64_t slots = (total + grp - 1) / grp;
+  const int64_t stride = (int64_t)gridDim.x * (blockDim.x >> 6);
+  const int lane = threadIdx.x & 63;
+  for (int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < slots; w += stride) {
+    const int64_t i0 = w * grp;
+    ScatterJob<T> mine{};
+    if (lane < grp && i0 + lane < total) {
+      const int64_t it = i0 + lane, g = it / per;
+      const int rest = (int)(it - g * per);
+      mine = scatter_job<T>(a, g, rest / a.nbounds, rest % a.nbounds);
+    }
+    unsigned long long todo = __ballot(mine.mode != 0);
+    if (!todo) continue;
+    int b = __ffsll((long long)todo) - 1;
+    todo &= todo - 1;
+    ScatterJob<T> J = job_of_lane(mine, b);
+    T x0, x1;
+    scatter_prefetch(J, x0, x1);
+    while (true) {
+      const bool more = todo != 0;
+      ScatterJob<T> K{};
+      T y0 = (T)0, y1 = (T)0;
+      if (more) {
+        b = __ffsll((long long)todo) - 1;
+        todo &= todo - 1;
+        K = job_of_lane(mine, b);
+        scatter_prefetch(K, y0, y1);
+      }
+      scatter_run(a, J, x0, x1);
+      if (!more) break;
+      J = K;
+      x0 = y0;
+      x1 = y1;
+    }
+  }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) compose_scatter_kernel(ComposeArgs a) {
   // order-1 and fallback neurons (the partials of the others are not read)
+  if (a.group > 1) {
+    scatter_grouped<T>(a);
+    return;
+  }
   for_wave_items(a, 1, [](int kind, int) { return kind == 1 || kind == kFallback; },
                  [&](int64_t g, int j, int s, int) { scatter_item<T>(a, g, j, s); });
 }
@@ -1002,7 +1131,7 @@ static hipError_t compose_all(const ComposeArgs &a_in, hipStream_t s) {
   if ((a.dcount || a.stage != 0) && (!a.lists_ready || !a.radii_later)) return hipErrorInvalidValue;
   const unsigned gx = (unsigned)a.nbx;
   // many items: a wave takes a group of items and reads their kinds at
-  // once; 64 for the scatter (its items are few and light), 8 for the
+  // once; 16 for the scatter (its items are few and light), 8 for the
   // square (heavier items, which the group's wave takes one after another)
   const int64_t items_all = a.nboxes * a.h * a.nbounds;
   const bool group = items_all >= 65536;
