@@ -782,12 +782,205 @@ __device__ void sq2_pair(const ComposeArgs &a, int64_t g, int j, int bx, double 
   }
 }
 
+// Grouped order-2 neurons, both bounds per wave (a.group > 1, at most 64):
+// lane b finds whether the slot's item b is one (all at once), and the
+// lanes read the square table's ranges of their outputs in the slot's chunk
+// once; the wave then runs the neurons in item order, loading each one's
+// coefficients (at most 128 per bound) and record fields ahead of the
+// previous neuron's products and stores. Every sum is that of sq2_pair, in
+// the same order.
+template <typename T>
+struct Sq2Job {
+  const T *p0, *p1;  // pre tensors of the two bounds
+  T *out0, *out1;    // post tensors
+  int64_t it;        // item of the upper bound (the lower bound's is it + 1)
+  double f;          // lane f < 8: field f of the record (c0, c1, c2, e, lo, hi, epsU, epsL)
+  T x[4];            // the lane's first two coefficients of each bound (Cin <= 128)
+};
+
+template <typename T>
+__device__ inline Sq2Job<T> sq2_job(const ComposeArgs &a, int64_t box, int j) {
+  const int lane = threadIdx.x & 63;
+  Sq2Job<T> J;
+  J.p0 = in_tensor<T>(a, box, j, 0);
+  J.p1 = in_tensor<T>(a, box, j, 1);
+  J.out0 = out_tensor<T>(a, box, j, 0);
+  J.out1 = out_tensor<T>(a, box, j, 1);
+  J.it = (box * a.h + j) * a.nbounds;
+  const NeuronRec &r = a.recs[box * a.h + j];
+  const int fl = lane & 7;
+  const double *fp = fl < 3 ? &r.c[fl] : fl == 3 ? &r.e : fl == 4 ? &r.lo : fl == 5 ? &r.hi : fl == 6 ? &r.epsU : &r.epsL;
+  J.f = *fp;
+  J.x[0] = J.x[1] = J.x[2] = J.x[3] = (T)0;
+  if (a.Cin <= 128) {
+    if (lane < a.Cin) {
+      J.x[0] = J.p0[lane];
+      J.x[2] = J.p1[lane];
+    }
+    if (lane + 64 < a.Cin) {
+      J.x[1] = J.p0[lane + 64];
+      J.x[3] = J.p1[lane + 64];
+    }
+  }
+  return J;
+}
+
+// The square table's range and diagonal of the lane's outputs in a chunk.
+struct Sq2Tab {
+  int off[kBlock / 64], end[kBlock / 64], diag[kBlock / 64];
+};
+
+template <typename T>
+__device__ void sq2_pair_run(const ComposeArgs &a, const Sq2Job<T> &J, int bx, double *nu, const Sq2Tab &tb) {
+  const int lane = threadIdx.x & 63;
+  const double c0 = lane_f64(J.f, 0), c1 = lane_f64(J.f, 1), c2 = lane_f64(J.f, 2), e = lane_f64(J.f, 3);
+  const double lo = lane_f64(J.f, 4), hi = lane_f64(J.f, 5);
+  const double shift0 = a.fp64 ? 0.0 : lane_f64(J.f, 6), shift1 = a.fp64 ? 0.0 : -lane_f64(J.f, 7);
+  const double w = hi - lo;  // nu_s = (p_s + shift_s [I = 0] - lo) / w
+  double *nu0 = nu, *nu1 = nu + a.Cin;
+  wave_sync();  // the previous neuron's reads of nu are done
+  for (int s = 0; s < 2; ++s) {
+    const T *p = s == 0 ? J.p0 : J.p1;
+    const double a0 = (s == 0 ? shift0 : shift1) - lo;
+    double *q = s == 0 ? nu0 : nu1;
+    if (a.Cin <= 128) {
+      for (int u = 0; u < 2; ++u) {
+        const int i = lane + 64 * u;
+        if (i < a.Cin) {
+          double v = (double)J.x[2 * s + u];
+          if (i == 0) v += a0;
+          q[i] = v / w;
+        }
+      }
+    } else {
+      for (int64_t i = lane; i < a.Cin; i += 64) {
+        double v = (double)p[i];
+        if (i == 0) v += a0;
+        q[i] = v / w;
+      }
+    }
+  }
+  wave_sync();
+  double rsum0 = 0.0, l1sum0 = 0.0, rsum1 = 0.0, l1sum1 = 0.0;
+  const int64_t K1 = min((int64_t)(bx + 1) * kBlock, a.Cout);
+#pragma unroll
+  for (int t = 0; t < kBlock / 64; ++t) {
+    const int64_t K = (int64_t)bx * kBlock + lane + 64 * t;
+    if (K >= K1) continue;
+    double v0 = 0.0, v1 = 0.0;
+    if (K < a.Sm[2]) {
+      double acc0 = 0.0, acc1 = 0.0;
+      int q = tb.off[t];
+      const int qe = tb.end[t];
+      for (; q < qe; ++q) {
+        const int2 pr = a.sq_pairs[q];
+        acc0 = fma(nu0[pr.x], nu0[pr.y], acc0);
+        acc1 = fma(nu1[pr.x], nu1[pr.y], acc1);
+      }
+      acc0 = acc0 + acc0;
+      acc1 = acc1 + acc1;
+      const int d = tb.diag[t];
+      if (d >= 0) {
+        acc0 = fma(nu0[d], nu0[d], acc0);
+        acc1 = fma(nu1[d], nu1[d], acc1);
+      }
+      v0 = c2 * acc0;
+      v1 = c2 * acc1;
+      if (K < a.Cin) {
+        v0 = fma(c1, nu0[K], v0);
+        v1 = fma(c1, nu1[K], v1);
+      }
+      if (K == 0) {
+        v0 += c0 - 0.0;
+        v1 += c0 - e;
+      }
+    }
+    store(J.out0 + K, v0, rsum0, l1sum0);
+    store(J.out1 + K, v1, rsum1, l1sum1);
+  }
+  if (a.part) {  // each bound's own slot for the chunk
+    for (int off = 32; off > 0; off >>= 1) {
+      rsum0 += __shfl_xor(rsum0, off, 64);
+      l1sum0 += __shfl_xor(l1sum0, off, 64);
+      rsum1 += __shfl_xor(rsum1, off, 64);
+      l1sum1 += __shfl_xor(l1sum1, off, 64);
+    }
+    for (int s = 0; s < 2; ++s) {
+      const int64_t it = J.it + s;
+      if (lane == 0) {
+        a.part[(it * pslots(a) + bx) * 2 + 0] = s == 0 ? rsum0 : rsum1;
+        a.part[(it * pslots(a) + bx) * 2 + 1] = s == 0 ? l1sum0 : l1sum1;
+      }
+      if (bx == 0)  // the slots past this class's chunks
+        for (int64_t b = a.nbx + lane; b < pslots(a); b += 64)
+          a.part[(it * pslots(a) + b) * 2 + 0] = a.part[(it * pslots(a) + b) * 2 + 1] = 0.0;
+    }
+  }
+}
+
+template <typename T>
+__device__ void sq2_pair_grouped(const ComposeArgs &a, double *nu) {
+  const int64_t per = (int64_t)a.h * a.nbounds, total = launch_items(a);
+  const int grp = a.group, chunks = (int)a.nbx;
+  const int64_t slots = (total + grp - 1) / grp * chunks;
+  const int64_t stride = (int64_t)gridDim.x * (blockDim.x >> 6);
+  const int lane = threadIdx.x & 63;
+  for (int64_t w0 = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w0 < slots; w0 += stride) {
+    const int bx = (int)(w0 % chunks);
+    const int64_t i0 = w0 / chunks * grp;
+    int64_t mbox = 0;
+    int mj = 0;
+    bool mine = false;
+    if (lane < grp && i0 + lane < total) {
+      const int64_t it = i0 + lane, g = it / per;
+      const int rest = (int)(it - g * per);
+      mj = rest / a.nbounds;
+      mbox = wave_box(a, g);
+      mine = rest % a.nbounds == 0 && a.recs[mbox * a.h + mj].kind == 2;
+    }
+    unsigned long long todo = __ballot(mine);
+    if (!todo) continue;
+    Sq2Tab tb;
+    const int64_t K1 = min((int64_t)(bx + 1) * kBlock, a.Cout);
+#pragma unroll
+    for (int t = 0; t < kBlock / 64; ++t) {
+      const int64_t K = (int64_t)bx * kBlock + lane + 64 * t;
+      tb.off[t] = tb.end[t] = 0;
+      tb.diag[t] = -1;
+      if (K < K1 && K < a.Sm[2]) {
+        tb.off[t] = a.sq_off[K];
+        tb.end[t] = a.sq_off[K + 1];
+        tb.diag[t] = a.sq_diag[K];
+      }
+    }
+    int b = __ffsll((long long)todo) - 1;
+    todo &= todo - 1;
+    Sq2Job<T> J = sq2_job<T>(a, lane_i64(mbox, b), lane_int(mj, b));
+    while (true) {
+      const bool more = todo != 0;
+      Sq2Job<T> K;
+      if (more) {
+        b = __ffsll((long long)todo) - 1;
+        todo &= todo - 1;
+        K = sq2_job<T>(a, lane_i64(mbox, b), lane_int(mj, b));
+      }
+      sq2_pair_run(a, J, bx, nu, tb);
+      if (!more) break;
+      J = K;
+    }
+  }
+}
+
 // kPair: both bounds per wave (the items of bound 1 are then skipped).
 template <typename T, bool kPair>
 __global__ void __launch_bounds__(kBlock) compose_sq2_kernel(ComposeArgs a) {
   extern __shared__ double lds_nu[];
   double *nu = lds_nu + (threadIdx.x >> 6) * (kPair ? 2 : 1) * a.Cin;  // the wave's nu
   if constexpr (kPair) {
+    if (a.group > 1) {
+      sq2_pair_grouped<T>(a, nu);
+      return;
+    }
     for_wave_items(a, (int)a.nbx, [](int kind, int s) { return kind == 2 && s == 0; },
                    [&](int64_t g, int j, int, int bx) { sq2_pair<T>(a, g, j, bx, nu); });
   } else {
