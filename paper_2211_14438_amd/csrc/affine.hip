@@ -41,6 +41,12 @@ __global__ void __launch_bounds__(kBlock) layer1_kernel(Layer1Args a) {
     T *out = reinterpret_cast<T *>(a.pre) + box * a.slot + (int64_t)j * 2 * C;
     out[c] = (T)v;
     out[C + c] = (T)v;
+    if (a.flags && c == 0 && j == 0) {  // the box's validity, once per box
+      int bad = 0;
+      for (int k = 0; k < a.n; ++k)
+        if (!(lo[k] <= hi[k]) || !isfinite(lo[k]) || !isfinite(hi[k])) bad = 1;
+      a.flags[box] = bad;
+    }
   }
 }
 

@@ -511,19 +511,8 @@ bern_status bern_workspace_size(const bern_net *net, const bern_opts *opts, int6
 
 }  // extern "C"
 
-// Device-side validity of the boxes of a wave: flag[b] = 1 for a box with
-// d_lo > d_hi or a non-finite coordinate; such boxes get NaN bounds.
-__global__ void box_check_kernel(int n, int64_t nb, const double *lo, const double *hi, int *flag) {
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nb) return;
-  int bad = 0;
-  for (int a = 0; a < n; ++a) {
-    const double l = lo[b * n + a], h = hi[b * n + a];
-    if (!(l <= h) || !std::isfinite(l) || !std::isfinite(h)) bad = 1;
-  }
-  flag[b] = bad;
-}
-
+// Boxes of a wave flagged invalid (flag[b] = 1: d_lo > d_hi or a non-finite
+// coordinate, set by the layer-1 kernel) get NaN bounds.
 __global__ void poison_kernel(int64_t nb, const int *flag, int nh, int o, double *nlo, double *nhi, double *olo,
                               double *ohi) {
   const int64_t b = blockIdx.x;
@@ -1041,13 +1030,6 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
   auto dev_ids = [&](int layer, int64_t k) -> const int * { return idlists + ((layer & 1) * slots + k) * B; };
   auto dev_cnt = [&](int layer, int64_t k) -> int * { return idlists + 2 * slots * B + (layer & 1) * slots + k; };
 
-  {
-    ProfScope ps(kProfMisc, s, 0.0);
-    hipLaunchKernelGGL(box_check_kernel, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, n, B, box_lo, box_hi,
-                       flags);
-  }
-  BERN_HIP_TRY(hipGetLastError());
-
   // host-side degree classes of the current layer's pre-activations
   std::vector<const int *> carried;  // device id lists the next layer's read-off can reuse
   std::vector<BoxClass> classes(1);
@@ -1101,8 +1083,9 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
   bool restart = true;  // every box at pre degree 1 (the first layer, or after a linearisation)
 
   {
+    // with every box's validity flag (the flags the last step reads)
     Layer1Args a{n, net->widths[1], B, nullptr, slotA, box_lo, box_hi, net->W64 + net->woff[0],
-                 net->b64 + net->boff[0], Aa[0], p.fp64 ? 1 : 0};
+                 net->b64 + net->boff[0], Aa[0], p.fp64 ? 1 : 0, flags};
     BERN_HIP_TRY(launch_layer1(a, s));
   }
 

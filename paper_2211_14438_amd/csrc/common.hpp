@@ -223,6 +223,7 @@ struct Layer1Args {
   const double *W, *b;            // W^(1) [h][n], b^(1) [h], FP64
   void *pre;                      // [B][h][2][n+1] (total-degree layout at degree 1)
   int fp64;
+  int *flags = nullptr;           // [B] when set: 1 for a box with lo > hi or a non-finite end, else 0
 };
 hipError_t launch_layer1(const Layer1Args &a, hipStream_t s);
 
