@@ -1082,13 +1082,6 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
   }
   bool restart = true;  // every box at pre degree 1 (the first layer, or after a linearisation)
 
-  {
-    // with every box's validity flag (the flags the last step reads)
-    Layer1Args a{n, net->widths[1], B, nullptr, slotA, box_lo, box_hi, net->W64 + net->woff[0],
-                 net->b64 + net->boff[0], Aa[0], p.fp64 ? 1 : 0, flags};
-    BERN_HIP_TRY(launch_layer1(a, s));
-  }
-
   for (int i = 0; i < p.H; ++i) {
     const int hin = net->widths[i], h = net->widths[i + 1];
     const bool last = (i == p.H - 1);
@@ -1121,6 +1114,16 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
         rc.push_back(LaunchClass{classes[k].Din, 0, cid[k], (int64_t)classes[k].ids.size(), nullptr});
     }
     carried.clear();
+    // The first layer's pre tensors: formed by its read-off when that is one
+    // degree-1 class of every box, else by the layer-1 kernel first; either
+    // sets every box's validity flag (read by the last step).
+    const bool from_box = i == 0 && rc.size() == 1 && rc[0].Din == 1 && !rc[0].bids && !rc[0].dcount &&
+                          rc[0].nboxes == B;
+    if (i == 0 && !from_box) {
+      Layer1Args a{n, net->widths[1], B, nullptr, slotA, box_lo, box_hi, net->W64 + net->woff[0],
+                   net->b64 + net->boff[0], Aa[0], p.fp64 ? 1 : 0, flags};
+      BERN_HIP_TRY(launch_layer1(a, s));
+    }
     // bounds read-off (+ rules and approximants for hidden layers), per class
     for (const LaunchClass &cl : rc) {
       ConvertArgs c{};
@@ -1162,6 +1165,8 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       c.b = net->b64 + net->boff[i];
       c.box_lo = box_lo;
       c.box_hi = box_hi;
+      c.from_box = from_box ? 1 : 0;
+      c.flags = from_box ? flags : nullptr;
       c.rpart = gpart;
       c.rpart_slot = (int64_t)(p.gpart / sizeof(double));
       c.cblocks = gemm_cblocks(c.S);

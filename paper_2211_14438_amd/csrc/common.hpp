@@ -282,6 +282,9 @@ struct ConvertArgs {
   const double *prad;             // [B][hin][4] their padU, padL, pl1U, pl1L (FP32 mode, layer > 0)
   const double *W, *b;            // this layer's W [h][hin] and b [h] (FP64)
   const double *box_lo, *box_hi;  // [B][n] (layer 0)
+  int from_box;                   // layer 0 at degree 1, every box (bids null): the read-off forms
+                                  // the pre tensors from the box, W and b itself and stores them
+  int *flags;                     // with from_box, optional: [B] 1 for an invalid box, else 0
   const double *rpart;            // GEMM rounding partials, per wave box (stride rpart_slot):
   int64_t rpart_slot;             //   [h][2][cblocks] (layer > 0)
   int64_t cblocks;

@@ -1070,7 +1070,10 @@ __global__ void __launch_bounds__(1024) convert_block_t(ConvertArgs a) {
 // beta_a = a_{1+a} and beta_0 = a_0 + sum_a a_{1+a} / 2 (the closed form of
 // the fit below at degree 1); and its remainders, the same constant
 // a_0 - beta_0 + sum_a beta_a / 2 at every corner (zero up to rounding). A
-// team of lanes per neuron, several neurons per wave.
+// team of lanes per neuron, several neurons per wave. For the first layer
+// over every box (from_box) the kernel also forms the coefficients from the
+// box, W and b (the layer-1 kernel's arithmetic) and stores them, so the
+// first layer takes one launch.
 // kL lanes per neuron (8 when the n + 1 coefficients fit, else 16), each
 // holding coefficients l, l + kL, ...
 template <int kL>
@@ -1093,13 +1096,47 @@ __global__ void __launch_bounds__(kBlock) convert_affine_kernel(ConvertArgs a) {
   const T *p = reinterpret_cast<const T *>(a.pre) + box * a.slot + (int64_t)j * 2 * a.S;
   // the lane's coefficients: indices l + r kL (n + 1 <= 17)
   double u[kR], w[kR];
+  if (a.from_box) {
+    // the first layer's pre-activation in closed form (upper = lower): with
+    // x_a = d_lo_a + (d_hi_a - d_lo_a) t_a, the constant b_j + W_j d_lo and
+    // the coefficient W_ja (d_hi_a - d_lo_a) of t_a; stored, and read off
+    // as stored
+    const double *lo = a.box_lo + box * a.n, *hi = a.box_hi + box * a.n;
+    const double *wj = a.W + (int64_t)j * a.n;
+    T *pw = reinterpret_cast<T *>(const_cast<void *>(a.pre)) + box * a.slot + (int64_t)j * 2 * a.S;
 #pragma unroll
-  for (int r = 0; r < kR; ++r) {
-    u[r] = w[r] = 0.0;
-    const int i = l + r * kAffLanes;
-    if (i < S) {
-      u[r] = (double)p[i];
-      w[r] = (double)p[S + i];
+    for (int r = 0; r < kR; ++r) {
+      u[r] = w[r] = 0.0;
+      const int i = l + r * kAffLanes;
+      if (i < S) {
+        double v;
+        if (i == 0) {
+          v = a.b[j];
+          for (int k = 0; k < a.n; ++k) v = fma(wj[k], lo[k], v);
+        } else {
+          v = wj[i - 1] * (hi[i - 1] - lo[i - 1]);
+        }
+        const T sv = (T)v;
+        pw[i] = sv;
+        pw[S + i] = sv;
+        u[r] = w[r] = (double)sv;
+      }
+    }
+    if (a.flags && j == 0 && l == 0) {  // the box's validity, once per box
+      int bad = 0;
+      for (int k = 0; k < a.n; ++k)
+        if (!(lo[k] <= hi[k]) || !isfinite(lo[k]) || !isfinite(hi[k])) bad = 1;
+      a.flags[box] = bad;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+      u[r] = w[r] = 0.0;
+      const int i = l + r * kAffLanes;
+      if (i < S) {
+        u[r] = (double)p[i];
+        w[r] = (double)p[S + i];
+      }
     }
   }
   if (a.mode == 2) {
@@ -1122,7 +1159,32 @@ __global__ void __launch_bounds__(kBlock) convert_affine_kernel(ConvertArgs a) {
   }
   double epsU = 0.0, epsL = 0.0;
   if (!a.fp64) {
-    if (a.layer == 0) {
+    if (a.layer == 0 && a.from_box) {
+      // pre_radii's layer-0 radius on the stored values in the team's
+      // registers (coefficient i on team lane i mod kL, slot i / kL), its
+      // sums in the same order
+      const int base = (int)(threadIdx.x & 63) & ~(kAffLanes - 1);
+      auto stored = [&](int i) {
+        double v = 0.0;
+#pragma unroll
+        for (int r = 0; r < kR; ++r)
+          if (r == i / kAffLanes) v = u[r];
+        return __shfl(v, base + i % kAffLanes, 64);
+      };
+      const double *lo = a.box_lo + box * a.n, *hi = a.box_hi + box * a.n;
+      const double *wj = a.W + (int64_t)j * a.n;
+      double a0 = a.b[j], sabs = fabs(a.b[j]);
+      for (int k = 0; k < a.n; ++k) {
+        a0 = fma(wj[k], lo[k], a0);
+        sabs += fabs(wj[k]) * (fabs(lo[k]) + fabs(hi[k] - lo[k]));
+      }
+      double rr = fabs(stored(0) - a0);
+      for (int k = 0; k < a.n; ++k) {
+        const double ak = wj[k] * (hi[k] - lo[k]);
+        rr += fabs(stored(1 + k) - ak);  // coefficient of t_k
+      }
+      epsU = epsL = (rr + gamma64(a.n + 4) * sabs) * kPadSafety;
+    } else if (a.layer == 0) {
       pre_radii(a, box, j, a.pre, 0, 1, [](double v) { return v; }, epsU, epsL);
     } else {
       double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // sU, sL, g, rU, rL
@@ -1267,11 +1329,13 @@ static double readoff_box_bytes(const ConvertArgs &a) { return (!a.fp64 && a.lay
 
 // Closed-form degree-1 read-off, per neuron: six sums over the n + 1
 // coefficients of both tensors with their min / max / abs (about ten
-// operations per coefficient), and in FP32 mode after the first layer the
-// radii's sums over the previous layer's neurons and the GEMM partials.
+// operations per coefficient), in FP32 mode after the first layer the
+// radii's sums over the previous layer's neurons and the GEMM partials, and
+// for the first layer formed from the box its coefficients.
 static double affine_ops(const ConvertArgs &a) {
   double f = 10.0 * (a.n + 1);
   if (!a.fp64 && a.layer > 0) f += 5.0 * a.hin + 2.0 * a.cblocks;
+  if (a.from_box) f += 4.0 * a.n;  // the coefficients formed from the box
   return f;
 }
 
