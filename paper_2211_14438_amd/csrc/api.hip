@@ -211,6 +211,7 @@ struct bern_net {
   // pinned host staging of the per-layer box classes (box degrees in, box id
   // lists out), so those copies run asynchronously
   mutable int *host_ids = nullptr;
+  mutable int *host_dev = nullptr;  // host_ids as kernels address it (mapped, coherent)
   mutable size_t host_n = 0;
 };
 
@@ -530,14 +531,17 @@ __global__ void poison_kernel(int64_t nb, const int *flag, int nh, int o, double
 
 // Largest per-neuron post degree of every box of the wave: one wave per box,
 // its lanes over the neurons.
-__global__ void box_degree_kernel(int64_t nb, int h, const NeuronRec *recs, int *deg) {
+__global__ void box_degree_kernel(int64_t nb, int h, const NeuronRec *recs, int *deg, int *hdeg) {
   const int64_t b = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (b >= nb) return;
   const int lane = threadIdx.x & 63;
   int d = 0;
   for (int j = lane; j < h; j += 64) d = max(d, recs[b * h + j].deg);
   for (int off = 32; off > 0; off >>= 1) d = max(d, __shfl_xor(d, off, 64));
-  if (lane == 0) deg[b] = d;
+  if (lane == 0) {
+    deg[b] = d;
+    if (hdeg) hdeg[b] = d;  // the host's copy (mapped host memory)
+  }
 }
 
 // Counters (bern_opts.counters): cleared by one block, then per hidden layer
@@ -1043,10 +1047,14 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
   if (!plain && !dev && net->host_n < need) {
     BERN_HIP_TRY(hipStreamSynchronize(s));
     if (net->host_ids) (void)hipHostFree(net->host_ids);
-    net->host_ids = nullptr;
+    net->host_ids = net->host_dev = nullptr;
     net->host_n = 0;
-    BERN_HIP_TRY(hipHostMalloc((void **)&net->host_ids, need * sizeof(int), hipHostMallocDefault));
+    // mapped and coherent: the kernels that find the box degrees store them
+    // here as well, so the host reads them with no copy
+    BERN_HIP_TRY(hipHostMalloc((void **)&net->host_ids, need * sizeof(int),
+                               hipHostMallocMapped | hipHostMallocCoherent));
     net->host_n = need;
+    BERN_HIP_TRY(hipHostGetDevicePointer((void **)&net->host_dev, net->host_ids, 0));
   }
   // a phase's lists into the pinned staging, their device addresses into
   // devl; the ints to copy (0: one class of every box, the identity)
@@ -1210,6 +1218,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       la.codes = codes;
       la.used = used;
       la.degs = learned ? ldeg : nullptr;  // the rules kernel also gives each box's post degree
+      la.hdegs = learned && !plain && !dev ? net->host_dev : nullptr;  // and the host's copy
       la.cap = cap;
       la.fp64 = p.fp64 ? 1 : 0;
       la.L = p.L;
@@ -1300,7 +1309,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       if (!learned) {  // (the learned rules kernel wrote them)
         ProfScope ps(kProfMisc, s, 0.0);
         hipLaunchKernelGGL(box_degree_kernel, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, s, B, h,
-                           (const NeuronRec *)recs, ldeg);
+                           (const NeuronRec *)recs, ldeg, dev ? nullptr : net->host_dev);
       }
       BERN_HIP_TRY(hipGetLastError());
       if (dev) {
@@ -1326,8 +1335,8 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
         for (int m = 0; m < t.nvals; ++m)
           gc.push_back(LaunchClass{0, dv[m], dev_ids(i, t.npairs + m), B, dev_cnt(i, t.npairs + m)});
       } else {
-        int *hd = net->host_ids;
-        BERN_HIP_TRY(hipMemcpyAsync(hd, ldeg, B * sizeof(int), hipMemcpyDeviceToHost, s));
+        // the degrees' host copy, stored by the kernel that found them
+        const int *hd = net->host_ids;
         BERN_HIP_TRY(spin_wait(s));
         for (int64_t b = 0; b < B; ++b) {
           const int din_b = dcur[b], dout_b = std::max(hd[b], 0);

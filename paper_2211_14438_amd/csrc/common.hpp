@@ -434,6 +434,7 @@ struct LearnArgs {
   int8_t *codes;                  // [B][nh] predicted codes (column block noff)
   int8_t *used;                   // [B][nh] or null
   int *degs;                      // [B] or null: each box's largest post degree (the rules kernel)
+  int *hdegs = nullptr;           // [B] or null: the same, into mapped host memory
   int cap, fp64, L;
   int raise;                      // raise classes below the layer's top class (bern_opts.no_raise == 0)
   int *live = nullptr;            // or null: the next affine map's input lists, written with the rules

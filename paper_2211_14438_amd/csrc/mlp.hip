@@ -223,7 +223,10 @@ __device__ void box_rules(const LearnArgs &a, int64_t g, int lane) {
   }
   if (a.degs) {  // the box's largest post degree, for the next layer's classes
     for (int off = 32; off > 0; off >>= 1) deg = max(deg, __shfl_xor(deg, off, 64));
-    if (lane == 0) a.degs[box] = deg;
+    if (lane == 0) {
+      a.degs[box] = deg;
+      if (a.hdegs) a.hdegs[box] = deg;  // the host's copy (mapped host memory)
+    }
   }
   if (a.live) {  // the next affine map's input lists (as live_kernel, from the kinds just decided)
     int *lv = a.live + box * a.live_ld;
