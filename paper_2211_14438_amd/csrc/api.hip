@@ -767,10 +767,13 @@ static bern_status compose_args(const bern_net *net, const Plan &p, int i, const
 // degrees din / dout, or at the uniform uDin / uDout where those are null),
 // the products of every (Din, Dout) class that can hold an order >= 2 (its
 // own square and Horner tables), then the post radii of every box (FP32).
-static bern_status compose_layer(const bern_net *net, const Plan &p, int i, const std::vector<LaunchClass> &pairs,
-                                 int uDin, int uDout, const int *din, const int *dout, int64_t B, void *pre,
-                                 void *post, int64_t slotA, int64_t slotB, NeuronRec *recs, double *rad,
-                                 double *cpart, void *horner, int *live, int64_t live_ld, hipStream_t s) {
+// The composition's first stage over every box (order-1 and fallback
+// neurons, each box at its own degrees din / dout): it needs no host
+// classes, so a host-class run enqueues it before waiting for them.
+static bern_status compose_scatter_stage(const bern_net *net, const Plan &p, int i, int uDin, int uDout,
+                                         const int *din, const int *dout, int64_t B, void *pre, void *post,
+                                         int64_t slotA, int64_t slotB, NeuronRec *recs, double *rad, double *cpart,
+                                         int *live, int64_t live_ld, hipStream_t s) {
   const int n = net->n, h = net->widths[i + 1];
   ComposeArgs m{};
   m.n = n;
@@ -802,6 +805,22 @@ static bern_status compose_layer(const bern_net *net, const Plan &p, int i, cons
   m.lists_ready = 1;
   m.radii_later = 1;
   BERN_HIP_TRY(launch_compose(m, s));
+  return BERN_OK;
+}
+
+// A hidden layer's composition: the first stage (unless already enqueued),
+// the products per (Din, Dout) class, then the post radii.
+static bern_status compose_layer(const bern_net *net, const Plan &p, int i, const std::vector<LaunchClass> &pairs,
+                                 int uDin, int uDout, const int *din, const int *dout, int64_t B, void *pre,
+                                 void *post, int64_t slotA, int64_t slotB, NeuronRec *recs, double *rad,
+                                 double *cpart, void *horner, int *live, int64_t live_ld, bool stage1,
+                                 hipStream_t s) {
+  const int n = net->n, h = net->widths[i + 1];
+  if (stage1) {
+    const bern_status st = compose_scatter_stage(net, p, i, uDin, uDout, din, dout, B, pre, post, slotA, slotB,
+                                                 recs, rad, cpart, live, live_ld, s);
+    if (st != BERN_OK) return st;
+  }
   for (const LaunchClass &cl : pairs) {
     if (class_order(p, cl.Din, cl.Dout) < 2) continue;  // no neuron of the class has a product
     ComposeArgs mp;
@@ -983,15 +1002,25 @@ static bern_status lin_layer_run(const bern_net *net, const Plan &p, int i, cons
 // thread and device) instead of a blocking stream synchronisation: the host
 // resumes within microseconds of the copy it waits for, which the per-layer
 // degree read-back of host classes pays once per hidden layer.
-static hipError_t spin_wait(hipStream_t s) {
+// A wait for the work enqueued on a stream up to a mark, by polling an event
+// of the calling thread's on the current device: spin_mark records it (work
+// enqueued after the mark is not waited for), spin_poll waits for it.
+static hipEvent_t *spin_event() {
   static thread_local hipEvent_t ev[64] = {};
   int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  if (dev < 0 || dev >= 64) return hipStreamSynchronize(s);
-  if (!ev[dev] && (e = hipEventCreateWithFlags(&ev[dev], hipEventDisableTiming)) != hipSuccess) return e;
-  if ((e = hipEventRecord(ev[dev], s)) != hipSuccess) return e;
-  while ((e = hipEventQuery(ev[dev])) == hipErrorNotReady) {
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  if (!ev[dev] && hipEventCreateWithFlags(&ev[dev], hipEventDisableTiming) != hipSuccess) return nullptr;
+  return &ev[dev];
+}
+static hipError_t spin_mark(hipStream_t s) {
+  hipEvent_t *ev = spin_event();
+  return ev ? hipEventRecord(*ev, s) : hipErrorInvalidResourceHandle;
+}
+static hipError_t spin_poll() {
+  hipEvent_t *ev = spin_event();
+  if (!ev) return hipErrorInvalidResourceHandle;
+  hipError_t e;
+  while ((e = hipEventQuery(*ev)) == hipErrorNotReady) {
   }
   return e;
 }
@@ -1294,6 +1323,10 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
     const int uDout = plain ? p.L * uDin : 0;
     const int *din = (plain || restart) ? nullptr : degs + ((i + 1) & 1) * B;
     const int *dout = plain ? nullptr : ldeg;
+    // a learned plan's host classes: the composition's first stage goes
+    // ahead of the wait for them (its inputs are on the device: the degrees
+    // and, from the rules kernel, the lists)
+    const bool early_scatter = learned && !plain && !dev;
     // (Din, Dout) classes for the products; post degree classes for the
     // affine map and the next layer's read-off
     std::vector<BoxClass> next, nc;  // host classes
@@ -1335,9 +1368,16 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
         for (int m = 0; m < t.nvals; ++m)
           gc.push_back(LaunchClass{0, dv[m], dev_ids(i, t.npairs + m), B, dev_cnt(i, t.npairs + m)});
       } else {
-        // the degrees' host copy, stored by the kernel that found them
+        // the degrees' host copy, stored by the kernel that found them; the
+        // composition's first stage runs while the host waits for them
         const int *hd = net->host_ids;
-        BERN_HIP_TRY(spin_wait(s));
+        BERN_HIP_TRY(spin_mark(s));
+        if (early_scatter) {
+          st = compose_scatter_stage(net, p, i, uDin, uDout, din, dout, B, Aa[i & 1], Bp, slotA, slotB, recs,
+                                     radbuf[i & 1], cpart, live, live_ld, s);
+          if (st != BERN_OK) return st;
+        }
+        BERN_HIP_TRY(spin_poll());
         for (int64_t b = 0; b < B; ++b) {
           const int din_b = dcur[b], dout_b = std::max(hd[b], 0);
           size_t k = 0;
@@ -1377,7 +1417,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       BERN_HIP_TRY(launch_live(ml, s));
     }
     st = compose_layer(net, p, i, pc, uDin, uDout, din, dout, B, Aa[i & 1], Bp, slotA, slotB, recs, radbuf[i & 1],
-                       cpart, horner, live, live_ld, s);
+                       cpart, horner, live, live_ld, !early_scatter, s);
     if (st != BERN_OK) return st;
     if (lin_layer) {
       st = lin_layer_run(net, p, i, gc, uDin, uDout, din, dout, B, Aa, Bp, slotA, slotB, recs, radbuf[i & 1], live,
