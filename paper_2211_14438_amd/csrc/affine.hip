@@ -219,8 +219,9 @@ __global__ void __launch_bounds__(kBlock) gemm_kernel(GemmArgs a) {
 // above, but G = 64 / C boxes share a wave (lanes g C .. g C + C - 1 hold box
 // g of the block's G), and the block's four waves take one quarter of the
 // inputs each, their sums added in wave order at the end. The inputs run
-// densely over k with a kind per (box, input) staged in LDS from the live
-// lists (0 none, 1 full, 2 degree-preserving prefix, 3 active in place), so
+// densely over k with a kind per (box, input) staged in LDS from the kind
+// bytes of the live lists (0 none, 1 full, 2 degree-preserving prefix, 3
+// active in place), so
 // k and the weights stay uniform across the wave; an input a lane's box does
 // not use reads an in-bounds element and contributes an exact zero. The
 // per-lane order of the sums depends neither on MB nor on the box's place in
@@ -257,18 +258,18 @@ __global__ void __launch_bounds__(kPackWaves * 64) gemm_pack_kernel(GemmArgs a) 
   double *wl = pk_lds;
   double *part = wl + (size_t)hin * MB;
   unsigned char *kind = reinterpret_cast<unsigned char *>(part + (size_t)(kPackWaves - 1) * 2 * MB * 64);
-  for (int i = threadIdx.x; i < G * hin; i += blockDim.x) kind[i] = 0;
   // weights through LDS: one uniform read per row instead of scalar loads
-  // whose latency each step would wait for
+  // whose latency each step would wait for; the block's boxes' input kinds
+  // from the kind bytes of their lists, both behind one barrier
   for (int i = threadIdx.x; i < hin * MB; i += blockDim.x) wl[i] = a.WT[(int64_t)(i / MB) * a.hp + m0 + i % MB];
-  __syncthreads();
-  for (int gg = 0; gg < G && slot0 + gg < nb; ++gg) {
-    const int64_t bx = a.bids ? a.bids[slot0 + gg] : slot0 + gg;
-    const int *lv = a.live + bx * a.live_ld;
-    for (int t = 0; t < 3; ++t) {
-      const int cnt = lv[t];
-      for (int i = threadIdx.x; i < cnt; i += blockDim.x) kind[gg * hin + lv[3 + t * hin + i]] = (unsigned char)(t + 1);
+  for (int t = threadIdx.x; t < G * hin; t += blockDim.x) {
+    const int gg = t / hin;
+    unsigned char kk = 0;
+    if (slot0 + gg < nb) {
+      const int64_t bx = a.bids ? a.bids[slot0 + gg] : slot0 + gg;
+      kk = live_kinds(a.live + bx * a.live_ld, hin)[t - gg * hin];
     }
+    kind[t] = kk;
   }
   __syncthreads();
   const int64_t box = a.bids ? a.bids[valid ? bslot : slot0] : (valid ? bslot : slot0);

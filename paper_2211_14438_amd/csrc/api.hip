@@ -321,7 +321,7 @@ static bern_status plan_net(const bern_net *net, const bern_opts *o, Plan &p) {
   p.dev_ok = p.mode != BERN_PLAN_PLAIN && dev_classes(p, p.dc);
   if (p.dev_ok) p.list_ints = std::max(p.list_ints, 4 * (size_t)p.dc.slots);
   p.flags = align256(sizeof(int) * (3 + p.list_ints) + (size_t)net->nh);
-  p.live = align256(sizeof(int) * (3 + 3 * (size_t)net->hmax));
+  p.live = align256(sizeof(int) * (3 + 3 * (size_t)net->hmax) + (size_t)net->hmax);  // lists, then kind bytes
   p.rad = align256(sizeof(double) * 4 * (size_t)net->hmax);
   p.oeps = align256(sizeof(double) * 2 * (size_t)net->o);
   if (o->mem_budget_bytes > 0 && p.per_box() > o->mem_budget_bytes) {

@@ -91,6 +91,17 @@ __host__ __device__ inline int64_t stored_count(int n, int d) {
 // A box's degree from a per-box degree array (negative values count as 0).
 __device__ inline int box_degree(const int *deg, int64_t box) { return max(deg[box], 0); }
 
+// A box's input lists of an affine map (lv: counts of full, prefix and
+// active inputs, then the three lists of h entries each) end with one kind
+// byte per input neuron: 0 none, 1 full tensor, 2 degree-Din prefix, 3
+// active (read in place).
+__host__ __device__ inline unsigned char *live_kinds(int *lv, int h) {
+  return reinterpret_cast<unsigned char *>(lv + 3 + 3 * h);
+}
+__host__ __device__ inline const unsigned char *live_kinds(const int *lv, int h) {
+  return reinterpret_cast<const unsigned char *>(lv + 3 + 3 * h);
+}
+
 // C(n + d, n) for d < kCountTable, carried by launches with per-box degrees
 // (a table lookup instead of the divisions of stored_count on the device).
 constexpr int kCountTable = 65;

@@ -440,6 +440,7 @@ __global__ void __launch_bounds__(kBlock) live_kernel(ComposeArgs a) {
     if (full) lv[3 + nf + __popcll(bf & below)] = j;
     if (small) lv[3 + a.h + ns + __popcll(bs & below)] = j;
     if (act) lv[3 + 2 * a.h + na + __popcll(ba & below)] = j;
+    if (j < a.h) live_kinds(lv, a.h)[j] = (unsigned char)(full ? 1 : small ? 2 : act ? 3 : 0);
     nf += __popcll(bf);
     ns += __popcll(bs);
     na += __popcll(ba);

@@ -240,6 +240,7 @@ __device__ void box_rules(const LearnArgs &a, int64_t g, int lane) {
       if (full) lv[3 + nf + __popcll(bf & below)] = j;
       if (small) lv[3 + a.h + ns + __popcll(bs & below)] = j;
       if (act) lv[3 + 2 * a.h + na + __popcll(ba & below)] = j;
+      if (j < a.h) live_kinds(lv, a.h)[j] = (unsigned char)(full ? 1 : small ? 2 : act ? 3 : 0);
       nf += __popcll(bf);
       ns += __popcll(bs);
       na += __popcll(ba);
