@@ -343,16 +343,23 @@ def main():
         return kw
 
     def autotune(kw):
-        # one-time setup, outside the timed region: kernel variants for this net and workload
+        # one-time setup, outside the timed region: kernel variants for this net and workload,
+        # each timed over about 10 ms of passes (2 to 16) so that short passes are not picked on noise
         tkw = {k: v for k, v in kw.items() if k not in ("graph",)}
         t0 = time.perf_counter()
+        B.bounds(net, lo, hi, **tkw)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        B.bounds(net, lo, hi, **tkw)
+        torch.cuda.synchronize()
+        reps = int(min(16, max(2, round(0.010 / max(time.perf_counter() - t1, 1e-6)))))
         if args.tune_cache:
             from paper_2211_14438_amd import tune_cache as TC
             arch = torch.cuda.get_device_properties(0).gcnArchName
-            choice, tms, cached = TC.tuned(net, case.widths, lo, hi, args.tune_cache, arch, reps=2, **tkw)
-            return dict(choice=choice, seconds=time.perf_counter() - t0, ms_per_pass=tms, cached=cached)
-        choice, tms = B.autotune(net, lo, hi, reps=2, **tkw)
-        return dict(choice=choice, seconds=time.perf_counter() - t0, ms_per_pass=tms)
+            choice, tms, cached = TC.tuned(net, case.widths, lo, hi, args.tune_cache, arch, reps=reps, **tkw)
+            return dict(choice=choice, seconds=time.perf_counter() - t0, ms_per_pass=tms, cached=cached, reps=reps)
+        choice, tms = B.autotune(net, lo, hi, reps=reps, **tkw)
+        return dict(choice=choice, seconds=time.perf_counter() - t0, ms_per_pass=tms, reps=reps)
 
     def timed(kw, steps, profile):
         for _ in range(args.warmup):
