@@ -271,6 +271,7 @@ __global__ void __launch_bounds__(256) learned_rules_kernel(LearnArgs a) {
 // class does not depend on the form or on where the item sits in the list.
 constexpr int kClassItems = 256;  // items per block of learned_classes_kernel
 constexpr int kClassWaves = 16;   // waves per block
+static_assert(kClassItems < 64 * kClassWaves, "threads past the items stage the weights");
 
 __device__ inline float mlp_param(const float *P, int i) { return i >= kOffW1 ? bf16_round(P[i]) : P[i]; }
 
@@ -333,10 +334,15 @@ __global__ void __launch_bounds__(64 * kClassWaves) learned_classes_kernel(Learn
   __shared__ float w1s[kH * (kF + 1)];     // the hidden layers' weights, rows padded by one
   __shared__ float w2s[kH * (kH + 1)];     //   (a lane reading its row hits its own bank)
   if (threadIdx.x == 0) ucount = 0;
-  for (int i = threadIdx.x; i < kC * kH; i += blockDim.x) w3s[i] = mlp_param(a.params, kOffW3 + i);
-  for (int i = threadIdx.x; i < kH * kF; i += blockDim.x) w1s[(i / kF) * (kF + 1) + i % kF] = mlp_param(a.params, kOffW1 + i);
-  for (int i = threadIdx.x; i < kH * kH; i += blockDim.x) w2s[(i / kH) * (kH + 1) + i % kH] = mlp_param(a.params, kOffW2 + i);
   __syncthreads();
+  // the items' features (the first kClassItems threads) and the weights (the
+  // other threads) load at once, behind one barrier
+  if (threadIdx.x >= kClassItems) {
+    const int t0 = threadIdx.x - kClassItems, nt = blockDim.x - kClassItems;
+    for (int i = t0; i < kC * kH; i += nt) w3s[i] = mlp_param(a.params, kOffW3 + i);
+    for (int i = t0; i < kH * kF; i += nt) w1s[(i / kF) * (kF + 1) + i % kF] = mlp_param(a.params, kOffW1 + i);
+    for (int i = t0; i < kH * kH; i += nt) w2s[(i / kH) * (kH + 1) + i % kH] = mlp_param(a.params, kOffW2 + i);
+  }
   // features of the block's items, one thread each; only unstable neurons
   // (lo < 0 < hi) go through the network
   if (threadIdx.x < kClassItems) {
