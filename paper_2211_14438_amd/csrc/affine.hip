@@ -234,10 +234,10 @@ constexpr int kPackKU = 4;
 __host__ __device__ inline int pack_groups(int64_t C) { return (int)(64 / C); }
 
 // Dynamic LDS: the block's weights W^T[k][m0 .. m0 + MB) (hin MB doubles),
-// the wave partials ((kPackWaves - 1) x 2 MB x 64 doubles, reused for the
-// rounding sums), then the kind table (G hin bytes).
+// one slot of wave partials (2 MB x 64 doubles, reused for the rounding
+// sums), then the kind table (G hin bytes).
 inline size_t pack_lds(int G, int hin, int MB) {
-  return ((size_t)hin * MB + (size_t)(kPackWaves - 1) * 2 * MB * 64) * sizeof(double) + (size_t)G * hin;
+  return ((size_t)hin * MB + (size_t)2 * MB * 64) * sizeof(double) + (size_t)G * hin;
 }
 
 template <typename T, int MB>
@@ -257,7 +257,7 @@ __global__ void __launch_bounds__(kPackWaves * 64) gemm_pack_kernel(GemmArgs a) 
   const bool valid = g < G && bslot < nb;
   double *wl = pk_lds;
   double *part = wl + (size_t)hin * MB;
-  unsigned char *kind = reinterpret_cast<unsigned char *>(part + (size_t)(kPackWaves - 1) * 2 * MB * 64);
+  unsigned char *kind = reinterpret_cast<unsigned char *>(part + (size_t)2 * MB * 64);
   // weights through LDS: one uniform read per row instead of scalar loads
   // whose latency each step would wait for; the block's boxes' input kinds
   // from the kind bytes of their lists, both behind one barrier
@@ -336,27 +336,27 @@ __global__ void __launch_bounds__(kPackWaves * 64) gemm_pack_kernel(GemmArgs a) 
       }
     }
   }
-  // the quarters' sums, added in wave order by wave 0
-  if (w > 0) {
-    double *pw = part + (int64_t)(w - 1) * 2 * MB * 64;
-#pragma unroll
-    for (int mm = 0; mm < MB; ++mm) {
-      pw[(2 * mm) * 64 + lane] = accM[mm];
-      pw[(2 * mm + 1) * 64 + lane] = accR[mm];
-    }
-  }
-  __syncthreads();
-  if (w == 0) {
-    for (int v = 0; v < kPackWaves - 1; ++v) {
-      const double *pw = part + (int64_t)v * 2 * MB * 64;
+  // the quarters' sums, added in wave order by wave 0 through one LDS slot
+  // that waves 1, 2, ... fill in turn (a smaller block footprint, so more
+  // blocks share a CU)
+  for (int v = 1; v < kPackWaves; ++v) {
+    if (w == v) {
 #pragma unroll
       for (int mm = 0; mm < MB; ++mm) {
-        accM[mm] += pw[(2 * mm) * 64 + lane];
-        accR[mm] += pw[(2 * mm + 1) * 64 + lane];
+        part[(2 * mm) * 64 + lane] = accM[mm];
+        part[(2 * mm + 1) * 64 + lane] = accR[mm];
       }
     }
+    __syncthreads();
+    if (w == 0) {
+#pragma unroll
+      for (int mm = 0; mm < MB; ++mm) {
+        accM[mm] += part[(2 * mm) * 64 + lane];
+        accR[mm] += part[(2 * mm + 1) * 64 + lane];
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
   const bool track = a.rpart != nullptr;
   if (w == 0) {
     T *Y = reinterpret_cast<T *>(a.pre) + box * a.slot_out;
