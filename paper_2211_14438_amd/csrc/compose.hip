@@ -1040,7 +1040,7 @@ __global__ void __launch_bounds__(kBlock) compose_hz_kernel(ComposeArgs a, int m
 }
 
 // ---------------------------------------------- post radii (FP32 mode)
-// One thread per (box, neuron): fold the blocks' partial sums and add the
+// One thread per (box, neuron, bound): fold the blocks' partial sums and add the
 // analytic part of the radius of each post polynomial:
 //  * the perturbation of nu by FP64 rounding: |nu~ - nu| <= dnu in sup norm,
 //    and since nu and nu~ stay in [0, 1 + dnu] on the box,
@@ -1049,8 +1049,10 @@ __global__ void __launch_bounds__(kBlock) compose_hz_kernel(ComposeArgs a, int m
 //  * FP64 accumulation of the products: gamma(L (C + 4)) sum_j |c_j| N^j with
 //    N >= ||nu~||_1 + 1.
 __global__ void post_radii_kernel(ComposeArgs a, NeuronRec *recs) {
-  const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (item >= a.nboxes * a.h) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.nboxes * a.h * 2) return;
+  const int64_t item = t >> 1;
+  const int s = (int)(t & 1);
   const int64_t box = wave_box(a, item / a.h);
   const int j = (int)(item % a.h);
   NeuronRec &r = recs[box * a.h + j];
@@ -1058,7 +1060,7 @@ __global__ void post_radii_kernel(ComposeArgs a, NeuronRec *recs) {
   // coefficients of the stored pre-activation tensors (degree r.dpre)
   double cin = 1.0;
   for (int q = 1; q <= a.n; ++q) cin = cin * (r.dpre + q) / q;
-  for (int s = 0; s < 2; ++s) {
+  {
     const int64_t it = (box * a.h + j) * 2 + s;
     double rs = 0.0, l1 = 0.0;
     if (kind != kActive && kind != kInactive) {  // stored by one of the kernels above
@@ -1103,13 +1105,11 @@ __global__ void post_radii_kernel(ComposeArgs a, NeuronRec *recs) {
       r.padL = pad;
       r.pl1L = l1;
     }
-  }
-  if (a.rad) {
-    double *q = a.rad + (box * a.h + j) * 4;
-    q[0] = r.padU;
-    q[1] = r.padL;
-    q[2] = r.pl1U;
-    q[3] = r.pl1L;
+    if (a.rad) {  // padU, padL, pl1U, pl1L: this bound's two
+      double *q = a.rad + (box * a.h + j) * 4;
+      q[s] = pad;
+      q[2 + s] = l1;
+    }
   }
 }
 
@@ -1385,7 +1385,7 @@ static hipError_t compose_all(const ComposeArgs &a_in, hipStream_t s) {
 hipError_t launch_post_radii(const ComposeArgs &a, hipStream_t s) {
   if (!a.part || !a.recs || a.dcount) return hipErrorInvalidValue;
   ProfScope ps(kProfMisc, s, 0.0);
-  hipLaunchKernelGGL(post_radii_kernel, dim3((unsigned)((a.nboxes * a.h + 63) / 64)), dim3(64), 0, s, a,
+  hipLaunchKernelGGL(post_radii_kernel, dim3((unsigned)((a.nboxes * a.h * 2 + 63) / 64)), dim3(64), 0, s, a,
                      const_cast<NeuronRec *>(a.recs));
   return hipGetLastError();
 }
