@@ -1072,7 +1072,8 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
   // pinned staging: B box degrees, then one id list per (layer, phase); a
   // list is written once per wave, and every wave's first copy follows a
   // stream synchronisation, so no staged list is rewritten in flight
-  const size_t need = (size_t)B * (1 + 2 * (size_t)p.H);
+  // (and last, one int the first layer's read-off sets when a box is invalid)
+  const size_t need = (size_t)B * (1 + 2 * (size_t)p.H) + 1;
   if (!plain && !dev && net->host_n < need) {
     BERN_HIP_TRY(hipStreamSynchronize(s));
     if (net->host_ids) (void)hipHostFree(net->host_ids);
@@ -1085,6 +1086,12 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
     net->host_n = need;
     BERN_HIP_TRY(hipHostGetDevicePointer((void **)&net->host_dev, net->host_ids, 0));
   }
+  // Host classes: the first layer's read-off reports an invalid box through
+  // the staging's last int, so that a run with none skips the NaN step.
+  volatile int *bad_h = (!plain && !dev) ? net->host_ids + need - 1 : nullptr;
+  int *bad_d = (!plain && !dev) ? net->host_dev + need - 1 : nullptr;
+  if (bad_h) *bad_h = 0;
+  bool bad_known = false, any_bad = true, from_box_0 = false;
   // a phase's lists into the pinned staging, their device addresses into
   // devl; the ints to copy (0: one class of every box, the identity)
   auto stage = [&](std::vector<BoxClass> &cl, int layer, int phase, std::vector<const int *> &devl) -> size_t {
@@ -1156,6 +1163,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
     // sets every box's validity flag (read by the last step).
     const bool from_box = i == 0 && rc.size() == 1 && rc[0].Din == 1 && !rc[0].bids && !rc[0].dcount &&
                           rc[0].nboxes == B;
+    if (i == 0) from_box_0 = from_box;
     if (i == 0 && !from_box) {
       Layer1Args a{n, net->widths[1], B, nullptr, slotA, box_lo, box_hi, net->W64 + net->woff[0],
                    net->b64 + net->boff[0], Aa[0], p.fp64 ? 1 : 0, flags};
@@ -1204,6 +1212,7 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
       c.box_hi = box_hi;
       c.from_box = from_box ? 1 : 0;
       c.flags = from_box ? flags : nullptr;
+      c.hbad = from_box ? bad_d : nullptr;
       c.rpart = gpart;
       c.rpart_slot = (int64_t)(p.gpart / sizeof(double));
       c.cblocks = gemm_cblocks(c.S);
@@ -1378,6 +1387,10 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
           if (st != BERN_OK) return st;
         }
         BERN_HIP_TRY(spin_poll());
+        if (i == 0 && from_box_0) {  // the first layer's read-off is done
+          any_bad = *bad_h != 0;
+          bad_known = true;
+        }
         for (int64_t b = 0; b < B; ++b) {
           const int din_b = dcur[b], dout_b = std::max(hd[b], 0);
           size_t k = 0;
@@ -1443,12 +1456,12 @@ static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts 
     carried = gid;
     classes.swap(nc);
   }
-  {
+  if (!bad_known || any_bad) {
     ProfScope ps(kProfMisc, s, 0.0);
     hipLaunchKernelGGL(poison_kernel, dim3((unsigned)B), dim3(64), 0, s, B, (const int *)flags, net->nh, net->o,
                        nlo, nhi, olo, ohi);
+    BERN_HIP_TRY(hipGetLastError());
   }
-  BERN_HIP_TRY(hipGetLastError());
   return BERN_OK;
 }
 

@@ -296,6 +296,8 @@ struct ConvertArgs {
   int from_box;                   // layer 0 at degree 1, every box (bids null): the read-off forms
                                   // the pre tensors from the box, W and b itself and stores them
   int *flags;                     // with from_box, optional: [B] 1 for an invalid box, else 0
+  int *hbad;                      // with from_box, optional: set to 1 (mapped host memory) when a box
+                                  // is invalid
   const double *rpart;            // GEMM rounding partials, per wave box (stride rpart_slot):
   int64_t rpart_slot;             //   [h][2][cblocks] (layer > 0)
   int64_t cblocks;

@@ -1127,6 +1127,7 @@ __global__ void __launch_bounds__(kBlock) convert_affine_kernel(ConvertArgs a) {
       for (int k = 0; k < a.n; ++k)
         if (!(lo[k] <= hi[k]) || !isfinite(lo[k]) || !isfinite(hi[k])) bad = 1;
       a.flags[box] = bad;
+      if (bad && a.hbad) *a.hbad = 1;
     }
   } else {
 #pragma unroll

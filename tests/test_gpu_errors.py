@@ -123,6 +123,30 @@ def test_counters_and_stats(precision):
     net.close()
 
 
+def test_invalid_box_under_host_classes():
+    """A per-neuron plan with host-side classes: an invalid box gets NaN
+    bounds and the others finite ones; the next call on valid boxes (same
+    handle, same staging) gives no NaN at all, and the same bounds as a
+    call on the valid boxes alone."""
+    case, net, lo, hi = _net_and_boxes([3, 6, 5, 2], seed=9, n_boxes=5)
+    plan = torch.full((case.n_boxes, case.n_hidden), 2, dtype=torch.int8, device=DEV)
+    kw = dict(L=2, plan="given", degree_plan=plan, sched="batched", precision="fp32")
+    bad_lo = lo.clone()
+    bad_lo[2, 1] = hi[2, 1] + 1.0
+    r = B.bounds(net, bad_lo, hi, **kw)
+    torch.cuda.synchronize()
+    out_lo = r["out_lo"].cpu().numpy()
+    assert np.all(np.isnan(out_lo[2])) and np.all(np.isnan(r["neuron_hi"].cpu().numpy()[2]))
+    assert np.all(np.isfinite(out_lo[[0, 1, 3, 4]]))
+    r2 = B.bounds(net, lo, hi, **kw)
+    torch.cuda.synchronize()
+    for k in ("neuron_lo", "neuron_hi", "out_lo", "out_hi"):
+        v = r2[k].cpu().numpy()
+        assert np.all(np.isfinite(v)), k
+        assert np.array_equal(v[[0, 1, 3, 4]], r[k].cpu().numpy()[[0, 1, 3, 4]]), k
+    net.close()
+
+
 def test_host_classes_refused_under_stream_capture():
     """A per-neuron plan run with host-side classes synchronises its stream;
     on a stream under capture it is refused before anything is enqueued, and
