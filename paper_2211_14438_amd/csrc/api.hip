@@ -513,7 +513,8 @@ bern_status bern_workspace_size(const bern_net *net, const bern_opts *opts, int6
 }  // extern "C"
 
 // Boxes of a wave flagged invalid (flag[b] = 1: d_lo > d_hi or a non-finite
-// coordinate, set by the layer-1 kernel) get NaN bounds.
+// coordinate, set where the first layer's coefficients are formed) get NaN
+// bounds.
 __global__ void poison_kernel(int64_t nb, const int *flag, int nh, int o, double *nlo, double *nhi, double *olo,
                               double *ohi) {
   const int64_t b = blockIdx.x;
@@ -990,21 +991,12 @@ static bern_status lin_layer_run(const bern_net *net, const Plan &p, int i, cons
   return gemm_layer(net, p, i, all, 1, nullptr, Aa, Bp, slotA, slotB, live, live_ld, gpart, s);
 }
 
-// Enqueue the launch sequence of one wave of `B` boxes. The plain rule keeps
-// every box at the same degrees: one class, no host round trip. Plans with
-// per-neuron degrees launch each degree class of boxes on its own (a box's
-// tensors stay dense at the box's own degree inside its fixed slot): with
-// `dc`, every class the rules can give, its box list and count written by a
-// classification kernel (no host round trip); without, the classes that
-// occur, read back once per hidden layer (the box degrees to the host, the
-// id lists to the device).
-// Waits for the work enqueued on s so far by polling an event (one per host
-// thread and device) instead of a blocking stream synchronisation: the host
-// resumes within microseconds of the copy it waits for, which the per-layer
-// degree read-back of host classes pays once per hidden layer.
 // A wait for the work enqueued on a stream up to a mark, by polling an event
-// of the calling thread's on the current device: spin_mark records it (work
-// enqueued after the mark is not waited for), spin_poll waits for it.
+// of the calling thread's on the current device (spin_mark records it; work
+// enqueued after the mark is not waited for; spin_poll waits for it) instead
+// of a blocking stream synchronisation: the host resumes within microseconds
+// of the kernel it waits for, which the per-layer degree read-back of host
+// classes pays once per hidden layer.
 static hipEvent_t *spin_event() {
   static thread_local hipEvent_t ev[64] = {};
   int dev = 0;
@@ -1025,6 +1017,14 @@ static hipError_t spin_poll() {
   return e;
 }
 
+// Enqueue the launch sequence of one wave of `B` boxes. The plain rule keeps
+// every box at the same degrees: one class, no host round trip. Plans with
+// per-neuron degrees launch each degree class of boxes on its own (a box's
+// tensors stay dense at the box's own degree inside its fixed slot): with
+// `dc`, every class the rules can give, its box list and count written by a
+// classification kernel (no host round trip); without, the classes that
+// occur, read back once per hidden layer (the box degrees to the host, the
+// id lists to the device).
 static bern_status run_wave(const bern_net *net, const Plan &p, const bern_opts *o, int64_t b0, int64_t B,
                             const double *box_lo, const double *box_hi, const int8_t *plan, double *nlo, double *nhi,
                             double *olo, double *ohi, int8_t *used, char *ws, hipStream_t s,
