@@ -94,3 +94,27 @@ def test_autotune_variants_agree_with_oracle():
     assert B.tune_get(net) == choice
     _oracle_close(case, _np(B.bounds(net, lo, hi, **kw)))
     net.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_grouped_compositions_match_one_item_per_wave(precision):
+    """With many items (at least 65,536 per launch) the scatter and square
+    compositions take groups of items per wave, their jobs built at once and
+    each loaded ahead of the previous one's stores; the same boxes in waves
+    small enough for one item per wave give the same bounds bit for bit (a
+    per-neuron plan of orders 1 and 2 and the linear fallback, so both
+    kernels run)."""
+    case = wl.random_net_case([6, 64, 64, 4], seed=23, n_boxes=512)
+    print(f"case {case.name} {precision}", flush=True)
+    net = B.Net(case.Ws, case.bs)
+    lo = torch.tensor(case.box_lo, dtype=torch.float64, device=DEV)
+    hi = torch.tensor(case.box_hi, dtype=torch.float64, device=DEV)
+    plan = np.random.default_rng(4).integers(0, 3, size=(case.n_boxes, case.n_hidden)).astype(np.int8)
+    kw = dict(L=2, precision=precision, sched="batched", plan="given", degree_plan=torch.tensor(plan, device=DEV))
+    grouped = _np(B.bounds(net, lo, hi, **kw))  # one wave: 512 x 64 x 2 items
+    single = _np(B.bounds(net, lo, hi, max_wave=128, **kw))  # 16,384 items per wave
+    used = grouped["used_plan"][:, :case.n_hidden]
+    assert (used == 1).any() and (used == 2).any() and (used == -2).any()
+    for k in KEYS:
+        assert np.array_equal(grouped[k], single[k], equal_nan=True), k
+    net.close()
