@@ -2316,8 +2316,11 @@ __device__ __forceinline__ void quad_pass(const double *c, const double *beta, i
 // fits, the two stored tensors.
 constexpr size_t quad_lds(int n) { return (size_t)(kRowScratch + 2 * (kMaxInputs + 1) + 2 * qsize(n)) * sizeof(double); }
 
+// Up to six inputs the kernel is held to six waves per SIMD (80 registers,
+// a few spilled), which hides more of a neuron's load latency than five.
 template <int N, typename T>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N <= 6 ? 6 : 1))) convert_quad_t(ConvertArgs a) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N <= 6 ? 6 : 1)))
+convert_quad_t(ConvertArgs a) {
   extern __shared__ double lds[];
   const int64_t item = xcd_item(blockIdx.x, a.h, launch_boxes(a));  // a box's neurons on one XCD
   if (item < 0) return;                                             // past the boxes (or a device count)
